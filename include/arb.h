@@ -1,0 +1,203 @@
+/*
+ * arb.h -- C ABI of the articulated-body Stokes solver hot path on gfx950.
+ *
+ * The library solves the constrained mobility problem of Balboa Usabiaga &
+ * Delmotte, "A numerical method for suspensions of articulated bodies in
+ * viscous flows" (arXiv:2107.10800), Sec. 2.3 Eq. linear_system:
+ *
+ *     [ M   -K   0  ] [lambda]   [ u_s ]
+ *     [-K^T  0  C^T ] [  U   ] = [ -F  ]
+ *     [ 0    C   0  ] [ phi  ]   [  B  ]
+ *
+ * for N blobs of radius a on M rigid bodies, with velocity constraints C U = B,
+ * using the block-diagonal preconditioner of Sec. 3.1 inside restarted GMRES.
+ *
+ * Conventions (all entry points):
+ *  - Floating point is IEEE double unless stated.  Vectors are AoS:
+ *    positions / lambda / blob velocities as x0 y0 z0 x1 ...; per body
+ *    U_p = (u, w), F_p = (f, tau) with the torque about the tracking point q_p;
+ *    quaternions theta_p = (s, p1, p2, p3), scalar first, unit norm.
+ *  - Blobs of one body are contiguous: body p owns blobs
+ *    blob_offset[p] .. blob_offset[p+1]-1.
+ *  - Host pointers are read during the call and never retained; the caller
+ *    owns them.  `_dev` entry points take device pointers (hipMalloc'ed or
+ *    torch tensors' data_ptr) and a hipStream_t (NULL = the context's stream);
+ *    they are asynchronous with respect to the host and allocate nothing on
+ *    the caller's behalf (the context's own workspace may grow on the first
+ *    call at a larger size).
+ *  - Return value: 0 success, > 0 warning (result usable), < 0 error (result
+ *    undefined).  arb_last_error() gives the message of the last non-zero code.
+ *  - One context per host thread; calls on one context are not thread safe.
+ */
+#ifndef ARB_H
+#define ARB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ARB_OK                 0
+#define ARB_W_NOT_CONVERGED    1   /* GMRES hit max_iter; best iterate returned   */
+#define ARB_W_PINV_USED        2   /* a pseudo-inverse replaced an inverse (Sec. 3.1) */
+#define ARB_W_LEARNED_FALLBACK 3   /* learned body mobility rejected; exact used */
+#define ARB_E_ARG             -1   /* bad argument / size / state not set        */
+#define ARB_E_NOT_SPD         -2   /* blob mobility block not positive definite  */
+#define ARB_E_BELOW_WALL      -3   /* a blob at z <= a with the wall on          */
+#define ARB_E_DEVICE          -4   /* HIP runtime error                          */
+#define ARB_E_NAN             -5   /* non-finite value met                       */
+
+/* precision of the blob-blob mobility product (the Krylov solver is always FP64) */
+#define ARB_FP64   0   /* pair sum in double                                   */
+#define ARB_FP32C  1   /* pair sum in float: hi/lo split positions, float sums */
+                       /* per 256-source tile, double sums across tiles        */
+/* preconditioners */
+#define ARB_PC_NONE    0
+#define ARB_PC_BLOCK   1   /* Sec. 3.1, Eq. precond                          */
+#define ARB_PC_LEARNED 2   /* body mobility N~_p from the learned network    */
+
+typedef struct arb_ctx arb_ctx;
+
+typedef struct {
+    int    device;     /* HIP device ordinal                                   */
+    int    precision;  /* ARB_FP64 | ARB_FP32C                                 */
+    int    wall;       /* 0 unbounded, 1 no-slip plane z = 0 (Sec. 2.3)        */
+    double eta;        /* viscosity                                            */
+    double a;          /* blob radius                                          */
+    double tol;        /* GMRES relative residual ||b - A y|| / ||b||          */
+    int    restart;    /* GMRES restart length (<= 256)                        */
+    int    max_iter;   /* GMRES iteration cap (all cycles)                     */
+    int    precond;    /* ARB_PC_*                                             */
+    int    slices;     /* source slices of the pair kernel; 0 = autotune       */
+} arb_options;
+
+typedef struct {
+    int    iterations;      /* Arnoldi steps over all cycles                   */
+    int    restarts;        /* completed cycles                                */
+    double rel_residual;    /* true ||b - A y|| / ||b|| of the returned iterate */
+    double rel_residual_fp64; /* same, with the FP64 pair sum (FP32C runs)     */
+    double t_build_ms;      /* preconditioner build                            */
+    double t_solve_ms;      /* Krylov iterations incl. final residual          */
+    int    pinv_used;       /* number of blocks inverted by pseudo-inverse     */
+    int    history_len;     /* entries written to history                      */
+    double history[1024];   /* relative residual estimate per iteration        */
+} arb_solve_info;
+
+/* -------------------------------------------------------------- lifetime */
+/* Create a context on opt->device.  Returns ARB_E_ARG for bad options. */
+int  arb_create(arb_ctx **out, const arb_options *opt);
+void arb_destroy(arb_ctx *ctx);
+const char *arb_last_error(const arb_ctx *ctx);
+/* Pair-kernel launch shape actually used (after autotuning): source slices. */
+int  arb_get_slices(const arb_ctx *ctx, int n_blobs);
+
+/* -------------------------------------------------------------- bodies
+ * Body partition and body-frame blob positions (Sec. 2.3: blobs r_i of body
+ * p, r_i = q_p + R(theta_p) r_i^ref).  blob_offset: M+1 int32, nondecreasing,
+ * blob_offset[0] = 0, blob_offset[M] = N.  r_ref: 3N body-frame positions.
+ * body_type: M int32 (>= 0) used by ARB_PC_LEARNED, may be NULL. */
+int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset,
+                   const double *r_ref, const int32_t *body_type);
+
+/* Body state x_p = {q_p, theta_p} (Sec. 2.1): q 3M, theta 4M (unit, scalar
+ * first).  Recomputes blob positions (a GPU kernel) and the constraint rows. */
+int arb_set_state(arb_ctx *ctx, const double *q, const double *theta);
+
+/* Lab-frame blob positions r_i = q_p + R(theta_p) r_i^ref, 3N (Sec. 2.3). */
+int arb_blob_positions(arb_ctx *ctx, double *r_out);
+
+/* -------------------------------------------------------------- constraints
+ * Links (Sec. 2.2, Eq. constraint / Eq. dg): link n joins body pq[2n] (+ end)
+ * and body pq[2n+1] (- end; -1 = a fixed lab point dl_q).  dl_p, dl_q: 3P
+ * body-frame arms; dldot_p, dldot_q: their time derivatives (NULL = passive,
+ * B = 0).  nproj: P counts in 1..3 (NULL = 3); proj: 9P, the first nproj[n]
+ * rows of proj[9n..] are body-p-frame directions d onto which the link's
+ * velocity constraint is projected (NULL = e_x, e_y, e_z).  Each kept row
+ * reads d.(u_p + w_p x l_p - u_q - w_q x l_q) = d.B_n, l = R dl (App. A).
+ * Replaces previously set links. */
+int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p,
+                  const double *dl_q, const double *dldot_p, const double *dldot_q,
+                  const int32_t *nproj, const double *proj);
+
+/* General rows (Sec. 2.2: a constraint may act on single components or on
+ * one body): row k couples bodies pq[2k] and pq[2k+1] (-1 = none) with
+ * body-frame (of body pq[2k]) coefficients coef[12k..] = (c_u_p, c_w_p,
+ * c_u_q, c_w_q); it reads c.U = rhs[k].  Rows follow the link rows in phi.
+ * Replaces previously set rows. */
+int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef,
+                 const double *rhs);
+
+/* Number of constraint rows N_c and of unknowns n = 3N + 6M + N_c. */
+int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n);
+
+/* -------------------------------------------------------------- operators
+ * u = M lambda over the context's blobs (Sec. 2.3 Eq. no-slip / Eq. RPY):
+ * u_i = sum_j M_ij lambda_j over all j including i; 3N in, 3N out. */
+int arb_mobility_apply(arb_ctx *ctx, const double *lambda, double *u);
+int arb_mobility_apply_dev(arb_ctx *ctx, const double *lambda_dev, double *u_dev,
+                           void *stream);
+
+/* Stateless pair sum for loose blobs: pos 3N, lambda 3N, u 3N (device
+ * pointers), using ctx's a, eta, wall and precision.  Blobs below the wall are
+ * not checked here (use arb_check_wall). */
+int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev,
+                      const double *lambda_dev, double *u_dev, void *stream);
+/* Host-pointer version of arb_rpy_apply_dev; checks z > a when the wall is on. */
+int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda,
+                  double *u);
+
+/* out = A y for y = [lambda; U; phi] (Eq. linear_system); n doubles each. */
+int arb_system_apply(arb_ctx *ctx, const double *y, double *out);
+/* K U (3N) and K^T lambda (6M) (Eq. no-slip / Eq. balance). */
+int arb_K_apply(arb_ctx *ctx, const double *U, double *out);
+int arb_KT_apply(arb_ctx *ctx, const double *lambda, double *out);
+/* Dense constraint rows in the lab frame: coef 12 Nc (c_u_p, c_w_p, c_u_q,
+ * c_w_q), body pair 2 Nc, and B (Nc). */
+int arb_constraint_rows(arb_ctx *ctx, double *coef, int32_t *pq, double *B);
+
+/* -------------------------------------------------------------- preconditioner
+ * Build the block-diagonal preconditioner of Sec. 3.1 for the current state
+ * (per-body M_pp, batched Cholesky, N~_p, per-assembly G~_a).  Returns
+ * ARB_W_PINV_USED if a pseudo-inverse was needed, ARB_E_NOT_SPD if some
+ * M_pp is not positive definite. */
+int arb_precond_build(arb_ctx *ctx);
+/* z = P^-1 r (Eq. precond solved exactly), n doubles each. */
+int arb_precond_apply(arb_ctx *ctx, const double *r, double *z);
+/* Lower Cholesky factor of body p's blob mobility (3n_p x 3n_p row-major,
+ * upper part zero), and N~_p (36, row-major). */
+int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde);
+
+/* -------------------------------------------------------------- solve
+ * Solve A y = b with b = [u_s; -F; B] (Eq. linear_system).  F: 6M;
+ * u_slip: 3N or NULL (zero); y0: n or NULL (zero initial guess, Sec. 3.2.1
+ * warm start otherwise).  Outputs (may be NULL): U 6M, phi N_c, lambda 3N.
+ * info may be NULL. */
+int arb_solve(arb_ctx *ctx, const double *F, const double *u_slip, const double *y0,
+              double *U, double *phi, double *lambda, arb_solve_info *info);
+/* Device-pointer version: F_dev 6M, u_slip_dev 3N or NULL, y_dev n (in: the
+ * initial guess if warm != 0, out: the solution). */
+int arb_solve_dev(arb_ctx *ctx, const double *F_dev, const double *u_slip_dev,
+                  double *y_dev, int warm, arb_solve_info *info, void *stream);
+
+/* -------------------------------------------------------------- time step
+ * Explicit Euler update of every body (Sec. 4.3 step 3, applied per body):
+ * q_p += dt u_p, theta_p <- theta_{w_p dt} . theta_p.  U: 6M.  The new state
+ * becomes the context's state; q/theta (3M/4M, may be NULL) receive it. */
+int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double *theta);
+
+/* Position/orientation correction (Sec. 4.2, Eq. min_probl, App. B): per
+ * assembly, Levenberg-Marquardt on the link residuals g_n plus
+ * ||dtheta_p||^2 - 1, exact Jacobian, mu = ||F||^2, until ||F||_2 <= tol or
+ * max_iter steps.  Applies q <- q + dq, theta <- dtheta . theta to the
+ * context state and writes it to q/theta (may be NULL).  iters (may be NULL)
+ * receives the largest step count over assemblies; resid the largest final
+ * link residual ||g||_2 per assembly. */
+int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q,
+                          double *theta, int *iters, double *resid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARB_H */

@@ -26,7 +26,7 @@ Reading: the printed indicial form of App. B drops these factors of 2 and
 swaps two Levi-Civita indices relative to Eq. rot_mat; Eq. rot_mat is taken
 as authoritative (the finite-difference test checks this Jacobian).
 
-Iteration: Levenberg-Marquardt with mu = ||F||^2 (Yamashita-Fukushima),
+Iteration (per articulated body): Levenberg-Marquardt with mu = ||F||^2 (Yamashita-Fukushima),
 step delta = -J^T (J J^T + mu I)^-1 F, accepted when ||F|| decreases, else mu
 is multiplied by 10 and the step retried (at most 20 times); stop when
 ||F||_2 <= tol or after max_iter accepted steps.  Bodies of one assembly are
@@ -95,23 +95,61 @@ def jacobian(wl, q, theta, x):
     return J
 
 
-def correct(wl, q, theta, tol=1e-10, max_iter=50):
-    """Return (q_new, theta_new, info): q + dq and dtheta . theta (Sec. 4.3, step 5)."""
+def link_assemblies(wl):
+    """Bodies joined by links (position constraints), as lists of body indices,
+    each with the indices of its links.  Bodies without links are left out."""
+    M = len(wl.q)
+    parent = list(range(M))
+
+    def find(i):
+        while parent[i] != i:
+            parent[i] = parent[parent[i]]
+            i = parent[i]
+        return i
+
+    for p, qq in wl.pq:
+        if qq >= 0:
+            a, b = find(int(p)), find(int(qq))
+            if a != b:
+                parent[max(a, b)] = min(a, b)
+    groups = {}
+    for n, (p, qq) in enumerate(wl.pq):
+        r = find(int(p))
+        groups.setdefault(r, [set(), []])
+        groups[r][0].add(int(p))
+        if qq >= 0:
+            groups[r][0].add(int(qq))
+        groups[r][1].append(n)
+    return [(np.array(sorted(b)), np.array(l)) for _, (b, l) in sorted(groups.items())]
+
+
+class _Sub:
+    """Links of one assembly with body indices renumbered locally."""
+
+    def __init__(self, wl, bodies, links):
+        loc = {int(b): k for k, b in enumerate(bodies)}
+        self.pq = np.array([[loc[int(wl.pq[n, 0])], loc.get(int(wl.pq[n, 1]), -1)]
+                            for n in links], dtype=int).reshape(-1, 2)
+        self.dl_p = wl.dl_p[links]
+        self.dl_q = wl.dl_q[links]
+
+
+def _lm(sub, q, theta, tol, max_iter):
     M = len(q)
     x = np.zeros(7 * M)
     x.reshape(M, 7)[:, 3] = 1.0
-    F = residual(wl, q, theta, x)
+    F = residual(sub, q, theta, x)
     f = np.linalg.norm(F)
     hist = [f]
     it = 0
     while f > tol and it < max_iter:
-        J = jacobian(wl, q, theta, x)
+        J = jacobian(sub, q, theta, x)
         mu = f * f
         for _ in range(20):
             S = J @ J.T + mu * np.eye(len(F))
             w = np.linalg.solve(S, F)
             xn = x - J.T @ w
-            Fn = residual(wl, q, theta, xn)
+            Fn = residual(sub, q, theta, xn)
             fn = np.linalg.norm(Fn)
             if fn < f:
                 break
@@ -121,9 +159,30 @@ def correct(wl, q, theta, tol=1e-10, max_iter=50):
         x, F, f = xn, Fn, fn
         hist.append(f)
         it += 1
-    X = x.reshape(M, 7)
-    dth = X[:, 3:] / np.linalg.norm(X[:, 3:], axis=1)[:, None]
-    return q + X[:, :3], quat_mul(dth, theta), dict(iterations=it, history=hist, residual=f)
+    return x, it, hist
+
+
+def correct(wl, q, theta, tol=1e-10, max_iter=50):
+    """Return (q_new, theta_new, info): q + dq and dtheta . theta (Sec. 4.3, step 5).
+
+    Each articulated body (bodies joined by links) is corrected separately, as
+    the paper counts nonlinear iterations per articulated body (Sec. 4.4)."""
+    q = np.array(q, float)
+    theta = np.array(theta, float)
+    qn, tn = q.copy(), theta.copy()
+    iters, hists = [], []
+    for bodies_a, links_a in link_assemblies(wl):
+        sub = _Sub(wl, bodies_a, links_a)
+        x, it, hist = _lm(sub, q[bodies_a], theta[bodies_a], tol, max_iter)
+        X = x.reshape(len(bodies_a), 7)
+        dth = X[:, 3:] / np.linalg.norm(X[:, 3:], axis=1)[:, None]
+        qn[bodies_a] = q[bodies_a] + X[:, :3]
+        tn[bodies_a] = quat_mul(dth, theta[bodies_a])
+        iters.append(it)
+        hists.append(hist)
+    return qn, tn, dict(iterations=max(iters) if iters else 0, per_assembly=iters,
+                        history=hists[0] if len(hists) == 1 else hists,
+                        residual=max((h[-1] for h in hists), default=0.0))
 
 
 def euler_update(q, theta, U, dt):

@@ -1,0 +1,1082 @@
+// C ABI of libarb (declared in include/arb.h): argument checking, topology
+// bookkeeping on the host, and launch orchestration.  Every arithmetic step of
+// the method runs in the HIP kernels of pair.hip, bodies.hip, precond.hip,
+// krylov.hip and correct.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+namespace arb {
+int64_t correct_ws_doubles(int nb, int nl);
+}
+
+using arb::DevBuf;
+
+namespace {
+
+constexpr int kMaxBodyBlobs = 512;
+constexpr int kMaxAsmRows = 2048;
+constexpr int kMaxCorrRows = 2048;
+
+int fail(arb_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, ARB_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)                 \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ < 0) return rc_;  \
+    } while (0)
+
+hipStream_t pick(arb_ctx *ctx, void *stream) {
+    return stream ? (hipStream_t)stream : ctx->stream;
+}
+
+template <class T>
+int upload(arb_ctx *ctx, DevBuf &b, const T *h, size_t n, hipStream_t s) {
+    HIPCHK(b.ensure(n * sizeof(T)));
+    if (n) HIPCHK(hipMemcpyAsync(b.p, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+    return 0;
+}
+
+int64_t n_unknowns(const arb_ctx *ctx) {
+    return 3 * (int64_t)ctx->N + 6 * (int64_t)ctx->M + ctx->Nc;
+}
+
+// ---------------------------------------------------------------- topology
+int build_topology(arb_ctx *ctx) {
+    if (!ctx->topo_dirty) return 0;
+    const int M = ctx->M;
+    hipStream_t s = ctx->stream;
+    // constraint row table: link rows (link order, nproj each), then general rows
+    std::vector<int> rp, rq, rk, rs, rm;
+    for (int n = 0; n < ctx->P; ++n)
+        for (int m = 0; m < ctx->h_nproj[n]; ++m) {
+            rp.push_back(ctx->h_pq[2 * n]);
+            rq.push_back(ctx->h_pq[2 * n + 1]);
+            rk.push_back(0);
+            rs.push_back(n);
+            rm.push_back(m);
+        }
+    for (int j = 0; j < ctx->Rg; ++j) {
+        rp.push_back(ctx->h_gpq[2 * j]);
+        rq.push_back(ctx->h_gpq[2 * j + 1]);
+        rk.push_back(1);
+        rs.push_back(j);
+        rm.push_back(0);
+    }
+    const int Nc = (int)rp.size();
+    ctx->Nc = Nc;
+    for (int k = 0; k < Nc; ++k)
+        if (rp[k] < 0 || rp[k] >= M || rq[k] < -1 || rq[k] >= M || rq[k] == rp[k])
+            return fail(ctx, ARB_E_ARG, "constraint refers to a body outside 0..M-1");
+    // per-body CSR of (row, side) entries for C^T phi, rows ascending
+    std::vector<int> bptr(M + 1, 0), bent;
+    for (int k = 0; k < Nc; ++k) {
+        bptr[rp[k] + 1]++;
+        if (rq[k] >= 0) bptr[rq[k] + 1]++;
+    }
+    for (int p = 0; p < M; ++p) bptr[p + 1] += bptr[p];
+    bent.assign(bptr[M], 0);
+    std::vector<int> fill(bptr.begin(), bptr.end() - 1);
+    for (int k = 0; k < Nc; ++k) {
+        bent[fill[rp[k]]++] = 2 * k;
+        if (rq[k] >= 0) bent[fill[rq[k]]++] = 2 * k + 1;
+    }
+    // assemblies: union of bodies joined by any row
+    std::vector<int> parent(M);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int i) {
+        while (parent[i] != i) {
+            parent[i] = parent[parent[i]];
+            i = parent[i];
+        }
+        return i;
+    };
+    for (int k = 0; k < Nc; ++k)
+        if (rq[k] >= 0) {
+            int a = find(rp[k]), b = find(rq[k]);
+            if (a != b) parent[std::max(a, b)] = std::min(a, b);
+        }
+    std::vector<int> label(M, -1), asm_of(M);
+    int A = 0;
+    for (int p = 0; p < M; ++p) {
+        const int r = find(p);
+        if (label[r] < 0) label[r] = A++;
+        asm_of[p] = label[r];
+    }
+    std::vector<int> abp(A + 1, 0), ab(M), arp(A + 1, 0), ar(Nc);
+    for (int p = 0; p < M; ++p) abp[asm_of[p] + 1]++;
+    for (int a = 0; a < A; ++a) abp[a + 1] += abp[a];
+    {
+        std::vector<int> f2(abp.begin(), abp.end() - 1);
+        for (int p = 0; p < M; ++p) ab[f2[asm_of[p]]++] = p;
+    }
+    for (int k = 0; k < Nc; ++k) arp[asm_of[rp[k]] + 1]++;
+    for (int a = 0; a < A; ++a) arp[a + 1] += arp[a];
+    {
+        std::vector<int> f2(arp.begin(), arp.end() - 1);
+        for (int k = 0; k < Nc; ++k) ar[f2[asm_of[rp[k]]]++] = k;
+    }
+    std::vector<int64_t> amo(A + 1, 0);
+    for (int a = 0; a < A; ++a) {
+        const int na = arp[a + 1] - arp[a];
+        if (na > kMaxAsmRows)
+            return fail(ctx, ARB_E_ARG, "articulated body with more than 2048 constraint rows");
+        amo[a + 1] = amo[a] + (int64_t)na * na;
+    }
+    ctx->n_asm = A;
+    ctx->h_asm_body_ptr = abp;
+    ctx->h_asm_bodies = ab;
+    ctx->h_asm_row_ptr = arp;
+    ctx->h_asm_rows = ar;
+    TRY(upload(ctx, ctx->row_p, rp.data(), Nc, s));
+    TRY(upload(ctx, ctx->row_q, rq.data(), Nc, s));
+    TRY(upload(ctx, ctx->row_kind, rk.data(), Nc, s));
+    TRY(upload(ctx, ctx->row_src, rs.data(), Nc, s));
+    TRY(upload(ctx, ctx->row_m, rm.data(), Nc, s));
+    TRY(upload(ctx, ctx->brow_ptr, bptr.data(), M + 1, s));
+    TRY(upload(ctx, ctx->brow_ent, bent.data(), bent.size(), s));
+    TRY(upload(ctx, ctx->asm_body_ptr, abp.data(), A + 1, s));
+    TRY(upload(ctx, ctx->asm_bodies, ab.data(), M, s));
+    TRY(upload(ctx, ctx->asm_row_ptr, arp.data(), A + 1, s));
+    TRY(upload(ctx, ctx->asm_rows, ar.data(), Nc, s));
+    TRY(upload(ctx, ctx->asm_mat_off, amo.data(), A + 1, s));
+    HIPCHK(ctx->G.ensure(std::max<int64_t>(amo[A], 1) * sizeof(double)));
+    HIPCHK(ctx->S.ensure(std::max<int64_t>(2 * amo[A], 1) * sizeof(double)));
+    HIPCHK(ctx->crow.ensure(std::max(Nc, 1) * 12 * sizeof(double)));
+    HIPCHK(ctx->Bc.ensure(std::max(Nc, 1) * sizeof(double)));
+    // link data (zero-size arrays still get a valid pointer)
+    const int P = ctx->P;
+    TRY(upload(ctx, ctx->dl_p, ctx->h_dl_p.data(), 3 * (size_t)P, s));
+    TRY(upload(ctx, ctx->dl_q, ctx->h_dl_q.data(), 3 * (size_t)P, s));
+    TRY(upload(ctx, ctx->dldot_p, ctx->h_dldot_p.data(), 3 * (size_t)P, s));
+    TRY(upload(ctx, ctx->dldot_q, ctx->h_dldot_q.data(), 3 * (size_t)P, s));
+    TRY(upload(ctx, ctx->proj, ctx->h_proj.data(), 9 * (size_t)P, s));
+    TRY(upload(ctx, ctx->gcoef, ctx->h_gcoef.data(), 12 * (size_t)ctx->Rg, s));
+    TRY(upload(ctx, ctx->grhs, ctx->h_grhs.data(), (size_t)ctx->Rg, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->topo_dirty = false;
+    ctx->pc_built = false;
+    return 0;
+}
+
+int refresh_rows(arb_ctx *ctx, hipStream_t s) {
+    if (ctx->Nc > 0)
+        arb::constraint_rows(s, ctx->Nc, ctx->row_p.as<int>(), ctx->row_q.as<int>(),
+                             ctx->row_kind.as<int>(), ctx->row_src.as<int>(), ctx->row_m.as<int>(),
+                             ctx->R9.as<double>(), ctx->dl_p.as<double>(), ctx->dl_q.as<double>(),
+                             ctx->dldot_p.as<double>(), ctx->dldot_q.as<double>(),
+                             ctx->proj.as<double>(), ctx->gcoef.as<double>(),
+                             ctx->grhs.as<double>(), ctx->crow.as<double>(), ctx->Bc.as<double>());
+    return 0;
+}
+
+int ready(arb_ctx *ctx) {
+    if (ctx->M <= 0) return fail(ctx, ARB_E_ARG, "bodies not set");
+    if (!ctx->have_state) return fail(ctx, ARB_E_ARG, "state not set");
+    if (ctx->topo_dirty) {
+        TRY(build_topology(ctx));
+        TRY(refresh_rows(ctx, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+// geometry of the current state: rotations, blob positions, constraint rows
+int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
+    const int N = ctx->N, M = ctx->M;
+    HIPCHK(ctx->R9.ensure(9 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->pos.ensure(3 * (size_t)N * sizeof(double)));
+    HIPCHK(ctx->dvec.ensure(3 * (size_t)N * sizeof(double)));
+    HIPCHK(ctx->p64.ensure((size_t)N * sizeof(double4)));
+    HIPCHK(ctx->hi.ensure((size_t)N * sizeof(float4)));
+    HIPCHK(ctx->lo.ensure((size_t)N * sizeof(float4)));
+    arb::rotations(s, M, ctx->theta.as<double>(), ctx->R9.as<double>());
+    arb::blob_geometry(s, N, ctx->body_of_blob.as<int>(), ctx->q.as<double>(), ctx->R9.as<double>(),
+                       ctx->r_ref.as<double>(), ctx->pos.as<double>(), ctx->dvec.as<double>());
+    arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->p64.as<double4>(), ctx->hi.as<float4>(),
+                        ctx->lo.as<float4>());
+    if (!ctx->topo_dirty) TRY(refresh_rows(ctx, s));
+    ctx->pc_built = false;
+    return 0;
+}
+
+// ---------------------------------------------------------------- pair launch
+int heuristic_slices(int N) {
+    const int ntiles = (N + arb::kTile - 1) / arb::kTile;
+    int s = 1;
+    while ((int64_t)ntiles * s * 2 <= 2048 && s * 2 <= ntiles) s *= 2;
+    return s;
+}
+
+int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
+             const float4 *lo, const double *lam, double *out, const double *U, const int *bob,
+             const double *dvec, int precision, bool wall, int slices) {
+    HIPCHK(ctx->partial.ensure((size_t)slices * 3 * N * sizeof(double)));
+    const int used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, slices,
+                                       ctx->partial.as<double>());
+    arb::pair_reduce(s, N, used, ctx->partial.as<double>(), 1.0 / (8.0 * arb::kPi * ctx->opt.eta),
+                     out, U, bob, dvec);
+    return 0;
+}
+
+int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
+                  const float4 *lo, const double *lam, int precision, bool wall) {
+    if (ctx->opt.slices > 0) return ctx->opt.slices;
+    const int64_t key = (int64_t)N * 4 + precision * 2 + (wall ? 1 : 0);
+    auto it = ctx->slice_cache.find(key);
+    if (it != ctx->slice_cache.end()) return it->second;
+    const int h = heuristic_slices(N);
+    const int ntiles = (N + arb::kTile - 1) / arb::kTile;
+    int best = h;
+    if (N >= 8192) {
+        // autotune: time candidate source splits on this problem (two runs each)
+        std::vector<int> cand;
+        for (int c = std::max(1, h / 4); c <= std::min(ntiles, h * 4); c *= 2) cand.push_back(c);
+        HIPCHK(ctx->tune_out.ensure(3 * (size_t)N * sizeof(double)));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float bt = 1e30f;
+        for (int c : cand) {
+            float tsum = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPCHK(hipEventRecord(e0, s));
+                TRY(run_pair(ctx, s, N, p64, hi, lo, lam, ctx->tune_out.as<double>(), nullptr, nullptr,
+                             nullptr, precision, wall, c));
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) tsum += ms;
+            }
+            if (tsum < bt) {
+                bt = tsum;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    ctx->slice_cache[key] = best;
+    return best;
+}
+
+int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const double *U,
+             int precision) {
+    const bool wall = ctx->opt.wall != 0;
+    const int sl = choose_slices(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
+                                 ctx->lo.as<float4>(), lam, precision, wall);
+    if (sl < 0) return sl;
+    return run_pair(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
+                    ctx->lo.as<float4>(), lam, out, U, ctx->body_of_blob.as<int>(),
+                    ctx->dvec.as<double>(), precision, wall, sl);
+}
+
+// out = A y (Eq. linear_system)
+int system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out, int precision) {
+    const int N = ctx->N, M = ctx->M;
+    const double *lam = y, *U = y + 3 * (size_t)N, *phi = y + 3 * (size_t)N + 6 * (size_t)M;
+    TRY(ctx_pair(ctx, s, lam, out, U, precision));
+    arb::KT_CT_apply(s, M, ctx->blob_off.as<int>(), ctx->dvec.as<double>(), lam, -1.0,
+                     ctx->brow_ptr.as<int>(), ctx->brow_ent.as<int>(), ctx->crow.as<double>(),
+                     ctx->Nc > 0 ? phi : nullptr, out + 3 * (size_t)N);
+    arb::C_apply(s, ctx->Nc, ctx->row_p.as<int>(), ctx->row_q.as<int>(), ctx->crow.as<double>(), U,
+                 out + 3 * (size_t)N + 6 * (size_t)M);
+    return 0;
+}
+
+arb::PrecondDev pc_view(arb_ctx *ctx) {
+    arb::PrecondDev P;
+    P.M = ctx->M;
+    P.A = ctx->n_asm;
+    P.blob_off = ctx->blob_off.as<int>();
+    P.mat_off = ctx->mat_off.as<int64_t>();
+    P.z_off = ctx->z_off.as<int64_t>();
+    P.asm_body_ptr = ctx->asm_body_ptr.as<int>();
+    P.asm_bodies = ctx->asm_bodies.as<int>();
+    P.asm_row_ptr = ctx->asm_row_ptr.as<int>();
+    P.asm_rows = ctx->asm_rows.as<int>();
+    P.asm_mat_off = ctx->asm_mat_off.as<int64_t>();
+    P.row_p = ctx->row_p.as<int>();
+    P.row_q = ctx->row_q.as<int>();
+    P.brow_ptr = ctx->brow_ptr.as<int>();
+    P.brow_ent = ctx->brow_ent.as<int>();
+    P.crow = ctx->crow.as<double>();
+    P.mats = ctx->mats.as<double>();
+    P.minv = ctx->minv.as<double>();
+    P.ldiag = ctx->ldiag.as<double>();
+    P.Z = ctx->Z.as<double>();
+    P.Nt = ctx->Nt.as<double>();
+    P.G = ctx->G.as<double>();
+    P.S = ctx->S.as<double>();
+    P.status = ctx->status.as<int>();
+    P.tmp = ctx->pctmp.as<double>();
+    return P;
+}
+
+int precond_build(arb_ctx *ctx, hipStream_t s) {
+    TRY(ready(ctx));
+    const int M = ctx->M;
+    std::vector<int64_t> mo(M + 1, 0), zo(M + 1, 0);
+    for (int p = 0; p < M; ++p) {
+        const int64_t m = 3 * (int64_t)(ctx->h_blob_off[p + 1] - ctx->h_blob_off[p]);
+        mo[p + 1] = mo[p] + m * m;
+        zo[p + 1] = zo[p] + 6 * m;
+    }
+    TRY(upload(ctx, ctx->mat_off, mo.data(), M + 1, s));
+    TRY(upload(ctx, ctx->z_off, zo.data(), M + 1, s));
+    HIPCHK(ctx->mats.ensure(std::max<int64_t>(mo[M], 1) * sizeof(double)));
+    HIPCHK(ctx->minv.ensure(std::max<int64_t>(mo[M], 1) * sizeof(double)));
+    HIPCHK(ctx->ldiag.ensure(3 * (size_t)ctx->N * sizeof(double)));
+    HIPCHK(ctx->Z.ensure(std::max<int64_t>(zo[M], 1) * sizeof(double)));
+    HIPCHK(ctx->Nt.ensure(36 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->pctmp.ensure(6 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->status.ensure(8 * sizeof(int)));
+    HIPCHK(hipMemsetAsync(ctx->status.p, 0, 8 * sizeof(int), s));
+    arb::PrecondDev P = pc_view(ctx);
+    arb::precond_assemble(s, P, ctx->pos.as<double>(), ctx->opt.a, ctx->opt.eta, ctx->opt.wall != 0);
+    arb::precond_factor(s, P, ctx->dvec.as<double>(), 0);
+    arb::precond_assembly(s, P);
+    int st[8];
+    HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st[2]) return fail(ctx, ARB_E_BELOW_WALL, "a blob is at or below z = a with the wall on");
+    if (st[0])
+        return fail(ctx, ARB_E_NOT_SPD,
+                    "blob mobility of body " + std::to_string(st[0] - 1) + " is not positive definite");
+    ctx->pc_built = true;
+    ctx->pc_pinv = st[1] + st[3];
+    return ctx->pc_pinv ? ARB_W_PINV_USED : ARB_OK;
+}
+
+int precond_apply(arb_ctx *ctx, hipStream_t s, const double *r, double *z) {
+    const int64_t n = n_unknowns(ctx);
+    if (ctx->opt.precond == ARB_PC_NONE) {
+        HIPCHK(hipMemcpyAsync(z, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return 0;
+    }
+    arb::PrecondDev P = pc_view(ctx);
+    arb::precond_apply(s, P, ctx->N, r, z);
+    return 0;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// ---------------------------------------------------------------- GMRES (Sec. 3.1)
+int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int warm,
+              arb_solve_info *info, hipStream_t s) {
+    TRY(ready(ctx));
+    const int N = ctx->N, M = ctx->M, Nc = ctx->Nc;
+    const int64_t n = n_unknowns(ctx);
+    const int m = ctx->opt.restart;
+    const int prec = ctx->opt.precision;
+    const double tol = ctx->opt.tol;
+    const int nch = (int)((n + 2047) / 2048);
+    HIPCHK(ctx->kb.ensure(n * sizeof(double)));
+    HIPCHK(ctx->kr.ensure(n * sizeof(double)));
+    HIPCHK(ctx->kz.ensure(n * sizeof(double)));
+    HIPCHK(ctx->kw.ensure(n * sizeof(double)));
+    HIPCHK(ctx->kv.ensure((size_t)(m + 1) * n * sizeof(double)));
+    HIPCHK(ctx->kH.ensure((size_t)(m + 1) * m * sizeof(double)));
+    HIPCHK(ctx->kcs.ensure((size_t)(m + 1) * sizeof(double)));
+    HIPCHK(ctx->ksn.ensure((size_t)(m + 1) * sizeof(double)));
+    HIPCHK(ctx->kg.ensure((size_t)(m + 2) * sizeof(double)));
+    HIPCHK(ctx->khcol.ensure((size_t)(2 * (m + 2) + 8) * sizeof(double)));
+    HIPCHK(ctx->ksv.ensure((size_t)(m + 1) * sizeof(double)));
+    HIPCHK(ctx->kpart.ensure((size_t)(m + 1) * nch * sizeof(double)));
+    double *b = ctx->kb.as<double>(), *r = ctx->kr.as<double>(), *z = ctx->kz.as<double>(),
+           *w = ctx->kw.as<double>(), *V = ctx->kv.as<double>(), *H = ctx->kH.as<double>(),
+           *cs = ctx->kcs.as<double>(), *sn = ctx->ksn.as<double>(), *g = ctx->kg.as<double>(),
+           *sv = ctx->ksv.as<double>(), *part = ctx->kpart.as<double>();
+    double *h1 = ctx->khcol.as<double>(), *h2 = h1 + (m + 2), *sc = h2 + (m + 2);  // sc: 8 scalars
+    double *pin = ctx->pinned;
+    arb_solve_info loc{};
+    arb_solve_info *inf = info ? info : &loc;
+    std::memset(inf, 0, sizeof(*inf));
+    auto push_hist = [&](double v) {
+        if (inf->history_len < 1024) inf->history[inf->history_len++] = v;
+    };
+
+    HIPCHK(hipStreamSynchronize(s));
+    const double t0 = now_ms();
+    int warn = 0;
+    if (ctx->opt.precond != ARB_PC_NONE) {
+        const int rc = precond_build(ctx, s);
+        if (rc < 0) return rc;
+        if (rc > 0) warn = rc;
+        inf->pinv_used = ctx->pc_pinv;
+    } else if (Nc > 0) {
+        TRY(refresh_rows(ctx, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t1 = now_ms();
+    inf->t_build_ms = t1 - t0;
+
+    arb::rhs_assemble(s, N, M, Nc, us, F, ctx->Bc.as<double>(), b);
+    arb::multidot(s, n, 1, b, n, b, part, sc);
+    HIPCHK(hipMemcpyAsync(pin, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(pin[0]);
+    if (!std::isfinite(bnorm)) return fail(ctx, ARB_E_NAN, "right-hand side is not finite");
+    if (bnorm == 0.0) {
+        HIPCHK(hipMemsetAsync(y, 0, n * sizeof(double), s));
+        HIPCHK(hipStreamSynchronize(s));
+        push_hist(0.0);
+        return ARB_OK;
+    }
+    if (warm) {
+        TRY(system_apply(ctx, s, y, r, prec));
+        arb::axpby(s, n, 1.0, b, -1.0, r);  // r = b - A y
+    } else {
+        HIPCHK(hipMemsetAsync(y, 0, n * sizeof(double), s));
+        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    int total = 0, restarts = 0;
+    double true_rel = 1.0;
+    const int max_iter = ctx->opt.max_iter;
+    for (;;) {
+        arb::multidot(s, n, 1, r, n, r, part, sc + 2);
+        arb::g_init(s, m, sc + 2, g, sc + 3);  // g = [beta, 0, ...], sc[3] = beta
+        HIPCHK(hipMemcpyAsync(pin, sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double beta = pin[0];
+        if (!std::isfinite(beta)) return fail(ctx, ARB_E_NAN, "GMRES residual is not finite");
+        true_rel = beta / bnorm;
+        push_hist(true_rel);
+        if (beta <= tol * bnorm || total >= max_iter) break;
+        arb::scale_copy(s, n, r, sc + 3, V);  // v_0 = r / beta
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = V + (size_t)j * n;
+            TRY(precond_apply(ctx, s, vj, z));
+            TRY(system_apply(ctx, s, z, w, prec));
+            // classical Gram-Schmidt, twice
+            arb::multidot(s, n, j + 1, V, n, w, part, h1);
+            arb::gemv_sub(s, n, j + 1, V, n, h1, w);
+            arb::multidot(s, n, j + 1, V, n, w, part, h2);
+            arb::gemv_sub(s, n, j + 1, V, n, h2, w);
+            arb::multidot(s, n, 1, w, n, w, part, sc + 4);
+            arb::arnoldi_post(s, j, m, h1, h2, sc + 4, H, cs, sn, g, sc + 5);  // sc5 = hn, sc6 = est
+            HIPCHK(hipMemcpyAsync(pin, sc + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double hn = pin[0], est = pin[1];
+            if (!std::isfinite(est)) return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
+            ++total;
+            k = j + 1;
+            push_hist(est / bnorm);
+            if (est <= tol * bnorm || total >= max_iter || hn == 0.0) break;
+            arb::scale_copy(s, n, w, sc + 5, V + (size_t)(j + 1) * n);
+        }
+        arb::upper_solve(s, k, m, H, g, sv);
+        arb::gemv_set(s, n, k, V, n, sv, w);
+        TRY(precond_apply(ctx, s, w, z));
+        arb::axpby(s, n, 1.0, z, 1.0, y);
+        TRY(system_apply(ctx, s, y, r, prec));
+        arb::axpby(s, n, 1.0, b, -1.0, r);
+        ++restarts;
+        if (inf->history_len > 0) inf->history_len--;  // estimate replaced by the true residual
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t2 = now_ms();
+    inf->t_solve_ms = t2 - t1;
+    inf->iterations = total;
+    inf->restarts = restarts;
+    inf->rel_residual = true_rel;
+    inf->rel_residual_fp64 = true_rel;
+    if (prec == ARB_FP32C) {
+        TRY(system_apply(ctx, s, y, w, ARB_FP64));
+        arb::axpby(s, n, 1.0, b, -1.0, w);
+        arb::multidot(s, n, 1, w, n, w, part, sc + 7);
+        HIPCHK(hipMemcpyAsync(pin, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        inf->rel_residual_fp64 = std::sqrt(pin[0]) / bnorm;
+    }
+    if (true_rel > tol) return ARB_W_NOT_CONVERGED;
+    return warn;
+}
+
+int check_finite(arb_ctx *ctx, const double *v, size_t n, const char *what) {
+    if (!v) return 0;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return fail(ctx, ARB_E_NAN, std::string(what) + " is not finite");
+    return 0;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int arb_create(arb_ctx **out, const arb_options *opt) {
+    arb_ctx *ctx = nullptr;
+    if (!out || !opt) return ARB_E_ARG;
+    *out = nullptr;
+    if (!(opt->a > 0) || !(opt->eta > 0) || !(opt->tol > 0) || opt->restart < 1 ||
+        opt->restart > 256 || opt->max_iter < 1 ||
+        (opt->precision != ARB_FP64 && opt->precision != ARB_FP32C) || opt->precond < 0 ||
+        opt->precond > 2 || opt->slices < 0 || opt->slices > 4096)
+        return ARB_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
+        return ARB_E_DEVICE;
+    if (hipSetDevice(opt->device) != hipSuccess) return ARB_E_DEVICE;
+    ctx = new arb_ctx();
+    ctx->opt = *opt;
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->pinned, 64 * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess) {
+        delete ctx;
+        return ARB_E_DEVICE;
+    }
+    *out = ctx;
+    return ARB_OK;
+}
+
+void arb_destroy(arb_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->opt.device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *arb_last_error(const arb_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int arb_get_slices(const arb_ctx *ctx, int n_blobs) {
+    if (!ctx) return ARB_E_ARG;
+    if (ctx->opt.slices > 0) return ctx->opt.slices;
+    for (int prec = 0; prec < 2; ++prec) {
+        const int64_t key = (int64_t)n_blobs * 4 + prec * 2 + (ctx->opt.wall ? 1 : 0);
+        if (prec == ctx->opt.precision) {
+            auto it = ctx->slice_cache.find(key);
+            if (it != ctx->slice_cache.end()) return it->second;
+        }
+    }
+    return heuristic_slices(n_blobs);
+}
+
+int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset, const double *r_ref,
+                   const int32_t *body_type) {
+    if (!ctx) return ARB_E_ARG;
+    if (M <= 0 || !blob_offset || !r_ref) return fail(ctx, ARB_E_ARG, "bad body arguments");
+    if (blob_offset[0] != 0) return fail(ctx, ARB_E_ARG, "blob_offset[0] must be 0");
+    for (int p = 0; p < M; ++p) {
+        const int nb = blob_offset[p + 1] - blob_offset[p];
+        if (nb < 1) return fail(ctx, ARB_E_ARG, "every body needs at least one blob");
+        if (nb > kMaxBodyBlobs) return fail(ctx, ARB_E_ARG, "more than 512 blobs in one body");
+    }
+    const int N = blob_offset[M];
+    if (check_finite(ctx, r_ref, 3 * (size_t)N, "r_ref")) return ARB_E_NAN;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    ctx->M = M;
+    ctx->N = N;
+    ctx->h_blob_off.assign(blob_offset, blob_offset + M + 1);
+    ctx->h_r_ref.assign(r_ref, r_ref + 3 * (size_t)N);
+    ctx->h_body_of_blob.resize(N);
+    for (int p = 0; p < M; ++p)
+        for (int i = blob_offset[p]; i < blob_offset[p + 1]; ++i) ctx->h_body_of_blob[i] = p;
+    if (body_type)
+        ctx->h_body_type.assign(body_type, body_type + M);
+    else
+        ctx->h_body_type.assign(M, 0);
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->blob_off, ctx->h_blob_off.data(), M + 1, s));
+    TRY(upload(ctx, ctx->body_of_blob, ctx->h_body_of_blob.data(), N, s));
+    TRY(upload(ctx, ctx->r_ref, ctx->h_r_ref.data(), 3 * (size_t)N, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->have_state = false;
+    ctx->topo_dirty = true;
+    ctx->pc_built = false;
+    ctx->slice_cache.clear();
+    return ARB_OK;
+}
+
+int arb_set_state(arb_ctx *ctx, const double *q, const double *theta) {
+    if (!ctx) return ARB_E_ARG;
+    if (ctx->M <= 0) return fail(ctx, ARB_E_ARG, "bodies not set");
+    if (!q || !theta) return fail(ctx, ARB_E_ARG, "null state");
+    const int M = ctx->M;
+    if (check_finite(ctx, q, 3 * (size_t)M, "q") || check_finite(ctx, theta, 4 * (size_t)M, "theta"))
+        return ARB_E_NAN;
+    for (int p = 0; p < M; ++p) {
+        const double *t = theta + 4 * p;
+        const double nn = t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3];
+        if (std::fabs(nn - 1.0) > 1e-8) return fail(ctx, ARB_E_ARG, "theta is not a unit quaternion");
+    }
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->q, q, 3 * (size_t)M, s));
+    TRY(upload(ctx, ctx->theta, theta, 4 * (size_t)M, s));
+    TRY(build_topology(ctx));
+    TRY(refresh_geometry(ctx, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->have_state = true;
+    if (ctx->opt.wall) {
+        HIPCHK(ctx->status.ensure(8 * sizeof(int)));
+        int flag = arb::pair_wall_violation(s, ctx->N, ctx->p64.as<double4>(), ctx->opt.a,
+                                            ctx->status.as<int>(), (int *)ctx->pinned);
+        if (flag) return fail(ctx, ARB_E_BELOW_WALL, "a blob is at or below z = a with the wall on");
+    }
+    return ARB_OK;
+}
+
+int arb_blob_positions(arb_ctx *ctx, double *r_out) {
+    if (!ctx || !r_out) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipMemcpyAsync(r_out, ctx->pos.p, 3 * (size_t)ctx->N * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ARB_OK;
+}
+
+int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p, const double *dl_q,
+                  const double *dldot_p, const double *dldot_q, const int32_t *nproj,
+                  const double *proj) {
+    if (!ctx) return ARB_E_ARG;
+    if (P < 0 || (P > 0 && (!pq || !dl_p || !dl_q))) return fail(ctx, ARB_E_ARG, "bad link arguments");
+    ctx->P = P;
+    ctx->h_pq.assign(pq, pq + 2 * (size_t)P);
+    ctx->h_dl_p.assign(dl_p, dl_p + 3 * (size_t)P);
+    ctx->h_dl_q.assign(dl_q, dl_q + 3 * (size_t)P);
+    ctx->h_dldot_p.assign(3 * (size_t)P, 0.0);
+    ctx->h_dldot_q.assign(3 * (size_t)P, 0.0);
+    if (dldot_p) ctx->h_dldot_p.assign(dldot_p, dldot_p + 3 * (size_t)P);
+    if (dldot_q) ctx->h_dldot_q.assign(dldot_q, dldot_q + 3 * (size_t)P);
+    ctx->h_nproj.assign(P, 3);
+    ctx->h_proj.assign(9 * (size_t)P, 0.0);
+    for (int n = 0; n < P; ++n) {
+        if (nproj) {
+            if (nproj[n] < 1 || nproj[n] > 3) return fail(ctx, ARB_E_ARG, "nproj must be 1..3");
+            ctx->h_nproj[n] = nproj[n];
+        }
+        for (int k = 0; k < 9; ++k)
+            ctx->h_proj[9 * n + k] = proj ? proj[9 * n + k] : ((k % 4 == 0) ? 1.0 : 0.0);
+    }
+    if (check_finite(ctx, ctx->h_dl_p.data(), ctx->h_dl_p.size(), "dl_p") ||
+        check_finite(ctx, ctx->h_dl_q.data(), ctx->h_dl_q.size(), "dl_q") ||
+        check_finite(ctx, ctx->h_proj.data(), ctx->h_proj.size(), "proj"))
+        return ARB_E_NAN;
+    ctx->topo_dirty = true;
+    ctx->pc_built = false;
+    if (ctx->have_state) {
+        HIPCHK(hipSetDevice(ctx->opt.device));
+        TRY(build_topology(ctx));
+        TRY(refresh_rows(ctx, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return ARB_OK;
+}
+
+int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef, const double *rhs) {
+    if (!ctx) return ARB_E_ARG;
+    if (R < 0 || (R > 0 && (!pq || !coef || !rhs))) return fail(ctx, ARB_E_ARG, "bad row arguments");
+    ctx->Rg = R;
+    ctx->h_gpq.assign(pq, pq + 2 * (size_t)R);
+    ctx->h_gcoef.assign(coef, coef + 12 * (size_t)R);
+    ctx->h_grhs.assign(rhs, rhs + (size_t)R);
+    if (check_finite(ctx, ctx->h_gcoef.data(), ctx->h_gcoef.size(), "coef") ||
+        check_finite(ctx, ctx->h_grhs.data(), ctx->h_grhs.size(), "rhs"))
+        return ARB_E_NAN;
+    ctx->topo_dirty = true;
+    ctx->pc_built = false;
+    if (ctx->have_state) {
+        HIPCHK(hipSetDevice(ctx->opt.device));
+        TRY(build_topology(ctx));
+        TRY(refresh_rows(ctx, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return ARB_OK;
+}
+
+int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n) {
+    if (!ctx) return ARB_E_ARG;
+    int nc = ctx->Nc;
+    if (ctx->topo_dirty) {
+        nc = ctx->Rg;
+        for (int k : ctx->h_nproj) nc += k;
+    }
+    if (N) *N = ctx->N;
+    if (M) *M = ctx->M;
+    if (Nc) *Nc = nc;
+    if (n) *n = 3 * (int64_t)ctx->N + 6 * (int64_t)ctx->M + nc;
+    return ARB_OK;
+}
+
+int arb_mobility_apply_dev(arb_ctx *ctx, const double *lambda_dev, double *u_dev, void *stream) {
+    if (!ctx || !lambda_dev || !u_dev) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    TRY(ctx_pair(ctx, pick(ctx, stream), lambda_dev, u_dev, nullptr, ctx->opt.precision));
+    HIPCHK(hipGetLastError());
+    return ARB_OK;
+}
+
+int arb_mobility_apply(arb_ctx *ctx, const double *lambda, double *u) {
+    if (!ctx || !lambda || !u) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const size_t n3 = 3 * (size_t)ctx->N;
+    if (check_finite(ctx, lambda, n3, "lambda")) return ARB_E_NAN;
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, lambda, n3, s));
+    HIPCHK(ctx->s_out.ensure(n3 * sizeof(double)));
+    TRY(ctx_pair(ctx, s, ctx->s_in.as<double>(), ctx->s_out.as<double>(), nullptr,
+                 ctx->opt.precision));
+    HIPCHK(hipMemcpyAsync(u, ctx->s_out.p, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *lambda_dev,
+                      double *u_dev, void *stream) {
+    if (!ctx || N < 0 || (N > 0 && (!pos_dev || !lambda_dev || !u_dev))) return ARB_E_ARG;
+    if (N == 0) return ARB_OK;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = pick(ctx, stream);
+    HIPCHK(ctx->s_pos.ensure((size_t)N * (sizeof(double4) + 2 * sizeof(float4))));
+    double4 *p64 = ctx->s_pos.as<double4>();
+    float4 *hi = reinterpret_cast<float4 *>(p64 + N);
+    float4 *lo = hi + N;
+    arb::prep_positions(s, N, pos_dev, p64, hi, lo);
+    const bool wall = ctx->opt.wall != 0;
+    const int sl = choose_slices(ctx, s, N, p64, hi, lo, lambda_dev, ctx->opt.precision, wall);
+    if (sl < 0) return sl;
+    TRY(run_pair(ctx, s, N, p64, hi, lo, lambda_dev, u_dev, nullptr, nullptr, nullptr,
+                 ctx->opt.precision, wall, sl));
+    HIPCHK(hipGetLastError());
+    return ARB_OK;
+}
+
+int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda, double *u) {
+    if (!ctx || N < 0 || (N > 0 && (!pos || !lambda || !u))) return ARB_E_ARG;
+    if (N == 0) return ARB_OK;
+    if (check_finite(ctx, pos, 3 * (size_t)N, "pos") ||
+        check_finite(ctx, lambda, 3 * (size_t)N, "lambda"))
+        return ARB_E_NAN;
+    if (ctx->opt.wall)
+        for (int i = 0; i < N; ++i)
+            if (!(pos[3 * i + 2] > ctx->opt.a))
+                return fail(ctx, ARB_E_BELOW_WALL, "a blob is at or below z = a with the wall on");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    const size_t n3 = 3 * (size_t)N;
+    TRY(upload(ctx, ctx->s_in, pos, n3, s));
+    TRY(upload(ctx, ctx->s_aux, lambda, n3, s));
+    HIPCHK(ctx->s_out.ensure(n3 * sizeof(double)));
+    TRY(arb_rpy_apply_dev(ctx, N, ctx->s_in.as<double>(), ctx->s_aux.as<double>(),
+                          ctx->s_out.as<double>(), s));
+    HIPCHK(hipMemcpyAsync(u, ctx->s_out.p, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_system_apply(arb_ctx *ctx, const double *y, double *out) {
+    if (!ctx || !y || !out) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const int64_t n = n_unknowns(ctx);
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, y, n, s));
+    HIPCHK(ctx->s_out.ensure(n * sizeof(double)));
+    TRY(system_apply(ctx, s, ctx->s_in.as<double>(), ctx->s_out.as<double>(), ctx->opt.precision));
+    HIPCHK(hipMemcpyAsync(out, ctx->s_out.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_K_apply(arb_ctx *ctx, const double *U, double *out) {
+    if (!ctx || !U || !out) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, U, 6 * (size_t)ctx->M, s));
+    HIPCHK(ctx->s_out.ensure(3 * (size_t)ctx->N * sizeof(double)));
+    arb::K_apply(s, ctx->N, ctx->body_of_blob.as<int>(), ctx->dvec.as<double>(),
+                 ctx->s_in.as<double>(), ctx->s_out.as<double>());
+    HIPCHK(hipMemcpyAsync(out, ctx->s_out.p, 3 * (size_t)ctx->N * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_KT_apply(arb_ctx *ctx, const double *lambda, double *out) {
+    if (!ctx || !lambda || !out) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, lambda, 3 * (size_t)ctx->N, s));
+    HIPCHK(ctx->s_out.ensure(6 * (size_t)ctx->M * sizeof(double)));
+    arb::KT_CT_apply(s, ctx->M, ctx->blob_off.as<int>(), ctx->dvec.as<double>(),
+                     ctx->s_in.as<double>(), 1.0, nullptr, nullptr, nullptr, nullptr,
+                     ctx->s_out.as<double>());
+    HIPCHK(hipMemcpyAsync(out, ctx->s_out.p, 6 * (size_t)ctx->M * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_constraint_rows(arb_ctx *ctx, double *coef, int32_t *pq, double *B) {
+    if (!ctx) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    const int Nc = ctx->Nc;
+    if (Nc == 0) return ARB_OK;
+    if (coef)
+        HIPCHK(hipMemcpyAsync(coef, ctx->crow.p, 12 * (size_t)Nc * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    if (B) HIPCHK(hipMemcpyAsync(B, ctx->Bc.p, (size_t)Nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<int> rp(Nc), rq(Nc);
+    HIPCHK(hipMemcpyAsync(rp.data(), ctx->row_p.p, Nc * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rq.data(), ctx->row_q.p, Nc * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (pq)
+        for (int k = 0; k < Nc; ++k) {
+            pq[2 * k] = rp[k];
+            pq[2 * k + 1] = rq[k];
+        }
+    return ARB_OK;
+}
+
+int arb_precond_build(arb_ctx *ctx) {
+    if (!ctx) return ARB_E_ARG;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    return precond_build(ctx, ctx->stream);
+}
+
+int arb_precond_apply(arb_ctx *ctx, const double *r, double *z) {
+    if (!ctx || !r || !z) return ARB_E_ARG;
+    TRY(ready(ctx));
+    if (ctx->opt.precond != ARB_PC_NONE && !ctx->pc_built)
+        return fail(ctx, ARB_E_ARG, "preconditioner not built for the current state");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const int64_t n = n_unknowns(ctx);
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, r, n, s));
+    HIPCHK(ctx->s_out.ensure(n * sizeof(double)));
+    TRY(precond_apply(ctx, s, ctx->s_in.as<double>(), ctx->s_out.as<double>()));
+    HIPCHK(hipMemcpyAsync(z, ctx->s_out.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde) {
+    if (!ctx) return ARB_E_ARG;
+    if (!ctx->pc_built) return fail(ctx, ARB_E_ARG, "preconditioner not built");
+    if (p < 0 || p >= ctx->M) return fail(ctx, ARB_E_ARG, "body index out of range");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    int64_t off = 0;
+    for (int k = 0; k < p; ++k) {
+        const int64_t m = 3 * (int64_t)(ctx->h_blob_off[k + 1] - ctx->h_blob_off[k]);
+        off += m * m;
+    }
+    const int64_t m = 3 * (int64_t)(ctx->h_blob_off[p + 1] - ctx->h_blob_off[p]);
+    if (L) {
+        HIPCHK(hipMemcpyAsync(L, ctx->mats.as<double>() + off, m * m * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    }
+    if (Ntilde)
+        HIPCHK(hipMemcpyAsync(Ntilde, ctx->Nt.as<double>() + 36 * (size_t)p, 36 * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (L)
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = i + 1; j < m; ++j) L[i * m + j] = 0.0;
+    return ARB_OK;
+}
+
+int arb_solve_dev(arb_ctx *ctx, const double *F_dev, const double *u_slip_dev, double *y_dev,
+                  int warm, arb_solve_info *info, void *stream) {
+    if (!ctx || !F_dev || !y_dev) return ARB_E_ARG;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    return solve_dev(ctx, F_dev, u_slip_dev, y_dev, warm, info, pick(ctx, stream));
+}
+
+int arb_solve(arb_ctx *ctx, const double *F, const double *u_slip, const double *y0, double *U,
+              double *phi, double *lambda, arb_solve_info *info) {
+    if (!ctx || !F) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const int N = ctx->N, M = ctx->M;
+    const int64_t n = n_unknowns(ctx);
+    if (check_finite(ctx, F, 6 * (size_t)M, "F") ||
+        check_finite(ctx, u_slip, u_slip ? 3 * (size_t)N : 0, "u_slip") ||
+        check_finite(ctx, y0, y0 ? (size_t)n : 0, "y0"))
+        return ARB_E_NAN;
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, F, 6 * (size_t)M, s));
+    if (u_slip) TRY(upload(ctx, ctx->s_aux, u_slip, 3 * (size_t)N, s));
+    HIPCHK(ctx->ky.ensure(n * sizeof(double)));
+    if (y0) HIPCHK(hipMemcpyAsync(ctx->ky.p, y0, n * sizeof(double), hipMemcpyHostToDevice, s));
+    const int rc = solve_dev(ctx, ctx->s_in.as<double>(), u_slip ? ctx->s_aux.as<double>() : nullptr,
+                             ctx->ky.as<double>(), y0 ? 1 : 0, info, s);
+    if (rc < 0) return rc;
+    const double *yd = ctx->ky.as<double>();
+    if (lambda)
+        HIPCHK(hipMemcpyAsync(lambda, yd, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (U)
+        HIPCHK(hipMemcpyAsync(U, yd + 3 * (size_t)N, 6 * (size_t)M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    if (phi && ctx->Nc > 0)
+        HIPCHK(hipMemcpyAsync(phi, yd + 3 * (size_t)N + 6 * (size_t)M, ctx->Nc * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return rc;
+}
+
+int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double *theta) {
+    if (!ctx || !U) return ARB_E_ARG;
+    TRY(ready(ctx));
+    if (check_finite(ctx, U, 6 * (size_t)ctx->M, "U")) return ARB_E_NAN;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, U, 6 * (size_t)ctx->M, s));
+    arb::euler_update(s, ctx->M, ctx->s_in.as<double>(), dt, ctx->q.as<double>(),
+                      ctx->theta.as<double>());
+    TRY(refresh_geometry(ctx, s));
+    if (q)
+        HIPCHK(hipMemcpyAsync(q, ctx->q.p, 3 * (size_t)ctx->M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    if (theta)
+        HIPCHK(hipMemcpyAsync(theta, ctx->theta.p, 4 * (size_t)ctx->M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, double *theta,
+                          int *iters, double *resid) {
+    if (!ctx || !(tol > 0) || max_iter < 0) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    const int M = ctx->M, P = ctx->P;
+    // assemblies of bodies joined by links (position constraints only)
+    std::vector<int> parent(M);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int i) {
+        while (parent[i] != i) {
+            parent[i] = parent[parent[i]];
+            i = parent[i];
+        }
+        return i;
+    };
+    for (int n = 0; n < P; ++n) {
+        const int p = ctx->h_pq[2 * n], qq = ctx->h_pq[2 * n + 1];
+        if (qq >= 0) {
+            const int a = find(p), b = find(qq);
+            if (a != b) parent[std::max(a, b)] = std::min(a, b);
+        }
+    }
+    std::vector<int> label(M, -1), has_link(M, 0);
+    for (int n = 0; n < P; ++n) {
+        has_link[ctx->h_pq[2 * n]] = 1;
+        if (ctx->h_pq[2 * n + 1] >= 0) has_link[ctx->h_pq[2 * n + 1]] = 1;
+    }
+    int A = 0;
+    std::vector<int> root_label(M, -1);
+    for (int p = 0; p < M; ++p) {
+        if (!has_link[p]) continue;
+        const int r = find(p);
+        if (root_label[r] < 0) root_label[r] = A++;
+        label[p] = root_label[r];
+    }
+    if (A == 0) {
+        if (iters) *iters = 0;
+        if (resid) *resid = 0.0;
+        return ARB_OK;
+    }
+    std::vector<int> abp(A + 1, 0), ab, alp(A + 1, 0), al(P), loc(M, -1);
+    for (int p = 0; p < M; ++p)
+        if (label[p] >= 0) abp[label[p] + 1]++;
+    for (int a = 0; a < A; ++a) abp[a + 1] += abp[a];
+    ab.assign(abp[A], 0);
+    {
+        std::vector<int> f2(abp.begin(), abp.end() - 1);
+        for (int p = 0; p < M; ++p)
+            if (label[p] >= 0) {
+                loc[p] = f2[label[p]] - abp[label[p]];
+                ab[f2[label[p]]++] = p;
+            }
+    }
+    for (int n = 0; n < P; ++n) alp[label[ctx->h_pq[2 * n]] + 1]++;
+    for (int a = 0; a < A; ++a) alp[a + 1] += alp[a];
+    {
+        std::vector<int> f2(alp.begin(), alp.end() - 1);
+        for (int n = 0; n < P; ++n) al[f2[label[ctx->h_pq[2 * n]]]++] = n;
+    }
+    std::vector<int64_t> wo(A + 1, 0);
+    for (int a = 0; a < A; ++a) {
+        const int nb = abp[a + 1] - abp[a], nl = alp[a + 1] - alp[a];
+        if (3 * nl + nb > kMaxCorrRows)
+            return fail(ctx, ARB_E_ARG, "articulated body too large for the correction kernel");
+        wo[a + 1] = wo[a] + arb::correct_ws_doubles(nb, nl);
+    }
+    TRY(upload(ctx, ctx->c_link_ptr, alp.data(), A + 1, s));
+    TRY(upload(ctx, ctx->c_links, al.data(), P, s));
+    TRY(upload(ctx, ctx->c_local, loc.data(), M, s));
+    TRY(upload(ctx, ctx->c_ws_off, wo.data(), A + 1, s));
+    TRY(upload(ctx, ctx->c_pq, ctx->h_pq.data(), 2 * (size_t)P, s));
+    TRY(upload(ctx, ctx->c_abp, abp.data(), A + 1, s));
+    TRY(upload(ctx, ctx->c_ab, ab.data(), ab.size(), s));
+    HIPCHK(ctx->c_ws.ensure(std::max<int64_t>(wo[A], 1) * sizeof(double)));
+    HIPCHK(ctx->c_iters.ensure(A * sizeof(int)));
+    HIPCHK(ctx->c_resid.ensure(A * sizeof(double)));
+    arb::CorrectDev C;
+    C.A = A;
+    C.M = M;
+    C.P = P;
+    C.asm_body_ptr = ctx->c_abp.as<int>();
+    C.asm_bodies = ctx->c_ab.as<int>();
+    C.asm_link_ptr = ctx->c_link_ptr.as<int>();
+    C.asm_links = ctx->c_links.as<int>();
+    C.local_index = ctx->c_local.as<int>();
+    C.pq = ctx->c_pq.as<int>();
+    C.dl_p = ctx->dl_p.as<double>();
+    C.dl_q = ctx->dl_q.as<double>();
+    C.ws_off = ctx->c_ws_off.as<int64_t>();
+    C.ws = ctx->c_ws.as<double>();
+    C.q = ctx->q.as<double>();
+    C.theta = ctx->theta.as<double>();
+    C.iters = ctx->c_iters.as<int>();
+    C.resid = ctx->c_resid.as<double>();
+    arb::correct_positions(s, C, tol, max_iter);
+    HIPCHK(hipGetLastError());
+    TRY(refresh_geometry(ctx, s));
+    std::vector<int> it(A);
+    std::vector<double> rs(A);
+    HIPCHK(hipMemcpyAsync(it.data(), C.iters, A * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rs.data(), C.resid, A * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (q)
+        HIPCHK(hipMemcpyAsync(q, ctx->q.p, 3 * (size_t)M * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (theta)
+        HIPCHK(hipMemcpyAsync(theta, ctx->theta.p, 4 * (size_t)M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (iters) *iters = *std::max_element(it.begin(), it.end());
+    if (resid) *resid = *std::max_element(rs.begin(), rs.end());
+    return ARB_OK;
+}
+
+}  // extern "C"

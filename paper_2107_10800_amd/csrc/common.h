@@ -1,0 +1,177 @@
+// Internal declarations shared by the HIP translation units of libarb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "arb.h"
+
+namespace arb {
+
+constexpr int kTile = 256;          // sources per LDS tile == threads per pair block
+constexpr int kWave = 64;           // CDNA wavefront
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- device buffer
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow-only; contents are not preserved when growing
+    hipError_t ensure(size_t nbytes) {
+        if (nbytes <= bytes && p) return hipSuccess;
+        release();
+        size_t nb = nbytes ? nbytes : 16;
+        hipError_t e = hipMalloc(&p, nb);
+        if (e == hipSuccess) bytes = nb;
+        return e;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------- kernel entry points
+// Pair sum u_i = sum_j M_ij lambda_j (Sec. 2.3): partial sums per source slice,
+// then an ordered reduction.  Positions are prepared by prep_positions().
+void prep_positions(hipStream_t s, int N, const double *pos_aos, double4 *p64, float4 *hi,
+                    float4 *lo);
+// returns the number of slices written (clamped to the tile count)
+int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+                  const float4 *hi, const float4 *lo, const double *lam, double a,
+                  int slices, double *partial);
+// out_i = scale * sum_s partial[s][c][i]  -  (K U)_i   (the K term only if U != nullptr)
+void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double scale,
+                 double *out, const double *U, const int *body_of_blob, const double *dvec);
+int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,
+                        int *flag_host);
+
+// Rigid-body kinematics (Sec. 2.1, 2.3, App. B)
+void rotations(hipStream_t s, int M, const double *theta, double *R9);
+void blob_geometry(hipStream_t s, int N, const int *body_of_blob, const double *q,
+                   const double *R9, const double *r_ref, double *pos_aos, double *dvec);
+void K_apply(hipStream_t s, int N, const int *body_of_blob, const double *dvec,
+             const double *U, double *out);
+// out_p = sign * (K^T lambda)_p + (C^T phi)_p  (phi may be null)
+void KT_CT_apply(hipStream_t s, int M, const int *blob_off, const double *dvec,
+                 const double *lam, double sign, const int *brow_ptr, const int *brow_ent,
+                 const double *crow, const double *phi, double *out);
+void constraint_rows(hipStream_t s, int Nc, const int *row_p, const int *row_q,
+                     const int *row_kind, const int *row_src, const int *row_m,
+                     const double *R9, const double *dl_p, const double *dl_q,
+                     const double *dldot_p, const double *dldot_q, const double *proj,
+                     const double *gcoef, const double *grhs, double *crow, double *B);
+void C_apply(hipStream_t s, int Nc, const int *row_p, const int *row_q, const double *crow,
+             const double *U, double *out);
+void euler_update(hipStream_t s, int M, const double *U, double dt, double *q, double *theta);
+
+// Block-diagonal preconditioner (Sec. 3.1)
+struct PrecondDev {
+    int M = 0, A = 0;
+    const int *blob_off = nullptr;     // M+1
+    const int64_t *mat_off = nullptr;  // M+1, doubles
+    const int64_t *z_off = nullptr;    // M+1, doubles (18 n_p per body)
+    const int *asm_body_ptr = nullptr, *asm_bodies = nullptr;
+    const int *asm_row_ptr = nullptr, *asm_rows = nullptr;
+    const int64_t *asm_mat_off = nullptr;
+    const int *row_p = nullptr, *row_q = nullptr;
+    const int *brow_ptr = nullptr, *brow_ent = nullptr;
+    const double *crow = nullptr;
+    double *mats = nullptr;   // per-body M_pp, Cholesky in place
+    double *minv = nullptr;   // per-body M_pp^-1 (same offsets as mats)
+    double *ldiag = nullptr;  // diag(L) per body (3N)
+    double *Z = nullptr;      // per-body Z_p = M_pp^-1 K_p (3n_p x 6)
+    double *Nt = nullptr;     // per-body N~_p (36)
+    double *G = nullptr;      // per-assembly G~_a
+    double *S = nullptr;      // per-assembly scratch (S_a and its factor)
+    int *status = nullptr;    // [0] not-SPD body+1, [1] G~ pinv count, [2] below wall,
+                              // [3] N~ with dropped eigenvalues
+    double *tmp = nullptr;    // apply scratch: U-hat (6M)
+};
+void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos, double a,
+                      double eta, bool wall);
+void precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
+void precond_assembly(hipStream_t s, const PrecondDev &P);
+void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z);
+
+// Dense helpers for the Krylov solver (FP64, Sec. 3.1)
+void multidot(hipStream_t s, int64_t n, int k, const double *V, int64_t ldv, const double *w,
+              double *partial, double *h);
+void gemv_sub(hipStream_t s, int64_t n, int k, const double *V, int64_t ldv, const double *h,
+              double *w);
+void gemv_set(hipStream_t s, int64_t n, int k, const double *V, int64_t ldv, const double *h,
+              double *out);
+void scale_copy(hipStream_t s, int64_t n, const double *x, const double *alpha_dev, double *y);
+void axpby(hipStream_t s, int64_t n, double a, const double *x, double b, double *y);
+void arnoldi_post(hipStream_t s, int j, int m, const double *h1, const double *h2,
+                  const double *hn2, double *Hbar, double *cs, double *sn, double *g,
+                  double *out);
+void g_init(hipStream_t s, int m, const double *beta2, double *g, double *beta);
+void upper_solve(hipStream_t s, int k, int m, const double *Hbar, const double *g, double *sv);
+void rhs_assemble(hipStream_t s, int N, int M, int Nc, const double *us, const double *F,
+                  const double *B, double *b);
+
+// Position correction (Sec. 4.2, App. B)
+struct CorrectDev {
+    int A = 0, M = 0, P = 0;
+    const int *asm_body_ptr = nullptr, *asm_bodies = nullptr;
+    const int *asm_link_ptr = nullptr, *asm_links = nullptr;
+    const int *local_index = nullptr;   // body -> index inside its assembly
+    const int *pq = nullptr;
+    const double *dl_p = nullptr, *dl_q = nullptr;
+    const int64_t *ws_off = nullptr;     // per assembly workspace offsets (doubles)
+    double *ws = nullptr;
+    double *q = nullptr, *theta = nullptr;
+    int *iters = nullptr;
+    double *resid = nullptr;
+};
+void correct_positions(hipStream_t s, const CorrectDev &C, double tol, int max_iter);
+
+}  // namespace arb
+
+// ---------------------------------------------------------------- context
+struct arb_ctx {
+    arb_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    // bodies
+    int N = 0, M = 0;
+    std::vector<int> h_blob_off, h_body_of_blob, h_body_type;
+    std::vector<double> h_r_ref;
+    bool have_state = false;
+    // constraints (host copies)
+    int P = 0, Rg = 0, Nc = 0;
+    std::vector<int> h_pq, h_nproj, h_gpq;
+    std::vector<double> h_dl_p, h_dl_q, h_dldot_p, h_dldot_q, h_proj, h_gcoef, h_grhs;
+    bool topo_dirty = true;
+    int n_asm = 0;
+    int max_m = 0;
+    std::vector<int> h_asm_body_ptr, h_asm_bodies, h_asm_row_ptr, h_asm_rows;
+    // autotune cache: key = N*4 + precision*2 + wall -> slices
+    std::map<int64_t, int> slice_cache;
+    bool pc_built = false;
+    int pc_pinv = 0;
+
+    // device buffers
+    arb::DevBuf blob_off, body_of_blob, r_ref, q, theta, R9, pos, dvec, p64, hi, lo,
+        partial, row_p, row_q, row_kind, row_src, row_m, dl_p, dl_q, dldot_p, dldot_q, proj,
+        gcoef, grhs, crow, Bc, brow_ptr, brow_ent, asm_body_ptr, asm_bodies, asm_row_ptr,
+        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, Z, Nt, G, S, status, pctmp;
+    // generic scratch for host entry points and the solver
+    arb::DevBuf s_in, s_out, s_aux, s_pos;
+    arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
+    double *pinned = nullptr;  // host pinned scratch (small)
+    // correction
+    arb::DevBuf c_link_ptr, c_links, c_local, c_ws_off, c_ws, c_iters, c_resid, c_pq, c_abp, c_ab;
+    arb::DevBuf tune_out;
+};

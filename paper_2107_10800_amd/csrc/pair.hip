@@ -1,0 +1,233 @@
+// Blob-blob RPY mobility product u = M lambda on gfx950 (Sec. 2.3, Eq. RPY).
+//
+// Pair tensor, in units of 1/(8 pi eta), for r = r_i - r_j (target minus source):
+//   unbounded (Rotne-Prager / Wajnryb et al.):
+//     r >  2a: c1 I + c2 r r^T,  c1 = (1 + 2a^2/(3 r^2))/r,  c2 = (1 - 2a^2/r^2)/r^3
+//     r <= 2a: c1 = 4/(3a) - 3r/(8a^2),  c2 = 1/(8 a^2 r)  (c2 r r^T -> 0 at r = 0)
+//   no-slip wall at z = 0 (Swan & Brady): add the Faxen-regularised image of
+//   Blake's solution.  With R = (x - y*) for the source image y* = (y1,y2,-y3),
+//   e = R/|R|, h = source height, p = a^2/|R|^2, hh = h/|R|, the image is
+//     I = (1/|R|) [A^ delta + B^ e e^T + C^ e z^T + D^ z e^T + E^ z z^T]
+//   with the scalar polynomials (z = unit wall normal, e3 = e.z)
+//     A^ = -1 + 2hh^2 - 2 e3 hh + p(2e3^2 - 2/3) + p^2(2/3 - 10e3^2/3)
+//     B^ = -1 - 6hh^2 + 6 e3 hh + p(2 - 10e3^2) + p^2(70e3^2/3 - 10/3)
+//     C^ = hh(2 - 12e3^2) + 12 e3 hh^2 + e3 [p(20e3^2 - 4) + p^2(40/3 - 140e3^2/3)]
+//     D^ = 2hh - (20/3) p^2 e3
+//     E^ = -4hh^2 - 4 p e3^2 + p^2(20e3^2 - 8/3)
+//   obtained by applying (1 + a^2/6 lap_x)(1 + a^2/6 lap_y) to Blake's image
+//   system and collecting terms (the same expression at x = y is the blob's
+//   wall-corrected self mobility).
+//
+// Launch: grid (ceil(N/256) target blocks) x (source slices).  Each thread owns
+// one target; the block streams its slice's sources through LDS in tiles of
+// 256 (x,y,z + lambda), all lanes reading the same LDS word (broadcast).  Each
+// slice writes its partial sums; pair_reduce adds slices in a fixed order, so
+// results are deterministic.  FP32C: positions are split hi + lo floats so
+// that differences keep ~double accuracy; sums are float inside a tile and
+// double across tiles.
+#include "rpy_device.h"
+
+namespace arb {
+
+__global__ void prep_positions_kernel(int N, const double *__restrict__ pos,
+                                      double4 *__restrict__ p64, float4 *__restrict__ hi,
+                                      float4 *__restrict__ lo) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    p64[i] = make_double4(x, y, z, 0.0);
+    const float xh = (float)x, yh = (float)y, zh = (float)z;
+    hi[i] = make_float4(xh, yh, zh, 0.f);
+    lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
+                        (float)(z - (double)zh), 0.f);
+}
+
+template <bool WALL>
+__global__ __launch_bounds__(kTile) void pair_f32c_kernel(
+    int N, const float4 *__restrict__ hi, const float4 *__restrict__ lo,
+    const double *__restrict__ lam, int tiles_per_slice, CoefF c,
+    double *__restrict__ partial) {
+    __shared__ float4 s_hi[kTile], s_lo[kTile], s_lam[kTile];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * kTile + tid;
+    const int ic = i < N ? i : N - 1;
+    const float4 th = hi[ic], tl = lo[ic];
+    const float zi = th.z + tl.z;
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    const int ntiles = (N + kTile - 1) / kTile;
+    const int t0 = blockIdx.y * tiles_per_slice;
+    const int t1 = min(t0 + tiles_per_slice, ntiles);
+    for (int t = t0; t < t1; ++t) {
+        const int j = t * kTile + tid;
+        __syncthreads();
+        if (j < N) {
+            s_hi[tid] = hi[j];
+            s_lo[tid] = lo[j];
+            s_lam[tid] = make_float4((float)lam[3 * j], (float)lam[3 * j + 1],
+                                     (float)lam[3 * j + 2], 0.f);
+        }
+        __syncthreads();
+        const int cnt = min(kTile, N - t * kTile);
+        float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll 2
+        for (int k = 0; k < cnt; ++k) {
+            const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
+            const float dx = (th.x - sh.x) + (tl.x - sl.x);
+            const float dy = (th.y - sh.y) + (tl.y - sl.y);
+            const float dz = (th.z - sh.z) + (tl.z - sl.z);
+            const float dxy2 = fmaf(dx, dx, dy * dy);
+            const float r2 = fmaf(dz, dz, dxy2);
+            const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+            rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
+            if (WALL) {
+                const float Rz = zi + sh.z;
+                const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+                rpy_image<float>(dx, dy, Rz, sh.z, Ri, L.x, L.y, L.z, c, ax, ay, az);
+            }
+        }
+        ux += (double)ax;
+        uy += (double)ay;
+        uz += (double)az;
+    }
+    if (i < N) {
+        const size_t base = (size_t)blockIdx.y * 3 * N + i;
+        partial[base] = ux;
+        partial[base + N] = uy;
+        partial[base + 2 * (size_t)N] = uz;
+    }
+}
+
+template <bool WALL>
+__global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *__restrict__ p64,
+                                                         const double *__restrict__ lam,
+                                                         int tiles_per_slice, CoefD c,
+                                                         double *__restrict__ partial) {
+    __shared__ double4 s_p[kTile];
+    __shared__ double s_l[3 * kTile];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * kTile + tid;
+    const int ic = i < N ? i : N - 1;
+    const double4 ti = p64[ic];
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    const int ntiles = (N + kTile - 1) / kTile;
+    const int t0 = blockIdx.y * tiles_per_slice;
+    const int t1 = min(t0 + tiles_per_slice, ntiles);
+    for (int t = t0; t < t1; ++t) {
+        const int j = t * kTile + tid;
+        __syncthreads();
+        if (j < N) {
+            s_p[tid] = p64[j];
+            s_l[3 * tid] = lam[3 * j];
+            s_l[3 * tid + 1] = lam[3 * j + 1];
+            s_l[3 * tid + 2] = lam[3 * j + 2];
+        }
+        __syncthreads();
+        const int cnt = min(kTile, N - t * kTile);
+        for (int k = 0; k < cnt; ++k) {
+            const double4 sj = s_p[k];
+            const double lx = s_l[3 * k], ly = s_l[3 * k + 1], lz = s_l[3 * k + 2];
+            const double dx = ti.x - sj.x, dy = ti.y - sj.y, dz = ti.z - sj.z;
+            const double dxy2 = fma(dx, dx, dy * dy);
+            const double r2 = fma(dz, dz, dxy2);
+            const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+            rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);
+            if (WALL) {
+                const double Rz = ti.z + sj.z;
+                const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
+                rpy_image<double>(dx, dy, Rz, sj.z, Ri, lx, ly, lz, c, ux, uy, uz);
+            }
+        }
+    }
+    if (i < N) {
+        const size_t base = (size_t)blockIdx.y * 3 * N + i;
+        partial[base] = ux;
+        partial[base + N] = uy;
+        partial[base + 2 * (size_t)N] = uz;
+    }
+}
+
+__global__ void pair_reduce_kernel(int N, int slices, const double *__restrict__ partial,
+                                   double scale, double *__restrict__ out,
+                                   const double *__restrict__ U, const int *__restrict__ bob,
+                                   const double *__restrict__ dvec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int s = 0; s < slices; ++s) {
+        const size_t base = (size_t)s * 3 * N + i;
+        s0 += partial[base];
+        s1 += partial[base + N];
+        s2 += partial[base + 2 * (size_t)N];
+    }
+    s0 *= scale;
+    s1 *= scale;
+    s2 *= scale;
+    if (U) {
+        // subtract (K U)_i = u_p + w_p x d_i  (Eq. no-slip)
+        const double *Up = U + 6 * (size_t)bob[i];
+        const double d0 = dvec[3 * i], d1 = dvec[3 * i + 1], d2 = dvec[3 * i + 2];
+        s0 -= Up[0] + (Up[4] * d2 - Up[5] * d1);
+        s1 -= Up[1] + (Up[5] * d0 - Up[3] * d2);
+        s2 -= Up[2] + (Up[3] * d1 - Up[4] * d0);
+    }
+    out[3 * i] = s0;
+    out[3 * i + 1] = s1;
+    out[3 * i + 2] = s2;
+}
+
+__global__ void wall_check_kernel(int N, const double4 *__restrict__ p64, double a,
+                                  int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && !(p64[i].z > a)) atomicOr(flag, 1);
+}
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+void prep_positions(hipStream_t s, int N, const double *pos_aos, double4 *p64, float4 *hi,
+                    float4 *lo) {
+    if (N <= 0) return;
+    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, p64, hi, lo);
+}
+
+int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+                  const float4 *hi, const float4 *lo, const double *lam, double a, int slices,
+                  double *partial) {
+    if (N <= 0) return 0;
+    const int ntiles = (N + kTile - 1) / kTile;
+    if (slices > ntiles) slices = ntiles;
+    const int tps = (ntiles + slices - 1) / slices;
+    dim3 grid(ntiles, slices);
+    if (precision == ARB_FP32C) {
+        const CoefF c = make_coef<CoefF, float>((float)a);
+        if (wall)
+            pair_f32c_kernel<true><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, c, partial);
+        else
+            pair_f32c_kernel<false><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, c, partial);
+    } else {
+        const CoefD c = make_coef<CoefD, double>(a);
+        if (wall)
+            pair_f64_kernel<true><<<grid, kTile, 0, s>>>(N, p64, lam, tps, c, partial);
+        else
+            pair_f64_kernel<false><<<grid, kTile, 0, s>>>(N, p64, lam, tps, c, partial);
+    }
+    return slices;
+}
+
+void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double scale,
+                 double *out, const double *U, const int *body_of_blob, const double *dvec) {
+    if (N <= 0) return;
+    pair_reduce_kernel<<<nblk(N, 256), 256, 0, s>>>(N, slices, partial, scale, out, U,
+                                                      body_of_blob, dvec);
+}
+
+int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,
+                        int *flag_host) {
+    if (N <= 0) return 0;
+    (void)hipMemsetAsync(flag_dev, 0, sizeof(int), s);
+    wall_check_kernel<<<nblk(N, 256), 256, 0, s>>>(N, p64, a, flag_dev);
+    (void)hipMemcpyAsync(flag_host, flag_dev, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    return *flag_host;
+}
+
+}  // namespace arb

@@ -1,0 +1,553 @@
+// Block-diagonal preconditioner of Sec. 3.1 (Eq. precond, Eq. block_diag_const_res).
+//
+// Build (once per state), per body p with m = 3 n_p:
+//   pc_assemble  M_pp (m x m, row-major) from the same pair code as the mat-vec
+//   pc_chol      M_pp = L L^T in place (right-looking; column k cached in LDS)
+//   pc_inverse   X = L^-1 (stored transposed in the upper triangle), then
+//                M_pp^-1 = X^T X into its own buffer
+//   pc_body      Z_p = M_pp^-1 K_p (m x 6), R_p = K_p^T Z_p, N~_p = R_p^+
+//                (cyclic Jacobi eigen-decomposition, eigenvalues below
+//                1e-12 * max dropped: the minimum-norm velocity of bodies with
+//                a resistance-free motion)
+// per assembly a (bodies joined by constraints):
+//   pc_asm       S_a = C_a N~_a C_a^T, G~_a = S_a^-1 by Cholesky, or S_a^+ when a
+//                pivot falls below 1e-12 * max diagonal (C_a without full row rank)
+// Apply (every GMRES iteration), for residual r = (r_lam, r_U, r_phi):
+//   pc_apply1    t_p = M_pp^-1 r_lam,p;  U^_p = -N~_p (r_U,p + Z_p^T r_lam,p)
+//   pc_apply2    phi_a = G~_a (r_phi,a - C_a U^_a)
+//   pc_apply3    U_p = U^_p + N~_p (C^T phi)_p;  lam_p = t_p + Z_p U_p
+// which is the exact solution of the body-diagonal saddle problem: row 1 gives
+// lam = M~^-1 (r_lam + K U), row 2 gives N~^-1 U = -r_U - K^T M~^-1 r_lam + C^T phi,
+// row 3 gives (C N~ C^T) phi = r_phi - C U^.
+#include "rpy_device.h"
+
+namespace arb {
+
+constexpr int kMaxBodyBlobs = 512;
+constexpr int kMaxM = 3 * kMaxBodyBlobs;
+constexpr int kMaxAsmRows = 2048;
+
+// cyclic Jacobi eigen-decomposition of symmetric S (n x n, destroyed) with
+// eigenvectors accumulated in V; writes the pseudo-inverse (cutoff relative to
+// the largest |eigenvalue|) to out.  Returns the number of dropped eigenvalues.
+// Single thread.
+__device__ int sym_pinv_serial(double *S, double *V, int n, double *out, double cutoff) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < n; ++i) {
+            dia += S[i * n + i] * S[i * n + i];
+            for (int j = i + 1; j < n; ++j) off += S[i * n + j] * S[i * n + j];
+        }
+        if (!(off > 1e-32 * dia)) break;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = S[p * n + q];
+                if (apq == 0.0) continue;
+                const double tau = (S[q * n + q] - S[p * n + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                for (int k = 0; k < n; ++k) {  // S <- S J
+                    const double akp = S[k * n + p], akq = S[k * n + q];
+                    S[k * n + p] = c * akp - s * akq;
+                    S[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // S <- J^T S
+                    const double apk = S[p * n + k], aqk = S[q * n + k];
+                    S[p * n + k] = c * apk - s * aqk;
+                    S[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {  // V <- V J
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    double wmax = 0.0;
+    for (int i = 0; i < n; ++i) wmax = fmax(wmax, fabs(S[i * n + i]));
+    const double lim = cutoff * wmax;
+    int dropped = 0;
+    for (int i = 0; i < n; ++i) {
+        const double w = S[i * n + i];
+        const double inv = fabs(w) > lim ? 1.0 / w : 0.0;
+        dropped += fabs(w) > lim ? 0 : 1;
+        S[i * n + i] = inv;  // keep 1/w on the diagonal
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += V[i * n + k] * S[k * n + k] * V[j * n + k];
+            out[i * n + j] = s;
+        }
+    return dropped;
+}
+
+__global__ __launch_bounds__(256) void pc_assemble_kernel(const int *__restrict__ blob_off,
+                                                          const int64_t *__restrict__ mat_off,
+                                                          const double *__restrict__ pos, CoefD c,
+                                                          double scale, int wall, double a,
+                                                          double *__restrict__ mats,
+                                                          int *__restrict__ status) {
+    const int p = blockIdx.x;
+    const int b0 = blob_off[p], n = blob_off[p + 1] - b0, m = 3 * n;
+    double *A = mats + mat_off[p];
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx - (idx / n) * n;
+        const double *xi = pos + 3 * (size_t)(b0 + i);
+        const double *xj = pos + 3 * (size_t)(b0 + j);
+        if (wall && i == j && !(xi[2] > a)) atomicOr(&status[2], 1);
+        double B[9];
+        rpy_block_f64(xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2], xi[2], xj[2], wall != 0, c, B);
+        for (int r = 0; r < 3; ++r)
+            for (int s = 0; s < 3; ++s) A[(size_t)(3 * i + r) * m + 3 * j + s] = scale * B[3 * r + s];
+    }
+}
+
+// In-place Cholesky M = L L^T.  Lower triangle: L; upper triangle: L^T (kept
+// for coalesced access by pc_inverse); Ldiag receives diag(L).
+__global__ __launch_bounds__(256) void pc_chol_kernel(const int *__restrict__ blob_off,
+                                                      const int64_t *__restrict__ mat_off,
+                                                      double *__restrict__ mats,
+                                                      double *__restrict__ ldiag,
+                                                      int *__restrict__ status) {
+    __shared__ double col[kMaxM];
+    __shared__ int fail;
+    const int p = blockIdx.x;
+    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    double *A = mats + mat_off[p];
+    if (threadIdx.x == 0) fail = 0;
+    for (int k = 0; k < m; ++k) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double d = A[(size_t)k * m + k];
+            if (!(d > 0.0)) {
+                fail = 1;
+            } else {
+                const double s = sqrt(d);
+                A[(size_t)k * m + k] = s;
+                col[k] = s;
+            }
+        }
+        __syncthreads();
+        if (fail) break;
+        const double inv = 1.0 / col[k];
+        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) {
+            const double v = A[(size_t)i * m + k] * inv;
+            A[(size_t)i * m + k] = v;
+            A[(size_t)k * m + i] = v;
+            col[i] = v;
+        }
+        __syncthreads();
+        const int w = m - k - 1;
+        for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+            const int ii = k + 1 + idx / w, jj = k + 1 + (idx - (idx / w) * w);
+            A[(size_t)ii * m + jj] -= col[ii] * col[jj];
+        }
+    }
+    __syncthreads();
+    if (fail) {
+        if (threadIdx.x == 0) atomicMax(&status[0], p + 1);
+        return;
+    }
+    const int b0 = 3 * blob_off[p];
+    for (int k = threadIdx.x; k < m; k += blockDim.x) ldiag[b0 + k] = col[k];
+}
+
+// X = L^-1 by right-looking forward substitution on the identity, X stored
+// as X^T in the upper triangle (the diagonal of X replaces that of L, whose
+// diagonal is saved in ldiag); then Minv = X^T X.
+__global__ __launch_bounds__(256) void pc_inverse_kernel(const int *__restrict__ blob_off,
+                                                         const int64_t *__restrict__ mat_off,
+                                                         double *__restrict__ mats,
+                                                         const double *__restrict__ ldiag,
+                                                         double *__restrict__ minv,
+                                                         const int *__restrict__ status) {
+    __shared__ double colL[kMaxM];
+    __shared__ double rowX[kMaxM];
+    const int p = blockIdx.x;
+    if (status[0] != 0) return;
+    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    const double *Ld = ldiag + 3 * blob_off[p];
+    double *A = mats + mat_off[p];
+    double *Mi = minv + mat_off[p];
+    // upper triangle incl. diagonal <- identity (X^T)
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int j = idx / m, i = idx - (idx / m) * m;  // element (j, i) = X[i][j]
+        if (i >= j) A[(size_t)j * m + i] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int k = 0; k < m; ++k) {
+        __syncthreads();
+        const double inv = 1.0 / Ld[k];
+        // row k of X: X[k][j], j <= k, lives at A[j*m + k]
+        for (int j = threadIdx.x; j <= k; j += blockDim.x) {
+            const double v = A[(size_t)j * m + k] * inv;
+            A[(size_t)j * m + k] = v;
+            rowX[j] = v;
+        }
+        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) colL[i] = A[(size_t)i * m + k];
+        __syncthreads();
+        const int w = m - k - 1;
+        const int tot = w * (k + 1);
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int j = idx / w, i = k + 1 + (idx - (idx / w) * w);
+            A[(size_t)j * m + i] -= colL[i] * rowX[j];
+        }
+    }
+    __syncthreads();
+    // Minv[i][j] = sum_{k >= max(i,j)} X[k][i] X[k][j] = sum_k A[i*m+k] A[j*m+k]
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx - (idx / m) * m;
+        if (j < i) continue;
+        const double *ri = A + (size_t)i * m;
+        const double *rj = A + (size_t)j * m;
+        double s = 0.0;
+        for (int k = j; k < m; ++k) s += ri[k] * rj[k];
+        Mi[(size_t)i * m + j] = s;
+        Mi[(size_t)j * m + i] = s;
+    }
+}
+
+// restore L's diagonal (for inspection) once the inverse no longer needs X
+__global__ void pc_restore_diag_kernel(const int *__restrict__ blob_off,
+                                       const int64_t *__restrict__ mat_off,
+                                       double *__restrict__ mats,
+                                       const double *__restrict__ ldiag) {
+    const int p = blockIdx.x;
+    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    double *A = mats + mat_off[p];
+    for (int k = threadIdx.x; k < m; k += blockDim.x)
+        A[(size_t)k * m + k] = ldiag[3 * blob_off[p] + k];
+}
+
+// rows of K_p: blob i, component a: u part e_a, w part row a of -(d_i^x)
+__device__ __forceinline__ double K_entry(const double *d, int a, int c) {
+    if (c < 3) return a == c ? 1.0 : 0.0;
+    const int b = c - 3;
+    // -(d^x)[a][b] with d^x = [[0,-d2,d1],[d2,0,-d0],[-d1,d0,0]]
+    if (a == b) return 0.0;
+    if (a == 0) return b == 1 ? d[2] : -d[1];
+    if (a == 1) return b == 0 ? -d[2] : d[0];
+    return b == 0 ? d[1] : -d[0];
+}
+
+__global__ __launch_bounds__(256) void pc_body_kernel(const int *__restrict__ blob_off,
+                                                      const int64_t *__restrict__ mat_off,
+                                                      const int64_t *__restrict__ z_off,
+                                                      const double *__restrict__ minv,
+                                                      const double *__restrict__ dvec,
+                                                      double *__restrict__ Zbuf,
+                                                      double *__restrict__ Nt,
+                                                      int *__restrict__ status) {
+    __shared__ double R[36], S6[36], V6[36];
+    const int p = blockIdx.x;
+    if (status[0] != 0) return;
+    const int b0 = blob_off[p], n = blob_off[p + 1] - b0, m = 3 * n;
+    const double *Mi = minv + mat_off[p];
+    double *Z = Zbuf + z_off[p];
+    const double *d = dvec + 3 * (size_t)b0;
+    // Z = M^-1 K (m x 6), row r
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        double z[6] = {0, 0, 0, 0, 0, 0};
+        const double *row = Mi + (size_t)r * m;
+        for (int i = 0; i < n; ++i) {
+            const double m0 = row[3 * i], m1 = row[3 * i + 1], m2 = row[3 * i + 2];
+            const double *di = d + 3 * i;
+            z[0] += m0;
+            z[1] += m1;
+            z[2] += m2;
+            // sum_a M[r][3i+a] * (-(d^x))[a][b]
+            z[3] += -m1 * di[2] + m2 * di[1];
+            z[4] += m0 * di[2] - m2 * di[0];
+            z[5] += -m0 * di[1] + m1 * di[0];
+        }
+        for (int c = 0; c < 6; ++c) Z[(size_t)r * 6 + c] = z[c];
+    }
+    __syncthreads();
+    // R = K^T Z
+    if (threadIdx.x < 36) {
+        const int c1 = threadIdx.x / 6, c2 = threadIdx.x % 6;
+        double s = 0.0;
+        for (int r = 0; r < m; ++r) s += K_entry(d + 3 * (r / 3), r % 3, c1) * Z[(size_t)r * 6 + c2];
+        R[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 36; ++k) S6[k] = 0.5 * (R[k] + R[(k % 6) * 6 + k / 6]);
+        const int dropped = sym_pinv_serial(S6, V6, 6, Nt + 36 * (size_t)p, 1e-12);
+        if (dropped) atomicAdd(&status[3], 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void pc_asm_kernel(
+    const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
+    const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
+    const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
+    double *__restrict__ Sbuf, double *__restrict__ Gbuf, int *__restrict__ status) {
+    __shared__ double col[kMaxAsmRows];
+    __shared__ int fail;
+    __shared__ double dmax;
+    const int a = blockIdx.x;
+    const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
+    if (na == 0) return;
+    if (status[0] != 0) return;
+    double *S = Sbuf + 2 * asm_mat_off[a];
+    double *X = S + (size_t)na * na;
+    double *G = Gbuf + asm_mat_off[a];
+    for (int pass = 0; pass < 2; ++pass) {
+        // S = C_a N~ C_a^T
+        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+            const int k = idx / na, l = idx - (idx / na) * na;
+            const int rk = asm_rows[r0 + k], rl = asm_rows[r0 + l];
+            double s = 0.0;
+            for (int sk = 0; sk < 2; ++sk) {
+                const int bk = sk ? row_q[rk] : row_p[rk];
+                if (bk < 0) continue;
+                const double *ck = crow + 12 * (size_t)rk + 6 * sk;
+                for (int sl = 0; sl < 2; ++sl) {
+                    const int bl = sl ? row_q[rl] : row_p[rl];
+                    if (bl != bk) continue;
+                    const double *cl = crow + 12 * (size_t)rl + 6 * sl;
+                    const double *Nb = Nt + 36 * (size_t)bk;
+                    for (int u = 0; u < 6; ++u) {
+                        double t = 0.0;
+                        for (int v = 0; v < 6; ++v) t += Nb[u * 6 + v] * cl[v];
+                        s += ck[u] * t;
+                    }
+                }
+            }
+            S[(size_t)k * na + l] = s;
+        }
+        __syncthreads();
+        if (pass == 1) {
+            // rank-deficient: symmetric pseudo-inverse (Sec. 3.1)
+            if (threadIdx.x == 0) {
+                sym_pinv_serial(S, X, na, G, 1e-12);
+                atomicAdd(&status[1], 1);
+            }
+            return;
+        }
+        if (threadIdx.x == 0) {
+            double mx = 0.0;
+            for (int k = 0; k < na; ++k) mx = fmax(mx, S[(size_t)k * na + k]);
+            dmax = mx;
+            fail = 0;
+        }
+        // Cholesky in place (lower = L, upper = L^T), pivot test relative to max diagonal
+        for (int k = 0; k < na; ++k) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const double dd = S[(size_t)k * na + k];
+                if (!(dd > 1e-12 * dmax)) {
+                    fail = 1;
+                } else {
+                    const double s = sqrt(dd);
+                    S[(size_t)k * na + k] = s;
+                    col[k] = s;
+                }
+            }
+            __syncthreads();
+            if (fail) break;
+            const double inv = 1.0 / col[k];
+            for (int i = k + 1 + threadIdx.x; i < na; i += blockDim.x) {
+                const double v = S[(size_t)i * na + k] * inv;
+                S[(size_t)i * na + k] = v;
+                S[(size_t)k * na + i] = v;
+                col[i] = v;
+            }
+            __syncthreads();
+            const int w = na - k - 1;
+            for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+                const int ii = k + 1 + idx / w, jj = k + 1 + (idx - (idx / w) * w);
+                S[(size_t)ii * na + jj] -= col[ii] * col[jj];
+            }
+        }
+        __syncthreads();
+        if (fail) continue;  // recompute S, then pseudo-inverse
+        // X = L^-1 (row-major lower), column by column of the identity
+        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+            const int i = idx / na, j = idx - (idx / na) * na;
+            X[idx] = (i == j) ? 1.0 : 0.0;
+        }
+        for (int k = 0; k < na; ++k) {
+            __syncthreads();
+            const double inv = 1.0 / S[(size_t)k * na + k];
+            for (int j = threadIdx.x; j <= k; j += blockDim.x) X[(size_t)k * na + j] *= inv;
+            __syncthreads();
+            const int w = na - k - 1;
+            for (int idx = threadIdx.x; idx < w * (k + 1); idx += blockDim.x) {
+                const int i = k + 1 + idx / (k + 1), j = idx - (idx / (k + 1)) * (k + 1);
+                X[(size_t)i * na + j] -= S[(size_t)i * na + k] * X[(size_t)k * na + j];
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+            const int i = idx / na, j = idx - (idx / na) * na;
+            double s = 0.0;
+            for (int k = (i > j ? i : j); k < na; ++k)
+                s += X[(size_t)k * na + i] * X[(size_t)k * na + j];
+            G[idx] = s;
+        }
+        return;
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) s += red[k];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void pc_apply1_kernel(
+    int N, const int *__restrict__ blob_off, const int64_t *__restrict__ mat_off,
+    const int64_t *__restrict__ z_off, const double *__restrict__ minv,
+    const double *__restrict__ Zbuf, const double *__restrict__ Nt, const double *__restrict__ r,
+    double *__restrict__ z, double *__restrict__ uhat) {
+    __shared__ double x[kMaxM];
+    __shared__ double red[8];
+    __shared__ double w6[6];
+    const int p = blockIdx.x;
+    const int b0 = blob_off[p], m = 3 * (blob_off[p + 1] - b0);
+    const double *Mi = minv + mat_off[p];
+    const double *Z = Zbuf + z_off[p];
+    const double *rl = r + 3 * (size_t)b0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) x[i] = rl[i];
+    __syncthreads();
+    // t = Minv r_lam (Minv symmetric: column access is coalesced)
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += Mi[(size_t)k * m + i] * x[k];
+        z[3 * (size_t)b0 + i] = s;
+    }
+    // Z^T r_lam
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < m; i += blockDim.x)
+        for (int c = 0; c < 6; ++c) acc[c] += Z[(size_t)i * 6 + c] * x[i];
+    for (int c = 0; c < 6; ++c) {
+        const double s = block_sum(acc[c], red);
+        if (threadIdx.x == 0) w6[c] = s + r[3 * (size_t)N + 6 * (size_t)p + c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double *Nb = Nt + 36 * (size_t)p;
+        double s = 0.0;
+        for (int c = 0; c < 6; ++c) s += Nb[threadIdx.x * 6 + c] * w6[c];
+        uhat[6 * (size_t)p + threadIdx.x] = -s;
+    }
+}
+
+__global__ __launch_bounds__(256) void pc_apply2_kernel(
+    int N, int M, const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
+    const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
+    const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Gbuf,
+    const double *__restrict__ r, const double *__restrict__ uhat, double *__restrict__ z) {
+    __shared__ double y[kMaxAsmRows];
+    const int a = blockIdx.x;
+    const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
+    if (na == 0) return;
+    const double *G = Gbuf + asm_mat_off[a];
+    const size_t off_phi = 3 * (size_t)N + 6 * (size_t)M;
+    for (int k = threadIdx.x; k < na; k += blockDim.x) {
+        const int rk = asm_rows[r0 + k];
+        const double *c = crow + 12 * (size_t)rk;
+        const double *Up = uhat + 6 * (size_t)row_p[rk];
+        double s = 0.0;
+        for (int u = 0; u < 6; ++u) s += c[u] * Up[u];
+        const int q = row_q[rk];
+        if (q >= 0) {
+            const double *Uq = uhat + 6 * (size_t)q;
+            for (int u = 0; u < 6; ++u) s += c[6 + u] * Uq[u];
+        }
+        y[k] = r[off_phi + rk] - s;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < na; k += blockDim.x) {
+        double s = 0.0;
+        for (int l = 0; l < na; ++l) s += G[(size_t)k * na + l] * y[l];
+        z[off_phi + asm_rows[r0 + k]] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void pc_apply3_kernel(
+    int N, int M, const int *__restrict__ blob_off, const int64_t *__restrict__ z_off,
+    const double *__restrict__ Zbuf, const double *__restrict__ Nt,
+    const int *__restrict__ brow_ptr, const int *__restrict__ brow_ent,
+    const double *__restrict__ crow, const double *__restrict__ uhat, double *__restrict__ z,
+    int has_rows) {
+    __shared__ double U[6];
+    __shared__ double f[6];
+    const int p = blockIdx.x;
+    const size_t off_phi = 3 * (size_t)N + 6 * (size_t)M;
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        if (has_rows) {
+            for (int e = brow_ptr[p]; e < brow_ptr[p + 1]; ++e) {
+                const int ent = brow_ent[e];
+                const int row = ent >> 1, side = ent & 1;
+                s += z[off_phi + row] * crow[12 * (size_t)row + 6 * side + threadIdx.x];
+            }
+        }
+        f[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double *Nb = Nt + 36 * (size_t)p;
+        double s = uhat[6 * (size_t)p + threadIdx.x];
+        for (int c = 0; c < 6; ++c) s += Nb[threadIdx.x * 6 + c] * f[c];
+        U[threadIdx.x] = s;
+        z[3 * (size_t)N + 6 * (size_t)p + threadIdx.x] = s;
+    }
+    __syncthreads();
+    const int b0 = blob_off[p], m = 3 * (blob_off[p + 1] - b0);
+    const double *Z = Zbuf + z_off[p];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < 6; ++c) s += Z[(size_t)i * 6 + c] * U[c];
+        z[3 * (size_t)b0 + i] += s;
+    }
+}
+
+void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos, double a, double eta,
+                      bool wall) {
+    if (P.M <= 0) return;
+    const CoefD c = make_coef<CoefD, double>(a);
+    pc_assemble_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, pos, c, 1.0 / (8 * kPi * eta),
+                                           wall ? 1 : 0, a, P.mats, P.status);
+}
+
+void precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int /*max_m*/) {
+    if (P.M <= 0) return;
+    pc_chol_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.status);
+    pc_inverse_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.minv,
+                                          P.status);
+    pc_restore_diag_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag);
+    pc_body_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.z_off, P.minv, dvec, P.Z, P.Nt,
+                                       P.status);
+}
+
+void precond_assembly(hipStream_t s, const PrecondDev &P) {
+    if (P.A <= 0) return;
+    pc_asm_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p, P.row_q,
+                                      P.crow, P.Nt, P.S, P.G, P.status);
+}
+
+void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z) {
+    if (P.M <= 0) return;
+    pc_apply1_kernel<<<P.M, 256, 0, s>>>(N, P.blob_off, P.mat_off, P.z_off, P.minv, P.Z, P.Nt, r, z,
+                                         P.tmp);
+    if (P.A > 0)
+        pc_apply2_kernel<<<P.A, 256, 0, s>>>(N, P.M, P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
+                                             P.row_p, P.row_q, P.crow, P.G, r, P.tmp, z);
+    pc_apply3_kernel<<<P.M, 256, 0, s>>>(N, P.M, P.blob_off, P.z_off, P.Z, P.Nt, P.brow_ptr,
+                                         P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);
+}
+
+}  // namespace arb

@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every entry point include/arb.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2107_10800_amd import arb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "arb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(arb_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_symbols():
+    assert sorted(arb.SYMBOLS) == declared()
+
+
+def test_library_exports_every_symbol():
+    if not os.path.exists(arb.LIB_PATH):
+        pytest.fail("libarb.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(arb.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_bad_options_rejected_before_device():
+    lib = arb.load()
+    for kw in (dict(a=-1.0), dict(eta=0.0), dict(tol=0.0), dict(restart=0), dict(restart=1000),
+               dict(precision=7), dict(precond=9), dict(max_iter=0)):
+        base = dict(device=0, precision=0, wall=0, eta=1.0, a=1.0, tol=1e-8, restart=50,
+                    max_iter=100, precond=1, slices=0)
+        base.update(kw)
+        opt = arb.arb_options(**base)
+        h = ctypes.c_void_p()
+        assert lib.arb_create(ctypes.byref(h), ctypes.byref(opt)) == arb.ARB_E_ARG
+        assert not h.value
+    assert lib.arb_create(None, None) == arb.ARB_E_ARG
+
+
+def test_null_context_calls_are_errors():
+    lib = arb.load()
+    assert lib.arb_set_state(None, None, None) == arb.ARB_E_ARG
+    assert lib.arb_solve(None, None, None, None, None, None, None, None) == arb.ARB_E_ARG
+    assert lib.arb_last_error(None) == b"null context"

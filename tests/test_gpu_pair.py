@@ -1,0 +1,102 @@
+"""GPU parity of the blob mobility product u = M lambda (Sec. 2.3) against the oracle.
+
+Tolerances: relative L2 <= 1e-12 for the FP64 pair sum, <= 1e-5 for FP32C.
+"""
+import numpy as np
+import pytest
+
+from oracle import rpy
+from paper_2107_10800_amd import arb
+from paper_2107_10800_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {arb.ARB_FP64: 1e-12, arb.ARB_FP32C: 1e-5}
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    out = {}
+    for prec in (arb.ARB_FP64, arb.ARB_FP32C):
+        for wall in (False, True):
+            out[(prec, wall)] = arb.arb_create(precision=prec, wall=wall)
+    yield out
+    for c in out.values():
+        arb.arb_destroy(c)
+
+
+@pytest.mark.parametrize("n", [1, 7, 256, 300, 1000])
+@pytest.mark.parametrize("wall", [False, True])
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_small_clouds(ctxs, n, wall, prec):
+    # overlapping random clouds: near and far branches, several tiles, ragged tail
+    cl = W.random_blobs(n, seed=100 + n)
+    print(f"pair n={n} wall={wall} prec={prec}", flush=True)
+    u = arb.arb_rpy_apply(ctxs[(prec, wall)], cl["pos"], cl["lam"])
+    uo = rpy.mobility_apply(cl["pos"], cl["lam"], 1.0, 1.0, wall)
+    assert rel(u, uo) <= TOL[prec]
+
+
+def test_self_mobility_single_blob(ctxs):
+    pos = np.array([[0.3, -1.0, 2.5]])
+    lam = np.array([1.0, -2.0, 0.5])
+    u = arb.arb_rpy_apply(ctxs[(arb.ARB_FP64, False)], pos, lam)
+    assert np.allclose(u, lam / (6 * np.pi), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("slices", [1, 3, 16])
+def test_slices_do_not_change_result(slices):
+    cl = W.random_blobs(2000, seed=9, box=30.0)
+    outs = []
+    for sl in (slices, 0):
+        c = arb.arb_create(precision=arb.ARB_FP64, wall=True, slices=sl)
+        try:
+            outs.append(arb.arb_rpy_apply(c, cl["pos"], cl["lam"]))
+            again = arb.arb_rpy_apply(c, cl["pos"], cl["lam"])
+            assert np.array_equal(outs[-1], again)  # deterministic reduction order
+        finally:
+            arb.arb_destroy(c)
+    assert rel(outs[0], outs[1]) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_slab_full_size_sampled(ctxs, prec):
+    # the 16,384-blob wall slab at full size, launch shape as in the benchmark;
+    # the oracle evaluates sampled rows exactly against every source
+    sl = W.slab()
+    N = len(sl["pos"])
+    print(f"pair slab N={N} prec={prec}", flush=True)
+    u = arb.arb_rpy_apply(ctxs[(prec, True)], sl["pos"], sl["lam"]).reshape(N, 3)
+    rng = np.random.default_rng(0)
+    tg = np.unique(np.concatenate([[0, 255, 256, N - 1], rng.integers(0, N, 28)]))
+    uo = rpy.mobility_apply(sl["pos"], sl["lam"], 1.0, 1.0, True, targets=tg)
+    assert rel(u[tg], uo) <= TOL[prec]
+
+
+def test_device_pointer_entry_point_matches_host(ctxs):
+    import torch
+
+    cl = W.random_blobs(777, seed=3)
+    c = ctxs[(arb.ARB_FP32C, True)]
+    u_host = arb.arb_rpy_apply(c, cl["pos"], cl["lam"])
+    pos = torch.tensor(cl["pos"], dtype=torch.float64, device="cuda")
+    lam = torch.tensor(cl["lam"], dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(lam)
+    stream = torch.cuda.current_stream()
+    arb.arb_rpy_apply_dev(c, 777, pos, lam, u, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy().ravel(), u_host)
+
+
+def test_below_wall_rejected(ctxs):
+    pos = np.array([[0.0, 0.0, 3.0], [1.0, 1.0, 0.9]])
+    with pytest.raises(arb.ArbError) as e:
+        arb.arb_rpy_apply(ctxs[(arb.ARB_FP64, True)], pos, np.ones(6))
+    assert e.value.code == arb.ARB_E_BELOW_WALL
+    with pytest.raises(arb.ArbError) as e:
+        arb.arb_rpy_apply(ctxs[(arb.ARB_FP64, False)], pos, np.array([1, np.nan, 0, 0, 0, 0.0]))
+    assert e.value.code == arb.ARB_E_NAN
