@@ -1,0 +1,249 @@
+"""Benchmark of the wall-corrected RPY blob-pair product and the GMRES solve on one GPU.
+
+Headline (`value`): wall-RPY blob-pair interactions per second for one mobility
+product u = M lambda over the 16,384-blob slab above a no-slip wall
+(400a x 400a x [1.5a, 20a], minimum separation 2a, lambda ~ N(0,1)), FP32
+pair sums with hi/lo positions and double accumulation across tiles.  One step
+= one full product (all N^2 ordered pairs, self included); inputs resident on
+the GPU before timing.
+
+Also reported: the same product in FP64, the dominant kernel's roofline
+(algorithmic flops / its HIP-event-timed duration), the CPU oracle on a bounded
+sample, and the time per GMRES solve to 1e-6 on the 1,024-bacteria suspension
+above a wall (FP32 pair sums, FP64 Krylov, block preconditioner).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--pmc-copy]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic flops per ordered pair, counted from the kernel expressions
+# (FMA = 2, add/sub/mul = 1, reciprocal square root = 1; selects and compares 0)
+FLOPS_PER_PAIR = {("f32c", True): 136, ("f32c", False): 45, ("f64", True): 130,
+                  ("f64", False): 39}
+# MI355X published vector peaks: 256 CUs x 2.4 GHz x 256 FP32 (128 FP64) flop/clk/CU
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+# HBM traffic of one timed launch from the FETCH_SIZE / WRITE_SIZE runs recorded in
+# profiles/pair_f32c_wall_slab16384.md, scaled by the counts of a 256 MiB copy; valid
+# only for the kernel source it was measured on
+TRAFFIC = {"pair_src_sha256_16": "ef7c7d3e765e2be7", "fetch_kib": 3605.2, "write_kib": 24576.0,
+           "copy_fetch_kib": 131091.4, "copy_write_kib": 262144.0, "copy_kib": 262144.0}
+
+
+def measured_traffic():
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2107_10800_amd", "csrc", "pair.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != TRAFFIC["pair_src_sha256_16"]:
+        return None
+    t = TRAFFIC
+    kib = (t["fetch_kib"] * t["copy_kib"] / t["copy_fetch_kib"]
+           + t["write_kib"] * t["copy_kib"] / t["copy_write_kib"])
+    return kib * 1024.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sl, budget_s=15.0):
+    """The oracle as it stands on a bounded sample: all 16,384 sources for a
+    block of targets, grown until about budget_s seconds of CPU time."""
+    import numpy as np
+    import psutil
+
+    from oracle import rpy
+
+    pos, lam = sl["pos"], sl["lam"]
+    N = len(pos)
+    rpy.mobility_apply(pos, lam, 1.0, 1.0, True, targets=[0])   # symbolic set-up, untimed
+    proc = psutil.Process()
+    ntg, elapsed, cpu = 8, 0.0, 0.0
+    while True:
+        tg = np.arange(ntg) * (N // ntg)
+        c0 = sum(proc.cpu_times()[:2])
+        t0 = time.perf_counter()
+        rpy.mobility_apply(pos, lam, 1.0, 1.0, True, targets=tg)
+        elapsed = time.perf_counter() - t0
+        cpu = sum(proc.cpu_times()[:2]) - c0
+        if elapsed > budget_s / 4 or ntg >= 1024:
+            break
+        ntg *= 4
+    pairs = ntg * N
+    return {"value": pairs / elapsed, "unit": "pairs/s",
+            "cores": max(1, round(cpu / elapsed)), "kind": "oracle",
+            "sample": f"{ntg} target blobs x all {N} sources of the wall slab "
+                      f"(float64 numpy, symbolic wall image), {elapsed:.1f} s"}
+
+
+def matvec_bench(torch, arb, sl, precision, steps, warmup):
+    import numpy as np
+
+    N = len(sl["pos"])
+    ctx = arb.arb_create(precision=precision, wall=True)
+    try:
+        dev = torch.device("cuda")
+        pos = torch.tensor(sl["pos"], dtype=torch.float64, device=dev)
+        lam = torch.tensor(sl["lam"], dtype=torch.float64, device=dev)
+        u = torch.zeros_like(lam)
+        # an explicit stream: the library takes a null handle as "its own stream"
+        stream = torch.cuda.Stream()
+        sh = stream.cuda_stream
+        torch.cuda.synchronize()
+        for _ in range(max(warmup, 1)):          # includes the launch-shape autotune
+            arb.arb_rpy_apply_dev(ctx, N, pos, lam, u, stream=sh)
+        torch.cuda.synchronize()
+        arb.arb_profile_read(ctx)
+        arb.arb_profile(ctx, True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            arb.arb_rpy_apply_dev(ctx, N, pos, lam, u, stream=sh)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        kms, launches = arb.arb_profile_read(ctx)
+        arb.arb_profile(ctx, False)
+        slices = arb.arb_get_slices(ctx, N)
+        out = u.cpu().numpy()
+        return dict(ms_per_step=ms / steps, wall_s=wall, kernel_ms=kms / max(launches, 1),
+                    launches=launches, slices=slices, u=out)
+    finally:
+        arb.arb_destroy(ctx)
+
+
+def solve_bench(torch, arb, W, precision, reps=2):
+    wl = W.bacteria(n_bact=1024, seed=3)
+    ctx = arb.context_for(wl, precision=precision, tol=1e-6, restart=100, max_iter=400)
+    try:
+        dev = torch.device("cuda")
+        F = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
+        n = wl.n_unknowns
+        y = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        sh = torch.cuda.Stream().cuda_stream
+        rc, info = arb.arb_solve_dev(ctx, F, None, y, warm=False, stream=sh)   # warm-up
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = arb.arb_solve_dev(ctx, F, None, y, warm=False, stream=sh)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return dict(workload=f"bacteria above a wall: {wl.N // 122} x (42-blob head + 80-blob "
+                             f"flagellum), N={wl.N}, M={wl.M}, Nc={wl.n_rows}, n={n}",
+                    precision="f32c pair sums, f64 Krylov" if precision else "f64",
+                    ms_per_solve=1e3 * min(times), iterations=info["iterations"],
+                    rel_residual=info["rel_residual"],
+                    rel_residual_fp64=info["rel_residual_fp64"],
+                    precond_build_ms=info["t_build_ms"], status=rc,
+                    pairs_per_matvec=wl.N ** 2)
+    finally:
+        arb.arb_destroy(ctx)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2107_10800_amd import arb
+    from paper_2107_10800_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    arb.load()
+    sl = W.slab()
+    N = len(sl["pos"])
+    if args.pmc_copy:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 268435456 bytes read, 268435456 bytes written")
+    log(f"bench: wall slab N={N} f32c, {args.steps} steps")
+    r32 = matvec_bench(torch, arb, sl, arb.ARB_FP32C, args.steps, args.warmup)
+    log(f"bench: f32c {r32['ms_per_step']:.4f} ms/step, kernel {r32['kernel_ms']:.4f} ms, "
+        f"slices {r32['slices']}")
+    r64 = matvec_bench(torch, arb, sl, arb.ARB_FP64, max(args.steps // 4, 5), 2)
+    log(f"bench: f64 {r64['ms_per_step']:.4f} ms/step")
+    err = None
+    if not args.no_check:
+        # spot parity against the oracle on a few rows (guards the timed output)
+        from oracle import rpy
+        tg = np.array([0, N // 3, N - 1])
+        uo = rpy.mobility_apply(sl["pos"], sl["lam"], 1.0, 1.0, True, targets=tg)
+        u = r32["u"].reshape(N, 3)[tg]
+        err = float(np.linalg.norm(u - uo) / np.linalg.norm(uo))
+    pairs = float(N) * N
+    value = pairs / (r32["ms_per_step"] * 1e-3)
+    flops = FLOPS_PER_PAIR[("f32c", True)] * pairs
+    achieved = flops / (r32["kernel_ms"] * 1e-3) / 1e12
+    res = {
+        "metric": "wall-RPY blob-pair interactions/s",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wall-RPY mobility product, 16384 blobs in 400a x 400a x "
+                               "[1.5a,20a] above a no-slip wall, min separation 2a, "
+                               "lambda ~ N(0,1); one product per step",
+                   "N": N, "pairs_per_step": int(pairs), "slices": r32["slices"],
+                   "parity_rel_err_sampled": err},
+        "roofline": {"bound": "alu", "kernel": "pair_f32c_kernel<wall>",
+                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "flops_per_pair": FLOPS_PER_PAIR[("f32c", True)],
+                     "kernel_ms": r32["kernel_ms"], "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch"},
+        "fp64": {"value": pairs / (r64["ms_per_step"] * 1e-3), "unit": "pairs/s",
+                 "ms_per_step": r64["ms_per_step"], "kernel_ms": r64["kernel_ms"],
+                 "achieved_tflops": FLOPS_PER_PAIR[("f64", True)] * pairs
+                 / (r64["kernel_ms"] * 1e-3) / 1e12,
+                 "frac_of_fp64_peak": FLOPS_PER_PAIR[("f64", True)] * pairs
+                 / (r64["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
+    }
+    if not args.no_solve:
+        log("bench: GMRES solve, bacteria 1024, f32c")
+        res["gmres"] = solve_bench(torch, arb, W, arb.ARB_FP32C)
+        log(f"bench: solve {res['gmres']['ms_per_solve']:.1f} ms, "
+            f"{res['gmres']['iterations']} iterations")
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        res["cpu_baseline"] = cpu_baseline(sl)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

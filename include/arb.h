@@ -76,8 +76,9 @@ typedef struct {
 typedef struct {
     int    iterations;      /* Arnoldi steps over all cycles                   */
     int    restarts;        /* completed cycles                                */
-    double rel_residual;    /* true ||b - A y|| / ||b|| of the returned iterate */
-    double rel_residual_fp64; /* same, with the FP64 pair sum (FP32C runs)     */
+    double rel_residual;    /* ||b - A y|| / ||b|| of the returned iterate with
+                               the context's pair-sum precision               */
+    double rel_residual_fp64; /* same with the FP64 pair sum (the stopping test) */
     double t_build_ms;      /* preconditioner build                            */
     double t_solve_ms;      /* Krylov iterations incl. final residual          */
     int    pinv_used;       /* number of blocks inverted by pseudo-inverse     */
@@ -170,7 +171,10 @@ int arb_precond_apply(arb_ctx *ctx, const double *r, double *z);
 int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde);
 
 /* -------------------------------------------------------------- solve
- * Solve A y = b with b = [u_s; -F; B] (Eq. linear_system).  F: 6M;
+ * Solve A y = b with b = [u_s; -F; B] (Eq. linear_system) by restarted,
+ * right-preconditioned GMRES to ||b - A y|| <= tol ||b|| in FP64.  With
+ * ARB_FP32C the solve is GMRES iterative refinement: inner GMRES with the FP32
+ * pair sum on the correction equation, residuals formed in FP64.  F: 6M;
  * u_slip: 3N or NULL (zero); y0: n or NULL (zero initial guess, Sec. 3.2.1
  * warm start otherwise).  Outputs (may be NULL): U 6M, phi N_c, lambda 3N.
  * info may be NULL. */
@@ -196,6 +200,14 @@ int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double
  * link residual ||g||_2 per assembly. */
 int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q,
                           double *theta, int *iters, double *resid);
+
+/* -------------------------------------------------------------- timing
+ * When enabled, HIP events are recorded on the launching stream around every
+ * launch of the blob-pair kernel (the dominant kernel).  arb_profile_read
+ * waits for the recorded events, returns the summed kernel time (ms) and the
+ * launch count since the last read, and clears them. */
+int arb_profile(arb_ctx *ctx, int enable);
+int arb_profile_read(arb_ctx *ctx, double *pair_ms, int *pair_launches);
 
 #ifdef __cplusplus
 }

@@ -38,7 +38,8 @@ SYMBOLS = [
     "arb_mobility_apply", "arb_mobility_apply_dev", "arb_rpy_apply_dev", "arb_rpy_apply",
     "arb_system_apply", "arb_K_apply", "arb_KT_apply", "arb_constraint_rows",
     "arb_precond_build", "arb_precond_apply", "arb_precond_block", "arb_solve",
-    "arb_solve_dev", "arb_euler_update", "arb_correct_positions",
+    "arb_solve_dev", "arb_euler_update", "arb_correct_positions", "arb_profile",
+    "arb_profile_read",
 ]
 
 
@@ -111,6 +112,8 @@ def load():
         "arb_euler_update": (C.c_int, [_P, _DP, C.c_double, _DP, _DP]),
         "arb_correct_positions": (C.c_int, [_P, C.c_double, C.c_int, _DP, _DP,
                                             C.POINTER(C.c_int), _DP]),
+        "arb_profile": (C.c_int, [_P, C.c_int]),
+        "arb_profile_read": (C.c_int, [_P, _DP, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -349,6 +352,18 @@ def arb_correct_positions(ctx, tol=1e-10, max_iter=50):
     _check(ctx, load().arb_correct_positions(ctx, float(tol), int(max_iter), qp, tp,
                                              C.byref(it), C.byref(res)))
     return q.reshape(M, 3), t.reshape(M, 4), it.value, res.value
+
+
+def arb_profile(ctx, enable=True):
+    return _check(ctx, load().arb_profile(ctx, int(bool(enable))))
+
+
+def arb_profile_read(ctx):
+    """(summed pair-kernel ms, launches) since the last read."""
+    ms = C.c_double()
+    n = C.c_int()
+    _check(ctx, load().arb_profile_read(ctx, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 # ------------------------------------------------------------------ convenience

@@ -226,8 +226,18 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
              const float4 *lo, const double *lam, double *out, const double *U, const int *bob,
              const double *dvec, int precision, bool wall, int slices) {
     HIPCHK(ctx->partial.ensure((size_t)slices * 3 * N * sizeof(double)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->prof) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+    }
     const int used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, slices,
                                        ctx->partial.as<double>());
+    if (ctx->prof) {
+        HIPCHK(hipEventRecord(e1, s));
+        ctx->prof_ev.emplace_back(e0, e1);
+    }
     arb::pair_reduce(s, N, used, ctx->partial.as<double>(), 1.0 / (8.0 * arb::kPi * ctx->opt.eta),
                      out, U, bob, dvec);
     return 0;
@@ -381,39 +391,126 @@ double now_ms() {
 }
 
 // ---------------------------------------------------------------- GMRES (Sec. 3.1)
-int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int warm,
-              arb_solve_info *info, hipStream_t s) {
-    TRY(ready(ctx));
-    const int N = ctx->N, M = ctx->M, Nc = ctx->Nc;
+struct Krylov {
+    int64_t n;
+    int m, nch;
+    double *b, *r, *z, *w, *V, *H, *cs, *sn, *g, *sv, *part, *h1, *h2, *sc;
+};
+
+int krylov_buffers(arb_ctx *ctx, Krylov &K) {
     const int64_t n = n_unknowns(ctx);
     const int m = ctx->opt.restart;
-    const int prec = ctx->opt.precision;
-    const double tol = ctx->opt.tol;
-    const int nch = (int)((n + 2047) / 2048);
+    K.n = n;
+    K.m = m;
+    K.nch = (int)((n + 2047) / 2048);
     HIPCHK(ctx->kb.ensure(n * sizeof(double)));
     HIPCHK(ctx->kr.ensure(n * sizeof(double)));
     HIPCHK(ctx->kz.ensure(n * sizeof(double)));
     HIPCHK(ctx->kw.ensure(n * sizeof(double)));
+    HIPCHK(ctx->kt.ensure(2 * n * sizeof(double)));
     HIPCHK(ctx->kv.ensure((size_t)(m + 1) * n * sizeof(double)));
     HIPCHK(ctx->kH.ensure((size_t)(m + 1) * m * sizeof(double)));
     HIPCHK(ctx->kcs.ensure((size_t)(m + 1) * sizeof(double)));
     HIPCHK(ctx->ksn.ensure((size_t)(m + 1) * sizeof(double)));
     HIPCHK(ctx->kg.ensure((size_t)(m + 2) * sizeof(double)));
-    HIPCHK(ctx->khcol.ensure((size_t)(2 * (m + 2) + 8) * sizeof(double)));
+    HIPCHK(ctx->khcol.ensure((size_t)(2 * (m + 2) + 16) * sizeof(double)));
     HIPCHK(ctx->ksv.ensure((size_t)(m + 1) * sizeof(double)));
-    HIPCHK(ctx->kpart.ensure((size_t)(m + 1) * nch * sizeof(double)));
-    double *b = ctx->kb.as<double>(), *r = ctx->kr.as<double>(), *z = ctx->kz.as<double>(),
-           *w = ctx->kw.as<double>(), *V = ctx->kv.as<double>(), *H = ctx->kH.as<double>(),
-           *cs = ctx->kcs.as<double>(), *sn = ctx->ksn.as<double>(), *g = ctx->kg.as<double>(),
-           *sv = ctx->ksv.as<double>(), *part = ctx->kpart.as<double>();
-    double *h1 = ctx->khcol.as<double>(), *h2 = h1 + (m + 2), *sc = h2 + (m + 2);  // sc: 8 scalars
+    HIPCHK(ctx->kpart.ensure((size_t)(m + 1) * K.nch * sizeof(double)));
+    K.b = ctx->kb.as<double>();
+    K.r = ctx->kr.as<double>();
+    K.z = ctx->kz.as<double>();
+    K.w = ctx->kw.as<double>();
+    K.V = ctx->kv.as<double>();
+    K.H = ctx->kH.as<double>();
+    K.cs = ctx->kcs.as<double>();
+    K.sn = ctx->ksn.as<double>();
+    K.g = ctx->kg.as<double>();
+    K.sv = ctx->ksv.as<double>();
+    K.part = ctx->kpart.as<double>();
+    K.h1 = ctx->khcol.as<double>();
+    K.h2 = K.h1 + (m + 2);
+    K.sc = K.h2 + (m + 2);  // 16 device scalars
+    return 0;
+}
+
+int dev_norm(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *x, int slot, double *out) {
+    arb::multidot(s, K.n, 1, x, K.n, x, K.part, K.sc + slot);
+    HIPCHK(hipMemcpyAsync(ctx->pinned, K.sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = std::sqrt(ctx->pinned[0]);
+    return 0;
+}
+
+// Restarted GMRES on A P^-1 (right preconditioning) for A y = rhs, starting
+// from the y already in place with its residual r = rhs - A y in K.r.  Stops
+// when the residual of the operator in `prec` is <= tol_abs, or after the
+// iteration budget.  Returns the final residual norm in *res (same operator).
+int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double *y,
+               double tol_abs, int prec, int max_iter, int *total, int *restarts,
+               double hist_scale, arb_solve_info *inf, double *res) {
+    const int64_t n = K.n;
+    const int m = K.m;
     double *pin = ctx->pinned;
+    auto push = [&](double v) {
+        if (inf->history_len < 1024) inf->history[inf->history_len++] = v;
+    };
+    for (;;) {
+        arb::multidot(s, n, 1, K.r, n, K.r, K.part, K.sc + 2);
+        arb::g_init(s, m, K.sc + 2, K.g, K.sc + 3);  // g = [beta, 0, ...], sc[3] = beta
+        HIPCHK(hipMemcpyAsync(pin, K.sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double beta = pin[0];
+        if (!std::isfinite(beta)) return fail(ctx, ARB_E_NAN, "GMRES residual is not finite");
+        *res = beta;
+        push(beta * hist_scale);
+        if (beta <= tol_abs || *total >= max_iter) break;
+        arb::scale_copy(s, n, K.r, K.sc + 3, K.V);  // v_0 = r / beta
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = K.V + (size_t)j * n;
+            TRY(precond_apply(ctx, s, vj, K.z));
+            TRY(system_apply(ctx, s, K.z, K.w, prec));
+            // classical Gram-Schmidt, twice
+            arb::multidot(s, n, j + 1, K.V, n, K.w, K.part, K.h1);
+            arb::gemv_sub(s, n, j + 1, K.V, n, K.h1, K.w);
+            arb::multidot(s, n, j + 1, K.V, n, K.w, K.part, K.h2);
+            arb::gemv_sub(s, n, j + 1, K.V, n, K.h2, K.w);
+            arb::multidot(s, n, 1, K.w, n, K.w, K.part, K.sc + 4);
+            arb::arnoldi_post(s, j, m, K.h1, K.h2, K.sc + 4, K.H, K.cs, K.sn, K.g, K.sc + 5);
+            HIPCHK(hipMemcpyAsync(pin, K.sc + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double hn = pin[0], est = pin[1];
+            if (!std::isfinite(est)) return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
+            ++*total;
+            k = j + 1;
+            push(est * hist_scale);
+            if (est <= tol_abs || *total >= max_iter || hn == 0.0) break;
+            arb::scale_copy(s, n, K.w, K.sc + 5, K.V + (size_t)(j + 1) * n);
+        }
+        arb::upper_solve(s, k, m, K.H, K.g, K.sv);
+        arb::gemv_set(s, n, k, K.V, n, K.sv, K.w);
+        TRY(precond_apply(ctx, s, K.w, K.z));
+        arb::axpby(s, n, 1.0, K.z, 1.0, y);
+        TRY(system_apply(ctx, s, y, K.r, prec));
+        arb::axpby(s, n, 1.0, rhs, -1.0, K.r);  // r = rhs - A y
+        ++*restarts;
+        if (inf->history_len > 0) inf->history_len--;  // estimate replaced by the true residual
+    }
+    return 0;
+}
+
+int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int warm,
+              arb_solve_info *info, hipStream_t s) {
+    TRY(ready(ctx));
+    const int N = ctx->N, M = ctx->M, Nc = ctx->Nc;
+    Krylov K;
+    TRY(krylov_buffers(ctx, K));
+    const int64_t n = K.n;
+    const int prec = ctx->opt.precision;
+    const double tol = ctx->opt.tol;
     arb_solve_info loc{};
     arb_solve_info *inf = info ? info : &loc;
     std::memset(inf, 0, sizeof(*inf));
-    auto push_hist = [&](double v) {
-        if (inf->history_len < 1024) inf->history[inf->history_len++] = v;
-    };
 
     HIPCHK(hipStreamSynchronize(s));
     const double t0 = now_ms();
@@ -423,93 +520,73 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
         if (rc < 0) return rc;
         if (rc > 0) warn = rc;
         inf->pinv_used = ctx->pc_pinv;
-    } else if (Nc > 0) {
-        TRY(refresh_rows(ctx, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now_ms();
     inf->t_build_ms = t1 - t0;
 
-    arb::rhs_assemble(s, N, M, Nc, us, F, ctx->Bc.as<double>(), b);
-    arb::multidot(s, n, 1, b, n, b, part, sc);
-    HIPCHK(hipMemcpyAsync(pin, sc, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(pin[0]);
+    arb::rhs_assemble(s, N, M, Nc, us, F, ctx->Bc.as<double>(), K.b);
+    double bnorm = 0.0;
+    TRY(dev_norm(ctx, s, K, K.b, 0, &bnorm));
     if (!std::isfinite(bnorm)) return fail(ctx, ARB_E_NAN, "right-hand side is not finite");
     if (bnorm == 0.0) {
         HIPCHK(hipMemsetAsync(y, 0, n * sizeof(double), s));
         HIPCHK(hipStreamSynchronize(s));
-        push_hist(0.0);
+        inf->history[inf->history_len++] = 0.0;
         return ARB_OK;
     }
     if (warm) {
-        TRY(system_apply(ctx, s, y, r, prec));
-        arb::axpby(s, n, 1.0, b, -1.0, r);  // r = b - A y
+        TRY(system_apply(ctx, s, y, K.r, ARB_FP64));
+        arb::axpby(s, n, 1.0, K.b, -1.0, K.r);  // r = b - A y
     } else {
         HIPCHK(hipMemsetAsync(y, 0, n * sizeof(double), s));
-        HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(K.r, K.b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     int total = 0, restarts = 0;
-    double true_rel = 1.0;
+    double res = 0.0;
     const int max_iter = ctx->opt.max_iter;
-    for (;;) {
-        arb::multidot(s, n, 1, r, n, r, part, sc + 2);
-        arb::g_init(s, m, sc + 2, g, sc + 3);  // g = [beta, 0, ...], sc[3] = beta
-        HIPCHK(hipMemcpyAsync(pin, sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        const double beta = pin[0];
-        if (!std::isfinite(beta)) return fail(ctx, ARB_E_NAN, "GMRES residual is not finite");
-        true_rel = beta / bnorm;
-        push_hist(true_rel);
-        if (beta <= tol * bnorm || total >= max_iter) break;
-        arb::scale_copy(s, n, r, sc + 3, V);  // v_0 = r / beta
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
-            double *vj = V + (size_t)j * n;
-            TRY(precond_apply(ctx, s, vj, z));
-            TRY(system_apply(ctx, s, z, w, prec));
-            // classical Gram-Schmidt, twice
-            arb::multidot(s, n, j + 1, V, n, w, part, h1);
-            arb::gemv_sub(s, n, j + 1, V, n, h1, w);
-            arb::multidot(s, n, j + 1, V, n, w, part, h2);
-            arb::gemv_sub(s, n, j + 1, V, n, h2, w);
-            arb::multidot(s, n, 1, w, n, w, part, sc + 4);
-            arb::arnoldi_post(s, j, m, h1, h2, sc + 4, H, cs, sn, g, sc + 5);  // sc5 = hn, sc6 = est
-            HIPCHK(hipMemcpyAsync(pin, sc + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const double hn = pin[0], est = pin[1];
-            if (!std::isfinite(est)) return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
-            ++total;
-            k = j + 1;
-            push_hist(est / bnorm);
-            if (est <= tol * bnorm || total >= max_iter || hn == 0.0) break;
-            arb::scale_copy(s, n, w, sc + 5, V + (size_t)(j + 1) * n);
+    if (prec == ARB_FP64) {
+        TRY(gmres_core(ctx, s, K, K.b, y, tol * bnorm, ARB_FP64, max_iter, &total, &restarts,
+                       1.0 / bnorm, inf, &res));
+    } else {
+        // GMRES iterative refinement: the correction equation A d = r is solved by
+        // GMRES with the FP32 pair sum to a modest relative tolerance; r = b - A y
+        // is always formed with the FP64 pair sum, so the stopping test is FP64.
+        double *rhs = ctx->kt.as<double>();     // current FP64 residual (inner rhs)
+        double *d = rhs + n;                     // inner solution
+        TRY(dev_norm(ctx, s, K, K.r, 1, &res));
+        for (int outer = 0; outer < 30; ++outer) {
+            inf->history[inf->history_len < 1024 ? inf->history_len++ : 1023] = res / bnorm;
+            if (res <= tol * bnorm || total >= max_iter) break;
+            HIPCHK(hipMemcpyAsync(rhs, K.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemsetAsync(d, 0, n * sizeof(double), s));
+            const double eta = std::max(1e-4, 0.5 * tol * bnorm / res);
+            double rin = 0.0;
+            TRY(gmres_core(ctx, s, K, rhs, d, eta * res, ARB_FP32C, max_iter, &total, &restarts,
+                           1.0 / bnorm, inf, &rin));
+            arb::axpby(s, n, 1.0, d, 1.0, y);
+            TRY(system_apply(ctx, s, y, K.r, ARB_FP64));
+            arb::axpby(s, n, 1.0, K.b, -1.0, K.r);
+            TRY(dev_norm(ctx, s, K, K.r, 1, &res));
+            if (!std::isfinite(res)) return fail(ctx, ARB_E_NAN, "refinement residual not finite");
         }
-        arb::upper_solve(s, k, m, H, g, sv);
-        arb::gemv_set(s, n, k, V, n, sv, w);
-        TRY(precond_apply(ctx, s, w, z));
-        arb::axpby(s, n, 1.0, z, 1.0, y);
-        TRY(system_apply(ctx, s, y, r, prec));
-        arb::axpby(s, n, 1.0, b, -1.0, r);
-        ++restarts;
-        if (inf->history_len > 0) inf->history_len--;  // estimate replaced by the true residual
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t2 = now_ms();
     inf->t_solve_ms = t2 - t1;
     inf->iterations = total;
     inf->restarts = restarts;
-    inf->rel_residual = true_rel;
-    inf->rel_residual_fp64 = true_rel;
+    inf->rel_residual = res / bnorm;
+    inf->rel_residual_fp64 = res / bnorm;
     if (prec == ARB_FP32C) {
-        TRY(system_apply(ctx, s, y, w, ARB_FP64));
-        arb::axpby(s, n, 1.0, b, -1.0, w);
-        arb::multidot(s, n, 1, w, n, w, part, sc + 7);
-        HIPCHK(hipMemcpyAsync(pin, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        inf->rel_residual_fp64 = std::sqrt(pin[0]) / bnorm;
+        // residual of the returned iterate with the FP32 pair sum, for reference
+        TRY(system_apply(ctx, s, y, K.w, ARB_FP32C));
+        arb::axpby(s, n, 1.0, K.b, -1.0, K.w);
+        double r32 = 0.0;
+        TRY(dev_norm(ctx, s, K, K.w, 7, &r32));
+        inf->rel_residual = r32 / bnorm;
     }
-    if (true_rel > tol) return ARB_W_NOT_CONVERGED;
+    if (inf->rel_residual_fp64 > tol) return ARB_W_NOT_CONVERGED;
     return warn;
 }
 
@@ -553,7 +630,11 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
 void arb_destroy(arb_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->opt.device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    (void)hipDeviceSynchronize();
+    for (auto &e : ctx->prof_ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1076,6 +1157,30 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
     HIPCHK(hipStreamSynchronize(s));
     if (iters) *iters = *std::max_element(it.begin(), it.end());
     if (resid) *resid = *std::max_element(rs.begin(), rs.end());
+    return ARB_OK;
+}
+
+int arb_profile(arb_ctx *ctx, int enable) {
+    if (!ctx) return ARB_E_ARG;
+    ctx->prof = enable != 0;
+    return ARB_OK;
+}
+
+int arb_profile_read(arb_ctx *ctx, double *pair_ms, int *pair_launches) {
+    if (!ctx) return ARB_E_ARG;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    double tot = 0.0;
+    for (auto &e : ctx->prof_ev) {
+        HIPCHK(hipEventSynchronize(e.second));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+        tot += ms;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (pair_ms) *pair_ms = tot;
+    if (pair_launches) *pair_launches = (int)ctx->prof_ev.size();
+    ctx->prof_ev.clear();
     return ARB_OK;
 }
 

@@ -174,4 +174,7 @@ struct arb_ctx {
     // correction
     arb::DevBuf c_link_ptr, c_links, c_local, c_ws_off, c_ws, c_iters, c_resid, c_pq, c_abp, c_ab;
     arb::DevBuf tune_out;
+    // pair-kernel timing (arb_profile)
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
 };

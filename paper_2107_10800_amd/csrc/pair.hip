@@ -23,8 +23,8 @@
 // 256 (x,y,z + lambda), all lanes reading the same LDS word (broadcast).  Each
 // slice writes its partial sums; pair_reduce adds slices in a fixed order, so
 // results are deterministic.  FP32C: positions are split hi + lo floats so
-// that differences keep ~double accuracy; sums are float inside a tile and
-// double across tiles.
+// that differences keep ~double accuracy; sums are float over runs of 32
+// sources and double across runs.
 #include "rpy_device.h"
 
 namespace arb {
@@ -41,6 +41,8 @@ __global__ void prep_positions_kernel(int N, const double *__restrict__ pos,
     lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
                         (float)(z - (double)zh), 0.f);
 }
+
+constexpr int kRun = 32;  // sources per float partial sum in the FP32C kernel
 
 template <bool WALL>
 __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
@@ -68,26 +70,30 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
         }
         __syncthreads();
         const int cnt = min(kTile, N - t * kTile);
-        float ax = 0.f, ay = 0.f, az = 0.f;
+        // float sums over runs of kRun sources, promoted to double after each run
+        for (int k0 = 0; k0 < cnt; k0 += kRun) {
+            const int k1 = min(k0 + kRun, cnt);
+            float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll 2
-        for (int k = 0; k < cnt; ++k) {
-            const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
-            const float dx = (th.x - sh.x) + (tl.x - sl.x);
-            const float dy = (th.y - sh.y) + (tl.y - sl.y);
-            const float dz = (th.z - sh.z) + (tl.z - sl.z);
-            const float dxy2 = fmaf(dx, dx, dy * dy);
-            const float r2 = fmaf(dz, dz, dxy2);
-            const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
-            rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
-            if (WALL) {
-                const float Rz = zi + sh.z;
-                const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                rpy_image<float>(dx, dy, Rz, sh.z, Ri, L.x, L.y, L.z, c, ax, ay, az);
+            for (int k = k0; k < k1; ++k) {
+                const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
+                const float dx = (th.x - sh.x) + (tl.x - sl.x);
+                const float dy = (th.y - sh.y) + (tl.y - sl.y);
+                const float dz = (th.z - sh.z) + (tl.z - sl.z);
+                const float dxy2 = fmaf(dx, dx, dy * dy);
+                const float r2 = fmaf(dz, dz, dxy2);
+                const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+                rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
+                if (WALL) {
+                    const float Rz = zi + sh.z;
+                    const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+                    rpy_image<float>(dx, dy, Rz, sh.z, Ri, L.x, L.y, L.z, c, ax, ay, az);
+                }
             }
+            ux += (double)ax;
+            uy += (double)ay;
+            uz += (double)az;
         }
-        ux += (double)ax;
-        uy += (double)ay;
-        uz += (double)az;
     }
     if (i < N) {
         const size_t base = (size_t)blockIdx.y * 3 * N + i;
