@@ -153,6 +153,69 @@ def solve_bench(torch, arb, W, precision, reps=2):
         arb.arb_destroy(ctx)
 
 
+def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=30, log=log):
+    """Learned body-mobility preconditioner vs exact block and body-frame blocks."""
+    import numpy as np
+
+    from oracle import mlp
+    from paper_2107_10800_amd import learned
+
+    t0 = time.perf_counter()
+    X, T = learned.make_dataset(n_train, seed=101)
+    t_data = time.perf_counter() - t0
+    Xh, Th = learned.make_dataset(1000, seed=202)          # held-out poses
+    sc = learned.scaling(X, T)
+    ctx = arb.arb_create(precision=arb.ARB_FP64, wall=True)
+    try:
+        learned.load_model(ctx, W.mlp_init_weights(seed=6), sc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = learned.train(ctx, X, T, epochs=epochs, batch=4096, lr=3e-3, seed=7, log=log)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        params = arb.arb_mlp_get_params(ctx)
+        Yh = arb.arb_mlp_forward(ctx, Xh)
+    finally:
+        arb.arb_destroy(ctx)
+    Np, Ne = mlp.mobility_from_output(Yh), mlp.mobility_from_output(Th)
+    err = np.linalg.norm(Np - Ne, axis=(1, 2)) / np.linalg.norm(Ne, axis=(1, 2))
+    wl = W.bacteria(n_bact=n_bact, seed=5)
+    dev = torch.device("cuda")
+    F = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
+    y = torch.zeros(wl.n_unknowns, dtype=torch.float64, device=dev)
+    out = {}
+    cases = [("fp64_exact_block", arb.ARB_FP64, arb.ARB_PC_BLOCK),
+             ("fp32c_exact_block", arb.ARB_FP32C, arb.ARB_PC_BLOCK),
+             ("fp32c_learned", arb.ARB_FP32C, arb.ARB_PC_LEARNED),
+             ("fp32c_body_frame", arb.ARB_FP32C, arb.ARB_PC_BODYFRAME)]
+    for name, prec, pc in cases:
+        c = arb.context_for(wl, precision=prec, tol=1e-6, restart=100, max_iter=600, precond=pc)
+        try:
+            learned.load_model(c, params, sc)
+            torch.cuda.synchronize()
+            sh = torch.cuda.Stream().cuda_stream
+            arb.arb_solve_dev(c, F, None, y, warm=False, stream=sh)     # warm-up / autotune
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = arb.arb_solve_dev(c, F, None, y, warm=False, stream=sh)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            arb.arb_destroy(c)
+        out[name] = dict(ms_per_solve=1e3 * dt, iterations=info["iterations"],
+                         rel_residual_fp64=info["rel_residual_fp64"],
+                         precond_build_ms=info["t_build_ms"], status=rc)
+        log(f"learned bench {name}: {1e3 * dt:.0f} ms, {info['iterations']} iterations, "
+            f"build {info['t_build_ms']:.1f} ms, residual {info['rel_residual_fp64']:.1e}")
+    return dict(workload=f"{n_bact} bacteria above a wall, N={wl.N}, n={wl.n_unknowns}, "
+                         f"GMRES to 1e-6 (FP64 residual)",
+                training=dict(poses=int(len(X)), seconds_dataset=t_data, seconds_train=t_train,
+                              epochs=epochs, batch=4096, final_batch_loss=hist[-1],
+                              heldout_body_mobility_rel_err_median=float(np.median(err)),
+                              heldout_body_mobility_rel_err_p95=float(np.percentile(err, 95))),
+                solves=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +224,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the body-mobility network and compare preconditioners "
+                         "on 4,096 bacteria (several minutes)")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -239,6 +305,9 @@ def main():
         res["gmres"] = solve_bench(torch, arb, W, arb.ARB_FP32C)
         log(f"bench: solve {res['gmres']['ms_per_solve']:.1f} ms, "
             f"{res['gmres']['iterations']} iterations")
+    if args.learned:
+        log("bench: learned preconditioner")
+        res["learned"] = learned_bench(torch, arb, W)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(sl)

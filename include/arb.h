@@ -57,6 +57,9 @@ extern "C" {
 #define ARB_PC_NONE    0
 #define ARB_PC_BLOCK   1   /* Sec. 3.1, Eq. precond                          */
 #define ARB_PC_LEARNED 2   /* body mobility N~_p from the learned network    */
+#define ARB_PC_BODYFRAME 3 /* free-space blocks of each body type rotated into
+                              each body (no per-solve factorisation; ignores the
+                              wall inside the blocks)                         */
 
 typedef struct arb_ctx arb_ctx;
 
@@ -200,6 +203,47 @@ int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double
  * link residual ||g||_2 per assembly. */
 int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q,
                           double *theta, int *iters, double *resid);
+
+/* -------------------------------------------------------------- learned body mobility
+ * A 7 -> 128 -> 128 -> 21 network (SiLU hidden layers, linear output, BF16
+ * operands with FP32 accumulation on the matrix cores, FP32 master weights)
+ * maps features x = [h/a, theta with s >= 0, onehot(type 0), onehot(type 1)]
+ * of one body to y, the row-major lower triangle of L (diagonal entries as
+ * log L_ii), L the Cholesky factor of D N~_p D with
+ * D = diag(sqrt(6 pi eta a) I3, sqrt(8 pi eta a^3) I3); N~_p is
+ * the body mobility [K_p^T (M^(pp))^-1 K_p]^-1 of the block preconditioner
+ * (Sec. 3.1).  Parameters: 20,245 floats, flat [W1 (128x7), b1, W2 (128x128),
+ * b2, W3 (21x128), b3], W row-major (out x in).  With ARB_PC_LEARNED the solve
+ * takes N~_p from the network and each body's blob block from the unbounded
+ * body-frame mobility of its type (all bodies of one type must share r_ref);
+ * a non-finite prediction (or |y| >= 80) makes the build fall back to the
+ * exact one (ARB_W_LEARNED_FALLBACK).  Inputs and outputs are standardised:
+ * the network sees (x - in_mu)/in_sd and y = out_mu + out_sd * output. */
+/* Standardisation constants (7, 7, 21, 21 floats; sd > 0); identity by default. */
+int arb_mlp_set_scaling(arb_ctx *ctx, const float *in_mu, const float *in_sd,
+                        const float *out_mu, const float *out_sd);
+/* Load parameters (n = 20245) and reset the Adam state. */
+int arb_mlp_set_params(arb_ctx *ctx, int n, const float *params);
+int arb_mlp_get_params(arb_ctx *ctx, int n, float *params);
+/* Y (B x 21) = network(X (B x 7)) with both standardisations applied, host arrays. */
+int arb_mlp_forward(arb_ctx *ctx, int B, const float *X, float *Y);
+/* Gradient (n = 20245 floats, parameter layout) of the mean squared error of
+ * the standardised outputs, (T - out_mu)/out_sd, over the B x 21 outputs at
+ * the current parameters; loss may be NULL. */
+int arb_mlp_grad(arb_ctx *ctx, int B, const float *X, const float *T, float *grad,
+                 double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch in device
+ * memory (X_dev B x 7, T_dev B x 21 floats).  loss (host, may be NULL) is the
+ * batch loss before the step; passing it synchronises the stream. */
+int arb_mlp_train_step_dev(arb_ctx *ctx, int B, const float *X_dev, const float *T_dev,
+                           float lr, double *loss, void *stream);
+/* Features of every body of the current state, M x 7 floats. */
+int arb_mlp_features(arb_ctx *ctx, float *X);
+/* Exact body mobilities of the current state from the block build (Sec. 3.1):
+ * Nt (36 M doubles, row-major, may be NULL) and the network's training labels
+ * target (21 M floats: lower triangle of chol(D N~_p D), log on the
+ * diagonal, may be NULL). */
+int arb_body_mobility(arb_ctx *ctx, double *Nt, float *target);
 
 /* -------------------------------------------------------------- timing
  * When enabled, HIP events are recorded on the launching stream around every

@@ -31,6 +31,7 @@ ARB_FP32C = 1
 ARB_PC_NONE = 0
 ARB_PC_BLOCK = 1
 ARB_PC_LEARNED = 2
+ARB_PC_BODYFRAME = 3
 
 SYMBOLS = [
     "arb_create", "arb_destroy", "arb_last_error", "arb_get_slices", "arb_set_bodies",
@@ -39,7 +40,9 @@ SYMBOLS = [
     "arb_system_apply", "arb_K_apply", "arb_KT_apply", "arb_constraint_rows",
     "arb_precond_build", "arb_precond_apply", "arb_precond_block", "arb_solve",
     "arb_solve_dev", "arb_euler_update", "arb_correct_positions", "arb_profile",
-    "arb_profile_read",
+    "arb_profile_read", "arb_mlp_set_params", "arb_mlp_get_params", "arb_mlp_forward",
+    "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
+    "arb_mlp_set_scaling",
 ]
 
 
@@ -74,6 +77,8 @@ _lib = None
 _P = C.c_void_p
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int32)
+_FP = C.POINTER(C.c_float)
+N_MLP_PARAMS = 20245
 
 
 def load():
@@ -113,6 +118,14 @@ def load():
         "arb_correct_positions": (C.c_int, [_P, C.c_double, C.c_int, _DP, _DP,
                                             C.POINTER(C.c_int), _DP]),
         "arb_profile": (C.c_int, [_P, C.c_int]),
+        "arb_mlp_set_params": (C.c_int, [_P, C.c_int, _FP]),
+        "arb_mlp_get_params": (C.c_int, [_P, C.c_int, _FP]),
+        "arb_mlp_forward": (C.c_int, [_P, C.c_int, _FP, _FP]),
+        "arb_mlp_grad": (C.c_int, [_P, C.c_int, _FP, _FP, _FP, _DP]),
+        "arb_mlp_train_step_dev": (C.c_int, [_P, C.c_int, _P, _P, C.c_float, _DP, _P]),
+        "arb_mlp_features": (C.c_int, [_P, _FP]),
+        "arb_body_mobility": (C.c_int, [_P, _DP, _FP]),
+        "arb_mlp_set_scaling": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
         "arb_profile_read": (C.c_int, [_P, _DP, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
@@ -364,6 +377,74 @@ def arb_profile_read(ctx):
     n = C.c_int()
     _check(ctx, load().arb_profile_read(ctx, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def _f(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a, a.ctypes.data_as(_FP)
+
+
+def arb_mlp_set_params(ctx, params):
+    p, pp = _f(params, N_MLP_PARAMS)
+    return _check(ctx, load().arb_mlp_set_params(ctx, N_MLP_PARAMS, pp))
+
+
+def arb_mlp_set_scaling(ctx, in_mu, in_sd, out_mu, out_sd):
+    a1, p1 = _f(in_mu, 7)
+    a2, p2 = _f(in_sd, 7)
+    a3, p3 = _f(out_mu, 21)
+    a4, p4 = _f(out_sd, 21)
+    return _check(ctx, load().arb_mlp_set_scaling(ctx, p1, p2, p3, p4))
+
+
+def arb_mlp_get_params(ctx):
+    out = np.zeros(N_MLP_PARAMS, np.float32)
+    _check(ctx, load().arb_mlp_get_params(ctx, N_MLP_PARAMS, out.ctypes.data_as(_FP)))
+    return out
+
+
+def arb_mlp_forward(ctx, X):
+    x, xp = _f(X)
+    B = x.size // 7
+    Y = np.zeros(B * 21, np.float32)
+    _check(ctx, load().arb_mlp_forward(ctx, B, xp, Y.ctypes.data_as(_FP)))
+    return Y.reshape(B, 21)
+
+
+def arb_mlp_grad(ctx, X, T):
+    x, xp = _f(X)
+    B = x.size // 7
+    t, tp = _f(T, B * 21)
+    g = np.zeros(N_MLP_PARAMS, np.float32)
+    loss = C.c_double()
+    _check(ctx, load().arb_mlp_grad(ctx, B, xp, tp, g.ctypes.data_as(_FP), C.byref(loss)))
+    return loss.value, g
+
+
+def arb_mlp_train_step_dev(ctx, B, X_dev, T_dev, lr, want_loss=False, stream=None):
+    loss = C.c_double()
+    _check(ctx, load().arb_mlp_train_step_dev(ctx, int(B), _ptr(X_dev), _ptr(T_dev),
+                                              float(lr), C.byref(loss) if want_loss else None,
+                                              _ptr(stream)))
+    return loss.value if want_loss else None
+
+
+def arb_mlp_features(ctx):
+    M = arb_sizes(ctx)[1]
+    X = np.zeros(M * 7, np.float32)
+    _check(ctx, load().arb_mlp_features(ctx, X.ctypes.data_as(_FP)))
+    return X.reshape(M, 7)
+
+
+def arb_body_mobility(ctx):
+    """(N~ (M,6,6) float64, training labels (M,21) float32)."""
+    M = arb_sizes(ctx)[1]
+    out, op = _out(36 * M)
+    T = np.zeros(M * 21, np.float32)
+    _check(ctx, load().arb_body_mobility(ctx, op, T.ctypes.data_as(_FP)))
+    return out.reshape(M, 6, 6), T.reshape(M, 21)
 
 
 # ------------------------------------------------------------------ convenience

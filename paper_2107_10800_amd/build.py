@@ -4,7 +4,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["pair.hip", "bodies.hip", "precond.hip", "krylov.hip", "correct.hip", "api.hip"]
+SOURCES = ["pair.hip", "bodies.hip", "precond.hip", "krylov.hip", "correct.hip", "mlp.hip",
+           "api.hip"]
 LIB = os.path.join(HERE, "libarb.so")
 
 HIPCC_FLAGS = [

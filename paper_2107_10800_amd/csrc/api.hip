@@ -255,7 +255,7 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
     if (N >= 8192) {
         // autotune: time candidate source splits on this problem (two runs each)
         std::vector<int> cand;
-        for (int c = std::max(1, h / 4); c <= std::min(ntiles, h * 4); c *= 2) cand.push_back(c);
+        for (int c = std::max(1, h / 2); c <= std::min(ntiles, h * 16); c *= 2) cand.push_back(c);
         HIPCHK(ctx->tune_out.ensure(3 * (size_t)N * sizeof(double)));
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -335,10 +335,148 @@ arb::PrecondDev pc_view(arb_ctx *ctx) {
     P.S = ctx->S.as<double>();
     P.status = ctx->status.as<int>();
     P.tmp = ctx->pctmp.as<double>();
+    P.learned = ctx->pc_learned ? 1 : 0;
+    P.type = ctx->body_type_d.as<int>();
+    P.tmat_off = ctx->t_mat_off.as<int64_t>();
+    P.tz_off = ctx->t_z_off.as<int64_t>();
+    P.tminv = ctx->t_minv.as<double>();
+    P.tZ = ctx->t_Z.as<double>();
+    P.R9 = ctx->R9.as<double>();
     return P;
 }
 
+// per-type body-frame unbounded blocks for the learned preconditioner (once
+// per body set): every body of a type must share its body-frame blobs
+int ensure_types(arb_ctx *ctx, hipStream_t s) {
+    if (ctx->types_ready) return 0;
+    const int M = ctx->M;
+    int T = 0;
+    for (int p = 0; p < M; ++p) T = std::max(T, ctx->h_body_type[p] + 1);
+    std::vector<int> ref(T, -1);
+    for (int p = 0; p < M; ++p) {
+        const int t = ctx->h_body_type[p];
+        if (t < 0) return fail(ctx, ARB_E_ARG, "negative body type");
+        if (ref[t] < 0) {
+            ref[t] = p;
+            continue;
+        }
+        const int r = ref[t];
+        const int nb = ctx->h_blob_off[p + 1] - ctx->h_blob_off[p];
+        if (nb != ctx->h_blob_off[r + 1] - ctx->h_blob_off[r])
+            return fail(ctx, ARB_E_ARG, "bodies of one type have different blob counts");
+        for (int k = 0; k < 3 * nb; ++k)
+            if (std::fabs(ctx->h_r_ref[3 * (size_t)ctx->h_blob_off[p] + k] -
+                          ctx->h_r_ref[3 * (size_t)ctx->h_blob_off[r] + k]) > 1e-12)
+                return fail(ctx, ARB_E_ARG, "bodies of one type have different body-frame blobs");
+    }
+    std::vector<int> tb(T + 1, 0);
+    std::vector<double> pos;
+    std::vector<int64_t> mo(T + 1, 0), zo(T + 1, 0);
+    for (int t = 0; t < T; ++t) {
+        const int r = ref[t];
+        const int nb = r < 0 ? 0 : ctx->h_blob_off[r + 1] - ctx->h_blob_off[r];
+        tb[t + 1] = tb[t] + nb;
+        for (int k = 0; k < 3 * nb; ++k) pos.push_back(ctx->h_r_ref[3 * (size_t)ctx->h_blob_off[r] + k]);
+        mo[t + 1] = mo[t] + 9 * (int64_t)nb * nb;
+        zo[t + 1] = zo[t] + 18 * (int64_t)nb;
+    }
+    TRY(upload(ctx, ctx->t_blob_off, tb.data(), T + 1, s));
+    TRY(upload(ctx, ctx->t_ref, pos.data(), pos.size(), s));
+    TRY(upload(ctx, ctx->t_mat_off, mo.data(), T + 1, s));
+    TRY(upload(ctx, ctx->t_z_off, zo.data(), T + 1, s));
+    HIPCHK(ctx->t_mats.ensure(std::max<int64_t>(mo[T], 1) * sizeof(double)));
+    HIPCHK(ctx->t_minv.ensure(std::max<int64_t>(mo[T], 1) * sizeof(double)));
+    HIPCHK(ctx->t_Z.ensure(std::max<int64_t>(zo[T], 1) * sizeof(double)));
+    HIPCHK(ctx->t_ldiag.ensure(std::max<size_t>(pos.size(), 1) * sizeof(double)));
+    HIPCHK(ctx->t_Nt.ensure(36 * (size_t)T * sizeof(double)));
+    HIPCHK(ctx->t_status.ensure(8 * sizeof(int)));
+    HIPCHK(hipMemsetAsync(ctx->t_status.p, 0, 8 * sizeof(int), s));
+    arb::PrecondDev P;
+    P.M = T;
+    P.blob_off = ctx->t_blob_off.as<int>();
+    P.mat_off = ctx->t_mat_off.as<int64_t>();
+    P.z_off = ctx->t_z_off.as<int64_t>();
+    P.mats = ctx->t_mats.as<double>();
+    P.minv = ctx->t_minv.as<double>();
+    P.ldiag = ctx->t_ldiag.as<double>();
+    P.Z = ctx->t_Z.as<double>();
+    P.Nt = ctx->t_Nt.as<double>();
+    P.status = ctx->t_status.as<int>();
+    arb::precond_assemble(s, P, ctx->t_ref.as<double>(), ctx->opt.a, ctx->opt.eta, false);
+    arb::precond_factor(s, P, ctx->t_ref.as<double>(), 0);
+    int st[8];
+    HIPCHK(hipMemcpyAsync(st, ctx->t_status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st[0]) return fail(ctx, ARB_E_NOT_SPD, "body-frame blob mobility of a type is not SPD");
+    ctx->h_type_ref = ref;
+    ctx->types_ready = true;
+    return 0;
+}
+
+int mlp_ensure_ws(arb_ctx *ctx, int Bp) {
+    HIPCHK(ctx->mlp_ws.ensure((size_t)arb::mlp_workspace_bytes(Bp)));
+    return 0;
+}
+
+int precond_build_exact(arb_ctx *ctx, hipStream_t s);
+
+// learned preconditioner build: network features -> N~_p; falls back to the
+// exact build when a predicted factor is not a valid Cholesky factor
 int precond_build(arb_ctx *ctx, hipStream_t s) {
+    TRY(ready(ctx));
+    ctx->pc_learned = false;
+    if (ctx->opt.precond == ARB_PC_BODYFRAME) {
+        // free-space blocks of each body type, rotated: no per-solve factorisation
+        TRY(ensure_types(ctx, s));
+        const int M = ctx->M;
+        HIPCHK(ctx->Nt.ensure(36 * (size_t)M * sizeof(double)));
+        HIPCHK(ctx->pctmp.ensure(6 * (size_t)M * sizeof(double)));
+        HIPCHK(ctx->status.ensure(8 * sizeof(int)));
+        HIPCHK(hipMemsetAsync(ctx->status.p, 0, 8 * sizeof(int), s));
+        arb::rotate_body_mobility(s, M, ctx->body_type_d.as<int>(), ctx->t_Nt.as<double>(),
+                                  ctx->R9.as<double>(), ctx->Nt.as<double>());
+        ctx->pc_learned = true;  // same per-type apply path
+        arb::PrecondDev P = pc_view(ctx);
+        arb::precond_assembly(s, P);
+        int st[8];
+        HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->pc_built = true;
+        ctx->pc_pinv = st[1];
+        return ctx->pc_pinv ? ARB_W_PINV_USED : ARB_OK;
+    }
+    if (ctx->opt.precond != ARB_PC_LEARNED) return precond_build_exact(ctx, s);
+    if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "learned preconditioner without parameters");
+    TRY(ensure_types(ctx, s));
+    const int M = ctx->M;
+    const int Bp = (M + 15) / 16 * 16;
+    TRY(mlp_ensure_ws(ctx, Bp));
+    HIPCHK(ctx->mlp_x.ensure((size_t)M * 7 * sizeof(float)));
+    HIPCHK(ctx->Nt.ensure(36 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->pctmp.ensure(6 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->status.ensure(8 * sizeof(int)));
+    HIPCHK(hipMemsetAsync(ctx->status.p, 0, 8 * sizeof(int), s));
+    arb::mlp_features(s, M, ctx->q.as<double>(), ctx->theta.as<double>(), ctx->body_type_d.as<int>(),
+                      ctx->opt.a, ctx->mlp_x.as<float>());
+    float *Y = arb::mlp_forward(s, ctx->mlp_params.p, ctx->mlp_ws.p, M, Bp, ctx->mlp_x.as<float>());
+    arb::mlp_mobility(s, ctx->mlp_params.p, M, Y, ctx->opt.a, ctx->opt.eta, ctx->Nt.as<double>(),
+                      ctx->status.as<int>() + 4);
+    arb::PrecondDev P = pc_view(ctx);
+    arb::precond_assembly(s, P);
+    int st[8];
+    HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st[4]) {
+        const int rc = precond_build_exact(ctx, s);
+        return rc < 0 ? rc : ARB_W_LEARNED_FALLBACK;
+    }
+    ctx->pc_learned = true;
+    ctx->pc_built = true;
+    ctx->pc_pinv = st[1];
+    return ctx->pc_pinv ? ARB_W_PINV_USED : ARB_OK;
+}
+
+int precond_build_exact(arb_ctx *ctx, hipStream_t s) {
     TRY(ready(ctx));
     const int M = ctx->M;
     std::vector<int64_t> mo(M + 1, 0), zo(M + 1, 0);
@@ -609,7 +747,7 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
     if (!(opt->a > 0) || !(opt->eta > 0) || !(opt->tol > 0) || opt->restart < 1 ||
         opt->restart > 256 || opt->max_iter < 1 ||
         (opt->precision != ARB_FP64 && opt->precision != ARB_FP32C) || opt->precond < 0 ||
-        opt->precond > 2 || opt->slices < 0 || opt->slices > 4096)
+        opt->precond > 3 || opt->slices < 0 || opt->slices > 4096)
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
@@ -683,7 +821,9 @@ int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset, const double
     TRY(upload(ctx, ctx->blob_off, ctx->h_blob_off.data(), M + 1, s));
     TRY(upload(ctx, ctx->body_of_blob, ctx->h_body_of_blob.data(), N, s));
     TRY(upload(ctx, ctx->r_ref, ctx->h_r_ref.data(), 3 * (size_t)N, s));
+    TRY(upload(ctx, ctx->body_type_d, ctx->h_body_type.data(), M, s));
     HIPCHK(hipStreamSynchronize(s));
+    ctx->types_ready = false;
     ctx->have_state = false;
     ctx->topo_dirty = true;
     ctx->pc_built = false;
@@ -1158,6 +1298,161 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
     if (iters) *iters = *std::max_element(it.begin(), it.end());
     if (resid) *resid = *std::max_element(rs.begin(), rs.end());
     return ARB_OK;
+}
+
+// parameter block: allocated once with identity standardisation
+static int mlp_alloc(arb_ctx *ctx) {
+    if (ctx->mlp_params.p) return 0;
+    HIPCHK(ctx->mlp_params.ensure((size_t)arb::mlp_param_bytes()));
+    HIPCHK(hipMemsetAsync(ctx->mlp_params.p, 0, (size_t)arb::mlp_param_bytes(), ctx->stream));
+    const float z[32] = {0}, o[32] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                      1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+    arb::mlp_set_scaling(ctx->stream, ctx->mlp_params.p, z, o, z, o);
+    return 0;
+}
+
+int arb_mlp_set_scaling(arb_ctx *ctx, const float *in_mu, const float *in_sd, const float *out_mu,
+                        const float *out_sd) {
+    if (!ctx || !in_mu || !in_sd || !out_mu || !out_sd) return ARB_E_ARG;
+    for (int k = 0; k < 7; ++k)
+        if (!(in_sd[k] > 0) || !std::isfinite(in_mu[k])) return fail(ctx, ARB_E_ARG, "bad input scaling");
+    for (int k = 0; k < 21; ++k)
+        if (!(out_sd[k] > 0) || !std::isfinite(out_mu[k])) return fail(ctx, ARB_E_ARG, "bad output scaling");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    TRY(mlp_alloc(ctx));
+    arb::mlp_set_scaling(ctx->stream, ctx->mlp_params.p, in_mu, in_sd, out_mu, out_sd);
+    return ARB_OK;
+}
+
+int arb_mlp_set_params(arb_ctx *ctx, int n, const float *params) {
+    if (!ctx || !params) return ARB_E_ARG;
+    if (n != arb::mlp_n_params()) return fail(ctx, ARB_E_ARG, "wrong parameter count");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(params[k])) return fail(ctx, ARB_E_NAN, "parameters not finite");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(mlp_alloc(ctx));
+    HIPCHK(hipMemsetAsync(ctx->mlp_params.p, 0, (size_t)arb::mlp_state_bytes(), s));
+    HIPCHK(hipMemcpyAsync(ctx->mlp_params.p, params, (size_t)n * sizeof(float),
+                          hipMemcpyHostToDevice, s));
+    arb::mlp_refresh(s, ctx->mlp_params.p);
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->mlp_ready = true;
+    ctx->mlp_step = 0;
+    return ARB_OK;
+}
+
+int arb_mlp_get_params(arb_ctx *ctx, int n, float *params) {
+    if (!ctx || !params) return ARB_E_ARG;
+    if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
+    if (n != arb::mlp_n_params()) return fail(ctx, ARB_E_ARG, "wrong parameter count");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipMemcpyAsync(params, ctx->mlp_params.p, (size_t)n * sizeof(float),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ARB_OK;
+}
+
+int arb_mlp_forward(arb_ctx *ctx, int B, const float *X, float *Y) {
+    if (!ctx || B <= 0 || !X || !Y) return ARB_E_ARG;
+    if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    const int Bp = (B + 15) / 16 * 16;
+    TRY(mlp_ensure_ws(ctx, Bp));
+    TRY(upload(ctx, ctx->mlp_x, X, (size_t)B * 7, s));
+    float *Yd = arb::mlp_forward(s, ctx->mlp_params.p, ctx->mlp_ws.p, B, Bp, ctx->mlp_x.as<float>());
+    arb::mlp_destandardize(s, ctx->mlp_params.p, B, Yd);
+    std::vector<float> tmp((size_t)Bp * 32);
+    HIPCHK(hipMemcpyAsync(tmp.data(), Yd, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < 21; ++k) Y[(size_t)b * 21 + k] = tmp[(size_t)b * 32 + k];
+    return ARB_OK;
+}
+
+static int mlp_grad_dev(arb_ctx *ctx, hipStream_t s, int B, const float *Xd, const float *Td,
+                        double *loss) {
+    const int Bp = (B + 15) / 16 * 16;
+    TRY(mlp_ensure_ws(ctx, Bp));
+    double *lp = nullptr;
+    const int nlp = arb::mlp_backward(s, ctx->mlp_params.p, ctx->mlp_ws.p, B, Bp, Xd, Td, &lp);
+    if (loss) {
+        std::vector<double> h(nlp);
+        HIPCHK(hipMemcpyAsync(h.data(), lp, nlp * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double t = 0.0;
+        for (double v : h) t += v;
+        *loss = t / ((double)B * 21.0);
+    }
+    return 0;
+}
+
+int arb_mlp_grad(arb_ctx *ctx, int B, const float *X, const float *T, float *grad, double *loss) {
+    if (!ctx || B <= 0 || !X || !T || !grad) return ARB_E_ARG;
+    if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->mlp_x, X, (size_t)B * 7, s));
+    TRY(upload(ctx, ctx->mlp_t, T, (size_t)B * 21, s));
+    TRY(mlp_grad_dev(ctx, s, B, ctx->mlp_x.as<float>(), ctx->mlp_t.as<float>(), loss));
+    const int n = arb::mlp_n_params();
+    const float *G = ctx->mlp_params.as<float>() + 3 * (size_t)n;
+    HIPCHK(hipMemcpyAsync(grad, G, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_mlp_train_step_dev(arb_ctx *ctx, int B, const float *X_dev, const float *T_dev, float lr,
+                           double *loss, void *stream) {
+    if (!ctx || B <= 0 || !X_dev || !T_dev || !(lr > 0)) return ARB_E_ARG;
+    if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = pick(ctx, stream);
+    TRY(mlp_grad_dev(ctx, s, B, X_dev, T_dev, loss));
+    arb::mlp_adam(s, ctx->mlp_params.p, lr, ++ctx->mlp_step);
+    HIPCHK(hipGetLastError());
+    return ARB_OK;
+}
+
+int arb_mlp_features(arb_ctx *ctx, float *X) {
+    if (!ctx || !X) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx->mlp_x.ensure((size_t)ctx->M * 7 * sizeof(float)));
+    arb::mlp_features(s, ctx->M, ctx->q.as<double>(), ctx->theta.as<double>(),
+                      ctx->body_type_d.as<int>(), ctx->opt.a, ctx->mlp_x.as<float>());
+    HIPCHK(hipMemcpyAsync(X, ctx->mlp_x.p, (size_t)ctx->M * 7 * sizeof(float),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_body_mobility(arb_ctx *ctx, double *Nt, float *target) {
+    if (!ctx || (!Nt && !target)) return ARB_E_ARG;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    const int rc = precond_build_exact(ctx, s);
+    if (rc < 0) return rc;
+    const int M = ctx->M;
+    if (Nt)
+        HIPCHK(hipMemcpyAsync(Nt, ctx->Nt.p, 36 * (size_t)M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    if (target) {
+        HIPCHK(ctx->mlp_t.ensure((size_t)M * 21 * sizeof(float)));
+        HIPCHK(hipMemsetAsync(ctx->status.as<int>() + 5, 0, sizeof(int), s));
+        arb::mlp_targets(s, M, ctx->Nt.as<double>(), ctx->opt.a, ctx->opt.eta, ctx->mlp_t.as<float>(),
+                         ctx->status.as<int>() + 5);
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, ctx->status.as<int>() + 5, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(target, ctx->mlp_t.p, (size_t)M * 21 * sizeof(float),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (bad) return fail(ctx, ARB_E_NOT_SPD, "a body mobility is not positive definite");
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return rc;
 }
 
 int arb_profile(arb_ctx *ctx, int enable) {

@@ -97,12 +97,19 @@ struct PrecondDev {
     int *status = nullptr;    // [0] not-SPD body+1, [1] G~ pinv count, [2] below wall,
                               // [3] N~ with dropped eigenvalues
     double *tmp = nullptr;    // apply scratch: U-hat (6M)
+    // learned variant: per-type body-frame blocks rotated by R_p
+    int learned = 0;
+    const int *type = nullptr;
+    const int64_t *tmat_off = nullptr, *tz_off = nullptr;
+    const double *tminv = nullptr, *tZ = nullptr, *R9 = nullptr;
 };
 void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos, double a,
                       double eta, bool wall);
 void precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
 void precond_assembly(hipStream_t s, const PrecondDev &P);
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z);
+void rotate_body_mobility(hipStream_t s, int M, const int *type, const double *tNt,
+                          const double *R9, double *Nt);
 
 // Dense helpers for the Krylov solver (FP64, Sec. 3.1)
 void multidot(hipStream_t s, int64_t n, int k, const double *V, int64_t ldv, const double *w,
@@ -120,6 +127,25 @@ void g_init(hipStream_t s, int m, const double *beta2, double *g, double *beta);
 void upper_solve(hipStream_t s, int k, int m, const double *Hbar, const double *g, double *sv);
 void rhs_assemble(hipStream_t s, int N, int M, int Nc, const double *us, const double *F,
                   const double *B, double *b);
+
+// Learned body mobility network (mlp.hip)
+int64_t mlp_workspace_bytes(int Bp);
+int64_t mlp_param_bytes();
+int mlp_n_params();
+void mlp_refresh(hipStream_t s, void *params);
+float *mlp_forward(hipStream_t s, void *params, void *ws, int n, int Bp, const float *X);
+int mlp_backward(hipStream_t s, void *params, void *ws, int n, int Bp, const float *X,
+                 const float *T, double **lpart);
+void mlp_adam(hipStream_t s, void *params, float lr, int t);
+void mlp_features(hipStream_t s, int M, const double *q, const double *theta, const int *type,
+                  double a, float *X);
+void mlp_mobility(hipStream_t s, void *params, int M, const float *Y, double a, double eta,
+                  double *Nt, int *bad);
+int64_t mlp_state_bytes();
+void mlp_set_scaling(hipStream_t s, void *params, const float *in_mu, const float *in_sd,
+                     const float *out_mu, const float *out_sd);
+void mlp_destandardize(hipStream_t s, void *params, int n, float *Y);
+void mlp_targets(hipStream_t s, int M, const double *Nt, double a, double eta, float *T, int *bad);
 
 // Position correction (Sec. 4.2, App. B)
 struct CorrectDev {
@@ -160,6 +186,7 @@ struct arb_ctx {
     // autotune cache: key = N*4 + precision*2 + wall -> slices
     std::map<int64_t, int> slice_cache;
     bool pc_built = false;
+    bool pc_learned = false;
     int pc_pinv = 0;
 
     // device buffers
@@ -174,6 +201,13 @@ struct arb_ctx {
     // correction
     arb::DevBuf c_link_ptr, c_links, c_local, c_ws_off, c_ws, c_iters, c_resid, c_pq, c_abp, c_ab;
     arb::DevBuf tune_out;
+    // learned body mobility: network parameters, workspace, per-type blocks
+    arb::DevBuf mlp_params, mlp_ws, mlp_x, mlp_t, body_type_d, t_ref, t_mat_off, t_z_off, t_minv,
+        t_Z, t_mats, t_ldiag, t_Nt, t_blob_off, t_status;
+    bool mlp_ready = false;
+    int mlp_step = 0;
+    bool types_ready = false;
+    std::vector<int> h_type_ref;  // reference body of each type
     // pair-kernel timing (arb_profile)
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;

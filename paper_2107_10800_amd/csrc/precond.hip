@@ -515,6 +515,145 @@ __global__ __launch_bounds__(256) void pc_apply3_kernel(
     }
 }
 
+
+// Learned variant (spec extension): each body's block uses the unbounded
+// blob mobility of its type in the body frame (computed once), rotated by R_p:
+// M_pp^-1 = (I x R) Minv_type (I x R^T), Z_p = (I x R) Z_type Q^T with
+// Q = diag(R, R); N~_p comes from the network.
+__global__ __launch_bounds__(256) void pc_apply1_learned_kernel(
+    int N, const int *__restrict__ blob_off, const int *__restrict__ type,
+    const int64_t *__restrict__ tmat_off, const int64_t *__restrict__ tz_off,
+    const double *__restrict__ tminv, const double *__restrict__ tZ, const double *__restrict__ R9,
+    const double *__restrict__ Nt, const double *__restrict__ r, double *__restrict__ z,
+    double *__restrict__ uhat) {
+    __shared__ double x[kMaxM];
+    __shared__ double tb[kMaxM];
+    __shared__ double red[8];
+    __shared__ double w6[6];
+    __shared__ double R[9];
+    const int p = blockIdx.x;
+    const int b0 = blob_off[p], n = blob_off[p + 1] - b0, m = 3 * n;
+    const int ty = type[p];
+    const double *Mi = tminv + tmat_off[ty];
+    const double *Z = tZ + tz_off[ty];
+    if (threadIdx.x < 9) R[threadIdx.x] = R9[9 * (size_t)p + threadIdx.x];
+    __syncthreads();
+    const double *rl = r + 3 * (size_t)b0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {  // x_b = R^T r_lam (per blob)
+        const double a0 = rl[3 * i], a1 = rl[3 * i + 1], a2 = rl[3 * i + 2];
+        for (int c = 0; c < 3; ++c) x[3 * i + c] = R[c] * a0 + R[3 + c] * a1 + R[6 + c] * a2;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += Mi[(size_t)k * m + i] * x[k];
+        tb[i] = s;
+    }
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < m; i += blockDim.x)
+        for (int c = 0; c < 6; ++c) acc[c] += Z[(size_t)i * 6 + c] * x[i];
+    double zb[6];
+    for (int c = 0; c < 6; ++c) zb[c] = block_sum(acc[c], red);  // syncs: tb complete
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {  // t_p = R t_b
+        const double a0 = tb[3 * i], a1 = tb[3 * i + 1], a2 = tb[3 * i + 2];
+        for (int c = 0; c < 3; ++c)
+            z[3 * (size_t)b0 + 3 * i + c] = R[3 * c] * a0 + R[3 * c + 1] * a1 + R[3 * c + 2] * a2;
+    }
+    if (threadIdx.x < 6) {
+        // Z_p^T r_lam = Q (Z_type^T x_b)
+        const int h = threadIdx.x / 3, c = threadIdx.x % 3;
+        const double v = R[3 * c] * zb[3 * h] + R[3 * c + 1] * zb[3 * h + 1] + R[3 * c + 2] * zb[3 * h + 2];
+        w6[threadIdx.x] = v + r[3 * (size_t)N + 6 * (size_t)p + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double *Nb = Nt + 36 * (size_t)p;
+        double s = 0.0;
+        for (int c = 0; c < 6; ++c) s += Nb[threadIdx.x * 6 + c] * w6[c];
+        uhat[6 * (size_t)p + threadIdx.x] = -s;
+    }
+}
+
+__global__ __launch_bounds__(256) void pc_apply3_learned_kernel(
+    int N, int M, const int *__restrict__ blob_off, const int *__restrict__ type,
+    const int64_t *__restrict__ tz_off, const double *__restrict__ tZ, const double *__restrict__ R9,
+    const double *__restrict__ Nt, const int *__restrict__ brow_ptr,
+    const int *__restrict__ brow_ent, const double *__restrict__ crow,
+    const double *__restrict__ uhat, double *__restrict__ z, int has_rows) {
+    __shared__ double U[6], Ub[6], f[6], R[9];
+    const int p = blockIdx.x;
+    const size_t off_phi = 3 * (size_t)N + 6 * (size_t)M;
+    if (threadIdx.x < 9) R[threadIdx.x] = R9[9 * (size_t)p + threadIdx.x];
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        if (has_rows) {
+            for (int e = brow_ptr[p]; e < brow_ptr[p + 1]; ++e) {
+                const int ent = brow_ent[e];
+                const int row = ent >> 1, side = ent & 1;
+                s += z[off_phi + row] * crow[12 * (size_t)row + 6 * side + threadIdx.x];
+            }
+        }
+        f[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double *Nb = Nt + 36 * (size_t)p;
+        double s = uhat[6 * (size_t)p + threadIdx.x];
+        for (int c = 0; c < 6; ++c) s += Nb[threadIdx.x * 6 + c] * f[c];
+        U[threadIdx.x] = s;
+        z[3 * (size_t)N + 6 * (size_t)p + threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {  // Q^T U
+        const int h = threadIdx.x / 3, c = threadIdx.x % 3;
+        Ub[threadIdx.x] = R[c] * U[3 * h] + R[3 + c] * U[3 * h + 1] + R[6 + c] * U[3 * h + 2];
+    }
+    __syncthreads();
+    const int b0 = blob_off[p], n = blob_off[p + 1] - b0;
+    const double *Z = tZ + tz_off[type[p]];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double v[3];
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += Z[(size_t)(3 * i + c) * 6 + k] * Ub[k];
+            v[c] = s;
+        }
+        for (int c = 0; c < 3; ++c)
+            z[3 * (size_t)b0 + 3 * i + c] += R[3 * c] * v[0] + R[3 * c + 1] * v[1] + R[3 * c + 2] * v[2];
+    }
+}
+
+// N~_p = Q N~_type Q^T, Q = diag(R_p, R_p): the free-space body mobility of
+// the body's type rotated into its orientation (no wall)
+__global__ void pc_rotate_nt_kernel(int M, const int *__restrict__ type,
+                                    const double *__restrict__ tNt, const double *__restrict__ R9,
+                                    double *__restrict__ Nt) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const double *R = R9 + 9 * (size_t)p;
+    const double *A = tNt + 36 * (size_t)type[p];
+    double T[36];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {  // (Q A)_ij
+            const int bi = i / 3, ri = i % 3;
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += R[3 * ri + k] * A[(3 * bi + k) * 6 + j];
+            T[i * 6 + j] = s;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {  // (Q A) Q^T
+            const int bj = j / 3, rj = j % 3;
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[i * 6 + 3 * bj + k] * R[3 * rj + k];
+            Nt[36 * (size_t)p + i * 6 + j] = s;
+        }
+}
+
+void rotate_body_mobility(hipStream_t s, int M, const int *type, const double *tNt,
+                          const double *R9, double *Nt) {
+    if (M > 0) pc_rotate_nt_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, type, tNt, R9, Nt);
+}
+
 void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos, double a, double eta,
                       bool wall) {
     if (P.M <= 0) return;
@@ -541,13 +680,22 @@ void precond_assembly(hipStream_t s, const PrecondDev &P) {
 
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z) {
     if (P.M <= 0) return;
-    pc_apply1_kernel<<<P.M, 256, 0, s>>>(N, P.blob_off, P.mat_off, P.z_off, P.minv, P.Z, P.Nt, r, z,
-                                         P.tmp);
+    if (P.learned)
+        pc_apply1_learned_kernel<<<P.M, 256, 0, s>>>(N, P.blob_off, P.type, P.tmat_off, P.tz_off,
+                                                     P.tminv, P.tZ, P.R9, P.Nt, r, z, P.tmp);
+    else
+        pc_apply1_kernel<<<P.M, 256, 0, s>>>(N, P.blob_off, P.mat_off, P.z_off, P.minv, P.Z, P.Nt,
+                                             r, z, P.tmp);
     if (P.A > 0)
         pc_apply2_kernel<<<P.A, 256, 0, s>>>(N, P.M, P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
                                              P.row_p, P.row_q, P.crow, P.G, r, P.tmp, z);
-    pc_apply3_kernel<<<P.M, 256, 0, s>>>(N, P.M, P.blob_off, P.z_off, P.Z, P.Nt, P.brow_ptr,
-                                         P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);
+    if (P.learned)
+        pc_apply3_learned_kernel<<<P.M, 256, 0, s>>>(N, P.M, P.blob_off, P.type, P.tz_off, P.tZ,
+                                                     P.R9, P.Nt, P.brow_ptr, P.brow_ent, P.crow,
+                                                     P.tmp, z, P.A > 0 ? 1 : 0);
+    else
+        pc_apply3_kernel<<<P.M, 256, 0, s>>>(N, P.M, P.blob_off, P.z_off, P.Z, P.Nt, P.brow_ptr,
+                                             P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);
 }
 
 }  // namespace arb

@@ -39,6 +39,8 @@ __all__ = [
     "helix80",
     "random_blobs",
     "random_rigid",
+    "bacterium_poses",
+    "mlp_init_weights",
 ]
 
 
@@ -455,3 +457,57 @@ def random_rigid(n_bodies: int = 3, blobs: int = 12, seed: int = 7,
     u_slip = rng.standard_normal((n_bodies * blobs, 3))
     return Workload("rigid", 1.0, 1.0, wall, r_ref, blob_offset, q, theta, F,
                     u_slip=u_slip, **L)
+
+
+# ---------------------------------------------------------------- learned mobility
+def bacterium_poses(n_bact: int, seed: int = 5, hmin: float = 8.0, hmax: float = 15.0,
+                    zmin: float = 1.5, head_radius: float = 5.0, n_flag: int = 80):
+    """Independent single-bacterium poses above the wall for training data.
+
+    Same geometry and height/orientation law as ``bacteria`` but without mutual
+    placement: every head centre sits at x = y = 0 (the wall is invariant under
+    in-plane shifts and the per-body mobility ignores other bodies).  Returns a
+    Workload with 2 bodies per bacterium (head type 0, flagellum type 1), no
+    constraints."""
+    rng = np.random.default_rng(seed)
+    a = 1.0
+    R = head_radius
+    head = icosphere42(R)
+    flag = helix80(n_flag)
+    f_origin = np.array([0.0, 0.0, R + 2 * a])
+    qs, ths = [], []
+    todo = n_bact
+    while todo > 0:
+        m = max(2 * todo, 64)
+        h = rng.uniform(hmin, hmax, m)
+        rot_h = Rotation.random(m, random_state=rng)
+        phase = rng.uniform(0, 2 * np.pi, m)
+        rot_f = rot_h * Rotation.from_rotvec(np.column_stack([0 * phase, 0 * phase, phase]))
+        centre = np.column_stack([0 * h, 0 * h, h])
+        fq = centre + rot_h.apply(f_origin)
+        zh = np.min(centre[:, None, 2] + np.einsum("mij,kj->mki", rot_h.as_matrix(), head)[..., 2], 1)
+        zf = np.min(fq[:, None, 2] + np.einsum("mij,kj->mki", rot_f.as_matrix(), flag)[..., 2], 1)
+        ok = np.where((zh >= zmin) & (zf >= zmin))[0][:todo]
+        for k in ok:
+            qs += [centre[k], fq[k]]
+            ths += [_quat_scalar_first(rot_h[int(k)])[0], _quat_scalar_first(rot_f[int(k)])[0]]
+        todo -= len(ok)
+    M = 2 * n_bact
+    r_ref = np.vstack([np.vstack([head, flag]) for _ in range(n_bact)])
+    sizes = np.tile([len(head), len(flag)], n_bact)
+    blob_offset = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    return Workload("bacterium_poses", a, 1.0, True, r_ref, blob_offset, np.array(qs),
+                    np.array(ths), np.zeros((M, 6)),
+                    body_type=np.tile(np.array([0, 1], np.int32), n_bact))
+
+
+def mlp_init_weights(seed: int = 6, sizes=(7, 128, 128, 21)) -> np.ndarray:
+    """He-normal initial weights (zero biases) of the body-mobility network, flat
+    in layer order [W1 (out x in), b1, W2, b2, W3, b3], float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(sizes) - 1):
+        nin, nout = sizes[i], sizes[i + 1]
+        parts.append((rng.standard_normal((nout, nin)) * np.sqrt(2.0 / nin)).ravel())
+        parts.append(np.zeros(nout))
+    return np.concatenate(parts).astype(np.float32)

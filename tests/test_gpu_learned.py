@@ -1,0 +1,176 @@
+"""GPU checks of the learned body-mobility network and its use as a preconditioner.
+
+BF16 operands bound the forward and gradient parity at about 2^-8 per operand:
+per-tensor relative L2 <= 3e-2 against the float64 oracle evaluated at the same
+(float32) parameters.  A preconditioner changes iteration counts, not the
+solution: the learned-preconditioned solve must match the exact solution within
+the same forward-error bar as the exact-preconditioned one.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp, system
+from paper_2107_10800_amd import arb
+from paper_2107_10800_amd import learned
+from paper_2107_10800_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = arb.arb_create(precision=arb.ARB_FP64, wall=True)
+    yield c
+    arb.arb_destroy(c)
+
+
+def test_forward_and_gradient_match_oracle(ctx):
+    P = W.mlp_init_weights(seed=11)
+    arb.arb_mlp_set_params(ctx, P)
+    assert np.array_equal(arb.arb_mlp_get_params(ctx), P)
+    rng = np.random.default_rng(3)
+    B = 300                                     # not a multiple of 16: ragged tile
+    X = np.column_stack([rng.uniform(8, 15, B), rng.standard_normal((B, 4)),
+                         rng.integers(0, 2, (B, 2))]).astype(np.float32)
+    T = (0.3 * rng.standard_normal((B, 21))).astype(np.float32)
+    Y = arb.arb_mlp_forward(ctx, X)
+    Yo, _ = mlp.forward(P.astype(float), X.astype(float))
+    print(f"forward rel err {rel(Y, Yo):.2e}")
+    assert rel(Y, Yo) <= 3e-2
+    loss, g = arb.arb_mlp_grad(ctx, X, T)
+    lo, go = mlp.loss_and_grad(P.astype(float), X.astype(float), T.astype(float))
+    assert abs(loss - lo) <= 3e-2 * lo
+    k = 0
+    for (Wo, bo) in mlp.unpack(go):
+        for part in (Wo.ravel(), bo):
+            e = rel(g[k:k + part.size], part)
+            print(f"grad block {k}: rel err {e:.2e}")
+            assert e <= 3e-2
+            k += part.size
+
+
+def test_features_match_oracle():
+    wl = W.bacterium_poses(40, seed=12)
+    c = arb.context_for(wl)
+    try:
+        X = arb.arb_mlp_features(c)
+    finally:
+        arb.arb_destroy(c)
+    Xo = mlp.features(wl.q[:, 2], wl.theta, wl.body_type)
+    assert np.abs(X - Xo).max() <= 1e-6 * np.abs(Xo).max()
+
+
+def test_labels_match_oracle():
+    wl = W.bacterium_poses(3, seed=13)
+    c = arb.context_for(wl)
+    try:
+        Nt, T = arb.arb_body_mobility(c)
+    finally:
+        arb.arb_destroy(c)
+    from oracle import bodies, rpy
+    r = bodies.blob_positions(wl.q, wl.theta, wl.r_ref, wl.blob_offset)
+    for p in range(wl.M):
+        sl = slice(wl.blob_offset[p], wl.blob_offset[p + 1])
+        Mpp = rpy.mobility_matrix(r[sl], 1.0, 1.0, True)
+        K = bodies.K_matrix(r[sl], wl.q[p:p + 1], np.array([0, sl.stop - sl.start]))
+        No = np.linalg.inv(K.T @ np.linalg.solve(Mpp, K))
+        assert rel(Nt[p], No) <= 1e-10
+    assert rel(T, mlp.target_from_mobility(Nt)) <= 1e-6
+
+
+def test_standardised_forward_matches_oracle(ctx):
+    P = W.mlp_init_weights(seed=12)
+    rng = np.random.default_rng(4)
+    X = np.column_stack([rng.uniform(8, 15, 64), rng.standard_normal((64, 4)),
+                         rng.integers(0, 2, (64, 2))]).astype(np.float32)
+    sc = (np.float32([11, 0, 0, 0, 0, .5, .5]), np.float32([2, .5, .5, .5, .5, .5, .5]),
+          (0.1 * rng.standard_normal(21)).astype(np.float32),
+          rng.uniform(0.5, 2, 21).astype(np.float32))
+    learned.load_model(ctx, P, sc)
+    try:
+        Y = arb.arb_mlp_forward(ctx, X)
+    finally:
+        arb.arb_mlp_set_scaling(ctx, np.zeros(7), np.ones(7), np.zeros(21), np.ones(21))
+    Yo = mlp.predict(P.astype(float), X.astype(float), *[np.asarray(c, float) for c in sc])
+    assert rel(Y, Yo) <= 3e-2
+
+
+@pytest.fixture(scope="module")
+def trained():
+    X, T = learned.make_dataset(4096, seed=21)
+    sc = learned.scaling(X, T)
+    c = arb.arb_create(precision=arb.ARB_FP64, wall=True)
+    learned.load_model(c, W.mlp_init_weights(seed=6), sc)
+    l0 = arb.arb_mlp_grad(c, X, T)[0]
+    learned.train(c, X, T, epochs=60, batch=512, lr=3e-3, seed=7)
+    l1 = arb.arb_mlp_grad(c, X, T)[0]
+    P = arb.arb_mlp_get_params(c)
+    Y = arb.arb_mlp_forward(c, X[:2000])
+    arb.arb_destroy(c)
+    Np = mlp.mobility_from_output(Y)
+    Ne = mlp.mobility_from_output(T[:2000])
+    err = np.linalg.norm(Np - Ne, axis=(1, 2)) / np.linalg.norm(Ne, axis=(1, 2))
+    print(f"training loss {l0:.3e} -> {l1:.3e}; body mobility rel err median "
+          f"{np.median(err):.2e} max {err.max():.2e}")
+    return (P, sc), l0, l1, X, T
+
+
+def test_training_reduces_loss(trained):
+    P, l0, l1, X, T = trained
+    assert l1 < 0.05 * l0
+
+
+def bar_of(S, info):
+    s = np.linalg.svd(S["A"], compute_uv=False)
+    return max(1e-5, 10 * s[0] / s[-1] * info["rel_residual_fp64"])
+
+
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_learned_preconditioner_solution(trained, prec):
+    model = trained[0]
+    wl = W.bacteria(n_bact=4, side=60.0, seed=21)
+    S = system.assemble(wl)
+    yd = system.solve_dense(S["A"], S["b"])
+    N, M = wl.N, wl.M
+    out = {}
+    for pc in (arb.ARB_PC_BLOCK, arb.ARB_PC_LEARNED, arb.ARB_PC_BODYFRAME):
+        c = arb.context_for(wl, precision=prec, tol=1e-8 if prec == arb.ARB_FP64 else 1e-6,
+                            precond=pc)
+        try:
+            learned.load_model(c, *model)
+            rc, U, phi, lam, info = arb.arb_solve(c, wl.F)
+        finally:
+            arb.arb_destroy(c)
+        assert rc == arb.ARB_OK
+        out[pc] = (U, info)
+    U, info = out[arb.ARB_PC_LEARNED]
+    Ue, infoe = out[arb.ARB_PC_BLOCK]
+    infob = out[arb.ARB_PC_BODYFRAME][1]
+    print(f"prec {prec}: iterations exact {infoe['iterations']} learned {info['iterations']} "
+          f"body-frame {infob['iterations']}, build ms exact {infoe['t_build_ms']:.2f} "
+          f"learned {info['t_build_ms']:.2f} body-frame {infob['t_build_ms']:.2f}")
+    assert rel(out[arb.ARB_PC_BODYFRAME][0], Ue) <= 2 * max(1e-5, bar_of(S, infob))
+    assert info["rel_residual_fp64"] <= (1e-8 if prec == arb.ARB_FP64 else 1e-6)
+    bar = bar_of(S, info)
+    assert rel(U, yd[3 * N:3 * N + 6 * M]) <= bar
+    assert rel(U, Ue) <= 2 * bar
+
+
+def test_learned_fallback_on_invalid_factor():
+    # output biases far outside the factor's range: the prediction is rejected
+    P = W.mlp_init_weights(seed=6).copy()
+    diag = [0, 2, 5, 9, 14, 20]
+    P[-21 + np.array(diag)] = 1e3
+    wl = W.bacteria(n_bact=2, side=40.0, seed=23)
+    c = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10, precond=arb.ARB_PC_LEARNED)
+    try:
+        arb.arb_mlp_set_params(c, P)
+        rc, U, phi, lam, info = arb.arb_solve(c, wl.F)
+    finally:
+        arb.arb_destroy(c)
+    assert rc == arb.ARB_W_LEARNED_FALLBACK
+    assert info["rel_residual"] <= 1e-10
