@@ -27,26 +27,45 @@ sys.path.insert(0, ROOT)
 # (FMA = 2, add/sub/mul = 1, reciprocal square root = 1; selects and compares 0)
 FLOPS_PER_PAIR = {("f32c", True): 136, ("f32c", False): 45, ("f64", True): 130,
                   ("f64", False): 39}
+# symmetric FP32 kernel: per unordered pair outside the 256-blob diagonal blocks
+# (tensor once, applied both ways); ordered pairs inside the blocks as above
+FLOPS_PER_SYM_PAIR = {True: 181, False: 63}
+
+
+def algorithmic_flops(N, shape, wall=True):
+    """Flops of one product for the launch shape used (< 0: symmetric kernel)."""
+    if shape > 0:
+        return FLOPS_PER_PAIR[("f32c", wall)] * float(N) * N
+    nb = [min(256, N - b) for b in range(0, N, 256)]
+    p_diag = float(sum(n * n for n in nb))
+    p_off = (float(N) * N - p_diag) / 2.0
+    return FLOPS_PER_SYM_PAIR[wall] * p_off + FLOPS_PER_PAIR[("f32c", wall)] * p_diag
 # MI355X published vector peaks: 256 CUs x 2.4 GHz x 256 FP32 (128 FP64) flop/clk/CU
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-# HBM traffic of one timed launch from the FETCH_SIZE / WRITE_SIZE runs recorded in
-# profiles/pair_f32c_wall_slab16384.md, scaled by the counts of a 256 MiB copy; valid
-# only for the kernel source it was measured on
-TRAFFIC = {"pair_src_sha256_16": "ef7c7d3e765e2be7", "fetch_kib": 3605.2, "write_kib": 24576.0,
-           "copy_fetch_kib": 131091.4, "copy_write_kib": 262144.0, "copy_kib": 262144.0}
+# HBM traffic of one timed pair product from the FETCH_SIZE / WRITE_SIZE runs recorded
+# under profiles/, scaled by the counts of a 256 MiB copy; each record is valid only
+# for the kernel source it was measured on (symmetric: diagonal + off-diagonal kernels)
+COPY_CAL = {"copy_fetch_kib": 131091.4, "copy_write_kib": 262144.0, "copy_kib": 262144.0}
+TRAFFIC = {
+    "target": {"src": "pair.hip", "sha256_16": "ef7c7d3e765e2be7",
+               "fetch_kib": 3605.2, "write_kib": 24576.0},
+    "symmetric": {"src": "pair_sym.hip", "sha256_16": None,
+                  "fetch_kib": None, "write_kib": None},
+}
 
 
-def measured_traffic():
+def measured_traffic(kind):
     import hashlib
 
-    src = os.path.join(ROOT, "paper_2107_10800_amd", "csrc", "pair.hip")
+    t = TRAFFIC[kind]
+    src = os.path.join(ROOT, "paper_2107_10800_amd", "csrc", t["src"])
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != TRAFFIC["pair_src_sha256_16"]:
+    if t["sha256_16"] is None or sha != t["sha256_16"]:
         return None
-    t = TRAFFIC
-    kib = (t["fetch_kib"] * t["copy_kib"] / t["copy_fetch_kib"]
-           + t["write_kib"] * t["copy_kib"] / t["copy_write_kib"])
+    c = COPY_CAL
+    kib = (t["fetch_kib"] * c["copy_kib"] / c["copy_fetch_kib"]
+           + t["write_kib"] * c["copy_kib"] / c["copy_write_kib"])
     return kib * 1024.0
 
 
@@ -267,7 +286,7 @@ def main():
         err = float(np.linalg.norm(u - uo) / np.linalg.norm(uo))
     pairs = float(N) * N
     value = pairs / (r32["ms_per_step"] * 1e-3)
-    flops = FLOPS_PER_PAIR[("f32c", True)] * pairs
+    flops = algorithmic_flops(N, r32["slices"])
     achieved = flops / (r32["kernel_ms"] * 1e-3) / 1e12
     res = {
         "metric": "wall-RPY blob-pair interactions/s",
@@ -287,11 +306,15 @@ def main():
                                "lambda ~ N(0,1); one product per step",
                    "N": N, "pairs_per_step": int(pairs), "slices": r32["slices"],
                    "parity_rel_err_sampled": err},
-        "roofline": {"bound": "alu", "kernel": "pair_f32c_kernel<wall>",
+        "roofline": {"bound": "alu",
+                     "kernel": ("pair_sym_f32c_kernel<wall> + pair_diag_f32c_kernel<wall>"
+                                if r32["slices"] < 0 else "pair_f32c_kernel<wall>"),
+                     "flops_per_launch": flops,
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "flops_per_pair": FLOPS_PER_PAIR[("f32c", True)],
-                     "kernel_ms": r32["kernel_ms"], "traffic": measured_traffic(),
+                     "flops_per_pair": (FLOPS_PER_SYM_PAIR[True] if r32["slices"] < 0
+                                        else FLOPS_PER_PAIR[("f32c", True)]),
+                     "kernel_ms": r32["kernel_ms"], "traffic": measured_traffic("symmetric" if r32["slices"] < 0 else "target"),
                      "traffic_unit": "bytes per launch"},
         "fp64": {"value": pairs / (r64["ms_per_step"] * 1e-3), "unit": "pairs/s",
                  "ms_per_step": r64["ms_per_step"], "kernel_ms": r64["kernel_ms"],

@@ -74,6 +74,9 @@ typedef struct {
     int    max_iter;   /* GMRES iteration cap (all cycles)                     */
     int    precond;    /* ARB_PC_*                                             */
     int    slices;     /* source slices of the pair kernel; 0 = autotune       */
+    int    pair_kernel; /* 0 = autotuned choice, 1 = target-parallel kernel,   */
+                        /* 2 = symmetric kernel (FP32C only: each unordered    */
+                        /* pair once, M_ji = M_ij^T)                           */
 } arb_options;
 
 typedef struct {
@@ -94,7 +97,9 @@ typedef struct {
 int  arb_create(arb_ctx **out, const arb_options *opt);
 void arb_destroy(arb_ctx *ctx);
 const char *arb_last_error(const arb_ctx *ctx);
-/* Pair-kernel launch shape actually used (after autotuning): source slices. */
+/* Pair-kernel launch shape actually used (after autotuning): > 0 source
+ * slices of the target-parallel kernel, < 0 the symmetric kernel with -value
+ * source tiles per work item. */
 int  arb_get_slices(const arb_ctx *ctx, int n_blobs);
 
 /* -------------------------------------------------------------- bodies

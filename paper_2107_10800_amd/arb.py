@@ -32,6 +32,9 @@ ARB_PC_NONE = 0
 ARB_PC_BLOCK = 1
 ARB_PC_LEARNED = 2
 ARB_PC_BODYFRAME = 3
+ARB_PAIR_AUTO = 0
+ARB_PAIR_TARGET = 1
+ARB_PAIR_SYMMETRIC = 2
 
 SYMBOLS = [
     "arb_create", "arb_destroy", "arb_last_error", "arb_get_slices", "arb_set_bodies",
@@ -56,7 +59,7 @@ class arb_options(C.Structure):
     _fields_ = [("device", C.c_int), ("precision", C.c_int), ("wall", C.c_int),
                 ("eta", C.c_double), ("a", C.c_double), ("tol", C.c_double),
                 ("restart", C.c_int), ("max_iter", C.c_int), ("precond", C.c_int),
-                ("slices", C.c_int)]
+                ("slices", C.c_int), ("pair_kernel", C.c_int)]
 
 
 class arb_solve_info(C.Structure):
@@ -177,9 +180,9 @@ def _check(ctx, rc):
 
 # ------------------------------------------------------------------ entry points
 def arb_create(device=0, precision=ARB_FP64, wall=False, eta=1.0, a=1.0, tol=1e-10,
-               restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0):
+               restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0, pair_kernel=0):
     opt = arb_options(device, precision, int(bool(wall)), eta, a, tol, restart, max_iter,
-                      precond, slices)
+                      precond, slices, pair_kernel)
     h = _P()
     rc = load().arb_create(C.byref(h), C.byref(opt))
     if rc < 0:
@@ -449,10 +452,11 @@ def arb_body_mobility(ctx):
 
 # ------------------------------------------------------------------ convenience
 def context_for(wl, precision=ARB_FP64, tol=1e-10, restart=100, max_iter=1000,
-                precond=ARB_PC_BLOCK, device=0, slices=0):
+                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0):
     """Create a context and load a workload (bodies, links, rows, state)."""
     ctx = arb_create(device=device, precision=precision, wall=wl.wall, eta=wl.eta, a=wl.a,
-                     tol=tol, restart=restart, max_iter=max_iter, precond=precond, slices=slices)
+                     tol=tol, restart=restart, max_iter=max_iter, precond=precond, slices=slices,
+                     pair_kernel=pair_kernel)
     arb_set_bodies(ctx, wl.blob_offset, wl.r_ref, wl.body_type)
     if len(wl.pq):
         arb_set_links(ctx, wl.pq, wl.dl_p, wl.dl_q, wl.dldot_p, wl.dldot_q, wl.nproj, wl.proj)

@@ -222,18 +222,46 @@ int heuristic_slices(int N) {
     return s;
 }
 
+int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R) {
+    if (ctx->sym_work_N == N && ctx->sym_work_R == R) return 0;
+    std::vector<int4> w = arb::pair_sym_worklist(N, R);
+    HIPCHK(ctx->sym_work.ensure(std::max<size_t>(w.size(), 1) * sizeof(int4)));
+    if (!w.empty())
+        HIPCHK(hipMemcpyAsync(ctx->sym_work.p, w.data(), w.size() * sizeof(int4),
+                              hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->sym_work_N = N;
+    ctx->sym_work_R = R;
+    ctx->sym_n_work = (int)w.size();
+    return 0;
+}
+
+// one pair product; shape > 0: target-parallel kernel with that many source
+// slices; shape < 0: symmetric FP32 kernel with -shape source tiles per item
 int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
              const float4 *lo, const double *lam, double *out, const double *U, const int *bob,
-             const double *dvec, int precision, bool wall, int slices) {
-    HIPCHK(ctx->partial.ensure((size_t)slices * 3 * N * sizeof(double)));
+             const double *dvec, int precision, bool wall, int shape) {
+    const bool sym = shape < 0 && precision == ARB_FP32C;
+    int used = 1;
+    if (sym) {
+        TRY(sym_worklist(ctx, s, N, -shape));
+        HIPCHK(ctx->partial.ensure((size_t)3 * N * sizeof(double)));
+    } else {
+        if (shape < 0) shape = heuristic_slices(N);
+        HIPCHK(ctx->partial.ensure((size_t)shape * 3 * N * sizeof(double)));
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->prof) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, s));
     }
-    const int used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, slices,
-                                       ctx->partial.as<double>());
+    if (sym)
+        arb::pair_sym_f32c(s, wall, N, hi, lo, lam, ctx->opt.a, ctx->sym_work.as<int4>(),
+                           ctx->sym_n_work, ctx->partial.as<double>());
+    else
+        used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, shape,
+                                 ctx->partial.as<double>());
     if (ctx->prof) {
         HIPCHK(hipEventRecord(e1, s));
         ctx->prof_ev.emplace_back(e0, e1);
@@ -243,19 +271,31 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
     return 0;
 }
 
+// launch shape for (N, precision, wall): from the options, the cache, or by
+// timing every candidate shape on the first product of that size
 int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
-                  const float4 *lo, const double *lam, int precision, bool wall) {
-    if (ctx->opt.slices > 0) return ctx->opt.slices;
+                  const float4 *lo, const double *lam, int precision, bool wall, int *shape) {
+    const int kind = ctx->opt.pair_kernel;
+    const bool sym_ok = precision == ARB_FP32C && kind != 1;
+    if (ctx->opt.slices > 0 && kind != 2) {
+        *shape = ctx->opt.slices;
+        return 0;
+    }
     const int64_t key = (int64_t)N * 4 + precision * 2 + (wall ? 1 : 0);
     auto it = ctx->slice_cache.find(key);
-    if (it != ctx->slice_cache.end()) return it->second;
+    if (it != ctx->slice_cache.end()) {
+        *shape = it->second;
+        return 0;
+    }
     const int h = heuristic_slices(N);
     const int ntiles = (N + arb::kTile - 1) / arb::kTile;
-    int best = h;
-    if (N >= 8192) {
-        // autotune: time candidate source splits on this problem (two runs each)
-        std::vector<int> cand;
+    std::vector<int> cand;
+    if (kind != 2 || precision != ARB_FP32C)
         for (int c = std::max(1, h / 2); c <= std::min(ntiles, h * 16); c *= 2) cand.push_back(c);
+    if (sym_ok)
+        for (int R : {2, 4, 8, 16}) cand.push_back(-R);
+    int best = cand.empty() ? h : cand[0];
+    if (N >= 8192 && cand.size() > 1) {
         HIPCHK(ctx->tune_out.ensure(3 * (size_t)N * sizeof(double)));
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -265,8 +305,8 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
             float tsum = 0.f;
             for (int rep = 0; rep < 3; ++rep) {
                 HIPCHK(hipEventRecord(e0, s));
-                TRY(run_pair(ctx, s, N, p64, hi, lo, lam, ctx->tune_out.as<double>(), nullptr, nullptr,
-                             nullptr, precision, wall, c));
+                TRY(run_pair(ctx, s, N, p64, hi, lo, lam, ctx->tune_out.as<double>(), nullptr,
+                             nullptr, nullptr, precision, wall, c));
                 HIPCHK(hipEventRecord(e1, s));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -280,17 +320,20 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+    } else if (sym_ok && kind == 2) {
+        best = -4;
     }
     ctx->slice_cache[key] = best;
-    return best;
+    *shape = best;
+    return 0;
 }
 
 int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const double *U,
              int precision) {
     const bool wall = ctx->opt.wall != 0;
-    const int sl = choose_slices(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
-                                 ctx->lo.as<float4>(), lam, precision, wall);
-    if (sl < 0) return sl;
+    int sl = 0;
+    TRY(choose_slices(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
+                      ctx->lo.as<float4>(), lam, precision, wall, &sl));
     return run_pair(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
                     ctx->lo.as<float4>(), lam, out, U, ctx->body_of_blob.as<int>(),
                     ctx->dvec.as<double>(), precision, wall, sl);
@@ -585,7 +628,7 @@ int dev_norm(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *x, int slot, 
 // iteration budget.  Returns the final residual norm in *res (same operator).
 int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double *y,
                double tol_abs, int prec, int max_iter, int *total, int *restarts,
-               double hist_scale, arb_solve_info *inf, double *res) {
+               double hist_scale, arb_solve_info *inf, double *res, bool trust_estimate) {
     const int64_t n = K.n;
     const int m = K.m;
     double *pin = ctx->pinned;
@@ -604,6 +647,7 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         if (beta <= tol_abs || *total >= max_iter) break;
         arb::scale_copy(s, n, K.r, K.sc + 3, K.V);  // v_0 = r / beta
         int k = 0;
+        double last_est = beta;
         for (int j = 0; j < m; ++j) {
             double *vj = K.V + (size_t)j * n;
             TRY(precond_apply(ctx, s, vj, K.z));
@@ -622,6 +666,7 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
             ++*total;
             k = j + 1;
             push(est * hist_scale);
+            last_est = est;
             if (est <= tol_abs || *total >= max_iter || hn == 0.0) break;
             arb::scale_copy(s, n, K.w, K.sc + 5, K.V + (size_t)(j + 1) * n);
         }
@@ -629,6 +674,13 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         arb::gemv_set(s, n, k, K.V, n, K.sv, K.w);
         TRY(precond_apply(ctx, s, K.w, K.z));
         arb::axpby(s, n, 1.0, K.z, 1.0, y);
+        ++*restarts;
+        if (trust_estimate && last_est <= tol_abs) {
+            // an outer loop recomputes the residual in higher precision
+            *res = last_est;
+            return 0;
+        }
+        --*restarts;
         TRY(system_apply(ctx, s, y, K.r, prec));
         arb::axpby(s, n, 1.0, rhs, -1.0, K.r);  // r = rhs - A y
         ++*restarts;
@@ -685,7 +737,7 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
     const int max_iter = ctx->opt.max_iter;
     if (prec == ARB_FP64) {
         TRY(gmres_core(ctx, s, K, K.b, y, tol * bnorm, ARB_FP64, max_iter, &total, &restarts,
-                       1.0 / bnorm, inf, &res));
+                       1.0 / bnorm, inf, &res, false));
     } else {
         // GMRES iterative refinement: the correction equation A d = r is solved by
         // GMRES with the FP32 pair sum to a modest relative tolerance; r = b - A y
@@ -701,7 +753,7 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
             const double eta = std::max(1e-4, 0.5 * tol * bnorm / res);
             double rin = 0.0;
             TRY(gmres_core(ctx, s, K, rhs, d, eta * res, ARB_FP32C, max_iter, &total, &restarts,
-                           1.0 / bnorm, inf, &rin));
+                           1.0 / bnorm, inf, &rin, true));
             arb::axpby(s, n, 1.0, d, 1.0, y);
             TRY(system_apply(ctx, s, y, K.r, ARB_FP64));
             arb::axpby(s, n, 1.0, K.b, -1.0, K.r);
@@ -747,7 +799,8 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
     if (!(opt->a > 0) || !(opt->eta > 0) || !(opt->tol > 0) || opt->restart < 1 ||
         opt->restart > 256 || opt->max_iter < 1 ||
         (opt->precision != ARB_FP64 && opt->precision != ARB_FP32C) || opt->precond < 0 ||
-        opt->precond > 3 || opt->slices < 0 || opt->slices > 4096)
+        opt->precond > 3 || opt->slices < 0 || opt->slices > 4096 || opt->pair_kernel < 0 ||
+        opt->pair_kernel > 2)
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
@@ -980,8 +1033,8 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *
     float4 *lo = hi + N;
     arb::prep_positions(s, N, pos_dev, p64, hi, lo);
     const bool wall = ctx->opt.wall != 0;
-    const int sl = choose_slices(ctx, s, N, p64, hi, lo, lambda_dev, ctx->opt.precision, wall);
-    if (sl < 0) return sl;
+    int sl = 0;
+    TRY(choose_slices(ctx, s, N, p64, hi, lo, lambda_dev, ctx->opt.precision, wall, &sl));
     TRY(run_pair(ctx, s, N, p64, hi, lo, lambda_dev, u_dev, nullptr, nullptr, nullptr,
                  ctx->opt.precision, wall, sl));
     HIPCHK(hipGetLastError());

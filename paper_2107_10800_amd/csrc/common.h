@@ -55,6 +55,10 @@ void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double
                  double *out, const double *U, const int *body_of_blob, const double *dvec);
 int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,
                         int *flag_host);
+// symmetric FP32 pair sums (pair_sym.hip): u [3][N] unscaled
+void pair_sym_f32c(hipStream_t s, bool wall, int N, const float4 *hi, const float4 *lo,
+                   const double *lam, double a, const int4 *work, int n_work, double *u);
+std::vector<int4> pair_sym_worklist(int N, int R);
 
 // Rigid-body kinematics (Sec. 2.1, 2.3, App. B)
 void rotations(hipStream_t s, int M, const double *theta, double *R9);
@@ -183,8 +187,12 @@ struct arb_ctx {
     int n_asm = 0;
     int max_m = 0;
     std::vector<int> h_asm_body_ptr, h_asm_bodies, h_asm_row_ptr, h_asm_rows;
-    // autotune cache: key = N*4 + precision*2 + wall -> slices
+    // autotune cache: key = N*4 + precision*2 + wall -> launch shape; values > 0
+    // are source slices of the target-parallel kernel, values < 0 select the
+    // symmetric kernel with -value source tiles per work item
     std::map<int64_t, int> slice_cache;
+    arb::DevBuf sym_work;
+    int sym_work_N = -1, sym_work_R = -1, sym_n_work = 0;
     bool pc_built = false;
     bool pc_learned = false;
     int pc_pinv = 0;

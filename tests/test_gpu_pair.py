@@ -100,3 +100,34 @@ def test_below_wall_rejected(ctxs):
     with pytest.raises(arb.ArbError) as e:
         arb.arb_rpy_apply(ctxs[(arb.ARB_FP64, False)], pos, np.array([1, np.nan, 0, 0, 0, 0.0]))
     assert e.value.code == arb.ARB_E_NAN
+
+
+@pytest.mark.parametrize("n", [1, 65, 300, 1000, 5000])
+@pytest.mark.parametrize("wall", [False, True])
+def test_symmetric_kernel_small(n, wall):
+    # FP32 symmetric kernel (each unordered pair once): ragged tiles and blocks
+    cl = W.random_blobs(n, seed=200 + n, box=8.0 + n ** (1 / 3))
+    c = arb.arb_create(precision=arb.ARB_FP32C, wall=wall, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
+    try:
+        print(f"symmetric pair n={n} wall={wall}", flush=True)
+        u = arb.arb_rpy_apply(c, cl["pos"], cl["lam"])
+    finally:
+        arb.arb_destroy(c)
+    uo = rpy.mobility_apply(cl["pos"], cl["lam"], 1.0, 1.0, wall)
+    assert rel(u, uo) <= TOL[arb.ARB_FP32C]
+
+
+def test_symmetric_kernel_slab_sampled():
+    sl = W.slab()
+    N = len(sl["pos"])
+    c = arb.arb_create(precision=arb.ARB_FP32C, wall=True, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
+    try:
+        u = arb.arb_rpy_apply(c, sl["pos"], sl["lam"]).reshape(N, 3)
+        shape = arb.arb_get_slices(c, N)
+    finally:
+        arb.arb_destroy(c)
+    assert shape < 0
+    rng = np.random.default_rng(1)
+    tg = np.unique(np.concatenate([[0, 63, 64, 255, 256, N - 1], rng.integers(0, N, 26)]))
+    uo = rpy.mobility_apply(sl["pos"], sl["lam"], 1.0, 1.0, True, targets=tg)
+    assert rel(u[tg], uo) <= TOL[arb.ARB_FP32C]
