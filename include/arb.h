@@ -74,9 +74,11 @@ typedef struct {
     int    max_iter;   /* GMRES iteration cap (all cycles)                     */
     int    precond;    /* ARB_PC_*                                             */
     int    slices;     /* source slices of the pair kernel; 0 = autotune       */
-    int    pair_kernel; /* 0 = autotuned choice, 1 = target-parallel kernel,   */
-                        /* 2 = symmetric kernel (FP32C only: each unordered    */
-                        /* pair once, M_ji = M_ij^T)                           */
+    int    pair_kernel; /* 0 = autotuned choice, 1 = target-parallel kernel   */
+                        /* (ordered reduction: bitwise reproducible),          */
+                        /* 2 = symmetric kernel (each unordered pair once,     */
+                        /* M_ji = M_ij^T; FP64 atomic sums, reproducible to    */
+                        /* rounding only)                                      */
 } arb_options;
 
 typedef struct {

@@ -237,17 +237,16 @@ int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R) {
 }
 
 // one pair product; shape > 0: target-parallel kernel with that many source
-// slices; shape < 0: symmetric FP32 kernel with -shape source tiles per item
+// slices; shape < 0: symmetric kernel with -shape source tiles per work item
 int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
              const float4 *lo, const double *lam, double *out, const double *U, const int *bob,
              const double *dvec, int precision, bool wall, int shape) {
-    const bool sym = shape < 0 && precision == ARB_FP32C;
+    const bool sym = shape < 0;
     int used = 1;
     if (sym) {
         TRY(sym_worklist(ctx, s, N, -shape));
         HIPCHK(ctx->partial.ensure((size_t)3 * N * sizeof(double)));
     } else {
-        if (shape < 0) shape = heuristic_slices(N);
         HIPCHK(ctx->partial.ensure((size_t)shape * 3 * N * sizeof(double)));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -257,8 +256,8 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
         HIPCHK(hipEventRecord(e0, s));
     }
     if (sym)
-        arb::pair_sym_f32c(s, wall, N, hi, lo, lam, ctx->opt.a, ctx->sym_work.as<int4>(),
-                           ctx->sym_n_work, ctx->partial.as<double>());
+        arb::pair_sym(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a,
+                      ctx->sym_work.as<int4>(), ctx->sym_n_work, ctx->partial.as<double>());
     else
         used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, shape,
                                  ctx->partial.as<double>());
@@ -276,7 +275,7 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
 int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
                   const float4 *lo, const double *lam, int precision, bool wall, int *shape) {
     const int kind = ctx->opt.pair_kernel;
-    const bool sym_ok = precision == ARB_FP32C && kind != 1;
+    const bool sym_ok = kind != 1;
     if (ctx->opt.slices > 0 && kind != 2) {
         *shape = ctx->opt.slices;
         return 0;
@@ -290,10 +289,10 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
     const int h = heuristic_slices(N);
     const int ntiles = (N + arb::kTile - 1) / arb::kTile;
     std::vector<int> cand;
-    if (kind != 2 || precision != ARB_FP32C)
+    if (kind != 2)
         for (int c = std::max(1, h / 2); c <= std::min(ntiles, h * 16); c *= 2) cand.push_back(c);
     if (sym_ok)
-        for (int R : {2, 4, 8, 16}) cand.push_back(-R);
+        for (int R : {1, 2, 4, 8, 16}) cand.push_back(-R);
     int best = cand.empty() ? h : cand[0];
     if (N >= 8192 && cand.size() > 1) {
         HIPCHK(ctx->tune_out.ensure(3 * (size_t)N * sizeof(double)));
@@ -372,6 +371,7 @@ arb::PrecondDev pc_view(arb_ctx *ctx) {
     P.mats = ctx->mats.as<double>();
     P.minv = ctx->minv.as<double>();
     P.ldiag = ctx->ldiag.as<double>();
+    P.dinv = ctx->dinv.as<double>();
     P.Z = ctx->Z.as<double>();
     P.Nt = ctx->Nt.as<double>();
     P.G = ctx->G.as<double>();
@@ -431,6 +431,7 @@ int ensure_types(arb_ctx *ctx, hipStream_t s) {
     HIPCHK(ctx->t_minv.ensure(std::max<int64_t>(mo[T], 1) * sizeof(double)));
     HIPCHK(ctx->t_Z.ensure(std::max<int64_t>(zo[T], 1) * sizeof(double)));
     HIPCHK(ctx->t_ldiag.ensure(std::max<size_t>(pos.size(), 1) * sizeof(double)));
+    HIPCHK(ctx->t_dinv.ensure(arb::precond_dinv_size(tb[T], T) * sizeof(double)));
     HIPCHK(ctx->t_Nt.ensure(36 * (size_t)T * sizeof(double)));
     HIPCHK(ctx->t_status.ensure(8 * sizeof(int)));
     HIPCHK(hipMemsetAsync(ctx->t_status.p, 0, 8 * sizeof(int), s));
@@ -442,11 +443,14 @@ int ensure_types(arb_ctx *ctx, hipStream_t s) {
     P.mats = ctx->t_mats.as<double>();
     P.minv = ctx->t_minv.as<double>();
     P.ldiag = ctx->t_ldiag.as<double>();
+    P.dinv = ctx->t_dinv.as<double>();
     P.Z = ctx->t_Z.as<double>();
     P.Nt = ctx->t_Nt.as<double>();
     P.status = ctx->t_status.as<int>();
     arb::precond_assemble(s, P, ctx->t_ref.as<double>(), ctx->opt.a, ctx->opt.eta, false);
-    arb::precond_factor(s, P, ctx->t_ref.as<double>(), 0);
+    int t_max_m = 0;
+    for (int t = 0; t < T; ++t) t_max_m = std::max(t_max_m, 3 * (tb[t + 1] - tb[t]));
+    HIPCHK(arb::precond_factor(s, P, ctx->t_ref.as<double>(), t_max_m));
     int st[8];
     HIPCHK(hipMemcpyAsync(st, ctx->t_status.p, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -523,16 +527,19 @@ int precond_build_exact(arb_ctx *ctx, hipStream_t s) {
     TRY(ready(ctx));
     const int M = ctx->M;
     std::vector<int64_t> mo(M + 1, 0), zo(M + 1, 0);
+    int max_m = 0;
     for (int p = 0; p < M; ++p) {
         const int64_t m = 3 * (int64_t)(ctx->h_blob_off[p + 1] - ctx->h_blob_off[p]);
         mo[p + 1] = mo[p] + m * m;
         zo[p + 1] = zo[p] + 6 * m;
+        max_m = std::max(max_m, (int)m);
     }
     TRY(upload(ctx, ctx->mat_off, mo.data(), M + 1, s));
     TRY(upload(ctx, ctx->z_off, zo.data(), M + 1, s));
     HIPCHK(ctx->mats.ensure(std::max<int64_t>(mo[M], 1) * sizeof(double)));
     HIPCHK(ctx->minv.ensure(std::max<int64_t>(mo[M], 1) * sizeof(double)));
     HIPCHK(ctx->ldiag.ensure(3 * (size_t)ctx->N * sizeof(double)));
+    HIPCHK(ctx->dinv.ensure(arb::precond_dinv_size(ctx->N, M) * sizeof(double)));
     HIPCHK(ctx->Z.ensure(std::max<int64_t>(zo[M], 1) * sizeof(double)));
     HIPCHK(ctx->Nt.ensure(36 * (size_t)M * sizeof(double)));
     HIPCHK(ctx->pctmp.ensure(6 * (size_t)M * sizeof(double)));
@@ -540,7 +547,7 @@ int precond_build_exact(arb_ctx *ctx, hipStream_t s) {
     HIPCHK(hipMemsetAsync(ctx->status.p, 0, 8 * sizeof(int), s));
     arb::PrecondDev P = pc_view(ctx);
     arb::precond_assemble(s, P, ctx->pos.as<double>(), ctx->opt.a, ctx->opt.eta, ctx->opt.wall != 0);
-    arb::precond_factor(s, P, ctx->dvec.as<double>(), 0);
+    HIPCHK(arb::precond_factor(s, P, ctx->dvec.as<double>(), max_m));
     arb::precond_assembly(s, P);
     int st[8];
     HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));

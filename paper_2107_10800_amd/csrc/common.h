@@ -55,9 +55,10 @@ void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double
                  double *out, const double *U, const int *body_of_blob, const double *dvec);
 int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,
                         int *flag_host);
-// symmetric FP32 pair sums (pair_sym.hip): u [3][N] unscaled
-void pair_sym_f32c(hipStream_t s, bool wall, int N, const float4 *hi, const float4 *lo,
-                   const double *lam, double a, const int4 *work, int n_work, double *u);
+// symmetric pair sums, FP32 (hi/lo) or FP64 (p64) (pair_sym.hip): u [3][N] unscaled
+void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+              const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
+              int n_work, double *u);
 std::vector<int4> pair_sym_worklist(int N, int R);
 
 // Rigid-body kinematics (Sec. 2.1, 2.3, App. B)
@@ -94,6 +95,7 @@ struct PrecondDev {
     double *mats = nullptr;   // per-body M_pp, Cholesky in place
     double *minv = nullptr;   // per-body M_pp^-1 (same offsets as mats)
     double *ldiag = nullptr;  // diag(L) per body (3N)
+    double *dinv = nullptr;   // inverses of L's 32 x 32 diagonal blocks per body
     double *Z = nullptr;      // per-body Z_p = M_pp^-1 K_p (3n_p x 6)
     double *Nt = nullptr;     // per-body N~_p (36)
     double *G = nullptr;      // per-assembly G~_a
@@ -109,7 +111,9 @@ struct PrecondDev {
 };
 void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos, double a,
                       double eta, bool wall);
-void precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
+// max_m = largest 3 n_p of the batch
+hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
+int64_t precond_dinv_size(int64_t n_blobs, int M);
 void precond_assembly(hipStream_t s, const PrecondDev &P);
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z);
 void rotate_body_mobility(hipStream_t s, int M, const int *type, const double *tNt,
@@ -201,7 +205,7 @@ struct arb_ctx {
     arb::DevBuf blob_off, body_of_blob, r_ref, q, theta, R9, pos, dvec, p64, hi, lo,
         partial, row_p, row_q, row_kind, row_src, row_m, dl_p, dl_q, dldot_p, dldot_q, proj,
         gcoef, grhs, crow, Bc, brow_ptr, brow_ent, asm_body_ptr, asm_bodies, asm_row_ptr,
-        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, Z, Nt, G, S, status, pctmp;
+        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp;
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
@@ -211,7 +215,7 @@ struct arb_ctx {
     arb::DevBuf tune_out;
     // learned body mobility: network parameters, workspace, per-type blocks
     arb::DevBuf mlp_params, mlp_ws, mlp_x, mlp_t, body_type_d, t_ref, t_mat_off, t_z_off, t_minv,
-        t_Z, t_mats, t_ldiag, t_Nt, t_blob_off, t_status;
+        t_Z, t_mats, t_ldiag, t_dinv, t_Nt, t_blob_off, t_status;
     bool mlp_ready = false;
     int mlp_step = 0;
     bool types_ready = false;

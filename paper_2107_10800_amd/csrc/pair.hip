@@ -83,11 +83,13 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
                 const float dxy2 = fmaf(dx, dx, dy * dy);
                 const float r2 = fmaf(dz, dz, dxy2);
                 const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
-                rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
                 if (WALL) {
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                    rpy_image<float>(dx, dy, Rz, sh.z, Ri, L.x, L.y, L.z, c, ax, ay, az);
+                    const PairCoef<float> w = wall_pair_coef<float>(r2, rinv, zi, sh.z, Rz, Ri, c);
+                    wall_pair_apply<float>(w, w.c, w.d, dx, dy, dz, Rz, L.x, L.y, L.z, ax, ay, az);
+                } else {
+                    rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
                 }
             }
             ux += (double)ax;
@@ -136,11 +138,13 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
             const double dxy2 = fma(dx, dx, dy * dy);
             const double r2 = fma(dz, dz, dxy2);
             const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
-            rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);
             if (WALL) {
                 const double Rz = ti.z + sj.z;
                 const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
-                rpy_image<double>(dx, dy, Rz, sj.z, Ri, lx, ly, lz, c, ux, uy, uz);
+                const PairCoef<double> w = wall_pair_coef<double>(r2, rinv, ti.z, sj.z, Rz, Ri, c);
+                wall_pair_apply<double>(w, w.c, w.d, dx, dy, dz, Rz, lx, ly, lz, ux, uy, uz);
+            } else {
+                rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);
             }
         }
     }

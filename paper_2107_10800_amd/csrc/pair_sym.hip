@@ -1,26 +1,29 @@
-// Symmetric blob-pair product for FP32 pair sums (Sec. 2.3, Eq. RPY).
+// Symmetric blob-pair product u = M lambda (Sec. 2.3, Eq. RPY), FP32 and FP64.
 //
 // The pair tensor obeys M(x_j, x_i) = M(x_i, x_j)^T (reciprocity of the RPY and
 // wall-corrected RPY tensors), so each unordered pair is evaluated once and
-// applied to both blobs: u_i += M_ij lambda_j and u_j += M_ij^T lambda_i.  For the
-// wall image I = (1/|R|)[A delta + B e e^T + C e z^T + D z e^T + E z z^T] the
-// transpose swaps C and D.
+// applied to both blobs: u_i += M_ij lambda_j and u_j += M_ij^T lambda_i.  With
+// the coefficients of rpy_device.h the transpose only swaps two scalars.
 //
 // Work decomposition: tiles of 64 blobs; an "I-block" is 4 consecutive tiles
-// (256 targets, one per thread of a 256-thread block).
-//   * pair_diag_f32c_kernel: all ordered pairs inside each I-block (the plain
-//     target-parallel loop), written to u (first writer).
-//   * pair_sym_f32c_kernel: one work item = (I-block b, source tiles J0..J0+nJ-1)
-//     with J0 >= 4b+4, so every tile pair (I < J) is visited exactly once.  Each
-//     wavefront keeps its 64 targets in registers; the source tile is staged in
-//     LDS; at step s lane l meets source (l + s) mod 64 and its source-side
-//     accumulator moves one lane down after each step (a wave shuffle), so after
-//     64 steps lane l holds source l's sum.  The 4 wavefronts' source sums are
-//     added in LDS and then to u in FP64 (device atomics); target sums are
-//     promoted to FP64 after each source tile and added to u at the end.
-// Float sums run over at most 64 pairs before promotion to double.  Rows beyond
-// N are padded with far-away zero-force blobs.  FP64 addition order of the
-// atomics varies between runs (results reproducible to FP64 rounding).
+// (256 targets, one per thread of a 256-thread block).  One launch runs a work
+// list of two kinds of items:
+//   * off-diagonal (b, J0, nJ, 0): I-block b against source tiles J0..J0+nJ-1
+//     with J0 >= 4b+4, so every tile pair (I < J) across blocks is visited once.
+//     Each wavefront keeps its 64 targets in registers; the source tile is
+//     staged in LDS; at step s lane l meets source (l + s) mod 64 and its
+//     source-side accumulator moves one lane down after each step (a wave
+//     shuffle), so after 64 steps lane l holds source l's sum.  The 4
+//     wavefronts' source sums are added in LDS and then to u in FP64 (device
+//     atomics);
+//   * diagonal (b, 4b, nJ, 1): all ordered pairs among I-block b's own tiles,
+//     target side only (the self pair included).
+// FP32 (positions split hi + lo): float sums over one source tile, promoted to
+// FP64 per tile.  FP64: the same work list with double positions and sums.
+// Target sums are promoted to FP64 after each source tile and added to u at the
+// end of the item.  u is cleared first; FP64 addition order of the atomics
+// varies between runs (results reproducible to FP64 rounding).  Rows beyond N
+// are padded with far-away zero-force blobs.
 #include <algorithm>
 #include <vector>
 
@@ -29,71 +32,26 @@
 namespace arb {
 
 // accumulate the free-space tensor both ways: f += M lj, a += M li
-__device__ __forceinline__ void sym_free(float dx, float dy, float dz, float r2, float rinv,
-                                         float lix, float liy, float liz, float ljx, float ljy,
-                                         float ljz, const CoefF &c, float &fx, float &fy,
-                                         float &fz, float &ax, float &ay, float &az) {
-    const float rinv2 = rinv * rinv;
-    float c1 = rinv * fmaf(c.k1, rinv2, 1.f);
-    float c2 = rinv * rinv2 * fmaf(-c.k2, rinv2, 1.f);
+template <class T, class C>
+__device__ __forceinline__ void sym_free(T dx, T dy, T dz, T r2, T rinv, T lix, T liy, T liz,
+                                         T ljx, T ljy, T ljz, const C &c, T &fx, T &fy, T &fz,
+                                         T &ax, T &ay, T &az) {
+    const T rinv2 = rinv * rinv;
+    T c1 = rinv * fma(c.k1, rinv2, T(1));
+    T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
     if (r2 <= c.four_a2) {
-        const float r = r2 * rinv;
-        c1 = fmaf(-c.n2, r, c.n1);
+        const T r = r2 * rinv;
+        c1 = fma(-c.n2, r, c.n1);
         c2 = rinv * c.n3;
     }
-    const float tj = c2 * fmaf(dx, ljx, fmaf(dy, ljy, dz * ljz));
-    const float ti = c2 * fmaf(dx, lix, fmaf(dy, liy, dz * liz));
-    fx = fmaf(c1, ljx, fmaf(tj, dx, fx));
-    fy = fmaf(c1, ljy, fmaf(tj, dy, fy));
-    fz = fmaf(c1, ljz, fmaf(tj, dz, fz));
-    ax = fmaf(c1, lix, fmaf(ti, dx, ax));
-    ay = fmaf(c1, liy, fmaf(ti, dy, ay));
-    az = fmaf(c1, liz, fmaf(ti, dz, az));
-}
-
-// wall image both ways; h = source height zj, Rz = zi + zj
-__device__ __forceinline__ void sym_image(float dx, float dy, float Rz, float h, float Ri,
-                                          float lix, float liy, float liz, float ljx, float ljy,
-                                          float ljz, const CoefF &c, float &fx, float &fy,
-                                          float &fz, float &ax, float &ay, float &az) {
-    const float e3 = Rz * Ri;
-    const float hh = h * Ri;
-    const float Ri2 = Ri * Ri;
-    const float p = c.a2 * Ri2;
-    const float p2 = p * p;
-    const float e32 = e3 * e3;
-    const float hh2 = hh * hh;
-    const float eh = e3 * hh;
-    float Ah = fmaf(2.f, hh2, -1.f);
-    Ah = fmaf(-2.f, eh, Ah);
-    Ah = fmaf(p, fmaf(2.f, e32, -2.f / 3.f), Ah);
-    Ah = fmaf(p2, fmaf(-10.f / 3.f, e32, 2.f / 3.f), Ah);
-    float Bh = fmaf(-6.f, hh2, -1.f);
-    Bh = fmaf(6.f, eh, Bh);
-    Bh = fmaf(p, fmaf(-10.f, e32, 2.f), Bh);
-    Bh = fmaf(p2, fmaf(70.f / 3.f, e32, -10.f / 3.f), Bh);
-    float Ch = hh * fmaf(-12.f, e32, 2.f);
-    Ch = fmaf(12.f * eh, hh, Ch);
-    Ch = fmaf(e3, fmaf(p, fmaf(20.f, e32, -4.f), p2 * fmaf(-140.f / 3.f, e32, 40.f / 3.f)), Ch);
-    const float Dh = fmaf(-20.f / 3.f, p2 * e3, 2.f * hh);
-    float Eh = p2 * fmaf(20.f, e32, -8.f / 3.f);
-    Eh = fmaf(-4.f, p * e32, Eh);
-    Eh = fmaf(-4.f, hh2, Eh);
-    const float AR = Ah * Ri;
-    // I lj
-    const float sj = Ri * fmaf(dx, ljx, fmaf(dy, ljy, Rz * ljz));
-    const float t1 = fmaf(Bh, sj, Ch * ljz) * Ri2;
-    const float t2 = fmaf(Dh, sj, Eh * ljz) * Ri;
-    fx = fmaf(AR, ljx, fmaf(t1, dx, fx));
-    fy = fmaf(AR, ljy, fmaf(t1, dy, fy));
-    fz = fmaf(AR, ljz, fmaf(t1, Rz, fz)) + t2;
-    // I^T li (C and D swap)
-    const float si = Ri * fmaf(dx, lix, fmaf(dy, liy, Rz * liz));
-    const float q1 = fmaf(Bh, si, Dh * liz) * Ri2;
-    const float q2 = fmaf(Ch, si, Eh * liz) * Ri;
-    ax = fmaf(AR, lix, fmaf(q1, dx, ax));
-    ay = fmaf(AR, liy, fmaf(q1, dy, ay));
-    az = fmaf(AR, liz, fmaf(q1, Rz, az)) + q2;
+    const T tj = c2 * fma(dx, ljx, fma(dy, ljy, dz * ljz));
+    const T ti = c2 * fma(dx, lix, fma(dy, liy, dz * liz));
+    fx = fma(c1, ljx, fma(tj, dx, fx));
+    fy = fma(c1, ljy, fma(tj, dy, fy));
+    fz = fma(c1, ljz, fma(tj, dz, fz));
+    ax = fma(c1, lix, fma(ti, dx, ax));
+    ay = fma(c1, liy, fma(ti, dy, ay));
+    az = fma(c1, liz, fma(ti, dz, az));
 }
 
 struct Blob32 {
@@ -118,48 +76,9 @@ __device__ __forceinline__ Blob32 load_blob(int i, int N, const float4 *__restri
     return b;
 }
 
-template <bool WALL>
-__global__ __launch_bounds__(256) void pair_diag_f32c_kernel(int N, const float4 *__restrict__ hi,
-                                                             const float4 *__restrict__ lo,
-                                                             const double *__restrict__ lam,
-                                                             CoefF c, double *__restrict__ u) {
-    __shared__ float4 s_hi[256], s_lo[256], s_lam[256];
-    const int tid = threadIdx.x;
-    const int i = blockIdx.x * 256 + tid;
-    const Blob32 t = load_blob(i, N, hi, lo, lam);
-    s_hi[tid] = t.hi;
-    s_lo[tid] = t.lo;
-    s_lam[tid] = t.lam;
-    __syncthreads();
-    const float zi = t.hi.z + t.lo.z;
-    double ux = 0.0, uy = 0.0, uz = 0.0;
-    for (int k0 = 0; k0 < 256; k0 += 32) {
-        float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll 2
-        for (int k = k0; k < k0 + 32; ++k) {
-            const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
-            const float dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
-            const float dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
-            const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
-            const float dxy2 = fmaf(dx, dx, dy * dy);
-            const float r2 = fmaf(dz, dz, dxy2);
-            const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
-            rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
-            if (WALL) {
-                const float Rz = zi + sh.z;
-                const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                rpy_image<float>(dx, dy, Rz, sh.z, Ri, L.x, L.y, L.z, c, ax, ay, az);
-            }
-        }
-        ux += (double)ax;
-        uy += (double)ay;
-        uz += (double)az;
-    }
-    if (i < N) {
-        u[i] = ux;
-        u[(size_t)N + i] = uy;
-        u[2 * (size_t)N + i] = uz;
-    }
+__global__ void zero_kernel(size_t n, double *__restrict__ u) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = 0.0;
 }
 
 template <bool WALL>
@@ -172,6 +91,7 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
     __shared__ float comb[4][3][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int4 it = work[blockIdx.x];
+    const bool diag = it.w != 0;
     const int i = (4 * it.x + w) * 64 + lane;
     const Blob32 t = load_blob(i, N, hi, lo, lam);
     const float zi = t.hi.z + t.lo.z;
@@ -186,43 +106,69 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
             s_lam[tid] = s.lam;
         }
         __syncthreads();
-        float fx = 0.f, fy = 0.f, fz = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        if (diag) {
 #pragma unroll 2
-        for (int st = 0; st < 64; ++st) {
-            const int k = (lane + st) & 63;
-            const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
-            const float dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
-            const float dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
-            const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
-            const float dxy2 = fmaf(dx, dx, dy * dy);
-            const float r2 = fmaf(dz, dz, dxy2);
-            const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
-            sym_free(dx, dy, dz, r2, rinv, t.lam.x, t.lam.y, t.lam.z, L.x, L.y, L.z, c, fx, fy, fz,
-                     ax, ay, az);
-            if (WALL) {
-                const float Rz = zi + sh.z;
-                const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                sym_image(dx, dy, Rz, sh.z, Ri, t.lam.x, t.lam.y, t.lam.z, L.x, L.y, L.z, c, fx,
-                          fy, fz, ax, ay, az);
+            for (int k = 0; k < 64; ++k) {
+                const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
+                const float dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
+                const float dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
+                const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
+                const float dxy2 = fmaf(dx, dx, dy * dy);
+                const float r2 = fmaf(dz, dz, dxy2);
+                const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+                if (WALL) {
+                    const float Rz = zi + sh.z;
+                    const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+                    const PairCoef<float> q = wall_pair_coef<float>(r2, rinv, zi, sh.z, Rz, Ri, c);
+                    wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
+                } else {
+                    rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
+                }
             }
-            // the source-side sums follow their sources: lane l takes lane l+1's
-            ax = __shfl(ax, src);
-            ay = __shfl(ay, src);
-            az = __shfl(az, src);
+        } else {
+            float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll 2
+            for (int st = 0; st < 64; ++st) {
+                const int k = (lane + st) & 63;
+                const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
+                const float dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
+                const float dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
+                const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
+                const float dxy2 = fmaf(dx, dx, dy * dy);
+                const float r2 = fmaf(dz, dz, dxy2);
+                const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+                if (WALL) {
+                    const float Rz = zi + sh.z;
+                    const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+                    const PairCoef<float> q = wall_pair_coef<float>(r2, rinv, zi, sh.z, Rz, Ri, c);
+                    wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
+                    wall_pair_apply<float>(q, q.d, q.c, dx, dy, dz, Rz, t.lam.x, t.lam.y, t.lam.z,
+                                           ax, ay, az);
+                } else {
+                    sym_free<float>(dx, dy, dz, r2, rinv, t.lam.x, t.lam.y, t.lam.z, L.x, L.y, L.z,
+                                    c, fx, fy, fz, ax, ay, az);
+                }
+                // the source-side sums follow their sources: lane l takes lane l+1's
+                ax = __shfl(ax, src);
+                ay = __shfl(ay, src);
+                az = __shfl(az, src);
+            }
+            comb[w][0][lane] = ax;
+            comb[w][1][lane] = ay;
+            comb[w][2][lane] = az;
+            __syncthreads();
+            if (tid < 192) {
+                const int cc = tid >> 6, l = tid & 63;
+                const int j = J * 64 + l;
+                const float s =
+                    (comb[0][cc][l] + comb[1][cc][l]) + (comb[2][cc][l] + comb[3][cc][l]);
+                if (j < N) atomicAdd(&u[(size_t)cc * N + j], (double)s);
+            }
         }
         ux += (double)fx;
         uy += (double)fy;
         uz += (double)fz;
-        comb[w][0][lane] = ax;
-        comb[w][1][lane] = ay;
-        comb[w][2][lane] = az;
-        __syncthreads();
-        if (tid < 192) {
-            const int cc = tid >> 6, l = tid & 63;
-            const int j = J * 64 + l;
-            const float s = (comb[0][cc][l] + comb[1][cc][l]) + (comb[2][cc][l] + comb[3][cc][l]);
-            if (j < N) atomicAdd(&u[(size_t)cc * N + j], (double)s);
-        }
     }
     if (i < N) {
         atomicAdd(&u[i], ux);
@@ -231,33 +177,139 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
     }
 }
 
-// u (layout [3][N], FP64) = sum over all pairs, unscaled (units 1/(8 pi eta))
-void pair_sym_f32c(hipStream_t s, bool wall, int N, const float4 *hi, const float4 *lo,
-                   const double *lam, double a, const int4 *work, int n_work, double *u) {
-    if (N <= 0) return;
-    const CoefF c = make_coef<CoefF, float>((float)a);
-    const int nblk = (N + 255) / 256;
-    if (wall) {
-        pair_diag_f32c_kernel<true><<<nblk, 256, 0, s>>>(N, hi, lo, lam, c, u);
-        if (n_work > 0) pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, c, u);
+// blob i in FP64, or a far-away zero-force blob beyond N
+__device__ __forceinline__ void load_blob64(int i, int N, const double4 *__restrict__ p64,
+                                            const double *__restrict__ lam, double4 &p,
+                                            double4 &l) {
+    if (i < N) {
+        p = p64[i];
+        l = make_double4(lam[3 * (size_t)i], lam[3 * (size_t)i + 1], lam[3 * (size_t)i + 2], 0.0);
     } else {
-        pair_diag_f32c_kernel<false><<<nblk, 256, 0, s>>>(N, hi, lo, lam, c, u);
-        if (n_work > 0)
-            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, c, u);
+        p = make_double4(1e6, 1e6, 10.0, 0.0);
+        l = make_double4(0.0, 0.0, 0.0, 0.0);
     }
 }
 
-// work items (b, J0, nJ, 0) covering every tile pair I < J across I-blocks,
-// chunks of at most R source tiles, longest first
+// the same work list in FP64 (no float runs; sums and the rotation in double)
+template <bool WALL>
+__global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 *__restrict__ p64,
+                                                           const double *__restrict__ lam,
+                                                           const int4 *__restrict__ work,
+                                                           CoefD c, double *__restrict__ u) {
+    __shared__ double4 s_p[64], s_l[64];
+    __shared__ double comb[4][3][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int4 it = work[blockIdx.x];
+    const bool diag = it.w != 0;
+    const int i = (4 * it.x + w) * 64 + lane;
+    double4 tp, tl;
+    load_blob64(i, N, p64, lam, tp, tl);
+    const int src = (lane + 1) & 63;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int J = it.y; J < it.y + it.z; ++J) {
+        __syncthreads();
+        if (tid < 64) load_blob64(J * 64 + tid, N, p64, lam, s_p[tid], s_l[tid]);
+        __syncthreads();
+        if (diag) {
+            for (int k = 0; k < 64; ++k) {
+                const double4 sp = s_p[k], L = s_l[k];
+                const double dx = tp.x - sp.x, dy = tp.y - sp.y, dz = tp.z - sp.z;
+                const double dxy2 = fma(dx, dx, dy * dy);
+                const double r2 = fma(dz, dz, dxy2);
+                const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+                if (WALL) {
+                    const double Rz = tp.z + sp.z;
+                    const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
+                    const PairCoef<double> q =
+                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, Rz, Ri, c);
+                    wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
+                } else {
+                    rpy_free<double>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
+                }
+            }
+        } else {
+            double ax = 0.0, ay = 0.0, az = 0.0;
+            for (int st = 0; st < 64; ++st) {
+                const int k = (lane + st) & 63;
+                const double4 sp = s_p[k], L = s_l[k];
+                const double dx = tp.x - sp.x, dy = tp.y - sp.y, dz = tp.z - sp.z;
+                const double dxy2 = fma(dx, dx, dy * dy);
+                const double r2 = fma(dz, dz, dxy2);
+                const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+                if (WALL) {
+                    const double Rz = tp.z + sp.z;
+                    const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
+                    const PairCoef<double> q =
+                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, Rz, Ri, c);
+                    wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
+                    wall_pair_apply<double>(q, q.d, q.c, dx, dy, dz, Rz, tl.x, tl.y, tl.z, ax, ay,
+                                            az);
+                } else {
+                    sym_free<double>(dx, dy, dz, r2, rinv, tl.x, tl.y, tl.z, L.x, L.y, L.z, c, fx,
+                                     fy, fz, ax, ay, az);
+                }
+                ax = __shfl(ax, src);
+                ay = __shfl(ay, src);
+                az = __shfl(az, src);
+            }
+            comb[w][0][lane] = ax;
+            comb[w][1][lane] = ay;
+            comb[w][2][lane] = az;
+            __syncthreads();
+            if (tid < 192) {
+                const int cc = tid >> 6, l = tid & 63;
+                const int j = J * 64 + l;
+                const double s =
+                    (comb[0][cc][l] + comb[1][cc][l]) + (comb[2][cc][l] + comb[3][cc][l]);
+                if (j < N) atomicAdd(&u[(size_t)cc * N + j], s);
+            }
+        }
+    }
+    if (i < N) {
+        atomicAdd(&u[i], fx);
+        atomicAdd(&u[(size_t)N + i], fy);
+        atomicAdd(&u[2 * (size_t)N + i], fz);
+    }
+}
+
+// u (layout [3][N], FP64) = sum over all pairs, unscaled (units 1/(8 pi eta))
+void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+              const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
+              int n_work, double *u) {
+    if (N <= 0) return;
+    const size_t n3 = 3 * (size_t)N;
+    zero_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(n3, u);
+    if (n_work <= 0) return;
+    if (precision == ARB_FP32C) {
+        const CoefF c = make_coef<CoefF, float>((float)a);
+        if (wall)
+            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, c, u);
+        else
+            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, c, u);
+    } else {
+        const CoefD c = make_coef<CoefD, double>(a);
+        if (wall)
+            pair_sym_f64_kernel<true><<<n_work, 256, 0, s>>>(N, p64, lam, work, c, u);
+        else
+            pair_sym_f64_kernel<false><<<n_work, 256, 0, s>>>(N, p64, lam, work, c, u);
+    }
+}
+
+// work items: the diagonal item of every I-block, then (b, J0, nJ, 0) covering
+// every tile pair I < J across I-blocks in chunks of at most R source tiles;
+// ordered by estimated cost, longest first (a diagonal tile costs about 0.6 of
+// an off-diagonal one: one direction instead of two)
 std::vector<int4> pair_sym_worklist(int N, int R) {
     const int nT = (N + 63) / 64;
     const int nB = (nT + 3) / 4;
     std::vector<int4> items;
+    for (int b = 0; b < nB; ++b) items.push_back(make_int4(b, 4 * b, std::min(4, nT - 4 * b), 1));
     for (int b = 0; b < nB; ++b)
         for (int J0 = 4 * b + 4; J0 < nT; J0 += R)
             items.push_back(make_int4(b, J0, std::min(R, nT - J0), 0));
+    auto cost = [](const int4 &x) { return x.w ? 0.6 * x.z : (double)x.z; };
     std::stable_sort(items.begin(), items.end(),
-                     [](const int4 &x, const int4 &y) { return x.z > y.z; });
+                     [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
     return items;
 }
 

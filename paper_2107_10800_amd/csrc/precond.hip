@@ -2,9 +2,16 @@
 //
 // Build (once per state), per body p with m = 3 n_p:
 //   pc_assemble  M_pp (m x m, row-major) from the same pair code as the mat-vec
-//   pc_chol      M_pp = L L^T in place (right-looking; column k cached in LDS)
-//   pc_inverse   X = L^-1 (stored transposed in the upper triangle), then
-//                M_pp^-1 = X^T X into its own buffer
+//   pc_potrf     M_pp = L L^T in place, blocked by 32 columns: the panel is
+//                factored in LDS, the trailing lower triangle updated in 64 x 64
+//                register tiles; the inverses of the 32 x 32 diagonal blocks of L
+//                are kept for the next step
+//   pc_potri     M_pp^-1 by block forward and backward substitution on the
+//                identity, one workgroup per (body, 32 columns), the block
+//                column held in LDS; every block step is a small GEMM because the
+//                diagonal blocks are applied through their stored inverses
+//   (bodies with more than 480 rows: pc_chol / pc_inverse, the unblocked
+//   right-looking versions, with X = L^-1 kept transposed in the upper triangle)
 //   pc_body      Z_p = M_pp^-1 K_p (m x 6), R_p = K_p^T Z_p, N~_p = R_p^+
 //                (cyclic Jacobi eigen-decomposition, eigenvalues below
 //                1e-12 * max dropped: the minimum-norm velocity of bodies with
@@ -208,6 +215,230 @@ __global__ __launch_bounds__(256) void pc_inverse_kernel(const int *__restrict__
         for (int k = j; k < m; ++k) s += ri[k] * rj[k];
         Mi[(size_t)i * m + j] = s;
         Mi[(size_t)j * m + i] = s;
+    }
+}
+
+constexpr int kNB = 32;          // block size of the blocked factorisation
+constexpr int kLd = kNB + 1;     // padded LDS row stride (doubles)
+constexpr int kFastMaxM = 480;   // largest body handled by the blocked kernels
+
+// offset (doubles) of body p's diagonal-block inverses: 1024 per 32-row block
+__device__ __forceinline__ int64_t dinv_offset(const int *blob_off, int p) {
+    return 32 * 3 * (int64_t)blob_off[p] + 1024 * (int64_t)p;
+}
+
+// Blocked in-place Cholesky of each M_pp (lower triangle; the upper triangle is
+// not touched).  Dynamic LDS: the panel, max_m x kLd doubles.
+__global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ blob_off,
+                                                       const int64_t *__restrict__ mat_off,
+                                                       double *__restrict__ mats,
+                                                       double *__restrict__ ldiag,
+                                                       double *__restrict__ dinv,
+                                                       int *__restrict__ status) {
+    extern __shared__ double Pn[];
+    __shared__ int fail;
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    double *A = mats + mat_off[p];
+    double *Dg = dinv + dinv_offset(blob_off, p);
+    if (tid == 0) fail = 0;
+    for (int k0 = 0; k0 < m; k0 += kNB) {
+        const int nb = min(kNB, m - k0), rows = m - k0;
+        __syncthreads();
+        for (int idx = tid; idx < rows * kNB; idx += 256) {
+            const int i = idx / kNB, t = idx % kNB;
+            Pn[i * kLd + t] = t < nb ? A[(size_t)(k0 + i) * m + k0 + t] : 0.0;
+        }
+        __syncthreads();
+        // panel: column j is final once its pivot is known; the update of the
+        // columns to its right uses the unscaled column divided by the pivot
+        for (int j = 0; j < nb; ++j) {
+            const double d = Pn[j * kLd + j];
+            if (!(d > 0.0)) {  // the same value for every thread: a uniform exit
+                if (tid == 0) fail = 1;
+                break;
+            }
+            const double inv = 1.0 / d;
+            const int w = nb - j - 1;
+            for (int idx = tid; idx < rows * w; idx += 256) {
+                const int i = idx / w, c = j + 1 + idx % w;
+                if (i >= c) Pn[i * kLd + c] -= Pn[i * kLd + j] * Pn[c * kLd + j] * inv;
+            }
+            __syncthreads();
+            const double sq = sqrt(d), isq = 1.0 / sq;
+            for (int i = j + tid; i < rows; i += 256)
+                Pn[i * kLd + j] = i == j ? sq : Pn[i * kLd + j] * isq;
+        }
+        __syncthreads();
+        if (fail) break;
+        for (int idx = tid; idx < rows * kNB; idx += 256) {
+            const int i = idx / kNB, t = idx % kNB;
+            if (t < nb && i >= t) A[(size_t)(k0 + i) * m + k0 + t] = Pn[i * kLd + t];
+        }
+        for (int t = tid; t < nb; t += 256) ldiag[3 * blob_off[p] + k0 + t] = Pn[t * kLd + t];
+        // inverse of the diagonal block: thread c solves L z = e_c (zero padded)
+        if (tid < kNB) {
+            const int c = tid;
+            double z[kNB];
+#pragma unroll
+            for (int i = 0; i < kNB; ++i) {
+                double v = 0.0;
+                if (i < nb && c < nb && i >= c) {
+                    double acc = i == c ? 1.0 : 0.0;
+#pragma unroll
+                    for (int k = 0; k < i; ++k)
+                        if (k >= c) acc -= Pn[i * kLd + k] * z[k];
+                    v = acc / Pn[i * kLd + i];
+                }
+                z[i] = v;
+            }
+            double *Db = Dg + (k0 / kNB) * (kNB * kNB);
+#pragma unroll
+            for (int i = 0; i < kNB; ++i) Db[i * kNB + c] = z[i];
+        }
+        // trailing update of the lower triangle: A_ij -= sum_t L_it L_jt
+        const int t0 = k0 + nb, nt = m - t0;
+        if (nt > 0) {
+            const int ntile = (nt + 63) / 64;
+            const int ty = tid / 16, tx = tid % 16;
+            for (int tile = 0; tile < ntile * (ntile + 1) / 2; ++tile) {
+                int bi = 0;
+                while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+                const int bj = tile - bi * (bi + 1) / 2;
+                const int i0 = 64 * bi + ty, j0 = 64 * bj + 4 * tx;
+                int ri[4], rj[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ri[r] = nb + min(i0 + 16 * r, nt - 1);
+                    rj[r] = nb + min(j0 + r, nt - 1);
+                }
+                double acc[4][4] = {};
+                for (int t = 0; t < nb; ++t) {
+                    double a[4], b[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        a[r] = Pn[ri[r] * kLd + t];
+                        b[r] = Pn[rj[r] * kLd + t];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + 16 * r;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int j = j0 + c;
+                        if (i < nt && j <= i) A[(size_t)(t0 + i) * m + t0 + j] -= acc[r][c];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (fail && tid == 0) atomicMax(&status[0], p + 1);
+}
+
+// stage the 32 x 32 block of L at (R0, C0), zero padded beyond m
+__device__ __forceinline__ void stage_block(double (*Ls)[kLd], const double *A, int m, int R0,
+                                            int C0) {
+    for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
+        const int t = idx / kNB, u = idx % kNB;
+        Ls[t][u] = (R0 + t < m && C0 + u < m) ? A[(size_t)(R0 + t) * m + C0 + u] : 0.0;
+    }
+}
+
+// M_pp^-1 columns [32 cb, 32 cb + 32) from L and the diagonal-block inverses:
+// forward Y = L^-1 E (rows of blocks before cb vanish), then X = L^-T Y.
+// Dynamic LDS: X, ceil(max_m / 32) * 32 x kLd doubles.
+__global__ __launch_bounds__(256) void pc_potri_kernel(const int *__restrict__ blob_off,
+                                                       const int64_t *__restrict__ mat_off,
+                                                       const double *__restrict__ mats,
+                                                       const double *__restrict__ dinv,
+                                                       double *__restrict__ minv,
+                                                       const int *__restrict__ status) {
+    extern __shared__ double X[];
+    __shared__ double Ls[kNB][kLd];
+    const int p = blockIdx.y, cb = blockIdx.x;
+    if (status[0] != 0) return;
+    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    const int nbk = (m + kNB - 1) / kNB;
+    if (cb >= nbk) return;
+    const double *A = mats + mat_off[p];
+    const double *Dg = dinv + dinv_offset(blob_off, p);
+    double *Mi = minv + mat_off[p];
+    const int tid = threadIdx.x, r = tid / 8, c4 = 4 * (tid % 8);
+    const int c0 = kNB * cb;
+    for (int i = cb; i < nbk; ++i) {
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = (kNB * i + r == c0 + c4 + q) ? 1.0 : 0.0;
+        for (int k = cb; k < i; ++k) {
+            __syncthreads();
+            stage_block(Ls, A, m, kNB * i, kNB * k);
+            __syncthreads();
+            const double *Xk = X + (size_t)kNB * k * kLd + c4;
+            for (int t = 0; t < kNB; ++t) {
+                const double a = Ls[r][t];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = fma(-a, Xk[t * kLd + q], acc[q]);
+            }
+        }
+        double *Xi = X + (size_t)kNB * i * kLd + c4;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = acc[q];
+        for (int idx = tid; idx < kNB * kNB; idx += 256)
+            Ls[idx / kNB][idx % kNB] = Dg[(size_t)i * kNB * kNB + idx];
+        __syncthreads();
+        double y[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < kNB; ++t) {
+            const double d = Ls[r][t];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) y[q] = fma(d, Xi[t * kLd + q], y[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = y[q];
+    }
+    for (int i = nbk - 1; i >= 0; --i) {
+        double *Xi = X + (size_t)kNB * i * kLd + c4;
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = i >= cb ? Xi[r * kLd + q] : 0.0;
+        for (int k = i + 1; k < nbk; ++k) {
+            __syncthreads();
+            stage_block(Ls, A, m, kNB * k, kNB * i);
+            __syncthreads();
+            const double *Xk = X + (size_t)kNB * k * kLd + c4;
+            for (int t = 0; t < kNB; ++t) {
+                const double a = Ls[t][r];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = fma(-a, Xk[t * kLd + q], acc[q]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = acc[q];
+        for (int idx = tid; idx < kNB * kNB; idx += 256)
+            Ls[idx / kNB][idx % kNB] = Dg[(size_t)i * kNB * kNB + idx];
+        __syncthreads();
+        double x[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < kNB; ++t) {
+            const double d = Ls[t][r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = fma(d, Xi[t * kLd + q], x[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = x[q];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < m * kNB; idx += 256) {
+        const int row = idx / kNB, c = idx % kNB;
+        if (c0 + c < m) Mi[(size_t)row * m + c0 + c] = X[(size_t)row * kLd + c];
     }
 }
 
@@ -662,15 +893,35 @@ void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos, dou
                                            wall ? 1 : 0, a, P.mats, P.status);
 }
 
-void precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int /*max_m*/) {
-    if (P.M <= 0) return;
-    pc_chol_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.status);
-    pc_inverse_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.minv,
-                                          P.status);
-    pc_restore_diag_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag);
+hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m) {
+    if (P.M <= 0) return hipSuccess;
+    if (max_m <= kFastMaxM) {
+        const size_t lds_f = (size_t)max_m * kLd * sizeof(double);
+        const int nbk = (max_m + kNB - 1) / kNB;
+        const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
+        hipError_t e = hipFuncSetAttribute((const void *)pc_potrf_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void *)pc_potri_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
+        if (e != hipSuccess) return e;
+        pc_potrf_kernel<<<P.M, 256, lds_f, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.dinv,
+                                                P.status);
+        pc_potri_kernel<<<dim3(nbk, P.M), 256, lds_i, s>>>(P.blob_off, P.mat_off, P.mats, P.dinv,
+                                                           P.minv, P.status);
+    } else {
+        pc_chol_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.status);
+        pc_inverse_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.minv,
+                                              P.status);
+        pc_restore_diag_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag);
+    }
     pc_body_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.z_off, P.minv, dvec, P.Z, P.Nt,
                                        P.status);
+    return hipGetLastError();
 }
+
+// doubles needed for the diagonal-block inverses of bodies holding n_blobs blobs
+int64_t precond_dinv_size(int64_t n_blobs, int M) { return 32 * 3 * n_blobs + 1024 * (int64_t)M; }
 
 void precond_assembly(hipStream_t s, const PrecondDev &P) {
     if (P.A <= 0) return;

@@ -6,10 +6,10 @@
 namespace arb {
 
 struct CoefF {
-    float k1, k2, n1, n2, n3, a2, four_a2;
+    float k1, k2, n1, n2, n3, a2, four_a2, a4;
 };
 struct CoefD {
-    double k1, k2, n1, n2, n3, a2, four_a2;
+    double k1, k2, n1, n2, n3, a2, four_a2, a4;
 };
 
 template <class C, class T>
@@ -22,6 +22,7 @@ __host__ __device__ inline C make_coef(T a) {
     c.n3 = T(1) / (T(8) * a * a);
     c.a2 = a * a;
     c.four_a2 = T(4) * a * a;
+    c.a4 = a * a * a * a;
     return c;
 }
 
@@ -46,43 +47,75 @@ __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T
     az = fma(c1, lz, fma(t, dz, az));
 }
 
-// accumulate the wall image I(x, y) lambda; dx, dy in-plane target-source,
-// Rz = target height + source height, h = source height, Ri = 1/|R|
+// Free-space tensor plus wall image of one pair, written for reuse in both
+// directions.  With d = x_i - x_j, R = (dx, dy, z_i + z_j), h = z_j, Ri = 1/|R|,
+// e = R Ri, p = a^2 Ri^2 and the image I = Ri [A^ delta + B^ e e^T + C^ e z^T +
+// D^ z e^T + E^ z z^T] (units 1/(8 pi eta)), every coefficient is a polynomial in
+// s = Ri^2, t = (e.z)^2 and q = z_i z_j: for instance h/|R| (h/|R| - e.z) = -s q.
+// Absorbing the powers of Ri gives
+//   M_ij l = (c1 + a) l + (c2 (d.l)) d + (b (R.l) + c l_z) R + (d' (R.l) + e l_z) z
+// with a = Ri A^, b = Ri^3 B^, c = Ri^2 C^, d' = Ri^2 D^, e = Ri E^ and the free
+// part c1 delta + c2 d d^T; M_ji = M_ij^T uses the same numbers with c and d'
+// swapped.  The free part and the image then share the in-plane dot product
+// and the l term.
+template <class T>
+struct PairCoef {
+    T cA, c2, b, c, d, e, h2;
+};
+
 template <class T, class C>
-__device__ __forceinline__ void rpy_image(T dx, T dy, T Rz, T h, T Ri, T lx, T ly, T lz,
-                                          const C &c, T &ax, T &ay, T &az) {
-    const T e3 = Rz * Ri;
-    const T hh = h * Ri;
-    const T Ri2 = Ri * Ri;
-    const T p = c.a2 * Ri2;
-    const T p2 = p * p;
-    const T e32 = e3 * e3;
-    const T hh2 = hh * hh;
-    const T eh = e3 * hh;
-    T Ah = fma(T(2), hh2, T(-1));
-    Ah = fma(T(-2), eh, Ah);
-    Ah = fma(p, fma(T(2), e32, T(-2.0 / 3.0)), Ah);
-    Ah = fma(p2, fma(T(-10.0 / 3.0), e32, T(2.0 / 3.0)), Ah);
-    T Bh = fma(T(-6), hh2, T(-1));
-    Bh = fma(T(6), eh, Bh);
-    Bh = fma(p, fma(T(-10), e32, T(2)), Bh);
-    Bh = fma(p2, fma(T(70.0 / 3.0), e32, T(-10.0 / 3.0)), Bh);
-    T Ch = hh * fma(T(-12), e32, T(2));
-    Ch = fma(T(12) * eh, hh, Ch);
-    Ch = fma(e3, fma(p, fma(T(20), e32, T(-4)), p2 * fma(T(-140.0 / 3.0), e32, T(40.0 / 3.0))),
-             Ch);
-    const T Dh = fma(T(-20.0 / 3.0), p2 * e3, T(2) * hh);
-    T Eh = p2 * fma(T(20), e32, T(-8.0 / 3.0));
-    Eh = fma(T(-4), p * e32, Eh);
-    Eh = fma(T(-4), hh2, Eh);
-    // v = Ri [A^ l + e (B^ s + C^ lz) + z (D^ s + E^ lz)],  s = e.l,  e = R Ri
-    const T s = Ri * fma(dx, lx, fma(dy, ly, Rz * lz));
-    const T t1 = fma(Bh, s, Ch * lz) * Ri2;
-    const T t2 = fma(Dh, s, Eh * lz) * Ri;
-    const T AR = Ah * Ri;
-    ax = fma(AR, lx, fma(t1, dx, ax));
-    ay = fma(AR, ly, fma(t1, dy, ay));
-    az = fma(AR, lz, fma(t1, Rz, az)) + t2;
+__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, T Rz, T Ri,
+                                                      const C &k) {
+    PairCoef<T> w;
+    const T rinv2 = rinv * rinv;
+    T c1 = rinv * fma(k.k1, rinv2, T(1));
+    T c2 = rinv * rinv2 * fma(-k.k2, rinv2, T(1));
+    if (r2 <= k.four_a2) {
+        c1 = fma(-k.n2, r2 * rinv, k.n1);
+        c2 = rinv * k.n3;
+    }
+    const T s = Ri * Ri;
+    const T Ri3 = Ri * s;
+    const T Ri5 = Ri3 * s;
+    const T u = Rz * Ri;
+    const T t = u * u;
+    const T q = zi * zj;
+    const T a4s = k.a4 * s;
+    const T RzRi5 = Rz * Ri5;
+    const T h2 = zj + zj;
+    const T h2Ri3 = h2 * Ri3;
+    const T a2 = k.a2;
+    const T iA = fma(a4s, fma(T(-10.0 / 3.0), t, T(2.0 / 3.0)),
+                     fma(T(2) * a2, t, fma(T(-2), q, T(-2.0 / 3.0) * a2)));
+    const T iB = fma(a4s, fma(T(70.0 / 3.0), t, T(-10.0 / 3.0)),
+                     fma(T(-10) * a2, t, fma(T(6), q, T(2) * a2)));
+    const T iC = fma(a4s, fma(T(-140.0 / 3.0), t, T(40.0 / 3.0)),
+                     fma(T(20) * a2, t, fma(T(-12), q, T(-4) * a2)));
+    const T iE = fma(a4s, fma(T(20), t, T(-8.0 / 3.0)), fma(T(-4) * a2, t, -(h2 * h2)));
+    w.cA = c1 + fma(Ri3, iA, -Ri);
+    w.c2 = c2;
+    w.b = fma(Ri5, iB, -Ri3);
+    w.c = fma(RzRi5, iC, h2Ri3);
+    w.d = fma(T(-20.0 / 3.0) * k.a4, RzRi5 * s, h2Ri3);
+    w.e = Ri3 * iE;
+    w.h2 = h2;
+    return w;
+}
+
+// f += M l for the pair coefficients w; pass (w.c, w.d) for M_ij and (w.d, w.c)
+// for M_ij^T.  The z row uses R_z = d_z + 2 h.
+template <class T>
+__device__ __forceinline__ void wall_pair_apply(const PairCoef<T> &w, T cc, T dd, T dx, T dy,
+                                                T dz, T Rz, T lx, T ly, T lz, T &fx, T &fy,
+                                                T &fz) {
+    const T dxy = fma(dx, lx, dy * ly);
+    const T Sd = fma(dz, lz, dxy);
+    const T SR = fma(Rz, lz, dxy);
+    const T g = fma(w.b, SR, cc * lz);
+    const T tg = fma(w.c2, Sd, g);
+    fx = fma(w.cA, lx, fma(tg, dx, fx));
+    fy = fma(w.cA, ly, fma(tg, dy, fy));
+    fz = fma(w.cA, lz, fma(tg, dz, fma(g, w.h2, fma(dd, SR, fma(w.e, lz, fz)))));
 }
 
 __device__ __forceinline__ double rsq_f64(double x) {
@@ -104,12 +137,15 @@ __device__ inline void rpy_block_f64(double dx, double dy, double dz, double zt,
     const double r2 = fma(dz, dz, dxy2);
     const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
     const double Rz = zt + zs;
-    const double Ri = wall ? rsq_f64(fma(Rz, Rz, dxy2)) : 0.0;
+    PairCoef<double> w{};
+    if (wall) w = wall_pair_coef<double>(r2, rinv, zt, zs, Rz, rsq_f64(fma(Rz, Rz, dxy2)), c);
     for (int col = 0; col < 3; ++col) {
         const double lx = col == 0, ly = col == 1, lz = col == 2;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ax, ay, az);
-        if (wall) rpy_image<double>(dx, dy, Rz, zs, Ri, lx, ly, lz, c, ax, ay, az);
+        if (wall)
+            wall_pair_apply<double>(w, w.c, w.d, dx, dy, dz, Rz, lx, ly, lz, ax, ay, az);
+        else
+            rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ax, ay, az);
         B[col] = ax;
         B[3 + col] = ay;
         B[6 + col] = az;

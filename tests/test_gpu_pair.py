@@ -104,24 +104,29 @@ def test_below_wall_rejected(ctxs):
 
 @pytest.mark.parametrize("n", [1, 65, 300, 1000, 5000])
 @pytest.mark.parametrize("wall", [False, True])
-def test_symmetric_kernel_small(n, wall):
-    # FP32 symmetric kernel (each unordered pair once): ragged tiles and blocks
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_symmetric_kernel_small(n, wall, prec):
+    # symmetric kernel (each unordered pair once): ragged tiles and blocks,
+    # coincident-free random clouds with overlapping pairs
     cl = W.random_blobs(n, seed=200 + n, box=8.0 + n ** (1 / 3))
-    c = arb.arb_create(precision=arb.ARB_FP32C, wall=wall, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
+    c = arb.arb_create(precision=prec, wall=wall, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
     try:
-        print(f"symmetric pair n={n} wall={wall}", flush=True)
+        print(f"symmetric pair n={n} wall={wall} prec={prec}", flush=True)
         u = arb.arb_rpy_apply(c, cl["pos"], cl["lam"])
+        assert arb.arb_get_slices(c, n) < 0
     finally:
         arb.arb_destroy(c)
     uo = rpy.mobility_apply(cl["pos"], cl["lam"], 1.0, 1.0, wall)
-    assert rel(u, uo) <= TOL[arb.ARB_FP32C]
+    assert rel(u, uo) <= TOL[prec]
 
 
-def test_symmetric_kernel_slab_sampled():
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_symmetric_kernel_slab_sampled(prec):
     sl = W.slab()
     N = len(sl["pos"])
-    c = arb.arb_create(precision=arb.ARB_FP32C, wall=True, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
+    c = arb.arb_create(precision=prec, wall=True, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
     try:
+        print(f"symmetric pair slab N={N} prec={prec}", flush=True)
         u = arb.arb_rpy_apply(c, sl["pos"], sl["lam"]).reshape(N, 3)
         shape = arb.arb_get_slices(c, N)
     finally:
@@ -130,4 +135,17 @@ def test_symmetric_kernel_slab_sampled():
     rng = np.random.default_rng(1)
     tg = np.unique(np.concatenate([[0, 63, 64, 255, 256, N - 1], rng.integers(0, N, 26)]))
     uo = rpy.mobility_apply(sl["pos"], sl["lam"], 1.0, 1.0, True, targets=tg)
-    assert rel(u[tg], uo) <= TOL[arb.ARB_FP32C]
+    assert rel(u[tg], uo) <= TOL[prec]
+
+
+def test_symmetric_matches_target_parallel_fp64():
+    # the two FP64 kernels agree to rounding on a ragged size above the autotune threshold
+    cl = W.random_blobs(9000, seed=31, box=60.0, zlo=1.5, zhi=12.0)
+    outs = []
+    for kind in (arb.ARB_PAIR_TARGET, arb.ARB_PAIR_SYMMETRIC):
+        c = arb.arb_create(precision=arb.ARB_FP64, wall=True, pair_kernel=kind)
+        try:
+            outs.append(arb.arb_rpy_apply(c, cl["pos"], cl["lam"]))
+        finally:
+            arb.arb_destroy(c)
+    assert rel(outs[1], outs[0]) <= 1e-13

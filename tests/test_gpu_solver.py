@@ -220,3 +220,36 @@ def test_error_paths():
         assert e.value.code == arb.ARB_E_ARG
     finally:
         arb.arb_destroy(ctx)
+
+
+@pytest.mark.parametrize("n_helix", [150, 170])
+def test_preconditioner_large_bodies(n_helix):
+    # a long helix (3n = 450: the blocked factorisation at its largest LDS
+    # footprint; 3n = 510: the unblocked path for bodies beyond 480 rows) next
+    # to a 42-blob shell, above the wall
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(40 + n_helix)
+    hel = W.helix80(n_helix, length=60.0)
+    hel -= hel.mean(0)
+    r_ref = np.vstack([hel, W.icosphere42(5.0)])
+    blob_offset = np.array([0, n_helix, n_helix + 42], np.int32)
+    q = np.array([[0.0, 0.0, 35.0], [40.0, 0.0, 10.0]])
+    theta = W._quat_scalar_first(Rotation.random(2, random_state=rng))
+    wl = W.Workload("large", 1.0, 1.0, True, r_ref, blob_offset, q, theta,
+                    rng.standard_normal((2, 6)), **W._links(0))
+    print(f"large bodies: helix {n_helix} blobs", flush=True)
+    S = system.assemble(wl)
+    ctx = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10)
+    try:
+        rc = arb.arb_precond_build(ctx)
+        assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
+        P = precond.BlockPreconditioner(wl, S["r"], S["C"])
+        for p in range(wl.M):
+            m = 3 * int(wl.blob_offset[p + 1] - wl.blob_offset[p])
+            L, Nt = arb.arb_precond_block(ctx, p, m)
+            assert rel(L, P.L[p]) <= 1e-13
+            assert rel(Nt, P.Nt[p]) <= 1e-11
+        r = rng.standard_normal(S["A"].shape[0])
+        assert rel(arb.arb_precond_apply(ctx, r), P.apply(r)) <= 1e-11
+    finally:
+        arb.arb_destroy(ctx)
