@@ -207,8 +207,8 @@ int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
     arb::rotations(s, M, ctx->theta.as<double>(), ctx->R9.as<double>());
     arb::blob_geometry(s, N, ctx->body_of_blob.as<int>(), ctx->q.as<double>(), ctx->R9.as<double>(),
                        ctx->r_ref.as<double>(), ctx->pos.as<double>(), ctx->dvec.as<double>());
-    arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->p64.as<double4>(), ctx->hi.as<float4>(),
-                        ctx->lo.as<float4>());
+    arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->opt.a, ctx->p64.as<double4>(),
+                        ctx->hi.as<float4>(), ctx->lo.as<float4>());
     if (!ctx->topo_dirty) TRY(refresh_rows(ctx, s));
     ctx->pc_built = false;
     return 0;
@@ -265,8 +265,10 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
         HIPCHK(hipEventRecord(e1, s));
         ctx->prof_ev.emplace_back(e0, e1);
     }
-    arb::pair_reduce(s, N, used, ctx->partial.as<double>(), 1.0 / (8.0 * arb::kPi * ctx->opt.eta),
-                     out, U, bob, dvec);
+    // FP32 sums are in units of the blob radius: M(a) = M_{a=1}(r / a) / a
+    const double scale = 1.0 / (8.0 * arb::kPi * ctx->opt.eta) /
+                         (precision == ARB_FP32C ? ctx->opt.a : 1.0);
+    arb::pair_reduce(s, N, used, ctx->partial.as<double>(), scale, out, U, bob, dvec);
     return 0;
 }
 
@@ -1038,7 +1040,7 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *
     double4 *p64 = ctx->s_pos.as<double4>();
     float4 *hi = reinterpret_cast<float4 *>(p64 + N);
     float4 *lo = hi + N;
-    arb::prep_positions(s, N, pos_dev, p64, hi, lo);
+    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo);
     const bool wall = ctx->opt.wall != 0;
     int sl = 0;
     TRY(choose_slices(ctx, s, N, p64, hi, lo, lambda_dev, ctx->opt.precision, wall, &sl));

@@ -44,8 +44,8 @@ struct DevBuf {
 // ---------------------------------------------------------------- kernel entry points
 // Pair sum u_i = sum_j M_ij lambda_j (Sec. 2.3): partial sums per source slice,
 // then an ordered reduction.  Positions are prepared by prep_positions().
-void prep_positions(hipStream_t s, int N, const double *pos_aos, double4 *p64, float4 *hi,
-                    float4 *lo);
+void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
+                    float4 *hi, float4 *lo);
 // returns the number of slices written (clamped to the tile count)
 int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
                   const float4 *hi, const float4 *lo, const double *lam, double a,

@@ -22,20 +22,21 @@
 // one target; the block streams its slice's sources through LDS in tiles of
 // 256 (x,y,z + lambda), all lanes reading the same LDS word (broadcast).  Each
 // slice writes its partial sums; pair_reduce adds slices in a fixed order, so
-// results are deterministic.  FP32C: positions are split hi + lo floats so
-// that differences keep ~double accuracy; sums are float over runs of 32
-// sources and double across runs.
+// results are deterministic.  FP32C: positions (in units of a) are split hi +
+// lo floats so that differences keep ~double accuracy; sums are float over
+// runs of 32 sources and double across runs.
 #include "rpy_device.h"
 
 namespace arb {
 
-__global__ void prep_positions_kernel(int N, const double *__restrict__ pos,
+// p64: positions; hi + lo: positions / a split into two floats
+__global__ void prep_positions_kernel(int N, const double *__restrict__ pos, double inv_a,
                                       double4 *__restrict__ p64, float4 *__restrict__ hi,
                                       float4 *__restrict__ lo) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    p64[i] = make_double4(x, y, z, 0.0);
+    p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
+    const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
     const float xh = (float)x, yh = (float)y, zh = (float)z;
     hi[i] = make_float4(xh, yh, zh, 0.f);
     lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
@@ -47,8 +48,8 @@ constexpr int kRun = 32;  // sources per float partial sum in the FP32C kernel
 template <bool WALL>
 __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
     int N, const float4 *__restrict__ hi, const float4 *__restrict__ lo,
-    const double *__restrict__ lam, int tiles_per_slice, CoefF c,
-    double *__restrict__ partial) {
+    const double *__restrict__ lam, int tiles_per_slice, double *__restrict__ partial) {
+    constexpr CoefF c = kUnitCoefF;
     __shared__ float4 s_hi[kTile], s_lo[kTile], s_lam[kTile];
     const int tid = threadIdx.x;
     const int i = blockIdx.x * kTile + tid;
@@ -193,10 +194,10 @@ __global__ void wall_check_kernel(int N, const double4 *__restrict__ p64, double
 
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-void prep_positions(hipStream_t s, int N, const double *pos_aos, double4 *p64, float4 *hi,
-                    float4 *lo) {
+void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
+                    float4 *hi, float4 *lo) {
     if (N <= 0) return;
-    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, p64, hi, lo);
+    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo);
 }
 
 int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
@@ -208,11 +209,10 @@ int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *
     const int tps = (ntiles + slices - 1) / slices;
     dim3 grid(ntiles, slices);
     if (precision == ARB_FP32C) {
-        const CoefF c = make_coef<CoefF, float>((float)a);
         if (wall)
-            pair_f32c_kernel<true><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, c, partial);
+            pair_f32c_kernel<true><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, partial);
         else
-            pair_f32c_kernel<false><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, c, partial);
+            pair_f32c_kernel<false><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, partial);
     } else {
         const CoefD c = make_coef<CoefD, double>(a);
         if (wall)

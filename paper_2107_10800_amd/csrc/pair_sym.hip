@@ -18,8 +18,8 @@
 //     atomics);
 //   * diagonal (b, 4b, nJ, 1): all ordered pairs among I-block b's own tiles,
 //     target side only (the self pair included).
-// FP32 (positions split hi + lo): float sums over one source tile, promoted to
-// FP64 per tile.  FP64: the same work list with double positions and sums.
+// FP32 (positions in units of a, split hi + lo): float sums over one source
+// tile, promoted to FP64 per tile.  FP64: the same work list with double positions and sums.
 // Target sums are promoted to FP64 after each source tile and added to u at the
 // end of the item.  u is cleared first; FP64 addition order of the atomics
 // varies between runs (results reproducible to FP64 rounding).  Rows beyond N
@@ -86,7 +86,8 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                                                             const float4 *__restrict__ lo,
                                                             const double *__restrict__ lam,
                                                             const int4 *__restrict__ work,
-                                                            CoefF c, double *__restrict__ u) {
+                                                            double *__restrict__ u) {
+    constexpr CoefF c = kUnitCoefF;
     __shared__ float4 s_hi[64], s_lo[64], s_lam[64];
     __shared__ float comb[4][3][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -281,11 +282,10 @@ void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64
     zero_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(n3, u);
     if (n_work <= 0) return;
     if (precision == ARB_FP32C) {
-        const CoefF c = make_coef<CoefF, float>((float)a);
         if (wall)
-            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, c, u);
+            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, u);
         else
-            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, c, u);
+            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, u);
     } else {
         const CoefD c = make_coef<CoefD, double>(a);
         if (wall)

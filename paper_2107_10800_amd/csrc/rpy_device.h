@@ -26,6 +26,11 @@ __host__ __device__ inline C make_coef(T a) {
     return c;
 }
 
+// Coefficients for a = 1.  The FP32 kernels work in units of the blob radius
+// (positions divided by a on upload, M(a) = M_{a=1}(r / a) / a): every
+// coefficient is then a compile-time literal rather than a kernel argument.
+constexpr CoefF kUnitCoefF{2.f / 3.f, 2.f, 4.f / 3.f, 3.f / 8.f, 1.f / 8.f, 1.f, 4.f, 1.f};
+
 __device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // accumulate M_free(r) lambda (units 1/(8 pi eta))

@@ -149,3 +149,18 @@ def test_symmetric_matches_target_parallel_fp64():
         finally:
             arb.arb_destroy(c)
     assert rel(outs[1], outs[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("kind", [arb.ARB_PAIR_TARGET, arb.ARB_PAIR_SYMMETRIC])
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_blob_radius_and_viscosity(kind, prec):
+    # a != 1 and eta != 1: the FP32 kernels work in units of a and rescale
+    a, eta = 0.7, 1.9
+    cl = W.random_blobs(600, seed=77, box=10.0, zlo=1.05 * a, zhi=5.0)
+    c = arb.arb_create(precision=prec, wall=True, a=a, eta=eta, pair_kernel=kind)
+    try:
+        u = arb.arb_rpy_apply(c, cl["pos"], cl["lam"])
+    finally:
+        arb.arb_destroy(c)
+    uo = rpy.mobility_apply(cl["pos"], cl["lam"], a, eta, True)
+    assert rel(u, uo) <= TOL[prec]
