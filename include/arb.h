@@ -85,8 +85,8 @@ typedef struct {
     int    iterations;      /* Arnoldi steps over all cycles                   */
     int    restarts;        /* completed cycles                                */
     double rel_residual;    /* ||b - A y|| / ||b|| of the returned iterate with
-                               the context's pair-sum precision               */
-    double rel_residual_fp64; /* same with the FP64 pair sum (the stopping test) */
+                               the FP64 pair sum (the stopping test)          */
+    double rel_residual_fp64; /* the same number (kept for callers that read it) */
     double t_build_ms;      /* preconditioner build                            */
     double t_solve_ms;      /* Krylov iterations incl. final residual          */
     int    pinv_used;       /* number of blocks inverted by pseudo-inverse     */
@@ -177,7 +177,9 @@ int arb_precond_build(arb_ctx *ctx);
 /* z = P^-1 r (Eq. precond solved exactly), n doubles each. */
 int arb_precond_apply(arb_ctx *ctx, const double *r, double *z);
 /* Lower Cholesky factor of body p's blob mobility (3n_p x 3n_p row-major,
- * upper part zero), and N~_p (36, row-major). */
+ * upper part zero), and N~_p (36, row-major); either may be NULL.  The
+ * per-type preconditioners (ARB_PC_LEARNED, ARB_PC_BODYFRAME) have no per-body
+ * factor: L must be NULL there (ARB_E_ARG otherwise). */
 int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde);
 
 /* -------------------------------------------------------------- solve
@@ -221,10 +223,13 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q,
  * the body mobility [K_p^T (M^(pp))^-1 K_p]^-1 of the block preconditioner
  * (Sec. 3.1).  Parameters: 20,245 floats, flat [W1 (128x7), b1, W2 (128x128),
  * b2, W3 (21x128), b3], W row-major (out x in).  With ARB_PC_LEARNED the solve
- * takes N~_p from the network and each body's blob block from the unbounded
- * body-frame mobility of its type (all bodies of one type must share r_ref);
- * a non-finite prediction (or |y| >= 80) makes the build fall back to the
- * exact one (ARB_W_LEARNED_FALLBACK).  Inputs and outputs are standardised:
+ * takes N~_w = N~_p from the network; each body's blob block is the unbounded
+ * body-frame mobility of its type (all bodies of one type must share r_ref),
+ * rotated, with a rank-6 correction that makes the block solve exact for
+ * N~_w: M~^-1 = A + Z_f D Z_f^T, D = N~_f N~_w^-1 N~_f - N~_f (A, Z_f, N~_f the
+ * rotated unbounded blocks), so K^T M~^-1 K = N~_w^-1.  A non-finite
+ * prediction (or |y| >= 80), or an N~_w or N~_f that is not positive definite,
+ * makes the build fall back to the exact one (ARB_W_LEARNED_FALLBACK).  Inputs and outputs are standardised:
  * the network sees (x - in_mu)/in_sd and y = out_mu + out_sd * output. */
 /* Standardisation constants (7, 7, 21, 21 floats; sd > 0); identity by default. */
 int arb_mlp_set_scaling(arb_ctx *ctx, const float *in_mu, const float *in_sd,

@@ -25,6 +25,8 @@ below 1e-12 * max diagonal, in which case the symmetric pseudo-inverse is used.
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 
 from . import bodies, rpy
@@ -109,3 +111,47 @@ class BlockPreconditioner:
             sl = slice(3 * self.off[p], 3 * self.off[p + 1])
             lam[sl] = t[sl] + self.Z[p] @ U[6 * p:6 * p + 6]
         return np.concatenate([lam, U, phi])
+
+
+class CorrectedBodyPreconditioner(BlockPreconditioner):
+    """The same block solve with given body mobilities N~_w (learned extension of
+    Sec. 3.1: a network predicts N~_p of each body above the wall).
+
+    The blob blocks are the unbounded M_f = M^(pp) (no wall), modified so that
+    the block solve is exact for a consistent pair (M~, N~_w):
+
+        M~^-1 = M_f^-1 + Z_f D Z_f^T,   Z_f = M_f^-1 K_p,
+        N~_f = (K_p^T Z_f)^-1,          D = N~_f N~_w^-1 N~_f - N~_f,
+
+    so that K_p^T M~^-1 K_p = N~_f^-1 + N~_f^-1 D N~_f^-1 = N~_w^-1.  Written
+    out plainly: M~ is formed densely per body and the exact block solve of
+    the base class runs on it with N~_p = N~_w.
+    """
+
+    def __init__(self, wl, r, C, Nw, q=None):
+        q = wl.q if q is None else q
+        free = dataclasses.replace(wl, wall=False)
+        super().__init__(free, r, C, q)
+        off = self.off
+        for p in range(self.M):
+            rp = r[off[p]:off[p + 1]]
+            Kp = bodies.K_matrix(rp, q[p:p + 1], np.array([0, len(rp)]))
+            Mf = self.L[p] @ self.L[p].T
+            Zf = np.linalg.solve(Mf, Kp)
+            Nf = np.linalg.inv(Kp.T @ Zf)
+            D = Nf @ np.linalg.inv(Nw[p]) @ Nf - Nf
+            Minv = np.linalg.inv(Mf) + Zf @ D @ Zf.T
+            Mmod = np.linalg.inv(0.5 * (Minv + Minv.T))
+            self.L[p] = np.linalg.cholesky(0.5 * (Mmod + Mmod.T))
+            self.Z[p] = np.linalg.solve(Mmod, Kp)
+            self.Nt[p] = np.asarray(Nw[p], float)
+        self.G, self.pinv_used = [], False
+        for bs, rs in zip(self.asm_bodies, self.asm_rows):
+            cols = np.concatenate([np.arange(6 * p, 6 * p + 6) for p in bs])
+            Ca = C[np.ix_(rs, cols)]
+            Na = np.zeros((len(cols), len(cols)))
+            for k, p in enumerate(bs):
+                Na[6 * k:6 * k + 6, 6 * k:6 * k + 6] = self.Nt[p]
+            Ga, used = _chol_or_pinv(Ca @ Na @ Ca.T)
+            self.pinv_used |= used
+            self.G.append(Ga)

@@ -323,10 +323,12 @@ def arb_precond_apply(ctx, r):
 
 
 def arb_precond_block(ctx, p, m):
-    L, Lp = _out(m * m)
+    """(L (m, m), N~ (6, 6)) of body p; m = 0 returns (None, N~) only (the
+    per-type variants have no per-body factor)."""
+    L, Lp = _out(m * m) if m > 0 else (None, None)
     Nt, Np = _out(36)
     _check(ctx, load().arb_precond_block(ctx, int(p), Lp, Np))
-    return L.reshape(m, m), Nt.reshape(6, 6)
+    return (L.reshape(m, m) if m > 0 else None), Nt.reshape(6, 6)
 
 
 def arb_solve(ctx, F, u_slip=None, y0=None):

@@ -249,6 +249,7 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
     } else {
         HIPCHK(ctx->partial.ensure((size_t)shape * 3 * N * sizeof(double)));
     }
+    if (sym) arb::pair_sym_clear(s, N, ctx->partial.as<double>());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->prof) {
         HIPCHK(hipEventCreate(&e0));
@@ -387,6 +388,8 @@ arb::PrecondDev pc_view(arb_ctx *ctx) {
     P.tminv = ctx->t_minv.as<double>();
     P.tZ = ctx->t_Z.as<double>();
     P.R9 = ctx->R9.as<double>();
+    P.lcorr = ctx->pc_lcorr ? ctx->lcorr.as<double>() : nullptr;
+    P.stmp = ctx->stmp.as<double>();
     return P;
 }
 
@@ -474,6 +477,7 @@ int precond_build_exact(arb_ctx *ctx, hipStream_t s);
 int precond_build(arb_ctx *ctx, hipStream_t s) {
     TRY(ready(ctx));
     ctx->pc_learned = false;
+    ctx->pc_lcorr = false;
     if (ctx->opt.precond == ARB_PC_BODYFRAME) {
         // free-space blocks of each body type, rotated: no per-solve factorisation
         TRY(ensure_types(ctx, s));
@@ -510,12 +514,19 @@ int precond_build(arb_ctx *ctx, hipStream_t s) {
     float *Y = arb::mlp_forward(s, ctx->mlp_params.p, ctx->mlp_ws.p, M, Bp, ctx->mlp_x.as<float>());
     arb::mlp_mobility(s, ctx->mlp_params.p, M, Y, ctx->opt.a, ctx->opt.eta, ctx->Nt.as<double>(),
                       ctx->status.as<int>() + 4);
+    HIPCHK(ctx->lcorr.ensure(108 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->stmp.ensure(6 * (size_t)M * sizeof(double)));
+    arb::learned_correction(s, M, ctx->body_type_d.as<int>(), ctx->t_Nt.as<double>(),
+                            ctx->R9.as<double>(), ctx->Nt.as<double>(), ctx->lcorr.as<double>(),
+                            ctx->status.as<int>() + 4);
+    ctx->pc_lcorr = true;
     arb::PrecondDev P = pc_view(ctx);
     arb::precond_assembly(s, P);
     int st[8];
     HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (st[4]) {
+        ctx->pc_lcorr = false;
         const int rc = precond_build_exact(ctx, s);
         return rc < 0 ? rc : ARB_W_LEARNED_FALLBACK;
     }
@@ -777,14 +788,6 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
     inf->restarts = restarts;
     inf->rel_residual = res / bnorm;
     inf->rel_residual_fp64 = res / bnorm;
-    if (prec == ARB_FP32C) {
-        // residual of the returned iterate with the FP32 pair sum, for reference
-        TRY(system_apply(ctx, s, y, K.w, ARB_FP32C));
-        arb::axpby(s, n, 1.0, K.b, -1.0, K.w);
-        double r32 = 0.0;
-        TRY(dev_norm(ctx, s, K, K.w, 7, &r32));
-        inf->rel_residual = r32 / bnorm;
-    }
     if (inf->rel_residual_fp64 > tol) return ARB_W_NOT_CONVERGED;
     return warn;
 }
@@ -1167,6 +1170,8 @@ int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde) {
     if (!ctx) return ARB_E_ARG;
     if (!ctx->pc_built) return fail(ctx, ARB_E_ARG, "preconditioner not built");
     if (p < 0 || p >= ctx->M) return fail(ctx, ARB_E_ARG, "body index out of range");
+    if (L && ctx->pc_learned)
+        return fail(ctx, ARB_E_ARG, "the per-type preconditioners have no per-body factor");
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = ctx->stream;
     int64_t off = 0;

@@ -55,7 +55,9 @@ void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double
                  double *out, const double *U, const int *body_of_blob, const double *dvec);
 int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,
                         int *flag_host);
-// symmetric pair sums, FP32 (hi/lo) or FP64 (p64) (pair_sym.hip): u [3][N] unscaled
+// symmetric pair sums, FP32 (hi/lo) or FP64 (p64) (pair_sym.hip): u [3][N]
+// unscaled, accumulated into u (cleared first by pair_sym_clear)
+void pair_sym_clear(hipStream_t s, int N, double *u);
 void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
               const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
               int n_work, double *u);
@@ -108,6 +110,8 @@ struct PrecondDev {
     const int *type = nullptr;
     const int64_t *tmat_off = nullptr, *tz_off = nullptr;
     const double *tminv = nullptr, *tZ = nullptr, *R9 = nullptr;
+    const double *lcorr = nullptr;  // learned: per body N~_f, E1, E2 (108); null: body frame
+    double *stmp = nullptr;         // learned apply scratch: s = Z_f^T r_lam (6M)
 };
 void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos, double a,
                       double eta, bool wall);
@@ -118,6 +122,8 @@ void precond_assembly(hipStream_t s, const PrecondDev &P);
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z);
 void rotate_body_mobility(hipStream_t s, int M, const int *type, const double *tNt,
                           const double *R9, double *Nt);
+void learned_correction(hipStream_t s, int M, const int *type, const double *tNt,
+                        const double *R9, const double *Nw, double *out, int *bad);
 
 // Dense helpers for the Krylov solver (FP64, Sec. 3.1)
 void multidot(hipStream_t s, int64_t n, int k, const double *V, int64_t ldv, const double *w,
@@ -199,13 +205,14 @@ struct arb_ctx {
     int sym_work_N = -1, sym_work_R = -1, sym_n_work = 0;
     bool pc_built = false;
     bool pc_learned = false;
+    bool pc_lcorr = false;  // learned body mobility with the consistent blob-block correction
     int pc_pinv = 0;
 
     // device buffers
     arb::DevBuf blob_off, body_of_blob, r_ref, q, theta, R9, pos, dvec, p64, hi, lo,
         partial, row_p, row_q, row_kind, row_src, row_m, dl_p, dl_q, dldot_p, dldot_q, proj,
         gcoef, grhs, crow, Bc, brow_ptr, brow_ent, asm_body_ptr, asm_bodies, asm_row_ptr,
-        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp;
+        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp, lcorr, stmp;
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;

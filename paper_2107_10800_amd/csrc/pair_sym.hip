@@ -273,14 +273,18 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
     }
 }
 
-// u (layout [3][N], FP64) = sum over all pairs, unscaled (units 1/(8 pi eta))
-void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-              const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
-              int n_work, double *u) {
+// u = 0 (3N doubles) before the symmetric kernel adds into it
+void pair_sym_clear(hipStream_t s, int N, double *u) {
     if (N <= 0) return;
     const size_t n3 = 3 * (size_t)N;
     zero_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(n3, u);
-    if (n_work <= 0) return;
+}
+
+// u (layout [3][N], FP64) += sum over all pairs, unscaled (units 1/(8 pi eta))
+void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+              const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
+              int n_work, double *u) {
+    if (N <= 0 || n_work <= 0) return;
     if (precision == ARB_FP32C) {
         if (wall)
             pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, u);

@@ -6,10 +6,12 @@
 //                factored in LDS, the trailing lower triangle updated in 64 x 64
 //                register tiles; the inverses of the 32 x 32 diagonal blocks of L
 //                are kept for the next step
-//   pc_potri     M_pp^-1 by block forward and backward substitution on the
-//                identity, one workgroup per (body, 32 columns), the block
-//                column held in LDS; every block step is a small GEMM because the
-//                diagonal blocks are applied through their stored inverses
+//   pc_trtri     X = L^-1 by block forward substitution on the identity, one
+//                workgroup per (body, 32 columns), the block column held in LDS;
+//                every block step is a small GEMM because the diagonal blocks
+//                are applied through their stored inverses; X^T is kept in the
+//                strictly upper triangle
+//   pc_lauum     M_pp^-1 = X^T X, one workgroup per (body, 64 x 64 tile)
 //   (bodies with more than 480 rows: pc_chol / pc_inverse, the unblocked
 //   right-looking versions, with X = L^-1 kept transposed in the upper triangle)
 //   pc_body      Z_p = M_pp^-1 K_p (m x 6), R_p = K_p^T Z_p, N~_p = R_p^+
@@ -312,6 +314,12 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
                     ri[r] = nb + min(i0 + 16 * r, nt - 1);
                     rj[r] = nb + min(j0 + r, nt - 1);
                 }
+                double cur[4][4];  // issued before the products: the loads overlap them
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        cur[r][c] = A[(size_t)(t0 + ri[r] - nb) * m + t0 + rj[c] - nb];
                 double acc[4][4] = {};
                 for (int t = 0; t < nb; ++t) {
                     double a[4], b[4];
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         const int j = j0 + c;
-                        if (i < nt && j <= i) A[(size_t)(t0 + i) * m + t0 + j] -= acc[r][c];
+                        if (i < nt && j <= i) A[(size_t)(t0 + i) * m + t0 + j] = cur[r][c] - acc[r][c];
                     }
                 }
             }
@@ -341,23 +349,32 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
     if (fail && tid == 0) atomicMax(&status[0], p + 1);
 }
 
-// stage the 32 x 32 block of L at (R0, C0), zero padded beyond m
-__device__ __forceinline__ void stage_block(double (*Ls)[kLd], const double *A, int m, int R0,
-                                            int C0) {
-    for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
-        const int t = idx / kNB, u = idx % kNB;
-        Ls[t][u] = (R0 + t < m && C0 + u < m) ? A[(size_t)(R0 + t) * m + C0 + u] : 0.0;
+// load (4 per thread) the 32 x 32 block of L at (R0, C0), zero padded beyond m
+__device__ __forceinline__ void load_block(double v[4], const double *A, int m, int R0, int C0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + 256 * e, t = idx / kNB, u = idx % kNB;
+        v[e] = (R0 + t < m && C0 + u < m) ? A[(size_t)(R0 + t) * m + C0 + u] : 0.0;
+    }
+}
+__device__ __forceinline__ void store_block(double (*Ls)[kLd], const double v[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + 256 * e;
+        Ls[idx / kNB][idx % kNB] = v[e];
     }
 }
 
-// M_pp^-1 columns [32 cb, 32 cb + 32) from L and the diagonal-block inverses:
-// forward Y = L^-1 E (rows of blocks before cb vanish), then X = L^-T Y.
-// Dynamic LDS: X, ceil(max_m / 32) * 32 x kLd doubles.
-__global__ __launch_bounds__(256) void pc_potri_kernel(const int *__restrict__ blob_off,
+// X = L^-1, block column [32 cb, 32 cb + 32): forward block substitution on the
+// identity, X_i = Dinv_i (E_i - sum_{cb <= k < i} L_ik X_k); the next block of
+// L is read into registers while the current one is used.  The strictly lower
+// part of X is stored transposed in the strictly upper triangle of M_pp's
+// storage (the diagonal of X is 1 / diag(L)).  Dynamic LDS: the block column,
+// ceil(max_m / 32) * 32 x kLd doubles.
+__global__ __launch_bounds__(256) void pc_trtri_kernel(const int *__restrict__ blob_off,
                                                        const int64_t *__restrict__ mat_off,
-                                                       const double *__restrict__ mats,
+                                                       double *__restrict__ mats,
                                                        const double *__restrict__ dinv,
-                                                       double *__restrict__ minv,
                                                        const int *__restrict__ status) {
     extern __shared__ double X[];
     __shared__ double Ls[kNB][kLd];
@@ -366,19 +383,23 @@ __global__ __launch_bounds__(256) void pc_potri_kernel(const int *__restrict__ b
     const int m = 3 * (blob_off[p + 1] - blob_off[p]);
     const int nbk = (m + kNB - 1) / kNB;
     if (cb >= nbk) return;
-    const double *A = mats + mat_off[p];
+    double *A = mats + mat_off[p];
     const double *Dg = dinv + dinv_offset(blob_off, p);
-    double *Mi = minv + mat_off[p];
     const int tid = threadIdx.x, r = tid / 8, c4 = 4 * (tid % 8);
     const int c0 = kNB * cb;
     for (int i = cb; i < nbk; ++i) {
+        double dreg[4], nxt[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dreg[e] = Dg[(size_t)i * kNB * kNB + tid + 256 * e];
+        if (cb < i) load_block(nxt, A, m, kNB * i, kNB * cb);
         double acc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = (kNB * i + r == c0 + c4 + q) ? 1.0 : 0.0;
         for (int k = cb; k < i; ++k) {
             __syncthreads();
-            stage_block(Ls, A, m, kNB * i, kNB * k);
+            store_block(Ls, nxt);
             __syncthreads();
+            if (k + 1 < i) load_block(nxt, A, m, kNB * i, kNB * (k + 1));
             const double *Xk = X + (size_t)kNB * k * kLd + c4;
             for (int t = 0; t < kNB; ++t) {
                 const double a = Ls[r][t];
@@ -390,8 +411,11 @@ __global__ __launch_bounds__(256) void pc_potri_kernel(const int *__restrict__ b
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = acc[q];
-        for (int idx = tid; idx < kNB * kNB; idx += 256)
-            Ls[idx / kNB][idx % kNB] = Dg[(size_t)i * kNB * kNB + idx];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e;
+            Ls[idx / kNB][idx % kNB] = dreg[e];
+        }
         __syncthreads();
         double y[4] = {0.0, 0.0, 0.0, 0.0};
         for (int t = 0; t < kNB; ++t) {
@@ -403,42 +427,96 @@ __global__ __launch_bounds__(256) void pc_potri_kernel(const int *__restrict__ b
 #pragma unroll
         for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = y[q];
     }
-    for (int i = nbk - 1; i >= 0; --i) {
-        double *Xi = X + (size_t)kNB * i * kLd + c4;
-        double acc[4];
+    __syncthreads();
+    // X[i][c0 + c] for i > c0 + c  ->  A[(c0 + c) m + i]  (consecutive i: coalesced)
+    const int rows = m - c0;
+    for (int idx = tid; idx < rows * kNB; idx += 256) {
+        const int c = idx / rows, i = c0 + idx % rows;
+        const int j = c0 + c;
+        if (j < m && i > j) A[(size_t)j * m + i] = X[(size_t)i * kLd + c];
+    }
+}
+
+// M_pp^-1 = X^T X = U U^T with U = X^T upper triangular (strictly upper part in
+// M_pp's storage; the diagonal, 1 / diag(L), read from the diagonal-block
+// inverses).  One workgroup per (body, 64 x 64 tile (I, J), I <= J); the sum
+// over k >= J runs in chunks of 32 staged in LDS, the next chunk read into
+// registers meanwhile.  Writes both (I, J) and (J, I).
+__global__ __launch_bounds__(256) void pc_lauum_kernel(const int *__restrict__ blob_off,
+                                                       const int64_t *__restrict__ mat_off,
+                                                       const double *__restrict__ mats,
+                                                       const double *__restrict__ dinv,
+                                                       double *__restrict__ minv,
+                                                       const int *__restrict__ status) {
+    __shared__ double Ua[64][kLd], Ub[64][kLd];
+    const int p = blockIdx.y;
+    if (status[0] != 0) return;
+    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    const int nt = (m + 63) / 64;
+    const int tile = blockIdx.x;
+    if (tile >= nt * (nt + 1) / 2) return;
+    int bj = 0;
+    while ((bj + 1) * (bj + 2) / 2 <= tile) ++bj;
+    const int bi = tile - bj * (bj + 1) / 2;  // bi <= bj
+    const int I0 = 64 * bi, J0 = 64 * bj;
+    const double *A = mats + mat_off[p];
+    const double *Dg = dinv + dinv_offset(blob_off, p);
+    double *Mi = minv + mat_off[p];
+    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    const int kl = tid & 31, r0 = tid >> 5;  // a thread stages column kl of rows r0 + 8e
+    // U[row][kk]: 0 below the diagonal, 1/L_kk on it, X[kk][row] above
+    auto u_at = [&](int row, int kk) -> double {
+        if (row >= m || kk >= m || kk < row) return 0.0;
+        if (kk == row) return Dg[(size_t)(row >> 5) * kNB * kNB + (row & 31) * (kNB + 1)];
+        return A[(size_t)row * m + kk];
+    };
+    double na[8], nb8[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = i >= cb ? Xi[r * kLd + q] : 0.0;
-        for (int k = i + 1; k < nbk; ++k) {
-            __syncthreads();
-            stage_block(Ls, A, m, kNB * k, kNB * i);
-            __syncthreads();
-            const double *Xk = X + (size_t)kNB * k * kLd + c4;
-            for (int t = 0; t < kNB; ++t) {
-                const double a = Ls[t][r];
+    for (int e = 0; e < 8; ++e) {
+        na[e] = u_at(I0 + r0 + 8 * e, J0 + kl);
+        nb8[e] = u_at(J0 + r0 + 8 * e, J0 + kl);
+    }
+    double acc[4][4] = {};
+    for (int k0 = J0; k0 < m; k0 += kNB) {
+        __syncthreads();
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = fma(-a, Xk[t * kLd + q], acc[q]);
+        for (int e = 0; e < 8; ++e) {
+            Ua[r0 + 8 * e][kl] = na[e];
+            Ub[r0 + 8 * e][kl] = nb8[e];
+        }
+        __syncthreads();
+        if (k0 + kNB < m) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                na[e] = u_at(I0 + r0 + 8 * e, k0 + kNB + kl);
+                nb8[e] = u_at(J0 + r0 + 8 * e, k0 + kNB + kl);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = acc[q];
-        for (int idx = tid; idx < kNB * kNB; idx += 256)
-            Ls[idx / kNB][idx % kNB] = Dg[(size_t)i * kNB * kNB + idx];
-        __syncthreads();
-        double x[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
         for (int t = 0; t < kNB; ++t) {
-            const double d = Ls[t][r];
+            double a[4], b[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = fma(d, Xi[t * kLd + q], x[q]);
+            for (int q = 0; q < 4; ++q) {
+                a[q] = Ua[ty + 16 * q][t];
+                b[q] = Ub[4 * tx + q][t];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[q][c] = fma(a[q], b[c], acc[q][c]);
         }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = x[q];
     }
-    __syncthreads();
-    for (int idx = tid; idx < m * kNB; idx += 256) {
-        const int row = idx / kNB, c = idx % kNB;
-        if (c0 + c < m) Mi[(size_t)row * m + c0 + c] = X[(size_t)row * kLd + c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = I0 + ty + 16 * q;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = J0 + 4 * tx + c;
+            if (i < m && j < m) {
+                Mi[(size_t)i * m + j] = acc[q][c];
+                Mi[(size_t)j * m + i] = acc[q][c];
+            }
+        }
     }
 }
 
@@ -747,16 +825,26 @@ __global__ __launch_bounds__(256) void pc_apply3_kernel(
 }
 
 
-// Learned variant (spec extension): each body's block uses the unbounded
-// blob mobility of its type in the body frame (computed once), rotated by R_p:
-// M_pp^-1 = (I x R) Minv_type (I x R^T), Z_p = (I x R) Z_type Q^T with
-// Q = diag(R, R); N~_p comes from the network.
+// Per-type variants (learned body mobility and body-frame blocks): each body's
+// block starts from the unbounded blob mobility of its type in the body frame
+// (factored once), rotated by R_p: A_p = (I x R) Minv_type (I x R^T),
+// Z_f = A_p K_p = (I x R) Z_type Q^T with Q = diag(R, R), N~_f = Q N~_type Q^T.
+// Body-frame variant: N~_p = N~_f, an exact block solve of the unbounded blocks.
+// Learned variant: the network gives the wall body mobility N~_w, and the blob
+// block is modified by a rank-6 term so that the block solve stays exact for
+// a consistent pair (M~, N~_w):
+//   M~^-1 = A_p + Z_f D Z_f^T,  D = N~_f N~_w^-1 N~_f - N~_f,
+// which gives K^T M~^-1 K = N~_w^-1 and K^T M~^-1 = N~_w^-1 N~_f Z_f^T.  Per body
+// E1 = D and E2 = D N~_f^-1 are formed at build time; the apply then reads
+//   U^ = -N~_w r_U - N~_f s,  s = Z_f^T r_lam,
+//   lam = A_p r_lam + Z_f (U + E1 s + E2 U),
+// with U = U^ + N~_w C^T phi as in the exact variant.
 __global__ __launch_bounds__(256) void pc_apply1_learned_kernel(
     int N, const int *__restrict__ blob_off, const int *__restrict__ type,
     const int64_t *__restrict__ tmat_off, const int64_t *__restrict__ tz_off,
     const double *__restrict__ tminv, const double *__restrict__ tZ, const double *__restrict__ R9,
-    const double *__restrict__ Nt, const double *__restrict__ r, double *__restrict__ z,
-    double *__restrict__ uhat) {
+    const double *__restrict__ Nt, const double *__restrict__ lcorr, const double *__restrict__ r,
+    double *__restrict__ z, double *__restrict__ uhat, double *__restrict__ stmp) {
     __shared__ double x[kMaxM];
     __shared__ double tb[kMaxM];
     __shared__ double red[8];
@@ -790,28 +878,37 @@ __global__ __launch_bounds__(256) void pc_apply1_learned_kernel(
         for (int c = 0; c < 3; ++c)
             z[3 * (size_t)b0 + 3 * i + c] = R[3 * c] * a0 + R[3 * c + 1] * a1 + R[3 * c + 2] * a2;
     }
+    __shared__ double s6[6];
     if (threadIdx.x < 6) {
-        // Z_p^T r_lam = Q (Z_type^T x_b)
+        // s = Z_f^T r_lam = Q (Z_type^T x_b)
         const int h = threadIdx.x / 3, c = threadIdx.x % 3;
         const double v = R[3 * c] * zb[3 * h] + R[3 * c + 1] * zb[3 * h + 1] + R[3 * c + 2] * zb[3 * h + 2];
-        w6[threadIdx.x] = v + r[3 * (size_t)N + 6 * (size_t)p + threadIdx.x];
+        const double ru = r[3 * (size_t)N + 6 * (size_t)p + threadIdx.x];
+        s6[threadIdx.x] = v;
+        w6[threadIdx.x] = lcorr ? ru : v + ru;
+        if (lcorr) stmp[6 * (size_t)p + threadIdx.x] = v;
     }
     __syncthreads();
     if (threadIdx.x < 6) {
         const double *Nb = Nt + 36 * (size_t)p;
-        double s = 0.0;
-        for (int c = 0; c < 6; ++c) s += Nb[threadIdx.x * 6 + c] * w6[c];
-        uhat[6 * (size_t)p + threadIdx.x] = -s;
+        double acc = 0.0;
+        for (int c = 0; c < 6; ++c) acc += Nb[threadIdx.x * 6 + c] * w6[c];
+        if (lcorr) {  // - N~_f s
+            const double *Nf = lcorr + 108 * (size_t)p;
+            for (int c = 0; c < 6; ++c) acc += Nf[threadIdx.x * 6 + c] * s6[c];
+        }
+        uhat[6 * (size_t)p + threadIdx.x] = -acc;
     }
 }
 
 __global__ __launch_bounds__(256) void pc_apply3_learned_kernel(
     int N, int M, const int *__restrict__ blob_off, const int *__restrict__ type,
     const int64_t *__restrict__ tz_off, const double *__restrict__ tZ, const double *__restrict__ R9,
-    const double *__restrict__ Nt, const int *__restrict__ brow_ptr,
+    const double *__restrict__ Nt, const double *__restrict__ lcorr,
+    const double *__restrict__ stmp, const int *__restrict__ brow_ptr,
     const int *__restrict__ brow_ent, const double *__restrict__ crow,
     const double *__restrict__ uhat, double *__restrict__ z, int has_rows) {
-    __shared__ double U[6], Ub[6], f[6], R[9];
+    __shared__ double U[6], V[6], Ub[6], f[6], R[9];
     const int p = blockIdx.x;
     const size_t off_phi = 3 * (size_t)N + 6 * (size_t)M;
     if (threadIdx.x < 9) R[threadIdx.x] = R9[9 * (size_t)p + threadIdx.x];
@@ -835,9 +932,19 @@ __global__ __launch_bounds__(256) void pc_apply3_learned_kernel(
         z[3 * (size_t)N + 6 * (size_t)p + threadIdx.x] = s;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {  // Q^T U
+    if (threadIdx.x < 6) {  // V = U (+ E1 s + E2 U with the learned correction)
+        double v = U[threadIdx.x];
+        if (lcorr) {
+            const double *E1 = lcorr + 108 * (size_t)p + 36, *E2 = E1 + 36;
+            const double *sp = stmp + 6 * (size_t)p;
+            for (int c = 0; c < 6; ++c) v += E1[threadIdx.x * 6 + c] * sp[c] + E2[threadIdx.x * 6 + c] * U[c];
+        }
+        V[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {  // Q^T V
         const int h = threadIdx.x / 3, c = threadIdx.x % 3;
-        Ub[threadIdx.x] = R[c] * U[3 * h] + R[3 + c] * U[3 * h + 1] + R[6 + c] * U[3 * h + 2];
+        Ub[threadIdx.x] = R[c] * V[3 * h] + R[3 + c] * V[3 * h + 1] + R[6 + c] * V[3 * h + 2];
     }
     __syncthreads();
     const int b0 = blob_off[p], n = blob_off[p + 1] - b0;
@@ -880,6 +987,95 @@ __global__ void pc_rotate_nt_kernel(int M, const int *__restrict__ type,
         }
 }
 
+// 6 x 6 SPD inverse by Cholesky; false if a pivot is not positive
+__device__ bool spd6_inverse(const double *A, double *X) {
+    double L[36] = {};
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j * 6 + j];
+        for (int k = 0; k < j; ++k) d -= L[j * 6 + k] * L[j * 6 + k];
+        if (!(d > 0.0)) return false;
+        L[j * 6 + j] = sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double v = 0.5 * (A[i * 6 + j] + A[j * 6 + i]);
+            for (int k = 0; k < j; ++k) v -= L[i * 6 + k] * L[j * 6 + k];
+            L[i * 6 + j] = v / L[j * 6 + j];
+        }
+    }
+    for (int c = 0; c < 6; ++c) {  // X e_c = L^-T L^-1 e_c
+        double y[6];
+        for (int i = 0; i < 6; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[i * 6 + k] * y[k];
+            y[i] = v / L[i * 6 + i];
+        }
+        for (int i = 5; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < 6; ++k) v -= L[k * 6 + i] * y[k];
+            y[i] = v / L[i * 6 + i];
+        }
+        for (int i = 0; i < 6; ++i) X[i * 6 + c] = y[i];
+    }
+    return true;
+}
+
+// per body: N~_f (rotated type mobility), E1 = N~_f N~_w^-1 N~_f - N~_f,
+// E2 = E1 N~_f^-1 (108 doubles); flags bodies whose N~_w or N~_f is not SPD
+__global__ void pc_learned_corr_kernel(int M, const int *__restrict__ type,
+                                       const double *__restrict__ tNt,
+                                       const double *__restrict__ R9,
+                                       const double *__restrict__ Nw, double *__restrict__ out,
+                                       int *__restrict__ bad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const double *R = R9 + 9 * (size_t)p;
+    const double *A = tNt + 36 * (size_t)type[p];
+    double T[36], Nf[36], Wi[36], Fi[36];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            const int bi = i / 3, ri = i % 3;
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += R[3 * ri + k] * A[(3 * bi + k) * 6 + j];
+            T[i * 6 + j] = s;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            const int bj = j / 3, rj = j % 3;
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[i * 6 + 3 * bj + k] * R[3 * rj + k];
+            Nf[i * 6 + j] = s;
+        }
+    const bool ok = spd6_inverse(Nw + 36 * (size_t)p, Wi) && spd6_inverse(Nf, Fi);
+    if (!ok) atomicOr(bad, 1);
+    double *o = out + 108 * (size_t)p;
+    for (int k = 0; k < 36; ++k) o[k] = Nf[k];
+    double WN[36], E1[36];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += Wi[i * 6 + k] * Nf[k * 6 + j];
+            WN[i * 6 + j] = s;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = -Nf[i * 6 + j];
+            for (int k = 0; k < 6; ++k) s += Nf[i * 6 + k] * WN[k * 6 + j];
+            E1[i * 6 + j] = ok ? s : 0.0;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += E1[i * 6 + k] * Fi[k * 6 + j];
+            o[36 + i * 6 + j] = E1[i * 6 + j];
+            o[72 + i * 6 + j] = ok ? s : 0.0;
+        }
+}
+
+void learned_correction(hipStream_t s, int M, const int *type, const double *tNt,
+                        const double *R9, const double *Nw, double *out, int *bad) {
+    if (M > 0)
+        pc_learned_corr_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, type, tNt, R9, Nw, out, bad);
+}
+
 void rotate_body_mobility(hipStream_t s, int M, const int *type, const double *tNt,
                           const double *R9, double *Nt) {
     if (M > 0) pc_rotate_nt_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, type, tNt, R9, Nt);
@@ -902,13 +1098,16 @@ hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec
         hipError_t e = hipFuncSetAttribute((const void *)pc_potrf_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f);
         if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)pc_potri_kernel,
+        e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
         if (e != hipSuccess) return e;
+        const int nt = (max_m + 63) / 64;
         pc_potrf_kernel<<<P.M, 256, lds_f, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.dinv,
                                                 P.status);
-        pc_potri_kernel<<<dim3(nbk, P.M), 256, lds_i, s>>>(P.blob_off, P.mat_off, P.mats, P.dinv,
-                                                           P.minv, P.status);
+        pc_trtri_kernel<<<dim3(nbk, P.M), 256, lds_i, s>>>(P.blob_off, P.mat_off, P.mats, P.dinv,
+                                                           P.status);
+        pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.M), 256, 0, s>>>(P.blob_off, P.mat_off, P.mats,
+                                                                    P.dinv, P.minv, P.status);
     } else {
         pc_chol_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.status);
         pc_inverse_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.minv,
@@ -933,7 +1132,8 @@ void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, d
     if (P.M <= 0) return;
     if (P.learned)
         pc_apply1_learned_kernel<<<P.M, 256, 0, s>>>(N, P.blob_off, P.type, P.tmat_off, P.tz_off,
-                                                     P.tminv, P.tZ, P.R9, P.Nt, r, z, P.tmp);
+                                                     P.tminv, P.tZ, P.R9, P.Nt, P.lcorr, r, z,
+                                                     P.tmp, P.stmp);
     else
         pc_apply1_kernel<<<P.M, 256, 0, s>>>(N, P.blob_off, P.mat_off, P.z_off, P.minv, P.Z, P.Nt,
                                              r, z, P.tmp);
@@ -942,8 +1142,9 @@ void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, d
                                              P.row_p, P.row_q, P.crow, P.G, r, P.tmp, z);
     if (P.learned)
         pc_apply3_learned_kernel<<<P.M, 256, 0, s>>>(N, P.M, P.blob_off, P.type, P.tz_off, P.tZ,
-                                                     P.R9, P.Nt, P.brow_ptr, P.brow_ent, P.crow,
-                                                     P.tmp, z, P.A > 0 ? 1 : 0);
+                                                     P.R9, P.Nt, P.lcorr, P.stmp, P.brow_ptr,
+                                                     P.brow_ent, P.crow, P.tmp, z,
+                                                     P.A > 0 ? 1 : 0);
     else
         pc_apply3_kernel<<<P.M, 256, 0, s>>>(N, P.M, P.blob_off, P.z_off, P.Z, P.Nt, P.brow_ptr,
                                              P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);

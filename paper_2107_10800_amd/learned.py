@@ -47,9 +47,12 @@ def load_model(ctx, params, scale):
 
 
 def train(ctx, X, T, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed: int = 7,
-          lr_decay: float = 0.93, log=None):
-    """Adam on the GPU over shuffled batches; returns the per-epoch loss of the
-    last batch (computed before its step, on standardised outputs)."""
+          lr_final: float = 1e-3, log=None):
+    """Adam on the GPU over shuffled batches, learning rate on a cosine from lr
+    down to lr * lr_final; returns the per-epoch loss of the last batch
+    (computed before its step, on standardised outputs)."""
+    import math
+
     import torch
 
     dev = torch.device("cuda", 0)
@@ -59,7 +62,9 @@ def train(ctx, X, T, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed
     rng = np.random.default_rng(seed)
     stream = torch.cuda.Stream()
     hist = []
+    lr0 = lr
     for ep in range(epochs):
+        lr = lr0 * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * ep / epochs)))
         perm = torch.tensor(rng.permutation(n), device=dev)
         with torch.cuda.stream(stream):
             for s0 in range(0, n - batch + 1, batch):
@@ -73,5 +78,18 @@ def train(ctx, X, T, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed
         hist.append(loss)
         if log:
             log(f"epoch {ep}: loss {loss:.3e} lr {lr:.2e}")
-        lr *= lr_decay
     return hist
+
+
+def mobility_from_output(Y, a: float = 1.0, eta: float = 1.0):
+    """Body mobilities (B, 6, 6) from network outputs (B, 21): lower triangle of L
+    row by row with log L_ii on the diagonal, N~ = D^-1 L L^T D^-1,
+    D = diag(sqrt(6 pi eta a) I3, sqrt(8 pi eta a^3) I3) (for reporting)."""
+    Y = np.asarray(Y, np.float64).reshape(-1, 21)
+    rows, cols = np.tril_indices(6)
+    L = np.zeros((len(Y), 6, 6))
+    L[:, rows, cols] = Y
+    d = np.arange(6)
+    L[:, d, d] = np.exp(L[:, d, d])
+    D = np.array([np.sqrt(6 * np.pi * eta * a)] * 3 + [np.sqrt(8 * np.pi * eta * a ** 3)] * 3)
+    return (L @ L.transpose(0, 2, 1)) / D[None, :, None] / D[None, None, :]

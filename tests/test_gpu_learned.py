@@ -6,10 +6,12 @@ per-tensor relative L2 <= 3e-2 against the float64 oracle evaluated at the same
 solution: the learned-preconditioned solve must match the exact solution within
 the same forward-error bar as the exact-preconditioned one.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
-from oracle import mlp, system
+from oracle import mlp, precond, system
 from paper_2107_10800_amd import arb
 from paper_2107_10800_amd import learned
 from paper_2107_10800_amd import workloads as W
@@ -158,6 +160,44 @@ def test_learned_preconditioner_solution(trained, prec):
     bar = bar_of(S, info)
     assert rel(U, yd[3 * N:3 * N + 6 * M]) <= bar
     assert rel(U, Ue) <= 2 * bar
+    # the corrected learned blocks are about as strong as the exact ones
+    assert info["iterations"] <= infoe["iterations"] + 2
+
+
+def test_learned_apply_matches_oracle(trained):
+    # the learned block solve: unbounded per-type blob blocks with the rank-6
+    # correction for the network's N~_w, against the oracle's dense version
+    model = trained[0]
+    wl = W.bacteria(n_bact=4, side=60.0, seed=21)
+    S = system.assemble(wl)
+    r = np.random.default_rng(9).standard_normal(S["A"].shape[0])
+    c = arb.context_for(wl, precision=arb.ARB_FP64, precond=arb.ARB_PC_LEARNED)
+    try:
+        learned.load_model(c, *model)
+        assert arb.arb_precond_build(c) == arb.ARB_OK
+        Nw = [arb.arb_precond_block(c, p, 0)[1] for p in range(wl.M)]
+        z = arb.arb_precond_apply(c, r)
+        with pytest.raises(arb.ArbError):
+            arb.arb_precond_block(c, 0, 3 * int(wl.blob_offset[1]))
+    finally:
+        arb.arb_destroy(c)
+    P = precond.CorrectedBodyPreconditioner(wl, S["r"], S["C"], Nw)
+    assert rel(z, P.apply(r)) <= 1e-10
+
+
+def test_bodyframe_apply_matches_oracle():
+    # rotated per-type unbounded blocks = the unbounded block preconditioner
+    wl = W.bacteria(n_bact=4, side=60.0, seed=21)
+    S = system.assemble(wl)
+    r = np.random.default_rng(10).standard_normal(S["A"].shape[0])
+    c = arb.context_for(wl, precision=arb.ARB_FP64, precond=arb.ARB_PC_BODYFRAME)
+    try:
+        assert arb.arb_precond_build(c) == arb.ARB_OK
+        z = arb.arb_precond_apply(c, r)
+    finally:
+        arb.arb_destroy(c)
+    P = precond.BlockPreconditioner(dataclasses.replace(wl, wall=False), S["r"], S["C"])
+    assert rel(z, P.apply(r)) <= 1e-10
 
 
 def test_learned_fallback_on_invalid_factor():
