@@ -159,9 +159,9 @@ def matvec_bench(torch, arb, sl, precision, steps, warmup):
         arb.arb_destroy(ctx)
 
 
-def solve_bench(torch, arb, W, precision, reps=2):
-    wl = W.bacteria(n_bact=1024, seed=3)
-    ctx = arb.context_for(wl, precision=precision, tol=1e-6, restart=100, max_iter=400)
+def solve_bench(torch, arb, wl, label, precision, tol=1e-6, reps=2):
+    """Device solve of A y = b to tol (FP64 residual), preconditioner rebuilt each time."""
+    ctx = arb.context_for(wl, precision=precision, tol=tol, restart=100, max_iter=1000)
     try:
         dev = torch.device("cuda")
         F = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
@@ -177,13 +177,41 @@ def solve_bench(torch, arb, W, precision, reps=2):
             rc, info = arb.arb_solve_dev(ctx, F, None, y, warm=False, stream=sh)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-        return dict(workload=f"bacteria above a wall: {wl.N // 122} x (42-blob head + 80-blob "
-                             f"flagellum), N={wl.N}, M={wl.M}, Nc={wl.n_rows}, n={n}",
+        return dict(workload=f"{label}, N={wl.N}, M={wl.M}, Nc={wl.n_rows}, n={n}",
                     precision="f32c pair sums, f64 Krylov" if precision else "f64",
-                    ms_per_solve=1e3 * min(times), iterations=info["iterations"],
+                    tol=tol, ms_per_solve=1e3 * min(times), iterations=info["iterations"],
                     rel_residual_fp64=info["rel_residual_fp64"],
                     precond_build_ms=info["t_build_ms"], status=rc,
-                    pairs_per_matvec=wl.N ** 2)
+                    pairs_per_matvec=int(wl.N) ** 2)
+    finally:
+        arb.arb_destroy(ctx)
+
+
+def filament_bench(arb, W, reps=5):
+    """Unbounded filament (20 rods x 4 blobs): FP64 solve to 1e-10, Euler step of 0.1
+    and the position correction, host-array entry points."""
+    wl = W.filament()
+    ctx = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10)
+    try:
+        arb.arb_solve(ctx, wl.F)                                                 # warm-up
+        ts, tc = [], []
+        for _ in range(reps):
+            arb.arb_set_state(ctx, wl.q, wl.theta)
+            t0 = time.perf_counter()
+            rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+            t1 = time.perf_counter()
+            arb.arb_euler_update(ctx, U.ravel(), 0.1)
+            t2 = time.perf_counter()
+            _, _, it, res = arb.arb_correct_positions(ctx, tol=1e-10, max_iter=50)
+            t3 = time.perf_counter()
+            ts.append(t1 - t0)
+            tc.append(t3 - t2)
+        return dict(workload=f"free filament, 20 rods x 4 blobs, unbounded, N={wl.N}, "
+                             f"M={wl.M}, Nc={wl.n_rows}, n={wl.n_unknowns}",
+                    precision="f64", tol=1e-10, ms_per_solve=1e3 * min(ts),
+                    iterations=info["iterations"], rel_residual=info["rel_residual"], status=rc,
+                    correction_ms=1e3 * min(tc), correction_iterations=it,
+                    correction_residual=res)
     finally:
         arb.arb_destroy(ctx)
 
@@ -333,9 +361,21 @@ def main():
     }
     if not args.no_solve:
         log("bench: GMRES solve, bacteria 1024, f32c")
-        res["gmres"] = solve_bench(torch, arb, W, arb.ARB_FP32C)
+        res["gmres"] = solve_bench(torch, arb, W.bacteria(n_bact=1024, seed=3),
+                                   "bacteria above a wall: 1024 x (42-blob head + 80-blob "
+                                   "flagellum)", arb.ARB_FP32C)
         log(f"bench: solve {res['gmres']['ms_per_solve']:.1f} ms, "
             f"{res['gmres']['iterations']} iterations")
+        log("bench: filament solve + correction, f64")
+        res["filament"] = filament_bench(arb, W)
+        log(f"bench: filament {res['filament']['ms_per_solve']:.2f} ms, "
+            f"{res['filament']['iterations']} iterations")
+        log("bench: GMRES solve, diatom colonies, f32c")
+        res["diatoms"] = solve_bench(torch, arb, W.diatoms(),
+                                     "256 unbounded diatom colonies of 5-40 plates (15 x 3 blobs) "
+                                     "with sliding links", arb.ARB_FP32C, reps=1)
+        log(f"bench: diatoms {res['diatoms']['ms_per_solve']:.1f} ms, "
+            f"{res['diatoms']['iterations']} iterations")
     if args.learned:
         log("bench: learned preconditioner")
         res["learned"] = learned_bench(torch, arb, W)

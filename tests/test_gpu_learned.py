@@ -55,6 +55,39 @@ def test_forward_and_gradient_match_oracle(ctx):
             k += part.size
 
 
+def test_adam_step_matches_oracle():
+    # one training step from fresh Adam moments against the oracle's Adam on the
+    # oracle's gradient: where the gradient is clearly non-zero (its sign is not
+    # decided by BF16 rounding) every weight moves by lr against that sign
+    import torch
+
+    P = W.mlp_init_weights(seed=13)
+    rng = np.random.default_rng(14)
+    B, lr = 256, 1e-3
+    X = np.column_stack([rng.uniform(8, 15, B), rng.standard_normal((B, 4)),
+                         rng.integers(0, 2, (B, 2))]).astype(np.float32)
+    T = (0.3 * rng.standard_normal((B, 21))).astype(np.float32)
+    c = arb.arb_create(precision=arb.ARB_FP64, wall=True)
+    try:
+        arb.arb_mlp_set_params(c, P)
+        st = torch.cuda.Stream()
+        xd = torch.tensor(X, device="cuda")
+        td = torch.tensor(T, device="cuda")
+        torch.cuda.synchronize()
+        arb.arb_mlp_train_step_dev(c, B, xd, td, lr, stream=st.cuda_stream)
+        torch.cuda.synchronize()
+        P1 = arb.arb_mlp_get_params(c).astype(float)
+    finally:
+        arb.arb_destroy(c)
+    _, g = mlp.loss_and_grad(P.astype(float), X.astype(float), T.astype(float))
+    Po, _, _ = mlp.adam(P.astype(float), g, np.zeros_like(g), np.zeros_like(g), 1, lr=lr)
+    big = np.abs(g) > 0.1 * np.sqrt(np.mean(g * g))
+    assert big.mean() > 0.1
+    d_gpu, d_or = P1 - P, Po - P
+    assert np.allclose(d_gpu[big], d_or[big], rtol=1e-3, atol=1e-7)
+    assert np.all(np.abs(d_gpu) <= lr * (1 + 1e-3) + 1e-7)
+
+
 def test_features_match_oracle():
     wl = W.bacterium_poses(40, seed=12)
     c = arb.context_for(wl)

@@ -72,3 +72,28 @@ def test_features_double_cover():
     assert np.all(x[:, 1] >= 0)
     assert np.allclose(x[1, 1:5], [0.5, -0.5, 0.5, -0.5])
     assert np.allclose(x[:, 5:], [[1, 0], [0, 1]])
+
+
+def test_adam_first_step_is_sign_descent():
+    # with zero moments the bias-corrected first step is lr * g / (|g| + eps):
+    # every weight moves by lr against the sign of its gradient
+    rng = np.random.default_rng(3)
+    flat = rng.standard_normal(50)
+    g = rng.standard_normal(50) * np.logspace(-3, 2, 50)
+    new, m, v = mlp.adam(flat, g, np.zeros(50), np.zeros(50), 1, lr=1e-2)
+    assert np.allclose(new - flat, -1e-2 * np.sign(g), rtol=1e-4, atol=0)
+    # a constant gradient keeps the step at lr (moments track g and g^2 exactly)
+    new2, _, _ = mlp.adam(new, g, m, v, 2, lr=1e-2)
+    assert np.allclose(new2 - new, -1e-2 * np.sign(g), rtol=1e-4, atol=0)
+
+
+def test_adam_minimises_a_quadratic():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((6, 6))
+    H = A @ A.T + np.eye(6)
+    xs = rng.standard_normal(6)
+    x, m, v = np.zeros(6), np.zeros(6), np.zeros(6)
+    for t in range(1, 3001):
+        lr = 0.05 * (0.5 * (1 + np.cos(np.pi * t / 3000)) + 1e-3)
+        x, m, v = mlp.adam(x, H @ (x - xs), m, v, t, lr=lr)
+    assert np.linalg.norm(x - xs) <= 1e-3 * np.linalg.norm(xs)
