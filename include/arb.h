@@ -79,6 +79,9 @@ typedef struct {
                         /* 2 = symmetric kernel (each unordered pair once,     */
                         /* M_ji = M_ij^T; FP64 atomic sums, reproducible to    */
                         /* rounding only)                                      */
+    int    graphs;     /* 0 = the GMRES iteration is captured once per Arnoldi */
+                       /* index in HIP graphs and replayed (default),          */
+                       /* 1 = plain launches                                   */
 } arb_options;
 
 typedef struct {

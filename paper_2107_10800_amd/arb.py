@@ -59,7 +59,7 @@ class arb_options(C.Structure):
     _fields_ = [("device", C.c_int), ("precision", C.c_int), ("wall", C.c_int),
                 ("eta", C.c_double), ("a", C.c_double), ("tol", C.c_double),
                 ("restart", C.c_int), ("max_iter", C.c_int), ("precond", C.c_int),
-                ("slices", C.c_int), ("pair_kernel", C.c_int)]
+                ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int)]
 
 
 class arb_solve_info(C.Structure):
@@ -180,9 +180,10 @@ def _check(ctx, rc):
 
 # ------------------------------------------------------------------ entry points
 def arb_create(device=0, precision=ARB_FP64, wall=False, eta=1.0, a=1.0, tol=1e-10,
-               restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0, pair_kernel=0):
+               restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0, pair_kernel=0,
+               graphs=0):
     opt = arb_options(device, precision, int(bool(wall)), eta, a, tol, restart, max_iter,
-                      precond, slices, pair_kernel)
+                      precond, slices, pair_kernel, graphs)
     h = _P()
     rc = load().arb_create(C.byref(h), C.byref(opt))
     if rc < 0:
@@ -454,11 +455,11 @@ def arb_body_mobility(ctx):
 
 # ------------------------------------------------------------------ convenience
 def context_for(wl, precision=ARB_FP64, tol=1e-10, restart=100, max_iter=1000,
-                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0):
+                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0, graphs=0):
     """Create a context and load a workload (bodies, links, rows, state)."""
     ctx = arb_create(device=device, precision=precision, wall=wl.wall, eta=wl.eta, a=wl.a,
                      tol=tol, restart=restart, max_iter=max_iter, precond=precond, slices=slices,
-                     pair_kernel=pair_kernel)
+                     pair_kernel=pair_kernel, graphs=graphs)
     arb_set_bodies(ctx, wl.blob_offset, wl.r_ref, wl.body_type)
     if len(wl.pq):
         arb_set_links(ctx, wl.pq, wl.dl_p, wl.dl_q, wl.dldot_p, wl.dldot_q, wl.nproj, wl.proj)

@@ -646,6 +646,54 @@ int dev_norm(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *x, int slot, 
 // from the y already in place with its residual r = rhs - A y in K.r.  Stops
 // when the residual of the operator in `prec` is <= tol_abs, or after the
 // iteration budget.  Returns the final residual norm in *res (same operator).
+// everything the launches of one Arnoldi step depend on besides buffer contents
+std::vector<long long> graph_key(arb_ctx *ctx, const Krylov &K, int prec) {
+    const int64_t skey = (int64_t)ctx->N * 4 + prec * 2 + (ctx->opt.wall ? 1 : 0);
+    auto it = ctx->slice_cache.find(skey);
+    return {(long long)arb::alloc_generation().load(), (long long)K.n, K.m, prec,
+            ctx->opt.precond, ctx->pc_learned ? 1 : 0, ctx->pc_lcorr ? 1 : 0, ctx->N, ctx->M,
+            ctx->Nc, ctx->n_asm, it == ctx->slice_cache.end() ? 0 : it->second,
+            (long long)(intptr_t)K.V, (long long)(intptr_t)ctx->pinned};
+}
+
+// run one Arnoldi step: replay its graph, capturing it first if needed; plain
+// launches if capture is unavailable
+template <class F>
+int run_step_graph(arb_ctx *ctx, hipStream_t s, int j, const std::vector<long long> &key,
+                   F &&body) {
+    GmresGraphs &G = ctx->ggraph;
+    if (G.broken) return body();
+    if (G.key != key) {
+        G.clear();
+        G.key = key;
+    }
+    if ((int)G.exec.size() <= j) G.exec.resize(j + 1, nullptr);
+    if (!G.exec[j]) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            G.broken = true;
+            return body();
+        }
+        const int rc = body();
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &g);
+        hipGraphExec_t x = nullptr;
+        const hipError_t e2 =
+            (rc == 0 && e == hipSuccess) ? hipGraphInstantiate(&x, g, nullptr, nullptr, 0) : e;
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != 0 || e2 != hipSuccess) {
+            // nothing recorded ran: fall back to plain launches for this context
+            (void)hipGetLastError();
+            if (x) (void)hipGraphExecDestroy(x);
+            G.broken = true;
+            return body();
+        }
+        G.exec[j] = x;
+    }
+    HIPCHK(hipGraphLaunch(G.exec[j], s));
+    return 0;
+}
+
 int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double *y,
                double tol_abs, int prec, int max_iter, int *total, int *restarts,
                double hist_scale, arb_solve_info *inf, double *res, bool trust_estimate) {
@@ -668,18 +716,29 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         arb::scale_copy(s, n, K.r, K.sc + 3, K.V);  // v_0 = r / beta
         int k = 0;
         double last_est = beta;
+        const bool graphs = ctx->opt.graphs == 0 && !ctx->prof;
         for (int j = 0; j < m; ++j) {
             double *vj = K.V + (size_t)j * n;
-            TRY(precond_apply(ctx, s, vj, K.z));
-            TRY(system_apply(ctx, s, K.z, K.w, prec));
-            // classical Gram-Schmidt, twice
-            arb::multidot(s, n, j + 1, K.V, n, K.w, K.part, K.h1);
-            arb::gemv_sub(s, n, j + 1, K.V, n, K.h1, K.w);
-            arb::multidot(s, n, j + 1, K.V, n, K.w, K.part, K.h2);
-            arb::gemv_sub(s, n, j + 1, K.V, n, K.h2, K.w);
-            arb::multidot(s, n, 1, K.w, n, K.w, K.part, K.sc + 4);
-            arb::arnoldi_post(s, j, m, K.h1, K.h2, K.sc + 4, K.H, K.cs, K.sn, K.g, K.sc + 5);
-            HIPCHK(hipMemcpyAsync(pin, K.sc + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            // one Arnoldi step; the first of a cycle runs plainly (it may tune the
+            // pair launch), the others replay a graph captured once per j
+            auto step = [&]() -> int {
+                if (j > 0) arb::scale_copy(s, n, K.w, K.sc + 5, vj);  // v_j = w / h_{j,j-1}
+                TRY(precond_apply(ctx, s, vj, K.z));
+                TRY(system_apply(ctx, s, K.z, K.w, prec));
+                // classical Gram-Schmidt, twice
+                arb::multidot(s, n, j + 1, K.V, n, K.w, K.part, K.h1);
+                arb::gemv_sub(s, n, j + 1, K.V, n, K.h1, K.w);
+                arb::multidot(s, n, j + 1, K.V, n, K.w, K.part, K.h2);
+                arb::gemv_sub(s, n, j + 1, K.V, n, K.h2, K.w);
+                arb::multidot(s, n, 1, K.w, n, K.w, K.part, K.sc + 4);
+                arb::arnoldi_post(s, j, m, K.h1, K.h2, K.sc + 4, K.H, K.cs, K.sn, K.g, K.sc + 5);
+                HIPCHK(hipMemcpyAsync(pin, K.sc + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                return 0;
+            };
+            if (graphs && j > 0)
+                TRY(run_step_graph(ctx, s, j, graph_key(ctx, K, prec), step));
+            else
+                TRY(step());
             HIPCHK(hipStreamSynchronize(s));
             const double hn = pin[0], est = pin[1];
             if (!std::isfinite(est)) return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
@@ -688,7 +747,6 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
             push(est * hist_scale);
             last_est = est;
             if (est <= tol_abs || *total >= max_iter || hn == 0.0) break;
-            arb::scale_copy(s, n, K.w, K.sc + 5, K.V + (size_t)(j + 1) * n);
         }
         arb::upper_solve(s, k, m, K.H, K.g, K.sv);
         arb::gemv_set(s, n, k, K.V, n, K.sv, K.w);
@@ -812,7 +870,7 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         opt->restart > 256 || opt->max_iter < 1 ||
         (opt->precision != ARB_FP64 && opt->precision != ARB_FP32C) || opt->precond < 0 ||
         opt->precond > 3 || opt->slices < 0 || opt->slices > 4096 || opt->pair_kernel < 0 ||
-        opt->pair_kernel > 2)
+        opt->pair_kernel > 2 || opt->graphs < 0 || opt->graphs > 1)
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
@@ -834,6 +892,7 @@ void arb_destroy(arb_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->opt.device);
     (void)hipDeviceSynchronize();
+    ctx->ggraph.clear();
     for (auto &e : ctx->prof_ev) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);

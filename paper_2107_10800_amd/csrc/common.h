@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -17,6 +18,13 @@ constexpr int kWave = 64;           // CDNA wavefront
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------- device buffer
+// bumped whenever any device buffer is (re)allocated: captured HIP graphs that
+// hold buffer addresses are rebuilt after it changes
+inline std::atomic<unsigned long long> &alloc_generation() {
+    static std::atomic<unsigned long long> g{0};
+    return g;
+}
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -36,6 +44,7 @@ struct DevBuf {
         size_t nb = nbytes ? nbytes : 16;
         hipError_t e = hipMalloc(&p, nb);
         if (e == hipSuccess) bytes = nb;
+        ++alloc_generation();
         return e;
     }
     template <class T> T *as() const { return static_cast<T *>(p); }
@@ -180,6 +189,24 @@ void correct_positions(hipStream_t s, const CorrectDev &C, double tol, int max_i
 }  // namespace arb
 
 // ---------------------------------------------------------------- context
+// HIP graphs of the GMRES iteration, one per Arnoldi index j >= 1, valid for
+// the key they were captured under
+struct GmresGraphs {
+    std::vector<hipGraphExec_t> exec;
+    std::vector<long long> key;
+    bool broken = false;  // a capture failed: plain launches from then on
+    void clear() {
+        for (auto &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        exec.clear();
+        key.clear();
+    }
+    GmresGraphs() = default;
+    GmresGraphs(const GmresGraphs &) = delete;
+    GmresGraphs &operator=(const GmresGraphs &) = delete;
+    ~GmresGraphs() { clear(); }
+};
+
 struct arb_ctx {
     arb_options opt{};
     hipStream_t stream = nullptr;
@@ -217,6 +244,7 @@ struct arb_ctx {
     arb::DevBuf s_in, s_out, s_aux, s_pos;
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
     double *pinned = nullptr;  // host pinned scratch (small)
+    GmresGraphs ggraph;
     // correction
     arb::DevBuf c_link_ptr, c_links, c_local, c_ws_off, c_ws, c_iters, c_resid, c_pq, c_abp, c_ab;
     arb::DevBuf tune_out;

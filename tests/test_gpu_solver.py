@@ -253,3 +253,26 @@ def test_preconditioner_large_bodies(n_helix):
         assert rel(arb.arb_precond_apply(ctx, r), P.apply(r)) <= 1e-11
     finally:
         arb.arb_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,prec", [("filament", arb.ARB_FP64), ("bacteria4", arb.ARB_FP32C),
+                                       ("diatoms2", arb.ARB_FP64)])
+def test_graph_replays_match_plain_launches(name, prec):
+    # the GMRES iteration captured in HIP graphs: every solve (the first
+    # captures, the later ones replay, with plain launches and host syncs in
+    # between) gives bit for bit the iterates of plain launches
+    wl = cases()[name]()
+    tol = 1e-10 if prec == arb.ARB_FP64 else 1e-6
+    outs = {}
+    for graphs in (1, 0):
+        c = arb.context_for(wl, precision=prec, tol=tol, graphs=graphs)
+        try:
+            outs[graphs] = [arb.arb_solve(c, wl.F, u_slip=wl.u_slip) for _ in range(3)]
+        finally:
+            arb.arb_destroy(c)
+    ref = outs[1][0]
+    print(f"{name}: {ref[4]['iterations']} iterations", flush=True)
+    for rc, U, phi, lam, info in outs[0] + outs[1]:
+        assert rc == ref[0] and info["iterations"] == ref[4]["iterations"]
+        assert np.array_equal(U, ref[1]) and np.array_equal(phi, ref[2])
+        assert np.array_equal(lam, ref[3])
