@@ -222,17 +222,18 @@ int heuristic_slices(int N) {
     return s;
 }
 
-int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R) {
-    if (ctx->sym_work_N == N && ctx->sym_work_R == R) return 0;
+int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R, int precision) {
+    const int pi = precision == ARB_FP32C ? 1 : 0;
+    if (ctx->sym_work_N[pi] == N && ctx->sym_work_R[pi] == R) return 0;
     std::vector<int4> w = arb::pair_sym_worklist(N, R);
-    HIPCHK(ctx->sym_work.ensure(std::max<size_t>(w.size(), 1) * sizeof(int4)));
+    HIPCHK(ctx->sym_work[pi].ensure(std::max<size_t>(w.size(), 1) * sizeof(int4)));
     if (!w.empty())
-        HIPCHK(hipMemcpyAsync(ctx->sym_work.p, w.data(), w.size() * sizeof(int4),
+        HIPCHK(hipMemcpyAsync(ctx->sym_work[pi].p, w.data(), w.size() * sizeof(int4),
                               hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
-    ctx->sym_work_N = N;
-    ctx->sym_work_R = R;
-    ctx->sym_n_work = (int)w.size();
+    ctx->sym_work_N[pi] = N;
+    ctx->sym_work_R[pi] = R;
+    ctx->sym_n_work[pi] = (int)w.size();
     return 0;
 }
 
@@ -244,7 +245,7 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
     const bool sym = shape < 0;
     int used = 1;
     if (sym) {
-        TRY(sym_worklist(ctx, s, N, -shape));
+        TRY(sym_worklist(ctx, s, N, -shape, precision));
         HIPCHK(ctx->partial.ensure((size_t)3 * N * sizeof(double)));
     } else {
         HIPCHK(ctx->partial.ensure((size_t)shape * 3 * N * sizeof(double)));
@@ -258,7 +259,8 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
     }
     if (sym)
         arb::pair_sym(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a,
-                      ctx->sym_work.as<int4>(), ctx->sym_n_work, ctx->partial.as<double>());
+                      ctx->sym_work[precision == ARB_FP32C].as<int4>(),
+                      ctx->sym_n_work[precision == ARB_FP32C], ctx->partial.as<double>());
     else
         used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, shape,
                                  ctx->partial.as<double>());

@@ -228,8 +228,12 @@ struct arb_ctx {
     // are source slices of the target-parallel kernel, values < 0 select the
     // symmetric kernel with -value source tiles per work item
     std::map<int64_t, int> slice_cache;
-    arb::DevBuf sym_work;
-    int sym_work_N = -1, sym_work_R = -1, sym_n_work = 0;
+    // symmetric-kernel work lists, one per precision [ARB_FP64, ARB_FP32C] (each
+    // keyed by size and tiles per item), so that a graph captured for one
+    // precision never reads a list rebuilt for the other
+    arb::DevBuf sym_work[2];
+    int sym_work_N[2] = {-1, -1}, sym_work_R[2] = {-1, -1};
+    int sym_n_work[2] = {0, 0};
     bool pc_built = false;
     bool pc_learned = false;
     bool pc_lcorr = false;  // learned body mobility with the consistent blob-block correction

@@ -39,11 +39,13 @@ __device__ __forceinline__ void sym_free(T dx, T dy, T dz, T r2, T rinv, T lix, 
     const T rinv2 = rinv * rinv;
     T c1 = rinv * fma(c.k1, rinv2, T(1));
     T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
+    ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
     if (r2 <= c.four_a2) {
         const T r = r2 * rinv;
         c1 = fma(-c.n2, r, c.n1);
         c2 = rinv * c.n3;
     }
+    ARB_END_IF_ANY
     const T tj = c2 * fma(dx, ljx, fma(dy, ljy, dz * ljz));
     const T ti = c2 * fma(dx, lix, fma(dy, liy, dz * liz));
     fx = fma(c1, ljx, fma(tj, dx, fx));

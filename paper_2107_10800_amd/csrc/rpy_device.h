@@ -33,6 +33,15 @@ constexpr CoefF kUnitCoefF{2.f / 3.f, 2.f, 4.f / 3.f, 3.f / 8.f, 1.f / 8.f, 1.f,
 
 __device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Overlapping pairs (r <= 2a) are rare away from a body's own blobs, so the
+// overlap coefficients are computed only when some lane of the wavefront has
+// one: a wave vote and a real branch.  The empty volatile asm keeps the branch
+// (speculated, the overlap path would be paid by every pair as selects).
+#define ARB_IF_ANY_OVERLAP(cond) \
+    if (__any(cond)) {           \
+        asm volatile("" ::: "memory");
+#define ARB_END_IF_ANY }
+
 // accumulate M_free(r) lambda (units 1/(8 pi eta))
 template <class T, class C>
 __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T ly, T lz,
@@ -40,11 +49,13 @@ __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T
     T rinv2 = rinv * rinv;
     T c1 = rinv * fma(c.k1, rinv2, T(1));
     T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
+    ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
     if (r2 <= c.four_a2) {
         T r = r2 * rinv;
         c1 = fma(-c.n2, r, c.n1);
         c2 = rinv * c.n3;
     }
+    ARB_END_IF_ANY
     T rl = fma(dx, lx, fma(dy, ly, dz * lz));
     T t = c2 * rl;
     ax = fma(c1, lx, fma(t, dx, ax));
@@ -75,10 +86,12 @@ __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, 
     const T rinv2 = rinv * rinv;
     T c1 = rinv * fma(k.k1, rinv2, T(1));
     T c2 = rinv * rinv2 * fma(-k.k2, rinv2, T(1));
+    ARB_IF_ANY_OVERLAP(r2 <= k.four_a2)
     if (r2 <= k.four_a2) {
         c1 = fma(-k.n2, r2 * rinv, k.n1);
         c2 = rinv * k.n3;
     }
+    ARB_END_IF_ANY
     const T s = Ri * Ri;
     const T Ri3 = Ri * s;
     const T Ri5 = Ri3 * s;
