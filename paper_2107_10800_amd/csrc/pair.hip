@@ -29,16 +29,17 @@
 
 namespace arb {
 
-// p64: positions; hi + lo: positions / a split into two floats
+// p64: positions (w = 2 z); hi + lo: positions / a split into two floats (hi.w =
+// 2 hi.z, the doubled source height the wall image uses)
 __global__ void prep_positions_kernel(int N, const double *__restrict__ pos, double inv_a,
                                       double4 *__restrict__ p64, float4 *__restrict__ hi,
                                       float4 *__restrict__ lo) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
+    p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 2.0 * pos[3 * i + 2]);
     const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
     const float xh = (float)x, yh = (float)y, zh = (float)z;
-    hi[i] = make_float4(xh, yh, zh, 0.f);
+    hi[i] = make_float4(xh, yh, zh, 2.f * zh);
     lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
                         (float)(z - (double)zh), 0.f);
 }
@@ -83,11 +84,12 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
                 const float dz = (th.z - sh.z) + (tl.z - sl.z);
                 const float dxy2 = fmaf(dx, dx, dy * dy);
                 const float r2 = fmaf(dz, dz, dxy2);
-                const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+                const float rinv = rsq_f32(r2);
                 if (WALL) {
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                    const PairCoef<float> w = wall_pair_coef<float>(r2, rinv, zi, sh.z, Rz, Ri, c);
+                    const PairCoef<float> w =
+                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, Rz, Ri, c);
                     wall_pair_apply<float>(w, w.c, w.d, dx, dy, dz, Rz, L.x, L.y, L.z, ax, ay, az);
                 } else {
                     rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
@@ -138,11 +140,12 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
             const double dx = ti.x - sj.x, dy = ti.y - sj.y, dz = ti.z - sj.z;
             const double dxy2 = fma(dx, dx, dy * dy);
             const double r2 = fma(dz, dz, dxy2);
-            const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+            const double rinv = rsq_f64(r2);
             if (WALL) {
                 const double Rz = ti.z + sj.z;
                 const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
-                const PairCoef<double> w = wall_pair_coef<double>(r2, rinv, ti.z, sj.z, Rz, Ri, c);
+                const PairCoef<double> w =
+                    wall_pair_coef<double>(r2, rinv, ti.z, sj.z, sj.w, Rz, Ri, c);
                 wall_pair_apply<double>(w, w.c, w.d, dx, dy, dz, Rz, lx, ly, lz, ux, uy, uz);
             } else {
                 rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);

@@ -41,9 +41,9 @@ __device__ __forceinline__ void sym_free(T dx, T dy, T dz, T r2, T rinv, T lix, 
     T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
     ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
     if (r2 <= c.four_a2) {
-        const T r = r2 * rinv;
-        c1 = fma(-c.n2, r, c.n1);
-        c2 = rinv * c.n3;
+        const T rv = r2 > T(0) ? rinv : T(0);
+        c1 = fma(-c.n2, r2 * rv, c.n1);
+        c2 = rv * c.n3;
     }
     ARB_END_IF_ANY
     const T tj = c2 * fma(dx, ljx, fma(dy, ljy, dz * ljz));
@@ -71,7 +71,7 @@ __device__ __forceinline__ Blob32 load_blob(int i, int N, const float4 *__restri
         b.lam = make_float4((float)lam[3 * (size_t)i], (float)lam[3 * (size_t)i + 1],
                             (float)lam[3 * (size_t)i + 2], 0.f);
     } else {
-        b.hi = make_float4(1e6f, 1e6f, 10.f, 0.f);
+        b.hi = make_float4(1e6f, 1e6f, 10.f, 20.f);
         b.lo = make_float4(0.f, 0.f, 0.f, 0.f);
         b.lam = make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -90,7 +90,8 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                                                             const int4 *__restrict__ work,
                                                             double *__restrict__ u) {
     constexpr CoefF c = kUnitCoefF;
-    __shared__ float4 s_hi[64], s_lo[64], s_lam[64];
+    // the source tile twice over, so the rotation reads lane + step without wrapping
+    __shared__ float4 s_hi[128], s_lo[128], s_lam[128];
     __shared__ float comb[4][3][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int4 it = work[blockIdx.x];
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
         __syncthreads();
         if (tid < 64) {
             const Blob32 s = load_blob(J * 64 + tid, N, hi, lo, lam);
-            s_hi[tid] = s.hi;
-            s_lo[tid] = s.lo;
-            s_lam[tid] = s.lam;
+            s_hi[tid] = s_hi[tid + 64] = s.hi;
+            s_lo[tid] = s_lo[tid + 64] = s.lo;
+            s_lam[tid] = s_lam[tid + 64] = s.lam;
         }
         __syncthreads();
         float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -119,11 +120,12 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                 const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
                 const float dxy2 = fmaf(dx, dx, dy * dy);
                 const float r2 = fmaf(dz, dz, dxy2);
-                const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+                const float rinv = rsq_f32(r2);
                 if (WALL) {
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                    const PairCoef<float> q = wall_pair_coef<float>(r2, rinv, zi, sh.z, Rz, Ri, c);
+                    const PairCoef<float> q =
+                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, Rz, Ri, c);
                     wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                 } else {
                     rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
@@ -133,18 +135,19 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
             float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll 2
             for (int st = 0; st < 64; ++st) {
-                const int k = (lane + st) & 63;
+                const int k = lane + st;
                 const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
                 const float dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
                 const float dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
                 const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
                 const float dxy2 = fmaf(dx, dx, dy * dy);
                 const float r2 = fmaf(dz, dz, dxy2);
-                const float rinv = r2 > 0.f ? rsq_f32(r2) : 0.f;
+                const float rinv = rsq_f32(r2);
                 if (WALL) {
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                    const PairCoef<float> q = wall_pair_coef<float>(r2, rinv, zi, sh.z, Rz, Ri, c);
+                    const PairCoef<float> q =
+                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, Rz, Ri, c);
                     wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                     wall_pair_apply<float>(q, q.d, q.c, dx, dy, dz, Rz, t.lam.x, t.lam.y, t.lam.z,
                                            ax, ay, az);
@@ -188,7 +191,7 @@ __device__ __forceinline__ void load_blob64(int i, int N, const double4 *__restr
         p = p64[i];
         l = make_double4(lam[3 * (size_t)i], lam[3 * (size_t)i + 1], lam[3 * (size_t)i + 2], 0.0);
     } else {
-        p = make_double4(1e6, 1e6, 10.0, 0.0);
+        p = make_double4(1e6, 1e6, 10.0, 20.0);
         l = make_double4(0.0, 0.0, 0.0, 0.0);
     }
 }
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                                                            const double *__restrict__ lam,
                                                            const int4 *__restrict__ work,
                                                            CoefD c, double *__restrict__ u) {
-    __shared__ double4 s_p[64], s_l[64];
+    __shared__ double4 s_p[128], s_l[128];  // the source tile twice over
     __shared__ double comb[4][3][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int4 it = work[blockIdx.x];
@@ -211,7 +214,11 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int J = it.y; J < it.y + it.z; ++J) {
         __syncthreads();
-        if (tid < 64) load_blob64(J * 64 + tid, N, p64, lam, s_p[tid], s_l[tid]);
+        if (tid < 64) {
+            load_blob64(J * 64 + tid, N, p64, lam, s_p[tid], s_l[tid]);
+            s_p[tid + 64] = s_p[tid];
+            s_l[tid + 64] = s_l[tid];
+        }
         __syncthreads();
         if (diag) {
             for (int k = 0; k < 64; ++k) {
@@ -219,12 +226,12 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                 const double dx = tp.x - sp.x, dy = tp.y - sp.y, dz = tp.z - sp.z;
                 const double dxy2 = fma(dx, dx, dy * dy);
                 const double r2 = fma(dz, dz, dxy2);
-                const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+                const double rinv = rsq_f64(r2);
                 if (WALL) {
                     const double Rz = tp.z + sp.z;
                     const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                     const PairCoef<double> q =
-                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, Rz, Ri, c);
+                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, Rz, Ri, c);
                     wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                 } else {
                     rpy_free<double>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
@@ -233,17 +240,17 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
         } else {
             double ax = 0.0, ay = 0.0, az = 0.0;
             for (int st = 0; st < 64; ++st) {
-                const int k = (lane + st) & 63;
+                const int k = lane + st;
                 const double4 sp = s_p[k], L = s_l[k];
                 const double dx = tp.x - sp.x, dy = tp.y - sp.y, dz = tp.z - sp.z;
                 const double dxy2 = fma(dx, dx, dy * dy);
                 const double r2 = fma(dz, dz, dxy2);
-                const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+                const double rinv = rsq_f64(r2);
                 if (WALL) {
                     const double Rz = tp.z + sp.z;
                     const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                     const PairCoef<double> q =
-                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, Rz, Ri, c);
+                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, Rz, Ri, c);
                     wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                     wall_pair_apply<double>(q, q.d, q.c, dx, dy, dz, Rz, tl.x, tl.y, tl.z, ax, ay,
                                             az);

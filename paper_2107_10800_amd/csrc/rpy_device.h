@@ -42,7 +42,7 @@ __device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf
         asm volatile("" ::: "memory");
 #define ARB_END_IF_ANY }
 
-// accumulate M_free(r) lambda (units 1/(8 pi eta))
+// accumulate M_free(r) lambda (units 1/(8 pi eta)); rinv = 1/sqrt(r2), infinite at r = 0
 template <class T, class C>
 __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T ly, T lz,
                                          const C &c, T &ax, T &ay, T &az) {
@@ -51,9 +51,9 @@ __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T
     T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
     ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
     if (r2 <= c.four_a2) {
-        T r = r2 * rinv;
-        c1 = fma(-c.n2, r, c.n1);
-        c2 = rinv * c.n3;
+        const T rv = r2 > T(0) ? rinv : T(0);  // rinv = 1/sqrt(0) = inf for coincident blobs
+        c1 = fma(-c.n2, r2 * rv, c.n1);
+        c2 = rv * c.n3;
     }
     ARB_END_IF_ANY
     T rl = fma(dx, lx, fma(dy, ly, dz * lz));
@@ -79,8 +79,9 @@ struct PairCoef {
     T cA, c2, b, c, d, e, h2;
 };
 
+// rinv = 1/sqrt(r2) (infinite for coincident blobs), h2 = 2 zj, Rz = zi + zj
 template <class T, class C>
-__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, T Rz, T Ri,
+__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, T h2, T Rz, T Ri,
                                                       const C &k) {
     PairCoef<T> w;
     const T rinv2 = rinv * rinv;
@@ -88,8 +89,9 @@ __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, 
     T c2 = rinv * rinv2 * fma(-k.k2, rinv2, T(1));
     ARB_IF_ANY_OVERLAP(r2 <= k.four_a2)
     if (r2 <= k.four_a2) {
-        c1 = fma(-k.n2, r2 * rinv, k.n1);
-        c2 = rinv * k.n3;
+        const T rv = r2 > T(0) ? rinv : T(0);
+        c1 = fma(-k.n2, r2 * rv, k.n1);
+        c2 = rv * k.n3;
     }
     ARB_END_IF_ANY
     const T s = Ri * Ri;
@@ -100,7 +102,6 @@ __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, 
     const T q = zi * zj;
     const T a4s = k.a4 * s;
     const T RzRi5 = Rz * Ri5;
-    const T h2 = zj + zj;
     const T h2Ri3 = h2 * Ri3;
     const T a2 = k.a2;
     const T iA = fma(a4s, fma(T(-10.0 / 3.0), t, T(2.0 / 3.0)),
@@ -153,10 +154,11 @@ __device__ inline void rpy_block_f64(double dx, double dy, double dz, double zt,
                                      bool wall, const CoefD &c, double *B) {
     const double dxy2 = fma(dx, dx, dy * dy);
     const double r2 = fma(dz, dz, dxy2);
-    const double rinv = r2 > 0.0 ? rsq_f64(r2) : 0.0;
+    const double rinv = rsq_f64(r2);
     const double Rz = zt + zs;
     PairCoef<double> w{};
-    if (wall) w = wall_pair_coef<double>(r2, rinv, zt, zs, Rz, rsq_f64(fma(Rz, Rz, dxy2)), c);
+    if (wall)
+        w = wall_pair_coef<double>(r2, rinv, zt, zs, zs + zs, Rz, rsq_f64(fma(Rz, Rz, dxy2)), c);
     for (int col = 0; col < 3; ++col) {
         const double lx = col == 0, ly = col == 1, lz = col == 2;
         double ax = 0.0, ay = 0.0, az = 0.0;
