@@ -25,13 +25,15 @@ sys.path.insert(0, ROOT)
 
 # algorithmic flops counted from the kernel expressions (FMA = 2, add/sub/mul = 1,
 # reciprocal square root = 1; selects and compares 0; the Newton steps of the FP64
-# reciprocal square root not counted).  One-way: M_ij lambda_j for one ordered
-# pair (target-parallel kernel, and the pairs inside the 256-blob diagonal blocks of
-# the symmetric kernel).  Symmetric: one unordered pair applied both ways.
-FLOPS_ONE_WAY = {("f32c", True): 113, ("f32c", False): 45, ("f64", True): 107,
-                 ("f64", False): 39}
-FLOPS_SYM = {("f32c", True): 143, ("f32c", False): 63, ("f64", True): 137,
-             ("f64", False): 57}
+# reciprocal square root not counted; the overlap coefficients (r <= 2a), computed
+# only when a wavefront holds an overlapping pair, not counted).  One-way: M_ij
+# lambda_j for one ordered pair (target-parallel kernel, and the pairs inside the
+# 256-blob diagonal blocks of the symmetric kernel).  Symmetric: one unordered pair
+# applied both ways.
+FLOPS_ONE_WAY = {("f32c", True): 108, ("f32c", False): 41, ("f64", True): 102,
+                 ("f64", False): 35}
+FLOPS_SYM = {("f32c", True): 138, ("f32c", False): 59, ("f64", True): 132,
+             ("f64", False): 53}
 
 
 def algorithmic_flops(N, shape, prec="f32c", wall=True):
