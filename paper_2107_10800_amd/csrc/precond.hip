@@ -4,14 +4,15 @@
 //   pc_assemble  M_pp (m x m, row-major) from the same pair code as the mat-vec
 //   pc_potrf     M_pp = L L^T in place, blocked by 32 columns: the panel is
 //                factored in LDS, the trailing lower triangle updated in 64 x 64
-//                register tiles; the inverses of the 32 x 32 diagonal blocks of L
-//                are kept for the next step
+//                tiles on the FP64 matrix cores; the inverses of the 32 x 32
+//                diagonal blocks of L are kept for the next step
 //   pc_trtri     X = L^-1 by block forward substitution on the identity, one
 //                workgroup per (body, 32 columns), the block column held in LDS;
-//                every block step is a small GEMM because the diagonal blocks
-//                are applied through their stored inverses; X^T is kept in the
-//                strictly upper triangle
-//   pc_lauum     M_pp^-1 = X^T X, one workgroup per (body, 64 x 64 tile)
+//                every block step is a small GEMM on the matrix cores because
+//                the diagonal blocks are applied through their stored inverses;
+//                X^T is kept in the strictly upper triangle
+//   pc_lauum     M_pp^-1 = X^T X on the matrix cores, one workgroup per (body,
+//                64 x 64 tile)
 //   (bodies with more than 480 rows: pc_chol / pc_inverse, the unblocked
 //   right-looking versions, with X = L^-1 kept transposed in the upper triangle)
 //   pc_body      Z_p = M_pp^-1 K_p (m x 6), R_p = K_p^T Z_p, N~_p = R_p^+
@@ -224,6 +225,14 @@ constexpr int kNB = 32;          // block size of the blocked factorisation
 constexpr int kLd = kNB + 1;     // padded LDS row stride (doubles)
 constexpr int kFastMaxM = 480;   // largest body handled by the blocked kernels
 
+// FP64 matrix core, one wavefront: D (16 x 16) += A (16 x 4) B (4 x 16).  Lane l
+// supplies a = A[l % 16][l / 16] and b = B[l / 16][l % 16] and holds
+// D[4 e + l / 16][l % 16] in element e of the accumulator.
+typedef double mfma_acc __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mfma_acc mfma_f64_16x16x4(double a, double b, mfma_acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // offset (doubles) of body p's diagonal-block inverses: 1024 per 32-row block
 __device__ __forceinline__ int64_t dinv_offset(const int *blob_off, int p) {
     return 32 * 3 * (int64_t)blob_off[p] + 1024 * (int64_t)p;
@@ -298,50 +307,57 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
 #pragma unroll
             for (int i = 0; i < kNB; ++i) Db[i * kNB + c] = z[i];
         }
-        // trailing update of the lower triangle: A_ij -= sum_t L_it L_jt
+        // trailing update of the lower triangle, A_ij -= sum_t L_it L_jt, in 64 x 64
+        // tiles: wavefront w takes the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 matrix-core
+        // tiles; columns t >= nb of the panel are zero
         const int t0 = k0 + nb, nt = m - t0;
         if (nt > 0) {
             const int ntile = (nt + 63) / 64;
-            const int ty = tid / 16, tx = tid % 16;
+            const int w = tid >> 6, l = tid & 63, wr = w >> 1, wc = w & 1;
+            const int kt = (nb + 3) & ~3;
             for (int tile = 0; tile < ntile * (ntile + 1) / 2; ++tile) {
                 int bi = 0;
                 while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
                 const int bj = tile - bi * (bi + 1) / 2;
-                const int i0 = 64 * bi + ty, j0 = 64 * bj + 4 * tx;
-                int ri[4], rj[4];
+                const int i0 = 64 * bi + 32 * wr, j0 = 64 * bj + 32 * wc;
+                int ra[2], rb[2];  // panel rows of this lane's A and B operands
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    ri[r] = nb + min(i0 + 16 * r, nt - 1);
-                    rj[r] = nb + min(j0 + r, nt - 1);
+                for (int q = 0; q < 2; ++q) {
+                    ra[q] = nb + min(i0 + 16 * q + (l & 15), nt - 1);
+                    rb[q] = nb + min(j0 + 16 * q + (l & 15), nt - 1);
                 }
-                double cur[4][4];  // issued before the products: the loads overlap them
+                double cur[2][2][4];  // issued before the products: the loads overlap them
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        cur[r][c] = A[(size_t)(t0 + ri[r] - nb) * m + t0 + rj[c] - nb];
-                double acc[4][4] = {};
-                for (int t = 0; t < nb; ++t) {
-                    double a[4], b[4];
+                    for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        a[r] = Pn[ri[r] * kLd + t];
-                        b[r] = Pn[rj[r] * kLd + t];
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+                        for (int e = 0; e < 4; ++e) {
+                            const int i = min(i0 + 16 * ti + 4 * e + (l >> 4), nt - 1);
+                            const int j = min(j0 + 16 * tj + (l & 15), nt - 1);
+                            cur[ti][tj][e] = A[(size_t)(t0 + i) * m + t0 + j];
+                        }
+                mfma_acc acc[2][2] = {};
+                for (int t = 0; t < kt; t += 4) {
+                    const int tc = t + (l >> 4);
+                    const double a0 = Pn[ra[0] * kLd + tc], a1 = Pn[ra[1] * kLd + tc];
+                    const double b0 = Pn[rb[0] * kLd + tc], b1 = Pn[rb[1] * kLd + tc];
+                    acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
+                    acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
+                    acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
+                    acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + 16 * r;
+                for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int j = j0 + c;
-                        if (i < nt && j <= i) A[(size_t)(t0 + i) * m + t0 + j] = cur[r][c] - acc[r][c];
-                    }
-                }
+                    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int i = i0 + 16 * ti + 4 * e + (l >> 4);
+                            const int j = j0 + 16 * tj + (l & 15);
+                            if (i < nt && j <= i)
+                                A[(size_t)(t0 + i) * m + t0 + j] = cur[ti][tj][e] - acc[ti][tj][e];
+                        }
             }
         }
     }
@@ -385,47 +401,46 @@ __global__ __launch_bounds__(256) void pc_trtri_kernel(const int *__restrict__ b
     if (cb >= nbk) return;
     double *A = mats + mat_off[p];
     const double *Dg = dinv + dinv_offset(blob_off, p);
-    const int tid = threadIdx.x, r = tid / 8, c4 = 4 * (tid % 8);
+    // wavefront w holds the 16 x 16 tile (w / 2, w % 2) of each 32 x 32 block step
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int wr = 16 * (w >> 1), wc = 16 * (w & 1);
+    const int lr = l & 15, lk = l >> 4;  // operand row and k offset of this lane
     const int c0 = kNB * cb;
     for (int i = cb; i < nbk; ++i) {
         double dreg[4], nxt[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) dreg[e] = Dg[(size_t)i * kNB * kNB + tid + 256 * e];
         if (cb < i) load_block(nxt, A, m, kNB * i, kNB * cb);
-        double acc[4];
+        mfma_acc acc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = (kNB * i + r == c0 + c4 + q) ? 1.0 : 0.0;
+        for (int e = 0; e < 4; ++e) acc[e] = (kNB * i + wr + 4 * e + lk == c0 + wc + lr) ? 1.0 : 0.0;
         for (int k = cb; k < i; ++k) {
             __syncthreads();
             store_block(Ls, nxt);
             __syncthreads();
             if (k + 1 < i) load_block(nxt, A, m, kNB * i, kNB * (k + 1));
-            const double *Xk = X + (size_t)kNB * k * kLd + c4;
-            for (int t = 0; t < kNB; ++t) {
-                const double a = Ls[r][t];
+            const double *Xk = X + (size_t)kNB * k * kLd + wc + lr;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = fma(-a, Xk[t * kLd + q], acc[q]);
-            }
+            for (int kk = 0; kk < kNB; kk += 4)
+                acc = mfma_f64_16x16x4(-Ls[wr + lr][kk + lk], Xk[(kk + lk) * kLd], acc);
         }
-        double *Xi = X + (size_t)kNB * i * kLd + c4;
+        double *Xi = X + (size_t)kNB * i * kLd;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = acc[q];
+        for (int e = 0; e < 4; ++e) Xi[(wr + 4 * e + lk) * kLd + wc + lr] = acc[e];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int idx = tid + 256 * e;
             Ls[idx / kNB][idx % kNB] = dreg[e];
         }
         __syncthreads();
-        double y[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int t = 0; t < kNB; ++t) {
-            const double d = Ls[r][t];
+        mfma_acc y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) y[q] = fma(d, Xi[t * kLd + q], y[q]);
-        }
+        for (int kk = 0; kk < kNB; kk += 4)
+            y = mfma_f64_16x16x4(Ls[wr + lr][kk + lk], Xi[(kk + lk) * kLd + wc + lr], y);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Xi[r * kLd + q] = y[q];
+        for (int e = 0; e < 4; ++e) Xi[(wr + 4 * e + lk) * kLd + wc + lr] = y[e];
     }
     __syncthreads();
     // X[i][c0 + c] for i > c0 + c  ->  A[(c0 + c) m + i]  (consecutive i: coalesced)
@@ -462,8 +477,11 @@ __global__ __launch_bounds__(256) void pc_lauum_kernel(const int *__restrict__ b
     const double *A = mats + mat_off[p];
     const double *Dg = dinv + dinv_offset(blob_off, p);
     double *Mi = minv + mat_off[p];
-    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    const int tid = threadIdx.x;
     const int kl = tid & 31, r0 = tid >> 5;  // a thread stages column kl of rows r0 + 8e
+    // wavefront w computes the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 matrix-core tiles
+    const int w = tid >> 6, l = tid & 63, wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    const int lr = l & 15, lk = l >> 4;
     // U[row][kk]: 0 below the diagonal, 1/L_kk on it, X[kk][row] above
     auto u_at = [&](int row, int kk) -> double {
         if (row >= m || kk >= m || kk < row) return 0.0;
@@ -476,7 +494,7 @@ __global__ __launch_bounds__(256) void pc_lauum_kernel(const int *__restrict__ b
         na[e] = u_at(I0 + r0 + 8 * e, J0 + kl);
         nb8[e] = u_at(J0 + r0 + 8 * e, J0 + kl);
     }
-    double acc[4][4] = {};
+    mfma_acc acc[2][2] = {};
     for (int k0 = J0; k0 < m; k0 += kNB) {
         __syncthreads();
 #pragma unroll
@@ -492,32 +510,29 @@ __global__ __launch_bounds__(256) void pc_lauum_kernel(const int *__restrict__ b
                 nb8[e] = u_at(J0 + r0 + 8 * e, k0 + kNB + kl);
             }
         }
-#pragma unroll 4
-        for (int t = 0; t < kNB; ++t) {
-            double a[4], b[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = Ua[ty + 16 * q][t];
-                b[q] = Ub[4 * tx + q][t];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[q][c] = fma(a[q], b[c], acc[q][c]);
+        for (int kk = 0; kk < kNB; kk += 4) {
+            const double a0 = Ua[wr + lr][kk + lk], a1 = Ua[wr + 16 + lr][kk + lk];
+            const double b0 = Ub[wc + lr][kk + lk], b1 = Ub[wc + 16 + lr][kk + lk];
+            acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
+            acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
+            acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
+            acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
         }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = I0 + ty + 16 * q;
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int j = J0 + 4 * tx + c;
-            if (i < m && j < m) {
-                Mi[(size_t)i * m + j] = acc[q][c];
-                Mi[(size_t)j * m + i] = acc[q][c];
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = I0 + wr + 16 * ti + 4 * e + lk;
+                const int j = J0 + wc + 16 * tj + lr;
+                if (i < m && j < m) {
+                    Mi[(size_t)i * m + j] = acc[ti][tj][e];
+                    Mi[(size_t)j * m + i] = acc[ti][tj][e];
+                }
             }
-        }
-    }
 }
 
 // restore L's diagonal (for inspection) once the inverse no longer needs X
