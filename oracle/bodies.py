@@ -44,8 +44,28 @@ def K_matrix(r, q, blob_offset):
     return K
 
 
-def constraint_rows(wl, q=None, theta=None):
-    """Dense C (Nc x 6M) and B (Nc) of the velocity constraints C U = B.
+def K_apply(r, q, blob_offset, U):
+    """(K U)_i = u_p + w_p x (r_i - q_p) for every blob i of body p (Eq. no-slip), (N, 3)."""
+    body = body_of_blob(blob_offset)
+    U = np.asarray(U, float).reshape(-1, 6)
+    return U[body, :3] + np.cross(U[body, 3:], np.asarray(r) - np.asarray(q)[body])
+
+
+def KT_apply(r, q, blob_offset, lam):
+    """(K^T lambda)_p = (sum_i lambda_i, sum_i (r_i - q_p) x lambda_i) over the blobs of
+    body p (Eq. balance), (M, 6)."""
+    body = body_of_blob(blob_offset)
+    lam = np.asarray(lam, float).reshape(-1, 3)
+    M = len(q)
+    out = np.zeros((M, 6))
+    np.add.at(out[:, :3], body, lam)
+    np.add.at(out[:, 3:], body, np.cross(np.asarray(r) - np.asarray(q)[body], lam))
+    return out
+
+
+def constraint_rows(wl, q=None, theta=None, sparse=False):
+    """C (Nc x 6M) and B (Nc) of the velocity constraints C U = B; C dense, or a
+    scipy CSR matrix with sparse=True.
 
     Link n (Eq. dg): u_p + w_p x l_p - u_q - w_q x l_q = B_n with lab arms
     l = R(theta) dl and B_n = R_q dldot_q - R_p dldot_p.  Row m keeps
@@ -58,7 +78,13 @@ def constraint_rows(wl, q=None, theta=None):
     R = rotation_matrix(theta)
     M = len(q)
     nc = int(wl.nproj.sum()) + len(wl.row_rhs)
-    C = np.zeros((nc, 6 * M))
+    rows, cols, vals = [], [], []
+
+    def put(k, col0, v):  # C[k, col0:col0 + 3] += v
+        rows.extend((k, k, k))
+        cols.extend((col0, col0 + 1, col0 + 2))
+        vals.extend(v)
+
     B = np.zeros(nc)
     k = 0
     for n in range(len(wl.pq)):
@@ -72,23 +98,28 @@ def constraint_rows(wl, q=None, theta=None):
             Bn = Bn + wl.dldot_q[n]
         for m in range(int(wl.nproj[n])):
             d = R[p] @ wl.proj[n, m]
-            C[k, 6 * p:6 * p + 3] += d
-            C[k, 6 * p + 3:6 * p + 6] += np.cross(lp, d)
+            put(k, 6 * p, d)
+            put(k, 6 * p + 3, np.cross(lp, d))
             if qq >= 0:
-                C[k, 6 * qq:6 * qq + 3] -= d
-                C[k, 6 * qq + 3:6 * qq + 6] -= np.cross(lq, d)
+                put(k, 6 * qq, -d)
+                put(k, 6 * qq + 3, -np.cross(lq, d))
             B[k] = d @ Bn
             k += 1
     for j in range(len(wl.row_rhs)):
         p, qq = int(wl.row_pq[j, 0]), int(wl.row_pq[j, 1])
         c = wl.row_coef[j].reshape(4, 3)
-        C[k, 6 * p:6 * p + 3] += R[p] @ c[0]
-        C[k, 6 * p + 3:6 * p + 6] += R[p] @ c[1]
+        put(k, 6 * p, R[p] @ c[0])
+        put(k, 6 * p + 3, R[p] @ c[1])
         if qq >= 0:
-            C[k, 6 * qq:6 * qq + 3] += R[p] @ c[2]
-            C[k, 6 * qq + 3:6 * qq + 6] += R[p] @ c[3]
+            put(k, 6 * qq, R[p] @ c[2])
+            put(k, 6 * qq + 3, R[p] @ c[3])
         B[k] = wl.row_rhs[j]
         k += 1
+    if sparse:
+        from scipy.sparse import coo_matrix
+        return coo_matrix((vals, (rows, cols)), shape=(nc, 6 * M)).tocsr(), B
+    C = np.zeros((nc, 6 * M))
+    np.add.at(C, (np.asarray(rows, int), np.asarray(cols, int)), np.asarray(vals, float))
     return C, B
 
 

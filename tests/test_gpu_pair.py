@@ -164,3 +164,23 @@ def test_blob_radius_and_viscosity(kind, prec):
         arb.arb_destroy(c)
     uo = rpy.mobility_apply(cl["pos"], cl["lam"], a, eta, True)
     assert rel(u, uo) <= TOL[prec]
+
+
+@pytest.mark.parametrize("kind", [arb.ARB_PAIR_TARGET, arb.ARB_PAIR_SYMMETRIC])
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_coincident_blobs_and_empty_input(kind, prec):
+    # two distinct blobs at one position (r = 0 off the diagonal: the self-mobility
+    # block) in the same and in different tiles; and N = 0
+    cl = W.random_blobs(300, seed=41, box=9.0)
+    pos = cl["pos"].copy()
+    pos[7] = pos[3]          # same 64-blob tile
+    pos[250] = pos[10]       # different tiles and I-blocks
+    c = arb.arb_create(precision=prec, wall=True, pair_kernel=kind)
+    try:
+        u = arb.arb_rpy_apply(c, pos, cl["lam"])
+        assert arb.arb_rpy_apply(c, np.zeros((0, 3)), np.zeros(0)).size == 0
+    finally:
+        arb.arb_destroy(c)
+    uo = rpy.mobility_apply(pos, cl["lam"], 1.0, 1.0, True)
+    assert np.all(np.isfinite(u))
+    assert rel(u, uo) <= TOL[prec]

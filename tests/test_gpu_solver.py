@@ -276,3 +276,47 @@ def test_graph_replays_match_plain_launches(name, prec):
         assert rc == ref[0] and info["iterations"] == ref[4]["iterations"]
         assert np.array_equal(U, ref[1]) and np.array_equal(phi, ref[2])
         assert np.array_equal(lam, ref[3])
+
+
+@pytest.mark.parametrize("cfg", ["bacteria1024", "diatoms256"])
+def test_full_size_solve_sampled(cfg):
+    # the benchmark's FP32 solves at full size: the returned iterate meets 1e-6 with
+    # the library's FP64 product, and that product matches the oracle on sampled
+    # blob rows and on every body and constraint row
+    from oracle import rpy
+
+    wl = W.bacteria(n_bact=1024, seed=3) if cfg == "bacteria1024" else W.diatoms()
+    N, M = wl.N, wl.M
+    print(f"full size {cfg}: N={N} M={M} Nc={wl.n_rows}", flush=True)
+    c = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-6, restart=100, max_iter=1000)
+    try:
+        rc, U, phi, lam, info = arb.arb_solve(c, wl.F, u_slip=wl.u_slip)
+    finally:
+        arb.arb_destroy(c)
+    assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
+    assert info["rel_residual_fp64"] <= 1e-6
+    y = np.concatenate([lam.ravel(), U.ravel(), phi])
+    c64 = arb.context_for(wl, precision=arb.ARB_FP64)
+    try:
+        Ay = arb.arb_system_apply(c64, y)
+    finally:
+        arb.arb_destroy(c64)
+    Cs, B = bodies.constraint_rows(wl, sparse=True)
+    us = np.zeros(3 * N) if wl.u_slip is None else wl.u_slip.ravel()
+    b = np.concatenate([us, -wl.F.ravel(), B])
+    res = np.linalg.norm(Ay - b) / np.linalg.norm(b)
+    print(f"  {info['iterations']} iterations, residual {res:.2e}", flush=True)
+    assert res <= 1.01e-6
+    r = bodies.blob_positions(wl.q, wl.theta, wl.r_ref, wl.blob_offset)
+    KU = bodies.K_apply(r, wl.q, wl.blob_offset, U)
+    tg = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(5).integers(0, N, 24)]))
+    Ml = rpy.mobility_apply(r, lam, wl.a, wl.eta, wl.wall, targets=tg)
+    Ml_gpu = Ay[:3 * N].reshape(N, 3)[tg] + KU[tg]
+    assert rel(Ml_gpu, Ml) <= 1e-12
+    KTl = bodies.KT_apply(r, wl.q, wl.blob_offset, lam).ravel()
+    CTp = Cs.T @ phi
+    body_rows = Ay[3 * N:3 * N + 6 * M]
+    scale = np.linalg.norm(KTl) + np.linalg.norm(CTp)
+    assert np.linalg.norm(body_rows - (-KTl + CTp)) <= 1e-12 * scale
+    CU = Cs @ U.ravel()
+    assert np.linalg.norm(Ay[3 * N + 6 * M:] - CU) <= 1e-12 * np.linalg.norm(CU)

@@ -95,3 +95,20 @@ def test_printed_system_sizes():
         assert n == c["n"], c["cite"]
     for c in g["ratios"]:
         assert abs(3 * c["links"] / (6 * c["bodies"]) - c["ratio"]) < 0.005
+
+
+def test_matrix_free_rigid_operators_match_dense():
+    # K U, K^T lambda and the sparse C of the oracle against its dense K and C
+    wl = W.bacteria(n_bact=3, side=50.0, seed=31)
+    r = bodies.blob_positions(wl.q, wl.theta, wl.r_ref, wl.blob_offset)
+    K = bodies.K_matrix(r, wl.q, wl.blob_offset)
+    rng = np.random.default_rng(8)
+    U = rng.standard_normal(6 * wl.M)
+    lam = rng.standard_normal(3 * wl.N)
+    assert np.allclose(bodies.K_apply(r, wl.q, wl.blob_offset, U).ravel(), K @ U,
+                       rtol=0, atol=1e-13 * np.abs(K @ U).max())
+    assert np.allclose(bodies.KT_apply(r, wl.q, wl.blob_offset, lam).ravel(), K.T @ lam,
+                       rtol=0, atol=1e-13 * np.abs(K.T @ lam).max())
+    C, B = bodies.constraint_rows(wl)
+    Cs, Bs = bodies.constraint_rows(wl, sparse=True)
+    assert np.array_equal(Cs.toarray(), C) and np.array_equal(Bs, B)
