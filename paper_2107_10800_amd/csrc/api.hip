@@ -304,10 +304,12 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
+        // the fastest of 4 timed runs per shape (after one untimed), so that a
+        // single slow run does not decide
         float bt = 1e30f;
         for (int c : cand) {
-            float tsum = 0.f;
-            for (int rep = 0; rep < 3; ++rep) {
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 5; ++rep) {
                 HIPCHK(hipEventRecord(e0, s));
                 TRY(run_pair(ctx, s, N, p64, hi, lo, lam, ctx->tune_out.as<double>(), nullptr,
                              nullptr, nullptr, precision, wall, c));
@@ -315,10 +317,10 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) tsum += ms;
+                if (rep > 0) tmin = std::min(tmin, ms);
             }
-            if (tsum < bt) {
-                bt = tsum;
+            if (tmin < bt) {
+                bt = tmin;
                 best = c;
             }
         }

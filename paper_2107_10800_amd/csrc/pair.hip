@@ -29,8 +29,8 @@
 
 namespace arb {
 
-// p64: positions (w = 2 z); hi + lo: positions / a split into two floats (hi.w =
-// 2 hi.z, the doubled source height the wall image uses)
+// p64: positions (w = 2 z); hi + lo: positions / a split into two floats, with
+// hi.w = 2 hi.z and lo.w = -(2 hi.z)^2, the source-height terms of the wall image
 __global__ void prep_positions_kernel(int N, const double *__restrict__ pos, double inv_a,
                                       double4 *__restrict__ p64, float4 *__restrict__ hi,
                                       float4 *__restrict__ lo) {
@@ -39,9 +39,10 @@ __global__ void prep_positions_kernel(int N, const double *__restrict__ pos, dou
     p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 2.0 * pos[3 * i + 2]);
     const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
     const float xh = (float)x, yh = (float)y, zh = (float)z;
-    hi[i] = make_float4(xh, yh, zh, 2.f * zh);
+    const float h2 = 2.f * zh;
+    hi[i] = make_float4(xh, yh, zh, h2);
     lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
-                        (float)(z - (double)zh), 0.f);
+                        (float)(z - (double)zh), -(h2 * h2));
 }
 
 constexpr int kRun = 32;  // sources per float partial sum in the FP32C kernel
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
                     const PairCoef<float> w =
-                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, Rz, Ri, c);
+                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, sl.w, Rz, Ri, c);
                     wall_pair_apply<float>(w, w.c, w.d, dx, dy, dz, Rz, L.x, L.y, L.z, ax, ay, az);
                 } else {
                     rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
                 const double Rz = ti.z + sj.z;
                 const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                 const PairCoef<double> w =
-                    wall_pair_coef<double>(r2, rinv, ti.z, sj.z, sj.w, Rz, Ri, c);
+                    wall_pair_coef<double>(r2, rinv, ti.z, sj.z, sj.w, -(sj.w * sj.w), Rz, Ri, c);
                 wall_pair_apply<double>(w, w.c, w.d, dx, dy, dz, Rz, lx, ly, lz, ux, uy, uz);
             } else {
                 rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);

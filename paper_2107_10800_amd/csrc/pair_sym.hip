@@ -36,9 +36,9 @@ template <class T, class C>
 __device__ __forceinline__ void sym_free(T dx, T dy, T dz, T r2, T rinv, T lix, T liy, T liz,
                                          T ljx, T ljy, T ljz, const C &c, T &fx, T &fy, T &fz,
                                          T &ax, T &ay, T &az) {
-    const T rinv2 = rinv * rinv;
-    T c1 = rinv * fma(c.k1, rinv2, T(1));
-    T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
+    const T rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+    T c1 = fma(c.k1, rinv3, rinv);
+    T c2 = fma(-c.k2, rinv3 * rinv2, rinv3);
     ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
     if (r2 <= c.four_a2) {
         const T rv = r2 > T(0) ? rinv : T(0);
@@ -72,7 +72,7 @@ __device__ __forceinline__ Blob32 load_blob(int i, int N, const float4 *__restri
                             (float)lam[3 * (size_t)i + 2], 0.f);
     } else {
         b.hi = make_float4(1e6f, 1e6f, 10.f, 20.f);
-        b.lo = make_float4(0.f, 0.f, 0.f, 0.f);
+        b.lo = make_float4(0.f, 0.f, 0.f, -400.f);
         b.lam = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     return b;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
                     const PairCoef<float> q =
-                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, Rz, Ri, c);
+                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, sl.w, Rz, Ri, c);
                     wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                 } else {
                     rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
                     const PairCoef<float> q =
-                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, Rz, Ri, c);
+                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, sl.w, Rz, Ri, c);
                     wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                     wall_pair_apply<float>(q, q.d, q.c, dx, dy, dz, Rz, t.lam.x, t.lam.y, t.lam.z,
                                            ax, ay, az);
@@ -231,7 +231,8 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                     const double Rz = tp.z + sp.z;
                     const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                     const PairCoef<double> q =
-                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, Rz, Ri, c);
+                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, -(sp.w * sp.w), Rz,
+                                               Ri, c);
                     wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                 } else {
                     rpy_free<double>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
@@ -250,7 +251,8 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                     const double Rz = tp.z + sp.z;
                     const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                     const PairCoef<double> q =
-                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, Rz, Ri, c);
+                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, -(sp.w * sp.w), Rz,
+                                               Ri, c);
                     wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                     wall_pair_apply<double>(q, q.d, q.c, dx, dy, dz, Rz, tl.x, tl.y, tl.z, ax, ay,
                                             az);

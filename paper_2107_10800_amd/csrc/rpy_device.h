@@ -46,9 +46,9 @@ __device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf
 template <class T, class C>
 __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T ly, T lz,
                                          const C &c, T &ax, T &ay, T &az) {
-    T rinv2 = rinv * rinv;
-    T c1 = rinv * fma(c.k1, rinv2, T(1));
-    T c2 = rinv * rinv2 * fma(-c.k2, rinv2, T(1));
+    const T rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+    T c1 = fma(c.k1, rinv3, rinv);            // (1 + k1/r^2)/r
+    T c2 = fma(-c.k2, rinv3 * rinv2, rinv3);  // (1 - k2/r^2)/r^3
     ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
     if (r2 <= c.four_a2) {
         const T rv = r2 > T(0) ? rinv : T(0);  // rinv = 1/sqrt(0) = inf for coincident blobs
@@ -76,17 +76,18 @@ __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T
 // and the l term.
 template <class T>
 struct PairCoef {
-    T cA, c2, b, c, d, e, h2;
+    T cA, cAe, c2, b, c, d, e, h2;  // cAe = cA + e (the z row)
 };
 
-// rinv = 1/sqrt(r2) (infinite for coincident blobs), h2 = 2 zj, Rz = zi + zj
+// rinv = 1/sqrt(r2) (infinite for coincident blobs), h2 = 2 zj, mh22 = -h2^2,
+// Rz = zi + zj
 template <class T, class C>
-__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, T h2, T Rz, T Ri,
-                                                      const C &k) {
+__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, T h2, T mh22,
+                                                      T Rz, T Ri, const C &k) {
     PairCoef<T> w;
-    const T rinv2 = rinv * rinv;
-    T c1 = rinv * fma(k.k1, rinv2, T(1));
-    T c2 = rinv * rinv2 * fma(-k.k2, rinv2, T(1));
+    const T rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+    T c1 = fma(k.k1, rinv3, rinv);
+    T c2 = fma(-k.k2, rinv3 * rinv2, rinv3);
     ARB_IF_ANY_OVERLAP(r2 <= k.four_a2)
     if (r2 <= k.four_a2) {
         const T rv = r2 > T(0) ? rinv : T(0);
@@ -110,13 +111,14 @@ __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, 
                      fma(T(-10) * a2, t, fma(T(6), q, T(2) * a2)));
     const T iC = fma(a4s, fma(T(-140.0 / 3.0), t, T(40.0 / 3.0)),
                      fma(T(20) * a2, t, fma(T(-12), q, T(-4) * a2)));
-    const T iE = fma(a4s, fma(T(20), t, T(-8.0 / 3.0)), fma(T(-4) * a2, t, -(h2 * h2)));
+    const T iE = fma(a4s, fma(T(20), t, T(-8.0 / 3.0)), fma(T(-4) * a2, t, mh22));
     w.cA = c1 + fma(Ri3, iA, -Ri);
     w.c2 = c2;
     w.b = fma(Ri5, iB, -Ri3);
     w.c = fma(RzRi5, iC, h2Ri3);
     w.d = fma(T(-20.0 / 3.0) * k.a4, RzRi5 * s, h2Ri3);
     w.e = Ri3 * iE;
+    w.cAe = w.cA + w.e;
     w.h2 = h2;
     return w;
 }
@@ -134,7 +136,7 @@ __device__ __forceinline__ void wall_pair_apply(const PairCoef<T> &w, T cc, T dd
     const T tg = fma(w.c2, Sd, g);
     fx = fma(w.cA, lx, fma(tg, dx, fx));
     fy = fma(w.cA, ly, fma(tg, dy, fy));
-    fz = fma(w.cA, lz, fma(tg, dz, fma(g, w.h2, fma(dd, SR, fma(w.e, lz, fz)))));
+    fz = fma(w.cAe, lz, fma(tg, dz, fma(g, w.h2, fma(dd, SR, fz))));
 }
 
 __device__ __forceinline__ double rsq_f64(double x) {
@@ -158,7 +160,8 @@ __device__ inline void rpy_block_f64(double dx, double dy, double dz, double zt,
     const double Rz = zt + zs;
     PairCoef<double> w{};
     if (wall)
-        w = wall_pair_coef<double>(r2, rinv, zt, zs, zs + zs, Rz, rsq_f64(fma(Rz, Rz, dxy2)), c);
+        w = wall_pair_coef<double>(r2, rinv, zt, zs, zs + zs, -4.0 * zs * zs, Rz,
+                                   rsq_f64(fma(Rz, Rz, dxy2)), c);
     for (int col = 0; col < 3; ++col) {
         const double lx = col == 0, ly = col == 1, lz = col == 2;
         double ax = 0.0, ay = 0.0, az = 0.0;

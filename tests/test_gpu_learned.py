@@ -247,3 +247,26 @@ def test_learned_fallback_on_invalid_factor():
         arb.arb_destroy(c)
     assert rc == arb.ARB_W_LEARNED_FALLBACK
     assert info["rel_residual"] <= 1e-10
+
+
+def test_full_size_learned_solve(trained):
+    # 4,096 bacteria above the wall: the learned-block FP32 solve and the plain
+    # FP64 exact-block solve both reach 1e-6, and their velocities agree to 1e-5
+    model = trained[0]
+    wl = W.bacteria(n_bact=4096, seed=5)
+    print(f"full size learned: N={wl.N} M={wl.M} Nc={wl.n_rows}", flush=True)
+    out = {}
+    for name, prec, pc in (("exact_fp64", arb.ARB_FP64, arb.ARB_PC_BLOCK),
+                           ("learned_fp32", arb.ARB_FP32C, arb.ARB_PC_LEARNED)):
+        c = arb.context_for(wl, precision=prec, tol=1e-6, restart=100, max_iter=1000,
+                            precond=pc)
+        try:
+            learned.load_model(c, *model)
+            rc, U, phi, lam, info = arb.arb_solve(c, wl.F)
+        finally:
+            arb.arb_destroy(c)
+        assert rc == arb.ARB_OK
+        assert info["rel_residual_fp64"] <= 1e-6
+        print(f"  {name}: {info['iterations']} iterations", flush=True)
+        out[name] = U
+    assert rel(out["learned_fp32"], out["exact_fp64"]) <= 1e-5
