@@ -18,5 +18,6 @@ Modules
   precond   block-diagonal preconditioner (Sec. 3.1)
   gmres     right-preconditioned restarted GMRES (Sec. 3.1)
   correct   position/orientation correction (Sec. 4.2, App. B)
+  timeloop  reconstruction of articulated bodies and the Euler step (Sec. 4.1, 4.3)
   mlp       float64 MLP used to judge the learned body-mobility network
 """

@@ -14,6 +14,8 @@ Workloads (all lengths in units of the blob radius a = 1, viscosity eta = 1):
 
 * ``filament``   -- one free filament of rigid rods joined by ball joints
   (Sec. 3.2.1 shapes; 20 rods x 4 blobs by default).
+* ``ring``       -- a closed loop of rigid bodies joined by ball joints (an
+  articulated body with a loop, Sec. 4.2).
 * ``slab``       -- loose blobs above a wall, random sequential addition
   with minimum separation 2a (mobility mat-vec throughput case).
 * ``bacteria``   -- spherical-shell heads + rigid helical flagella joined by
@@ -32,6 +34,7 @@ from scipy.spatial.transform import Rotation
 __all__ = [
     "Workload",
     "filament",
+    "ring",
     "slab",
     "bacteria",
     "diatoms",
@@ -159,6 +162,43 @@ def filament(n_rods: int = 20, blobs_per_rod: int = 4, seed: int = 1,
         L["dl_q"][n] = (-half, 0, 0)
     return Workload("filament", 1.0, 1.0, False, r_ref, blob_offset, q, theta, F,
                     extra=dict(axis=axis, beta=beta), **L)
+
+
+# ---------------------------------------------------------------- ring
+def ring(n_bodies: int = 8, seed: int = 8, wall: bool = False, height: float = 12.0,
+         tilt: float = 0.0) -> Workload:
+    """Closed loop of rigid bodies joined end to end by ball joints.
+
+    Each body has blobs at body-frame (x, 0, 0), x in {-3,-1,1,3}, plus one at
+    (0, 0, 1.8), so that it resists every rotation (no spin null space).
+    Joint n sits at +4 e_x of body n and -4 e_x of body n+1 (mod n_bodies); at
+    t = 0 the joints are the vertices of a regular polygon of side 8 in the
+    plane z = height (tilted by ``tilt`` radians about the lab x axis), so
+    every link holds.  Forces and torques are N(0,1) per body.  With
+    ``wall`` the no-slip wall z = 0 is present.
+    """
+    rng = np.random.default_rng(seed)
+    r_body = np.array([[-3.0, 0, 0], [-1.0, 0, 0], [1.0, 0, 0], [3.0, 0, 0], [0, 0, 1.8]])
+    Rc = 4.0 / np.sin(np.pi / n_bodies)
+    ang = 2 * np.pi * np.arange(n_bodies + 1) / n_bodies
+    V = np.stack([Rc * np.cos(ang), Rc * np.sin(ang), 0 * ang], 1)
+    tilt_rot = Rotation.from_rotvec([tilt, 0, 0])
+    q = np.zeros((n_bodies, 3))
+    theta = np.zeros((n_bodies, 4))
+    for p in range(n_bodies):
+        d = V[p + 1] - V[p]
+        rot = tilt_rot * Rotation.from_rotvec([0, 0, np.arctan2(d[1], d[0])])
+        q[p] = tilt_rot.apply(0.5 * (V[p] + V[p + 1])) + np.array([0, 0, height])
+        theta[p] = _quat_scalar_first(rot)[0]
+    r_ref = np.tile(r_body, (n_bodies, 1))
+    blob_offset = np.arange(n_bodies + 1, dtype=np.int32) * len(r_body)
+    F = rng.standard_normal((n_bodies, 6))
+    L = _links(n_bodies)
+    for n in range(n_bodies):
+        L["pq"][n] = (n, (n + 1) % n_bodies)
+        L["dl_p"][n] = (4.0, 0, 0)
+        L["dl_q"][n] = (-4.0, 0, 0)
+    return Workload("ring", 1.0, 1.0, wall, r_ref, blob_offset, q, theta, F, **L)
 
 
 # ---------------------------------------------------------------- blobs

@@ -1,0 +1,184 @@
+"""Pins of the time-integration oracle (Sec. 4): reconstruction and Euler step.
+
+Each check rests on something other than the oracle's own pseudo-inverse
+formula: the robot-arm chain walk of Sec. 4.1 (Eq. robot-arm), the normal
+equations that characterise a least-squares solution, the paper's statements
+that loop-free articulated bodies are rebuilt exactly and that the constraint
+error of an explicit Euler step decays as dt^2 (Sec. 4.2, Fig.
+convergence_nonlinear a), and invariants (zero-mean pseudo-inverse solution,
+fixed points)."""
+import numpy as np
+import pytest
+
+from oracle import bodies, timeloop
+from oracle.correct import link_assemblies
+from oracle.quat import quat_from_rotvec, quat_mul, rotation_matrix
+from paper_2107_10800_amd import workloads as W
+
+
+def _perturb(theta, scale, seed):
+    rng = np.random.default_rng(seed)
+    return quat_mul(quat_from_rotvec(scale * rng.standard_normal((len(theta), 3))), theta)
+
+
+def _tree():
+    """Four rods joined as a branched tree: 0-1, 0-2 (mid-rod branch), 2-3."""
+    wl = W.filament(n_rods=4, seed=3)
+    wl.pq = np.array([[0, 1], [0, 2], [2, 3]], np.int32)
+    wl.dl_p = np.array([[4.0, 0, 0], [0.0, 0, 0], [4.0, 0, 0]])
+    wl.dl_q = np.array([[-4.0, 0, 0], [-4.0, 0, 0], [-4.0, 0, 0]])
+    for k in ("dldot_p", "dldot_q"):
+        setattr(wl, k, np.zeros((3, 3)))
+    wl.nproj = np.full(3, 3, np.int32)
+    wl.proj = np.tile(np.eye(3), (3, 1, 1))
+    return wl
+
+
+def test_robot_arm_equivalence_for_a_chain():
+    """For a linear chain the reconstruction equals the robot-arm walk (Eq.
+    robot-arm) from body 1, shifted to the same centre of mass (Sec. 4.1)."""
+    wl = W.filament(n_rods=12, seed=5)
+    th = _perturb(wl.theta, 0.4, 1)
+    R = rotation_matrix(th)
+    walk = np.zeros_like(wl.q)
+    for n in range(wl.M - 1):          # link n: q_n + R_n dl_p = q_{n+1} + R_{n+1} dl_q
+        walk[n + 1] = walk[n] + R[n] @ wl.dl_p[n] - R[n + 1] @ wl.dl_q[n]
+    q_in = wl.q + np.random.default_rng(2).standard_normal(wl.q.shape)
+    walk += q_in.mean(0) - walk.mean(0)
+    out = timeloop.reconstruct(wl, q_in, th)
+    assert np.abs(out - walk).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["ring", "filament", "bacteria", "diatoms"])
+def test_pinv_solution_has_zero_mean(name):
+    """The minimum-norm solution has no null-space component, i.e. zero COM (Sec. 4.1)."""
+    wl = dict(ring=lambda: W.ring(), filament=lambda: W.filament(),
+              bacteria=lambda: W.bacteria(n_bact=2, side=200.0),
+              diatoms=lambda: W.diatoms(n_col=2, kmin=5, kmax=7))[name]()
+    th = _perturb(wl.theta, 0.2, 3)
+    for b, l in link_assemblies(wl):
+        qt = timeloop.pinv_positions(wl, b, l, th)
+        assert np.abs(qt.mean(0)).max() < 1e-12 * (1 + np.abs(qt).max())
+
+
+@pytest.mark.parametrize("name", ["ring", "filament", "bacteria", "diatoms"])
+def test_consistent_state_is_a_fixed_point(name):
+    """Positions that satisfy every link are rebuilt unchanged."""
+    wl = dict(ring=lambda: W.ring(), filament=lambda: W.filament(),
+              bacteria=lambda: W.bacteria(n_bact=2, side=200.0),
+              diatoms=lambda: W.diatoms(n_col=2, kmin=5, kmax=7))[name]()
+    assert np.abs(bodies.link_residual(wl, wl.q, wl.theta)).max() < 1e-12
+    out = timeloop.reconstruct(wl, wl.q, wl.theta)
+    assert np.abs(out - wl.q).max() < 1e-12
+
+
+@pytest.mark.parametrize("make", [lambda: W.filament(n_rods=15, seed=9), _tree])
+def test_loop_free_bodies_are_rebuilt_exactly(make):
+    """Chains and branched trees obey every link after reconstruction, for any
+    orientations (Sec. 4.2: only loops can leave a violation)."""
+    wl = make()
+    th = _perturb(wl.theta, 0.5, 4)
+    out = timeloop.reconstruct(wl, wl.q, th)
+    assert np.abs(bodies.link_residual(wl, out, th)).max() < 1e-12
+
+
+def test_loop_reconstruction_is_the_least_squares_solution():
+    """With a loop the links cannot all hold; the rebuilt positions satisfy the
+    normal equations P^T g = 0 (sum of +-g_n over each body's links vanishes)."""
+    wl = W.ring(n_bodies=7)
+    th = _perturb(wl.theta, 0.1, 5)
+    out = timeloop.reconstruct(wl, wl.q, th)
+    g = bodies.link_residual(wl, out, th)
+    assert np.abs(g).max() > 1e-3
+    ne = np.zeros((wl.M, 3))
+    for n, (p, qq) in enumerate(wl.pq):
+        ne[p] += g[n]
+        ne[qq] -= g[n]
+    assert np.abs(ne).max() < 1e-12
+    # any other placement with the same COM has a larger residual
+    rng = np.random.default_rng(6)
+    for _ in range(5):
+        d = 1e-3 * rng.standard_normal(out.shape)
+        d -= d.mean(0)
+        g2 = bodies.link_residual(wl, out + d, th)
+        assert (g2 ** 2).sum() > (g ** 2).sum()
+
+
+def test_anchored_chain():
+    """A chain tied to a fixed lab point is rebuilt exactly and independently of
+    the incoming tracking points (no translational freedom)."""
+    wl = W.filament(n_rods=6, seed=2)
+    R0 = rotation_matrix(wl.theta[0])
+    anchor = wl.q[0] + R0 @ np.array([-4.0, 0, 0])
+    wl.pq = np.vstack([wl.pq, [[0, -1]]]).astype(np.int32)
+    wl.dl_p = np.vstack([wl.dl_p, [[-4.0, 0, 0]]])
+    wl.dl_q = np.vstack([wl.dl_q, [anchor]])
+    wl.dldot_p = np.vstack([wl.dldot_p, np.zeros((1, 3))])
+    wl.dldot_q = np.vstack([wl.dldot_q, np.zeros((1, 3))])
+    wl.nproj = np.append(wl.nproj, 3).astype(np.int32)
+    wl.proj = np.concatenate([wl.proj, np.eye(3)[None]])
+    th = _perturb(wl.theta, 0.3, 7)
+    out1 = timeloop.reconstruct(wl, wl.q, th)
+    out2 = timeloop.reconstruct(wl, wl.q + 5.0, th)
+    assert np.abs(out1 - out2).max() < 1e-12
+    assert np.abs(bodies.link_residual(wl, out1, th)).max() < 1e-12
+
+
+def test_euler_constraint_error_is_second_order():
+    """E3 (Sec. 4.2): from a state that obeys the links, one explicit Euler step
+    of a loop leaves ||g||_inf ~ dt^2; an open chain leaves none."""
+    wl = W.ring()
+    U, _ = timeloop.solve_velocities(wl, wl.q, wl.theta)
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        _, _, info = timeloop.euler_step(wl, wl.q, wl.theta, dt, delta=np.inf, U=U)
+        assert not info["corrected"]
+        errs.append(info["g_inf_star"])
+    assert errs[0] > 1e-8
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4
+    fl = W.filament()
+    for dt in (0.2, 0.05):
+        _, _, info = timeloop.euler_step(fl, fl.q, fl.theta, dt, delta=np.inf)
+        assert info["g_inf_star"] < 1e-12
+
+
+def test_euler_step_moves_the_com_with_the_mean_velocity():
+    """Eq. ucom and step 3: the rebuilt articulated body is centred at
+    q_COM + dt u_COM; orientations follow theta_{w dt} . theta."""
+    wl = W.ring()
+    U = np.random.default_rng(8).standard_normal((wl.M, 6))
+    dt = 0.07
+    _, _, info = timeloop.euler_step(wl, wl.q, wl.theta, dt, delta=np.inf, U=U)
+    assert np.abs(info["q_star"].mean(0) - (wl.q.mean(0) + dt * U[:, :3].mean(0))).max() < 1e-12
+    for p in range(wl.M):
+        w = U[p, 3:]
+        ang = np.linalg.norm(w) * dt
+        Rw = rotation_matrix(quat_from_rotvec(w * dt))
+        # the rotation by w dt about w: axis fixed, angle |w| dt (Rodrigues)
+        assert np.abs(Rw @ w - w).max() < 1e-12
+        assert abs(np.trace(Rw) - (1 + 2 * np.cos(ang))) < 1e-12
+        assert np.abs(rotation_matrix(info["theta_star"][p]) - Rw @ rotation_matrix(wl.theta[p])).max() < 1e-12
+
+
+def test_euler_step_with_correction_meets_tolerance():
+    """When ||g*||^2 >= delta the correction of Sec. 4.2 brings the links to
+    its tolerance in a few iterations (Fig. convergence_nonlinear b)."""
+    wl = W.ring()
+    q, th, info = timeloop.euler_step(wl, wl.q, wl.theta, 0.2, delta=1e-20, corr_tol=1e-12)
+    assert info["corrected"] and info["corr"]["iterations"] <= 5
+    assert info["corr"]["residual"] <= 1e-12
+    # normalising the quaternion increments afterwards moves g by ~ |dl| x 1e-12
+    assert info["g_inf"] < 1e-10
+    assert np.allclose(np.linalg.norm(th, axis=1), 1.0, atol=1e-14)
+    # and a step whose check passes is taken as rebuilt
+    q2, th2, info2 = timeloop.euler_step(wl, wl.q, wl.theta, 0.2, delta=1.0)
+    assert not info2["corrected"]
+    assert np.array_equal(q2, info2["q_star"])
+
+
+def test_bodies_without_links_take_the_plain_euler_step():
+    wl = W.random_rigid(n_bodies=3, blobs=12, seed=7, links="none")
+    U = np.random.default_rng(9).standard_normal((wl.M, 6))
+    q, th, info = timeloop.euler_step(wl, wl.q, wl.theta, 0.1, delta=np.inf, U=U)
+    assert np.abs(q - (wl.q + 0.1 * U[:, :3])).max() < 1e-15
