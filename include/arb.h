@@ -206,6 +206,60 @@ int arb_solve_dev(arb_ctx *ctx, const double *F_dev, const double *u_slip_dev,
  * becomes the context's state; q/theta (3M/4M, may be NULL) receive it. */
 int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double *theta);
 
+/* Reconstruction of articulated bodies (Sec. 4.1, Eq. Pq_eq_z, Eq.
+ * pseudo-inv-sol, Eq. reconst-up-COM).  An articulated body is a set of
+ * bodies joined by links; for each, at the context's orientations and link
+ * arms, the link equations read P q = -z with row block n of P q equal to
+ * q_p - q_q and z_n = R(theta_p) dl_np - R(theta_q) dl_nq.  The tracking
+ * points are replaced by q~ + q_COM, q~ = -P^+ z (the zero-mean minimum-norm
+ * solution) and q_COM the mean of the current tracking points of that
+ * articulated body.  An articulated body with a link to a fixed lab point
+ * has no translational freedom: q = -P^+ z.  Bodies without links keep their
+ * positions.  Loop-free articulated bodies then obey every link exactly;
+ * with loops the links hold in the least-squares sense.  The result becomes
+ * the context's state.  q (3M, may be NULL) receives it; g_inf (may be NULL)
+ * the largest |component| of g_n over all links afterwards, g2 (may be NULL)
+ * the sum of g_n . g_n.  ARB_E_ARG if an articulated body has more than 2048
+ * bodies. */
+int arb_reconstruct(arb_ctx *ctx, double *q, double *g_inf, double *g2);
+
+/* Link residual g_n (Eq. constraint) at the context's state: g_inf and g2 as
+ * for arb_reconstruct (either may be NULL).  The state is not changed. */
+int arb_link_residual(arb_ctx *ctx, double *g_inf, double *g2);
+
+typedef struct {
+    int    solve_status;     /* return code of the step's solve (0 or a warning) */
+    int    iterations;       /* its GMRES iterations                             */
+    double rel_residual;     /* its FP64 relative residual                       */
+    double t_build_ms;       /* its preconditioner build                         */
+    double t_solve_ms;       /* its Krylov iterations                            */
+    double g_inf_star;       /* max |g_n component| after the reconstruction     */
+    double g2_star;          /* sum of g_n . g_n after the reconstruction        */
+    int    corrected;        /* 1 if the correction ran                          */
+    int    corr_iterations;  /* its largest step count over articulated bodies   */
+    double corr_residual;    /* its largest final ||F||_2                        */
+    double g_inf;            /* max |g_n component| at the end of the step       */
+} arb_step_info;
+
+/* One explicit Euler step with reconstruction and correction (Sec. 4.3):
+ *  1. solve Eq. linear_system at the context's state (forces F, 6M; slip
+ *     u_slip, 3N or NULL) for U; with warm != 0 GMRES starts from the last
+ *     solution this context computed (by arb_solve or arb_step_euler) when its
+ *     length matches, otherwise from zero;
+ *  2.-3. every body moves by q_p += dt u_p, theta_p <- theta_{w_p dt} . theta_p,
+ *     so each articulated body's mean tracking point moves by dt u_COM (Eq. ucom);
+ *  4. every articulated body is rebuilt as in arb_reconstruct;
+ *  5. if sum g_n . g_n >= delta, the correction of arb_correct_positions runs
+ *     with tolerance corr_tol (> 0) and at most corr_max_iter (>= 0) steps.
+ * The new state becomes the context's state; q (3M), theta (4M) and U (6M,
+ * the velocities of step 1) receive it when not NULL; info (may be NULL) the
+ * figures of the step.  Links are those set on the context (for arms that
+ * change in time the caller sets them before each step).  Returns the solve's
+ * code (a warning > 0 still completes the step) or an error. */
+int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
+                   double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
+                   double *U, arb_step_info *info);
+
 /* Position/orientation correction (Sec. 4.2, Eq. min_probl, App. B): per
  * assembly, Levenberg-Marquardt on the link residuals g_n plus
  * ||dtheta_p||^2 - 1, exact Jacobian, mu = ||F||^2, until ||F||_2 <= tol or

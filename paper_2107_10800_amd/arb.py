@@ -45,7 +45,7 @@ SYMBOLS = [
     "arb_solve_dev", "arb_euler_update", "arb_correct_positions", "arb_profile",
     "arb_profile_read", "arb_mlp_set_params", "arb_mlp_get_params", "arb_mlp_forward",
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
-    "arb_mlp_set_scaling",
+    "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
 ]
 
 
@@ -60,6 +60,16 @@ class arb_options(C.Structure):
                 ("eta", C.c_double), ("a", C.c_double), ("tol", C.c_double),
                 ("restart", C.c_int), ("max_iter", C.c_int), ("precond", C.c_int),
                 ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int)]
+
+
+class arb_step_info(C.Structure):
+    _fields_ = [("solve_status", C.c_int), ("iterations", C.c_int), ("rel_residual", C.c_double),
+                ("t_build_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("g_inf_star", C.c_double), ("g2_star", C.c_double), ("corrected", C.c_int),
+                ("corr_iterations", C.c_int), ("corr_residual", C.c_double), ("g_inf", C.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class arb_solve_info(C.Structure):
@@ -130,6 +140,10 @@ def load():
         "arb_body_mobility": (C.c_int, [_P, _DP, _FP]),
         "arb_mlp_set_scaling": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
         "arb_profile_read": (C.c_int, [_P, _DP, C.POINTER(C.c_int)]),
+        "arb_reconstruct": (C.c_int, [_P, _DP, _DP, _DP]),
+        "arb_link_residual": (C.c_int, [_P, _DP, _DP]),
+        "arb_step_euler": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double, C.c_int,
+                                     C.c_int, _DP, _DP, _DP, C.POINTER(arb_step_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -371,6 +385,38 @@ def arb_correct_positions(ctx, tol=1e-10, max_iter=50):
     _check(ctx, load().arb_correct_positions(ctx, float(tol), int(max_iter), qp, tp,
                                              C.byref(it), C.byref(res)))
     return q.reshape(M, 3), t.reshape(M, 4), it.value, res.value
+
+
+def arb_reconstruct(ctx):
+    """Returns (q (M,3), g_inf, g2) after rebuilding the articulated bodies."""
+    N, M, _, _ = arb_sizes(ctx)
+    q, qp = _out(3 * M)
+    gi, g2 = C.c_double(), C.c_double()
+    _check(ctx, load().arb_reconstruct(ctx, qp, C.byref(gi), C.byref(g2)))
+    return q.reshape(M, 3), gi.value, g2.value
+
+
+def arb_link_residual(ctx):
+    """(g_inf, g2) of the links at the context's state."""
+    gi, g2 = C.c_double(), C.c_double()
+    _check(ctx, load().arb_link_residual(ctx, C.byref(gi), C.byref(g2)))
+    return gi.value, g2.value
+
+
+def arb_step_euler(ctx, F, dt, delta=1e-10, corr_tol=1e-10, corr_max_iter=50, warm=True,
+                   u_slip=None):
+    """Returns (status, q (M,3), theta (M,4), U (M,6), info dict) after one step."""
+    N, M, _, _ = arb_sizes(ctx)
+    F_, Fp = _d(F, 6 * M)
+    us_, usp = _d(u_slip, 3 * N) if u_slip is not None else (None, None)
+    q, qp = _out(3 * M)
+    t, tp = _out(4 * M)
+    U, Up = _out(6 * M)
+    info = arb_step_info()
+    rc = _check(ctx, load().arb_step_euler(ctx, Fp, usp, float(dt), float(delta),
+                                           float(corr_tol), int(corr_max_iter), int(bool(warm)),
+                                           qp, tp, Up, C.byref(info)))
+    return rc, q.reshape(M, 3), t.reshape(M, 4), U.reshape(M, 6), info.to_dict()
 
 
 def arb_profile(ctx, enable=True):

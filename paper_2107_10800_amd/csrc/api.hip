@@ -21,6 +21,44 @@ namespace {
 constexpr int kMaxBodyBlobs = 512;
 constexpr int kMaxAsmRows = 2048;
 constexpr int kMaxCorrRows = 2048;
+// largest articulated body (in bodies) the reconstruction takes: G is M_a^2 doubles
+constexpr int kMaxReconBodies = 2048;
+
+// in-place inverse of a symmetric positive definite n x n row-major matrix by
+// Cholesky (A = C C^T, A^-1 = C^-T C^-1); returns nonzero if not SPD
+static int spd_inverse(double *A, int n) {
+    std::vector<double> C((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
+        if (!(d > 0.0)) return 1;
+        const double cjj = std::sqrt(d);
+        C[(size_t)j * n + j] = cjj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
+            C[(size_t)i * n + j] = v / cjj;
+        }
+    }
+    // W = C^-1 (lower), then A^-1 = W^T W
+    std::vector<double> W((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        W[(size_t)j * n + j] = 1.0 / C[(size_t)j * n + j];
+        for (int i = j + 1; i < n; ++i) {
+            double v = 0.0;
+            for (int k = j; k < i; ++k) v -= C[(size_t)i * n + k] * W[(size_t)k * n + j];
+            W[(size_t)i * n + j] = v / C[(size_t)i * n + i];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = 0.0;
+            for (int k = i; k < n; ++k) v += W[(size_t)k * n + i] * W[(size_t)k * n + j];
+            A[(size_t)i * n + j] = v;
+            A[(size_t)j * n + i] = v;
+        }
+    return 0;
+}
 
 int fail(arb_ctx *ctx, int code, const std::string &msg) {
     if (ctx) ctx->err = msg;
@@ -954,6 +992,7 @@ int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset, const double
     ctx->types_ready = false;
     ctx->have_state = false;
     ctx->topo_dirty = true;
+    ctx->lasm_dirty = true;
     ctx->pc_built = false;
     ctx->slice_cache.clear();
     return ARB_OK;
@@ -1026,6 +1065,7 @@ int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p, co
         check_finite(ctx, ctx->h_proj.data(), ctx->h_proj.size(), "proj"))
         return ARB_E_NAN;
     ctx->topo_dirty = true;
+    ctx->lasm_dirty = true;
     ctx->pc_built = false;
     if (ctx->have_state) {
         HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1047,6 +1087,7 @@ int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef, con
         check_finite(ctx, ctx->h_grhs.data(), ctx->h_grhs.size(), "rhs"))
         return ARB_E_NAN;
     ctx->topo_dirty = true;
+    ctx->lasm_dirty = true;
     ctx->pc_built = false;
     if (ctx->have_state) {
         HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1283,6 +1324,7 @@ int arb_solve(arb_ctx *ctx, const double *F, const double *u_slip, const double 
     const int rc = solve_dev(ctx, ctx->s_in.as<double>(), u_slip ? ctx->s_aux.as<double>() : nullptr,
                              ctx->ky.as<double>(), y0 ? 1 : 0, info, s);
     if (rc < 0) return rc;
+    ctx->ky_n = n;
     const double *yd = ctx->ky.as<double>();
     if (lambda)
         HIPCHK(hipMemcpyAsync(lambda, yd, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1316,14 +1358,14 @@ int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double
     return ARB_OK;
 }
 
-int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, double *theta,
-                          int *iters, double *resid) {
-    if (!ctx || !(tol > 0) || max_iter < 0) return ARB_E_ARG;
-    TRY(ready(ctx));
-    HIPCHK(hipSetDevice(ctx->opt.device));
-    hipStream_t s = ctx->stream;
+// Articulated bodies of the link graph (bodies joined by links; bodies without
+// links are left out) with their bodies and links, the correction's workspace
+// offsets, and for the reconstruction each body's signed link list and
+// G = (L + 1 1^T / M_a)^-1 (L^-1 with a link to a lab point), L = Phat^T Phat
+// the body graph's Laplacian.  Rebuilt when bodies or links change.
+static int link_assemblies(arb_ctx *ctx, hipStream_t s) {
+    if (!ctx->lasm_dirty) return 0;
     const int M = ctx->M, P = ctx->P;
-    // assemblies of bodies joined by links (position constraints only)
     std::vector<int> parent(M);
     std::iota(parent.begin(), parent.end(), 0);
     auto find = [&](int i) {
@@ -1353,10 +1395,11 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
         if (root_label[r] < 0) root_label[r] = A++;
         label[p] = root_label[r];
     }
+    ctx->lasm_A = A;
+    ctx->lasm_fits_corr = true;
     if (A == 0) {
-        if (iters) *iters = 0;
-        if (resid) *resid = 0.0;
-        return ARB_OK;
+        ctx->lasm_dirty = false;
+        return 0;
     }
     std::vector<int> abp(A + 1, 0), ab, alp(A + 1, 0), al(P), loc(M, -1);
     for (int p = 0; p < M; ++p)
@@ -1377,12 +1420,57 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
         std::vector<int> f2(alp.begin(), alp.end() - 1);
         for (int n = 0; n < P; ++n) al[f2[label[ctx->h_pq[2 * n]]]++] = n;
     }
+    // correction workspace
     std::vector<int64_t> wo(A + 1, 0);
     for (int a = 0; a < A; ++a) {
         const int nb = abp[a + 1] - abp[a], nl = alp[a + 1] - alp[a];
-        if (3 * nl + nb > kMaxCorrRows)
-            return fail(ctx, ARB_E_ARG, "articulated body too large for the correction kernel");
-        wo[a + 1] = wo[a] + arb::correct_ws_doubles(nb, nl);
+        if (3 * nl + nb > kMaxCorrRows) ctx->lasm_fits_corr = false;
+        wo[a + 1] = wo[a] + (ctx->lasm_fits_corr ? arb::correct_ws_doubles(nb, nl) : 0);
+    }
+    ctx->lasm_ws = ctx->lasm_fits_corr ? wo[A] : 0;
+    // reconstruction: signed link lists per body, anchored flags, G per articulated body
+    std::vector<int> adj_ptr(abp[A] + 1, 0), adj, anch(A, 0);
+    std::vector<int64_t> goff(A + 1, 0);
+    for (int a = 0; a < A; ++a) {
+        const int nb = abp[a + 1] - abp[a];
+        if (nb > kMaxReconBodies)
+            return fail(ctx, ARB_E_ARG, "articulated body has more bodies than the reconstruction takes");
+        goff[a + 1] = goff[a] + (int64_t)nb * nb;
+        for (int e = 0; e < alp[a + 1] - alp[a]; ++e) {
+            const int n = al[alp[a] + e];
+            adj_ptr[abp[a] + loc[ctx->h_pq[2 * n]] + 1]++;
+            if (ctx->h_pq[2 * n + 1] >= 0)
+                adj_ptr[abp[a] + loc[ctx->h_pq[2 * n + 1]] + 1]++;
+            else
+                anch[a] = 1;
+        }
+    }
+    for (int k = 0; k < abp[A]; ++k) adj_ptr[k + 1] += adj_ptr[k];
+    adj.assign(adj_ptr[abp[A]], 0);
+    std::vector<double> G(goff[A], 0.0);
+    {
+        std::vector<int> f2(adj_ptr.begin(), adj_ptr.end() - 1);
+        for (int a = 0; a < A; ++a) {
+            const int nb = abp[a + 1] - abp[a];
+            double *La = G.data() + goff[a];
+            for (int e = 0; e < alp[a + 1] - alp[a]; ++e) {
+                const int n = al[alp[a] + e];
+                const int lp = loc[ctx->h_pq[2 * n]], qq = ctx->h_pq[2 * n + 1];
+                adj[f2[abp[a] + lp]++] = 2 * e;
+                La[(size_t)lp * nb + lp] += 1.0;
+                if (qq >= 0) {
+                    const int lq = loc[qq];
+                    adj[f2[abp[a] + lq]++] = 2 * e + 1;
+                    La[(size_t)lq * nb + lq] += 1.0;
+                    La[(size_t)lp * nb + lq] -= 1.0;
+                    La[(size_t)lq * nb + lp] -= 1.0;
+                }
+            }
+            if (!anch[a])
+                for (int64_t k = 0; k < (int64_t)nb * nb; ++k) La[k] += 1.0 / nb;
+            if (spd_inverse(La, nb) != 0)
+                return fail(ctx, ARB_E_ARG, "link graph of an articulated body is singular");
+        }
     }
     TRY(upload(ctx, ctx->c_link_ptr, alp.data(), A + 1, s));
     TRY(upload(ctx, ctx->c_links, al.data(), P, s));
@@ -1391,13 +1479,37 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
     TRY(upload(ctx, ctx->c_pq, ctx->h_pq.data(), 2 * (size_t)P, s));
     TRY(upload(ctx, ctx->c_abp, abp.data(), A + 1, s));
     TRY(upload(ctx, ctx->c_ab, ab.data(), ab.size(), s));
-    HIPCHK(ctx->c_ws.ensure(std::max<int64_t>(wo[A], 1) * sizeof(double)));
+    TRY(upload(ctx, ctx->r_adj_ptr, adj_ptr.data(), adj_ptr.size(), s));
+    TRY(upload(ctx, ctx->r_adj, adj.data(), std::max<size_t>(adj.size(), 1), s));
+    TRY(upload(ctx, ctx->r_anch, anch.data(), A, s));
+    TRY(upload(ctx, ctx->r_goff, goff.data(), A + 1, s));
+    TRY(upload(ctx, ctx->r_G, G.data(), G.size(), s));
+    HIPCHK(ctx->c_ws.ensure(std::max<int64_t>(ctx->lasm_ws, 1) * sizeof(double)));
     HIPCHK(ctx->c_iters.ensure(A * sizeof(int)));
     HIPCHK(ctx->c_resid.ensure(A * sizeof(double)));
+    HIPCHK(ctx->r_z.ensure(std::max<int64_t>(3 * (int64_t)P, 1) * sizeof(double)));
+    HIPCHK(ctx->r_b.ensure(std::max<int64_t>(3 * (int64_t)abp[A], 1) * sizeof(double)));
+    HIPCHK(ctx->r_ginf.ensure(A * sizeof(double)));
+    HIPCHK(ctx->r_g2.ensure(A * sizeof(double)));
+    HIPCHK(hipStreamSynchronize(s));  // the host vectors above end with this scope
+    ctx->lasm_dirty = false;
+    return 0;
+}
+
+// correction of every articulated body on stream s (state on the device)
+static int correct_run(arb_ctx *ctx, hipStream_t s, double tol, int max_iter, int *iters,
+                       double *resid) {
+    TRY(link_assemblies(ctx, s));
+    const int A = ctx->lasm_A;
+    if (iters) *iters = 0;
+    if (resid) *resid = 0.0;
+    if (A == 0) return 0;
+    if (!ctx->lasm_fits_corr)
+        return fail(ctx, ARB_E_ARG, "articulated body too large for the correction kernel");
     arb::CorrectDev C;
     C.A = A;
-    C.M = M;
-    C.P = P;
+    C.M = ctx->M;
+    C.P = ctx->P;
     C.asm_body_ptr = ctx->c_abp.as<int>();
     C.asm_bodies = ctx->c_ab.as<int>();
     C.asm_link_ptr = ctx->c_link_ptr.as<int>();
@@ -1414,20 +1526,166 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
     C.resid = ctx->c_resid.as<double>();
     arb::correct_positions(s, C, tol, max_iter);
     HIPCHK(hipGetLastError());
-    TRY(refresh_geometry(ctx, s));
     std::vector<int> it(A);
     std::vector<double> rs(A);
     HIPCHK(hipMemcpyAsync(it.data(), C.iters, A * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(rs.data(), C.resid, A * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (q)
-        HIPCHK(hipMemcpyAsync(q, ctx->q.p, 3 * (size_t)M * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (theta)
-        HIPCHK(hipMemcpyAsync(theta, ctx->theta.p, 4 * (size_t)M * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (iters) *iters = *std::max_element(it.begin(), it.end());
     if (resid) *resid = *std::max_element(rs.begin(), rs.end());
+    return 0;
+}
+
+// reconstruction (rebuild != 0) and/or link residual on stream s: g_inf = the
+// largest |g_n component|, g2 = sum of g_n . g_n over all links
+static int recon_run(arb_ctx *ctx, hipStream_t s, int rebuild, double *g_inf, double *g2) {
+    TRY(link_assemblies(ctx, s));
+    const int A = ctx->lasm_A;
+    *g_inf = 0.0;
+    *g2 = 0.0;
+    if (A == 0) return 0;
+    arb::ReconDev D;
+    D.A = A;
+    D.asm_body_ptr = ctx->c_abp.as<int>();
+    D.asm_bodies = ctx->c_ab.as<int>();
+    D.asm_link_ptr = ctx->c_link_ptr.as<int>();
+    D.asm_links = ctx->c_links.as<int>();
+    D.adj_ptr = ctx->r_adj_ptr.as<int>();
+    D.adj = ctx->r_adj.as<int>();
+    D.pq = ctx->c_pq.as<int>();
+    D.anchored = ctx->r_anch.as<int>();
+    D.g_off = ctx->r_goff.as<int64_t>();
+    D.G = ctx->r_G.as<double>();
+    D.dl_p = ctx->dl_p.as<double>();
+    D.dl_q = ctx->dl_q.as<double>();
+    D.theta = ctx->theta.as<double>();
+    D.q = ctx->q.as<double>();
+    D.z = ctx->r_z.as<double>();
+    D.b = ctx->r_b.as<double>();
+    D.ginf = ctx->r_ginf.as<double>();
+    D.g2 = ctx->r_g2.as<double>();
+    arb::reconstruct(s, D, rebuild);
+    HIPCHK(hipGetLastError());
+    std::vector<double> gi(A), gs(A);
+    HIPCHK(hipMemcpyAsync(gi.data(), D.ginf, A * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(gs.data(), D.g2, A * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int a = 0; a < A; ++a) {
+        *g_inf = std::max(*g_inf, gi[a]);
+        *g2 += gs[a];
+    }
+    return 0;
+}
+
+static int copy_state_out(arb_ctx *ctx, hipStream_t s, double *q, double *theta) {
+    if (q)
+        HIPCHK(hipMemcpyAsync(q, ctx->q.p, 3 * (size_t)ctx->M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    if (theta)
+        HIPCHK(hipMemcpyAsync(theta, ctx->theta.p, 4 * (size_t)ctx->M * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    return 0;
+}
+
+int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, double *theta,
+                          int *iters, double *resid) {
+    if (!ctx || !(tol > 0) || max_iter < 0) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(correct_run(ctx, s, tol, max_iter, iters, resid));
+    TRY(refresh_geometry(ctx, s));
+    TRY(copy_state_out(ctx, s, q, theta));
+    HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+}
+
+int arb_reconstruct(arb_ctx *ctx, double *q, double *g_inf, double *g2) {
+    if (!ctx) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    double gi = 0.0, gs = 0.0;
+    TRY(recon_run(ctx, s, 1, &gi, &gs));
+    TRY(refresh_geometry(ctx, s));
+    TRY(copy_state_out(ctx, s, q, nullptr));
+    HIPCHK(hipStreamSynchronize(s));
+    if (g_inf) *g_inf = gi;
+    if (g2) *g2 = gs;
+    return ARB_OK;
+}
+
+int arb_link_residual(arb_ctx *ctx, double *g_inf, double *g2) {
+    if (!ctx) return ARB_E_ARG;
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    double gi = 0.0, gs = 0.0;
+    TRY(recon_run(ctx, ctx->stream, 0, &gi, &gs));
+    if (g_inf) *g_inf = gi;
+    if (g2) *g2 = gs;
+    return ARB_OK;
+}
+
+int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
+                   double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
+                   double *U, arb_step_info *info) {
+    if (!ctx || !F) return ARB_E_ARG;
+    if (!std::isfinite(dt) || std::isnan(delta) || !(corr_tol > 0) || corr_max_iter < 0)
+        return fail(ctx, ARB_E_ARG, "bad time-step arguments");
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const int N = ctx->N, M = ctx->M;
+    const int64_t n = n_unknowns(ctx);
+    if (check_finite(ctx, F, 6 * (size_t)M, "F") ||
+        check_finite(ctx, u_slip, u_slip ? 3 * (size_t)N : 0, "u_slip"))
+        return ARB_E_NAN;
+    hipStream_t s = ctx->stream;
+    // 1. velocities at t_k, from the previous step's solution when warm
+    TRY(upload(ctx, ctx->s_in, F, 6 * (size_t)M, s));
+    if (u_slip) TRY(upload(ctx, ctx->s_aux, u_slip, 3 * (size_t)N, s));
+    HIPCHK(ctx->ky.ensure(n * sizeof(double)));
+    const int w = (warm && ctx->ky_n == n) ? 1 : 0;
+    arb_solve_info si{};
+    const int rc = solve_dev(ctx, ctx->s_in.as<double>(), u_slip ? ctx->s_aux.as<double>() : nullptr,
+                             ctx->ky.as<double>(), w, &si, s);
+    if (rc < 0) return rc;
+    ctx->ky_n = n;
+    const double *Ud = ctx->ky.as<double>() + 3 * (size_t)N;
+    // 2.-3. every body by explicit Euler (the mean of the new tracking points of
+    // an articulated body is then q_COM + dt u_COM), orientations by
+    // theta_{w dt} . theta
+    arb::euler_update(s, M, Ud, dt, ctx->q.as<double>(), ctx->theta.as<double>());
+    HIPCHK(hipGetLastError());
+    // 4. rebuild the articulated bodies at the new orientations
+    double gi = 0.0, gs = 0.0;
+    TRY(recon_run(ctx, s, 1, &gi, &gs));
+    // 5. check, and correct when the links are violated beyond delta
+    int corrected = 0, cit = 0;
+    double cres = 0.0, gi_end = gi;
+    if (ctx->lasm_A > 0 && !(gs < delta)) {
+        TRY(correct_run(ctx, s, corr_tol, corr_max_iter, &cit, &cres));
+        corrected = 1;
+        double g2e = 0.0;
+        TRY(recon_run(ctx, s, 0, &gi_end, &g2e));
+    }
+    TRY(refresh_geometry(ctx, s));
+    TRY(copy_state_out(ctx, s, q, theta));
+    if (U) HIPCHK(hipMemcpyAsync(U, Ud, 6 * (size_t)M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) {
+        info->solve_status = rc;
+        info->iterations = si.iterations;
+        info->rel_residual = si.rel_residual;
+        info->t_build_ms = si.t_build_ms;
+        info->t_solve_ms = si.t_solve_ms;
+        info->g_inf_star = gi;
+        info->g2_star = gs;
+        info->corrected = corrected;
+        info->corr_iterations = cit;
+        info->corr_residual = cres;
+        info->g_inf = gi_end;
+    }
+    return rc;
 }
 
 // parameter block: allocated once with identity standardisation

@@ -186,6 +186,29 @@ struct CorrectDev {
 };
 void correct_positions(hipStream_t s, const CorrectDev &C, double tol, int max_iter);
 
+// Reconstruction of articulated bodies from their orientations (Sec. 4.1) and
+// the link residual.  Articulated bodies (bodies joined by links) are listed
+// as in CorrectDev; per body (by position in asm_bodies) a CSR list of its
+// links: entry 2 e + s, e the link's position inside its articulated body's
+// link list, s = 1 when the body is the link's - end.
+struct ReconDev {
+    int A = 0;
+    const int *asm_body_ptr = nullptr, *asm_bodies = nullptr;
+    const int *asm_link_ptr = nullptr, *asm_links = nullptr;
+    const int *adj_ptr = nullptr, *adj = nullptr;
+    const int *pq = nullptr;
+    const int *anchored = nullptr;       // per articulated body: has a link to a lab point
+    const int64_t *g_off = nullptr;      // per articulated body: offset of G (doubles)
+    const double *G = nullptr;           // M_a x M_a row-major per articulated body
+    const double *dl_p = nullptr, *dl_q = nullptr, *theta = nullptr;
+    double *q = nullptr;
+    double *z = nullptr;                 // 3 per link (by position in asm_links)
+    double *b = nullptr;                 // 3 per body (by position in asm_bodies)
+    double *ginf = nullptr, *g2 = nullptr;  // per articulated body
+};
+// rebuild != 0: q <- reconstruction, then the residual; rebuild == 0: residual only
+void reconstruct(hipStream_t s, const ReconDev &D, int rebuild);
+
 }  // namespace arb
 
 // ---------------------------------------------------------------- context
@@ -249,8 +272,16 @@ struct arb_ctx {
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
     double *pinned = nullptr;  // host pinned scratch (small)
     GmresGraphs ggraph;
-    // correction
+    // articulated bodies (bodies joined by links) for the correction and the
+    // reconstruction, rebuilt when bodies or links change
+    bool lasm_dirty = true;
+    int lasm_A = 0;
+    int64_t lasm_ws = 0;   // correction workspace (doubles)
+    bool lasm_fits_corr = true;
     arb::DevBuf c_link_ptr, c_links, c_local, c_ws_off, c_ws, c_iters, c_resid, c_pq, c_abp, c_ab;
+    arb::DevBuf r_adj_ptr, r_adj, r_anch, r_goff, r_G, r_z, r_b, r_ginf, r_g2;
+    // last solution of a solve (warm start of the next time step); ky_n = its length
+    int64_t ky_n = 0;
     arb::DevBuf tune_out;
     // learned body mobility: network parameters, workspace, per-type blocks
     arb::DevBuf mlp_params, mlp_ws, mlp_x, mlp_t, body_type_d, t_ref, t_mat_off, t_z_off, t_minv,

@@ -1,0 +1,223 @@
+"""GPU parity of the time loop (Sec. 4.1, 4.3): reconstruction of articulated
+bodies, the link residual and the explicit Euler step with correction, against
+the oracle.
+
+Reconstruction and residual are direct FP64 formulas: compared at 1e-12 of
+the coordinates' scale.  A time step contains a solve: U agrees with the
+oracle's dense solve within max(1e-9, 10 kappa(A) r) relative, and the new
+state within dt times that (plus the rounding of the rebuild)."""
+import numpy as np
+import pytest
+
+from oracle import bodies, system, timeloop
+from oracle.correct import link_assemblies
+from oracle.quat import quat_from_rotvec, quat_mul, rotation_matrix
+from paper_2107_10800_amd import arb
+from paper_2107_10800_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _perturb(theta, scale, seed):
+    rng = np.random.default_rng(seed)
+    return quat_mul(quat_from_rotvec(scale * rng.standard_normal((len(theta), 3))), theta)
+
+
+def _anchored_chain():
+    wl = W.filament(n_rods=6, seed=2)
+    anchor = wl.q[0] + rotation_matrix(wl.theta[0]) @ np.array([-4.0, 0, 0])
+    wl.pq = np.vstack([wl.pq, [[0, -1]]]).astype(np.int32)
+    wl.dl_p = np.vstack([wl.dl_p, [[-4.0, 0, 0]]])
+    wl.dl_q = np.vstack([wl.dl_q, [anchor]])
+    wl.dldot_p = np.vstack([wl.dldot_p, np.zeros((1, 3))])
+    wl.dldot_q = np.vstack([wl.dldot_q, np.zeros((1, 3))])
+    wl.nproj = np.append(wl.nproj, 3).astype(np.int32)
+    wl.proj = np.concatenate([wl.proj, np.eye(3)[None]])
+    return wl
+
+
+def _tree_with_free_bodies():
+    """A branched tree (0-1, 0-2, 2-3) plus two bodies without links."""
+    wl = W.filament(n_rods=6, seed=3)
+    wl.pq = np.array([[0, 1], [0, 2], [2, 3]], np.int32)
+    wl.dl_p = np.array([[4.0, 0, 0], [0.0, 0, 0], [4.0, 0, 0]])
+    wl.dl_q = np.array([[-4.0, 0, 0], [-4.0, 0, 0], [-4.0, 0, 0]])
+    wl.dldot_p = np.zeros((3, 3))
+    wl.dldot_q = np.zeros((3, 3))
+    wl.nproj = np.full(3, 3, np.int32)
+    wl.proj = np.tile(np.eye(3), (3, 1, 1))
+    return wl
+
+
+RECON_CASES = {
+    "ring": lambda: W.ring(),
+    "ring_wall": lambda: W.ring(n_bodies=11, wall=True, tilt=0.3),
+    "filament": lambda: W.filament(),
+    "bacteria4": lambda: W.bacteria(n_bact=4, side=60.0, seed=21),
+    "diatoms3": lambda: W.diatoms(n_col=3, kmin=5, kmax=12, seed=22, lattice=(3, 1, 1)),
+    "anchored_chain": _anchored_chain,
+    "tree_and_free_bodies": _tree_with_free_bodies,
+}
+
+
+@pytest.mark.parametrize("name", list(RECON_CASES))
+def test_reconstruct_matches_oracle(name):
+    wl = RECON_CASES[name]()
+    rng = np.random.default_rng(11)
+    th = _perturb(wl.theta, 0.05, 12)
+    q_in = wl.q + 0.3 * rng.standard_normal(wl.q.shape)
+    print(f"reconstruct {name}: M={wl.M} P={wl.P}", flush=True)
+    ctx = arb.context_for(wl)
+    try:
+        arb.arb_set_state(ctx, q_in, th)
+        gi0, g20 = arb.arb_link_residual(ctx)
+        g_in = bodies.link_residual(wl, q_in, th)
+        scale = 1.0 + np.abs(q_in).max()
+        assert abs(gi0 - np.abs(g_in).max()) <= 1e-12 * scale
+        assert abs(g20 - (g_in ** 2).sum()) <= 1e-12 * scale * max(1.0, (g_in ** 2).sum())
+        q_gpu, gi, g2 = arb.arb_reconstruct(ctx)
+    finally:
+        arb.arb_destroy(ctx)
+    q_ref = timeloop.reconstruct(wl, q_in, th)
+    assert np.abs(q_gpu - q_ref).max() <= 1e-12 * scale
+    g = bodies.link_residual(wl, q_ref, th)
+    assert abs(gi - np.abs(g).max()) <= 1e-12 * scale
+    assert abs(g2 - (g ** 2).sum()) <= 1e-11 * scale * max(1e-3, (g ** 2).sum())
+
+
+def test_reconstruct_full_size_bacteria_and_diatoms():
+    """1,024 bacteria (2,048 bodies, 2 links each) and 256 diatom colonies
+    (5-40 plates) rebuilt at perturbed orientations, every body against the oracle."""
+    for wl in (W.bacteria(n_bact=1024), W.diatoms()):
+        th = _perturb(wl.theta, 0.02, 13)
+        # lifted by 2a so that the turned flagella stay above z = a
+        q_in = wl.q + np.array([0.0, 0.0, 2.0])
+        print(f"reconstruct full size {wl.name}: M={wl.M} P={wl.P}", flush=True)
+        ctx = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-6)
+        try:
+            arb.arb_set_state(ctx, q_in, th)
+            q_gpu, gi, g2 = arb.arb_reconstruct(ctx)
+        finally:
+            arb.arb_destroy(ctx)
+        q_ref = timeloop.reconstruct(wl, q_in, th)
+        scale = 1.0 + np.abs(q_in).max()
+        assert np.abs(q_gpu - q_ref).max() <= 1e-12 * scale
+        g = bodies.link_residual(wl, q_ref, th)
+        assert abs(gi - np.abs(g).max()) <= 1e-12 * scale
+
+
+def _kappa(A):
+    s = np.linalg.svd(A, compute_uv=False)
+    nz = s[s > 1e-12 * s[0]]
+    return s[0] / nz[-1]
+
+
+STEP_CASES = {
+    "ring": lambda: W.ring(),
+    "ring_wall": lambda: W.ring(n_bodies=9, wall=True, tilt=0.4, seed=10),
+    "filament": lambda: W.filament(),
+    "bacteria2": lambda: W.bacteria(n_bact=2, side=40.0, seed=23),
+}
+
+
+@pytest.mark.parametrize("name", list(STEP_CASES))
+@pytest.mark.parametrize("delta", [np.inf, 1e-20])
+def test_euler_step_matches_oracle(name, delta):
+    """One step from the workload's state: velocities, the rebuilt state, the
+    check of step 5 and (delta = 1e-20) the corrected state."""
+    wl = STEP_CASES[name]()
+    dt = 0.1
+    S = system.assemble(wl)
+    kap = _kappa(S["A"])
+    print(f"euler step {name} delta={delta}: M={wl.M} P={wl.P} kappa={kap:.2e}", flush=True)
+    ctx = arb.context_for(wl, tol=1e-12)
+    try:
+        rc, q, th, U, info = arb.arb_step_euler(ctx, wl.F, dt, delta=delta, corr_tol=1e-12,
+                                                 corr_max_iter=50, warm=False, u_slip=wl.u_slip)
+    finally:
+        arb.arb_destroy(ctx)
+    assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED) and info["rel_residual"] <= 1e-12
+    U_ref, _ = timeloop.solve_velocities(wl, wl.q, wl.theta)
+    tolU = max(1e-9, 10 * kap * 1e-12)
+    assert np.linalg.norm(U - U_ref) <= tolU * np.linalg.norm(U_ref)
+    # the integrator on the GPU's velocities, in the oracle
+    q_ref, th_ref, ref = timeloop.euler_step(wl, wl.q, wl.theta, dt, delta=delta, corr_tol=1e-12,
+                                              U=U)
+    scale = 1.0 + np.abs(wl.q).max()
+    assert info["corrected"] == int(ref["corrected"])
+    assert abs(info["g_inf_star"] - ref["g_inf_star"]) <= 1e-12 * scale
+    assert np.abs(q - q_ref).max() <= 1e-10 * scale
+    assert np.abs(th - th_ref).max() <= 1e-10
+    if ref["corrected"]:
+        # same Levenberg-Marquardt steps; the last one may fall either side of the tolerance
+        assert abs(info["corr_iterations"] - ref["corr"]["iterations"]) <= 1
+        assert info["g_inf"] <= 1e-10
+    else:
+        assert info["g_inf"] == info["g_inf_star"]
+
+
+def test_euler_constraint_error_is_second_order_on_gpu():
+    """E3 (Sec. 4.2): the rebuilt ring violates its links by O(dt^2); the open
+    filament not at all."""
+    wl = W.ring()
+    errs = []
+    ctx = arb.context_for(wl, tol=1e-12)
+    try:
+        for dt in (0.2, 0.1, 0.05, 0.025):
+            arb.arb_set_state(ctx, wl.q, wl.theta)
+            rc, q, th, U, info = arb.arb_step_euler(ctx, wl.F, dt, delta=np.inf, warm=False)
+            assert not info["corrected"]
+            errs.append(info["g_inf_star"])
+    finally:
+        arb.arb_destroy(ctx)
+    print("ring ||g*||_inf:", errs, flush=True)
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4
+    fl = W.filament()
+    ctx = arb.context_for(fl, tol=1e-12)
+    try:
+        for dt in (0.2, 0.05):
+            arb.arb_set_state(ctx, fl.q, fl.theta)
+            rc, q, th, U, info = arb.arb_step_euler(ctx, fl.F, dt, delta=np.inf, warm=False)
+            assert info["g_inf_star"] < 1e-12
+    finally:
+        arb.arb_destroy(ctx)
+
+
+def test_time_loop_with_warm_start_matches_oracle():
+    """Six steps of the ring above the wall with correction (delta = 1e-20):
+    GPU warm-started GMRES against the oracle's dense solves at every step."""
+    wl = W.ring(n_bodies=8, wall=True, tilt=0.2, seed=14)
+    dt, steps = 0.2, 6
+    q_ref, th_ref = wl.q.copy(), wl.theta.copy()
+    ctx = arb.context_for(wl, tol=1e-12)
+    its = []
+    try:
+        for k in range(steps):
+            rc, q, th, U, info = arb.arb_step_euler(ctx, wl.F, dt, delta=1e-20, corr_tol=1e-12,
+                                                     warm=True)
+            assert rc == 0
+            its.append(info["iterations"])
+            q_ref, th_ref, ref = timeloop.euler_step(wl, q_ref, th_ref, dt, delta=1e-20,
+                                                      corr_tol=1e-12)
+            scale = 1.0 + np.abs(q_ref).max()
+            print(f"step {k}: iters {info['iterations']} g*={info['g_inf_star']:.2e} "
+                  f"dq={np.abs(q - q_ref).max():.2e}", flush=True)
+            assert np.abs(q - q_ref).max() <= 1e-9 * scale
+            assert np.abs(th - th_ref).max() <= 1e-9
+            assert info["g_inf"] <= 1e-10
+    finally:
+        arb.arb_destroy(ctx)
+    assert np.mean(its[1:]) < its[0]     # the warm start shortens the later solves
+
+
+def test_step_argument_errors():
+    wl = W.ring()
+    ctx = arb.context_for(wl)
+    try:
+        for kw in (dict(dt=np.nan), dict(dt=0.1, corr_tol=0.0), dict(dt=0.1, corr_max_iter=-1)):
+            dt = kw.pop("dt")
+            with pytest.raises(arb.ArbError):
+                arb.arb_step_euler(ctx, wl.F, dt, **kw)
+    finally:
+        arb.arb_destroy(ctx)
