@@ -192,30 +192,74 @@ def solve_bench(torch, arb, wl, label, precision, tol=1e-6, reps=2):
 
 
 def filament_bench(arb, W, reps=5):
-    """Unbounded filament (20 rods x 4 blobs): FP64 solve to 1e-10, Euler step of 0.1
-    and the position correction, host-array entry points."""
+    """Unbounded filament (20 rods x 4 blobs): FP64 solve to 1e-10, then one time step
+    of 0.1 (solve, Euler update, reconstruction, correction run unconditionally),
+    host-array entry points."""
     wl = W.filament()
     ctx = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10)
     try:
         arb.arb_solve(ctx, wl.F)                                                 # warm-up
-        ts, tc = [], []
+        ts, tt = [], []
         for _ in range(reps):
             arb.arb_set_state(ctx, wl.q, wl.theta)
             t0 = time.perf_counter()
             rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
             t1 = time.perf_counter()
-            arb.arb_euler_update(ctx, U.ravel(), 0.1)
+            arb.arb_set_state(ctx, wl.q, wl.theta)
             t2 = time.perf_counter()
-            _, _, it, res = arb.arb_correct_positions(ctx, tol=1e-10, max_iter=50)
+            rs, q, th, U2, si = arb.arb_step_euler(ctx, wl.F, 0.1, delta=0.0, corr_tol=1e-10,
+                                                   corr_max_iter=50, warm=False)
             t3 = time.perf_counter()
             ts.append(t1 - t0)
-            tc.append(t3 - t2)
+            tt.append(t3 - t2)
         return dict(workload=f"free filament, 20 rods x 4 blobs, unbounded, N={wl.N}, "
                              f"M={wl.M}, Nc={wl.n_rows}, n={wl.n_unknowns}",
                     precision="f64", tol=1e-10, ms_per_solve=1e3 * min(ts),
                     iterations=info["iterations"], rel_residual=info["rel_residual"], status=rc,
-                    correction_ms=1e3 * min(tc), correction_iterations=it,
-                    correction_residual=res)
+                    dt=0.1, ms_per_step=1e3 * min(tt), step_g_inf_rebuilt=si["g_inf_star"],
+                    correction_iterations=si["corr_iterations"],
+                    correction_residual=si["corr_residual"], step_g_inf=si["g_inf"])
+    finally:
+        arb.arb_destroy(ctx)
+
+
+def timestep_bench(arb, W, n_bact=1024, dt=0.02, steps=3):
+    """Explicit Euler steps of the bacteria suspension (Sec. 4.3): FP32 pair sums in
+    GMRES to 1e-6 warm-started from the previous step, Euler update, reconstruction,
+    check against delta = 1e-10 and correction to 1e-10; one cold step first."""
+    import numpy as np
+
+    wl = W.bacteria(n_bact=n_bact, seed=3)
+    ctx = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-6)
+    try:
+        rc, q, th, U, cold = arb.arb_step_euler(ctx, wl.F, dt, delta=1e-10, corr_tol=1e-10,
+                                                warm=False)
+        ts, infos = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            rc, q, th, U, info = arb.arb_step_euler(ctx, wl.F, dt, delta=1e-10, corr_tol=1e-10,
+                                                    warm=True)
+            ts.append(time.perf_counter() - t0)
+            infos.append(info)
+        # the rebuild alone (host entry point, synchronous)
+        tr = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            arb.arb_reconstruct(ctx)
+            tr.append(time.perf_counter() - t0)
+        return dict(workload=f"bacteria above a wall: {n_bact} x (42-blob head + 80-blob "
+                             f"flagellum), N={wl.N}, M={wl.M}, Nc={wl.n_rows}, "
+                             f"n={wl.n_unknowns}; dt={dt}",
+                    precision="f32c pair sums, f64 Krylov", tol=1e-6,
+                    ms_per_step=1e3 * float(np.mean(ts)), ms_per_step_min=1e3 * min(ts),
+                    iterations_cold=cold["iterations"],
+                    iterations_warm=[i["iterations"] for i in infos],
+                    solve_ms_warm=[i["t_solve_ms"] for i in infos],
+                    g_inf_rebuilt=[i["g_inf_star"] for i in infos],
+                    corrected=[i["corrected"] for i in infos],
+                    correction_iterations=[i["corr_iterations"] for i in infos],
+                    g_inf_end=[i["g_inf"] for i in infos],
+                    reconstruct_ms=1e3 * min(tr), status=rc)
     finally:
         arb.arb_destroy(ctx)
 
@@ -373,7 +417,16 @@ def main():
         log("bench: filament solve + correction, f64")
         res["filament"] = filament_bench(arb, W)
         log(f"bench: filament {res['filament']['ms_per_solve']:.2f} ms, "
-            f"{res['filament']['iterations']} iterations")
+            f"{res['filament']['iterations']} iterations, step {res['filament']['ms_per_step']:.2f} ms")
+        log("bench: time steps, bacteria 1024, f32c")
+        try:
+            res["timestep"] = timestep_bench(arb, W)
+            log(f"bench: time step {res['timestep']['ms_per_step']:.1f} ms, iterations "
+                f"{res['timestep']['iterations_cold']} cold, "
+                f"{res['timestep']['iterations_warm']} warm")
+        except Exception as e:          # reported, not fatal to the headline line
+            res["timestep"] = {"error": str(e)}
+            log(f"bench: time steps failed: {e}")
         log("bench: GMRES solve, diatom colonies, f32c")
         res["diatoms"] = solve_bench(torch, arb, W.diatoms(),
                                      "256 unbounded diatom colonies of 5-40 plates (15 x 3 blobs) "
