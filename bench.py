@@ -55,6 +55,7 @@ def kernel_name(shape, prec="f32c"):
 # MI355X published vector peaks: 256 CUs x 2.4 GHz x 256 FP32 (128 FP64) flop/clk/CU
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+HBM_TBS = 8.0
 # HBM traffic of one timed pair product from the FETCH_SIZE / WRITE_SIZE runs recorded
 # under profiles/, scaled by the counts of a 256 MiB copy; each record is valid only
 # for the kernel sources and launch shape it was measured on
@@ -163,6 +164,33 @@ def matvec_bench(torch, arb, sl, precision, steps, warmup):
         arb.arb_destroy(ctx)
 
 
+def solve_roofline(wl, info, ms_measured):
+    """Roofline time of one solve: the sum over its phases of algorithmic flops / peak or
+    algorithmic bytes / HBM bandwidth, with the solver's own counts of products and
+    preconditioner applications.  Products at the symmetric kernel's flops (each
+    unordered pair once, the 256-blob diagonal blocks one way); preconditioner apply:
+    M_pp^-1 (8 m^2 B) and Z_p (48 m B) per body read once; Krylov: CGS2 reads the basis
+    twice per pass, 4 (j+1) n 8 B at Arnoldi step j, counted as one cycle; build:
+    Cholesky, triangular inverse and product (m^3 / 3 flops each) per body at the FP64
+    matrix-core peak.  Returns the phase times (ms) and roofline / measured."""
+    import numpy as np
+
+    N, n = wl.N, wl.n_unknowns
+    m = 3 * np.diff(np.asarray(wl.blob_offset, np.int64)).astype(float)
+    t32 = info["products_fp32"] * algorithmic_flops(N, -1, "f32c", wl.wall) / (PEAK_FP32_TFLOPS * 1e9)
+    t64 = info["products_fp64"] * algorithmic_flops(N, -1, "f64", wl.wall) / (PEAK_FP64_TFLOPS * 1e9)
+    pc_bytes = float(np.sum(8.0 * m * m + 48.0 * m))
+    t_pc = info["precond_applies"] * pc_bytes / (HBM_TBS * 1e9)
+    it = info["iterations"]
+    t_kry = sum(4.0 * (j + 1) * n * 8.0 for j in range(it)) / (HBM_TBS * 1e9)
+    t_build = float(np.sum(m ** 3)) / (PEAK_FP64_TFLOPS * 1e9)
+    total = t32 + t64 + t_pc + t_kry + t_build
+    return dict(products_fp32=info["products_fp32"], products_fp64=info["products_fp64"],
+                precond_applies=info["precond_applies"],
+                ms_pair_fp32=t32, ms_pair_fp64=t64, ms_precond_apply=t_pc, ms_krylov=t_kry,
+                ms_build=t_build, ms_roofline=total, frac=total / ms_measured)
+
+
 def solve_bench(torch, arb, wl, label, precision, tol=1e-6, reps=2):
     """Device solve of A y = b to tol (FP64 residual), preconditioner rebuilt each time."""
     ctx = arb.context_for(wl, precision=precision, tol=tol, restart=100, max_iter=1000)
@@ -186,7 +214,8 @@ def solve_bench(torch, arb, wl, label, precision, tol=1e-6, reps=2):
                     tol=tol, ms_per_solve=1e3 * min(times), iterations=info["iterations"],
                     rel_residual_fp64=info["rel_residual_fp64"],
                     precond_build_ms=info["t_build_ms"], status=rc,
-                    pairs_per_matvec=int(wl.N) ** 2)
+                    pairs_per_matvec=int(wl.N) ** 2,
+                    roofline=solve_roofline(wl, info, 1e3 * min(times)))
     finally:
         arb.arb_destroy(ctx)
 

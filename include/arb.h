@@ -95,6 +95,9 @@ typedef struct {
     int    pinv_used;       /* number of blocks inverted by pseudo-inverse     */
     int    history_len;     /* entries written to history                      */
     double history[1024];   /* relative residual estimate per iteration        */
+    int    products_fp64;   /* blob mobility products with the FP64 pair sum   */
+    int    products_fp32;   /* ... with the FP32 pair sum                      */
+    int    precond_applies; /* preconditioner applications                     */
 } arb_solve_info;
 
 /* -------------------------------------------------------------- lifetime */

@@ -76,14 +76,17 @@ class arb_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("rel_residual", C.c_double),
                 ("rel_residual_fp64", C.c_double), ("t_build_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("pinv_used", C.c_int), ("history_len", C.c_int),
-                ("history", C.c_double * 1024)]
+                ("history", C.c_double * 1024), ("products_fp64", C.c_int),
+                ("products_fp32", C.c_int), ("precond_applies", C.c_int)]
 
     def to_dict(self):
         return dict(iterations=self.iterations, restarts=self.restarts,
                     rel_residual=self.rel_residual, rel_residual_fp64=self.rel_residual_fp64,
                     t_build_ms=self.t_build_ms, t_solve_ms=self.t_solve_ms,
                     pinv_used=self.pinv_used,
-                    history=list(self.history[:self.history_len]))
+                    history=list(self.history[:self.history_len]),
+                    products_fp64=self.products_fp64, products_fp32=self.products_fp32,
+                    precond_applies=self.precond_applies)
 
 
 _lib = None

@@ -745,6 +745,8 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
     auto push = [&](double v) {
         if (inf->history_len < 1024) inf->history[inf->history_len++] = v;
     };
+    // work counts (a replayed graph runs the same product and apply as step())
+    auto count_product = [&]() { ++(prec == ARB_FP64 ? inf->products_fp64 : inf->products_fp32); };
     for (;;) {
         arb::multidot(s, n, 1, K.r, n, K.r, K.part, K.sc + 2);
         arb::g_init(s, m, K.sc + 2, K.g, K.sc + 3);  // g = [beta, 0, ...], sc[3] = beta
@@ -785,6 +787,8 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
             const double hn = pin[0], est = pin[1];
             if (!std::isfinite(est)) return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
             ++*total;
+            count_product();
+            ++inf->precond_applies;
             k = j + 1;
             push(est * hist_scale);
             last_est = est;
@@ -793,6 +797,7 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         arb::upper_solve(s, k, m, K.H, K.g, K.sv);
         arb::gemv_set(s, n, k, K.V, n, K.sv, K.w);
         TRY(precond_apply(ctx, s, K.w, K.z));
+        ++inf->precond_applies;
         arb::axpby(s, n, 1.0, K.z, 1.0, y);
         ++*restarts;
         if (trust_estimate && last_est <= tol_abs) {
@@ -802,6 +807,7 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         }
         --*restarts;
         TRY(system_apply(ctx, s, y, K.r, prec));
+        count_product();
         arb::axpby(s, n, 1.0, rhs, -1.0, K.r);  // r = rhs - A y
         ++*restarts;
         if (inf->history_len > 0) inf->history_len--;  // estimate replaced by the true residual
@@ -847,6 +853,7 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
     }
     if (warm) {
         TRY(system_apply(ctx, s, y, K.r, ARB_FP64));
+        ++inf->products_fp64;
         arb::axpby(s, n, 1.0, K.b, -1.0, K.r);  // r = b - A y
     } else {
         HIPCHK(hipMemsetAsync(y, 0, n * sizeof(double), s));
@@ -876,6 +883,7 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
                            1.0 / bnorm, inf, &rin, true));
             arb::axpby(s, n, 1.0, d, 1.0, y);
             TRY(system_apply(ctx, s, y, K.r, ARB_FP64));
+            ++inf->products_fp64;
             arb::axpby(s, n, 1.0, K.b, -1.0, K.r);
             TRY(dev_norm(ctx, s, K, K.r, 1, &res));
             if (!std::isfinite(res)) return fail(ctx, ARB_E_NAN, "refinement residual not finite");

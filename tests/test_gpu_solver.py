@@ -320,3 +320,27 @@ def test_full_size_solve_sampled(cfg):
     assert np.linalg.norm(body_rows - (-KTl + CTp)) <= 1e-12 * scale
     CU = Cs @ U.ravel()
     assert np.linalg.norm(Ay[3 * N + 6 * M:] - CU) <= 1e-12 * np.linalg.norm(CU)
+
+
+def test_solve_work_counts():
+    """The solve's counts of products and preconditioner applications: FP32
+    refinement takes one FP32 product per inner Arnoldi step and one FP64
+    product per refinement residual; FP64 GMRES one product per step plus one
+    per true-residual check at the end of a cycle."""
+    wl = W.bacteria(n_bact=4, side=60.0, seed=21)
+    for prec in (arb.ARB_FP32C, arb.ARB_FP64):
+        ctx = arb.context_for(wl, precision=prec, tol=1e-8)
+        try:
+            rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+        finally:
+            arb.arb_destroy(ctx)
+        it = info["iterations"]
+        print(f"  precision {prec}: iterations {it}, products {info['products_fp32']} + "
+              f"{info['products_fp64']}, applies {info['precond_applies']}", flush=True)
+        assert info["precond_applies"] >= it + 1
+        if prec == arb.ARB_FP32C:
+            assert it <= info["products_fp32"] <= it + info["restarts"]
+            assert 1 <= info["products_fp64"] <= 30
+        else:
+            assert info["products_fp32"] == 0
+            assert it + 1 <= info["products_fp64"] <= it + 1 + info["restarts"]
