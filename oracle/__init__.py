@@ -19,5 +19,7 @@ Modules
   gmres     right-preconditioned restarted GMRES (Sec. 3.1)
   correct   position/orientation correction (Sec. 4.2, App. B)
   timeloop  reconstruction of articulated bodies and the Euler step (Sec. 4.1, 4.3)
+  rpy_rot   generalised RPY tensor of single-blob bodies, unbounded (Sec. 2.4)
+  single_blob  the single-blob system Eq. linear_system_general and its preconditioner
   mlp       float64 MLP used to judge the learned body-mobility network
 """

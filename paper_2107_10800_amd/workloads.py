@@ -16,6 +16,8 @@ Workloads (all lengths in units of the blob radius a = 1, viscosity eta = 1):
   (Sec. 3.2.1 shapes; 20 rods x 4 blobs by default).
 * ``ring``       -- a closed loop of rigid bodies joined by ball joints (an
   articulated body with a loop, Sec. 4.2).
+* ``blob_filaments``, ``blob_shells`` -- articulated bodies of single-blob
+  bodies (Sec. 2.4; the filament and shell arrays of Sec. 3.2), unbounded.
 * ``slab``       -- loose blobs above a wall, random sequential addition
   with minimum separation 2a (mobility mat-vec throughput case).
 * ``bacteria``   -- spherical-shell heads + rigid helical flagella joined by
@@ -35,6 +37,8 @@ __all__ = [
     "Workload",
     "filament",
     "ring",
+    "blob_filaments",
+    "blob_shells",
     "slab",
     "bacteria",
     "diatoms",
@@ -258,8 +262,8 @@ def random_blobs(n: int, seed: int, box: float = 8.0, zlo: float = 1.2,
 
 
 # ---------------------------------------------------------------- bacteria
-def icosphere42(radius: float = 5.0) -> np.ndarray:
-    """12 icosahedron vertices + 30 edge midpoints pushed to the sphere."""
+def _icosahedron():
+    """Unit icosahedron vertices (12,3) and its 30 edges (i < j, in scan order)."""
     t = (1 + 5 ** 0.5) / 2
     v = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
                   [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
@@ -267,15 +271,100 @@ def icosphere42(radius: float = 5.0) -> np.ndarray:
     v /= np.linalg.norm(v, axis=1)[:, None]
     d = np.linalg.norm(v[:, None] - v[None], axis=2)
     emin = d[d > 1e-9].min()
-    mids = []
-    for i in range(12):
-        for j in range(i + 1, 12):
-            if abs(d[i, j] - emin) < 1e-9:
-                m = v[i] + v[j]
-                mids.append(m / np.linalg.norm(m))
+    edges = [(i, j) for i in range(12) for j in range(i + 1, 12) if abs(d[i, j] - emin) < 1e-9]
+    assert len(edges) == 30
+    return v, edges
+
+
+def icosphere42(radius: float = 5.0) -> np.ndarray:
+    """12 icosahedron vertices + 30 edge midpoints pushed to the sphere."""
+    v, edges = _icosahedron()
+    mids = [(v[i] + v[j]) / np.linalg.norm(v[i] + v[j]) for i, j in edges]
     pts = np.vstack([v, np.array(mids)])
     assert pts.shape == (42, 3)
     return radius * pts
+
+
+# ---------------------------------------------------------------- single-blob bodies
+def _single_blob_links(x, theta, pairs):
+    """Ball joints midway between blob centres x[p], x[q] for every (p, q) pair,
+    arms expressed in each body's frame (rotation theta, scalar first)."""
+    rot = Rotation.from_quat(np.concatenate([theta[:, 1:], theta[:, :1]], axis=1))
+    L = _links(len(pairs))
+    for n, (p, qq) in enumerate(pairs):
+        mid = 0.5 * (x[p] + x[qq])
+        L["pq"][n] = (p, qq)
+        L["dl_p"][n] = rot[p].inv().apply(mid - x[p])
+        L["dl_q"][n] = rot[qq].inv().apply(mid - x[qq])
+    return L
+
+
+def blob_filaments(nx: int = 1, nz: int = 1, n_blobs: int = 15, lc: float = 2.5,
+                   gap: float = 4.0, seed: int = 31) -> Workload:
+    """Array of straight filaments of single-blob bodies along x (Sec. 3.2.1).
+
+    Each filament has n_blobs bodies spaced lc apart, joined by ball joints
+    midway (dl = +-lc/2 e_x); filaments sit on an nx x nz grid in the (x, z)
+    plane, ``gap`` apart end to end along x and ``gap`` apart along z.  Every
+    body carries the force (0, 0, -1) (gravity along -z) and no torque.
+    Unbounded; the blobs sit at the tracking points.
+    """
+    length = (n_blobs - 1) * lc + 2.0
+    q, pairs = [], []
+    for iz in range(nz):
+        for ix in range(nx):
+            b0 = len(q)
+            for k in range(n_blobs):
+                q.append([ix * (length + gap) + k * lc, 0.0, iz * gap])
+            pairs += [(b0 + k, b0 + k + 1) for k in range(n_blobs - 1)]
+    q = np.array(q, float)
+    M = len(q)
+    theta = np.tile([1.0, 0, 0, 0], (M, 1))
+    F = np.zeros((M, 6))
+    F[:, 2] = -1.0
+    return Workload("blob_filaments", 1.0, 1.0, False, np.zeros((M, 3)),
+                    np.arange(M + 1, dtype=np.int32), q, theta, F,
+                    extra=dict(single_blob=True), **_single_blob_links(q, theta, pairs))
+
+
+def blob_shells(n_side: int = 1, lc: float = 2.5, forcing: str = "random",
+                seed: int = 32) -> Workload:
+    """Cubic lattice of n_side^3 deformable shells of single-blob bodies (Sec. 3.2.2).
+
+    A shell is the 42-point icosphere (12 icosahedron vertices, 30 projected
+    edge midpoints) scaled so that a vertex and a neighbouring midpoint are lc
+    apart; each midpoint is linked to the two vertices of its edge (60 links:
+    the midpoints have 2 neighbours, the vertices 5).  Shell centres are two
+    diameters apart.  Bodies get random orientations (the link arms follow);
+    ``forcing`` = "random": N(0,1) forces and torques, "gravity": (0, 0, -1).
+    Unbounded.
+    """
+    rng = np.random.default_rng(seed)
+    v, edges = _icosahedron()
+    mids = np.array([(v[i] + v[j]) / np.linalg.norm(v[i] + v[j]) for i, j in edges])
+    R = lc / np.linalg.norm(v[edges[0][0]] - mids[0])
+    shell = R * np.vstack([v, mids])
+    pairs1 = [(i, 12 + e) for e, (i, j) in enumerate(edges)] + \
+             [(j, 12 + e) for e, (i, j) in enumerate(edges)]
+    q, pairs = [], []
+    for ix in range(n_side):
+        for iy in range(n_side):
+            for iz in range(n_side):
+                b0 = len(q)
+                q.extend(shell + 4 * R * np.array([ix, iy, iz], float))
+                pairs += [(b0 + a, b0 + b) for a, b in pairs1]
+    q = np.array(q)
+    M = len(q)
+    theta = _quat_scalar_first(Rotation.random(M, random_state=rng))
+    if forcing == "random":
+        F = rng.standard_normal((M, 6))
+    else:
+        F = np.zeros((M, 6))
+        F[:, 2] = -1.0
+    return Workload("blob_shells", 1.0, 1.0, False, np.zeros((M, 3)),
+                    np.arange(M + 1, dtype=np.int32), q, theta, F,
+                    extra=dict(single_blob=True, shell_radius=R),
+                    **_single_blob_links(q, theta, pairs))
 
 
 def helix80(n: int = 80, length: float = 40.0, pitch: float = 10.0,
