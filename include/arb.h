@@ -61,6 +61,14 @@ extern "C" {
                               each body (no per-solve factorisation; ignores the
                               wall inside the blocks)                         */
 
+/* body models */
+#define ARB_MODEL_MULTIBLOB   0  /* rigid multiblob bodies, Eq. linear_system (Sec. 2.3) */
+#define ARB_MODEL_SINGLE_BLOB 1  /* every body one blob at its tracking point with the
+                                    generalised RPY tensor (Sec. 2.4), unknowns
+                                    y = [U (6M); phi (Nc)] of Eq. linear_system_general,
+                                    rows [U - N C^T phi; C U] = [N F; B]; unbounded,
+                                    ARB_FP64, preconditioner NONE or BLOCK only   */
+
 typedef struct arb_ctx arb_ctx;
 
 typedef struct {
@@ -82,6 +90,7 @@ typedef struct {
     int    graphs;     /* 0 = the GMRES iteration is captured once per Arnoldi */
                        /* index in HIP graphs and replayed (default),          */
                        /* 1 = plain launches                                   */
+    int    model;      /* ARB_MODEL_MULTIBLOB (default) or ARB_MODEL_SINGLE_BLOB */
 } arb_options;
 
 typedef struct {
@@ -146,7 +155,8 @@ int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p,
 int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef,
                  const double *rhs);
 
-/* Number of constraint rows N_c and of unknowns n = 3N + 6M + N_c. */
+/* Number of constraint rows N_c and of unknowns n = 3N + 6M + N_c (6M + N_c
+ * in the single-blob model). */
 int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n);
 
 /* -------------------------------------------------------------- operators
@@ -165,7 +175,17 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev,
 int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda,
                   double *u);
 
-/* out = A y for y = [lambda; U; phi] (Eq. linear_system); n doubles each. */
+/* Body mobility of single-blob bodies (Sec. 2.4; ARB_MODEL_SINGLE_BLOB only):
+ * UW = N FT with N the unbounded generalised RPY tensor (all ordered body
+ * pairs, self blocks included) at the context's state.  FT: 6M (f, tau per
+ * body), UW: 6M (u, w per body).  ARB_E_ARG in the multiblob model. */
+int arb_body_mobility_apply(arb_ctx *ctx, const double *FT, double *UW);
+/* Device-pointer version on stream (NULL = the context's stream). */
+int arb_body_mobility_apply_dev(arb_ctx *ctx, const double *FT_dev, double *UW_dev,
+                                void *stream);
+
+/* out = A y for y = [lambda; U; phi] (Eq. linear_system); n doubles each.  In
+ * the single-blob model y = [U; phi] and out = [U - N C^T phi; C U]. */
 int arb_system_apply(arb_ctx *ctx, const double *y, double *out);
 /* K U (3N) and K^T lambda (6M) (Eq. no-slip / Eq. balance). */
 int arb_K_apply(arb_ctx *ctx, const double *U, double *out);

@@ -32,6 +32,8 @@ ARB_PC_NONE = 0
 ARB_PC_BLOCK = 1
 ARB_PC_LEARNED = 2
 ARB_PC_BODYFRAME = 3
+ARB_MODEL_MULTIBLOB = 0
+ARB_MODEL_SINGLE_BLOB = 1
 ARB_PAIR_AUTO = 0
 ARB_PAIR_TARGET = 1
 ARB_PAIR_SYMMETRIC = 2
@@ -46,6 +48,7 @@ SYMBOLS = [
     "arb_profile_read", "arb_mlp_set_params", "arb_mlp_get_params", "arb_mlp_forward",
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
     "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
+    "arb_body_mobility_apply", "arb_body_mobility_apply_dev",
 ]
 
 
@@ -59,7 +62,8 @@ class arb_options(C.Structure):
     _fields_ = [("device", C.c_int), ("precision", C.c_int), ("wall", C.c_int),
                 ("eta", C.c_double), ("a", C.c_double), ("tol", C.c_double),
                 ("restart", C.c_int), ("max_iter", C.c_int), ("precond", C.c_int),
-                ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int)]
+                ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int),
+                ("model", C.c_int)]
 
 
 class arb_step_info(C.Structure):
@@ -144,6 +148,8 @@ def load():
         "arb_mlp_set_scaling": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
         "arb_profile_read": (C.c_int, [_P, _DP, C.POINTER(C.c_int)]),
         "arb_reconstruct": (C.c_int, [_P, _DP, _DP, _DP]),
+        "arb_body_mobility_apply": (C.c_int, [_P, _DP, _DP]),
+        "arb_body_mobility_apply_dev": (C.c_int, [_P, _P, _P, _P]),
         "arb_link_residual": (C.c_int, [_P, _DP, _DP]),
         "arb_step_euler": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double, C.c_int,
                                      C.c_int, _DP, _DP, _DP, C.POINTER(arb_step_info)]),
@@ -198,9 +204,9 @@ def _check(ctx, rc):
 # ------------------------------------------------------------------ entry points
 def arb_create(device=0, precision=ARB_FP64, wall=False, eta=1.0, a=1.0, tol=1e-10,
                restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0, pair_kernel=0,
-               graphs=0):
+               graphs=0, model=ARB_MODEL_MULTIBLOB):
     opt = arb_options(device, precision, int(bool(wall)), eta, a, tol, restart, max_iter,
-                      precond, slices, pair_kernel, graphs)
+                      precond, slices, pair_kernel, graphs, model)
     h = _P()
     rc = load().arb_create(C.byref(h), C.byref(opt))
     if rc < 0:
@@ -274,6 +280,20 @@ def arb_mobility_apply(ctx, lam):
     u, up = _out(3 * N)
     _check(ctx, load().arb_mobility_apply(ctx, lp, up))
     return u
+
+
+def arb_body_mobility_apply(ctx, FT):
+    """(u, w) per body (M,6) = N (f, tau) for single-blob bodies."""
+    M = arb_sizes(ctx)[1]
+    f_, fp = _d(FT, 6 * M)
+    u, up = _out(6 * M)
+    _check(ctx, load().arb_body_mobility_apply(ctx, fp, up))
+    return u.reshape(M, 6)
+
+
+def arb_body_mobility_apply_dev(ctx, FT_dev, UW_dev, stream=None):
+    return _check(ctx, load().arb_body_mobility_apply_dev(ctx, _ptr(FT_dev), _ptr(UW_dev),
+                                                          _ptr(stream)))
 
 
 def arb_mobility_apply_dev(ctx, lam_dev, u_dev, stream=None):
@@ -504,11 +524,14 @@ def arb_body_mobility(ctx):
 
 # ------------------------------------------------------------------ convenience
 def context_for(wl, precision=ARB_FP64, tol=1e-10, restart=100, max_iter=1000,
-                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0, graphs=0):
-    """Create a context and load a workload (bodies, links, rows, state)."""
+                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0, graphs=0, model=None):
+    """Create a context and load a workload (bodies, links, rows, state).  The body
+    model defaults to single-blob for workloads that mark themselves so."""
+    if model is None:
+        model = ARB_MODEL_SINGLE_BLOB if wl.extra.get("single_blob") else ARB_MODEL_MULTIBLOB
     ctx = arb_create(device=device, precision=precision, wall=wl.wall, eta=wl.eta, a=wl.a,
                      tol=tol, restart=restart, max_iter=max_iter, precond=precond, slices=slices,
-                     pair_kernel=pair_kernel, graphs=graphs)
+                     pair_kernel=pair_kernel, graphs=graphs, model=model)
     arb_set_bodies(ctx, wl.blob_offset, wl.r_ref, wl.body_type)
     if len(wl.pq):
         arb_set_links(ctx, wl.pq, wl.dl_p, wl.dl_q, wl.dldot_p, wl.dldot_q, wl.nproj, wl.proj)

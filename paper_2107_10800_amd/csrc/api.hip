@@ -90,7 +90,27 @@ int upload(arb_ctx *ctx, DevBuf &b, const T *h, size_t n, hipStream_t s) {
 }
 
 int64_t n_unknowns(const arb_ctx *ctx) {
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) return 6 * (int64_t)ctx->M + ctx->Nc;
     return 3 * (int64_t)ctx->N + 6 * (int64_t)ctx->M + ctx->Nc;
+}
+
+// M+1 zero blob offsets for the single-blob model (stages written for blobs run
+// with none)
+static int ensure_zero_offsets(arb_ctx *ctx, hipStream_t s) {
+    const size_t want = (size_t)(ctx->M + 1);
+    if (ctx->zero_off.bytes >= want * sizeof(int) && ctx->zero_off64.bytes >= want * sizeof(int64_t))
+        return 0;
+    std::vector<int> z(want, 0);
+    std::vector<int64_t> z64(want, 0);
+    TRY(upload(ctx, ctx->zero_off, z.data(), want, s));
+    TRY(upload(ctx, ctx->zero_off64, z64.data(), want, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return 0;
+}
+
+// offset of U inside the solution vector
+static int64_t u_offset(const arb_ctx *ctx) {
+    return ctx->opt.model == ARB_MODEL_SINGLE_BLOB ? 0 : 3 * (int64_t)ctx->N;
 }
 
 // ---------------------------------------------------------------- topology
@@ -384,7 +404,10 @@ int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const 
 }
 
 // out = A y (Eq. linear_system)
+int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out);
+
 int system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out, int precision) {
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) return single_blob_system_apply(ctx, s, y, out);
     const int N = ctx->N, M = ctx->M;
     const double *lam = y, *U = y + 3 * (size_t)N, *phi = y + 3 * (size_t)N + 6 * (size_t)M;
     TRY(ctx_pair(ctx, s, lam, out, U, precision));
@@ -393,6 +416,35 @@ int system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out, int 
                      ctx->Nc > 0 ? phi : nullptr, out + 3 * (size_t)N);
     arb::C_apply(s, ctx->Nc, ctx->row_p.as<int>(), ctx->row_q.as<int>(), ctx->crow.as<double>(), U,
                  out + 3 * (size_t)N + 6 * (size_t)M);
+    return 0;
+}
+
+// generalised RPY product N x6 (6M) scaled into out = base + scale' N x6, with the
+// kernel's 1/(8 pi eta) folded into scale' = scale / (8 pi eta)
+int body_mobility_dev(arb_ctx *ctx, hipStream_t s, const double *x6, double scale,
+                      const double *base, double *out) {
+    const int M = ctx->M;
+    HIPCHK(ctx->rot_partial.ensure(std::max<int64_t>(
+        (int64_t)arb::rot_pair_slices(M) * 6 * M, 1) * sizeof(double)));
+    const double k = 1.0 / (8.0 * 3.14159265358979323846 * ctx->opt.eta);
+    arb::rot_pair_apply(s, M, ctx->p64.as<double4>(), x6, ctx->opt.a, scale * k, base,
+                        ctx->rot_partial.as<double>(), out);
+    return 0;
+}
+
+// y = [U; phi] -> [U - N C^T phi; C U] (Eq. linear_system_general, rows reordered)
+int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out) {
+    const int M = ctx->M;
+    const double *U = y, *phi = y + 6 * (size_t)M;
+    HIPCHK(ctx->rot_ct.ensure(6 * (size_t)M * sizeof(double)));
+    TRY(ensure_zero_offsets(ctx, s));
+    // C^T phi: the balance-row kernel with no blobs
+    arb::KT_CT_apply(s, M, ctx->zero_off.as<int>(), ctx->dvec.as<double>(), nullptr, -1.0,
+                     ctx->brow_ptr.as<int>(), ctx->brow_ent.as<int>(), ctx->crow.as<double>(),
+                     ctx->Nc > 0 ? phi : nullptr, ctx->rot_ct.as<double>());
+    TRY(body_mobility_dev(ctx, s, ctx->rot_ct.as<double>(), -1.0, U, out));
+    arb::C_apply(s, ctx->Nc, ctx->row_p.as<int>(), ctx->row_q.as<int>(), ctx->crow.as<double>(), U,
+                 out + 6 * (size_t)M);
     return 0;
 }
 
@@ -516,10 +568,13 @@ int precond_build_exact(arb_ctx *ctx, hipStream_t s);
 
 // learned preconditioner build: network features -> N~_p; falls back to the
 // exact build when a predicted factor is not a valid Cholesky factor
+int precond_build_single(arb_ctx *ctx, hipStream_t s);
+
 int precond_build(arb_ctx *ctx, hipStream_t s) {
     TRY(ready(ctx));
     ctx->pc_learned = false;
     ctx->pc_lcorr = false;
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) return precond_build_single(ctx, s);
     if (ctx->opt.precond == ARB_PC_BODYFRAME) {
         // free-space blocks of each body type, rotated: no per-solve factorisation
         TRY(ensure_types(ctx, s));
@@ -578,6 +633,25 @@ int precond_build(arb_ctx *ctx, hipStream_t s) {
     return ctx->pc_pinv ? ARB_W_PINV_USED : ARB_OK;
 }
 
+// single-blob bodies: N~_p = self blocks, G~_a = (C_a N~_a C_a^T)^-1 (Sec. 3.1)
+int precond_build_single(arb_ctx *ctx, hipStream_t s) {
+    const int M = ctx->M;
+    HIPCHK(ctx->Nt.ensure(36 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->pctmp.ensure(6 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->status.ensure(8 * sizeof(int)));
+    HIPCHK(hipMemsetAsync(ctx->status.p, 0, 8 * sizeof(int), s));
+    TRY(ensure_zero_offsets(ctx, s));
+    arb::single_blob_body_mobility(s, M, ctx->opt.a, ctx->opt.eta, ctx->Nt.as<double>());
+    arb::PrecondDev P = pc_view(ctx);
+    arb::precond_assembly(s, P);
+    int st[8];
+    HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->pc_built = true;
+    ctx->pc_pinv = st[1];
+    return ctx->pc_pinv ? ARB_W_PINV_USED : ARB_OK;
+}
+
 int precond_build_exact(arb_ctx *ctx, hipStream_t s) {
     TRY(ready(ctx));
     const int M = ctx->M;
@@ -623,7 +697,11 @@ int precond_apply(arb_ctx *ctx, hipStream_t s, const double *r, double *z) {
         return 0;
     }
     arb::PrecondDev P = pc_view(ctx);
-    arb::precond_apply(s, P, ctx->N, r, z);
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB)
+        arb::precond_apply_single(s, P, ctx->zero_off.as<int>(), ctx->zero_off64.as<int64_t>(), r,
+                                  z);
+    else
+        arb::precond_apply(s, P, ctx->N, r, z);
     return 0;
 }
 
@@ -818,6 +896,8 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
 int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int warm,
               arb_solve_info *info, hipStream_t s) {
     TRY(ready(ctx));
+    if (us && ctx->opt.model == ARB_MODEL_SINGLE_BLOB)
+        return fail(ctx, ARB_E_ARG, "single-blob model: no blob slip velocity");
     const int N = ctx->N, M = ctx->M, Nc = ctx->Nc;
     Krylov K;
     TRY(krylov_buffers(ctx, K));
@@ -841,7 +921,15 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
     const double t1 = now_ms();
     inf->t_build_ms = t1 - t0;
 
-    arb::rhs_assemble(s, N, M, Nc, us, F, ctx->Bc.as<double>(), K.b);
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) {
+        // b = [N F; B]
+        TRY(body_mobility_dev(ctx, s, F, 1.0, nullptr, K.b));
+        if (Nc > 0)
+            HIPCHK(hipMemcpyAsync(K.b + 6 * (size_t)M, ctx->Bc.p, Nc * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+    } else {
+        arb::rhs_assemble(s, N, M, Nc, us, F, ctx->Bc.as<double>(), K.b);
+    }
     double bnorm = 0.0;
     TRY(dev_norm(ctx, s, K, K.b, 0, &bnorm));
     if (!std::isfinite(bnorm)) return fail(ctx, ARB_E_NAN, "right-hand side is not finite");
@@ -920,7 +1008,12 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         opt->restart > 256 || opt->max_iter < 1 ||
         (opt->precision != ARB_FP64 && opt->precision != ARB_FP32C) || opt->precond < 0 ||
         opt->precond > 3 || opt->slices < 0 || opt->slices > 4096 || opt->pair_kernel < 0 ||
-        opt->pair_kernel > 2 || opt->graphs < 0 || opt->graphs > 1)
+        opt->pair_kernel > 2 || opt->graphs < 0 || opt->graphs > 1 ||
+        (opt->model != ARB_MODEL_MULTIBLOB && opt->model != ARB_MODEL_SINGLE_BLOB))
+        return ARB_E_ARG;
+    // single-blob bodies: unbounded FP64 generalised RPY, exact or no preconditioner
+    if (opt->model == ARB_MODEL_SINGLE_BLOB &&
+        (opt->wall != 0 || opt->precision != ARB_FP64 || opt->precond > ARB_PC_BLOCK))
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
@@ -979,6 +1072,12 @@ int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset, const double
     }
     const int N = blob_offset[M];
     if (check_finite(ctx, r_ref, 3 * (size_t)N, "r_ref")) return ARB_E_NAN;
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) {
+        if (N != M) return fail(ctx, ARB_E_ARG, "single-blob model: one blob per body");
+        for (int i = 0; i < 3 * N; ++i)
+            if (r_ref[i] != 0.0)
+                return fail(ctx, ARB_E_ARG, "single-blob model: blobs sit at the tracking points");
+    }
     HIPCHK(hipSetDevice(ctx->opt.device));
     ctx->M = M;
     ctx->N = N;
@@ -1116,7 +1215,9 @@ int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n) {
     if (N) *N = ctx->N;
     if (M) *M = ctx->M;
     if (Nc) *Nc = nc;
-    if (n) *n = 3 * (int64_t)ctx->N + 6 * (int64_t)ctx->M + nc;
+    if (n)
+        *n = (ctx->opt.model == ARB_MODEL_SINGLE_BLOB ? 0 : 3 * (int64_t)ctx->N) +
+             6 * (int64_t)ctx->M + nc;
     return ARB_OK;
 }
 
@@ -1184,6 +1285,36 @@ int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda, 
     TRY(arb_rpy_apply_dev(ctx, N, ctx->s_in.as<double>(), ctx->s_aux.as<double>(),
                           ctx->s_out.as<double>(), s));
     HIPCHK(hipMemcpyAsync(u, ctx->s_out.p, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ARB_OK;
+}
+
+int arb_body_mobility_apply_dev(arb_ctx *ctx, const double *FT_dev, double *UW_dev,
+                                void *stream) {
+    if (!ctx || !FT_dev || !UW_dev) return ARB_E_ARG;
+    if (ctx->opt.model != ARB_MODEL_SINGLE_BLOB)
+        return fail(ctx, ARB_E_ARG, "body mobility product needs the single-blob model");
+    TRY(ready(ctx));
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    TRY(body_mobility_dev(ctx, s, FT_dev, 1.0, nullptr, UW_dev));
+    HIPCHK(hipGetLastError());
+    return ARB_OK;
+}
+
+int arb_body_mobility_apply(arb_ctx *ctx, const double *FT, double *UW) {
+    if (!ctx || !FT || !UW) return ARB_E_ARG;
+    if (ctx->opt.model != ARB_MODEL_SINGLE_BLOB)
+        return fail(ctx, ARB_E_ARG, "body mobility product needs the single-blob model");
+    TRY(ready(ctx));
+    const size_t m6 = 6 * (size_t)ctx->M;
+    if (check_finite(ctx, FT, m6, "FT")) return ARB_E_NAN;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    TRY(upload(ctx, ctx->s_in, FT, m6, s));
+    HIPCHK(ctx->s_out.ensure(m6 * sizeof(double)));
+    TRY(body_mobility_dev(ctx, s, ctx->s_in.as<double>(), 1.0, nullptr, ctx->s_out.as<double>()));
+    HIPCHK(hipMemcpyAsync(UW, ctx->s_out.p, m6 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
 }
@@ -1334,13 +1465,14 @@ int arb_solve(arb_ctx *ctx, const double *F, const double *u_slip, const double 
     if (rc < 0) return rc;
     ctx->ky_n = n;
     const double *yd = ctx->ky.as<double>();
-    if (lambda)
+    const int64_t uo = u_offset(ctx);
+    if (lambda && ctx->opt.model != ARB_MODEL_SINGLE_BLOB)
         HIPCHK(hipMemcpyAsync(lambda, yd, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost, s));
     if (U)
-        HIPCHK(hipMemcpyAsync(U, yd + 3 * (size_t)N, 6 * (size_t)M * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(U, yd + uo, 6 * (size_t)M * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
     if (phi && ctx->Nc > 0)
-        HIPCHK(hipMemcpyAsync(phi, yd + 3 * (size_t)N + 6 * (size_t)M, ctx->Nc * sizeof(double),
+        HIPCHK(hipMemcpyAsync(phi, yd + uo + 6 * (size_t)M, ctx->Nc * sizeof(double),
                               hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return rc;
@@ -1658,7 +1790,7 @@ int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double d
                              ctx->ky.as<double>(), w, &si, s);
     if (rc < 0) return rc;
     ctx->ky_n = n;
-    const double *Ud = ctx->ky.as<double>() + 3 * (size_t)N;
+    const double *Ud = ctx->ky.as<double>() + u_offset(ctx);
     // 2.-3. every body by explicit Euler (the mean of the new tracking points of
     // an articulated body is then q_COM + dt u_COM), orientations by
     // theta_{w dt} . theta

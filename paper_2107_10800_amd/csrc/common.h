@@ -186,6 +186,15 @@ struct CorrectDev {
 };
 void correct_positions(hipStream_t s, const CorrectDev &C, double tol, int max_iter);
 
+// Single-blob bodies (Sec. 2.4): generalised RPY product (rot_pair.hip), the
+// self-mobility blocks N~ and the preconditioner apply for y = [U; phi]
+int rot_pair_slices(int M);
+void rot_pair_apply(hipStream_t s, int M, const double4 *p64, const double *x6, double a,
+                    double scale, const double *base, double *partial, double *out);
+void single_blob_body_mobility(hipStream_t s, int M, double a, double eta, double *Nt);
+void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_off,
+                          const int64_t *zero_off64, const double *r, double *z);
+
 // Reconstruction of articulated bodies from their orientations (Sec. 4.1) and
 // the link residual.  Articulated bodies (bodies joined by links) are listed
 // as in CorrectDev; per body (by position in asm_bodies) a CSR list of its
@@ -282,6 +291,9 @@ struct arb_ctx {
     arb::DevBuf r_adj_ptr, r_adj, r_anch, r_goff, r_G, r_z, r_b, r_ginf, r_g2;
     // last solution of a solve (warm start of the next time step); ky_n = its length
     int64_t ky_n = 0;
+    // single-blob model: M+1 zero offsets (no blobs in the preconditioner's body
+    // stage), partial sums of the generalised RPY product, C^T phi
+    arb::DevBuf zero_off, zero_off64, rot_partial, rot_ct;
     arb::DevBuf tune_out;
     // learned body mobility: network parameters, workspace, per-type blocks
     arb::DevBuf mlp_params, mlp_ws, mlp_x, mlp_t, body_type_d, t_ref, t_mat_off, t_z_off, t_minv,

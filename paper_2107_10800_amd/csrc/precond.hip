@@ -1137,6 +1137,42 @@ hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec
 // doubles needed for the diagonal-block inverses of bodies holding n_blobs blobs
 int64_t precond_dinv_size(int64_t n_blobs, int M) { return 32 * 3 * n_blobs + 1024 * (int64_t)M; }
 
+// Single-blob bodies (Sec. 2.4 with Sec. 3.1): N~_p = diag(mt I, mr I), the
+// self mobilities 1/(6 pi eta a) and 1/(8 pi eta a^3)
+__global__ void single_blob_nt_kernel(int M, double mt, double mr, double *__restrict__ Nt) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 36 * M) return;
+    const int e = idx % 36, r = e / 6, c = e % 6;
+    Nt[idx] = r != c ? 0.0 : (r < 3 ? mt : mr);
+}
+
+__global__ void copy_kernel(int64_t n, const double *__restrict__ x, double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+void single_blob_body_mobility(hipStream_t s, int M, double a, double eta, double *Nt) {
+    if (M <= 0) return;
+    const double pi = 3.14159265358979323846;
+    single_blob_nt_kernel<<<(36 * M + 255) / 256, 256, 0, s>>>(
+        M, 1.0 / (6.0 * pi * eta * a), 1.0 / (8.0 * pi * eta * a * a * a), Nt);
+}
+
+// z = P^-1 r for y = [U; phi]: phi = G~ (r_phi - C r_U), U = r_U + N~ C^T phi.
+// These are the assembly and body stages of the multiblob apply with no blobs
+// (r_U takes the place of U^); zero_off / zero_off64 are M+1 zeros.
+void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_off,
+                          const int64_t *zero_off64, const double *r, double *z) {
+    if (P.M <= 0) return;
+    const int64_t m6 = 6 * (int64_t)P.M;
+    copy_kernel<<<(int)((m6 + 255) / 256), 256, 0, s>>>(m6, r, P.tmp);
+    if (P.A > 0)
+        pc_apply2_kernel<<<P.A, 256, 0, s>>>(0, P.M, P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
+                                             P.row_p, P.row_q, P.crow, P.G, r, P.tmp, z);
+    pc_apply3_kernel<<<P.M, 256, 0, s>>>(0, P.M, zero_off, zero_off64, P.Nt, P.Nt, P.brow_ptr,
+                                         P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);
+}
+
 void precond_assembly(hipStream_t s, const PrecondDev &P) {
     if (P.A <= 0) return;
     pc_asm_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p, P.row_q,

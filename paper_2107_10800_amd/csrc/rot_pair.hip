@@ -1,0 +1,149 @@
+// Body mobility of single-blob bodies (Sec. 2.4): the generalised RPY tensor,
+// unbounded, applied to the generalised forces (f, tau) of every body,
+//     (u_i, w_i) = sum_j N_ij (f_j, tau_j)      (all ordered pairs, i = j included).
+// With r = x_i - x_j, r = |r|, in units of 1/(8 pi eta):
+//     u_i += c1 f_j + c2 (r . f_j) r + c_r tau_j x r
+//     w_i += c_r f_j x r + d1 tau_j + d2 (r . tau_j) r
+// translation: c1, c2 of the RPY tensor (as in pair.hip);
+// r > 2a : c_r = 1/r^3, d1 = -1/(2 r^3), d2 = 3/(2 r^5);
+// r <= 2a: c_r = (1 - 3r/(8a)) / (2a^3),
+//          d1 = (1 - 27r/(32a) + 5r^3/(64a^3)) / a^3,
+//          d2 = (9/(32 a r) - 3r/(64a^3)) / a^3  (its r r^T term vanishes at r = 0).
+// At r = 0 this gives the self mobilities 1/(6 pi eta a), 1/(8 pi eta a^3).
+//
+// One target body per lane; source tiles of 256 bodies staged in LDS; the
+// sources are split into slices (grid y) whose partial sums a second kernel
+// adds in slice order (bitwise reproducible), scales and adds to a base vector.
+#include "rpy_device.h"
+
+namespace arb {
+
+namespace {
+
+constexpr int kRotTile = 256;
+
+struct RotCoef {
+    double k1, k2, n1, n2, n3, four_a2, e1, e2, g0, g1, g3, h1, h3;
+};
+
+RotCoef rot_coef(double a) {
+    RotCoef c;
+    const double a2 = a * a, a3 = a2 * a, a4 = a2 * a2, a6 = a3 * a3;
+    c.k1 = 2.0 * a2 / 3.0;
+    c.k2 = 2.0 * a2;
+    c.n1 = 4.0 / (3.0 * a);
+    c.n2 = 3.0 / (8.0 * a2);
+    c.n3 = 1.0 / (8.0 * a2);
+    c.four_a2 = 4.0 * a2;
+    c.e1 = 1.0 / (2.0 * a3);
+    c.e2 = 3.0 / (16.0 * a4);
+    c.g0 = 1.0 / a3;
+    c.g1 = 27.0 / (32.0 * a4);
+    c.g3 = 5.0 / (64.0 * a6);
+    c.h1 = 9.0 / (32.0 * a4);
+    c.h3 = 3.0 / (64.0 * a6);
+    return c;
+}
+
+__global__ __launch_bounds__(kRotTile) void rot_pair_f64_kernel(
+    int M, const double4 *__restrict__ p64, const double *__restrict__ x6, int tiles_per_slice,
+    RotCoef c, double *__restrict__ partial) {
+    __shared__ double4 s_p[kRotTile];
+    __shared__ double s_x[6 * kRotTile];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * kRotTile + tid;
+    const double4 ti = p64[i < M ? i : M - 1];
+    double ux = 0.0, uy = 0.0, uz = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
+    const int ntiles = (M + kRotTile - 1) / kRotTile;
+    const int t0 = blockIdx.y * tiles_per_slice;
+    const int t1 = min(t0 + tiles_per_slice, ntiles);
+    for (int t = t0; t < t1; ++t) {
+        const int j = t * kRotTile + tid;
+        __syncthreads();
+        if (j < M) {
+            s_p[tid] = p64[j];
+            for (int k = 0; k < 6; ++k) s_x[6 * tid + k] = x6[6 * (size_t)j + k];
+        }
+        __syncthreads();
+        const int cnt = min(kRotTile, M - t * kRotTile);
+        for (int k = 0; k < cnt; ++k) {
+            const double4 sj = s_p[k];
+            const double *x = s_x + 6 * k;
+            const double fx = x[0], fy = x[1], fz = x[2], tx = x[3], ty = x[4], tz = x[5];
+            const double dx = ti.x - sj.x, dy = ti.y - sj.y, dz = ti.z - sj.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const double rinv = rsq_f64(r2);
+            const double rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+            double c1 = fma(c.k1, rinv3, rinv);
+            double c2 = fma(-c.k2, rinv3 * rinv2, rinv3);
+            double cr = rinv3;
+            double d1 = -0.5 * rinv3;
+            double d2 = 1.5 * rinv3 * rinv2;
+            ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
+            if (r2 <= c.four_a2) {
+                const double rv = r2 > 0.0 ? rinv : 0.0;  // rinv is not finite at r = 0
+                const double r = r2 * rv;
+                c1 = fma(-c.n2, r, c.n1);
+                c2 = rv * c.n3;
+                cr = fma(-c.e2, r, c.e1);
+                d1 = fma(r, fma(c.g3, r * r, -c.g1), c.g0);
+                d2 = fma(c.h1, rv, -c.h3 * r);
+            }
+            ARB_END_IF_ANY
+            const double tf = c2 * fma(dx, fx, fma(dy, fy, dz * fz));
+            const double tt = d2 * fma(dx, tx, fma(dy, ty, dz * tz));
+            ux = fma(c1, fx, fma(tf, dx, fma(cr, fma(ty, dz, -tz * dy), ux)));
+            uy = fma(c1, fy, fma(tf, dy, fma(cr, fma(tz, dx, -tx * dz), uy)));
+            uz = fma(c1, fz, fma(tf, dz, fma(cr, fma(tx, dy, -ty * dx), uz)));
+            wx = fma(d1, tx, fma(tt, dx, fma(cr, fma(fy, dz, -fz * dy), wx)));
+            wy = fma(d1, ty, fma(tt, dy, fma(cr, fma(fz, dx, -fx * dz), wy)));
+            wz = fma(d1, tz, fma(tt, dz, fma(cr, fma(fx, dy, -fy * dx), wz)));
+        }
+    }
+    if (i < M) {
+        double *o = partial + (size_t)blockIdx.y * 6 * M + i;
+        o[0] = ux;
+        o[(size_t)M] = uy;
+        o[2 * (size_t)M] = uz;
+        o[3 * (size_t)M] = wx;
+        o[4 * (size_t)M] = wy;
+        o[5 * (size_t)M] = wz;
+    }
+}
+
+// out = base + scale * sum over slices (base may be NULL: zero)
+__global__ void rot_reduce_kernel(int M, int slices, const double *__restrict__ partial,
+                                  double scale, const double *__restrict__ base,
+                                  double *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    for (int k = 0; k < 6; ++k) {
+        double s = 0.0;
+        for (int sl = 0; sl < slices; ++sl) s += partial[((size_t)sl * 6 + k) * M + i];
+        const double b = base ? base[6 * (size_t)i + k] : 0.0;
+        out[6 * (size_t)i + k] = fma(scale, s, b);
+    }
+}
+
+}  // namespace
+
+int rot_pair_slices(int M) {
+    if (M <= 0) return 1;
+    const int ntiles = (M + kRotTile - 1) / kRotTile;
+    const int want = (2048 + ntiles - 1) / ntiles;   // about 2,048 workgroups
+    return std::max(1, std::min(want, ntiles));
+}
+
+void rot_pair_apply(hipStream_t s, int M, const double4 *p64, const double *x6, double a,
+                    double scale, const double *base, double *partial, double *out) {
+    if (M <= 0) return;
+    const int ntiles = (M + kRotTile - 1) / kRotTile;
+    const int slices = rot_pair_slices(M);
+    const int tps = (ntiles + slices - 1) / slices;
+    const int used = (ntiles + tps - 1) / tps;
+    rot_pair_f64_kernel<<<dim3(ntiles, used), kRotTile, 0, s>>>(M, p64, x6, tps, rot_coef(a),
+                                                                  partial);
+    rot_reduce_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, used, partial, scale, base, out);
+}
+
+}  // namespace arb
