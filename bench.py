@@ -36,6 +36,11 @@ FLOPS_SYM = {("f32c", True): 133, ("f32c", False): 58, ("f64", True): 128,
              ("f64", False): 52}
 
 
+# generalised RPY product of single-blob bodies (FP64, unbounded): one ordered pair,
+# same counting rules (translation, both couplings and rotation terms)
+FLOPS_ROT_PAIR = 85
+
+
 def algorithmic_flops(N, shape, prec="f32c", wall=True):
     """Flops of one product for the launch shape used (< 0: symmetric kernel)."""
     if shape > 0:
@@ -293,6 +298,79 @@ def timestep_bench(arb, W, n_bact=1024, dt=0.02, steps=3):
         arb.arb_destroy(ctx)
 
 
+def single_blob_bench(torch, arb, W, reps=5):
+    """Single-blob bodies (Sec. 2.4, unbounded, FP64): the generalised RPY product on
+    4,096 shells (172,032 bodies), and GMRES iterations to 1e-10 against the number of
+    shells (Sec. 3.2.2; random forces and torques, and gravity) and of filaments
+    (Sec. 3.2.1, 15 single blobs each, gravity, to 1e-8)."""
+    out = {}
+    wl = W.blob_shells(16)
+    ctx = arb.context_for(wl)
+    try:
+        dev = torch.device("cuda")
+        F = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
+        UW = torch.zeros_like(F)
+        stream = torch.cuda.Stream()
+        sh = stream.cuda_stream
+        arb.arb_body_mobility_apply_dev(ctx, F, UW, stream=sh)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            arb.arb_body_mobility_apply_dev(ctx, F, UW, stream=sh)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+    finally:
+        arb.arb_destroy(ctx)
+    M = wl.M
+    pairs = float(M) * M
+    tf = FLOPS_ROT_PAIR * pairs / (ms * 1e-3) / 1e12
+    out["product"] = dict(workload=f"generalised RPY product, 4096 shells of 42 single blobs, "
+                                   f"M={M}, unbounded", M=M, ms=ms,
+                          pairs_per_s=pairs / (ms * 1e-3), flops_per_pair=FLOPS_ROT_PAIR,
+                          achieved_tflops=tf, frac_of_fp64_peak=tf / PEAK_FP64_TFLOPS,
+                          kernel="rot_pair_f64_kernel")
+
+    def solve(wl, tol, timed):
+        c = arb.context_for(wl, tol=tol)
+        try:
+            Fd = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
+            y = torch.zeros(wl.n_unknowns - 3 * wl.N, dtype=torch.float64, device=dev)
+            if timed:
+                arb.arb_solve_dev(c, Fd, None, y, warm=False, stream=sh)      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = arb.arb_solve_dev(c, Fd, None, y, warm=False, stream=sh)
+            torch.cuda.synchronize()
+            return rc, info, 1e3 * (time.perf_counter() - t0)
+        finally:
+            arb.arb_destroy(c)
+
+    scan = []
+    for n_side in (1, 2, 4, 8, 16):
+        for forcing in ("random", "gravity"):
+            if n_side == 16 and forcing == "gravity":
+                continue
+            wl = W.blob_shells(n_side, forcing=forcing)
+            rc, info, ms = solve(wl, 1e-10, n_side < 16)
+            scan.append(dict(shells=n_side ** 3, forcing=forcing, M=wl.M, Nc=wl.n_rows,
+                             n=6 * wl.M + wl.n_rows, iterations=info["iterations"],
+                             rel_residual=info["rel_residual"], ms_per_solve=ms, status=rc))
+            log(f"bench: {n_side ** 3} shells ({forcing}): {info['iterations']} iterations, "
+                f"{ms:.1f} ms")
+    out["shell_scan"] = scan
+    fscan = []
+    for k in (1, 2, 5, 10, 20):
+        wl = W.blob_filaments(k, k)
+        rc, info, ms = solve(wl, 1e-8, True)
+        fscan.append(dict(filaments=k * k, M=wl.M, Nc=wl.n_rows, n=6 * wl.M + wl.n_rows,
+                          iterations=info["iterations"], rel_residual=info["rel_residual"],
+                          ms_per_solve=ms, status=rc))
+    out["filament_scan"] = fscan
+    return out
+
+
 def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, log=log):
     """Learned body-mobility preconditioner vs exact block and body-frame blocks."""
     import numpy as np
@@ -456,6 +534,15 @@ def main():
         except Exception as e:          # reported, not fatal to the headline line
             res["timestep"] = {"error": str(e)}
             log(f"bench: time steps failed: {e}")
+        log("bench: single-blob bodies (generalised RPY), f64")
+        try:
+            res["single_blob"] = single_blob_bench(torch, arb, W)
+            pr = res["single_blob"]["product"]
+            log(f"bench: generalised RPY product {pr['ms']:.1f} ms, {pr['pairs_per_s']:.3e} "
+                f"pairs/s, {pr['frac_of_fp64_peak']:.3f} of FP64 peak")
+        except Exception as e:          # reported, not fatal to the headline line
+            res["single_blob"] = {"error": str(e)}
+            log(f"bench: single-blob bodies failed: {e}")
         log("bench: GMRES solve, diatom colonies, f32c")
         res["diatoms"] = solve_bench(torch, arb, W.diatoms(),
                                      "256 unbounded diatom colonies of 5-40 plates (15 x 3 blobs) "
