@@ -21,6 +21,9 @@ Sec. 4.3 (explicit Euler with reconstruction and correction), one step:
   4. rebuild the bodies from the new orientations (Sec. 4.1);
   5. g* = g(q*, theta*): accepted if ||g*||_2^2 < delta, otherwise the
      correction of Sec. 4.2 is applied.
+App. C (explicit midpoint): steps 2-5 over dt/2 with U^k give the midpoint
+state; step 1 there gives U^(k+1/2); steps 2-5 over dt from the initial state
+with U^(k+1/2) give the new state.
 
 Readings (where the paper is silent):
   * q_COM at the start of a step is the mean of the current tracking points,
@@ -106,17 +109,13 @@ def solve_velocities(wl, q, theta, F=None):
     return U.reshape(-1, 6), y
 
 
-def euler_step(wl, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50, F=None, U=None):
-    """One explicit Euler step with reconstruction and correction (Sec. 4.3).
-
-    U: body velocities (M,6) to use instead of solving step 1 (for tests that
-    compare the integrator alone).  Returns (q_new, theta_new, info) with
-    info: U, q_star, theta_star, g_star (P,3), g2_star, g_inf_star, corrected,
-    corr (the correction's info or None), g_inf (after the step)."""
+def advance(wl, q, theta, U, dt, delta, corr_tol=1e-10, corr_max_iter=50):
+    """Steps 2-5 of Sec. 4.3 from the state (q, theta) with body velocities U (M,6)
+    over dt: u_COM (Eq. ucom), COM and orientation update, rebuild (Sec. 4.1),
+    check ||g*||^2 < delta, else the correction of Sec. 4.2.  Returns
+    (q_new, theta_new, info) as euler_step."""
     q = np.array(q, float)
     theta = np.array(theta, float)
-    if U is None:
-        U, _ = solve_velocities(wl, q, theta, F)
     U = np.asarray(U, float).reshape(-1, 6)
     # step 3 for the orientations, and the plain Euler step for bodies without links
     theta_s = quat_mul(quat_from_rotvec(dt * U[:, 3:]), theta)
@@ -144,3 +143,39 @@ def euler_step(wl, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50, F=None
     gn = bodies.link_residual(wl, q_n, th_n)
     info["g_inf"] = float(np.max(np.abs(gn))) if gn.size else 0.0
     return q_n, th_n, info
+
+
+def euler_step(wl, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50, F=None, U=None,
+               solve=None):
+    """One explicit Euler step with reconstruction and correction (Sec. 4.3).
+
+    U: body velocities (M,6) to use instead of solving step 1 (for tests that
+    compare the integrator alone); solve(wl, q, theta, F) -> U replaces the
+    dense multiblob solve (e.g. for single-blob bodies).  Returns (q_new,
+    theta_new, info) with info: U, q_star, theta_star, g_star (P,3), g2_star,
+    g_inf_star, corrected, corr (the correction's info or None), g_inf (after
+    the step)."""
+    if U is None:
+        U = (solve or _solve_multiblob)(wl, q, theta, F)
+    return advance(wl, q, theta, U, dt, delta, corr_tol, corr_max_iter)
+
+
+def midpoint_step(wl, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50, F=None,
+                  solve=None):
+    """One explicit midpoint (RK2) step with reconstruction and correction (App. C):
+    velocities U^k at the state; a half step dt/2 (rebuild, check, correction) to
+    the midpoint state; velocities U^(k+1/2) there; the full step dt from the
+    initial state with U^(k+1/2) (rebuild, check, correction).  Returns
+    (q_new, theta_new, info) with info['half'] the half step's info and
+    info['U_half'] = U^(k+1/2)."""
+    solve = solve or _solve_multiblob
+    U0 = solve(wl, q, theta, F)
+    qh, thh, ih = advance(wl, q, theta, U0, 0.5 * dt, delta, corr_tol, corr_max_iter)
+    Uh = solve(wl, qh, thh, F)
+    qn, thn, info = advance(wl, q, theta, Uh, dt, delta, corr_tol, corr_max_iter)
+    info.update(half=ih, U0=np.asarray(U0).reshape(-1, 6), U_half=np.asarray(Uh).reshape(-1, 6))
+    return qn, thn, info
+
+
+def _solve_multiblob(wl, q, theta, F):
+    return solve_velocities(wl, q, theta, F)[0]

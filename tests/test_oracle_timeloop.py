@@ -182,3 +182,38 @@ def test_bodies_without_links_take_the_plain_euler_step():
     U = np.random.default_rng(9).standard_normal((wl.M, 6))
     q, th, info = timeloop.euler_step(wl, wl.q, wl.theta, 0.1, delta=np.inf, U=U)
     assert np.abs(q - (wl.q + 0.1 * U[:, :3])).max() < 1e-15
+
+
+def _integrate(wl, step, T, n, **kw):
+    q, th = wl.q.copy(), wl.theta.copy()
+    for _ in range(n):
+        q, th, _ = step(wl, q, th, T / n, **kw)
+    return q, th
+
+
+def test_global_order_euler_one_midpoint_two():
+    """Sec. 4.4 and App. C: with reconstruction and correction, explicit Euler
+    keeps first-order and the explicit midpoint scheme second-order global
+    convergence (errors at t = 2 against 64 midpoint steps, ring of 6 bodies)."""
+    wl = W.ring(n_bodies=6)
+    wl.F = 20.0 * wl.F
+    T = 2.0
+    kw = dict(delta=1e-20, corr_tol=1e-13)
+    ref = _integrate(wl, timeloop.midpoint_step, T, 64, **kw)[0]
+    for step, order in ((timeloop.euler_step, 1), (timeloop.midpoint_step, 2)):
+        errs = [np.abs(_integrate(wl, step, T, n, **kw)[0] - ref).max() for n in (4, 8, 16)]
+        for a, b in zip(errs, errs[1:]):
+            assert 0.8 * 2 ** order < a / b < 1.25 * 2 ** order, (step.__name__, errs)
+
+
+def test_midpoint_step_stages():
+    """App. C: the half step uses U^k over dt/2, the full step restarts from the
+    initial state with the midpoint velocities over dt."""
+    wl = W.ring()
+    q, th, info = timeloop.midpoint_step(wl, wl.q, wl.theta, 0.3, delta=np.inf)
+    qh, thh, _ = timeloop.advance(wl, wl.q, wl.theta, info["U0"], 0.15, np.inf)
+    assert np.allclose(info["half"]["q_star"], qh, atol=0, rtol=0)
+    U_half, _ = timeloop.solve_velocities(wl, qh, thh)
+    assert np.allclose(info["U_half"], U_half, atol=1e-14)
+    q2, th2, _ = timeloop.advance(wl, wl.q, wl.theta, U_half, 0.3, np.inf)
+    assert np.abs(q - q2).max() < 1e-13 and np.abs(th - th2).max() < 1e-13
