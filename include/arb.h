@@ -283,6 +283,20 @@ int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double d
                    double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
                    double *U, arb_step_info *info);
 
+/* One explicit midpoint (RK2) step with reconstruction and correction (App. C):
+ * U^k at the context's state (warm as for arb_step_euler); steps 2-5 of
+ * arb_step_euler over dt/2 to the midpoint state; U^(k+1/2) there (GMRES
+ * warm-started from U^k's solution); steps 2-5 over dt from the initial state
+ * with U^(k+1/2).  Arguments as for arb_step_euler; U receives U^(k+1/2).
+ * info: iterations summed over the two solves, rel_residual the larger, the
+ * constraint figures of the full step (corrected = 1 if either stage
+ * corrected, corr_iterations the larger).  Returns ARB_W_NOT_CONVERGED if
+ * either solve did not converge, else the first warning of the two, or an
+ * error. */
+int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                      double delta, double corr_tol, int corr_max_iter, int warm, double *q,
+                      double *theta, double *U, arb_step_info *info);
+
 /* Position/orientation correction (Sec. 4.2, Eq. min_probl, App. B): per
  * assembly, Levenberg-Marquardt on the link residuals g_n plus
  * ||dtheta_p||^2 - 1, exact Jacobian, mu = ||F||^2, until ||F||_2 <= tol or

@@ -48,7 +48,7 @@ SYMBOLS = [
     "arb_profile_read", "arb_mlp_set_params", "arb_mlp_get_params", "arb_mlp_forward",
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
     "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
-    "arb_body_mobility_apply", "arb_body_mobility_apply_dev",
+    "arb_body_mobility_apply", "arb_body_mobility_apply_dev", "arb_step_midpoint",
 ]
 
 
@@ -148,6 +148,9 @@ def load():
         "arb_mlp_set_scaling": (C.c_int, [_P, _FP, _FP, _FP, _FP]),
         "arb_profile_read": (C.c_int, [_P, _DP, C.POINTER(C.c_int)]),
         "arb_reconstruct": (C.c_int, [_P, _DP, _DP, _DP]),
+        "arb_step_midpoint": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double,
+                                        C.c_int, C.c_int, _DP, _DP, _DP,
+                                        C.POINTER(arb_step_info)]),
         "arb_body_mobility_apply": (C.c_int, [_P, _DP, _DP]),
         "arb_body_mobility_apply_dev": (C.c_int, [_P, _P, _P, _P]),
         "arb_link_residual": (C.c_int, [_P, _DP, _DP]),
@@ -439,6 +442,22 @@ def arb_step_euler(ctx, F, dt, delta=1e-10, corr_tol=1e-10, corr_max_iter=50, wa
     rc = _check(ctx, load().arb_step_euler(ctx, Fp, usp, float(dt), float(delta),
                                            float(corr_tol), int(corr_max_iter), int(bool(warm)),
                                            qp, tp, Up, C.byref(info)))
+    return rc, q.reshape(M, 3), t.reshape(M, 4), U.reshape(M, 6), info.to_dict()
+
+
+def arb_step_midpoint(ctx, F, dt, delta=1e-10, corr_tol=1e-10, corr_max_iter=50, warm=True,
+                      u_slip=None):
+    """Returns (status, q (M,3), theta (M,4), U^(k+1/2) (M,6), info dict) after one step."""
+    N, M, _, _ = arb_sizes(ctx)
+    F_, Fp = _d(F, 6 * M)
+    us_, usp = _d(u_slip, 3 * N) if u_slip is not None else (None, None)
+    q, qp = _out(3 * M)
+    t, tp = _out(4 * M)
+    U, Up = _out(6 * M)
+    info = arb_step_info()
+    rc = _check(ctx, load().arb_step_midpoint(ctx, Fp, usp, float(dt), float(delta),
+                                              float(corr_tol), int(corr_max_iter),
+                                              int(bool(warm)), qp, tp, Up, C.byref(info)))
     return rc, q.reshape(M, 3), t.reshape(M, 4), U.reshape(M, 6), info.to_dict()
 
 

@@ -1766,65 +1766,144 @@ int arb_link_residual(arb_ctx *ctx, double *g_inf, double *g2) {
     return ARB_OK;
 }
 
-int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
-                   double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
-                   double *U, arb_step_info *info) {
+// figures of one advance (steps 2-5 of Sec. 4.3)
+struct AdvanceInfo {
+    double g_inf_star = 0.0, g2_star = 0.0, corr_residual = 0.0, g_inf = 0.0;
+    int corrected = 0, corr_iterations = 0;
+};
+
+// steps 2-5 of Sec. 4.3 from the context's state with body velocities Ud (device,
+// 6M) over dt: every body by explicit Euler (the mean of the new tracking points
+// of an articulated body is then q_COM + dt u_COM), orientations by
+// theta_{w dt} . theta, rebuild, check sum g.g < delta, else correction
+static int advance_dev(arb_ctx *ctx, hipStream_t s, const double *Ud, double dt, double delta,
+                       double corr_tol, int corr_max_iter, AdvanceInfo *ai) {
+    arb::euler_update(s, ctx->M, Ud, dt, ctx->q.as<double>(), ctx->theta.as<double>());
+    HIPCHK(hipGetLastError());
+    TRY(recon_run(ctx, s, 1, &ai->g_inf_star, &ai->g2_star));
+    ai->g_inf = ai->g_inf_star;
+    if (ctx->lasm_A > 0 && !(ai->g2_star < delta)) {
+        TRY(correct_run(ctx, s, corr_tol, corr_max_iter, &ai->corr_iterations, &ai->corr_residual));
+        ai->corrected = 1;
+        double g2e = 0.0;
+        TRY(recon_run(ctx, s, 0, &ai->g_inf, &g2e));
+    }
+    TRY(refresh_geometry(ctx, s));
+    return 0;
+}
+
+// common checks and uploads of the time-step entry points; F, u_slip land in
+// s_in / s_aux
+static int step_prologue(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                         double delta, double corr_tol, int corr_max_iter) {
     if (!ctx || !F) return ARB_E_ARG;
     if (!std::isfinite(dt) || std::isnan(delta) || !(corr_tol > 0) || corr_max_iter < 0)
         return fail(ctx, ARB_E_ARG, "bad time-step arguments");
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
     const int N = ctx->N, M = ctx->M;
-    const int64_t n = n_unknowns(ctx);
     if (check_finite(ctx, F, 6 * (size_t)M, "F") ||
         check_finite(ctx, u_slip, u_slip ? 3 * (size_t)N : 0, "u_slip"))
         return ARB_E_NAN;
-    hipStream_t s = ctx->stream;
-    // 1. velocities at t_k, from the previous step's solution when warm
-    TRY(upload(ctx, ctx->s_in, F, 6 * (size_t)M, s));
-    if (u_slip) TRY(upload(ctx, ctx->s_aux, u_slip, 3 * (size_t)N, s));
-    HIPCHK(ctx->ky.ensure(n * sizeof(double)));
+    TRY(upload(ctx, ctx->s_in, F, 6 * (size_t)M, ctx->stream));
+    if (u_slip) TRY(upload(ctx, ctx->s_aux, u_slip, 3 * (size_t)N, ctx->stream));
+    HIPCHK(ctx->ky.ensure(n_unknowns(ctx) * sizeof(double)));
+    return 0;
+}
+
+// step 1 of Sec. 4.3 at the context's state into ky (warm: from ky's previous
+// solution when its length matches)
+static int step_solve(arb_ctx *ctx, hipStream_t s, bool has_slip, int warm, arb_solve_info *si) {
+    const int64_t n = n_unknowns(ctx);
     const int w = (warm && ctx->ky_n == n) ? 1 : 0;
+    const int rc = solve_dev(ctx, ctx->s_in.as<double>(), has_slip ? ctx->s_aux.as<double>() : nullptr,
+                             ctx->ky.as<double>(), w, si, s);
+    if (rc >= 0) ctx->ky_n = n;
+    return rc;
+}
+
+static void fill_step_info(arb_step_info *info, int rc, const arb_solve_info &si,
+                           const AdvanceInfo &ai) {
+    if (!info) return;
+    info->solve_status = rc;
+    info->iterations = si.iterations;
+    info->rel_residual = si.rel_residual;
+    info->t_build_ms = si.t_build_ms;
+    info->t_solve_ms = si.t_solve_ms;
+    info->g_inf_star = ai.g_inf_star;
+    info->g2_star = ai.g2_star;
+    info->corrected = ai.corrected;
+    info->corr_iterations = ai.corr_iterations;
+    info->corr_residual = ai.corr_residual;
+    info->g_inf = ai.g_inf;
+}
+
+int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
+                   double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
+                   double *U, arb_step_info *info) {
+    TRY(step_prologue(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter));
+    hipStream_t s = ctx->stream;
     arb_solve_info si{};
-    const int rc = solve_dev(ctx, ctx->s_in.as<double>(), u_slip ? ctx->s_aux.as<double>() : nullptr,
-                             ctx->ky.as<double>(), w, &si, s);
+    const int rc = step_solve(ctx, s, u_slip != nullptr, warm, &si);
     if (rc < 0) return rc;
-    ctx->ky_n = n;
     const double *Ud = ctx->ky.as<double>() + u_offset(ctx);
-    // 2.-3. every body by explicit Euler (the mean of the new tracking points of
-    // an articulated body is then q_COM + dt u_COM), orientations by
-    // theta_{w dt} . theta
-    arb::euler_update(s, M, Ud, dt, ctx->q.as<double>(), ctx->theta.as<double>());
-    HIPCHK(hipGetLastError());
-    // 4. rebuild the articulated bodies at the new orientations
-    double gi = 0.0, gs = 0.0;
-    TRY(recon_run(ctx, s, 1, &gi, &gs));
-    // 5. check, and correct when the links are violated beyond delta
-    int corrected = 0, cit = 0;
-    double cres = 0.0, gi_end = gi;
-    if (ctx->lasm_A > 0 && !(gs < delta)) {
-        TRY(correct_run(ctx, s, corr_tol, corr_max_iter, &cit, &cres));
-        corrected = 1;
-        double g2e = 0.0;
-        TRY(recon_run(ctx, s, 0, &gi_end, &g2e));
-    }
-    TRY(refresh_geometry(ctx, s));
+    AdvanceInfo ai;
+    TRY(advance_dev(ctx, s, Ud, dt, delta, corr_tol, corr_max_iter, &ai));
+    TRY(copy_state_out(ctx, s, q, theta));
+    if (U)
+        HIPCHK(hipMemcpyAsync(U, Ud, 6 * (size_t)ctx->M * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
+    HIPCHK(hipStreamSynchronize(s));
+    fill_step_info(info, rc, si, ai);
+    return rc;
+}
+
+int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                      double delta, double corr_tol, int corr_max_iter, int warm, double *q,
+                      double *theta, double *U, arb_step_info *info) {
+    TRY(step_prologue(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter));
+    hipStream_t s = ctx->stream;
+    const int M = ctx->M;
+    // the initial state, to which the full step returns
+    HIPCHK(ctx->q0.ensure(3 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->th0.ensure(4 * (size_t)M * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(ctx->q0.p, ctx->q.p, 3 * (size_t)M * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->th0.p, ctx->theta.p, 4 * (size_t)M * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    const double *Ud = ctx->ky.as<double>() + u_offset(ctx);
+    // U^k, half step to the midpoint state
+    arb_solve_info s0{};
+    const int rc0 = step_solve(ctx, s, u_slip != nullptr, warm, &s0);
+    if (rc0 < 0) return rc0;
+    AdvanceInfo ah;
+    TRY(advance_dev(ctx, s, Ud, 0.5 * dt, delta, corr_tol, corr_max_iter, &ah));
+    // U^(k+1/2) at the midpoint state, warm-started from U^k's solution
+    arb_solve_info s1{};
+    const int rc1 = step_solve(ctx, s, u_slip != nullptr, 1, &s1);
+    if (rc1 < 0) return rc1;
+    // full step from the initial state
+    HIPCHK(hipMemcpyAsync(ctx->q.p, ctx->q0.p, 3 * (size_t)M * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->theta.p, ctx->th0.p, 4 * (size_t)M * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    AdvanceInfo af;
+    TRY(advance_dev(ctx, s, Ud, dt, delta, corr_tol, corr_max_iter, &af));
     TRY(copy_state_out(ctx, s, q, theta));
     if (U) HIPCHK(hipMemcpyAsync(U, Ud, 6 * (size_t)M * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (info) {
-        info->solve_status = rc;
-        info->iterations = si.iterations;
-        info->rel_residual = si.rel_residual;
-        info->t_build_ms = si.t_build_ms;
-        info->t_solve_ms = si.t_solve_ms;
-        info->g_inf_star = gi;
-        info->g2_star = gs;
-        info->corrected = corrected;
-        info->corr_iterations = cit;
-        info->corr_residual = cres;
-        info->g_inf = gi_end;
-    }
+    arb_solve_info st = s1;
+    st.iterations = s0.iterations + s1.iterations;
+    st.rel_residual = std::max(s0.rel_residual, s1.rel_residual);
+    st.t_build_ms = s0.t_build_ms + s1.t_build_ms;
+    st.t_solve_ms = s0.t_solve_ms + s1.t_solve_ms;
+    af.corrected |= ah.corrected;
+    af.corr_iterations = std::max(af.corr_iterations, ah.corr_iterations);
+    // a solve that did not converge outranks other warnings
+    const int rc = (rc0 == ARB_W_NOT_CONVERGED || rc1 == ARB_W_NOT_CONVERGED)
+                       ? ARB_W_NOT_CONVERGED
+                       : (rc0 > 0 ? rc0 : rc1);
+    fill_step_info(info, rc, st, af);
     return rc;
 }
 

@@ -294,6 +294,8 @@ struct arb_ctx {
     // single-blob model: M+1 zero offsets (no blobs in the preconditioner's body
     // stage), partial sums of the generalised RPY product, C^T phi
     arb::DevBuf zero_off, zero_off64, rot_partial, rot_ct;
+    // the initial state of a midpoint step
+    arb::DevBuf q0, th0;
     arb::DevBuf tune_out;
     // learned body mobility: network parameters, workspace, per-type blocks
     arb::DevBuf mlp_params, mlp_ws, mlp_x, mlp_t, body_type_d, t_ref, t_mat_off, t_z_off, t_minv,

@@ -221,3 +221,75 @@ def test_step_argument_errors():
                 arb.arb_step_euler(ctx, wl.F, dt, **kw)
     finally:
         arb.arb_destroy(ctx)
+
+
+def _single_blob_solve(wl, q, theta, F):
+    from oracle import single_blob
+    S = single_blob.assemble(wl, q, theta, F)
+    return single_blob.solve_dense(S)[:6 * wl.M].reshape(-1, 6)
+
+
+def _filament_forces_only():
+    """The filament with its torques removed: the rods' free axial spin keeps the
+    system consistent at every orientation only without applied torques."""
+    wl = W.filament()
+    wl.F[:, 3:] = 0.0
+    return wl
+
+
+MID_CASES = {
+    "ring": (lambda: W.ring(), None),
+    "ring_wall": (lambda: W.ring(n_bodies=9, wall=True, tilt=0.4, seed=10), None),
+    "filament": (_filament_forces_only, None),
+    "blob_shell": (lambda: W.blob_shells(1), _single_blob_solve),
+}
+
+
+@pytest.mark.parametrize("name", list(MID_CASES))
+@pytest.mark.parametrize("delta", [np.inf, 1e-20])
+def test_midpoint_step_matches_oracle(name, delta):
+    """App. C: one explicit midpoint step against the oracle's (dense solves at
+    both stages)."""
+    make, solve = MID_CASES[name]
+    wl = make()
+    dt = 0.2
+    print(f"midpoint step {name} delta={delta}: M={wl.M}", flush=True)
+    ctx = arb.context_for(wl, tol=1e-12)
+    try:
+        rc, q, th, U, info = arb.arb_step_midpoint(ctx, wl.F, dt, delta=delta, corr_tol=1e-12,
+                                                    warm=False)
+    finally:
+        arb.arb_destroy(ctx)
+    assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED) and info["rel_residual"] <= 1e-12
+    q_ref, th_ref, ref = timeloop.midpoint_step(wl, wl.q, wl.theta, dt, delta=delta,
+                                                corr_tol=1e-12, solve=solve)
+    scale = 1.0 + np.abs(wl.q).max()
+    assert np.abs(U - ref["U_half"]).max() <= 1e-8 * np.abs(ref["U_half"]).max()
+    assert np.abs(q - q_ref).max() <= 1e-9 * scale
+    assert np.abs(th - th_ref).max() <= 1e-9
+    assert info["corrected"] == int(ref["corrected"] or ref["half"]["corrected"])
+
+
+def test_midpoint_is_second_order_on_gpu():
+    """Global error at t = 2 of 4, 8, 16 midpoint steps against 64 (ring of 6
+    bodies): ratios near 4; explicit Euler near 2."""
+    wl = W.ring(n_bodies=6)
+    F = 20.0 * wl.F
+    T = 2.0
+    ctx = arb.context_for(wl, tol=1e-12)
+
+    def run(step, n):
+        arb.arb_set_state(ctx, wl.q, wl.theta)
+        for _ in range(n):
+            rc, q, th, U, info = step(ctx, F, T / n, delta=1e-20, corr_tol=1e-13)
+        return q
+
+    try:
+        ref = run(arb.arb_step_midpoint, 64)
+        for step, order in ((arb.arb_step_euler, 1), (arb.arb_step_midpoint, 2)):
+            errs = [np.abs(run(step, n) - ref).max() for n in (4, 8, 16)]
+            print(step.__name__, errs, flush=True)
+            for a, b in zip(errs, errs[1:]):
+                assert 0.8 * 2 ** order < a / b < 1.25 * 2 ** order
+    finally:
+        arb.arb_destroy(ctx)
