@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
     const int ic = i < N ? i : N - 1;
     const float4 th = hi[ic], tl = lo[ic];
     const float zi = th.z + tl.z;
+    const TargetZ<float> zsc = target_z(zi);
     double ux = 0.0, uy = 0.0, uz = 0.0;
     const int ntiles = (N + kTile - 1) / kTile;
     const int t0 = blockIdx.y * tiles_per_slice;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
                     const PairCoef<float> w =
-                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, sl.w, Rz, Ri, c);
+                        wall_pair_coef<float>(r2, rinv, dxy2, zsc, sh.z, sh.w, sl.w, Rz, Ri, c);
                     wall_pair_apply<float>(w, w.c, w.d, dx, dy, dz, Rz, L.x, L.y, L.z, ax, ay, az);
                 } else {
                     rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, ax, ay, az);
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
     const int i = blockIdx.x * kTile + tid;
     const int ic = i < N ? i : N - 1;
     const double4 ti = p64[ic];
+    const TargetZ<double> zsc = target_z(ti.z);
     double ux = 0.0, uy = 0.0, uz = 0.0;
     const int ntiles = (N + kTile - 1) / kTile;
     const int t0 = blockIdx.y * tiles_per_slice;
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
                 const double Rz = ti.z + sj.z;
                 const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                 const PairCoef<double> w =
-                    wall_pair_coef<double>(r2, rinv, ti.z, sj.z, sj.w, -(sj.w * sj.w), Rz, Ri, c);
+                    wall_pair_coef<double>(r2, rinv, dxy2, zsc, sj.z, sj.w, -(sj.w * sj.w), Rz, Ri, c);
                 wall_pair_apply<double>(w, w.c, w.d, dx, dy, dz, Rz, lx, ly, lz, ux, uy, uz);
             } else {
                 rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);

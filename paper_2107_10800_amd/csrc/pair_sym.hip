@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
     const int i = (4 * it.x + w) * 64 + lane;
     const Blob32 t = load_blob(i, N, hi, lo, lam);
     const float zi = t.hi.z + t.lo.z;
+    const TargetZ<float> zsc = target_z(zi);
     const int src = (lane + 1) & 63;
     double ux = 0.0, uy = 0.0, uz = 0.0;
     for (int J = it.y; J < it.y + it.z; ++J) {
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
                     const PairCoef<float> q =
-                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, sl.w, Rz, Ri, c);
+                        wall_pair_coef<float>(r2, rinv, dxy2, zsc, sh.z, sh.w, sl.w, Rz, Ri, c);
                     wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                 } else {
                     rpy_free<float>(dx, dy, dz, r2, rinv, L.x, L.y, L.z, c, fx, fy, fz);
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                     const float Rz = zi + sh.z;
                     const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
                     const PairCoef<float> q =
-                        wall_pair_coef<float>(r2, rinv, zi, sh.z, sh.w, sl.w, Rz, Ri, c);
+                        wall_pair_coef<float>(r2, rinv, dxy2, zsc, sh.z, sh.w, sl.w, Rz, Ri, c);
                     wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                     wall_pair_apply<float>(q, q.d, q.c, dx, dy, dz, Rz, t.lam.x, t.lam.y, t.lam.z,
                                            ax, ay, az);
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
     const int i = (4 * it.x + w) * 64 + lane;
     double4 tp, tl;
     load_blob64(i, N, p64, lam, tp, tl);
+    const TargetZ<double> zsc = target_z(tp.z);
     const int src = (lane + 1) & 63;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int J = it.y; J < it.y + it.z; ++J) {
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                     const double Rz = tp.z + sp.z;
                     const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                     const PairCoef<double> q =
-                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, -(sp.w * sp.w), Rz,
+                        wall_pair_coef<double>(r2, rinv, dxy2, zsc, sp.z, sp.w, -(sp.w * sp.w), Rz,
                                                Ri, c);
                     wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                 } else {
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                     const double Rz = tp.z + sp.z;
                     const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
                     const PairCoef<double> q =
-                        wall_pair_coef<double>(r2, rinv, tp.z, sp.z, sp.w, -(sp.w * sp.w), Rz,
+                        wall_pair_coef<double>(r2, rinv, dxy2, zsc, sp.z, sp.w, -(sp.w * sp.w), Rz,
                                                Ri, c);
                     wall_pair_apply<double>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
                     wall_pair_apply<double>(q, q.d, q.c, dx, dy, dz, Rz, tl.x, tl.y, tl.z, ax, ay,

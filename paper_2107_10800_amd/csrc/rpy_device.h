@@ -68,6 +68,7 @@ __device__ __forceinline__ void rpy_free(T dx, T dy, T dz, T r2, T rinv, T lx, T
 // e = R Ri, p = a^2 Ri^2 and the image I = Ri [A^ delta + B^ e e^T + C^ e z^T +
 // D^ z e^T + E^ z z^T] (units 1/(8 pi eta)), every coefficient is a polynomial in
 // s = Ri^2, t = (e.z)^2 and q = z_i z_j: for instance h/|R| (h/|R| - e.z) = -s q.
+// (t is formed as 1 - (dx^2 + dy^2) s, q through pre-scaled target heights.)
 // Absorbing the powers of Ri gives
 //   M_ij l = (c1 + a) l + (c2 (d.l)) d + (b (R.l) + c l_z) R + (d' (R.l) + e l_z) z
 // with a = Ri A^, b = Ri^3 B^, c = Ri^2 C^, d' = Ri^2 D^, e = Ri E^ and the free
@@ -79,11 +80,23 @@ struct PairCoef {
     T cA, cAe, c2, b, c, d, e, h2;  // cAe = cA + e (the z row)
 };
 
-// rinv = 1/sqrt(r2) (infinite for coincident blobs), h2 = 2 zj, mh22 = -h2^2,
-// Rz = zi + zj
+// Target-side heights scaled once per target: zs = (-2 zi, 6 zi, -12 zi), so that the
+// q = zi zj terms of the image coefficients are single FMAs with zj.
+template <class T>
+struct TargetZ {
+    T a, b, c;
+};
+template <class T>
+__device__ __forceinline__ TargetZ<T> target_z(T zi) {
+    return TargetZ<T>{T(-2) * zi, T(6) * zi, T(-12) * zi};
+}
+
+// rinv = 1/sqrt(r2) (infinite for coincident blobs), dxy2 = dx^2 + dy^2,
+// zs = target_z(zi), h2 = 2 zj, mh22 = -h2^2, Rz = zi + zj, Ri = 1/|R|
 template <class T, class C>
-__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, T h2, T mh22,
-                                                      T Rz, T Ri, const C &k) {
+__device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T dxy2, const TargetZ<T> &zs,
+                                                      T zj, T h2, T mh22, T Rz, T Ri,
+                                                      const C &k) {
     PairCoef<T> w;
     const T rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
     T c1 = fma(k.k1, rinv3, rinv);
@@ -98,19 +111,17 @@ __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T zi, T zj, 
     const T s = Ri * Ri;
     const T Ri3 = Ri * s;
     const T Ri5 = Ri3 * s;
-    const T u = Rz * Ri;
-    const T t = u * u;
-    const T q = zi * zj;
+    const T t = fma(-dxy2, s, T(1));  // (e.z)^2 = Rz^2 / R^2 = 1 - dxy2 / R^2
     const T a4s = k.a4 * s;
     const T RzRi5 = Rz * Ri5;
     const T h2Ri3 = h2 * Ri3;
     const T a2 = k.a2;
     const T iA = fma(a4s, fma(T(-10.0 / 3.0), t, T(2.0 / 3.0)),
-                     fma(T(2) * a2, t, fma(T(-2), q, T(-2.0 / 3.0) * a2)));
+                     fma(T(2) * a2, t, fma(zs.a, zj, T(-2.0 / 3.0) * a2)));
     const T iB = fma(a4s, fma(T(70.0 / 3.0), t, T(-10.0 / 3.0)),
-                     fma(T(-10) * a2, t, fma(T(6), q, T(2) * a2)));
+                     fma(T(-10) * a2, t, fma(zs.b, zj, T(2) * a2)));
     const T iC = fma(a4s, fma(T(-140.0 / 3.0), t, T(40.0 / 3.0)),
-                     fma(T(20) * a2, t, fma(T(-12), q, T(-4) * a2)));
+                     fma(T(20) * a2, t, fma(zs.c, zj, T(-4) * a2)));
     const T iE = fma(a4s, fma(T(20), t, T(-8.0 / 3.0)), fma(T(-4) * a2, t, mh22));
     w.cA = c1 + fma(Ri3, iA, -Ri);
     w.c2 = c2;
@@ -160,7 +171,7 @@ __device__ inline void rpy_block_f64(double dx, double dy, double dz, double zt,
     const double Rz = zt + zs;
     PairCoef<double> w{};
     if (wall)
-        w = wall_pair_coef<double>(r2, rinv, zt, zs, zs + zs, -4.0 * zs * zs, Rz,
+        w = wall_pair_coef<double>(r2, rinv, dxy2, target_z(zt), zs, zs + zs, -4.0 * zs * zs, Rz,
                                    rsq_f64(fma(Rz, Rz, dxy2)), c);
     for (int col = 0; col < 3; ++col) {
         const double lx = col == 0, ly = col == 1, lz = col == 2;
