@@ -67,7 +67,9 @@ extern "C" {
                                     generalised RPY tensor (Sec. 2.4), unknowns
                                     y = [U (6M); phi (Nc)] of Eq. linear_system_general,
                                     rows [U - N C^T phi; C U] = [N F; B]; unbounded,
-                                    ARB_FP64, preconditioner NONE or BLOCK only   */
+                                    preconditioner NONE or BLOCK only; ARB_FP32C
+                                    sums the tensor in float (units of a, float runs
+                                    promoted to double) inside FP64 refinement  */
 
 typedef struct arb_ctx arb_ctx;
 

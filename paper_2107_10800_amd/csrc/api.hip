@@ -404,10 +404,12 @@ int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const 
 }
 
 // out = A y (Eq. linear_system)
-int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out);
+int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out,
+                             int precision);
 
 int system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out, int precision) {
-    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) return single_blob_system_apply(ctx, s, y, out);
+    if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB)
+        return single_blob_system_apply(ctx, s, y, out, precision);
     const int N = ctx->N, M = ctx->M;
     const double *lam = y, *U = y + 3 * (size_t)N, *phi = y + 3 * (size_t)N + 6 * (size_t)M;
     TRY(ctx_pair(ctx, s, lam, out, U, precision));
@@ -422,18 +424,20 @@ int system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out, int 
 // generalised RPY product N x6 (6M) scaled into out = base + scale' N x6, with the
 // kernel's 1/(8 pi eta) folded into scale' = scale / (8 pi eta)
 int body_mobility_dev(arb_ctx *ctx, hipStream_t s, const double *x6, double scale,
-                      const double *base, double *out) {
+                      const double *base, double *out, int precision) {
     const int M = ctx->M;
     HIPCHK(ctx->rot_partial.ensure(std::max<int64_t>(
         (int64_t)arb::rot_pair_slices(M) * 6 * M, 1) * sizeof(double)));
     const double k = 1.0 / (8.0 * 3.14159265358979323846 * ctx->opt.eta);
-    arb::rot_pair_apply(s, M, ctx->p64.as<double4>(), x6, ctx->opt.a, scale * k, base,
+    arb::rot_pair_apply(s, precision, M, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
+                        ctx->lo.as<float4>(), x6, ctx->opt.a, scale * k, base,
                         ctx->rot_partial.as<double>(), out);
     return 0;
 }
 
 // y = [U; phi] -> [U - N C^T phi; C U] (Eq. linear_system_general, rows reordered)
-int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out) {
+int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out,
+                             int precision) {
     const int M = ctx->M;
     const double *U = y, *phi = y + 6 * (size_t)M;
     HIPCHK(ctx->rot_ct.ensure(6 * (size_t)M * sizeof(double)));
@@ -442,7 +446,7 @@ int single_blob_system_apply(arb_ctx *ctx, hipStream_t s, const double *y, doubl
     arb::KT_CT_apply(s, M, ctx->zero_off.as<int>(), ctx->dvec.as<double>(), nullptr, -1.0,
                      ctx->brow_ptr.as<int>(), ctx->brow_ent.as<int>(), ctx->crow.as<double>(),
                      ctx->Nc > 0 ? phi : nullptr, ctx->rot_ct.as<double>());
-    TRY(body_mobility_dev(ctx, s, ctx->rot_ct.as<double>(), -1.0, U, out));
+    TRY(body_mobility_dev(ctx, s, ctx->rot_ct.as<double>(), -1.0, U, out, precision));
     arb::C_apply(s, ctx->Nc, ctx->row_p.as<int>(), ctx->row_q.as<int>(), ctx->crow.as<double>(), U,
                  out + 6 * (size_t)M);
     return 0;
@@ -923,7 +927,7 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
 
     if (ctx->opt.model == ARB_MODEL_SINGLE_BLOB) {
         // b = [N F; B]
-        TRY(body_mobility_dev(ctx, s, F, 1.0, nullptr, K.b));
+        TRY(body_mobility_dev(ctx, s, F, 1.0, nullptr, K.b, ARB_FP64));
         if (Nc > 0)
             HIPCHK(hipMemcpyAsync(K.b + 6 * (size_t)M, ctx->Bc.p, Nc * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
@@ -1011,9 +1015,8 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         opt->pair_kernel > 2 || opt->graphs < 0 || opt->graphs > 1 ||
         (opt->model != ARB_MODEL_MULTIBLOB && opt->model != ARB_MODEL_SINGLE_BLOB))
         return ARB_E_ARG;
-    // single-blob bodies: unbounded FP64 generalised RPY, exact or no preconditioner
-    if (opt->model == ARB_MODEL_SINGLE_BLOB &&
-        (opt->wall != 0 || opt->precision != ARB_FP64 || opt->precond > ARB_PC_BLOCK))
+    // single-blob bodies: unbounded generalised RPY, exact or no preconditioner
+    if (opt->model == ARB_MODEL_SINGLE_BLOB && (opt->wall != 0 || opt->precond > ARB_PC_BLOCK))
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
@@ -1297,7 +1300,7 @@ int arb_body_mobility_apply_dev(arb_ctx *ctx, const double *FT_dev, double *UW_d
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-    TRY(body_mobility_dev(ctx, s, FT_dev, 1.0, nullptr, UW_dev));
+    TRY(body_mobility_dev(ctx, s, FT_dev, 1.0, nullptr, UW_dev, ctx->opt.precision));
     HIPCHK(hipGetLastError());
     return ARB_OK;
 }
@@ -1313,7 +1316,8 @@ int arb_body_mobility_apply(arb_ctx *ctx, const double *FT, double *UW) {
     hipStream_t s = ctx->stream;
     TRY(upload(ctx, ctx->s_in, FT, m6, s));
     HIPCHK(ctx->s_out.ensure(m6 * sizeof(double)));
-    TRY(body_mobility_dev(ctx, s, ctx->s_in.as<double>(), 1.0, nullptr, ctx->s_out.as<double>()));
+    TRY(body_mobility_dev(ctx, s, ctx->s_in.as<double>(), 1.0, nullptr, ctx->s_out.as<double>(),
+                          ctx->opt.precision));
     HIPCHK(hipMemcpyAsync(UW, ctx->s_out.p, m6 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;

@@ -189,8 +189,9 @@ void correct_positions(hipStream_t s, const CorrectDev &C, double tol, int max_i
 // Single-blob bodies (Sec. 2.4): generalised RPY product (rot_pair.hip), the
 // self-mobility blocks N~ and the preconditioner apply for y = [U; phi]
 int rot_pair_slices(int M);
-void rot_pair_apply(hipStream_t s, int M, const double4 *p64, const double *x6, double a,
-                    double scale, const double *base, double *partial, double *out);
+void rot_pair_apply(hipStream_t s, int precision, int M, const double4 *p64, const float4 *hi,
+                    const float4 *lo, const double *x6, double a, double scale,
+                    const double *base, double *partial, double *out);
 void single_blob_body_mobility(hipStream_t s, int M, double a, double eta, double *Nt);
 void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_off,
                           const int64_t *zero_off64, const double *r, double *z);

@@ -14,6 +14,7 @@
 // One target body per lane; source tiles of 256 bodies staged in LDS; the
 // sources are split into slices (grid y) whose partial sums a second kernel
 // adds in slice order (bitwise reproducible), scales and adds to a base vector.
+// FP64 in absolute units, or FP32 in units of a (below).
 #include "rpy_device.h"
 
 namespace arb {
@@ -111,17 +112,103 @@ __global__ __launch_bounds__(kRotTile) void rot_pair_f64_kernel(
     }
 }
 
-// out = base + scale * sum over slices (base may be NULL: zero)
+// The same sum in FP32 in units of the blob radius (positions hi + lo = x / a,
+// torques scaled by 1/a on loading, literal coefficients for a = 1): then
+// u = (1/a) sum and w = (1/a^2) sum, applied by the reduction.  Float sums over
+// runs of kRotRun sources are promoted to double after each run.
+constexpr int kRotRun = 32;
+
+__global__ __launch_bounds__(kRotTile) void rot_pair_f32c_kernel(
+    int M, const float4 *__restrict__ hi, const float4 *__restrict__ lo,
+    const double *__restrict__ x6, double inv_a, int tiles_per_slice,
+    double *__restrict__ partial) {
+    // a = 1: k1 = 2/3, k2 = 2, n1 = 4/3, n2 = 3/8, n3 = 1/8, 4a^2 = 4, e1 = 1/2,
+    // e2 = 3/16, g0 = 1, g1 = 27/32, g3 = 5/64, h1 = 9/32, h3 = 3/64
+    __shared__ float4 s_hi[kRotTile], s_lo[kRotTile];
+    __shared__ float s_x[6 * kRotTile];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * kRotTile + tid;
+    const int ic = i < M ? i : M - 1;
+    const float4 th = hi[ic], tl = lo[ic];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int ntiles = (M + kRotTile - 1) / kRotTile;
+    const int t0 = blockIdx.y * tiles_per_slice;
+    const int t1 = min(t0 + tiles_per_slice, ntiles);
+    for (int t = t0; t < t1; ++t) {
+        const int j = t * kRotTile + tid;
+        __syncthreads();
+        if (j < M) {
+            s_hi[tid] = hi[j];
+            s_lo[tid] = lo[j];
+            for (int k = 0; k < 6; ++k)
+                s_x[6 * tid + k] = (float)(k < 3 ? x6[6 * (size_t)j + k] : x6[6 * (size_t)j + k] * inv_a);
+        }
+        __syncthreads();
+        const int cnt = min(kRotTile, M - t * kRotTile);
+        for (int k0 = 0; k0 < cnt; k0 += kRotRun) {
+            const int k1 = min(k0 + kRotRun, cnt);
+            float ux = 0.f, uy = 0.f, uz = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+            for (int k = k0; k < k1; ++k) {
+                const float4 sh = s_hi[k], sl = s_lo[k];
+                const float *x = s_x + 6 * k;
+                const float fx = x[0], fy = x[1], fz = x[2], tx = x[3], ty = x[4], tz = x[5];
+                const float dx = (th.x - sh.x) + (tl.x - sl.x);
+                const float dy = (th.y - sh.y) + (tl.y - sl.y);
+                const float dz = (th.z - sh.z) + (tl.z - sl.z);
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float rinv = rsq_f32(r2);
+                const float rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+                float c1 = fmaf(2.f / 3.f, rinv3, rinv);
+                float c2 = fmaf(-2.f, rinv3 * rinv2, rinv3);
+                float cr = rinv3;
+                float d1 = -0.5f * rinv3;
+                float d2 = 1.5f * rinv3 * rinv2;
+                ARB_IF_ANY_OVERLAP(r2 <= 4.f)
+                if (r2 <= 4.f) {
+                    const float rv = r2 > 0.f ? rinv : 0.f;  // rinv is infinite at r = 0
+                    const float r = r2 * rv;
+                    c1 = fmaf(-3.f / 8.f, r, 4.f / 3.f);
+                    c2 = rv * (1.f / 8.f);
+                    cr = fmaf(-3.f / 16.f, r, 0.5f);
+                    d1 = fmaf(r, fmaf(5.f / 64.f, r * r, -27.f / 32.f), 1.f);
+                    d2 = fmaf(9.f / 32.f, rv, -(3.f / 64.f) * r);
+                }
+                ARB_END_IF_ANY
+                const float tf = c2 * fmaf(dx, fx, fmaf(dy, fy, dz * fz));
+                const float tt = d2 * fmaf(dx, tx, fmaf(dy, ty, dz * tz));
+                ux = fmaf(c1, fx, fmaf(tf, dx, fmaf(cr, fmaf(ty, dz, -tz * dy), ux)));
+                uy = fmaf(c1, fy, fmaf(tf, dy, fmaf(cr, fmaf(tz, dx, -tx * dz), uy)));
+                uz = fmaf(c1, fz, fmaf(tf, dz, fmaf(cr, fmaf(tx, dy, -ty * dx), uz)));
+                wx = fmaf(d1, tx, fmaf(tt, dx, fmaf(cr, fmaf(fy, dz, -fz * dy), wx)));
+                wy = fmaf(d1, ty, fmaf(tt, dy, fmaf(cr, fmaf(fz, dx, -fx * dz), wy)));
+                wz = fmaf(d1, tz, fmaf(tt, dz, fmaf(cr, fmaf(fx, dy, -fy * dx), wz)));
+            }
+            acc[0] += (double)ux;
+            acc[1] += (double)uy;
+            acc[2] += (double)uz;
+            acc[3] += (double)wx;
+            acc[4] += (double)wy;
+            acc[5] += (double)wz;
+        }
+    }
+    if (i < M) {
+        double *o = partial + (size_t)blockIdx.y * 6 * M + i;
+        for (int k = 0; k < 6; ++k) o[k * (size_t)M] = acc[k];
+    }
+}
+
+// out = base + scale_u * sum (u rows) / scale_w * sum (w rows) over slices
+// (base may be NULL: zero)
 __global__ void rot_reduce_kernel(int M, int slices, const double *__restrict__ partial,
-                                  double scale, const double *__restrict__ base,
-                                  double *__restrict__ out) {
+                                  double scale_u, double scale_w,
+                                  const double *__restrict__ base, double *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     for (int k = 0; k < 6; ++k) {
         double s = 0.0;
         for (int sl = 0; sl < slices; ++sl) s += partial[((size_t)sl * 6 + k) * M + i];
         const double b = base ? base[6 * (size_t)i + k] : 0.0;
-        out[6 * (size_t)i + k] = fma(scale, s, b);
+        out[6 * (size_t)i + k] = fma(k < 3 ? scale_u : scale_w, s, b);
     }
 }
 
@@ -134,16 +221,25 @@ int rot_pair_slices(int M) {
     return std::max(1, std::min(want, ntiles));
 }
 
-void rot_pair_apply(hipStream_t s, int M, const double4 *p64, const double *x6, double a,
-                    double scale, const double *base, double *partial, double *out) {
+void rot_pair_apply(hipStream_t s, int precision, int M, const double4 *p64, const float4 *hi,
+                    const float4 *lo, const double *x6, double a, double scale,
+                    const double *base, double *partial, double *out) {
     if (M <= 0) return;
     const int ntiles = (M + kRotTile - 1) / kRotTile;
     const int slices = rot_pair_slices(M);
     const int tps = (ntiles + slices - 1) / slices;
     const int used = (ntiles + tps - 1) / tps;
-    rot_pair_f64_kernel<<<dim3(ntiles, used), kRotTile, 0, s>>>(M, p64, x6, tps, rot_coef(a),
-                                                                  partial);
-    rot_reduce_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, used, partial, scale, base, out);
+    double su = scale, sw = scale;
+    if (precision == ARB_FP32C) {
+        rot_pair_f32c_kernel<<<dim3(ntiles, used), kRotTile, 0, s>>>(M, hi, lo, x6, 1.0 / a, tps,
+                                                                       partial);
+        su = scale / a;
+        sw = scale / (a * a);
+    } else {
+        rot_pair_f64_kernel<<<dim3(ntiles, used), kRotTile, 0, s>>>(M, p64, x6, tps,
+                                                                      rot_coef(a), partial);
+    }
+    rot_reduce_kernel<<<(M + 255) / 256, 256, 0, s>>>(M, used, partial, su, sw, base, out);
 }
 
 }  // namespace arb

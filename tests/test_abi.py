@@ -34,8 +34,8 @@ def test_bad_options_rejected_before_device():
     for kw in (dict(a=-1.0), dict(eta=0.0), dict(tol=0.0), dict(restart=0), dict(restart=1000),
                dict(precision=7), dict(precond=9), dict(precond=4), dict(max_iter=0),
                dict(pair_kernel=3), dict(graphs=2), dict(model=2),
-               # single-blob bodies: unbounded, FP64, exact or no preconditioner
-               dict(model=1, wall=1), dict(model=1, precision=1), dict(model=1, precond=2)):
+               # single-blob bodies: unbounded, exact or no preconditioner
+               dict(model=1, wall=1), dict(model=1, precond=2)):
         base = dict(device=0, precision=0, wall=0, eta=1.0, a=1.0, tol=1e-8, restart=50,
                     max_iter=100, precond=1, slices=0, pair_kernel=0)
         base.update(kw)

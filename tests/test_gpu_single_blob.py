@@ -2,8 +2,10 @@
 the system of Eq. linear_system_general, its preconditioner, the solve and a
 time step, against the oracle.
 
-FP64 throughout: the product and the operators at 1e-12 relative to the
-largest entry; solves at the forward-error bar max(1e-10, 10 kappa(A) r)."""
+FP64: the product and the operators at 1e-12 relative to the largest entry;
+solves at the forward-error bar max(1e-10, 10 kappa(A) r).  FP32 sums: the
+product at 1e-5 of the largest entry, solves (FP64 refinement residuals) at
+max(1e-5, 10 kappa(A) r)."""
 import numpy as np
 import pytest
 
@@ -38,6 +40,45 @@ def test_body_mobility_matches_oracle(M, box):
         arb.arb_destroy(ctx)
     ref = rpy_rot.body_mobility_apply(wl.q, wl.F, wl.a, wl.eta)
     assert np.abs(uw - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("M,box", [(7, 4.0), (300, 12.0), (2049, 60.0)])
+def test_body_mobility_fp32c_matches_oracle(M, box):
+    """FP32 sums (hi/lo positions in units of a, float runs promoted to double):
+    within 1e-5 of the largest entry, overlaps and a coincident pair included."""
+    wl = loose_blobs(M, 40 + M, box)
+    wl.q[1] = wl.q[0]
+    wl.a, wl.eta = 0.8, 1.7
+    ctx = arb.context_for(wl, precision=arb.ARB_FP32C)
+    try:
+        uw = arb.arb_body_mobility_apply(ctx, wl.F)
+    finally:
+        arb.arb_destroy(ctx)
+    ref = rpy_rot.body_mobility_apply(wl.q, wl.F, wl.a, wl.eta)
+    err = np.abs(uw - ref).max() / np.abs(ref).max()
+    print(f"  fp32c body mobility M={M}: max error {err:.1e} of the largest entry", flush=True)
+    assert err <= 1e-5
+
+
+def test_fp32c_single_blob_solve():
+    """FP32 products inside FP64 refinement (the FP64 residual meets tol) against
+    the dense solve: within max(1e-5, 10 kappa r)."""
+    wl = W.blob_shells(2)
+    S = single_blob.assemble(wl)
+    kap = _kappa(S["A"])
+    ctx = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-8)
+    try:
+        rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+    finally:
+        arb.arb_destroy(ctx)
+    M = wl.M
+    y = single_blob.solve_dense(S)
+    print(f"  fp32c single-blob solve: {info['iterations']} iterations, FP64 residual "
+          f"{info['rel_residual']:.1e}, products {info['products_fp32']} + {info['products_fp64']}",
+          flush=True)
+    assert info["rel_residual"] <= 1e-8 and info["products_fp32"] >= info["iterations"]
+    tol = max(1e-5, 10 * kap * info["rel_residual"])
+    assert np.linalg.norm(U.ravel() - y[:6 * M]) <= tol * np.linalg.norm(y[:6 * M])
 
 
 def test_body_mobility_sampled_rows_at_4096_shells():
