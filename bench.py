@@ -377,8 +377,10 @@ def single_blob_bench(torch, arb, W, reps=5):
     # sums inside FP64 refinement
     prac = []
     wl = W.blob_shells(16)
-    for prec, name in ((arb.ARB_FP64, "f64"), (arb.ARB_FP32C, "f32c")):
-        rc, info, ms = solve(wl, 1e-4, False, prec)
+    wlg = W.blob_shells(16, forcing="gravity")
+    for w, prec, name in ((wl, arb.ARB_FP64, "f64"), (wl, arb.ARB_FP32C, "f32c"),
+                          (wlg, arb.ARB_FP32C, "f32c gravity")):
+        rc, info, ms = solve(w, 1e-4, False, prec)
         prac.append(dict(precision=name, tol=1e-4, iterations=info["iterations"],
                          rel_residual_fp64=info["rel_residual"], ms_per_solve=ms,
                          products_fp32=info["products_fp32"],

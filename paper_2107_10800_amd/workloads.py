@@ -305,8 +305,9 @@ def blob_filaments(nx: int = 1, nz: int = 1, n_blobs: int = 15, lc: float = 2.5,
 
     Each filament has n_blobs bodies spaced lc apart, joined by ball joints
     midway (dl = +-lc/2 e_x); filaments sit on an nx x nz grid in the (x, z)
-    plane, ``gap`` apart end to end along x and ``gap`` apart along z.  Every
-    body carries the force (0, 0, -1) (gravity along -z) and no torque.
+    plane with surface gaps of ``gap`` end to end along x and side by side
+    along z (centre lines gap + 2a apart; local area fraction about 0.3).
+    Every body carries the force (0, 0, -1) (gravity along -z) and no torque.
     Unbounded; the blobs sit at the tracking points.
     """
     length = (n_blobs - 1) * lc + 2.0
@@ -315,7 +316,7 @@ def blob_filaments(nx: int = 1, nz: int = 1, n_blobs: int = 15, lc: float = 2.5,
         for ix in range(nx):
             b0 = len(q)
             for k in range(n_blobs):
-                q.append([ix * (length + gap) + k * lc, 0.0, iz * gap])
+                q.append([ix * (length + gap) + k * lc, 0.0, iz * (gap + 2.0)])
             pairs += [(b0 + k, b0 + k + 1) for k in range(n_blobs - 1)]
     q = np.array(q, float)
     M = len(q)
