@@ -56,6 +56,20 @@ __device__ __forceinline__ void sym_free(T dx, T dy, T dz, T r2, T rinv, T lix, 
     az = fma(c1, liz, fma(ti, dz, az));
 }
 
+// v of lane (l + 1) mod 64 for lane l: DPP wave_rol:1 (a VALU move across the
+// whole wavefront)
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF,
+                                                      false));
+}
+
+__device__ __forceinline__ double from_next_lane(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 struct Blob32 {
     float4 hi, lo, lam;
 };
@@ -156,10 +170,19 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
                     sym_free<float>(dx, dy, dz, r2, rinv, t.lam.x, t.lam.y, t.lam.z, L.x, L.y, L.z,
                                     c, fx, fy, fz, ax, ay, az);
                 }
-                // the source-side sums follow their sources: lane l takes lane l+1's
-                ax = __shfl(ax, src);
-                ay = __shfl(ay, src);
-                az = __shfl(az, src);
+                // the source-side sums follow their sources: lane l takes lane l+1's.
+                // The free-space loop has VALU to spare and waits on the LDS, so it
+                // rotates with a whole-wave DPP move; the wall loop is VALU-bound and
+                // uses the LDS crossbar.
+                if (WALL) {
+                    ax = __shfl(ax, src);
+                    ay = __shfl(ay, src);
+                    az = __shfl(az, src);
+                } else {
+                    ax = from_next_lane(ax);
+                    ay = from_next_lane(ay);
+                    az = from_next_lane(az);
+                }
             }
             comb[w][0][lane] = ax;
             comb[w][1][lane] = ay;
@@ -262,9 +285,15 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
                     sym_free<double>(dx, dy, dz, r2, rinv, tl.x, tl.y, tl.z, L.x, L.y, L.z, c, fx,
                                      fy, fz, ax, ay, az);
                 }
-                ax = __shfl(ax, src);
-                ay = __shfl(ay, src);
-                az = __shfl(az, src);
+                if (WALL) {
+                    ax = __shfl(ax, src);
+                    ay = __shfl(ay, src);
+                    az = __shfl(az, src);
+                } else {
+                    ax = from_next_lane(ax);
+                    ay = from_next_lane(ay);
+                    az = from_next_lane(az);
+                }
             }
             comb[w][0][lane] = ax;
             comb[w][1][lane] = ay;
