@@ -38,7 +38,7 @@ FLOPS_SYM = {("f32c", True): 132, ("f32c", False): 58, ("f64", True): 127,
 
 # generalised RPY product of single-blob bodies (FP64, unbounded): one ordered pair,
 # same counting rules (translation, both couplings and rotation terms)
-FLOPS_ROT_PAIR = 85
+FLOPS_ROT_PAIR = 82
 
 
 def algorithmic_flops(N, shape, prec="f32c", wall=True):

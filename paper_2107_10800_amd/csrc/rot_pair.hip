@@ -93,12 +93,14 @@ __global__ __launch_bounds__(kRotTile) void rot_pair_f64_kernel(
             ARB_END_IF_ANY
             const double tf = c2 * fma(dx, fx, fma(dy, fy, dz * fz));
             const double tt = d2 * fma(dx, tx, fma(dy, ty, dz * tz));
-            ux = fma(c1, fx, fma(tf, dx, fma(cr, fma(ty, dz, -tz * dy), ux)));
-            uy = fma(c1, fy, fma(tf, dy, fma(cr, fma(tz, dx, -tx * dz), uy)));
-            uz = fma(c1, fz, fma(tf, dz, fma(cr, fma(tx, dy, -ty * dx), uz)));
-            wx = fma(d1, tx, fma(tt, dx, fma(cr, fma(fy, dz, -fz * dy), wx)));
-            wy = fma(d1, ty, fma(tt, dy, fma(cr, fma(fz, dx, -fx * dz), wy)));
-            wz = fma(d1, tz, fma(tt, dz, fma(cr, fma(fx, dy, -fy * dx), wz)));
+            // c_r (tau x r) and c_r (f x r) through r scaled by c_r once
+            const double ex = cr * dx, ey = cr * dy, ez = cr * dz;
+            ux = fma(c1, fx, fma(tf, dx, fma(ty, ez, fma(-tz, ey, ux))));
+            uy = fma(c1, fy, fma(tf, dy, fma(tz, ex, fma(-tx, ez, uy))));
+            uz = fma(c1, fz, fma(tf, dz, fma(tx, ey, fma(-ty, ex, uz))));
+            wx = fma(d1, tx, fma(tt, dx, fma(fy, ez, fma(-fz, ey, wx))));
+            wy = fma(d1, ty, fma(tt, dy, fma(fz, ex, fma(-fx, ez, wy))));
+            wz = fma(d1, tz, fma(tt, dz, fma(fx, ey, fma(-fy, ex, wz))));
         }
     }
     if (i < M) {
@@ -176,12 +178,13 @@ __global__ __launch_bounds__(kRotTile) void rot_pair_f32c_kernel(
                 ARB_END_IF_ANY
                 const float tf = c2 * fmaf(dx, fx, fmaf(dy, fy, dz * fz));
                 const float tt = d2 * fmaf(dx, tx, fmaf(dy, ty, dz * tz));
-                ux = fmaf(c1, fx, fmaf(tf, dx, fmaf(cr, fmaf(ty, dz, -tz * dy), ux)));
-                uy = fmaf(c1, fy, fmaf(tf, dy, fmaf(cr, fmaf(tz, dx, -tx * dz), uy)));
-                uz = fmaf(c1, fz, fmaf(tf, dz, fmaf(cr, fmaf(tx, dy, -ty * dx), uz)));
-                wx = fmaf(d1, tx, fmaf(tt, dx, fmaf(cr, fmaf(fy, dz, -fz * dy), wx)));
-                wy = fmaf(d1, ty, fmaf(tt, dy, fmaf(cr, fmaf(fz, dx, -fx * dz), wy)));
-                wz = fmaf(d1, tz, fmaf(tt, dz, fmaf(cr, fmaf(fx, dy, -fy * dx), wz)));
+                const float ex = cr * dx, ey = cr * dy, ez = cr * dz;
+                ux = fmaf(c1, fx, fmaf(tf, dx, fmaf(ty, ez, fmaf(-tz, ey, ux))));
+                uy = fmaf(c1, fy, fmaf(tf, dy, fmaf(tz, ex, fmaf(-tx, ez, uy))));
+                uz = fmaf(c1, fz, fmaf(tf, dz, fmaf(tx, ey, fmaf(-ty, ex, uz))));
+                wx = fmaf(d1, tx, fmaf(tt, dx, fmaf(fy, ez, fmaf(-fz, ey, wx))));
+                wy = fmaf(d1, ty, fmaf(tt, dy, fmaf(fz, ex, fmaf(-fx, ez, wy))));
+                wz = fmaf(d1, tz, fmaf(tt, dz, fmaf(fx, ey, fmaf(-fy, ex, wz))));
             }
             acc[0] += (double)ux;
             acc[1] += (double)uy;
