@@ -428,7 +428,7 @@ int body_mobility_dev(arb_ctx *ctx, hipStream_t s, const double *x6, double scal
     const int M = ctx->M;
     HIPCHK(ctx->rot_partial.ensure(std::max<int64_t>(
         (int64_t)arb::rot_pair_slices(M) * 6 * M, 1) * sizeof(double)));
-    const double k = 1.0 / (8.0 * 3.14159265358979323846 * ctx->opt.eta);
+    const double k = 1.0 / (8.0 * arb::kPi * ctx->opt.eta);
     arb::rot_pair_apply(s, precision, M, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
                         ctx->lo.as<float4>(), x6, ctx->opt.a, scale * k, base,
                         ctx->rot_partial.as<double>(), out);

@@ -14,20 +14,6 @@ namespace arb {
 
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-__device__ __forceinline__ void quat_to_R(const double *t, double *R) {
-    const double s = t[0], p0 = t[1], p1 = t[2], p2 = t[3];
-    const double d = s * s - 0.5;
-    R[0] = 2.0 * (p0 * p0 + d);
-    R[1] = 2.0 * (p0 * p1 - s * p2);
-    R[2] = 2.0 * (p0 * p2 + s * p1);
-    R[3] = 2.0 * (p1 * p0 + s * p2);
-    R[4] = 2.0 * (p1 * p1 + d);
-    R[5] = 2.0 * (p1 * p2 - s * p0);
-    R[6] = 2.0 * (p2 * p0 - s * p1);
-    R[7] = 2.0 * (p2 * p1 + s * p0);
-    R[8] = 2.0 * (p2 * p2 + d);
-}
-
 __device__ __forceinline__ void matvec3(const double *R, const double *v, double *o) {
     o[0] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
     o[1] = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
@@ -44,7 +30,7 @@ __global__ void rotations_kernel(int M, const double *__restrict__ theta, double
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
     double R[9];
-    quat_to_R(theta + 4 * (size_t)p, R);
+    rotation_from_quat(theta + 4 * (size_t)p, R);
     for (int k = 0; k < 9; ++k) R9[9 * (size_t)p + k] = R[k];
 }
 

@@ -17,6 +17,23 @@ constexpr int kTile = 256;          // sources per LDS tile == threads per pair 
 constexpr int kWave = 64;           // CDNA wavefront
 constexpr double kPi = 3.14159265358979323846;
 
+// R(theta) = 2 [p p^T + s p^x + (s^2 - 1/2) I] of a quaternion theta = (s, p),
+// row-major (App. B, Eq. rot_mat): a rotation for unit theta; the position
+// correction also evaluates it at its non-unit iterates, as App. B writes it
+__device__ __forceinline__ void rotation_from_quat(const double *t, double *R) {
+    const double s = t[0], p0 = t[1], p1 = t[2], p2 = t[3];
+    const double d = s * s - 0.5;
+    R[0] = 2.0 * (p0 * p0 + d);
+    R[1] = 2.0 * (p0 * p1 - s * p2);
+    R[2] = 2.0 * (p0 * p2 + s * p1);
+    R[3] = 2.0 * (p1 * p0 + s * p2);
+    R[4] = 2.0 * (p1 * p1 + d);
+    R[5] = 2.0 * (p1 * p2 - s * p0);
+    R[6] = 2.0 * (p2 * p0 - s * p1);
+    R[7] = 2.0 * (p2 * p1 + s * p0);
+    R[8] = 2.0 * (p2 * p2 + d);
+}
+
 // ---------------------------------------------------------------- device buffer
 // bumped whenever any device buffer is (re)allocated: captured HIP graphs that
 // hold buffer addresses are rebuilt after it changes

@@ -17,20 +17,6 @@ namespace arb {
 
 constexpr int kMaxCorrRows = 2048;
 
-__device__ __forceinline__ void rotm(const double *t, double *R) {
-    const double s = t[0], p0 = t[1], p1 = t[2], p2 = t[3];
-    const double d = s * s - 0.5;
-    R[0] = 2.0 * (p0 * p0 + d);
-    R[1] = 2.0 * (p0 * p1 - s * p2);
-    R[2] = 2.0 * (p0 * p2 + s * p1);
-    R[3] = 2.0 * (p1 * p0 + s * p2);
-    R[4] = 2.0 * (p1 * p1 + d);
-    R[5] = 2.0 * (p1 * p2 - s * p0);
-    R[6] = 2.0 * (p2 * p0 - s * p1);
-    R[7] = 2.0 * (p2 * p1 + s * p0);
-    R[8] = 2.0 * (p2 * p2 + d);
-}
-
 __device__ __forceinline__ double block_sum_c(double v, double *red) {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
     __syncthreads();
@@ -58,7 +44,7 @@ __device__ void corr_residual(int nb, int nl, const int *links, const int *pq, c
         const int p = pq[2 * n], qq = pq[2 * n + 1];
         const int lp = loc[p];
         double R[9];
-        rotm(x + 7 * lp + 3, R);
+        rotation_from_quat(x + 7 * lp + 3, R);
         const double *l = lt + 6 * e;
         double g[3];
         for (int i = 0; i < 3; ++i)
@@ -66,7 +52,7 @@ __device__ void corr_residual(int nb, int nl, const int *links, const int *pq, c
                    (R[3 * i] * l[0] + R[3 * i + 1] * l[1] + R[3 * i + 2] * l[2]);
         if (qq >= 0) {
             const int lq = loc[qq];
-            rotm(x + 7 * lq + 3, R);
+            rotation_from_quat(x + 7 * lq + 3, R);
             for (int i = 0; i < 3; ++i)
                 g[i] -= q[3 * (size_t)qq + i] + x[7 * lq + i] +
                         (R[3 * i] * l[3] + R[3 * i + 1] * l[4] + R[3 * i + 2] * l[5]);
@@ -136,12 +122,12 @@ __global__ __launch_bounds__(256) void correct_kernel(
         const int n = links[e];
         const int p = pq[2 * n], qq = pq[2 * n + 1];
         double R[9];
-        rotm(theta + 4 * (size_t)p, R);
+        rotation_from_quat(theta + 4 * (size_t)p, R);
         for (int i = 0; i < 3; ++i)
             W.lt[6 * e + i] = R[3 * i] * dl_p[3 * n] + R[3 * i + 1] * dl_p[3 * n + 1] +
                               R[3 * i + 2] * dl_p[3 * n + 2];
         if (qq >= 0) {
-            rotm(theta + 4 * (size_t)qq, R);
+            rotation_from_quat(theta + 4 * (size_t)qq, R);
             for (int i = 0; i < 3; ++i)
                 W.lt[6 * e + 3 + i] = R[3 * i] * dl_q[3 * n] + R[3 * i + 1] * dl_q[3 * n + 1] +
                                       R[3 * i + 2] * dl_q[3 * n + 2];
@@ -275,12 +261,12 @@ __global__ __launch_bounds__(256) void correct_kernel(
         const int n = links[e];
         const int p = pq[2 * n], qq = pq[2 * n + 1];
         double R[9], v[3];
-        rotm(theta + 4 * (size_t)p, R);
+        rotation_from_quat(theta + 4 * (size_t)p, R);
         for (int i = 0; i < 3; ++i)
             v[i] = q[3 * (size_t)p + i] + R[3 * i] * dl_p[3 * n] + R[3 * i + 1] * dl_p[3 * n + 1] +
                    R[3 * i + 2] * dl_p[3 * n + 2];
         if (qq >= 0) {
-            rotm(theta + 4 * (size_t)qq, R);
+            rotation_from_quat(theta + 4 * (size_t)qq, R);
             for (int i = 0; i < 3; ++i)
                 v[i] -= q[3 * (size_t)qq + i] + R[3 * i] * dl_q[3 * n] +
                         R[3 * i + 1] * dl_q[3 * n + 1] + R[3 * i + 2] * dl_q[3 * n + 2];

@@ -1153,9 +1153,8 @@ __global__ void copy_kernel(int64_t n, const double *__restrict__ x, double *__r
 
 void single_blob_body_mobility(hipStream_t s, int M, double a, double eta, double *Nt) {
     if (M <= 0) return;
-    const double pi = 3.14159265358979323846;
     single_blob_nt_kernel<<<(36 * M + 255) / 256, 256, 0, s>>>(
-        M, 1.0 / (6.0 * pi * eta * a), 1.0 / (8.0 * pi * eta * a * a * a), Nt);
+        M, 1.0 / (6.0 * kPi * eta * a), 1.0 / (8.0 * kPi * eta * a * a * a), Nt);
 }
 
 // z = P^-1 r for y = [U; phi]: phi = G~ (r_phi - C r_U), U = r_U + N~ C^T phi.

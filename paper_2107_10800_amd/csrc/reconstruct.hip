@@ -22,20 +22,6 @@ namespace arb {
 
 namespace {
 
-__device__ __forceinline__ void rot_of(const double *t, double *R) {
-    const double s = t[0], p0 = t[1], p1 = t[2], p2 = t[3];
-    const double d = s * s - 0.5;
-    R[0] = 2.0 * (p0 * p0 + d);
-    R[1] = 2.0 * (p0 * p1 - s * p2);
-    R[2] = 2.0 * (p0 * p2 + s * p1);
-    R[3] = 2.0 * (p1 * p0 + s * p2);
-    R[4] = 2.0 * (p1 * p1 + d);
-    R[5] = 2.0 * (p1 * p2 - s * p0);
-    R[6] = 2.0 * (p2 * p0 - s * p1);
-    R[7] = 2.0 * (p2 * p1 + s * p0);
-    R[8] = 2.0 * (p2 * p2 + d);
-}
-
 __device__ __forceinline__ void rot_apply(const double *R, const double *v, double *o) {
     o[0] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
     o[1] = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
@@ -63,11 +49,11 @@ __device__ double block_reduce(double v, double *red) {
 __device__ __forceinline__ void link_g(const ReconDev &D, int n, double *g) {
     const int p = D.pq[2 * n], qq = D.pq[2 * n + 1];
     double R[9], v[3];
-    rot_of(D.theta + 4 * (size_t)p, R);
+    rotation_from_quat(D.theta + 4 * (size_t)p, R);
     rot_apply(R, D.dl_p + 3 * (size_t)n, v);
     for (int i = 0; i < 3; ++i) g[i] = D.q[3 * (size_t)p + i] + v[i];
     if (qq >= 0) {
-        rot_of(D.theta + 4 * (size_t)qq, R);
+        rotation_from_quat(D.theta + 4 * (size_t)qq, R);
         rot_apply(R, D.dl_q + 3 * (size_t)n, v);
         for (int i = 0; i < 3; ++i) g[i] -= D.q[3 * (size_t)qq + i] + v[i];
     } else {
@@ -98,10 +84,10 @@ __global__ __launch_bounds__(kReconThreads) void reconstruct_kernel(ReconDev D, 
             const int n = D.asm_links[l0 + e];
             const int p = D.pq[2 * n], qq = D.pq[2 * n + 1];
             double R[9], v[3], z[3];
-            rot_of(D.theta + 4 * (size_t)p, R);
+            rotation_from_quat(D.theta + 4 * (size_t)p, R);
             rot_apply(R, D.dl_p + 3 * (size_t)n, z);
             if (qq >= 0) {
-                rot_of(D.theta + 4 * (size_t)qq, R);
+                rotation_from_quat(D.theta + 4 * (size_t)qq, R);
                 rot_apply(R, D.dl_q + 3 * (size_t)n, v);
             } else {
                 for (int i = 0; i < 3; ++i) v[i] = D.dl_q[3 * (size_t)n + i];

@@ -206,3 +206,19 @@ def test_single_blob_argument_errors():
             arb.arb_set_bodies(ctx, rr.blob_offset, rr.r_ref, None)
     finally:
         arb.arb_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_unlinked_single_blobs_solve_to_the_mobility_product(prec):
+    """No links: the system reduces to U = N F (no constraint rows, no assemblies
+    in the preconditioner)."""
+    wl = loose_blobs(300, 77, 12.0)
+    ctx = arb.context_for(wl, precision=prec, tol=1e-10)
+    try:
+        assert arb.arb_sizes(ctx)[2] == 0
+        rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+    finally:
+        arb.arb_destroy(ctx)
+    ref = rpy_rot.body_mobility_apply(wl.q, wl.F, wl.a, wl.eta)
+    assert info["rel_residual"] <= 1e-10
+    assert np.abs(U - ref).max() <= 1e-9 * np.abs(ref).max()
