@@ -61,6 +61,11 @@ extern "C" {
                               each body (no per-solve factorisation; ignores the
                               wall inside the blocks)                         */
 
+/* pair kernel choice (arb_options.pair_kernel) */
+#define ARB_PAIR_AUTO      0  /* autotuned (wall RPY) / by size (single-blob bodies) */
+#define ARB_PAIR_TARGET    1  /* target-parallel: ordered sums, bitwise reproducible */
+#define ARB_PAIR_SYMMETRIC 2  /* each unordered pair once, FP64 atomic sums           */
+
 /* body models */
 #define ARB_MODEL_MULTIBLOB   0  /* rigid multiblob bodies, Eq. linear_system (Sec. 2.3) */
 #define ARB_MODEL_SINGLE_BLOB 1  /* every body one blob at its tracking point with the

@@ -423,15 +423,37 @@ int system_apply(arb_ctx *ctx, hipStream_t s, const double *y, double *out, int 
 
 // generalised RPY product N x6 (6M) scaled into out = base + scale' N x6, with the
 // kernel's 1/(8 pi eta) folded into scale' = scale / (8 pi eta)
+// the symmetric form from 4,096 bodies on (or when the options ask for it): enough
+// work items to fill the chip; the target-parallel form below
+static bool rot_symmetric(const arb_ctx *ctx) {
+    return ctx->opt.pair_kernel == ARB_PAIR_SYMMETRIC ||
+           (ctx->opt.pair_kernel == ARB_PAIR_AUTO && ctx->M >= 4096);
+}
+
 int body_mobility_dev(arb_ctx *ctx, hipStream_t s, const double *x6, double scale,
                       const double *base, double *out, int precision) {
     const int M = ctx->M;
     HIPCHK(ctx->rot_partial.ensure(std::max<int64_t>(
         (int64_t)arb::rot_pair_slices(M) * 6 * M, 1) * sizeof(double)));
+    const int4 *work = nullptr;
+    if (rot_symmetric(ctx)) {
+        if (ctx->rot_work_M != M) {
+            // built on the first product of a size (the solve's right-hand side), so
+            // never inside a captured GMRES step
+            std::vector<int4> w = arb::pair_sym_worklist(M, 1);
+            HIPCHK(ctx->rot_work.ensure(std::max<size_t>(w.size(), 1) * sizeof(int4)));
+            HIPCHK(hipMemcpyAsync(ctx->rot_work.p, w.data(), w.size() * sizeof(int4),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ctx->rot_work_M = M;
+            ctx->rot_n_work = (int)w.size();
+        }
+        work = ctx->rot_work.as<int4>();
+    }
     const double k = 1.0 / (8.0 * arb::kPi * ctx->opt.eta);
     arb::rot_pair_apply(s, precision, M, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
                         ctx->lo.as<float4>(), x6, ctx->opt.a, scale * k, base,
-                        ctx->rot_partial.as<double>(), out);
+                        ctx->rot_partial.as<double>(), out, work, ctx->rot_n_work);
     return 0;
 }
 

@@ -206,9 +206,13 @@ void correct_positions(hipStream_t s, const CorrectDev &C, double tol, int max_i
 // Single-blob bodies (Sec. 2.4): generalised RPY product (rot_pair.hip), the
 // self-mobility blocks N~ and the preconditioner apply for y = [U; phi]
 int rot_pair_slices(int M);
+// work / n_work: the symmetric form on that work list (pair_sym_worklist of M
+// bodies), NULL: the target-parallel form; partial holds rot_pair_slices(M) x 6M
+// doubles (6M for the symmetric form)
 void rot_pair_apply(hipStream_t s, int precision, int M, const double4 *p64, const float4 *hi,
                     const float4 *lo, const double *x6, double a, double scale,
-                    const double *base, double *partial, double *out);
+                    const double *base, double *partial, double *out, const int4 *work,
+                    int n_work);
 void single_blob_body_mobility(hipStream_t s, int M, double a, double eta, double *Nt);
 void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_off,
                           const int64_t *zero_off64, const double *r, double *z);
@@ -311,7 +315,8 @@ struct arb_ctx {
     int64_t ky_n = 0;
     // single-blob model: M+1 zero offsets (no blobs in the preconditioner's body
     // stage), partial sums of the generalised RPY product, C^T phi
-    arb::DevBuf zero_off, zero_off64, rot_partial, rot_ct;
+    arb::DevBuf zero_off, zero_off64, rot_partial, rot_ct, rot_work;
+    int rot_work_M = -1, rot_n_work = 0;
     // the initial state of a midpoint step
     arb::DevBuf q0, th0;
     arb::DevBuf tune_out;

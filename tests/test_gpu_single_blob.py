@@ -24,16 +24,20 @@ def loose_blobs(M, seed, box):
                       rng.standard_normal((M, 6)), extra=dict(single_blob=True))
 
 
+KERNELS = {"target": arb.ARB_PAIR_TARGET, "symmetric": arb.ARB_PAIR_SYMMETRIC}
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("M,box", [(1, 1.0), (7, 4.0), (300, 12.0), (1000, 20.0), (2049, 60.0)])
-def test_body_mobility_matches_oracle(M, box):
-    """Ragged tiles (one tile of 256 bodies, several, one body past a tile),
-    dense boxes with many overlapping pairs, and a coincident pair."""
+def test_body_mobility_matches_oracle(M, box, kernel):
+    """Both kernel forms; ragged tiles (one tile of 256 bodies, several, one body
+    past a tile), dense boxes with many overlapping pairs, and a coincident pair."""
     wl = loose_blobs(M, 40 + M, box)
     if M > 2:
         wl.q[1] = wl.q[0]                       # coincident blobs
     wl.a, wl.eta = 0.8, 1.7
-    print(f"body mobility M={M}", flush=True)
-    ctx = arb.context_for(wl)
+    print(f"body mobility M={M} {kernel}", flush=True)
+    ctx = arb.context_for(wl, pair_kernel=KERNELS[kernel])
     try:
         uw = arb.arb_body_mobility_apply(ctx, wl.F)
     finally:
@@ -42,21 +46,24 @@ def test_body_mobility_matches_oracle(M, box):
     assert np.abs(uw - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("M,box", [(7, 4.0), (300, 12.0), (2049, 60.0)])
-def test_body_mobility_fp32c_matches_oracle(M, box):
-    """FP32 sums (hi/lo positions in units of a, float runs promoted to double):
-    within 1e-5 of the largest entry, overlaps and a coincident pair included."""
+def test_body_mobility_fp32c_matches_oracle(M, box, kernel):
+    """FP32 sums (hi/lo positions in units of a, float sums promoted to double),
+    both kernel forms: within 1e-5 of the largest entry, overlaps and a
+    coincident pair included."""
     wl = loose_blobs(M, 40 + M, box)
     wl.q[1] = wl.q[0]
     wl.a, wl.eta = 0.8, 1.7
-    ctx = arb.context_for(wl, precision=arb.ARB_FP32C)
+    ctx = arb.context_for(wl, precision=arb.ARB_FP32C, pair_kernel=KERNELS[kernel])
     try:
         uw = arb.arb_body_mobility_apply(ctx, wl.F)
     finally:
         arb.arb_destroy(ctx)
     ref = rpy_rot.body_mobility_apply(wl.q, wl.F, wl.a, wl.eta)
     err = np.abs(uw - ref).max() / np.abs(ref).max()
-    print(f"  fp32c body mobility M={M}: max error {err:.1e} of the largest entry", flush=True)
+    print(f"  fp32c body mobility M={M} {kernel}: max error {err:.1e} of the largest entry",
+          flush=True)
     assert err <= 1e-5
 
 
@@ -81,20 +88,24 @@ def test_fp32c_single_blob_solve():
     assert np.linalg.norm(U.ravel() - y[:6 * M]) <= tol * np.linalg.norm(y[:6 * M])
 
 
-def test_body_mobility_sampled_rows_at_4096_shells():
-    """172,032 bodies: 64 sampled rows against the oracle's row-by-row sum."""
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_body_mobility_sampled_rows_at_4096_shells(prec):
+    """172,032 bodies (the symmetric form, chosen by size): 64 sampled rows
+    against the oracle's row-by-row sum, at 1e-12 (FP64) or 1e-5 (FP32) of the
+    row's largest entry."""
     wl = W.blob_shells(16)
-    print(f"body mobility, 4096 shells: M={wl.M}", flush=True)
-    ctx = arb.context_for(wl)
+    print(f"body mobility, 4096 shells: M={wl.M} precision {prec}", flush=True)
+    ctx = arb.context_for(wl, precision=prec)
     try:
         uw = arb.arb_body_mobility_apply(ctx, wl.F)
     finally:
         arb.arb_destroy(ctx)
+    tol = 1e-12 if prec == arb.ARB_FP64 else 1e-5
     rows = np.random.default_rng(3).choice(wl.M, 64, replace=False)
     for t in rows:
         blk = rpy_rot.pair_blocks(wl.q[t] - wl.q, wl.a, wl.eta)          # (M,6,6)
         ref = np.einsum("mij,mj->i", blk, wl.F)
-        assert np.abs(uw[t] - ref).max() <= 1e-12 * np.abs(ref).max() + 1e-16
+        assert np.abs(uw[t] - ref).max() <= tol * np.abs(ref).max() + 1e-16
 
 
 CASES = {
