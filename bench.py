@@ -78,7 +78,7 @@ COPY_CAL = {"copy_fetch_kib": 131091.4, "copy_write_kib": 262144.0, "copy_kib": 
 TRAFFIC = {
     "target": {"src": ("pair.hip", "rpy_device.h"), "sha256_16": None, "shape": 64,
                "fetch_kib": None, "write_kib": None},
-    "symmetric": {"src": ("pair_sym.hip", "rpy_device.h"), "sha256_16": "a9f08414787a5fc2",
+    "symmetric": {"src": ("pair_sym.hip", "rpy_device.h"), "sha256_16": "20eb993d4912d64c",
                   "shape": -1, "fetch_kib": 4062.8, "write_kib": 60864.0},
 }
 
