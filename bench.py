@@ -409,7 +409,7 @@ def single_blob_bench(torch, arb, W, reps=5):
     return out
 
 
-def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, log=log):
+def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, batch=1024, log=log):
     """Learned body-mobility preconditioner vs exact block and body-frame blocks."""
     import numpy as np
 
@@ -425,7 +425,7 @@ def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, log=lo
         learned.load_model(ctx, W.mlp_init_weights(seed=6), sc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hist = learned.train(ctx, X, T, epochs=epochs, batch=1024, lr=2e-3, seed=7, log=log)
+        hist = learned.train(ctx, X, T, epochs=epochs, batch=batch, lr=2e-3, seed=7, log=log)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         params = arb.arb_mlp_get_params(ctx)
@@ -465,7 +465,7 @@ def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, log=lo
     return dict(workload=f"{n_bact} bacteria above a wall, N={wl.N}, n={wl.n_unknowns}, "
                          f"GMRES to 1e-6 (FP64 residual)",
                 training=dict(poses=int(len(X)), seconds_dataset=t_data, seconds_train=t_train,
-                              epochs=epochs, batch=4096, final_batch_loss=hist[-1],
+                              epochs=epochs, batch=batch, final_batch_loss=hist[-1],
                               heldout_body_mobility_rel_err_median=float(np.median(err)),
                               heldout_body_mobility_rel_err_p95=float(np.percentile(err, 95))),
                 solves=out)
