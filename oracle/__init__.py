@@ -22,4 +22,6 @@ Modules
   rpy_rot   generalised RPY tensor of single-blob bodies, unbounded (Sec. 2.4)
   single_blob  the single-blob system Eq. linear_system_general and its preconditioner
   mlp       float64 MLP used to judge the learned body-mobility network
+  fastsum   the interpolation-based multipole approximation of the blob
+            mobility product (fast summation, Sec. 2.3 and Sec. 6)
 """

@@ -1,0 +1,115 @@
+"""Pins of the oracle of the fast multipole approximation (oracle/fastsum.py).
+
+The approximation has a plain definition: interpolate the pair tensor of
+well-separated cells in both arguments, sum the rest directly.  The pins check
+it against facts that do not come from that code:
+  * the Lagrange basis at Chebyshev points of the first kind: l_k(xi_j) =
+    delta_kj, partition of unity, and exact reproduction of polynomials of
+    degree < n in each coordinate;
+  * a kernel that is such a polynomial in x and in y is interpolated exactly,
+    so the approximation must equal the direct sum to rounding: this fails for
+    a source counted twice or missed (a wrong interaction list, a lost level),
+    a transposed weight or a wrong proxy point;
+  * with L <= 1 there is no interpolation: the direct RPY sum of the pinned
+    dense oracle;
+  * with the RPY tensor the error against the dense sum falls geometrically
+    with n (free space and above the wall).
+"""
+import numpy as np
+import pytest
+
+from oracle import fastsum, rpy
+
+
+def test_lagrange_basis():
+    for n in (2, 3, 5, 8):
+        x = fastsum.cheb_nodes(n)
+        assert np.allclose(x, np.cos((2 * np.arange(n) + 1) * np.pi / (2 * n)))
+        assert np.abs(fastsum.lagrange(n, x) - np.eye(n)).max() < 1e-13
+        u = np.linspace(-1, 1, 17)
+        assert np.abs(fastsum.lagrange(n, u).sum(1) - 1).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6])
+def test_weights_reproduce_polynomials(n):
+    rng = np.random.default_rng(n)
+    c, w = np.array([1.5, -2.0, 4.0]), 0.75
+    x = c + w * rng.uniform(-1, 1, (20, 3))
+    W = fastsum.weights(n, x, c, w)
+    t = fastsum.proxies(n, c, w)
+    for ex in [(0, 0, 0), (n - 1, 0, 0), (0, n - 1, n - 1), (n - 1, n - 1, n - 1), (1, 0, n - 1)]:
+        p = lambda z: np.prod(z ** np.array(ex), axis=-1)    # noqa: E731
+        assert np.abs(W @ p(t) - p(x)).max() <= 1e-11 * max(1.0, np.abs(p(x)).max())
+
+
+def blobs(N, box, seed, a=1.0, z0=1.5):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, (N, 3)) * np.array(box)
+    pos[:, 2] += z0 * a
+    return pos, rng.standard_normal((N, 3))
+
+
+def poly_kernel(n):
+    """A 3x3 kernel of degree n-1 in each coordinate of x and of y."""
+    B = np.arange(1.0, 10.0).reshape(3, 3)
+
+    def K(x, y):
+        x, y = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float))
+        s = 1 + 0.3 * x[..., 0] * y[..., 1] - 0.2 * (x[..., 2] ** (n - 1)) * y[..., 2] \
+            + 0.1 * x[..., 1] * (y[..., 0] ** (n - 1))
+        out = B * s[..., None, None]
+        out = out + 0.05 * x[..., :, None] * y[..., None, :]
+        return out
+    return K
+
+
+@pytest.mark.parametrize("n,L", [(2, 2), (3, 3), (4, 3)])
+def test_polynomial_kernel_is_exact(n, L):
+    pos, lam = blobs(300, (40, 40, 20), 11 + n)
+    K = poly_kernel(n)
+    u = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, n, L, kernel=K)
+    ref = np.einsum("tsij,sj->ti", K(pos[:, None, :], pos[None, :, :]), lam)
+    assert np.abs(u - ref).max() <= 1e-10 * np.abs(ref).max()
+    # the interpolated part is not empty: the same kernel with one degree too
+    # many in y is no longer exact
+    K2 = poly_kernel(n + 1)
+    u2 = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, n, L, kernel=K2)
+    ref2 = np.einsum("tsij,sj->ti", K2(pos[:, None, :], pos[None, :, :]), lam)
+    assert np.abs(u2 - ref2).max() > 1e-6 * np.abs(ref2).max()
+
+
+def test_levels_and_root_cube():
+    pos, _ = blobs(200, (40, 20, 10), 3, a=0.5)
+    o, S = fastsum.root_cube(pos, 0.5)
+    assert np.all(fastsum.cell_coords(pos, o, S, 4) < 16) and np.all(fastsum.cell_coords(pos, o, S, 4) >= 0)
+    L = fastsum.max_level(pos, 0.5)
+    assert S / 2 ** L >= 1.0 > S / 2 ** (L + 1)
+    with pytest.raises(ValueError):
+        fastsum.fmm_apply(pos, np.zeros_like(pos), 0.5, 1.0, False, 3, L + 1)
+
+
+@pytest.mark.parametrize("wall", [False, True])
+def test_no_interaction_list_is_the_direct_sum(wall):
+    pos, lam = blobs(120, (30, 30, 8), 5)
+    for L in (0, 1):
+        u = fastsum.fmm_apply(pos, lam, 1.0, 1.3, wall, 4, L)
+        ref = rpy.mobility_apply(pos, lam, 1.0, 1.3, wall)
+        assert np.abs(u - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("wall", [False, True])
+def test_rpy_error_falls_geometrically_with_order(wall):
+    """A slab two leaves thick (leaf side 6a; 12a above the wall): the max error
+    over blobs, relative to the largest entry, falls by a roughly constant
+    factor per order."""
+    pos, lam = blobs(400 if not wall else 200, (48, 48, 10), 9)
+    ref = rpy.mobility_apply(pos, lam, 1.0, 1.0, wall)
+    errs = []
+    # (the wall tensor of the oracle is slow: fewer, larger cells there)
+    for n in ((2, 3, 4, 5) if not wall else (2, 3, 4)):
+        u = fastsum.fmm_apply(pos, lam, 1.0, 1.0, wall, n, 3 if not wall else 2)
+        errs.append(np.abs(u - ref).max() / np.abs(ref).max())
+    print("max error by order:", ["%.1e" % e for e in errs])
+    assert errs[0] > 1e-4                   # the interpolation is really used
+    assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < errs[0] * (1e-2 if not wall else 3e-2)
