@@ -65,6 +65,9 @@ extern "C" {
 #define ARB_PAIR_AUTO      0  /* autotuned (wall RPY) / by size (single-blob bodies) */
 #define ARB_PAIR_TARGET    1  /* target-parallel: ordered sums, bitwise reproducible */
 #define ARB_PAIR_SYMMETRIC 2  /* each unordered pair once, FP64 atomic sums           */
+#define ARB_PAIR_FMM       3  /* fast product for large N: Chebyshev-interpolation     */
+                              /* multipole method (fmm_* options); an approximation   */
+                              /* of every blob mobility product, FP32 arithmetic      */
 
 /* body models */
 #define ARB_MODEL_MULTIBLOB   0  /* rigid multiblob bodies, Eq. linear_system (Sec. 2.3) */
@@ -98,6 +101,21 @@ typedef struct {
                        /* index in HIP graphs and replayed (default),          */
                        /* 1 = plain launches                                   */
     int    model;      /* ARB_MODEL_MULTIBLOB (default) or ARB_MODEL_SINGLE_BLOB */
+    /* ARB_PAIR_FMM only (rigid multiblob bodies).  The octree's root cube spans
+     * the blobs; cells of a level are adjacent when their integer coordinates
+     * differ by at most 1.  Pairs in adjacent leaves are summed directly; the
+     * tensor between well-separated cells is replaced by its tensor-product
+     * Chebyshev interpolant (fmm_order points per direction) in both
+     * arguments.  The error falls geometrically with fmm_order (max error
+     * relative to the largest entry about 1e-4 at 5, 1e-5 at 6 for dense
+     * suspensions).  The tree is rebuilt on the host whenever the state
+     * changes (one device-to-host copy of the positions and a sort).        */
+    int    fmm_order;  /* Chebyshev points per direction, 2..8 (0 = 6)          */
+    int    fmm_levels; /* leaf level L (0 = the shallowest level whose mean     */
+                       /* occupancy is <= fmm_leaf); never deeper than the      */
+                       /* deepest level with a cell side >= 2a; L <= 1 gives the */
+                       /* direct sum                                            */
+    int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = fmm_order^3)        */
 } arb_options;
 
 typedef struct {

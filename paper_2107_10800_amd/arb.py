@@ -37,6 +37,7 @@ ARB_MODEL_SINGLE_BLOB = 1
 ARB_PAIR_AUTO = 0
 ARB_PAIR_TARGET = 1
 ARB_PAIR_SYMMETRIC = 2
+ARB_PAIR_FMM = 3
 
 SYMBOLS = [
     "arb_create", "arb_destroy", "arb_last_error", "arb_get_slices", "arb_set_bodies",
@@ -63,7 +64,8 @@ class arb_options(C.Structure):
                 ("eta", C.c_double), ("a", C.c_double), ("tol", C.c_double),
                 ("restart", C.c_int), ("max_iter", C.c_int), ("precond", C.c_int),
                 ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int),
-                ("model", C.c_int)]
+                ("model", C.c_int), ("fmm_order", C.c_int), ("fmm_levels", C.c_int),
+                ("fmm_leaf", C.c_int)]
 
 
 class arb_step_info(C.Structure):
@@ -207,9 +209,10 @@ def _check(ctx, rc):
 # ------------------------------------------------------------------ entry points
 def arb_create(device=0, precision=ARB_FP64, wall=False, eta=1.0, a=1.0, tol=1e-10,
                restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0, pair_kernel=0,
-               graphs=0, model=ARB_MODEL_MULTIBLOB):
+               graphs=0, model=ARB_MODEL_MULTIBLOB, fmm_order=0, fmm_levels=0, fmm_leaf=0):
     opt = arb_options(device, precision, int(bool(wall)), eta, a, tol, restart, max_iter,
-                      precond, slices, pair_kernel, graphs, model)
+                      precond, slices, pair_kernel, graphs, model, fmm_order, fmm_levels,
+                      fmm_leaf)
     h = _P()
     rc = load().arb_create(C.byref(h), C.byref(opt))
     if rc < 0:
@@ -543,14 +546,16 @@ def arb_body_mobility(ctx):
 
 # ------------------------------------------------------------------ convenience
 def context_for(wl, precision=ARB_FP64, tol=1e-10, restart=100, max_iter=1000,
-                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0, graphs=0, model=None):
+                precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0, graphs=0, model=None,
+                fmm_order=0, fmm_levels=0, fmm_leaf=0):
     """Create a context and load a workload (bodies, links, rows, state).  The body
     model defaults to single-blob for workloads that mark themselves so."""
     if model is None:
         model = ARB_MODEL_SINGLE_BLOB if wl.extra.get("single_blob") else ARB_MODEL_MULTIBLOB
     ctx = arb_create(device=device, precision=precision, wall=wl.wall, eta=wl.eta, a=wl.a,
                      tol=tol, restart=restart, max_iter=max_iter, precond=precond, slices=slices,
-                     pair_kernel=pair_kernel, graphs=graphs, model=model)
+                     pair_kernel=pair_kernel, graphs=graphs, model=model, fmm_order=fmm_order,
+                     fmm_levels=fmm_levels, fmm_leaf=fmm_leaf)
     arb_set_bodies(ctx, wl.blob_offset, wl.r_ref, wl.body_type)
     if len(wl.pq):
         arb_set_links(ctx, wl.pq, wl.dl_p, wl.dl_q, wl.dldot_p, wl.dldot_q, wl.nproj, wl.proj)

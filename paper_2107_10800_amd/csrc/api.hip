@@ -269,6 +269,7 @@ int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
                         ctx->hi.as<float4>(), ctx->lo.as<float4>());
     if (!ctx->topo_dirty) TRY(refresh_rows(ctx, s));
     ctx->pc_built = false;
+    ctx->fmm.dirty = true;
     return 0;
 }
 
@@ -392,8 +393,44 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
     return 0;
 }
 
+// the fast product (ARB_PAIR_FMM): the tree is rebuilt when the geometry has
+// changed (or when asked), then out = M lambda - K U as run_pair writes it
+int fmm_pair(arb_ctx *ctx, hipStream_t s, int N, const double *pos, const float4 *hi,
+             const float4 *lo, const double *lam, double *out, const double *U, const int *bob,
+             const double *dvec, bool rebuild, int precision) {
+    arb::FmmState &F = ctx->fmm;
+    if (rebuild || F.dirty || !F.ready || F.N != N) {
+        std::string msg;
+        const int rc = arb::fmm_build(F, s, N, pos, hi, lo, ctx->opt.a, ctx->opt.fmm_order,
+                                      ctx->opt.fmm_levels, ctx->opt.fmm_leaf, &msg);
+        if (rc) return fail(ctx, rc, msg);
+        F.dirty = false;
+    }
+    HIPCHK(ctx->partial.ensure((size_t)3 * std::max(N, 1) * sizeof(double)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->prof) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+    }
+    arb::fmm_apply(F, s, ctx->opt.wall != 0, precision == ARB_FP64, lam,
+                   ctx->partial.as<double>());
+    if (ctx->prof) {
+        HIPCHK(hipEventRecord(e1, s));
+        ctx->prof_ev.emplace_back(e0, e1);
+    }
+    // sums in units of the blob radius: M(a) = M_{a=1}(r / a) / a
+    const double scale = 1.0 / (8.0 * arb::kPi * ctx->opt.eta) / ctx->opt.a;
+    if (N > 0) arb::pair_reduce(s, N, 1, ctx->partial.as<double>(), scale, out, U, bob, dvec);
+    return 0;
+}
+
 int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const double *U,
              int precision) {
+    if (ctx->opt.pair_kernel == ARB_PAIR_FMM)
+        return fmm_pair(ctx, s, ctx->N, ctx->pos.as<double>(), ctx->hi.as<float4>(),
+                        ctx->lo.as<float4>(), lam, out, U, ctx->body_of_blob.as<int>(),
+                        ctx->dvec.as<double>(), false, precision);
     const bool wall = ctx->opt.wall != 0;
     int sl = 0;
     TRY(choose_slices(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
@@ -799,7 +836,7 @@ std::vector<long long> graph_key(arb_ctx *ctx, const Krylov &K, int prec) {
     return {(long long)arb::alloc_generation().load(), (long long)K.n, K.m, prec,
             ctx->opt.precond, ctx->pc_learned ? 1 : 0, ctx->pc_lcorr ? 1 : 0, ctx->N, ctx->M,
             ctx->Nc, ctx->n_asm, it == ctx->slice_cache.end() ? 0 : it->second,
-            (long long)(intptr_t)K.V, (long long)(intptr_t)ctx->pinned};
+            (long long)(intptr_t)K.V, (long long)(intptr_t)ctx->pinned, ctx->fmm.version};
 }
 
 // run one Arnoldi step: replay its graph, capturing it first if needed; plain
@@ -1034,11 +1071,15 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         opt->restart > 256 || opt->max_iter < 1 ||
         (opt->precision != ARB_FP64 && opt->precision != ARB_FP32C) || opt->precond < 0 ||
         opt->precond > 3 || opt->slices < 0 || opt->slices > 4096 || opt->pair_kernel < 0 ||
-        opt->pair_kernel > 2 || opt->graphs < 0 || opt->graphs > 1 ||
-        (opt->model != ARB_MODEL_MULTIBLOB && opt->model != ARB_MODEL_SINGLE_BLOB))
+        opt->pair_kernel > ARB_PAIR_FMM || opt->graphs < 0 || opt->graphs > 1 ||
+        (opt->model != ARB_MODEL_MULTIBLOB && opt->model != ARB_MODEL_SINGLE_BLOB) ||
+        (opt->fmm_order != 0 && (opt->fmm_order < 2 || opt->fmm_order > arb::kFmmMaxOrder)) ||
+        opt->fmm_levels < 0 || opt->fmm_levels > arb::kFmmMaxLevel || opt->fmm_leaf < 0)
         return ARB_E_ARG;
-    // single-blob bodies: unbounded generalised RPY, exact or no preconditioner
-    if (opt->model == ARB_MODEL_SINGLE_BLOB && (opt->wall != 0 || opt->precond > ARB_PC_BLOCK))
+    // single-blob bodies: unbounded generalised RPY, exact or no preconditioner,
+    // direct sums
+    if (opt->model == ARB_MODEL_SINGLE_BLOB &&
+        (opt->wall != 0 || opt->precond > ARB_PC_BLOCK || opt->pair_kernel == ARB_PAIR_FMM))
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
@@ -1282,6 +1323,14 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *
     float4 *hi = reinterpret_cast<float4 *>(p64 + N);
     float4 *lo = hi + N;
     arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo);
+    if (ctx->opt.pair_kernel == ARB_PAIR_FMM) {
+        // a tree of these positions; the context's own is rebuilt at its next product
+        TRY(fmm_pair(ctx, s, N, pos_dev, hi, lo, lambda_dev, u_dev, nullptr, nullptr, nullptr,
+                     true, ctx->opt.precision));
+        ctx->fmm.dirty = true;
+        HIPCHK(hipGetLastError());
+        return ARB_OK;
+    }
     const bool wall = ctx->opt.wall != 0;
     int sl = 0;
     TRY(choose_slices(ctx, s, N, p64, hi, lo, lambda_dev, ctx->opt.precision, wall, &sl));

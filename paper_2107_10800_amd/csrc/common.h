@@ -67,6 +67,36 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// ---------------------------------------------------------------- fast product (fmm.hip)
+constexpr int kFmmMaxOrder = 8;                                          // Chebyshev points per direction
+constexpr int kFmmMaxP = kFmmMaxOrder * kFmmMaxOrder * kFmmMaxOrder;   // proxies per cell
+constexpr int kFmmMaxLevel = 16;
+constexpr int kFmmDefaultOrder = 6;
+
+// octree and proxy buffers of the fast product; cells of all levels 0..L in
+// Morton order, level l at [lvl[l], lvl[l+1])
+struct FmmState {
+    DevBuf perm, cc, rng, parent, kids, il_ptr, il, near_ptr, nearl, work, tab, shi, slo, slam,
+        qhat, v;
+    int N = 0, L = 0, n = 0, P = 0, ncell = 0, nleaf = 0, nwork = 0;
+    int64_t n_il = 0, n_near_pairs = 0;  // interaction-list entries, direct pairs
+    std::vector<int> lvl;
+    double o[3] = {0.0, 0.0, 0.0}, S = 0.0;  // root cube in units of a
+    long long version = 0;                   // bumped by every build
+    bool ready = false, dirty = true;
+};
+// tree of N blobs (positions in units of length on the device, hi/lo as
+// prep_positions makes them); order = Chebyshev points per direction (0: the
+// default), levels = leaf level (0: from leaf, the mean blobs per leaf aimed at;
+// 0: n^3).  Returns 0 or an ARB_E_* code with *msg set.
+int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
+              const float4 *lo, double a, int order, int levels, int leaf, std::string *msg);
+// partial[c][i] (3 x N, original order) = the approximation of M_{a=1} lambda,
+// M in units of 1/(8 pi eta) with positions in units of a; fp64: lambda and
+// every sum in double (linear in lambda to double rounding), else in float
+void fmm_apply(const FmmState &F, hipStream_t s, bool wall, bool fp64, const double *lam,
+               double *partial);
+
 // ---------------------------------------------------------------- kernel entry points
 // Pair sum u_i = sum_j M_ij lambda_j (Sec. 2.3): partial sums per source slice,
 // then an ordered reduction.  Positions are prepared by prep_positions().
@@ -327,6 +357,8 @@ struct arb_ctx {
     int mlp_step = 0;
     bool types_ready = false;
     std::vector<int> h_type_ref;  // reference body of each type
+    // fast product (ARB_PAIR_FMM)
+    arb::FmmState fmm;
     // pair-kernel timing (arb_profile)
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;

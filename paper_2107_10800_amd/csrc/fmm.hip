@@ -1,0 +1,742 @@
+// Fast blob mobility product u = M lambda for large systems (Sec. 2.3; the
+// paper names fast summation, Sec. 1 and Sec. 6, as the route past dense sums).
+//
+// A kernel-independent multipole method (the black-box FMM of Fong and Darve,
+// J. Comput. Phys. 228, 2009): the RPY tensor of two well-separated cells is
+// replaced by its tensor-product Chebyshev interpolant in both arguments,
+//   M(x, y) ~ sum_k sum_m S_k(x) M(t_k, s_m) S_m(y),
+// with t, s the n^3 proxy points of the target and source cells.  The pair
+// function is the one of the direct sums (unbounded, or with the wall image):
+// above the wall nothing else changes, since the image y* of a source is never
+// closer to a target than y itself, so a well-separated pair stays
+// well-separated for the image term too.
+//
+// Tree (built on the host once per geometry, in units of length):
+//   root cube: origin o = componentwise minimum of the positions, side
+//   S = largest extent * (1 + 2^-20) (S = a when all blobs coincide); a blob
+//   lies at level l in the cell floor(((x - o) / S) 2^l); cells of one level are
+//   adjacent when their coordinates differ by at most 1 per direction.  Leaf
+//   level L: fixed by the options, or the shallowest level whose mean
+//   occupancy is at most the requested blobs per leaf, never deeper than the
+//   deepest level with a cell side >= 2a (so every interpolated pair has
+//   r > 2a and stays off the overlap branch of the tensor).  Interaction list
+//   of a cell at level l >= 2: the non-empty cells whose parent is adjacent to
+//   its parent and which are not adjacent to it.
+// Per product (all on the GPU, sorted by Morton key):
+//   P2M  qhat^c_m = sum_{j in c} S^c_m(y_j) lam_j at the leaves;
+//   M2M  the parent's qhat from its children's proxies (exact: the parent's
+//        Lagrange polynomials have degree n-1 and the children interpolate
+//        them exactly);
+//   M2L  v^c_k = sum_{c' in IL(c)} sum_m M(t^c_k, s^c'_m) qhat^c'_m, matrix-free
+//        with the FP32 pair function (one workgroup per cell, one lane per
+//        target proxy, the source proxies of each listed cell staged in LDS);
+//   L2L  the children's v gain the parent's interpolant at their proxies;
+//   near + L2P  direct sums over the adjacent leaves (hi/lo split positions,
+//        float runs promoted to double, as in the dense FP32 kernel) plus
+//        sum_k S^leaf_k(x_i) v^leaf_k, written in the original blob order.
+// With L <= 1 there is no interaction list: one cell, the direct sum.
+// Two arithmetic variants share the tree and the float-rounded kernel values
+// and weights: A = float (lambda, qhat and the runs of sums in float) and
+// A = double (lambda, qhat and every sum in double).  The second is linear in
+// lambda to double rounding, so Krylov iterations on it converge to any
+// tolerance; the float variant serves the inner iterations of FP64 iterative
+// refinement.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "rpy_device.h"
+
+namespace arb {
+
+namespace {
+
+constexpr int kTabNode = 0, kTabDen = kFmmMaxOrder, kTabT1 = 2 * kFmmMaxOrder;
+constexpr int kTabSize = 2 * kFmmMaxOrder + 2 * kFmmMaxOrder * kFmmMaxOrder;
+constexpr int kNearBlock = 64;
+constexpr int kFmmRun = 32;
+
+template <class A>
+using Vec4 = std::conditional_t<std::is_same_v<A, float>, float4, double4>;
+
+template <class A>
+__device__ __forceinline__ Vec4<A> vec4(A x, A y, A z) {
+    Vec4<A> r;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.w = A(0);
+    return r;
+}
+
+// free-space RPY coefficients c1, c2 (units of a) of M = c1 I + c2 r r^T
+__device__ __forceinline__ void free_coef(float r2, float rinv, float &c1, float &c2) {
+    constexpr CoefF c = kUnitCoefF;
+    const float rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+    c1 = fmaf(c.k1, rinv3, rinv);
+    c2 = fmaf(-c.k2, rinv3 * rinv2, rinv3);
+    ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
+    if (r2 <= c.four_a2) {
+        const float rv = r2 > 0.f ? rinv : 0.f;
+        c1 = fmaf(-c.n2, r2 * rv, c.n1);
+        c2 = rv * c.n3;
+    }
+    ARB_END_IF_ANY
+}
+
+// acc += M(d) l for one pair: tensor coefficients in float, applied in A
+template <bool WALL, class A>
+__device__ __forceinline__ void pair_acc(float dx, float dy, float dz, float dxy2,
+                                         const TargetZ<float> &zsc, float zi, float zj, float h2,
+                                         float mh22, A lx, A ly, A lz, A &ax, A &ay, A &az) {
+    constexpr CoefF cf = kUnitCoefF;
+    const float r2 = fmaf(dz, dz, dxy2);
+    const float rinv = rsq_f32(r2);
+    if constexpr (WALL) {
+        const float Rz = zi + zj;
+        const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+        const PairCoef<float> pc =
+            wall_pair_coef<float>(r2, rinv, dxy2, zsc, zj, h2, mh22, Rz, Ri, cf);
+        if constexpr (std::is_same_v<A, float>) {
+            wall_pair_apply<float>(pc, pc.c, pc.d, dx, dy, dz, Rz, lx, ly, lz, ax, ay, az);
+        } else {
+            const PairCoef<double> pd{pc.cA, pc.cAe, pc.c2, pc.b, pc.c, pc.d, pc.e, pc.h2};
+            wall_pair_apply<double>(pd, pd.c, pd.d, dx, dy, dz, Rz, lx, ly, lz, ax, ay, az);
+        }
+    } else {
+        float c1, c2;
+        free_coef(r2, rinv, c1, c2);
+        const A rl = fma((A)dx, lx, fma((A)dy, ly, (A)dz * lz));
+        const A t = (A)c2 * rl;
+        ax = fma((A)c1, lx, fma(t, (A)dx, ax));
+        ay = fma((A)c1, ly, fma(t, (A)dy, ay));
+        az = fma((A)c1, lz, fma(t, (A)dz, az));
+    }
+}
+
+struct Geo {
+    double ox, oy, oz, S;  // root cube in units of a
+    int n, P;
+};
+
+__device__ __forceinline__ void load_tab(const float *__restrict__ g, float *tab) {
+    for (int i = threadIdx.x; i < kTabSize; i += blockDim.x) tab[i] = g[i];
+    __syncthreads();
+}
+
+// Lagrange polynomial l_k(u) at the Chebyshev points (product form)
+__device__ __forceinline__ float lag(const float *tab, int n, int k, float u) {
+    float p = tab[kTabDen + k];
+    for (int j = 0; j < n; ++j)
+        if (j != k) p *= u - tab[kTabNode + j];
+    return p;
+}
+
+// a double split into float hi + lo
+struct F2 {
+    float h, l;
+};
+__device__ __forceinline__ F2 split(double x) {
+    const float h = (float)x;
+    return F2{h, (float)(x - (double)h)};
+}
+
+__device__ __forceinline__ double centre(double o, double side, int i) {
+    return o + ((double)i + 0.5) * side;
+}
+
+__global__ void fmm_sort_pos_kernel(int N, const int *__restrict__ perm,
+                                    const float4 *__restrict__ hi, const float4 *__restrict__ lo,
+                                    float4 *__restrict__ shi, float4 *__restrict__ slo) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int i = perm[k];
+    shi[k] = hi[i];
+    slo[k] = lo[i];
+}
+
+template <class A>
+__global__ void fmm_gather_lam_kernel(int N, const int *__restrict__ perm,
+                                      const double *__restrict__ lam, Vec4<A> *__restrict__ slam) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int i = perm[k];
+    slam[k] = vec4<A>((A)lam[3 * i], (A)lam[3 * i + 1], (A)lam[3 * i + 2]);
+}
+
+// qhat of the leaves, one workgroup per leaf, one lane per proxy
+template <class A>
+__global__ __launch_bounds__(kFmmMaxP) void fmm_p2m_kernel(
+    Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
+    const int2 *__restrict__ rng, int cell0, const float4 *__restrict__ shi,
+    const float4 *__restrict__ slo, const Vec4<A> *__restrict__ slam, Vec4<A> *__restrict__ qhat) {
+    __shared__ float tab[kTabSize];
+    load_tab(tabg, tab);
+    const int c = cell0 + blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= g.P) return;
+    const int n = g.n;
+    const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
+    const int4 ci = cc[c];
+    const int2 r = rng[c];
+    const double side = ldexp(g.S, -ci.w);
+    const F2 cx = split(centre(g.ox, side, ci.x)), cy = split(centre(g.oy, side, ci.y)),
+             cz = split(centre(g.oz, side, ci.z));
+    const float iw = (float)(2.0 / side);
+    double qx = 0.0, qy = 0.0, qz = 0.0;
+    for (int j = r.x; j < r.y; ++j) {
+        const float4 h = shi[j], l = slo[j];
+        const Vec4<A> L = slam[j];
+        const float ux = ((h.x - cx.h) + (l.x - cx.l)) * iw;
+        const float uy = ((h.y - cy.h) + (l.y - cy.l)) * iw;
+        const float uz = ((h.z - cz.h) + (l.z - cz.l)) * iw;
+        const A s = (A)(lag(tab, n, kx, ux) * lag(tab, n, ky, uy) * lag(tab, n, kz, uz));
+        qx += (double)(s * L.x);
+        qy += (double)(s * L.y);
+        qz += (double)(s * L.z);
+    }
+    qhat[(size_t)c * g.P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
+}
+
+// qhat of the cells of one level from their children
+template <class A>
+__global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *__restrict__ tabg,
+                                                           const int4 *__restrict__ cc,
+                                                           const int2 *__restrict__ kids,
+                                                           int cell0, Vec4<A> *__restrict__ qhat) {
+    __shared__ float tab[kTabSize];
+    load_tab(tabg, tab);
+    const int c = cell0 + blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= g.P) return;
+    const int n = g.n, P = g.P;
+    const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
+    const int2 kr = kids[c];
+    double qx = 0.0, qy = 0.0, qz = 0.0;
+    for (int ch = kr.x; ch < kr.y; ++ch) {
+        const int4 cci = cc[ch];
+        // t1[sigma][k][m] = l_k(sigma/2 + xi_m/2): the parent's polynomial at the
+        // child's proxies (sigma = -1 for the lower child, the even coordinate)
+        const float *tx = tab + kTabT1 + (cci.x & 1) * kFmmMaxOrder * kFmmMaxOrder + kx * kFmmMaxOrder;
+        const float *ty = tab + kTabT1 + (cci.y & 1) * kFmmMaxOrder * kFmmMaxOrder + ky * kFmmMaxOrder;
+        const float *tz = tab + kTabT1 + (cci.z & 1) * kFmmMaxOrder * kFmmMaxOrder + kz * kFmmMaxOrder;
+        const Vec4<A> *q = qhat + (size_t)ch * P;
+        A fx = 0, fy = 0, fz = 0;
+        for (int mx = 0; mx < n; ++mx)
+            for (int my = 0; my < n; ++my) {
+                const float a = tx[mx] * ty[my];
+                for (int mz = 0; mz < n; ++mz) {
+                    const A w = (A)(a * tz[mz]);
+                    const Vec4<A> Q = q[(mx * n + my) * n + mz];
+                    fx = fma(w, Q.x, fx);
+                    fy = fma(w, Q.y, fy);
+                    fz = fma(w, Q.z, fz);
+                }
+            }
+        qx += fx;
+        qy += fy;
+        qz += fz;
+    }
+    qhat[(size_t)c * P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
+}
+
+// v of every cell of levels 2..L over its interaction list
+template <bool WALL, class A>
+__global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
+    Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
+    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0,
+    const Vec4<A> *__restrict__ qhat, double *__restrict__ v) {
+    __shared__ float tab[kTabSize];
+    __shared__ float4 s_off[kFmmMaxP];
+    __shared__ Vec4<A> s_q[kFmmMaxP];
+    load_tab(tabg, tab);
+    const int c = cell0 + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int n = g.n, P = g.P;
+    const int4 ct = cc[c];
+    const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
+    // proxy offsets w xi of this level (the same for every cell of it)
+    for (int m = tid; m < P; m += blockDim.x) {
+        const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
+        s_off[m] = make_float4((float)(w * tab[kTabNode + mx]), (float)(w * tab[kTabNode + my]),
+                               (float)(w * tab[kTabNode + mz]), 0.f);
+    }
+    const bool act = tid < P;
+    const int k = act ? tid : 0;
+    const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
+    const float okx = (float)(w * tab[kTabNode + kx]), oky = (float)(w * tab[kTabNode + ky]),
+                okz = (float)(w * tab[kTabNode + kz]);
+    const double czt = centre(g.oz, side, ct.z);
+    const float zi = (float)(czt + w * tab[kTabNode + kz]);  // target proxy height
+    const TargetZ<float> zsc = target_z(zi);
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    const int e1 = il_ptr[c + 1];
+    for (int e = il_ptr[c]; e < e1; ++e) {
+        const int sc = il[e];
+        const int4 cs = cc[sc];
+        __syncthreads();
+        for (int m = tid; m < P; m += blockDim.x) s_q[m] = qhat[(size_t)sc * P + m];
+        __syncthreads();
+        // target proxy minus source cell centre, from the integer offset
+        const float ax = (float)((double)(ct.x - cs.x) * side) + okx;
+        const float ay = (float)((double)(ct.y - cs.y) * side) + oky;
+        const float az = (float)((double)(ct.z - cs.z) * side) + okz;
+        const float zc = (float)centre(g.oz, side, cs.z);
+        for (int m0 = 0; m0 < P; m0 += kFmmRun) {
+            const int m1 = min(m0 + kFmmRun, P);
+            A fx = 0, fy = 0, fz = 0;
+            for (int m = m0; m < m1; ++m) {
+                const float4 o = s_off[m];
+                const Vec4<A> q = s_q[m];
+                const float dx = ax - o.x, dy = ay - o.y, dz = az - o.z;
+                const float dxy2 = fmaf(dx, dx, dy * dy);
+                const float zj = zc + o.z;
+                const float h2 = 2.f * zj;
+                pair_acc<WALL, A>(dx, dy, dz, dxy2, zsc, zi, zj, h2, -(h2 * h2), q.x, q.y, q.z, fx,
+                                  fy, fz);
+            }
+            ux += fx;
+            uy += fy;
+            uz += fz;
+        }
+    }
+    if (act) {
+        double *o = v + ((size_t)c * P + k) * 3;
+        o[0] = ux;
+        o[1] = uy;
+        o[2] = uz;
+    }
+}
+
+// the children at one level gain the parent's interpolant at their proxies
+__global__ __launch_bounds__(kFmmMaxP) void fmm_l2l_kernel(Geo g, const float *__restrict__ tabg,
+                                                           const int4 *__restrict__ cc,
+                                                           const int *__restrict__ parent,
+                                                           int cell0, double *__restrict__ v) {
+    __shared__ float tab[kTabSize];
+    load_tab(tabg, tab);
+    const int c = cell0 + blockIdx.x;
+    const int m = threadIdx.x;
+    if (m >= g.P) return;
+    const int n = g.n, P = g.P;
+    const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
+    const int4 cci = cc[c];
+    const float *tx = tab + kTabT1 + (cci.x & 1) * kFmmMaxOrder * kFmmMaxOrder + mx;
+    const float *ty = tab + kTabT1 + (cci.y & 1) * kFmmMaxOrder * kFmmMaxOrder + my;
+    const float *tz = tab + kTabT1 + (cci.z & 1) * kFmmMaxOrder * kFmmMaxOrder + mz;
+    const double *vp = v + (size_t)parent[c] * P * 3;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int kx = 0; kx < n; ++kx)
+        for (int ky = 0; ky < n; ++ky) {
+            const double a = (double)(tx[kx * kFmmMaxOrder] * ty[ky * kFmmMaxOrder]);
+            for (int kz = 0; kz < n; ++kz) {
+                const double wk = a * (double)tz[kz * kFmmMaxOrder];
+                const double *pv = vp + 3 * ((kx * n + ky) * n + kz);
+                sx = fma(wk, pv[0], sx);
+                sy = fma(wk, pv[1], sy);
+                sz = fma(wk, pv[2], sz);
+            }
+        }
+    double *o = v + ((size_t)c * P + m) * 3;
+    o[0] += sx;
+    o[1] += sy;
+    o[2] += sz;
+}
+
+// direct sums over the adjacent leaves plus the leaf's interpolant; one
+// workgroup per (leaf, run of 64 targets); output in the original blob order
+template <bool WALL, class A>
+__global__ __launch_bounds__(kNearBlock) void fmm_near_kernel(
+    Geo g, const float *__restrict__ tabg, int N, int far, const int4 *__restrict__ cc,
+    const int2 *__restrict__ rng, const int *__restrict__ near_ptr, const int *__restrict__ near,
+    int leaf0, const int2 *__restrict__ work, const int *__restrict__ perm,
+    const float4 *__restrict__ shi, const float4 *__restrict__ slo,
+    const Vec4<A> *__restrict__ slam, const double *__restrict__ v, double *__restrict__ partial) {
+    __shared__ float tab[kTabSize];
+    __shared__ float4 s_hi[kNearBlock], s_lo[kNearBlock];
+    __shared__ Vec4<A> s_lam[kNearBlock];
+    load_tab(tabg, tab);
+    const int tid = threadIdx.x;
+    const int2 wk = work[blockIdx.x];
+    const int c = wk.x;
+    const int2 tr = rng[c];
+    const int i = wk.y + tid;
+    const bool act = i < tr.y;
+    const int ic = act ? i : tr.y - 1;
+    const float4 th = shi[ic], tl = slo[ic];
+    const float zi = th.z + tl.z;
+    const TargetZ<float> zsc = target_z(zi);
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    const int lf = c - leaf0;
+    const int e1 = near_ptr[lf + 1];
+    for (int e = near_ptr[lf]; e < e1; ++e) {
+        const int2 sr = rng[near[e]];
+        for (int j0 = sr.x; j0 < sr.y; j0 += kNearBlock) {
+            const int j = j0 + tid;
+            __syncthreads();
+            if (j < sr.y) {
+                s_hi[tid] = shi[j];
+                s_lo[tid] = slo[j];
+                s_lam[tid] = slam[j];
+            }
+            __syncthreads();
+            const int cnt = min(kNearBlock, sr.y - j0);
+            for (int k0 = 0; k0 < cnt; k0 += kFmmRun) {
+                const int k1 = min(k0 + kFmmRun, cnt);
+                A ax = 0, ay = 0, az = 0;
+                for (int k = k0; k < k1; ++k) {
+                    const float4 sh = s_hi[k], sl = s_lo[k];
+                    const Vec4<A> L = s_lam[k];
+                    const float dx = (th.x - sh.x) + (tl.x - sl.x);
+                    const float dy = (th.y - sh.y) + (tl.y - sl.y);
+                    const float dz = (th.z - sh.z) + (tl.z - sl.z);
+                    const float dxy2 = fmaf(dx, dx, dy * dy);
+                    pair_acc<WALL, A>(dx, dy, dz, dxy2, zsc, zi, sh.z, sh.w, sl.w, L.x, L.y, L.z,
+                                      ax, ay, az);
+                }
+                ux += ax;
+                uy += ay;
+                uz += az;
+            }
+        }
+    }
+    if (far) {
+        const int n = g.n;
+        const int4 ci = cc[c];
+        const double side = ldexp(g.S, -ci.w);
+        const F2 cx = split(centre(g.ox, side, ci.x)), cy = split(centre(g.oy, side, ci.y)),
+                 cz = split(centre(g.oz, side, ci.z));
+        const float iw = (float)(2.0 / side);
+        const float px = ((th.x - cx.h) + (tl.x - cx.l)) * iw;
+        const float py = ((th.y - cy.h) + (tl.y - cy.l)) * iw;
+        const float pz = ((th.z - cz.h) + (tl.z - cz.l)) * iw;
+        const double *vc = v + (size_t)c * g.P * 3;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int kx = 0; kx < n; ++kx) {
+            const float a = lag(tab, n, kx, px);
+            for (int ky = 0; ky < n; ++ky) {
+                const float b = a * lag(tab, n, ky, py);
+                for (int kz = 0; kz < n; ++kz) {
+                    const double wk = (double)(b * lag(tab, n, kz, pz));
+                    const double *pv = vc + 3 * ((kx * n + ky) * n + kz);
+                    sx = fma(wk, pv[0], sx);
+                    sy = fma(wk, pv[1], sy);
+                    sz = fma(wk, pv[2], sz);
+                }
+            }
+        }
+        ux += sx;
+        uy += sy;
+        uz += sz;
+    }
+    if (act) {
+        const size_t o = (size_t)perm[i];
+        partial[o] = ux;
+        partial[(size_t)N + o] = uy;
+        partial[2 * (size_t)N + o] = uz;
+    }
+}
+
+// ---------------------------------------------------------------- host tree
+inline uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
+    x &= 0x1fffff;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+inline uint64_t morton(int x, int y, int z) {
+    return (spread3((uint64_t)x) << 2) | (spread3((uint64_t)y) << 1) | spread3((uint64_t)z);
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
+              const float4 *lo, double a, int order, int levels, int leaf, std::string *msg) {
+    F.N = 0;
+    F.ready = false;
+    const int n = order > 0 ? order : kFmmDefaultOrder;
+    if (n < 2 || n > kFmmMaxOrder || levels < 0 || leaf < 0 || N < 0) {
+        *msg = "fast product: order must be 2..8, levels and leaf >= 0";
+        return ARB_E_ARG;
+    }
+    F.n = n;
+    F.P = n * n * n;
+    ++F.version;
+    if (N == 0) {
+        F.ready = true;
+        return 0;
+    }
+    std::vector<double> h(3 * (size_t)N);
+    if (hipMemcpyAsync(h.data(), pos_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        *msg = "fast product: copying positions failed";
+        return ARB_E_DEVICE;
+    }
+    // root cube
+    double o[3], ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double lo_d = h[d], hi_d = h[d];
+        for (int i = 1; i < N; ++i) {
+            lo_d = std::min(lo_d, h[3 * (size_t)i + d]);
+            hi_d = std::max(hi_d, h[3 * (size_t)i + d]);
+        }
+        o[d] = lo_d;
+        ext = std::max(ext, hi_d - lo_d);
+    }
+    const double S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : a;
+    int Lhi = 0;  // deepest level with a cell side >= 2a
+    while (Lhi < kFmmMaxLevel && S / std::ldexp(1.0, Lhi + 1) >= 2.0 * a) ++Lhi;
+    // cell coordinates at level Lhi and Morton keys
+    std::vector<int> crd(3 * (size_t)N);
+    std::vector<std::pair<uint64_t, int>> kk((size_t)N);
+    const double scale = std::ldexp(1.0, Lhi);
+    for (int i = 0; i < N; ++i) {
+        int cq[3];
+        for (int d = 0; d < 3; ++d) {
+            const double u = (h[3 * (size_t)i + d] - o[d]) / S;
+            cq[d] = (int)std::floor(u * scale);
+            crd[3 * (size_t)i + d] = cq[d];
+        }
+        kk[i] = {morton(cq[0], cq[1], cq[2]), i};
+    }
+    std::sort(kk.begin(), kk.end());
+    // leaf level
+    const int leaf_target = leaf > 0 ? leaf : F.P;
+    int L;
+    if (Lhi < 2) {
+        L = 0;
+    } else if (levels > 0) {
+        L = levels < 2 ? 0 : std::min(levels, Lhi);
+    } else {
+        L = Lhi;
+        for (int l = 2; l <= Lhi; ++l) {
+            const int sh = 3 * (Lhi - l);
+            int64_t cells = 1;
+            for (int j = 1; j < N; ++j) cells += (kk[j].first >> sh) != (kk[j - 1].first >> sh);
+            if ((int64_t)N <= (int64_t)leaf_target * cells) {
+                L = l;
+                break;
+            }
+        }
+    }
+    F.L = L;
+    // cells of every level in Morton order, with their blob ranges
+    std::vector<int4> cc;
+    std::vector<int2> rng;
+    std::vector<uint64_t> pk;
+    std::vector<int> lvl(L + 2, 0);
+    for (int l = 0; l <= L; ++l) {
+        lvl[l] = (int)cc.size();
+        const int sh = 3 * (Lhi - l);
+        for (int j = 0; j < N;) {
+            const uint64_t p = kk[j].first >> sh;
+            int e = j + 1;
+            while (e < N && (kk[e].first >> sh) == p) ++e;
+            const int i0 = kk[j].second;
+            const int dl = Lhi - l;
+            cc.push_back(make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
+                                   crd[3 * (size_t)i0 + 2] >> dl, l));
+            rng.push_back(make_int2(j, e));
+            pk.push_back(p);
+            j = e;
+        }
+    }
+    lvl[L + 1] = (int)cc.size();
+    const int ncell = (int)cc.size();
+    std::vector<int> parent(ncell, -1);
+    std::vector<int2> kids(ncell, make_int2(0, 0));
+    for (int l = 1; l <= L; ++l) {
+        int p = lvl[l - 1];
+        for (int c = lvl[l]; c < lvl[l + 1]; ++c) {
+            while (rng[p].y <= rng[c].x) ++p;
+            parent[c] = p;
+            if (kids[p].y == 0) kids[p] = make_int2(c, c + 1);
+            else kids[p].y = c + 1;
+        }
+    }
+    auto find = [&](int l, int x, int y, int z) -> int {
+        const int lim = 1 << l;
+        if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
+        const uint64_t key = morton(x, y, z);
+        auto b = pk.begin() + lvl[l], e = pk.begin() + lvl[l + 1];
+        auto it = std::lower_bound(b, e, key);
+        return (it != e && *it == key) ? (int)(it - pk.begin()) : -1;
+    };
+    auto adjacent = [&](int c1, int c2) {
+        return std::abs(cc[c1].x - cc[c2].x) <= 1 && std::abs(cc[c1].y - cc[c2].y) <= 1 &&
+               std::abs(cc[c1].z - cc[c2].z) <= 1;
+    };
+    // interaction lists (levels 2..L) and the adjacent leaves
+    std::vector<int> il_ptr(ncell + 1, 0), il;
+    for (int c = 0; c < ncell; ++c) {
+        const int l = cc[c].w;
+        if (l >= 2) {
+            const int4 pc = cc[parent[c]];
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int q = find(l - 1, pc.x + dx, pc.y + dy, pc.z + dz);
+                        if (q < 0) continue;
+                        for (int ch = kids[q].x; ch < kids[q].y; ++ch)
+                            if (!adjacent(ch, c)) il.push_back(ch);
+                    }
+        }
+        il_ptr[c + 1] = (int)il.size();
+    }
+    const int leaf0 = lvl[L], nleaf = lvl[L + 1] - lvl[L];
+    std::vector<int> near_ptr(nleaf + 1, 0), nearl;
+    std::vector<int2> work;
+    for (int c = leaf0; c < leaf0 + nleaf; ++c) {
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int q = find(L, cc[c].x + dx, cc[c].y + dy, cc[c].z + dz);
+                    if (q >= 0) nearl.push_back(q);
+                }
+        near_ptr[c - leaf0 + 1] = (int)nearl.size();
+        for (int k0 = rng[c].x; k0 < rng[c].y; k0 += kNearBlock) work.push_back(make_int2(c, k0));
+    }
+    // every target sees every source exactly once: the adjacent leaves and the
+    // interaction lists of its ancestors hold N blobs between them, and every
+    // index handed to a kernel is in range
+    for (int c = leaf0; c < leaf0 + nleaf; ++c) {
+        int64_t cnt = 0;
+        for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e) {
+            const int q = nearl[e];
+            if (q < leaf0 || q >= leaf0 + nleaf) {
+                *msg = "fast product: internal error (near list)";
+                return ARB_E_ARG;
+            }
+            cnt += rng[q].y - rng[q].x;
+        }
+        for (int a2 = c; a2 >= 0 && cc[a2].w >= 2; a2 = parent[a2])
+            for (int e = il_ptr[a2]; e < il_ptr[a2 + 1]; ++e) cnt += rng[il[e]].y - rng[il[e]].x;
+        if (cnt != N) {
+            *msg = "fast product: internal error (cells do not partition the blobs)";
+            return ARB_E_ARG;
+        }
+    }
+    // Chebyshev points, Lagrange denominators, parent polynomials at child proxies
+    std::vector<float> tab(kTabSize, 0.f);
+    double xn[kFmmMaxOrder];
+    for (int k = 0; k < n; ++k) xn[k] = std::cos((2 * k + 1) * kPi / (2 * n));
+    for (int k = 0; k < n; ++k) {
+        double den = 1.0;
+        for (int j = 0; j < n; ++j)
+            if (j != k) den *= xn[k] - xn[j];
+        tab[kTabNode + k] = (float)xn[k];
+        tab[kTabDen + k] = (float)(1.0 / den);
+    }
+    for (int sg = 0; sg < 2; ++sg)
+        for (int k = 0; k < n; ++k)
+            for (int m = 0; m < n; ++m) {
+                const double u = (sg ? 0.5 : -0.5) + 0.5 * xn[m];
+                double p = 1.0;
+                for (int j = 0; j < n; ++j)
+                    if (j != k) p *= (u - xn[j]) / (xn[k] - xn[j]);
+                tab[kTabT1 + (sg * kFmmMaxOrder + k) * kFmmMaxOrder + m] = (float)p;
+            }
+    std::vector<int> perm((size_t)N);
+    for (int j = 0; j < N; ++j) perm[j] = kk[j].second;
+    // upload
+    const int P = F.P;
+    auto up = [&](DevBuf &b, const void *src, size_t bytes) -> bool {
+        if (b.ensure(std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+        return bytes == 0 ||
+               hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool ok = up(F.perm, perm.data(), perm.size() * sizeof(int)) &&
+              up(F.cc, cc.data(), cc.size() * sizeof(int4)) &&
+              up(F.rng, rng.data(), rng.size() * sizeof(int2)) &&
+              up(F.parent, parent.data(), parent.size() * sizeof(int)) &&
+              up(F.kids, kids.data(), kids.size() * sizeof(int2)) &&
+              up(F.il_ptr, il_ptr.data(), il_ptr.size() * sizeof(int)) &&
+              up(F.il, il.data(), il.size() * sizeof(int)) &&
+              up(F.near_ptr, near_ptr.data(), near_ptr.size() * sizeof(int)) &&
+              up(F.nearl, nearl.data(), nearl.size() * sizeof(int)) &&
+              up(F.work, work.data(), work.size() * sizeof(int2)) &&
+              up(F.tab, tab.data(), tab.size() * sizeof(float)) &&
+              F.shi.ensure((size_t)N * sizeof(float4)) == hipSuccess &&
+              F.slo.ensure((size_t)N * sizeof(float4)) == hipSuccess &&
+              F.slam.ensure((size_t)N * sizeof(double4)) == hipSuccess &&
+              F.qhat.ensure((size_t)ncell * P * sizeof(double4)) == hipSuccess &&
+              F.v.ensure((size_t)ncell * P * 3 * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        *msg = "fast product: device allocation or copy failed";
+        return ARB_E_DEVICE;
+    }
+    fmm_sort_pos_kernel<<<(N + 255) / 256, 256, 0, s>>>(N, F.perm.as<int>(), hi, lo,
+                                                         F.shi.as<float4>(), F.slo.as<float4>());
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        *msg = "fast product: device error while sorting positions";
+        return ARB_E_DEVICE;
+    }
+    F.lvl.assign(lvl.begin(), lvl.end());
+    F.o[0] = o[0] / a;
+    F.o[1] = o[1] / a;
+    F.o[2] = o[2] / a;
+    F.S = S / a;
+    F.ncell = ncell;
+    F.nleaf = nleaf;
+    F.nwork = (int)work.size();
+    F.n_il = (int64_t)il.size();
+    F.n_near_pairs = 0;
+    for (int c = leaf0; c < leaf0 + nleaf; ++c)
+        for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e)
+            F.n_near_pairs +=
+                (int64_t)(rng[c].y - rng[c].x) * (rng[nearl[e]].y - rng[nearl[e]].x);
+    F.N = N;
+    F.ready = true;
+    return 0;
+}
+
+namespace {
+
+template <bool WALL, class A>
+void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partial) {
+    const int N = F.N, L = F.L, P = F.P;
+    const Geo g{F.o[0], F.o[1], F.o[2], F.S, F.n, P};
+    const int B = round_up(P, kWave);
+    const float *tab = F.tab.as<float>();
+    Vec4<A> *slam = F.slam.as<Vec4<A>>(), *qhat = F.qhat.as<Vec4<A>>();
+    fmm_gather_lam_kernel<A><<<(N + 255) / 256, 256, 0, s>>>(N, F.perm.as<int>(), lam, slam);
+    if (L >= 2) {
+        fmm_p2m_kernel<A><<<F.lvl[L + 1] - F.lvl[L], B, 0, s>>>(
+            g, tab, F.cc.as<int4>(), F.rng.as<int2>(), F.lvl[L], F.shi.as<float4>(),
+            F.slo.as<float4>(), slam, qhat);
+        for (int l = L - 1; l >= 2; --l)
+            fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(g, tab, F.cc.as<int4>(),
+                                                                   F.kids.as<int2>(), F.lvl[l],
+                                                                   qhat);
+        fmm_m2l_kernel<WALL, A><<<F.lvl[L + 1] - F.lvl[2], B, 0, s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], qhat,
+            F.v.as<double>());
+        for (int l = 3; l <= L; ++l)
+            fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], F.v.as<double>());
+    }
+    fmm_near_kernel<WALL, A><<<F.nwork, kNearBlock, 0, s>>>(
+        g, tab, N, L >= 2 ? 1 : 0, F.cc.as<int4>(), F.rng.as<int2>(), F.near_ptr.as<int>(),
+        F.nearl.as<int>(), F.lvl[L], F.work.as<int2>(), F.perm.as<int>(), F.shi.as<float4>(),
+        F.slo.as<float4>(), slam, F.v.as<double>(), partial);
+}
+
+}  // namespace
+
+void fmm_apply(const FmmState &F, hipStream_t s, bool wall, bool fp64, const double *lam,
+               double *partial) {
+    if (F.N == 0) return;
+    if (wall)
+        fp64 ? fmm_run<true, double>(F, s, lam, partial) : fmm_run<true, float>(F, s, lam, partial);
+    else
+        fp64 ? fmm_run<false, double>(F, s, lam, partial)
+             : fmm_run<false, float>(F, s, lam, partial);
+}
+
+}  // namespace arb

@@ -1,0 +1,158 @@
+"""GPU parity of the fast mobility product (ARB_PAIR_FMM).
+
+Two oracles: the plain sum over cell pairs of the same interpolation
+approximation (oracle/fastsum.py), which the GPU must reproduce to FP32
+rounding (1e-5 of the largest entry), and the dense RPY sum (oracle/rpy.py),
+which it must approach within the approximation's error, falling with the
+order.  Inputs: loose blobs in slabs above the wall and in free space, ragged
+leaves, explicit and automatic leaf levels, the degenerate trees (one cell,
+coincident blobs, a single blob)."""
+import numpy as np
+import pytest
+
+from oracle import bodies, fastsum, rpy, system
+from paper_2107_10800_amd import arb
+from paper_2107_10800_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def blobs(N, box, seed, z0=1.5):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, (N, 3)) * np.array(box, float)
+    pos[:, 2] += z0
+    return pos, rng.standard_normal((N, 3))
+
+
+def fmm(pos, lam, wall, n, L, a=1.0, eta=1.0, leaf=0, precision=arb.ARB_FP64):
+    ctx = arb.arb_create(wall=wall, a=a, eta=eta, pair_kernel=arb.ARB_PAIR_FMM, fmm_order=n,
+                         fmm_levels=L, fmm_leaf=leaf, precision=precision)
+    try:
+        return arb.arb_rpy_apply(ctx, pos, lam).reshape(-1, 3)
+    finally:
+        arb.arb_destroy(ctx)
+
+
+CASES = [  # (N, box, wall, n, L)
+    (400, (48, 48, 10), False, 4, 3),
+    (401, (48, 48, 10), False, 3, 3),
+    (700, (40, 40, 40), False, 5, 2),
+    (300, (48, 48, 10), True, 4, 2),
+    (257, (30, 60, 8), True, 3, 3),
+]
+
+
+@pytest.mark.parametrize("N,box,wall,n,L", CASES)
+def test_matches_the_oracle_of_the_approximation(N, box, wall, n, L):
+    pos, lam = blobs(N, box, 100 + N)
+    a, eta = 0.9, 1.3
+    pos *= a
+    print(f"fmm vs oracle approximation: N={N} wall={wall} n={n} L={L}", flush=True)
+    ref = fastsum.fmm_apply(pos, lam, a, eta, wall, n, L)
+    dense = rpy.mobility_apply(pos, lam, a, eta, wall)
+    approx = np.abs(ref - dense).max() / np.abs(dense).max()
+    for prec in (arb.ARB_FP64, arb.ARB_FP32C):     # double and float sums
+        u = fmm(pos, lam, wall, n, L, a, eta, precision=prec)
+        err = np.abs(u - ref).max() / np.abs(ref).max()
+        print(f"  precision {prec}: GPU vs approximation {err:.1e}; approximation vs dense "
+              f"{approx:.1e}", flush=True)
+        assert err <= 1e-5
+        assert approx > 10 * err          # the comparison resolves the approximation
+
+
+@pytest.mark.parametrize("wall", [False, True])
+def test_direct_sum_when_no_level_separates(wall):
+    """fmm_levels = 1, a cluster narrower than 8a (no level with side >= 2a
+    below the root), a single blob and coincident blobs: the direct sum."""
+    pos, lam = blobs(300, (30, 30, 10), 7)
+    for L in (1,):
+        u = fmm(pos, lam, wall, 4, L)
+        ref = rpy.mobility_apply(pos, lam, 1.0, 1.0, wall)
+        assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
+    small, lam2 = blobs(50, (5, 5, 3), 8)
+    small[1] = small[0]
+    u = fmm(small, lam2, wall, 6, 0)
+    ref = rpy.mobility_apply(small, lam2, 1.0, 1.0, wall)
+    assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
+    one = np.array([[3.0, 4.0, 5.0]])
+    u = fmm(one, lam2[:1], wall, 4, 0)
+    ref = rpy.mobility_apply(one, lam2[:1], 1.0, 1.0, wall)
+    assert np.abs(u - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("wall", [False, True])
+def test_error_against_dense_falls_with_order(wall):
+    """The slab of the headline product (16,384 blobs, 400a x 400a x
+    [1.5a, 20a]), automatic leaf level: 48 sampled rows of the dense oracle."""
+    sl = W.slab()
+    pos, lam = sl["pos"], sl["lam"]
+    rows = np.random.default_rng(4).choice(len(pos), 48, replace=False)
+    ref = rpy.mobility_apply(pos, lam, 1.0, 1.0, wall, targets=rows)
+    errs = []
+    for n in (3, 4, 5, 6):
+        u = fmm(pos, lam, wall, n, 0)
+        errs.append(np.abs(u[rows] - ref).max() / np.abs(ref).max())
+    print(f"slab wall={wall}: sampled max error by order 3..6:", ["%.1e" % e for e in errs],
+          flush=True)
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] <= 2e-4
+
+
+def test_options_are_checked():
+    for bad in (dict(fmm_order=1), dict(fmm_order=9), dict(fmm_levels=-1), dict(fmm_leaf=-2),
+                dict(pair_kernel=4)):
+        with pytest.raises(arb.ArbError):
+            arb.arb_create(**bad)
+    with pytest.raises(arb.ArbError):
+        arb.arb_create(pair_kernel=arb.ARB_PAIR_FMM, model=arb.ARB_MODEL_SINGLE_BLOB)
+    # a leaf level deeper than the side of 2a allows is clamped, not an error
+    pos, lam = blobs(200, (20, 20, 5), 3)
+    u = fmm(pos, lam, False, 4, 12)
+    ref = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, 4, fastsum.max_level(pos, 1.0))
+    assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_solve_with_the_fast_product(prec):
+    """Constrained bacteria above the wall: GMRES on the fast operator (L = 2,
+    n = 6) to 1e-10 (FP64: double sums, linear in lambda; FP32C: float sums
+    inside refinement by the double-sum operator) against the dense
+    minimum-norm solve of the oracle; the velocities agree to the
+    approximation's accuracy."""
+    wl = W.bacteria(n_bact=4, seed=3)
+    ctx = arb.context_for(wl, precision=prec, tol=1e-10, pair_kernel=arb.ARB_PAIR_FMM,
+                          fmm_order=6, fmm_levels=2)
+    try:
+        rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+    finally:
+        arb.arb_destroy(ctx)
+    print(f"fmm solve precision {prec}: {info['iterations']} iterations, residual "
+          f"{info['rel_residual']:.1e}, products {info['products_fp64']} + "
+          f"{info['products_fp32']}", flush=True)
+    assert info["rel_residual"] <= 1e-10 and rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
+    d = system.assemble(wl)
+    y = system.solve_dense(d["A"], d["b"])
+    _, Ur, _ = system.split(y, wl.N, wl.M)
+    Ur = Ur.reshape(-1, 6)
+    err = np.abs(U - Ur).max() / np.abs(Ur).max()
+    print(f"  body velocities vs dense solve: {err:.1e}", flush=True)
+    assert err <= 1e-3
+
+
+def test_tree_follows_the_state():
+    """After a time step and a new state the product uses a tree of the new
+    positions (the state's positions computed by the oracle; order 3 keeps the
+    oracle's wall tensor cheap)."""
+    wl = W.bacteria(n_bact=4, seed=3)
+    lam = np.random.default_rng(1).standard_normal((wl.N, 3))
+    q2 = wl.q + np.array([7.0, -3.0, 2.0]) * np.arange(1, wl.M + 1)[:, None] / wl.M
+    ctx = arb.context_for(wl, tol=1e-8, pair_kernel=arb.ARB_PAIR_FMM, fmm_order=3, fmm_levels=2)
+    try:
+        arb.arb_step_euler(ctx, wl.F, 0.05)
+        arb.arb_set_state(ctx, q2, wl.theta)
+        u = arb.arb_mobility_apply(ctx, lam).reshape(-1, 3)
+    finally:
+        arb.arb_destroy(ctx)
+    pos = bodies.blob_positions(q2, wl.theta, wl.r_ref, wl.blob_offset)
+    ref = fastsum.fmm_apply(pos, lam, wl.a, wl.eta, wl.wall, 3, 2)
+    assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
