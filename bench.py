@@ -409,6 +409,90 @@ def single_blob_bench(torch, arb, W, reps=5):
     return out
 
 
+def fmm_bench(torch, arb, W, n_bact=8192, reps=10, log=log):
+    """Fast wall mobility product (ARB_PAIR_FMM) on 8,192 bacteria above the wall
+    (999,424 blobs): product time by Chebyshev order against the dense FP32 product,
+    error against that product, tree statistics, and GMRES to 1e-6 on the fast
+    operator (FP32 sums inside refinement by the double-sum variant)."""
+    import numpy as np
+
+    t0 = time.perf_counter()
+    wl = W.bacteria(n_bact=n_bact, seed=3)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda")
+    lam = torch.tensor(np.random.default_rng(1).standard_normal(3 * wl.N), device=dev)
+    u = torch.zeros(3 * wl.N, dtype=torch.float64, device=dev)
+    ud = torch.zeros_like(u)
+    # dense FP32 product (target-parallel kernel, one slice: no autotuning at this size)
+    c = arb.context_for(wl, precision=arb.ARB_FP32C, pair_kernel=arb.ARB_PAIR_TARGET, slices=1)
+    try:
+        arb.arb_mobility_apply_dev(c, lam, ud)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        arb.arb_mobility_apply_dev(c, lam, ud)
+        torch.cuda.synchronize()
+        dense_ms = 1e3 * (time.perf_counter() - t0)
+    finally:
+        arb.arb_destroy(c)
+    ref = ud.cpu().numpy()
+    log(f"fmm bench: dense FP32 product {dense_ms:.0f} ms at N={wl.N}")
+    rows = []
+    for n in (4, 5, 6, 7):
+        for prec, name in ((arb.ARB_FP32C, "float sums"), (arb.ARB_FP64, "double sums")):
+            if n != 6 and prec == arb.ARB_FP64:
+                continue
+            c = arb.context_for(wl, precision=prec, pair_kernel=arb.ARB_PAIR_FMM, fmm_order=n)
+            try:
+                arb.arb_mobility_apply_dev(c, lam, u)
+                st = arb.arb_fmm_get_stats(c)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    arb.arb_mobility_apply_dev(c, lam, u)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / reps
+            finally:
+                arb.arb_destroy(c)
+            err = float(np.abs(u.cpu().numpy() - ref).max() / np.abs(ref).max())
+            pairs = st["near_pairs"] + st["m2l_pairs"]
+            tflops = pairs * FLOPS_ONE_WAY[("f32c", True)] / (ms * 1e-3) / 1e12
+            rows.append(dict(order=n, sums=name, ms_per_product=ms, speedup_vs_dense=dense_ms / ms,
+                             max_rel_err_vs_dense=err, levels=st["levels"], leaves=st["leaves"],
+                             near_pairs=st["near_pairs"], m2l_pairs=st["m2l_pairs"],
+                             tree_build_ms=st["build_ms"], pair_tflops=tflops,
+                             frac_of_fp32_peak=tflops / PEAK_FP32_TFLOPS))
+            log(f"fmm bench: n={n} {name}: {ms:.2f} ms ({dense_ms / ms:.0f}x dense), max error "
+                f"{err:.1e}, L={st['levels']}, tree {st['build_ms']:.0f} ms, "
+                f"{tflops:.1f} TFLOP/s of pair work")
+    # GMRES on the fast operator
+    c = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-6, restart=100, max_iter=600,
+                        pair_kernel=arb.ARB_PAIR_FMM)
+    try:
+        F = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
+        y = torch.zeros(wl.n_unknowns, dtype=torch.float64, device=dev)
+        sh = torch.cuda.Stream().cuda_stream
+        arb.arb_solve_dev(c, F, None, y, warm=False, stream=sh)      # builds tree and blocks
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = arb.arb_solve_dev(c, F, None, y, warm=False, stream=sh)
+        torch.cuda.synchronize()
+        solve_ms = 1e3 * (time.perf_counter() - t0)
+    finally:
+        arb.arb_destroy(c)
+    log(f"fmm bench: solve {solve_ms:.0f} ms, {info['iterations']} iterations, residual "
+        f"{info['rel_residual_fp64']:.1e}")
+    return dict(workload=f"{n_bact} bacteria above a wall (42-blob head + 80-blob flagellum), "
+                         f"N={wl.N} blobs, lambda ~ N(0,1)",
+                seconds_generate=t_gen, dense_fp32_ms=dense_ms,
+                dense_kernel="target-parallel FP32, one slice", products=rows,
+                solve=dict(tol=1e-6, order=6, ms_per_solve=solve_ms,
+                           iterations=info["iterations"],
+                           rel_residual_fp64=info["rel_residual_fp64"],
+                           products_fp64=info["products_fp64"],
+                           products_fp32=info["products_fp32"],
+                           precond_build_ms=info["t_build_ms"], status=rc))
+
+
 def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, batch=1024, log=log):
     """Learned body-mobility preconditioner vs exact block and body-frame blocks."""
     import numpy as np
@@ -483,6 +567,9 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="also train the body-mobility network and compare preconditioners "
                          "on 4,096 bacteria (several minutes)")
+    ap.add_argument("--fmm-only", action="store_true",
+                    help="run only the fast-product block (for profiling)")
+    ap.add_argument("--no-fmm", action="store_true", help="skip the fast-product block")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -499,6 +586,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     arb.load()
+    if args.fmm_only:
+        print(json.dumps({"fmm": fmm_bench(torch, arb, W, reps=args.steps)}), flush=True)
+        return
     sl = W.slab()
     N = len(sl["pos"])
     if args.pmc_copy:
@@ -589,6 +679,13 @@ def main():
                                      "with sliding links", arb.ARB_FP32C, reps=1)
         log(f"bench: diatoms {res['diatoms']['ms_per_solve']:.1f} ms, "
             f"{res['diatoms']['iterations']} iterations")
+    if not args.no_solve and not args.no_fmm:
+        log("bench: fast product, 8192 bacteria")
+        try:
+            res["fmm"] = fmm_bench(torch, arb, W)
+        except Exception as e:          # reported, not fatal to the headline line
+            res["fmm"] = {"error": str(e)}
+            log(f"bench: fast product failed: {e}")
     if args.learned:
         log("bench: learned preconditioner")
         res["learned"] = learned_bench(torch, arb, W)

@@ -115,7 +115,7 @@ typedef struct {
                        /* occupancy is <= fmm_leaf); never deeper than the      */
                        /* deepest level with a cell side >= 2a; L <= 1 gives the */
                        /* direct sum                                            */
-    int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = fmm_order^3)        */
+    int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = 2 fmm_order^3)      */
 } arb_options;
 
 typedef struct {
@@ -133,6 +133,19 @@ typedef struct {
     int    products_fp32;   /* ... with the FP32 pair sum                      */
     int    precond_applies; /* preconditioner applications                     */
 } arb_solve_info;
+
+/* Work of the fast product's current tree (ARB_PAIR_FMM), filled by
+ * arb_fmm_get_stats after a product has built it. */
+typedef struct {
+    int       levels;       /* leaf level L (0: one cell, the direct sum)        */
+    int       order;        /* Chebyshev points per direction n                  */
+    int       cells;        /* cells of all levels                               */
+    int       leaves;       /* non-empty leaves                                  */
+    long long near_pairs;   /* ordered blob pairs summed directly per product    */
+    long long interactions; /* interaction-list entries (cell pairs)             */
+    long long m2l_pairs;    /* proxy pairs evaluated per product: entries * n^6  */
+    double    build_ms;     /* host time of the last tree build (incl. copies)   */
+} arb_fmm_stats;
 
 /* -------------------------------------------------------------- lifetime */
 /* Create a context on opt->device.  Returns ARB_E_ARG for bad options. */
@@ -183,6 +196,10 @@ int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef,
 /* Number of constraint rows N_c and of unknowns n = 3N + 6M + N_c (6M + N_c
  * in the single-blob model). */
 int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n);
+
+/* Statistics of the fast product's tree (ARB_PAIR_FMM).  ARB_E_ARG when the
+ * context does not use the fast product or no product has built a tree yet. */
+int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out);
 
 /* -------------------------------------------------------------- operators
  * u = M lambda over the context's blobs (Sec. 2.3 Eq. no-slip / Eq. RPY):

@@ -50,6 +50,7 @@ SYMBOLS = [
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
     "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
     "arb_body_mobility_apply", "arb_body_mobility_apply_dev", "arb_step_midpoint",
+    "arb_fmm_get_stats",
 ]
 
 
@@ -66,6 +67,13 @@ class arb_options(C.Structure):
                 ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int),
                 ("model", C.c_int), ("fmm_order", C.c_int), ("fmm_levels", C.c_int),
                 ("fmm_leaf", C.c_int)]
+
+
+class arb_fmm_stats(C.Structure):
+    _fields_ = [("levels", C.c_int), ("order", C.c_int), ("cells", C.c_int),
+                ("leaves", C.c_int), ("near_pairs", C.c_longlong),
+                ("interactions", C.c_longlong), ("m2l_pairs", C.c_longlong),
+                ("build_ms", C.c_double)]
 
 
 class arb_step_info(C.Structure):
@@ -156,6 +164,7 @@ def load():
         "arb_body_mobility_apply": (C.c_int, [_P, _DP, _DP]),
         "arb_body_mobility_apply_dev": (C.c_int, [_P, _P, _P, _P]),
         "arb_link_residual": (C.c_int, [_P, _DP, _DP]),
+        "arb_fmm_get_stats": (C.c_int, [_P, C.POINTER(arb_fmm_stats)]),
         "arb_step_euler": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double, C.c_int,
                                      C.c_int, _DP, _DP, _DP, C.POINTER(arb_step_info)]),
     }
@@ -466,6 +475,13 @@ def arb_step_midpoint(ctx, F, dt, delta=1e-10, corr_tol=1e-10, corr_max_iter=50,
 
 def arb_profile(ctx, enable=True):
     return _check(ctx, load().arb_profile(ctx, int(bool(enable))))
+
+
+def arb_fmm_get_stats(ctx):
+    """Tree statistics of the fast product (after a product has built the tree)."""
+    st = arb_fmm_stats()
+    _check(ctx, load().arb_fmm_get_stats(ctx, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
 
 
 def arb_profile_read(ctx):

@@ -401,9 +401,13 @@ int fmm_pair(arb_ctx *ctx, hipStream_t s, int N, const double *pos, const float4
     arb::FmmState &F = ctx->fmm;
     if (rebuild || F.dirty || !F.ready || F.N != N) {
         std::string msg;
+        const auto t0 = std::chrono::steady_clock::now();
         const int rc = arb::fmm_build(F, s, N, pos, hi, lo, ctx->opt.a, ctx->opt.fmm_order,
                                       ctx->opt.fmm_levels, ctx->opt.fmm_leaf, &msg);
         if (rc) return fail(ctx, rc, msg);
+        F.build_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                .count();
         F.dirty = false;
     }
     HIPCHK(ctx->partial.ensure((size_t)3 * std::max(N, 1) * sizeof(double)));
@@ -1284,6 +1288,21 @@ int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n) {
     if (n)
         *n = (ctx->opt.model == ARB_MODEL_SINGLE_BLOB ? 0 : 3 * (int64_t)ctx->N) +
              6 * (int64_t)ctx->M + nc;
+    return ARB_OK;
+}
+
+int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out) {
+    if (!ctx || !out) return ARB_E_ARG;
+    const arb::FmmState &F = ctx->fmm;
+    if (ctx->opt.pair_kernel != ARB_PAIR_FMM || !F.ready) return ARB_E_ARG;
+    out->levels = F.L;
+    out->order = F.n;
+    out->cells = F.ncell;
+    out->leaves = F.nleaf;
+    out->near_pairs = F.n_near_pairs;
+    out->interactions = F.n_il;
+    out->m2l_pairs = F.n_il * (long long)F.P * F.P;
+    out->build_ms = F.build_ms;
     return ARB_OK;
 }
 

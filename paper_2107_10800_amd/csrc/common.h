@@ -83,12 +83,13 @@ struct FmmState {
     std::vector<int> lvl;
     double o[3] = {0.0, 0.0, 0.0}, S = 0.0;  // root cube in units of a
     long long version = 0;                   // bumped by every build
+    double build_ms = 0.0;                   // host time of the last build
     bool ready = false, dirty = true;
 };
 // tree of N blobs (positions in units of length on the device, hi/lo as
 // prep_positions makes them); order = Chebyshev points per direction (0: the
 // default), levels = leaf level (0: from leaf, the mean blobs per leaf aimed at;
-// 0: n^3).  Returns 0 or an ARB_E_* code with *msg set.
+// 0: 2 n^3).  Returns 0 or an ARB_E_* code with *msg set.
 int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
               const float4 *lo, double a, int order, int levels, int leaf, std::string *msg);
 // partial[c][i] (3 x N, original order) = the approximation of M_{a=1} lambda,

@@ -164,38 +164,59 @@ __global__ void fmm_gather_lam_kernel(int N, const int *__restrict__ perm,
     slam[k] = vec4<A>((A)lam[3 * i], (A)lam[3 * i + 1], (A)lam[3 * i + 2]);
 }
 
-// qhat of the leaves, one workgroup per leaf, one lane per proxy
+// qhat of the leaves, one workgroup per leaf, one lane per proxy: the leaf's
+// blobs are staged in LDS in chunks with their 1D Lagrange values, computed
+// once per blob and direction
+constexpr int kP2MChunk = 64;
+
 template <class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_p2m_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
     const int2 *__restrict__ rng, int cell0, const float4 *__restrict__ shi,
     const float4 *__restrict__ slo, const Vec4<A> *__restrict__ slam, Vec4<A> *__restrict__ qhat) {
     __shared__ float tab[kTabSize];
+    __shared__ float s_l[3][kP2MChunk][kFmmMaxOrder];
+    __shared__ Vec4<A> s_lam[kP2MChunk];
     load_tab(tabg, tab);
     const int c = cell0 + blockIdx.x;
-    const int k = threadIdx.x;
-    if (k >= g.P) return;
+    const int tid = threadIdx.x;
     const int n = g.n;
+    const bool act = tid < g.P;
+    const int k = act ? tid : 0;
     const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
     const int4 ci = cc[c];
     const int2 r = rng[c];
     const double side = ldexp(g.S, -ci.w);
-    const F2 cx = split(centre(g.ox, side, ci.x)), cy = split(centre(g.oy, side, ci.y)),
-             cz = split(centre(g.oz, side, ci.z));
+    const F2 cd[3] = {split(centre(g.ox, side, ci.x)), split(centre(g.oy, side, ci.y)),
+                      split(centre(g.oz, side, ci.z))};
     const float iw = (float)(2.0 / side);
     double qx = 0.0, qy = 0.0, qz = 0.0;
-    for (int j = r.x; j < r.y; ++j) {
-        const float4 h = shi[j], l = slo[j];
-        const Vec4<A> L = slam[j];
-        const float ux = ((h.x - cx.h) + (l.x - cx.l)) * iw;
-        const float uy = ((h.y - cy.h) + (l.y - cy.l)) * iw;
-        const float uz = ((h.z - cz.h) + (l.z - cz.l)) * iw;
-        const A s = (A)(lag(tab, n, kx, ux) * lag(tab, n, ky, uy) * lag(tab, n, kz, uz));
-        qx += (double)(s * L.x);
-        qy += (double)(s * L.y);
-        qz += (double)(s * L.z);
+    for (int j0 = r.x; j0 < r.y; j0 += kP2MChunk) {
+        const int cnt = min(kP2MChunk, r.y - j0);
+        __syncthreads();
+        for (int t = tid; t < 3 * cnt; t += blockDim.x) {
+            const int jj = t / 3, d = t - 3 * jj;
+            const float4 h = shi[j0 + jj], l = slo[j0 + jj];
+            const float hx = d == 0 ? h.x : (d == 1 ? h.y : h.z);
+            const float lx = d == 0 ? l.x : (d == 1 ? l.y : l.z);
+            const float u = ((hx - cd[d].h) + (lx - cd[d].l)) * iw;
+            for (int kk = 0; kk < n; ++kk) s_l[d][jj][kk] = lag(tab, n, kk, u);
+            if (d == 0) s_lam[jj] = slam[j0 + jj];
+        }
+        __syncthreads();
+        A fx = 0, fy = 0, fz = 0;
+        for (int jj = 0; jj < cnt; ++jj) {
+            const A w = (A)(s_l[0][jj][kx] * s_l[1][jj][ky] * s_l[2][jj][kz]);
+            const Vec4<A> L = s_lam[jj];
+            fx = fma(w, L.x, fx);
+            fy = fma(w, L.y, fy);
+            fz = fma(w, L.z, fz);
+        }
+        qx += fx;
+        qy += fy;
+        qz += fz;
     }
-    qhat[(size_t)c * g.P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
+    if (act) qhat[(size_t)c * g.P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
 }
 
 // qhat of the cells of one level from their children
@@ -507,7 +528,7 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
     }
     std::sort(kk.begin(), kk.end());
     // leaf level
-    const int leaf_target = leaf > 0 ? leaf : F.P;
+    const int leaf_target = leaf > 0 ? leaf : 2 * F.P;
     int L;
     if (Lhi < 2) {
         L = 0;
