@@ -261,19 +261,27 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *_
     qhat[(size_t)c * P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
 }
 
-// v of every cell of levels 2..L over its interaction list
+// v of every cell of levels 2..L over its interaction list: `groups` lane
+// groups of P (one lane per target proxy) take interaction-list entries in
+// turn, so that groups * P fills the workgroup's waves; the groups' sums meet
+// in LDS at the end
 template <bool WALL, class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
-    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0,
+    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int groups,
     const Vec4<A> *__restrict__ qhat, double *__restrict__ v) {
-    __shared__ float tab[kTabSize];
-    __shared__ float4 s_off[kFmmMaxP];
-    __shared__ Vec4<A> s_q[kFmmMaxP];
+    // LDS sized by the host (m2l_lds_bytes): multipole weights of `groups`
+    // listed cells, the level's proxy offsets, the groups' sums, the table
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int n = g.n, P = g.P;
+    const int GP = groups * P;  // <= kFmmMaxP
+    Vec4<A> *s_q = reinterpret_cast<Vec4<A> *>(lds);
+    float4 *s_off = reinterpret_cast<float4 *>(s_q + GP);
+    double *s_acc = reinterpret_cast<double *>(s_off + P);
+    float *tab = reinterpret_cast<float *>(s_acc + 3 * (GP - P));
     load_tab(tabg, tab);
     const int c = cell0 + blockIdx.x;
     const int tid = threadIdx.x;
-    const int n = g.n, P = g.P;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
     // proxy offsets w xi of this level (the same for every cell of it)
@@ -282,8 +290,9 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
         s_off[m] = make_float4((float)(w * tab[kTabNode + mx]), (float)(w * tab[kTabNode + my]),
                                (float)(w * tab[kTabNode + mz]), 0.f);
     }
-    const bool act = tid < P;
-    const int k = act ? tid : 0;
+    const bool act = tid < GP;
+    const int gi = act ? tid / P : 0;
+    const int k = act ? tid - gi * P : 0;
     const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
     const float okx = (float)(w * tab[kTabNode + kx]), oky = (float)(w * tab[kTabNode + ky]),
                 okz = (float)(w * tab[kTabNode + kz]);
@@ -292,23 +301,28 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     const TargetZ<float> zsc = target_z(zi);
     double ux = 0.0, uy = 0.0, uz = 0.0;
     const int e1 = il_ptr[c + 1];
-    for (int e = il_ptr[c]; e < e1; ++e) {
-        const int sc = il[e];
-        const int4 cs = cc[sc];
+    for (int e0 = il_ptr[c]; e0 < e1; e0 += groups) {
         __syncthreads();
-        for (int m = tid; m < P; m += blockDim.x) s_q[m] = qhat[(size_t)sc * P + m];
+        for (int t = tid; t < GP; t += blockDim.x) {
+            const int gg = t / P;
+            if (e0 + gg < e1) s_q[t] = qhat[(size_t)il[e0 + gg] * P + (t - gg * P)];
+        }
         __syncthreads();
+        const int e = e0 + gi;
+        if (!act || e >= e1) continue;
+        const int4 cs = cc[il[e]];
         // target proxy minus source cell centre, from the integer offset
         const float ax = (float)((double)(ct.x - cs.x) * side) + okx;
         const float ay = (float)((double)(ct.y - cs.y) * side) + oky;
         const float az = (float)((double)(ct.z - cs.z) * side) + okz;
         const float zc = (float)centre(g.oz, side, cs.z);
+        const Vec4<A> *sq = s_q + gi * P;
         for (int m0 = 0; m0 < P; m0 += kFmmRun) {
             const int m1 = min(m0 + kFmmRun, P);
             A fx = 0, fy = 0, fz = 0;
             for (int m = m0; m < m1; ++m) {
                 const float4 o = s_off[m];
-                const Vec4<A> q = s_q[m];
+                const Vec4<A> q = sq[m];
                 const float dx = ax - o.x, dy = ay - o.y, dz = az - o.z;
                 const float dxy2 = fmaf(dx, dx, dy * dy);
                 const float zj = zc + o.z;
@@ -321,7 +335,22 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
             uz += fz;
         }
     }
-    if (act) {
+    // the groups' sums, added in group order
+    __syncthreads();
+    if (act && gi > 0) {
+        double *a = s_acc + 3 * (tid - P);
+        a[0] = ux;
+        a[1] = uy;
+        a[2] = uz;
+    }
+    __syncthreads();
+    if (act && gi == 0) {
+        for (int gg = 1; gg < groups; ++gg) {
+            const double *a = s_acc + 3 * ((gg - 1) * P + k);
+            ux += a[0];
+            uy += a[1];
+            uz += a[2];
+        }
         double *o = v + ((size_t)c * P + k) * 3;
         o[0] = ux;
         o[1] = uy;
@@ -735,8 +764,22 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
             fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(g, tab, F.cc.as<int4>(),
                                                                    F.kids.as<int2>(), F.lvl[l],
                                                                    qhat);
-        fmm_m2l_kernel<WALL, A><<<F.lvl[L + 1] - F.lvl[2], B, 0, s>>>(
-            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], qhat,
+        // lane groups per workgroup: the count (up to 8 within 512 lanes) that
+        // leaves the fewest idle lanes in its waves
+        int groups = 1;
+        double best = 0.0;
+        for (int gq = 1; gq <= 8 && gq * P <= kFmmMaxP; ++gq) {
+            const double util = (double)(gq * P) / round_up(gq * P, kWave);
+            if (util > best + 1e-9) {
+                best = util;
+                groups = gq;
+            }
+        }
+        const size_t lds = (size_t)groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
+                           (size_t)3 * (groups - 1) * P * sizeof(double) +
+                           kTabSize * sizeof(float);
+        fmm_m2l_kernel<WALL, A><<<F.lvl[L + 1] - F.lvl[2], round_up(groups * P, kWave), lds, s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], groups, qhat,
             F.v.as<double>());
         for (int l = 3; l <= L; ++l)
             fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
