@@ -481,6 +481,25 @@ def fmm_bench(torch, arb, W, n_bact=8192, reps=10, log=log):
         arb.arb_destroy(c)
     log(f"fmm bench: solve {solve_ms:.0f} ms, {info['iterations']} iterations, residual "
         f"{info['rel_residual_fp64']:.1e}")
+    # explicit Euler steps on the fast operator (Sec. 4.3): tree rebuilt per state,
+    # GMRES warm-started from the previous step, reconstruction, check, correction
+    c = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-6, restart=100, max_iter=600,
+                        pair_kernel=arb.ARB_PAIR_FMM)
+    try:
+        arb.arb_step_euler(c, wl.F, 0.02, delta=1e-10, corr_tol=1e-10, warm=False)
+        steps = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            rc_s, _, _, _, si = arb.arb_step_euler(c, wl.F, 0.02, delta=1e-10, corr_tol=1e-10,
+                                                   warm=True)
+            steps.append(dict(ms=1e3 * (time.perf_counter() - t0), iterations=si["iterations"],
+                              rel_residual=si["rel_residual"], corrected=si["corrected"],
+                              g_inf=si["g_inf"], tree_build_ms=arb.arb_fmm_get_stats(c)["build_ms"],
+                              status=rc_s))
+    finally:
+        arb.arb_destroy(c)
+    log(f"fmm bench: Euler steps {[round(x['ms']) for x in steps]} ms, iterations "
+        f"{[x['iterations'] for x in steps]}")
     return dict(workload=f"{n_bact} bacteria above a wall (42-blob head + 80-blob flagellum), "
                          f"N={wl.N} blobs, lambda ~ N(0,1)",
                 seconds_generate=t_gen, dense_fp32_ms=dense_ms,
@@ -490,7 +509,8 @@ def fmm_bench(torch, arb, W, n_bact=8192, reps=10, log=log):
                            rel_residual_fp64=info["rel_residual_fp64"],
                            products_fp64=info["products_fp64"],
                            products_fp32=info["products_fp32"],
-                           precond_build_ms=info["t_build_ms"], status=rc))
+                           precond_build_ms=info["t_build_ms"], status=rc),
+                euler_steps=dict(dt=0.02, tol=1e-6, order=6, steps=steps))
 
 
 def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, batch=1024, log=log):
