@@ -201,6 +201,15 @@ int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n);
  * context does not use the fast product or no product has built a tree yet. */
 int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out);
 
+/* The fast product's octree for N blobs at pos (3N doubles, xyz per blob, host
+ * memory, units of length), planned on the host with no device and no
+ * context: the leaf level and work counts a product over these positions
+ * would use (a = blob radius; order, levels, leaf as the fmm_* options, 0 for
+ * their defaults); build_ms is the host time of the planning.  Returns
+ * ARB_E_ARG for bad sizes or options, ARB_E_NAN for a non-finite position. */
+int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int leaf,
+                 arb_fmm_stats *out);
+
 /* -------------------------------------------------------------- operators
  * u = M lambda over the context's blobs (Sec. 2.3 Eq. no-slip / Eq. RPY):
  * u_i = sum_j M_ij lambda_j over all j including i; 3N in, 3N out. */

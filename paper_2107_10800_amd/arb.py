@@ -50,7 +50,7 @@ SYMBOLS = [
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
     "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
     "arb_body_mobility_apply", "arb_body_mobility_apply_dev", "arb_step_midpoint",
-    "arb_fmm_get_stats",
+    "arb_fmm_get_stats", "arb_fmm_plan",
 ]
 
 
@@ -165,6 +165,8 @@ def load():
         "arb_body_mobility_apply_dev": (C.c_int, [_P, _P, _P, _P]),
         "arb_link_residual": (C.c_int, [_P, _DP, _DP]),
         "arb_fmm_get_stats": (C.c_int, [_P, C.POINTER(arb_fmm_stats)]),
+        "arb_fmm_plan": (C.c_int, [C.c_int, _DP, C.c_double, C.c_int, C.c_int, C.c_int,
+                                   C.POINTER(arb_fmm_stats)]),
         "arb_step_euler": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double, C.c_int,
                                      C.c_int, _DP, _DP, _DP, C.POINTER(arb_step_info)]),
     }
@@ -481,6 +483,17 @@ def arb_fmm_get_stats(ctx):
     """Tree statistics of the fast product (after a product has built the tree)."""
     st = arb_fmm_stats()
     _check(ctx, load().arb_fmm_get_stats(ctx, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def arb_fmm_plan(pos, a, order=0, levels=0, leaf=0):
+    """Host-only plan of the fast product's octree (no device): its statistics."""
+    p_, pp = _d(pos)
+    st = arb_fmm_stats()
+    rc = load().arb_fmm_plan(p_.size // 3, pp, float(a), int(order), int(levels), int(leaf),
+                             C.byref(st))
+    if rc < 0:
+        raise ArbError(rc, "arb_fmm_plan")
     return {k: getattr(st, k) for k, _ in st._fields_}
 
 

@@ -42,6 +42,7 @@
 // tolerance; the float variant serves the inner iterations of FP64 iterative
 // refinement.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <type_traits>
 
@@ -505,46 +506,40 @@ int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 }  // namespace
 
-int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
-              const float4 *lo, double a, int order, int levels, int leaf, std::string *msg) {
-    F.N = 0;
-    F.ready = false;
-    const int n = order > 0 ? order : kFmmDefaultOrder;
-    if (n < 2 || n > kFmmMaxOrder || levels < 0 || leaf < 0 || N < 0) {
-        *msg = "fast product: order must be 2..8, levels and leaf >= 0";
-        return ARB_E_ARG;
-    }
-    F.n = n;
-    F.P = n * n * n;
-    ++F.version;
-    if (N == 0) {
-        F.ready = true;
-        return 0;
-    }
-    std::vector<double> h(3 * (size_t)N);
-    if (hipMemcpyAsync(h.data(), pos_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        *msg = "fast product: copying positions failed";
-        return ARB_E_DEVICE;
-    }
-    // root cube
-    double o[3], ext = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        double lo_d = h[d], hi_d = h[d];
-        for (int i = 1; i < N; ++i) {
-            lo_d = std::min(lo_d, h[3 * (size_t)i + d]);
-            hi_d = std::max(hi_d, h[3 * (size_t)i + d]);
+// the octree of N positions (units of length, host memory), built on the host
+struct FmmPlan {
+    int n = 0, P = 0, L = 0, ncell = 0, nleaf = 0;
+    double o[3] = {0.0, 0.0, 0.0}, S = 0.0;  // root cube, units of length
+    int64_t n_near_pairs = 0;
+    std::vector<int> perm, lvl, parent, il_ptr, il, near_ptr, nearl;
+    std::vector<int4> cc;
+    std::vector<int2> rng, kids, work;
+    std::vector<float> tab;
+};
+
+int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, int leaf,
+             std::string *msg) {
+    const int P = n * n * n;
+    for (size_t i = 0; i < 3 * (size_t)N; ++i)
+        if (!std::isfinite(h[i])) {
+            *msg = "fast product: a position is not finite";
+            return ARB_E_NAN;
         }
-        o[d] = lo_d;
-        ext = std::max(ext, hi_d - lo_d);
-    }
+    // root cube
+    double o[3] = {h[0], h[1], h[2]}, hi_d[3] = {h[0], h[1], h[2]}, ext = 0.0;
+    for (size_t i = 1; i < (size_t)N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            o[d] = std::min(o[d], h[3 * i + d]);
+            hi_d[d] = std::max(hi_d[d], h[3 * i + d]);
+        }
+    for (int d = 0; d < 3; ++d) ext = std::max(ext, hi_d[d] - o[d]);
     const double S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : a;
     int Lhi = 0;  // deepest level with a cell side >= 2a
     while (Lhi < kFmmMaxLevel && S / std::ldexp(1.0, Lhi + 1) >= 2.0 * a) ++Lhi;
     // cell coordinates at level Lhi and Morton keys
     std::vector<int> crd(3 * (size_t)N);
-    std::vector<std::pair<uint64_t, int>> kk((size_t)N);
+    std::vector<uint64_t> key((size_t)N), key2((size_t)N);
+    std::vector<int> idx((size_t)N), idx2((size_t)N);
     const double scale = std::ldexp(1.0, Lhi);
     for (int i = 0; i < N; ++i) {
         int cq[3];
@@ -553,11 +548,46 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
             cq[d] = (int)std::floor(u * scale);
             crd[3 * (size_t)i + d] = cq[d];
         }
-        kk[i] = {morton(cq[0], cq[1], cq[2]), i};
+        key[i] = morton(cq[0], cq[1], cq[2]);
+        idx[i] = i;
     }
-    std::sort(kk.begin(), kk.end());
+    // stable LSD radix sort of the 3 Lhi-bit keys in the fewest passes of at
+    // most 14 bits: blobs in Morton order, equal keys in ascending blob index
+    {
+        const int bits = 3 * Lhi, passes = (bits + 13) / 14;
+        const int dbits = passes ? (bits + passes - 1) / passes : 0;
+        const uint64_t mask = (1ull << dbits) - 1;
+        std::vector<int> cnt((size_t)mask + 2);
+        for (int ps = 0; ps < passes; ++ps) {
+            const int shift = ps * dbits;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int i = 0; i < N; ++i) ++cnt[((key[i] >> shift) & mask) + 1];
+            for (size_t b = 0; b <= mask; ++b) cnt[b + 1] += cnt[b];
+            for (int i = 0; i < N; ++i) {
+                const int at = cnt[(key[i] >> shift) & mask]++;
+                key2[at] = key[i];
+                idx2[at] = idx[i];
+            }
+            key.swap(key2);
+            idx.swap(idx2);
+        }
+    }
+    // the shallowest level at which sorted blob j starts a new cell (a cell
+    // starts at every deeper level too): the highest differing key bit / 3
+    std::vector<unsigned char> first((size_t)N, 0);
+    std::vector<int64_t> new_at(Lhi + 2, 0);
+    for (int j = 1; j < N; ++j) {
+        const uint64_t d = key[j] ^ key[j - 1];
+        if (!d) {
+            first[j] = (unsigned char)(Lhi + 1);  // same cell at every level
+            continue;
+        }
+        const int hb = 63 - __builtin_clzll(d);
+        first[j] = (unsigned char)(Lhi - hb / 3);
+        ++new_at[first[j]];
+    }
     // leaf level
-    const int leaf_target = leaf > 0 ? leaf : 2 * F.P;
+    const int leaf_target = leaf > 0 ? leaf : 2 * P;
     int L;
     if (Lhi < 2) {
         L = 0;
@@ -565,36 +595,34 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
         L = levels < 2 ? 0 : std::min(levels, Lhi);
     } else {
         L = Lhi;
-        for (int l = 2; l <= Lhi; ++l) {
-            const int sh = 3 * (Lhi - l);
-            int64_t cells = 1;
-            for (int j = 1; j < N; ++j) cells += (kk[j].first >> sh) != (kk[j - 1].first >> sh);
-            if ((int64_t)N <= (int64_t)leaf_target * cells) {
+        int64_t cells = 1;
+        for (int l = 1; l <= Lhi; ++l) {
+            cells += new_at[l];
+            if (l >= 2 && (int64_t)N <= (int64_t)leaf_target * cells) {
                 L = l;
                 break;
             }
         }
     }
-    F.L = L;
     // cells of every level in Morton order, with their blob ranges
+    std::vector<std::vector<int>> starts(L + 1, std::vector<int>(1, 0));
+    for (int j = 1; j < N; ++j)
+        for (int l = first[j]; l <= L; ++l) starts[l].push_back(j);
     std::vector<int4> cc;
     std::vector<int2> rng;
     std::vector<uint64_t> pk;
     std::vector<int> lvl(L + 2, 0);
     for (int l = 0; l <= L; ++l) {
         lvl[l] = (int)cc.size();
-        const int sh = 3 * (Lhi - l);
-        for (int j = 0; j < N;) {
-            const uint64_t p = kk[j].first >> sh;
-            int e = j + 1;
-            while (e < N && (kk[e].first >> sh) == p) ++e;
-            const int i0 = kk[j].second;
-            const int dl = Lhi - l;
+        const int sh = 3 * (Lhi - l), dl = Lhi - l;
+        const std::vector<int> &st = starts[l];
+        for (size_t t = 0; t < st.size(); ++t) {
+            const int j = st[t], e = t + 1 < st.size() ? st[t + 1] : N;
+            const int i0 = idx[j];
             cc.push_back(make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
                                    crd[3 * (size_t)i0 + 2] >> dl, l));
             rng.push_back(make_int2(j, e));
-            pk.push_back(p);
-            j = e;
+            pk.push_back(key[j] >> sh);
         }
     }
     lvl[L + 1] = (int)cc.size();
@@ -692,26 +720,80 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
                     if (j != k) p *= (u - xn[j]) / (xn[k] - xn[j]);
                 tab[kTabT1 + (sg * kFmmMaxOrder + k) * kFmmMaxOrder + m] = (float)p;
             }
-    std::vector<int> perm((size_t)N);
-    for (int j = 0; j < N; ++j) perm[j] = kk[j].second;
+    std::vector<int> &perm = idx;  // sorted position -> blob
+    pl.n = n;
+    pl.P = P;
+    pl.L = L;
+    pl.o[0] = o[0];
+    pl.o[1] = o[1];
+    pl.o[2] = o[2];
+    pl.S = S;
+    pl.ncell = ncell;
+    pl.nleaf = nleaf;
+    pl.n_near_pairs = 0;
+    for (int c = leaf0; c < leaf0 + nleaf; ++c)
+        for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e)
+            pl.n_near_pairs +=
+                (int64_t)(rng[c].y - rng[c].x) * (rng[nearl[e]].y - rng[nearl[e]].x);
+    pl.perm = std::move(perm);
+    pl.lvl = std::move(lvl);
+    pl.cc = std::move(cc);
+    pl.rng = std::move(rng);
+    pl.parent = std::move(parent);
+    pl.kids = std::move(kids);
+    pl.il_ptr = std::move(il_ptr);
+    pl.il = std::move(il);
+    pl.near_ptr = std::move(near_ptr);
+    pl.nearl = std::move(nearl);
+    pl.work = std::move(work);
+    pl.tab = std::move(tab);
+    return 0;
+}
+
+int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
+              const float4 *lo, double a, int order, int levels, int leaf, std::string *msg) {
+    F.N = 0;
+    F.ready = false;
+    const int n = order > 0 ? order : kFmmDefaultOrder;
+    if (n < 2 || n > kFmmMaxOrder || levels < 0 || leaf < 0 || N < 0) {
+        *msg = "fast product: order must be 2..8, levels and leaf >= 0";
+        return ARB_E_ARG;
+    }
+    F.n = n;
+    F.P = n * n * n;
+    ++F.version;
+    if (N == 0) {
+        F.ready = true;
+        return 0;
+    }
+    std::vector<double> h(3 * (size_t)N);
+    if (hipMemcpyAsync(h.data(), pos_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        *msg = "fast product: copying positions failed";
+        return ARB_E_DEVICE;
+    }
+    FmmPlan pl;
+    const int prc = fmm_plan(pl, N, h.data(), a, n, levels, leaf, msg);
+    if (prc) return prc;
     // upload
-    const int P = F.P;
+    const int P = F.P, ncell = pl.ncell;
     auto up = [&](DevBuf &b, const void *src, size_t bytes) -> bool {
         if (b.ensure(std::max<size_t>(bytes, 16)) != hipSuccess) return false;
         return bytes == 0 ||
                hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
     };
-    bool ok = up(F.perm, perm.data(), perm.size() * sizeof(int)) &&
-              up(F.cc, cc.data(), cc.size() * sizeof(int4)) &&
-              up(F.rng, rng.data(), rng.size() * sizeof(int2)) &&
-              up(F.parent, parent.data(), parent.size() * sizeof(int)) &&
-              up(F.kids, kids.data(), kids.size() * sizeof(int2)) &&
-              up(F.il_ptr, il_ptr.data(), il_ptr.size() * sizeof(int)) &&
-              up(F.il, il.data(), il.size() * sizeof(int)) &&
-              up(F.near_ptr, near_ptr.data(), near_ptr.size() * sizeof(int)) &&
-              up(F.nearl, nearl.data(), nearl.size() * sizeof(int)) &&
-              up(F.work, work.data(), work.size() * sizeof(int2)) &&
-              up(F.tab, tab.data(), tab.size() * sizeof(float)) &&
+    bool ok = up(F.perm, pl.perm.data(), pl.perm.size() * sizeof(int)) &&
+              up(F.cc, pl.cc.data(), pl.cc.size() * sizeof(int4)) &&
+              up(F.rng, pl.rng.data(), pl.rng.size() * sizeof(int2)) &&
+              up(F.parent, pl.parent.data(), pl.parent.size() * sizeof(int)) &&
+              up(F.kids, pl.kids.data(), pl.kids.size() * sizeof(int2)) &&
+              up(F.il_ptr, pl.il_ptr.data(), pl.il_ptr.size() * sizeof(int)) &&
+              up(F.il, pl.il.data(), pl.il.size() * sizeof(int)) &&
+              up(F.near_ptr, pl.near_ptr.data(), pl.near_ptr.size() * sizeof(int)) &&
+              up(F.nearl, pl.nearl.data(), pl.nearl.size() * sizeof(int)) &&
+              up(F.work, pl.work.data(), pl.work.size() * sizeof(int2)) &&
+              up(F.tab, pl.tab.data(), pl.tab.size() * sizeof(float)) &&
               F.shi.ensure((size_t)N * sizeof(float4)) == hipSuccess &&
               F.slo.ensure((size_t)N * sizeof(float4)) == hipSuccess &&
               F.slam.ensure((size_t)N * sizeof(double4)) == hipSuccess &&
@@ -727,20 +809,17 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
         *msg = "fast product: device error while sorting positions";
         return ARB_E_DEVICE;
     }
-    F.lvl.assign(lvl.begin(), lvl.end());
-    F.o[0] = o[0] / a;
-    F.o[1] = o[1] / a;
-    F.o[2] = o[2] / a;
-    F.S = S / a;
-    F.ncell = ncell;
-    F.nleaf = nleaf;
-    F.nwork = (int)work.size();
-    F.n_il = (int64_t)il.size();
-    F.n_near_pairs = 0;
-    for (int c = leaf0; c < leaf0 + nleaf; ++c)
-        for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e)
-            F.n_near_pairs +=
-                (int64_t)(rng[c].y - rng[c].x) * (rng[nearl[e]].y - rng[nearl[e]].x);
+    F.L = pl.L;
+    F.lvl = pl.lvl;
+    F.o[0] = pl.o[0] / a;
+    F.o[1] = pl.o[1] / a;
+    F.o[2] = pl.o[2] / a;
+    F.S = pl.S / a;
+    F.ncell = pl.ncell;
+    F.nleaf = pl.nleaf;
+    F.nwork = (int)pl.work.size();
+    F.n_il = (int64_t)pl.il.size();
+    F.n_near_pairs = pl.n_near_pairs;
     F.N = N;
     F.ready = true;
     return 0;
@@ -804,3 +883,30 @@ void fmm_apply(const FmmState &F, hipStream_t s, bool wall, bool fp64, const dou
 }
 
 }  // namespace arb
+
+int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int leaf,
+                 arb_fmm_stats *out) {
+    using namespace arb;
+    if (N < 0 || (N > 0 && !pos) || !(a > 0.0) || !out ||
+        (order != 0 && (order < 2 || order > kFmmMaxOrder)) || levels < 0 ||
+        levels > kFmmMaxLevel || leaf < 0)
+        return ARB_E_ARG;
+    const int n = order > 0 ? order : kFmmDefaultOrder;
+    *out = arb_fmm_stats{};
+    out->order = n;
+    if (N == 0) return ARB_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    FmmPlan pl;
+    std::string msg;
+    const int rc = fmm_plan(pl, N, pos, a, n, levels, leaf, &msg);
+    if (rc) return rc;
+    out->levels = pl.L;
+    out->cells = pl.ncell;
+    out->leaves = pl.nleaf;
+    out->near_pairs = pl.n_near_pairs;
+    out->interactions = (long long)pl.il.size();
+    out->m2l_pairs = (long long)pl.il.size() * pl.P * pl.P;
+    out->build_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return ARB_OK;
+}

@@ -1,0 +1,97 @@
+"""Host logic of the fast product: the octree the library plans (arb_fmm_plan,
+host only, no device) against the definitions written out in oracle/fastsum.py,
+counted here with numpy: leaf level (explicit, clamped and automatic), cells of
+every level, non-empty leaves, directly summed pairs of adjacent leaves and
+interaction-list entries.  Runs without a GPU."""
+import numpy as np
+import pytest
+
+from oracle import fastsum
+from paper_2107_10800_amd import arb
+
+
+def counts(pos, a, n, L):
+    """(cells of levels 0..L, leaves, direct pairs, interaction-list entries)."""
+    o, S = fastsum.root_cube(pos, a)
+    cells = 0
+    inter = 0
+    for lev in range(L + 1):
+        u = np.unique(fastsum.cell_coords(pos, o, S, lev), axis=0)
+        cells += len(u)
+        if lev >= 2:
+            for c in u:
+                inter += int(np.sum((np.abs(u // 2 - c // 2).max(1) <= 1)
+                                    & (np.abs(u - c).max(1) > 1)))
+    leaf = fastsum.cell_coords(pos, o, S, L)
+    keys, cnt = np.unique(leaf, axis=0, return_counts=True)
+    near = 0
+    for k, m in zip(keys, cnt):
+        near += int(m) * int(cnt[np.abs(keys - k).max(1) <= 1].sum())
+    return cells, len(keys), near, inter
+
+
+def auto_level(pos, a, leaf):
+    """The documented rule: the shallowest level l >= 2 whose mean occupancy is
+    at most `leaf`, never deeper than the deepest level with side >= 2a."""
+    Lhi = min(fastsum.max_level(pos, a), 16)
+    if Lhi < 2:
+        return 0
+    o, S = fastsum.root_cube(pos, a)
+    for lev in range(2, Lhi + 1):
+        if len(pos) <= leaf * len(np.unique(fastsum.cell_coords(pos, o, S, lev), axis=0)):
+            return lev
+    return Lhi
+
+
+def blobs(N, box, seed, z0=1.5):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, (N, 3)) * np.array(box, float)
+    pos[:, 2] += z0
+    return pos
+
+
+SHAPES = [(500, (40, 40, 10)), (777, (60, 20, 20)), (300, (30, 30, 30)), (1000, (200, 200, 4))]
+
+
+@pytest.mark.parametrize("N,box", SHAPES)
+@pytest.mark.parametrize("L", [1, 2, 3, 5])
+def test_plan_matches_the_definitions(N, box, L):
+    pos = blobs(N, box, N + L)
+    a = 0.8
+    n = 4
+    Lexp = 0 if L < 2 else min(L, fastsum.max_level(pos, a))
+    st = arb.arb_fmm_plan(pos, a, order=n, levels=L)
+    assert st["levels"] == Lexp
+    cells, leaves, near, inter = counts(pos, a, n, Lexp)
+    assert (st["cells"], st["leaves"], st["near_pairs"], st["interactions"]) == \
+        (cells, leaves, near, inter)
+    assert st["m2l_pairs"] == inter * n ** 6
+
+
+@pytest.mark.parametrize("N,box", SHAPES)
+@pytest.mark.parametrize("leaf", [0, 16, 100])
+def test_automatic_level(N, box, leaf):
+    pos = blobs(N, box, 3 * N + leaf)
+    n = 3
+    st = arb.arb_fmm_plan(pos, 1.0, order=n, leaf=leaf)
+    L = auto_level(pos, 1.0, leaf if leaf else 2 * n ** 3)
+    assert st["levels"] == L
+    assert st["cells"] == counts(pos, 1.0, n, L)[0]
+
+
+def test_degenerate_inputs():
+    # coincident blobs: one cell, the direct sum of every pair
+    pos = np.tile([[3.0, 4.0, 5.0]], (10, 1))
+    st = arb.arb_fmm_plan(pos, 1.0, order=4)
+    assert (st["levels"], st["cells"], st["leaves"], st["near_pairs"]) == (0, 1, 1, 100)
+    st = arb.arb_fmm_plan(np.zeros((0, 3)), 1.0)
+    assert st["cells"] == 0 and st["order"] == 6
+    # a cluster narrower than 8a: no level below the root has a side >= 2a
+    pos = blobs(50, (5, 5, 3), 1)
+    assert arb.arb_fmm_plan(pos, 1.0, levels=4)["levels"] == 0
+    for bad in (dict(order=1), dict(order=9), dict(levels=-1), dict(levels=17), dict(leaf=-1)):
+        with pytest.raises(arb.ArbError):
+            arb.arb_fmm_plan(pos, 1.0, **bad)
+    pos[3, 1] = np.nan
+    with pytest.raises(arb.ArbError):
+        arb.arb_fmm_plan(pos, 1.0)
