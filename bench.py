@@ -500,6 +500,34 @@ def fmm_bench(torch, arb, W, n_bact=8192, reps=10, log=log):
         arb.arb_destroy(c)
     log(f"fmm bench: Euler steps {[round(x['ms']) for x in steps]} ms, iterations "
         f"{[x['iterations'] for x in steps]}")
+    # unbounded: the diatom colonies on the fast operator (the dense solve is the
+    # `diatoms` block)
+    dw = W.diatoms()
+    c = arb.context_for(dw, precision=arb.ARB_FP32C, tol=1e-6, restart=100, max_iter=1000,
+                        pair_kernel=arb.ARB_PAIR_FMM)
+    try:
+        Fd = torch.tensor(dw.F.ravel(), dtype=torch.float64, device=dev)
+        yd = torch.zeros(dw.n_unknowns, dtype=torch.float64, device=dev)
+        arb.arb_solve_dev(c, Fd, None, yd, warm=False, stream=sh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc_d, info_d = arb.arb_solve_dev(c, Fd, None, yd, warm=False, stream=sh)
+        torch.cuda.synchronize()
+        diatom_ms = 1e3 * (time.perf_counter() - t0)
+        ud = torch.zeros(3 * dw.N, dtype=torch.float64, device=dev)
+        lam_d = torch.tensor(np.random.default_rng(2).standard_normal(3 * dw.N), device=dev)
+        arb.arb_mobility_apply_dev(c, lam_d, ud)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            arb.arb_mobility_apply_dev(c, lam_d, ud)
+        torch.cuda.synchronize()
+        diatom_prod_ms = 1e3 * (time.perf_counter() - t0) / reps
+        dst = arb.arb_fmm_get_stats(c)
+    finally:
+        arb.arb_destroy(c)
+    log(f"fmm bench: diatoms (unbounded, N={dw.N}) product {diatom_prod_ms:.2f} ms, solve "
+        f"{diatom_ms:.0f} ms, {info_d['iterations']} iterations")
     return dict(workload=f"{n_bact} bacteria above a wall (42-blob head + 80-blob flagellum), "
                          f"N={wl.N} blobs, lambda ~ N(0,1)",
                 seconds_generate=t_gen, dense_fp32_ms=dense_ms,
@@ -510,7 +538,11 @@ def fmm_bench(torch, arb, W, n_bact=8192, reps=10, log=log):
                            products_fp64=info["products_fp64"],
                            products_fp32=info["products_fp32"],
                            precond_build_ms=info["t_build_ms"], status=rc),
-                euler_steps=dict(dt=0.02, tol=1e-6, order=6, steps=steps))
+                euler_steps=dict(dt=0.02, tol=1e-6, order=6, steps=steps),
+                diatoms_unbounded=dict(N=dw.N, ms_per_product=diatom_prod_ms, levels=dst["levels"],
+                                       ms_per_solve=diatom_ms, iterations=info_d["iterations"],
+                                       rel_residual_fp64=info_d["rel_residual_fp64"],
+                                       status=rc_d))
 
 
 def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, batch=1024, log=log):
