@@ -102,12 +102,14 @@ def max_level(pos: np.ndarray, a: float) -> int:
 
 
 def fmm_apply(pos, lam, a, eta, wall, n, L, kernel=None):
-    """The approximation defined in the module docstring, (N,3).
+    """The approximation defined in the module docstring, (N, d).
 
-    kernel(x, y) -> (..., 3, 3) blocks for broadcastable point arrays; by
-    default the RPY tensor M(x, y) (unbounded or above the wall)."""
+    lam: (N, d) generalised forces; kernel(x, y) -> (..., d, d) blocks for
+    broadcastable point arrays; by default the RPY tensor M(x, y) (d = 3,
+    unbounded or above the wall).  For single-blob bodies (Sec. 2.4) the kernel
+    is the generalised RPY tensor N(x, y) (d = 6) and lam = (f, tau)."""
     pos = np.asarray(pos, float)
-    lam = np.asarray(lam, float).reshape(-1, 3)
+    lam = np.asarray(lam, float).reshape(len(pos), -1)
     if kernel is None:
         def kernel(x, y):
             return rpy.pair_blocks(x, y, a, eta, wall)

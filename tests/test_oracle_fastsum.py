@@ -113,3 +113,50 @@ def test_rpy_error_falls_geometrically_with_order(wall):
     assert errs[0] > 1e-4                   # the interpolation is really used
     assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))
     assert errs[-1] < errs[0] * (1e-2 if not wall else 3e-2)
+
+
+def poly_kernel6(n):
+    """A 6x6 kernel of degree n-1 in each coordinate of x and of y."""
+    K3 = poly_kernel(n)
+
+    def K(x, y):
+        x, y = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float))
+        k = K3(x, y)
+        out = np.zeros(x.shape[:-1] + (6, 6))
+        out[..., :3, :3] = k
+        out[..., 3:, :3] = 0.5 * np.swapaxes(k, -1, -2)
+        out[..., :3, 3:] = -0.3 * k
+        out[..., 3:, 3:] = 2.0 * k + np.eye(3) * (x[..., 1] * y[..., 2])[..., None, None]
+        return out
+    return K
+
+
+@pytest.mark.parametrize("n,L", [(2, 2), (3, 3)])
+def test_six_component_polynomial_kernel_is_exact(n, L):
+    """Generalised forces (f, tau) and a 6x6 kernel (the single-blob form)."""
+    pos, _ = blobs(250, (40, 40, 20), 21 + n)
+    lam6 = np.random.default_rng(n).standard_normal((250, 6))
+    K = poly_kernel6(n)
+    u = fastsum.fmm_apply(pos, lam6, 1.0, 1.0, False, n, L, kernel=K)
+    ref = np.einsum("tsij,sj->ti", K(pos[:, None, :], pos[None, :, :]), lam6)
+    assert u.shape == (250, 6)
+    assert np.abs(u - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_generalised_rpy_error_falls_with_order():
+    """The single-blob tensor (Sec. 2.4) in the interpolation: the error against
+    the dense generalised sum falls with the order."""
+    from oracle import rpy_rot
+    pos, _ = blobs(200, (48, 48, 10), 13)
+    ft = np.random.default_rng(5).standard_normal((200, 6))
+    ref = rpy_rot.body_mobility_apply(pos, ft, 1.0, 1.0)
+
+    def K(x, y):
+        return rpy_rot.pair_blocks(np.asarray(x) - np.asarray(y), 1.0, 1.0)
+    errs = []
+    for n in (2, 3, 4):
+        u = fastsum.fmm_apply(pos, ft, 1.0, 1.0, False, n, 2, kernel=K)
+        errs.append(np.abs(u - ref).max() / np.abs(ref).max())
+    print("generalised RPY, max error by order 2..4:", ["%.1e" % e for e in errs])
+    assert errs[0] > 1e-4
+    assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))
