@@ -403,7 +403,7 @@ int fmm_pair(arb_ctx *ctx, hipStream_t s, int N, const double *pos, const float4
         std::string msg;
         const auto t0 = std::chrono::steady_clock::now();
         const int rc = arb::fmm_build(F, s, N, pos, hi, lo, ctx->opt.a, ctx->opt.fmm_order,
-                                      ctx->opt.fmm_levels, ctx->opt.fmm_leaf, &msg);
+                                      ctx->opt.fmm_levels, ctx->opt.fmm_leaf, 1, &msg);
         if (rc) return fail(ctx, rc, msg);
         F.build_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
@@ -474,6 +474,28 @@ static bool rot_symmetric(const arb_ctx *ctx) {
 int body_mobility_dev(arb_ctx *ctx, hipStream_t s, const double *x6, double scale,
                       const double *base, double *out, int precision) {
     const int M = ctx->M;
+    if (ctx->opt.pair_kernel == ARB_PAIR_FMM) {
+        // the fast product of the generalised tensor: tree of the body positions
+        // with a torque channel, rebuilt when the state has changed
+        arb::FmmState &F = ctx->fmm;
+        if (F.dirty || !F.ready || F.N != M || F.channels < 2) {
+            std::string msg;
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = arb::fmm_build(F, s, M, ctx->pos.as<double>(), ctx->hi.as<float4>(),
+                                          ctx->lo.as<float4>(), ctx->opt.a, ctx->opt.fmm_order,
+                                          ctx->opt.fmm_levels, ctx->opt.fmm_leaf, 2, &msg);
+            if (rc) return fail(ctx, rc, msg);
+            F.build_ms = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t0)
+                             .count();
+            F.dirty = false;
+        }
+        HIPCHK(ctx->rot_partial.ensure(std::max<int64_t>(6 * (int64_t)M, 1) * sizeof(double)));
+        const double a = ctx->opt.a, k = scale / (8.0 * arb::kPi * ctx->opt.eta);
+        arb::fmm_apply6(F, s, precision == ARB_FP64, x6, 1.0 / a, ctx->rot_partial.as<double>());
+        arb::rot_reduce(s, M, ctx->rot_partial.as<double>(), k / a, k / (a * a), base, out);
+        return 0;
+    }
     HIPCHK(ctx->rot_partial.ensure(std::max<int64_t>(
         (int64_t)arb::rot_pair_slices(M) * 6 * M, 1) * sizeof(double)));
     const int4 *work = nullptr;
@@ -1082,8 +1104,7 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         return ARB_E_ARG;
     // single-blob bodies: unbounded generalised RPY, exact or no preconditioner,
     // direct sums
-    if (opt->model == ARB_MODEL_SINGLE_BLOB &&
-        (opt->wall != 0 || opt->precond > ARB_PC_BLOCK || opt->pair_kernel == ARB_PAIR_FMM))
+    if (opt->model == ARB_MODEL_SINGLE_BLOB && (opt->wall != 0 || opt->precond > ARB_PC_BLOCK))
         return ARB_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)

@@ -77,8 +77,8 @@ constexpr int kFmmDefaultOrder = 6;
 // Morton order, level l at [lvl[l], lvl[l+1])
 struct FmmState {
     DevBuf perm, cc, rng, parent, kids, il_ptr, il, near_ptr, nearl, work, tab, shi, slo, slam,
-        qhat, v;
-    int N = 0, L = 0, n = 0, P = 0, ncell = 0, nleaf = 0, nwork = 0;
+        qhat, v, slam2, qhat2, v2;  // second channel: the torques of single-blob bodies
+    int N = 0, L = 0, n = 0, P = 0, ncell = 0, nleaf = 0, nwork = 0, channels = 1;
     int64_t n_il = 0, n_near_pairs = 0;  // interaction-list entries, direct pairs
     std::vector<int> lvl;
     double o[3] = {0.0, 0.0, 0.0}, S = 0.0;  // root cube in units of a
@@ -91,12 +91,19 @@ struct FmmState {
 // default), levels = leaf level (0: from leaf, the mean blobs per leaf aimed at;
 // 0: 2 n^3).  Returns 0 or an ARB_E_* code with *msg set.
 int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
-              const float4 *lo, double a, int order, int levels, int leaf, std::string *msg);
+              const float4 *lo, double a, int order, int levels, int leaf, int channels,
+              std::string *msg);
 // partial[c][i] (3 x N, original order) = the approximation of M_{a=1} lambda,
 // M in units of 1/(8 pi eta) with positions in units of a; fp64: lambda and
 // every sum in double (linear in lambda to double rounding), else in float
 void fmm_apply(const FmmState &F, hipStream_t s, bool wall, bool fp64, const double *lam,
                double *partial);
+// single-blob bodies (unbounded, generalised RPY, a tree built with channels = 2):
+// partial[j][i] (6 x M, original order) = the approximation of N_{a=1} (f, tau / a)
+// with positions in units of a; the caller scales u by 1/(8 pi eta a), w by
+// 1/(8 pi eta a^2)
+void fmm_apply6(const FmmState &F, hipStream_t s, bool fp64, const double *x6, double inv_a,
+                double *partial);
 
 // ---------------------------------------------------------------- kernel entry points
 // Pair sum u_i = sum_j M_ij lambda_j (Sec. 2.3): partial sums per source slice,
@@ -244,6 +251,9 @@ void rot_pair_apply(hipStream_t s, int precision, int M, const double4 *p64, con
                     const float4 *lo, const double *x6, double a, double scale,
                     const double *base, double *partial, double *out, const int4 *work,
                     int n_work);
+// out_i = base_i + (scale_u u_i, scale_w w_i) from one 6 x M partial sum
+void rot_reduce(hipStream_t s, int M, const double *partial, double scale_u, double scale_w,
+                const double *base, double *out);
 void single_blob_body_mobility(hipStream_t s, int M, double a, double eta, double *Nt);
 void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_off,
                           const int64_t *zero_off64, const double *r, double *z);

@@ -46,7 +46,7 @@
 #include <cmath>
 #include <type_traits>
 
-#include "rpy_device.h"
+#include "rot_device.h"
 
 namespace arb {
 
@@ -488,6 +488,208 @@ __global__ __launch_bounds__(kNearBlock) void fmm_near_kernel(
     }
 }
 
+// ---------------------------------------------------------------- single-blob bodies
+// Generalised forces (f, tau) in two channels, f and tau / a (units of a), each
+// carried by the channel-wise P2M, M2M and L2L kernels above; M2L and the near
+// field apply the 6 x 6 generalised tensor (Sec. 2.4) between the channels.
+
+template <class A>
+__global__ void fmm_gather6_kernel(int M, const int *__restrict__ perm,
+                                   const double *__restrict__ x6, double inv_a,
+                                   Vec4<A> *__restrict__ sf, Vec4<A> *__restrict__ st) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const double *x = x6 + 6 * (size_t)perm[k];
+    sf[k] = vec4<A>((A)x[0], (A)x[1], (A)x[2]);
+    st[k] = vec4<A>((A)(x[3] * inv_a), (A)(x[4] * inv_a), (A)(x[5] * inv_a));
+}
+
+// acc += N(d) (f, t): tensor coefficients in float (a = 1), applied in A
+template <class A>
+__device__ __forceinline__ void rot_acc(float dx, float dy, float dz, float r2, const Vec4<A> &f,
+                                        const Vec4<A> &t, A *acc) {
+    const float rinv = rsq_f32(r2);
+    const RotTerms<float> kf = rot_terms<float>(r2, rinv, kUnitRotCoef);
+    if constexpr (std::is_same_v<A, float>) {
+        rot_one_way<float>(kf, dx, dy, dz, f.x, f.y, f.z, t.x, t.y, t.z, acc);
+    } else {
+        const RotTerms<double> kd{kf.c1, kf.c2, kf.cr, kf.d1, kf.d2};
+        rot_one_way<double>(kd, dx, dy, dz, f.x, f.y, f.z, t.x, t.y, t.z, acc);
+    }
+}
+
+// M2L of the generalised tensor (unbounded), lane groups as in fmm_m2l_kernel
+template <class A>
+__global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
+    Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
+    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int groups,
+    const Vec4<A> *__restrict__ qf, const Vec4<A> *__restrict__ qt, double *__restrict__ vu,
+    double *__restrict__ vw) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int n = g.n, P = g.P;
+    const int GP = groups * P;  // <= kFmmMaxP
+    Vec4<A> *s_qf = reinterpret_cast<Vec4<A> *>(lds);
+    Vec4<A> *s_qt = s_qf + GP;
+    float4 *s_off = reinterpret_cast<float4 *>(s_qt + GP);
+    double *s_acc = reinterpret_cast<double *>(s_off + P);
+    float *tab = reinterpret_cast<float *>(s_acc + 6 * (GP - P));
+    load_tab(tabg, tab);
+    const int c = cell0 + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int4 ct = cc[c];
+    const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
+    for (int m = tid; m < P; m += blockDim.x) {
+        const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
+        s_off[m] = make_float4((float)(w * tab[kTabNode + mx]), (float)(w * tab[kTabNode + my]),
+                               (float)(w * tab[kTabNode + mz]), 0.f);
+    }
+    const bool act = tid < GP;
+    const int gi = act ? tid / P : 0;
+    const int k = act ? tid - gi * P : 0;
+    const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
+    const float okx = (float)(w * tab[kTabNode + kx]), oky = (float)(w * tab[kTabNode + ky]),
+                okz = (float)(w * tab[kTabNode + kz]);
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int e1 = il_ptr[c + 1];
+    for (int e0 = il_ptr[c]; e0 < e1; e0 += groups) {
+        __syncthreads();
+        for (int t = tid; t < GP; t += blockDim.x) {
+            const int gg = t / P;
+            if (e0 + gg < e1) {
+                const size_t q = (size_t)il[e0 + gg] * P + (t - gg * P);
+                s_qf[t] = qf[q];
+                s_qt[t] = qt[q];
+            }
+        }
+        __syncthreads();
+        const int e = e0 + gi;
+        if (!act || e >= e1) continue;
+        const int4 cs = cc[il[e]];
+        const float ax = (float)((double)(ct.x - cs.x) * side) + okx;
+        const float ay = (float)((double)(ct.y - cs.y) * side) + oky;
+        const float az = (float)((double)(ct.z - cs.z) * side) + okz;
+        const Vec4<A> *sf = s_qf + gi * P, *st = s_qt + gi * P;
+        for (int m0 = 0; m0 < P; m0 += kFmmRun) {
+            const int m1 = min(m0 + kFmmRun, P);
+            A f6[6] = {0, 0, 0, 0, 0, 0};
+            for (int m = m0; m < m1; ++m) {
+                const float4 o = s_off[m];
+                const float dx = ax - o.x, dy = ay - o.y, dz = az - o.z;
+                rot_acc<A>(dx, dy, dz, fmaf(dz, dz, fmaf(dx, dx, dy * dy)), sf[m], st[m], f6);
+            }
+#pragma unroll
+            for (int j = 0; j < 6; ++j) acc[j] += f6[j];
+        }
+    }
+    __syncthreads();
+    if (act && gi > 0) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) s_acc[6 * (tid - P) + j] = acc[j];
+    }
+    __syncthreads();
+    if (act && gi == 0) {
+        for (int gg = 1; gg < groups; ++gg)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) acc[j] += s_acc[6 * ((gg - 1) * P + k) + j];
+        double *ou = vu + ((size_t)c * P + k) * 3, *ow = vw + ((size_t)c * P + k) * 3;
+        ou[0] = acc[0];
+        ou[1] = acc[1];
+        ou[2] = acc[2];
+        ow[0] = acc[3];
+        ow[1] = acc[4];
+        ow[2] = acc[5];
+    }
+}
+
+// direct sums of the generalised tensor over adjacent leaves plus both
+// channels' interpolants; partial[j][body] (6 x M, original order)
+template <class A>
+__global__ __launch_bounds__(kNearBlock) void fmm_near6_kernel(
+    Geo g, const float *__restrict__ tabg, int M, int far, const int4 *__restrict__ cc,
+    const int2 *__restrict__ rng, const int *__restrict__ near_ptr, const int *__restrict__ near,
+    int leaf0, const int2 *__restrict__ work, const int *__restrict__ perm,
+    const float4 *__restrict__ shi, const float4 *__restrict__ slo, const Vec4<A> *__restrict__ sf,
+    const Vec4<A> *__restrict__ st, const double *__restrict__ vu, const double *__restrict__ vw,
+    double *__restrict__ partial) {
+    __shared__ float tab[kTabSize];
+    __shared__ float4 s_hi[kNearBlock], s_lo[kNearBlock];
+    __shared__ Vec4<A> s_f[kNearBlock], s_t[kNearBlock];
+    load_tab(tabg, tab);
+    const int tid = threadIdx.x;
+    const int2 wk = work[blockIdx.x];
+    const int c = wk.x;
+    const int2 tr = rng[c];
+    const int i = wk.y + tid;
+    const bool act = i < tr.y;
+    const int ic = act ? i : tr.y - 1;
+    const float4 th = shi[ic], tl = slo[ic];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int lf = c - leaf0;
+    const int e1 = near_ptr[lf + 1];
+    for (int e = near_ptr[lf]; e < e1; ++e) {
+        const int2 sr = rng[near[e]];
+        for (int j0 = sr.x; j0 < sr.y; j0 += kNearBlock) {
+            const int j = j0 + tid;
+            __syncthreads();
+            if (j < sr.y) {
+                s_hi[tid] = shi[j];
+                s_lo[tid] = slo[j];
+                s_f[tid] = sf[j];
+                s_t[tid] = st[j];
+            }
+            __syncthreads();
+            const int cnt = min(kNearBlock, sr.y - j0);
+            for (int k0 = 0; k0 < cnt; k0 += kFmmRun) {
+                const int k1 = min(k0 + kFmmRun, cnt);
+                A f6[6] = {0, 0, 0, 0, 0, 0};
+                for (int k = k0; k < k1; ++k) {
+                    const float4 sh = s_hi[k], sl = s_lo[k];
+                    const float dx = (th.x - sh.x) + (tl.x - sl.x);
+                    const float dy = (th.y - sh.y) + (tl.y - sl.y);
+                    const float dz = (th.z - sh.z) + (tl.z - sl.z);
+                    rot_acc<A>(dx, dy, dz, fmaf(dz, dz, fmaf(dx, dx, dy * dy)), s_f[k], s_t[k],
+                               f6);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 6; ++jj) acc[jj] += f6[jj];
+            }
+        }
+    }
+    if (far) {
+        const int n = g.n;
+        const int4 ci = cc[c];
+        const double side = ldexp(g.S, -ci.w);
+        const F2 cx = split(centre(g.ox, side, ci.x)), cy = split(centre(g.oy, side, ci.y)),
+                 cz = split(centre(g.oz, side, ci.z));
+        const float iw = (float)(2.0 / side);
+        const float px = ((th.x - cx.h) + (tl.x - cx.l)) * iw;
+        const float py = ((th.y - cy.h) + (tl.y - cy.l)) * iw;
+        const float pz = ((th.z - cz.h) + (tl.z - cz.l)) * iw;
+        const double *pu = vu + (size_t)c * g.P * 3, *pw = vw + (size_t)c * g.P * 3;
+        for (int kx = 0; kx < n; ++kx) {
+            const float a = lag(tab, n, kx, px);
+            for (int ky = 0; ky < n; ++ky) {
+                const float b = a * lag(tab, n, ky, py);
+                for (int kz = 0; kz < n; ++kz) {
+                    const double wk2 = (double)(b * lag(tab, n, kz, pz));
+                    const int q = 3 * ((kx * n + ky) * n + kz);
+                    acc[0] = fma(wk2, pu[q], acc[0]);
+                    acc[1] = fma(wk2, pu[q + 1], acc[1]);
+                    acc[2] = fma(wk2, pu[q + 2], acc[2]);
+                    acc[3] = fma(wk2, pw[q], acc[3]);
+                    acc[4] = fma(wk2, pw[q + 1], acc[4]);
+                    acc[5] = fma(wk2, pw[q + 2], acc[5]);
+                }
+            }
+        }
+    }
+    if (act) {
+        const size_t o = (size_t)perm[i];
+#pragma unroll
+        for (int jj = 0; jj < 6; ++jj) partial[(size_t)jj * M + o] = acc[jj];
+    }
+}
+
 // ---------------------------------------------------------------- host tree
 inline uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
     x &= 0x1fffff;
@@ -503,6 +705,21 @@ inline uint64_t morton(int x, int y, int z) {
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// M2L lane groups per workgroup: the count (up to 8 within 512 lanes) that
+// leaves the fewest idle lanes in its waves
+int m2l_groups(int P) {
+    int groups = 1;
+    double best = 0.0;
+    for (int gq = 1; gq <= 8 && gq * P <= kFmmMaxP; ++gq) {
+        const double util = (double)(gq * P) / round_up(gq * P, kWave);
+        if (util > best + 1e-9) {
+            best = util;
+            groups = gq;
+        }
+    }
+    return groups;
+}
 
 }  // namespace
 
@@ -751,7 +968,8 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
 }
 
 int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
-              const float4 *lo, double a, int order, int levels, int leaf, std::string *msg) {
+              const float4 *lo, double a, int order, int levels, int leaf, int channels,
+              std::string *msg) {
     F.N = 0;
     F.ready = false;
     const int n = order > 0 ? order : kFmmDefaultOrder;
@@ -798,7 +1016,11 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
               F.slo.ensure((size_t)N * sizeof(float4)) == hipSuccess &&
               F.slam.ensure((size_t)N * sizeof(double4)) == hipSuccess &&
               F.qhat.ensure((size_t)ncell * P * sizeof(double4)) == hipSuccess &&
-              F.v.ensure((size_t)ncell * P * 3 * sizeof(double)) == hipSuccess;
+              F.v.ensure((size_t)ncell * P * 3 * sizeof(double)) == hipSuccess &&
+              (channels < 2 ||
+               (F.slam2.ensure((size_t)N * sizeof(double4)) == hipSuccess &&
+                F.qhat2.ensure((size_t)ncell * P * sizeof(double4)) == hipSuccess &&
+                F.v2.ensure((size_t)ncell * P * 3 * sizeof(double)) == hipSuccess));
     if (!ok) {
         *msg = "fast product: device allocation or copy failed";
         return ARB_E_DEVICE;
@@ -820,6 +1042,7 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
     F.nwork = (int)pl.work.size();
     F.n_il = (int64_t)pl.il.size();
     F.n_near_pairs = pl.n_near_pairs;
+    F.channels = channels;
     F.N = N;
     F.ready = true;
     return 0;
@@ -843,17 +1066,7 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
             fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(g, tab, F.cc.as<int4>(),
                                                                    F.kids.as<int2>(), F.lvl[l],
                                                                    qhat);
-        // lane groups per workgroup: the count (up to 8 within 512 lanes) that
-        // leaves the fewest idle lanes in its waves
-        int groups = 1;
-        double best = 0.0;
-        for (int gq = 1; gq <= 8 && gq * P <= kFmmMaxP; ++gq) {
-            const double util = (double)(gq * P) / round_up(gq * P, kWave);
-            if (util > best + 1e-9) {
-                best = util;
-                groups = gq;
-            }
-        }
+        const int groups = m2l_groups(P);
         const size_t lds = (size_t)groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
                            (size_t)3 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
@@ -880,6 +1093,58 @@ void fmm_apply(const FmmState &F, hipStream_t s, bool wall, bool fp64, const dou
     else
         fp64 ? fmm_run<false, double>(F, s, lam, partial)
              : fmm_run<false, float>(F, s, lam, partial);
+}
+
+}  // namespace arb
+
+namespace arb {
+
+namespace {
+
+template <class A>
+void fmm_run6(const FmmState &F, hipStream_t s, const double *x6, double inv_a, double *partial) {
+    const int M = F.N, L = F.L, P = F.P;
+    const Geo g{F.o[0], F.o[1], F.o[2], F.S, F.n, P};
+    const int B = round_up(P, kWave);
+    const float *tab = F.tab.as<float>();
+    Vec4<A> *sf = F.slam.as<Vec4<A>>(), *st = F.slam2.as<Vec4<A>>();
+    Vec4<A> *qf = F.qhat.as<Vec4<A>>(), *qt = F.qhat2.as<Vec4<A>>();
+    double *vu = F.v.as<double>(), *vw = F.v2.as<double>();
+    fmm_gather6_kernel<A><<<(M + 255) / 256, 256, 0, s>>>(M, F.perm.as<int>(), x6, inv_a, sf, st);
+    if (L >= 2) {
+        const int nl = F.lvl[L + 1] - F.lvl[L];
+        for (int ch = 0; ch < 2; ++ch)
+            fmm_p2m_kernel<A><<<nl, B, 0, s>>>(g, tab, F.cc.as<int4>(), F.rng.as<int2>(),
+                                               F.lvl[L], F.shi.as<float4>(), F.slo.as<float4>(),
+                                               ch ? st : sf, ch ? qt : qf);
+        for (int l = L - 1; l >= 2; --l)
+            for (int ch = 0; ch < 2; ++ch)
+                fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                    g, tab, F.cc.as<int4>(), F.kids.as<int2>(), F.lvl[l], ch ? qt : qf);
+        const int groups = m2l_groups(P);
+        const size_t lds = (size_t)2 * groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
+                           (size_t)6 * (groups - 1) * P * sizeof(double) +
+                           kTabSize * sizeof(float);
+        fmm_m2l6_kernel<A><<<F.lvl[L + 1] - F.lvl[2], round_up(groups * P, kWave), lds, s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], groups, qf, qt,
+            vu, vw);
+        for (int l = 3; l <= L; ++l)
+            for (int ch = 0; ch < 2; ++ch)
+                fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                    g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], ch ? vw : vu);
+    }
+    fmm_near6_kernel<A><<<F.nwork, kNearBlock, 0, s>>>(
+        g, tab, M, L >= 2 ? 1 : 0, F.cc.as<int4>(), F.rng.as<int2>(), F.near_ptr.as<int>(),
+        F.nearl.as<int>(), F.lvl[L], F.work.as<int2>(), F.perm.as<int>(), F.shi.as<float4>(),
+        F.slo.as<float4>(), sf, st, vu, vw, partial);
+}
+
+}  // namespace
+
+void fmm_apply6(const FmmState &F, hipStream_t s, bool fp64, const double *x6, double inv_a,
+                double *partial) {
+    if (F.N == 0) return;
+    fp64 ? fmm_run6<double>(F, s, x6, inv_a, partial) : fmm_run6<float>(F, s, x6, inv_a, partial);
 }
 
 }  // namespace arb

@@ -34,8 +34,8 @@ def test_bad_options_rejected_before_device():
     for kw in (dict(a=-1.0), dict(eta=0.0), dict(tol=0.0), dict(restart=0), dict(restart=1000),
                dict(precision=7), dict(precond=9), dict(precond=4), dict(max_iter=0),
                dict(pair_kernel=4), dict(graphs=2), dict(model=2),
-               # single-blob bodies: unbounded, exact or no preconditioner, direct sums
-               dict(model=1, wall=1), dict(model=1, precond=2), dict(model=1, pair_kernel=3),
+               # single-blob bodies: unbounded, exact or no preconditioner
+               dict(model=1, wall=1), dict(model=1, precond=2),
                # fast product: 2..8 points per direction, levels 0..16, leaf >= 0
                dict(pair_kernel=3, fmm_order=1), dict(pair_kernel=3, fmm_order=9),
                dict(fmm_levels=-1), dict(fmm_levels=17), dict(fmm_leaf=-1)):

@@ -10,7 +10,7 @@ coincident blobs, a single blob)."""
 import numpy as np
 import pytest
 
-from oracle import bodies, fastsum, rpy, system
+from oracle import bodies, fastsum, rpy, rpy_rot, single_blob, system
 from paper_2107_10800_amd import arb
 from paper_2107_10800_amd import workloads as W
 
@@ -103,8 +103,6 @@ def test_options_are_checked():
                 dict(pair_kernel=4)):
         with pytest.raises(arb.ArbError):
             arb.arb_create(**bad)
-    with pytest.raises(arb.ArbError):
-        arb.arb_create(pair_kernel=arb.ARB_PAIR_FMM, model=arb.ARB_MODEL_SINGLE_BLOB)
     # a leaf level deeper than the side of 2a allows is clamped, not an error
     pos, lam = blobs(200, (20, 20, 5), 3)
     u = fmm(pos, lam, False, 4, 12)
@@ -181,3 +179,84 @@ def test_full_size_sampled_rows():
         print(f"  precision {prec}: L={st['levels']}, max error on sampled rows {err:.1e}",
               flush=True)
         assert st["levels"] >= 5 and err <= 1e-4
+
+
+# ---------------------------------------------------------------- single-blob bodies
+def loose_bodies(M, box, seed, a):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0, 1, (M, 3)) * np.array(box, float) * a
+    return W.Workload("loose", a, 1.7, False, np.zeros((M, 3)),
+                      np.arange(M + 1, dtype=np.int32), q, np.tile([1.0, 0, 0, 0], (M, 1)),
+                      rng.standard_normal((M, 6)), extra=dict(single_blob=True))
+
+
+def rot_kernel(a, eta):
+    def K(x, y):
+        return rpy_rot.pair_blocks(np.asarray(x) - np.asarray(y), a, eta)
+    return K
+
+
+@pytest.mark.parametrize("M,box,n,L", [(300, (40, 40, 10), 4, 3), (301, (30, 30, 30), 3, 2),
+                                       (260, (48, 24, 12), 5, 2)])
+def test_single_blob_matches_the_oracle_of_the_approximation(M, box, n, L):
+    """The generalised tensor (Sec. 2.4) in the fast product, force and torque
+    channels, both variants, against the oracle's plain sum of the same
+    approximation; coincident bodies included."""
+    wl = loose_bodies(M, box, 60 + M, 0.8)
+    wl.q[1] = wl.q[0]
+    ref = fastsum.fmm_apply(wl.q, wl.F, wl.a, wl.eta, False, n, L, kernel=rot_kernel(wl.a, wl.eta))
+    dense = rpy_rot.body_mobility_apply(wl.q, wl.F, wl.a, wl.eta)
+    approx = np.abs(ref - dense).max() / np.abs(dense).max()
+    for prec in (arb.ARB_FP64, arb.ARB_FP32C):
+        ctx = arb.context_for(wl, precision=prec, pair_kernel=arb.ARB_PAIR_FMM, fmm_order=n,
+                              fmm_levels=L)
+        try:
+            uw = arb.arb_body_mobility_apply(ctx, wl.F)
+        finally:
+            arb.arb_destroy(ctx)
+        err = np.abs(uw - ref).max() / np.abs(ref).max()
+        print(f"single-blob fast product M={M} n={n} L={L} precision {prec}: {err:.1e} "
+              f"(approximation vs dense {approx:.1e})", flush=True)
+        assert err <= 1e-5 and approx > 10 * err
+
+
+def test_single_blob_sampled_rows_at_4096_shells():
+    """172,032 single-blob bodies, default order and level: 32 sampled rows
+    against the oracle's dense generalised sums, within 1e-4 of the row's
+    largest entry."""
+    wl = W.blob_shells(16)
+    ctx = arb.context_for(wl, precision=arb.ARB_FP32C, pair_kernel=arb.ARB_PAIR_FMM)
+    try:
+        uw = arb.arb_body_mobility_apply(ctx, wl.F)
+        st = arb.arb_fmm_get_stats(ctx)
+    finally:
+        arb.arb_destroy(ctx)
+    rows = np.random.default_rng(3).choice(wl.M, 32, replace=False)
+    worst = 0.0
+    for t in rows:
+        blk = rpy_rot.pair_blocks(wl.q[t] - wl.q, wl.a, wl.eta)
+        ref = np.einsum("mij,mj->i", blk, wl.F)
+        worst = max(worst, np.abs(uw[t] - ref).max() / np.abs(ref).max())
+    print(f"4096 shells fast product: L={st['levels']}, worst sampled row error {worst:.1e}",
+          flush=True)
+    assert st["levels"] >= 3 and worst <= 1e-4
+
+
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_single_blob_solve_with_the_fast_product(prec):
+    """Eight linked shells (Eq. linear_system_general) on the fast operator
+    (n = 6, L = 2) to 1e-10 against the oracle's dense solve."""
+    wl = W.blob_shells(2)
+    S = single_blob.assemble(wl)
+    y = single_blob.solve_dense(S)
+    ctx = arb.context_for(wl, precision=prec, tol=1e-10, pair_kernel=arb.ARB_PAIR_FMM,
+                          fmm_order=6, fmm_levels=2)
+    try:
+        rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+    finally:
+        arb.arb_destroy(ctx)
+    M = wl.M
+    err = np.linalg.norm(U.ravel() - y[:6 * M]) / np.linalg.norm(y[:6 * M])
+    print(f"single-blob fast solve precision {prec}: {info['iterations']} iterations, residual "
+          f"{info['rel_residual']:.1e}, velocities vs dense solve {err:.1e}", flush=True)
+    assert info["rel_residual"] <= 1e-10 and err <= 1e-3
