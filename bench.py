@@ -356,8 +356,8 @@ def single_blob_bench(torch, arb, W, reps=5):
                         kernel=f"rot_pair_sym_{pname}_kernel")
     out["product"]["frac_of_fp64_peak"] = out["product"]["frac_of_peak"]
 
-    def solve(wl, tol, timed, prec=arb.ARB_FP64):
-        c = arb.context_for(wl, tol=tol, precision=prec)
+    def solve(wl, tol, timed, prec=arb.ARB_FP64, pair_kernel=0):
+        c = arb.context_for(wl, tol=tol, precision=prec, pair_kernel=pair_kernel)
         try:
             Fd = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
             y = torch.zeros(wl.n_unknowns - 3 * wl.N, dtype=torch.float64, device=dev)
@@ -406,6 +406,48 @@ def single_blob_bench(torch, arb, W, reps=5):
                           iterations=info["iterations"], rel_residual=info["rel_residual"],
                           ms_per_solve=ms, status=rc))
     out["filament_scan"] = fscan
+    # the fast product (ARB_PAIR_FMM, default order 6) on the 4,096 shells
+    import numpy as np
+    wl = W.blob_shells(16)
+    F = torch.tensor(wl.F.ravel(), dtype=torch.float64, device=dev)
+    ref = torch.zeros_like(F)
+    c = arb.context_for(wl, precision=arb.ARB_FP64)
+    try:
+        arb.arb_body_mobility_apply_dev(c, F, ref, stream=sh)
+        torch.cuda.synchronize()
+    finally:
+        arb.arb_destroy(c)
+    ref_h = ref.cpu().numpy()
+    fast = {}
+    for prec, name, dense_ms in ((arb.ARB_FP32C, "float sums", out["product_fp32c"]["ms"]),
+                                 (arb.ARB_FP64, "double sums", out["product"]["ms"])):
+        c = arb.context_for(wl, precision=prec, pair_kernel=arb.ARB_PAIR_FMM)
+        try:
+            UW = torch.zeros_like(F)
+            arb.arb_body_mobility_apply_dev(c, F, UW, stream=sh)
+            st = arb.arb_fmm_get_stats(c)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                arb.arb_body_mobility_apply_dev(c, F, UW, stream=sh)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+        finally:
+            arb.arb_destroy(c)
+        err = float(np.abs(UW.cpu().numpy() - ref_h).max() / np.abs(ref_h).max())
+        fast[name] = dict(ms=ms, dense_ms=dense_ms, speedup=dense_ms / ms,
+                          max_rel_err_vs_dense_fp64=err, levels=st["levels"],
+                          near_pairs=st["near_pairs"], m2l_pairs=st["m2l_pairs"])
+        log(f"bench: 4096 shells, fast product ({name}) {ms:.2f} ms ({dense_ms / ms:.1f}x the "
+            f"dense kernel), max error {err:.1e}")
+    for tol, prec, name in ((1e-10, arb.ARB_FP64, "f64"), (1e-4, arb.ARB_FP32C, "f32c")):
+        rc, info, ms = solve(wl, tol, True, prec, arb.ARB_PAIR_FMM)
+        fast[f"solve_{name}_tol{tol:g}"] = dict(iterations=info["iterations"],
+                                                rel_residual=info["rel_residual"],
+                                                ms_per_solve=ms, status=rc)
+        log(f"bench: 4096 shells to {tol:g} on the fast product ({name}): "
+            f"{info['iterations']} iterations, {ms:.1f} ms")
+    out["fast_product_4096_shells"] = fast
     return out
 
 

@@ -101,7 +101,8 @@ typedef struct {
                        /* index in HIP graphs and replayed (default),          */
                        /* 1 = plain launches                                   */
     int    model;      /* ARB_MODEL_MULTIBLOB (default) or ARB_MODEL_SINGLE_BLOB */
-    /* ARB_PAIR_FMM only (rigid multiblob bodies).  The octree's root cube spans
+    /* ARB_PAIR_FMM only.  For single-blob bodies the generalised tensor of Sec. 2.4
+ * is interpolated with force and torque channels.  The octree's root cube spans
      * the blobs; cells of a level are adjacent when their integer coordinates
      * differ by at most 1.  Pairs in adjacent leaves are summed directly; the
      * tensor between well-separated cells is replaced by its tensor-product
@@ -111,11 +112,14 @@ typedef struct {
      * suspensions).  The tree is rebuilt on the host whenever the state
      * changes (one device-to-host copy of the positions and a sort).        */
     int    fmm_order;  /* Chebyshev points per direction, 2..8 (0 = 6)          */
-    int    fmm_levels; /* leaf level L (0 = the shallowest level whose mean     */
-                       /* occupancy is <= fmm_leaf); never deeper than the      */
-                       /* deepest level with a cell side >= 2a; L <= 1 gives the */
-                       /* direct sum                                            */
-    int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = 2 fmm_order^3)      */
+    int    fmm_levels; /* leaf level L; 0 = chosen: with fmm_leaf > 0 the       */
+                       /* shallowest level whose mean occupancy is <= fmm_leaf, */
+                       /* else the level with the fewest pair evaluations per   */
+                       /* product (direct pairs + fmm_order^6 per interaction-  */
+                       /* list entry), going deeper from level 2 while they     */
+                       /* fall; never deeper than the deepest level with a cell */
+                       /* side >= 2a; L <= 1 gives the direct sum               */
+    int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = see fmm_levels)     */
 } arb_options;
 
 typedef struct {

@@ -88,8 +88,10 @@ struct FmmState {
 };
 // tree of N blobs (positions in units of length on the device, hi/lo as
 // prep_positions makes them); order = Chebyshev points per direction (0: the
-// default), levels = leaf level (0: from leaf, the mean blobs per leaf aimed at;
-// 0: 2 n^3).  Returns 0 or an ARB_E_* code with *msg set.
+// default), levels = leaf level (0: chosen, from leaf, the mean blobs per leaf
+// aimed at, or when leaf = 0 the level with the fewest pair evaluations);
+// channels = 2 adds the torque channel of single-blob bodies.  Returns 0 or an
+// ARB_E_* code with *msg set.
 int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const float4 *hi,
               const float4 *lo, double a, int order, int levels, int leaf, int channels,
               std::string *msg);

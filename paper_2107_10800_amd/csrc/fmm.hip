@@ -706,6 +706,43 @@ inline uint64_t morton(int x, int y, int z) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// open-addressing map from the Morton keys of one level's cells (< 2^48) to
+// their indices
+struct CellHash {
+    std::vector<uint64_t> keys;
+    std::vector<int> vals;
+    uint64_t mask = 0;
+    static uint64_t mix(uint64_t x) {
+        x ^= x >> 30;
+        x *= 0xbf58476d1ce4e5b9ull;
+        x ^= x >> 27;
+        x *= 0x94d049bb133111ebull;
+        return x ^ (x >> 31);
+    }
+    void build(const uint64_t *k, int n, int base) {
+        size_t cap = 16;
+        while (cap < 2 * (size_t)n) cap *= 2;
+        mask = cap - 1;
+        keys.assign(cap, ~0ull);
+        vals.assign(cap, -1);
+        for (int i = 0; i < n; ++i) {
+            uint64_t h = mix(k[i]) & mask;
+            while (keys[h] != ~0ull) h = (h + 1) & mask;
+            keys[h] = k[i];
+            vals[h] = base + i;
+        }
+    }
+    // index of the cell with coordinates (x, y, z) at a level of side 2^l, or -1
+    int get(int l, int x, int y, int z) const {
+        const int lim = 1 << l;
+        if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
+        const uint64_t k = morton(x, y, z);
+        for (uint64_t h = mix(k) & mask; keys[h] != ~0ull; h = (h + 1) & mask)
+            if (keys[h] == k) return vals[h];
+        return -1;
+    }
+};
+
 // M2L lane groups per workgroup: the count (up to 8 within 512 lanes) that
 // leaves the fewest idle lanes in its waves
 int m2l_groups(int P) {
@@ -803,120 +840,214 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
         first[j] = (unsigned char)(Lhi - hb / 3);
         ++new_at[first[j]];
     }
+    // the cells of levels 0..L with their blob ranges, parents and children, the
+    // interaction lists, the adjacent leaves and the work items of leaf level L
+    auto build = [&](int L, FmmPlan &q) -> int {
+        // cells of every level in Morton order, with their blob ranges
+        std::vector<std::vector<int>> starts(L + 1, std::vector<int>(1, 0));
+        for (int j = 1; j < N; ++j)
+            for (int l = first[j]; l <= L; ++l) starts[l].push_back(j);
+        std::vector<int4> cc;
+        std::vector<int2> rng;
+        std::vector<uint64_t> pk;
+        std::vector<int> lvl(L + 2, 0);
+        for (int l = 0; l <= L; ++l) {
+            lvl[l] = (int)cc.size();
+            const int sh = 3 * (Lhi - l), dl = Lhi - l;
+            const std::vector<int> &st = starts[l];
+            for (size_t t = 0; t < st.size(); ++t) {
+                const int j = st[t], e = t + 1 < st.size() ? st[t + 1] : N;
+                const int i0 = idx[j];
+                cc.push_back(make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
+                                       crd[3 * (size_t)i0 + 2] >> dl, l));
+                rng.push_back(make_int2(j, e));
+                pk.push_back(key[j] >> sh);
+            }
+        }
+        lvl[L + 1] = (int)cc.size();
+        const int ncell = (int)cc.size();
+        std::vector<int> parent(ncell, -1);
+        std::vector<int2> kids(ncell, make_int2(0, 0));
+        for (int l = 1; l <= L; ++l) {
+            int p = lvl[l - 1];
+            for (int c = lvl[l]; c < lvl[l + 1]; ++c) {
+                while (rng[p].y <= rng[c].x) ++p;
+                parent[c] = p;
+                if (kids[p].y == 0) kids[p] = make_int2(c, c + 1);
+                else kids[p].y = c + 1;
+            }
+        }
+        std::vector<CellHash> hash(L + 1);
+        for (int l = 0; l <= L; ++l)
+            hash[l].build(pk.data() + lvl[l], lvl[l + 1] - lvl[l], lvl[l]);
+        auto find = [&](int l, int x, int y, int z) -> int { return hash[l].get(l, x, y, z); };
+        auto adjacent = [&](int c1, int c2) {
+            return std::abs(cc[c1].x - cc[c2].x) <= 1 && std::abs(cc[c1].y - cc[c2].y) <= 1 &&
+                   std::abs(cc[c1].z - cc[c2].z) <= 1;
+        };
+        // interaction lists (levels 2..L) and the adjacent leaves
+        std::vector<int> il_ptr(ncell + 1, 0), il;
+        for (int c = 0; c < ncell; ++c) {
+            const int l = cc[c].w;
+            if (l >= 2) {
+                const int4 pc = cc[parent[c]];
+                for (int dx = -1; dx <= 1; ++dx)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dz = -1; dz <= 1; ++dz) {
+                            const int q = find(l - 1, pc.x + dx, pc.y + dy, pc.z + dz);
+                            if (q < 0) continue;
+                            for (int ch = kids[q].x; ch < kids[q].y; ++ch)
+                                if (!adjacent(ch, c)) il.push_back(ch);
+                        }
+            }
+            il_ptr[c + 1] = (int)il.size();
+        }
+        const int leaf0 = lvl[L], nleaf = lvl[L + 1] - lvl[L];
+        std::vector<int> near_ptr(nleaf + 1, 0), nearl;
+        std::vector<int2> work;
+        for (int c = leaf0; c < leaf0 + nleaf; ++c) {
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int q = find(L, cc[c].x + dx, cc[c].y + dy, cc[c].z + dz);
+                        if (q >= 0) nearl.push_back(q);
+                    }
+            near_ptr[c - leaf0 + 1] = (int)nearl.size();
+            for (int k0 = rng[c].x; k0 < rng[c].y; k0 += kNearBlock) work.push_back(make_int2(c, k0));
+        }
+        // every target sees every source exactly once: the adjacent leaves and the
+        // interaction lists of its ancestors hold N blobs between them, and every
+        // index handed to a kernel is in range
+        for (int c = leaf0; c < leaf0 + nleaf; ++c) {
+            int64_t cnt = 0;
+            for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e) {
+                const int q = nearl[e];
+                if (q < leaf0 || q >= leaf0 + nleaf) {
+                    *msg = "fast product: internal error (near list)";
+                    return ARB_E_ARG;
+                }
+                cnt += rng[q].y - rng[q].x;
+            }
+            for (int a2 = c; a2 >= 0 && cc[a2].w >= 2; a2 = parent[a2])
+                for (int e = il_ptr[a2]; e < il_ptr[a2 + 1]; ++e) cnt += rng[il[e]].y - rng[il[e]].x;
+            if (cnt != N) {
+                *msg = "fast product: internal error (cells do not partition the blobs)";
+                return ARB_E_ARG;
+            }
+        }
+        q.L = L;
+        q.ncell = ncell;
+        q.nleaf = nleaf;
+        q.n_near_pairs = 0;
+        for (int c = leaf0; c < leaf0 + nleaf; ++c)
+            for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e)
+                q.n_near_pairs +=
+                    (int64_t)(rng[c].y - rng[c].x) * (rng[nearl[e]].y - rng[nearl[e]].x);
+        q.lvl = std::move(lvl);
+        q.cc = std::move(cc);
+        q.rng = std::move(rng);
+        q.parent = std::move(parent);
+        q.kids = std::move(kids);
+        q.il_ptr = std::move(il_ptr);
+        q.il = std::move(il);
+        q.near_ptr = std::move(near_ptr);
+        q.nearl = std::move(nearl);
+        q.work = std::move(work);
+        return 0;
+    };
     // leaf level
-    const int leaf_target = leaf > 0 ? leaf : 2 * P;
-    int L;
+    int rc;
     if (Lhi < 2) {
-        L = 0;
+        rc = build(0, pl);
     } else if (levels > 0) {
-        L = levels < 2 ? 0 : std::min(levels, Lhi);
-    } else {
-        L = Lhi;
+        rc = build(levels < 2 ? 0 : std::min(levels, Lhi), pl);
+    } else if (leaf > 0) {
+        // the shallowest level whose mean occupancy is at most `leaf`
+        int L = Lhi;
         int64_t cells = 1;
         for (int l = 1; l <= Lhi; ++l) {
             cells += new_at[l];
-            if (l >= 2 && (int64_t)N <= (int64_t)leaf_target * cells) {
+            if (l >= 2 && (int64_t)N <= (int64_t)leaf * cells) {
                 L = l;
                 break;
             }
         }
-    }
-    // cells of every level in Morton order, with their blob ranges
-    std::vector<std::vector<int>> starts(L + 1, std::vector<int>(1, 0));
-    for (int j = 1; j < N; ++j)
-        for (int l = first[j]; l <= L; ++l) starts[l].push_back(j);
-    std::vector<int4> cc;
-    std::vector<int2> rng;
-    std::vector<uint64_t> pk;
-    std::vector<int> lvl(L + 2, 0);
-    for (int l = 0; l <= L; ++l) {
-        lvl[l] = (int)cc.size();
-        const int sh = 3 * (Lhi - l), dl = Lhi - l;
-        const std::vector<int> &st = starts[l];
-        for (size_t t = 0; t < st.size(); ++t) {
-            const int j = st[t], e = t + 1 < st.size() ? st[t + 1] : N;
-            const int i0 = idx[j];
-            cc.push_back(make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
-                                   crd[3 * (size_t)i0 + 2] >> dl, l));
-            rng.push_back(make_int2(j, e));
-            pk.push_back(key[j] >> sh);
-        }
-    }
-    lvl[L + 1] = (int)cc.size();
-    const int ncell = (int)cc.size();
-    std::vector<int> parent(ncell, -1);
-    std::vector<int2> kids(ncell, make_int2(0, 0));
-    for (int l = 1; l <= L; ++l) {
-        int p = lvl[l - 1];
-        for (int c = lvl[l]; c < lvl[l + 1]; ++c) {
-            while (rng[p].y <= rng[c].x) ++p;
-            parent[c] = p;
-            if (kids[p].y == 0) kids[p] = make_int2(c, c + 1);
-            else kids[p].y = c + 1;
-        }
-    }
-    auto find = [&](int l, int x, int y, int z) -> int {
-        const int lim = 1 << l;
-        if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
-        const uint64_t key = morton(x, y, z);
-        auto b = pk.begin() + lvl[l], e = pk.begin() + lvl[l + 1];
-        auto it = std::lower_bound(b, e, key);
-        return (it != e && *it == key) ? (int)(it - pk.begin()) : -1;
-    };
-    auto adjacent = [&](int c1, int c2) {
-        return std::abs(cc[c1].x - cc[c2].x) <= 1 && std::abs(cc[c1].y - cc[c2].y) <= 1 &&
-               std::abs(cc[c1].z - cc[c2].z) <= 1;
-    };
-    // interaction lists (levels 2..L) and the adjacent leaves
-    std::vector<int> il_ptr(ncell + 1, 0), il;
-    for (int c = 0; c < ncell; ++c) {
-        const int l = cc[c].w;
-        if (l >= 2) {
-            const int4 pc = cc[parent[c]];
-            for (int dx = -1; dx <= 1; ++dx)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dz = -1; dz <= 1; ++dz) {
-                        const int q = find(l - 1, pc.x + dx, pc.y + dy, pc.z + dz);
-                        if (q < 0) continue;
-                        for (int ch = kids[q].x; ch < kids[q].y; ++ch)
-                            if (!adjacent(ch, c)) il.push_back(ch);
-                    }
-        }
-        il_ptr[c + 1] = (int)il.size();
-    }
-    const int leaf0 = lvl[L], nleaf = lvl[L + 1] - lvl[L];
-    std::vector<int> near_ptr(nleaf + 1, 0), nearl;
-    std::vector<int2> work;
-    for (int c = leaf0; c < leaf0 + nleaf; ++c) {
-        for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dz = -1; dz <= 1; ++dz) {
-                    const int q = find(L, cc[c].x + dx, cc[c].y + dy, cc[c].z + dz);
-                    if (q >= 0) nearl.push_back(q);
-                }
-        near_ptr[c - leaf0 + 1] = (int)nearl.size();
-        for (int k0 = rng[c].x; k0 < rng[c].y; k0 += kNearBlock) work.push_back(make_int2(c, k0));
-    }
-    // every target sees every source exactly once: the adjacent leaves and the
-    // interaction lists of its ancestors hold N blobs between them, and every
-    // index handed to a kernel is in range
-    for (int c = leaf0; c < leaf0 + nleaf; ++c) {
-        int64_t cnt = 0;
-        for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e) {
-            const int q = nearl[e];
-            if (q < leaf0 || q >= leaf0 + nleaf) {
-                *msg = "fast product: internal error (near list)";
-                return ARB_E_ARG;
+        rc = build(L, pl);
+    } else {
+        // the level with the fewest pair evaluations: deeper from level 2 while
+        // the count falls.  Counted level by level (the interaction lists of the
+        // shallower levels are the same for every leaf level), then built once.
+        auto cells_of = [&](int l, std::vector<int4> &c4, std::vector<int2> &r2,
+                            std::vector<uint64_t> &k) {
+            c4.clear();
+            r2.clear();
+            k.clear();
+            const int sh = 3 * (Lhi - l), dl = Lhi - l;
+            for (int j0 = 0, j = 1; j <= N; ++j) {
+                if (j < N && first[j] > l) continue;
+                const int i0 = idx[j0];
+                c4.push_back(make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
+                                       crd[3 * (size_t)i0 + 2] >> dl, l));
+                r2.push_back(make_int2(j0, j));
+                k.push_back(key[j0] >> sh);
+                j0 = j;
             }
-            cnt += rng[q].y - rng[q].x;
+        };
+        std::vector<int4> pc, cc2;
+        std::vector<int2> pr, rr;
+        std::vector<uint64_t> pk2, kk2;
+        CellHash ph, ch;
+        cells_of(1, pc, pr, pk2);
+        ph.build(pk2.data(), (int)pk2.size(), 0);
+        int64_t il_total = 0, best = -1;
+        int L = 2;
+        for (int l = 2; l <= Lhi; ++l) {
+            cells_of(l, cc2, rr, kk2);
+            ch.build(kk2.data(), (int)kk2.size(), 0);
+            // children of each parent (contiguous) and the parent of each cell
+            std::vector<int2> kid(pc.size());
+            std::vector<int> par(cc2.size());
+            for (size_t p = 0, c = 0; p < pc.size(); ++p) {
+                const size_t c0 = c;
+                while (c < cc2.size() && rr[c].x < pr[p].y) par[c++] = (int)p;
+                kid[p] = make_int2((int)c0, (int)c);
+            }
+            for (size_t c = 0; c < cc2.size(); ++c) {
+                const int4 q = pc[par[c]];
+                for (int dx = -1; dx <= 1; ++dx)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dz = -1; dz <= 1; ++dz) {
+                            const int g = ph.get(l - 1, q.x + dx, q.y + dy, q.z + dz);
+                            if (g < 0) continue;
+                            for (int ch = kid[g].x; ch < kid[g].y; ++ch)
+                                il_total += std::abs(cc2[ch].x - cc2[c].x) > 1 ||
+                                            std::abs(cc2[ch].y - cc2[c].y) > 1 ||
+                                            std::abs(cc2[ch].z - cc2[c].z) > 1;
+                        }
+            }
+            int64_t near_pairs = 0;
+            for (size_t c = 0; c < cc2.size(); ++c) {
+                int64_t adj = 0;
+                for (int dx = -1; dx <= 1; ++dx)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dz = -1; dz <= 1; ++dz) {
+                            const int g = ch.get(l, cc2[c].x + dx, cc2[c].y + dy, cc2[c].z + dz);
+                            if (g >= 0) adj += rr[g].y - rr[g].x;
+                        }
+                near_pairs += adj * (rr[c].y - rr[c].x);
+            }
+            const int64_t cl = near_pairs + il_total * P * P;
+            if (best >= 0 && cl >= best) break;
+            best = cl;
+            L = l;
+            pc.swap(cc2);
+            pr.swap(rr);
+            pk2.swap(kk2);
+            std::swap(ph, ch);
         }
-        for (int a2 = c; a2 >= 0 && cc[a2].w >= 2; a2 = parent[a2])
-            for (int e = il_ptr[a2]; e < il_ptr[a2 + 1]; ++e) cnt += rng[il[e]].y - rng[il[e]].x;
-        if (cnt != N) {
-            *msg = "fast product: internal error (cells do not partition the blobs)";
-            return ARB_E_ARG;
-        }
+        rc = build(L, pl);
     }
+    if (rc) return rc;
     // Chebyshev points, Lagrange denominators, parent polynomials at child proxies
     std::vector<float> tab(kTabSize, 0.f);
     double xn[kFmmMaxOrder];
@@ -937,32 +1068,13 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                     if (j != k) p *= (u - xn[j]) / (xn[k] - xn[j]);
                 tab[kTabT1 + (sg * kFmmMaxOrder + k) * kFmmMaxOrder + m] = (float)p;
             }
-    std::vector<int> &perm = idx;  // sorted position -> blob
     pl.n = n;
     pl.P = P;
-    pl.L = L;
     pl.o[0] = o[0];
     pl.o[1] = o[1];
     pl.o[2] = o[2];
     pl.S = S;
-    pl.ncell = ncell;
-    pl.nleaf = nleaf;
-    pl.n_near_pairs = 0;
-    for (int c = leaf0; c < leaf0 + nleaf; ++c)
-        for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e)
-            pl.n_near_pairs +=
-                (int64_t)(rng[c].y - rng[c].x) * (rng[nearl[e]].y - rng[nearl[e]].x);
-    pl.perm = std::move(perm);
-    pl.lvl = std::move(lvl);
-    pl.cc = std::move(cc);
-    pl.rng = std::move(rng);
-    pl.parent = std::move(parent);
-    pl.kids = std::move(kids);
-    pl.il_ptr = std::move(il_ptr);
-    pl.il = std::move(il);
-    pl.near_ptr = std::move(near_ptr);
-    pl.nearl = std::move(nearl);
-    pl.work = std::move(work);
+    pl.perm = std::move(idx);  // sorted position -> blob
     pl.tab = std::move(tab);
     return 0;
 }

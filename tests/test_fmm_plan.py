@@ -68,15 +68,43 @@ def test_plan_matches_the_definitions(N, box, L):
     assert st["m2l_pairs"] == inter * n ** 6
 
 
+def fewest_pairs_level(pos, a, n):
+    """The documented default: from level 2, one level deeper while the pair
+    evaluations per product (direct pairs + n^6 per interaction-list entry)
+    fall."""
+    Lhi = min(fastsum.max_level(pos, a), 16)
+    if Lhi < 2:
+        return 0
+    cost = lambda lev: counts(pos, a, n, lev)[2] + counts(pos, a, n, lev)[3] * n ** 6  # noqa
+    L, best = 2, cost(2)
+    for lev in range(3, Lhi + 1):
+        c = cost(lev)
+        if c >= best:
+            break
+        L, best = lev, c
+    return L
+
+
 @pytest.mark.parametrize("N,box", SHAPES)
-@pytest.mark.parametrize("leaf", [0, 16, 100])
-def test_automatic_level(N, box, leaf):
+@pytest.mark.parametrize("leaf", [16, 100])
+def test_level_from_occupancy(N, box, leaf):
     pos = blobs(N, box, 3 * N + leaf)
     n = 3
     st = arb.arb_fmm_plan(pos, 1.0, order=n, leaf=leaf)
-    L = auto_level(pos, 1.0, leaf if leaf else 2 * n ** 3)
+    L = auto_level(pos, 1.0, leaf)
     assert st["levels"] == L
     assert st["cells"] == counts(pos, 1.0, n, L)[0]
+
+
+@pytest.mark.parametrize("N,box", SHAPES)
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_default_level_has_the_fewest_pair_evaluations(N, box, n):
+    pos = blobs(N, box, 5 * N + n)
+    st = arb.arb_fmm_plan(pos, 1.0, order=n)
+    L = fewest_pairs_level(pos, 1.0, n)
+    assert st["levels"] == L
+    cells, leaves, near, inter = counts(pos, 1.0, n, L)
+    assert (st["cells"], st["near_pairs"], st["interactions"]) == (cells, near, inter)
 
 
 def test_degenerate_inputs():
