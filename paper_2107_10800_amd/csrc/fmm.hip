@@ -17,24 +17,30 @@
 //   lies at level l in the cell floor(((x - o) / S) 2^l); cells of one level are
 //   adjacent when their coordinates differ by at most 1 per direction.  Leaf
 //   level L: fixed by the options, or the shallowest level whose mean
-//   occupancy is at most the requested blobs per leaf, never deeper than the
-//   deepest level with a cell side >= 2a (so every interpolated pair has
-//   r > 2a and stays off the overlap branch of the tensor).  Interaction list
-//   of a cell at level l >= 2: the non-empty cells whose parent is adjacent to
-//   its parent and which are not adjacent to it.
+//   occupancy is at most the requested blobs per leaf, or by default the level
+//   with the fewest pair evaluations per product (direct pairs plus n^6 per
+//   interaction-list entry, counted level by level from level 2 while they
+//   fall); never deeper than the deepest level with a cell side >= 2a (so every
+//   interpolated pair has r > 2a and stays off the overlap branch of the
+//   tensor).  Interaction list of a cell at level l >= 2: the non-empty cells
+//   whose parent is adjacent to its parent and which are not adjacent to it.
 // Per product (all on the GPU, sorted by Morton key):
 //   P2M  qhat^c_m = sum_{j in c} S^c_m(y_j) lam_j at the leaves;
 //   M2M  the parent's qhat from its children's proxies (exact: the parent's
 //        Lagrange polynomials have degree n-1 and the children interpolate
 //        them exactly);
 //   M2L  v^c_k = sum_{c' in IL(c)} sum_m M(t^c_k, s^c'_m) qhat^c'_m, matrix-free
-//        with the FP32 pair function (one workgroup per cell, one lane per
-//        target proxy, the source proxies of each listed cell staged in LDS);
+//        with the FP32 pair function (one workgroup per cell, lane groups of
+//        one lane per target proxy taking listed cells in turn, the source
+//        proxies of each listed cell staged in LDS);
 //   L2L  the children's v gain the parent's interpolant at their proxies;
 //   near + L2P  direct sums over the adjacent leaves (hi/lo split positions,
 //        float runs promoted to double, as in the dense FP32 kernel) plus
 //        sum_k S^leaf_k(x_i) v^leaf_k, written in the original blob order.
 // With L <= 1 there is no interaction list: one cell, the direct sum.
+// Single-blob bodies (Sec. 2.4): the generalised tensor, with the forces and
+// the torques / a in two channels through P2M, M2M and L2L; M2L and the near
+// field apply the 6 x 6 tensor between them.
 // Two arithmetic variants share the tree and the float-rounded kernel values
 // and weights: A = float (lambda, qhat and the runs of sums in float) and
 // A = double (lambda, qhat and every sum in double).  The second is linear in
