@@ -131,6 +131,18 @@ __device__ __forceinline__ void load_tab(const float *__restrict__ g, float *tab
     __syncthreads();
 }
 
+// the item of this workgroup when the launch has round_up(items, 8 kXcdChunk)
+// workgroups: consecutive workgroups are dealt round-robin to the 8 XCDs, so
+// this gives each XCD runs of kXcdChunk consecutive items (neighbouring cells in
+// Morton order, which read the same leaves and multipole weights, share its
+// L2), the runs dealt round-robin to keep the XCDs' loads even; -1 past the end
+constexpr int kXcdChunk = 16;
+__device__ __forceinline__ int xcd_item(int items) {
+    const int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int it = (j / kXcdChunk) * 8 * kXcdChunk + x * kXcdChunk + j % kXcdChunk;
+    return it < items ? it : -1;
+}
+
 // Lagrange polynomial l_k(u) at the Chebyshev points (product form)
 __device__ __forceinline__ float lag(const float *tab, int n, int k, float u) {
     float p = tab[kTabDen + k];
@@ -275,8 +287,10 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *_
 template <bool WALL, class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
-    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int groups,
+    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int items, int groups,
     const Vec4<A> *__restrict__ qhat, double *__restrict__ v) {
+    const int item = xcd_item(items);
+    if (item < 0) return;
     // LDS sized by the host (m2l_lds_bytes): multipole weights of `groups`
     // listed cells, the level's proxy offsets, the groups' sums, the table
     extern __shared__ __align__(16) unsigned char lds[];
@@ -287,7 +301,7 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     double *s_acc = reinterpret_cast<double *>(s_off + P);
     float *tab = reinterpret_cast<float *>(s_acc + 3 * (GP - P));
     load_tab(tabg, tab);
-    const int c = cell0 + blockIdx.x;
+    const int c = cell0 + item;
     const int tid = threadIdx.x;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
@@ -406,15 +420,17 @@ template <bool WALL, class A>
 __global__ __launch_bounds__(kNearBlock) void fmm_near_kernel(
     Geo g, const float *__restrict__ tabg, int N, int far, const int4 *__restrict__ cc,
     const int2 *__restrict__ rng, const int *__restrict__ near_ptr, const int *__restrict__ near,
-    int leaf0, const int2 *__restrict__ work, const int *__restrict__ perm,
+    int leaf0, const int2 *__restrict__ work, int items, const int *__restrict__ perm,
     const float4 *__restrict__ shi, const float4 *__restrict__ slo,
     const Vec4<A> *__restrict__ slam, const double *__restrict__ v, double *__restrict__ partial) {
+    const int item = xcd_item(items);
+    if (item < 0) return;
     __shared__ float tab[kTabSize];
     __shared__ float4 s_hi[kNearBlock], s_lo[kNearBlock];
     __shared__ Vec4<A> s_lam[kNearBlock];
     load_tab(tabg, tab);
     const int tid = threadIdx.x;
-    const int2 wk = work[blockIdx.x];
+    const int2 wk = work[item];
     const int c = wk.x;
     const int2 tr = rng[c];
     const int i = wk.y + tid;
@@ -528,9 +544,11 @@ __device__ __forceinline__ void rot_acc(float dx, float dy, float dz, float r2, 
 template <class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
-    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int groups,
+    const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int items, int groups,
     const Vec4<A> *__restrict__ qf, const Vec4<A> *__restrict__ qt, double *__restrict__ vu,
     double *__restrict__ vw) {
+    const int item = xcd_item(items);
+    if (item < 0) return;
     extern __shared__ __align__(16) unsigned char lds[];
     const int n = g.n, P = g.P;
     const int GP = groups * P;  // <= kFmmMaxP
@@ -540,7 +558,7 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     double *s_acc = reinterpret_cast<double *>(s_off + P);
     float *tab = reinterpret_cast<float *>(s_acc + 6 * (GP - P));
     load_tab(tabg, tab);
-    const int c = cell0 + blockIdx.x;
+    const int c = cell0 + item;
     const int tid = threadIdx.x;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
@@ -613,16 +631,18 @@ template <class A>
 __global__ __launch_bounds__(kNearBlock) void fmm_near6_kernel(
     Geo g, const float *__restrict__ tabg, int M, int far, const int4 *__restrict__ cc,
     const int2 *__restrict__ rng, const int *__restrict__ near_ptr, const int *__restrict__ near,
-    int leaf0, const int2 *__restrict__ work, const int *__restrict__ perm,
+    int leaf0, const int2 *__restrict__ work, int items, const int *__restrict__ perm,
     const float4 *__restrict__ shi, const float4 *__restrict__ slo, const Vec4<A> *__restrict__ sf,
     const Vec4<A> *__restrict__ st, const double *__restrict__ vu, const double *__restrict__ vw,
     double *__restrict__ partial) {
+    const int item = xcd_item(items);
+    if (item < 0) return;
     __shared__ float tab[kTabSize];
     __shared__ float4 s_hi[kNearBlock], s_lo[kNearBlock];
     __shared__ Vec4<A> s_f[kNearBlock], s_t[kNearBlock];
     load_tab(tabg, tab);
     const int tid = threadIdx.x;
-    const int2 wk = work[blockIdx.x];
+    const int2 wk = work[item];
     const int c = wk.x;
     const int2 tr = rng[c];
     const int i = wk.y + tid;
@@ -1188,16 +1208,18 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
         const size_t lds = (size_t)groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
                            (size_t)3 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
-        fmm_m2l_kernel<WALL, A><<<F.lvl[L + 1] - F.lvl[2], round_up(groups * P, kWave), lds, s>>>(
-            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], groups, qhat,
-            F.v.as<double>());
+        const int nc = F.lvl[L + 1] - F.lvl[2];
+        fmm_m2l_kernel<WALL, A><<<round_up(nc, 8 * kXcdChunk), round_up(groups * P, kWave), lds, s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc, groups,
+            qhat, F.v.as<double>());
         for (int l = 3; l <= L; ++l)
             fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
                 g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], F.v.as<double>());
     }
-    fmm_near_kernel<WALL, A><<<F.nwork, kNearBlock, 0, s>>>(
+    fmm_near_kernel<WALL, A><<<round_up(F.nwork, 8 * kXcdChunk), kNearBlock, 0, s>>>(
         g, tab, N, L >= 2 ? 1 : 0, F.cc.as<int4>(), F.rng.as<int2>(), F.near_ptr.as<int>(),
-        F.nearl.as<int>(), F.lvl[L], F.work.as<int2>(), F.perm.as<int>(), F.shi.as<float4>(),
+        F.nearl.as<int>(), F.lvl[L], F.work.as<int2>(), F.nwork, F.perm.as<int>(),
+        F.shi.as<float4>(),
         F.slo.as<float4>(), slam, F.v.as<double>(), partial);
 }
 
@@ -1243,17 +1265,19 @@ void fmm_run6(const FmmState &F, hipStream_t s, const double *x6, double inv_a, 
         const size_t lds = (size_t)2 * groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
                            (size_t)6 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
-        fmm_m2l6_kernel<A><<<F.lvl[L + 1] - F.lvl[2], round_up(groups * P, kWave), lds, s>>>(
-            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], groups, qf, qt,
-            vu, vw);
+        const int nc = F.lvl[L + 1] - F.lvl[2];
+        fmm_m2l6_kernel<A><<<round_up(nc, 8 * kXcdChunk), round_up(groups * P, kWave), lds, s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc, groups,
+            qf, qt, vu, vw);
         for (int l = 3; l <= L; ++l)
             for (int ch = 0; ch < 2; ++ch)
                 fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
                     g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], ch ? vw : vu);
     }
-    fmm_near6_kernel<A><<<F.nwork, kNearBlock, 0, s>>>(
+    fmm_near6_kernel<A><<<round_up(F.nwork, 8 * kXcdChunk), kNearBlock, 0, s>>>(
         g, tab, M, L >= 2 ? 1 : 0, F.cc.as<int4>(), F.rng.as<int2>(), F.near_ptr.as<int>(),
-        F.nearl.as<int>(), F.lvl[L], F.work.as<int2>(), F.perm.as<int>(), F.shi.as<float4>(),
+        F.nearl.as<int>(), F.lvl[L], F.work.as<int2>(), F.nwork, F.perm.as<int>(),
+        F.shi.as<float4>(),
         F.slo.as<float4>(), sf, st, vu, vw, partial);
 }
 
