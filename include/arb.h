@@ -147,7 +147,9 @@ typedef struct {
     int       leaves;       /* non-empty leaves                                  */
     long long near_pairs;   /* ordered blob pairs summed directly per product    */
     long long interactions; /* interaction-list entries (cell pairs)             */
-    long long m2l_pairs;    /* proxy pairs evaluated per product: entries * n^6  */
+    long long m2l_pairs;    /* M2L pairs evaluated per product: n^3 per proxy of */
+                            /* each listed cell, or per blob when it holds fewer */
+                            /* blobs than proxies                                */
     double    build_ms;     /* host time of the last tree build (incl. copies)   */
 } arb_fmm_stats;
 

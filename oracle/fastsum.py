@@ -36,7 +36,9 @@ Definitions (units of length; the library uses the same ones):
                   sum_m M(t^c_k, s^{c'}_m) qhat^{c'}_m,
         qhat^{c'}_m = sum_{j in c'} S^{c'}_m(y_j) lam_j,
     with c = c_l(i) the level-l cell of blob i, t^c the proxy points of c and
-    s^{c'} those of c'.  Each source is counted once for each target: the
+    s^{c'} those of c'; a listed cell c' holding fewer blobs than proxies
+    (|c'| < n^3) enters with its blobs instead: sum_{j in c'} M(t^c_k, y_j)
+    lam_j (exact in the source argument, and cheaper).  Each source is counted once for each target: the
     adjacent leaves and the interaction lists of the ancestors partition the
     blobs.  With L <= 1 there is no interaction list and the product is the
     direct sum.  A leaf side of at least 2a keeps every interpolated pair out of
@@ -141,8 +143,11 @@ def fmm_apply(pos, lam, a, eta, wall, n, L, kernel=None):
             if not len(il):
                 continue
             t = proxies(n, centre[c], w)
-            s = np.concatenate([proxies(n, centre[d], w) for d in il])
-            q = np.concatenate([qhat[d] for d in il])
+            # sparse listed cells enter with their blobs, the others with proxies
+            s = np.concatenate([pos[members[d]] if len(members[d]) < n ** 3
+                                else proxies(n, centre[d], w) for d in il])
+            q = np.concatenate([lam[members[d]] if len(members[d]) < n ** 3 else qhat[d]
+                                for d in il])
             v = np.einsum("tsij,sj->ti", kernel(t[:, None, :], s[None, :, :]), q)
             out[members[c]] += weights(n, pos[members[c]], centre[c], w) @ v
     return out

@@ -1322,7 +1322,7 @@ int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out) {
     out->leaves = F.nleaf;
     out->near_pairs = F.n_near_pairs;
     out->interactions = F.n_il;
-    out->m2l_pairs = F.n_il * (long long)F.P * F.P;
+    out->m2l_pairs = F.n_m2l_pairs;
     out->build_ms = F.build_ms;
     return ARB_OK;
 }

@@ -80,6 +80,7 @@ struct FmmState {
         qhat, v, slam2, qhat2, v2;  // second channel: the torques of single-blob bodies
     int N = 0, L = 0, n = 0, P = 0, ncell = 0, nleaf = 0, nwork = 0, channels = 1;
     int64_t n_il = 0, n_near_pairs = 0;  // interaction-list entries, direct pairs
+    int64_t n_m2l_pairs = 0;             // M2L pair evaluations per product
     std::vector<int> lvl;
     double o[3] = {0.0, 0.0, 0.0}, S = 0.0;  // root cube in units of a
     long long version = 0;                   // bumped by every build

@@ -288,29 +288,24 @@ template <bool WALL, class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
     const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int items, int groups,
-    const Vec4<A> *__restrict__ qhat, double *__restrict__ v) {
+    const int2 *__restrict__ rng, const float4 *__restrict__ shi, const float4 *__restrict__ slo,
+    const Vec4<A> *__restrict__ slam, const Vec4<A> *__restrict__ qhat, double *__restrict__ v) {
     const int item = xcd_item(items);
     if (item < 0) return;
-    // LDS sized by the host (m2l_lds_bytes): multipole weights of `groups`
-    // listed cells, the level's proxy offsets, the groups' sums, the table
+    // LDS sized by the host: the sources of `groups` listed cells (offsets from
+    // the cell's centre and charges), the groups' sums, the table
     extern __shared__ __align__(16) unsigned char lds[];
     const int n = g.n, P = g.P;
     const int GP = groups * P;  // <= kFmmMaxP
     Vec4<A> *s_q = reinterpret_cast<Vec4<A> *>(lds);
     float4 *s_off = reinterpret_cast<float4 *>(s_q + GP);
-    double *s_acc = reinterpret_cast<double *>(s_off + P);
+    double *s_acc = reinterpret_cast<double *>(s_off + GP);
     float *tab = reinterpret_cast<float *>(s_acc + 3 * (GP - P));
     load_tab(tabg, tab);
     const int c = cell0 + item;
     const int tid = threadIdx.x;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
-    // proxy offsets w xi of this level (the same for every cell of it)
-    for (int m = tid; m < P; m += blockDim.x) {
-        const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
-        s_off[m] = make_float4((float)(w * tab[kTabNode + mx]), (float)(w * tab[kTabNode + my]),
-                               (float)(w * tab[kTabNode + mz]), 0.f);
-    }
     const bool act = tid < GP;
     const int gi = act ? tid / P : 0;
     const int k = act ? tid - gi * P : 0;
@@ -324,25 +319,50 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     const int e1 = il_ptr[c + 1];
     for (int e0 = il_ptr[c]; e0 < e1; e0 += groups) {
         __syncthreads();
+        // a listed cell with fewer blobs than proxies enters with its blobs,
+        // the others with their proxies (offsets w xi) and multipole weights
         for (int t = tid; t < GP; t += blockDim.x) {
-            const int gg = t / P;
-            if (e0 + gg < e1) s_q[t] = qhat[(size_t)il[e0 + gg] * P + (t - gg * P)];
+            const int gg = t / P, m = t - gg * P;
+            if (e0 + gg >= e1) continue;
+            const int sc = il[e0 + gg];
+            const int2 r = rng[sc];
+            if (r.y - r.x < P) {
+                if (m < r.y - r.x) {
+                    const int4 cs = cc[sc];
+                    const F2 cx = split(centre(g.ox, side, cs.x)),
+                             cy = split(centre(g.oy, side, cs.y)),
+                             cz = split(centre(g.oz, side, cs.z));
+                    const float4 h = shi[r.x + m], l = slo[r.x + m];
+                    s_off[t] = make_float4((h.x - cx.h) + (l.x - cx.l), (h.y - cy.h) + (l.y - cy.l),
+                                           (h.z - cz.h) + (l.z - cz.l), 0.f);
+                    s_q[t] = slam[r.x + m];
+                }
+            } else {
+                const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
+                s_off[t] = make_float4((float)(w * tab[kTabNode + mx]),
+                                       (float)(w * tab[kTabNode + my]),
+                                       (float)(w * tab[kTabNode + mz]), 0.f);
+                s_q[t] = qhat[(size_t)sc * P + m];
+            }
         }
         __syncthreads();
         const int e = e0 + gi;
         if (!act || e >= e1) continue;
-        const int4 cs = cc[il[e]];
+        const int sc = il[e];
+        const int4 cs = cc[sc];
+        const int cnt = min(P, rng[sc].y - rng[sc].x);
         // target proxy minus source cell centre, from the integer offset
         const float ax = (float)((double)(ct.x - cs.x) * side) + okx;
         const float ay = (float)((double)(ct.y - cs.y) * side) + oky;
         const float az = (float)((double)(ct.z - cs.z) * side) + okz;
         const float zc = (float)centre(g.oz, side, cs.z);
+        const float4 *so = s_off + gi * P;
         const Vec4<A> *sq = s_q + gi * P;
-        for (int m0 = 0; m0 < P; m0 += kFmmRun) {
-            const int m1 = min(m0 + kFmmRun, P);
+        for (int m0 = 0; m0 < cnt; m0 += kFmmRun) {
+            const int m1 = min(m0 + kFmmRun, cnt);
             A fx = 0, fy = 0, fz = 0;
             for (int m = m0; m < m1; ++m) {
-                const float4 o = s_off[m];
+                const float4 o = so[m];
                 const Vec4<A> q = sq[m];
                 const float dx = ax - o.x, dy = ay - o.y, dz = az - o.z;
                 const float dxy2 = fmaf(dx, dx, dy * dy);
@@ -545,6 +565,8 @@ template <class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
     const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int items, int groups,
+    const int2 *__restrict__ rng, const float4 *__restrict__ shi, const float4 *__restrict__ slo,
+    const Vec4<A> *__restrict__ sf, const Vec4<A> *__restrict__ st,
     const Vec4<A> *__restrict__ qf, const Vec4<A> *__restrict__ qt, double *__restrict__ vu,
     double *__restrict__ vw) {
     const int item = xcd_item(items);
@@ -555,18 +577,13 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     Vec4<A> *s_qf = reinterpret_cast<Vec4<A> *>(lds);
     Vec4<A> *s_qt = s_qf + GP;
     float4 *s_off = reinterpret_cast<float4 *>(s_qt + GP);
-    double *s_acc = reinterpret_cast<double *>(s_off + P);
+    double *s_acc = reinterpret_cast<double *>(s_off + GP);
     float *tab = reinterpret_cast<float *>(s_acc + 6 * (GP - P));
     load_tab(tabg, tab);
     const int c = cell0 + item;
     const int tid = threadIdx.x;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
-    for (int m = tid; m < P; m += blockDim.x) {
-        const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
-        s_off[m] = make_float4((float)(w * tab[kTabNode + mx]), (float)(w * tab[kTabNode + my]),
-                               (float)(w * tab[kTabNode + mz]), 0.f);
-    }
     const bool act = tid < GP;
     const int gi = act ? tid / P : 0;
     const int k = act ? tid - gi * P : 0;
@@ -577,10 +594,30 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     const int e1 = il_ptr[c + 1];
     for (int e0 = il_ptr[c]; e0 < e1; e0 += groups) {
         __syncthreads();
+        // sparse listed cells enter with their bodies, the others with proxies
         for (int t = tid; t < GP; t += blockDim.x) {
-            const int gg = t / P;
-            if (e0 + gg < e1) {
-                const size_t q = (size_t)il[e0 + gg] * P + (t - gg * P);
+            const int gg = t / P, m = t - gg * P;
+            if (e0 + gg >= e1) continue;
+            const int sc = il[e0 + gg];
+            const int2 r = rng[sc];
+            if (r.y - r.x < P) {
+                if (m < r.y - r.x) {
+                    const int4 cs = cc[sc];
+                    const F2 cx = split(centre(g.ox, side, cs.x)),
+                             cy = split(centre(g.oy, side, cs.y)),
+                             cz = split(centre(g.oz, side, cs.z));
+                    const float4 h = shi[r.x + m], l = slo[r.x + m];
+                    s_off[t] = make_float4((h.x - cx.h) + (l.x - cx.l), (h.y - cy.h) + (l.y - cy.l),
+                                           (h.z - cz.h) + (l.z - cz.l), 0.f);
+                    s_qf[t] = sf[r.x + m];
+                    s_qt[t] = st[r.x + m];
+                }
+            } else {
+                const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
+                s_off[t] = make_float4((float)(w * tab[kTabNode + mx]),
+                                       (float)(w * tab[kTabNode + my]),
+                                       (float)(w * tab[kTabNode + mz]), 0.f);
+                const size_t q = (size_t)sc * P + m;
                 s_qf[t] = qf[q];
                 s_qt[t] = qt[q];
             }
@@ -588,18 +625,21 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
         __syncthreads();
         const int e = e0 + gi;
         if (!act || e >= e1) continue;
-        const int4 cs = cc[il[e]];
+        const int sc = il[e];
+        const int4 cs = cc[sc];
+        const int cnt = min(P, rng[sc].y - rng[sc].x);
         const float ax = (float)((double)(ct.x - cs.x) * side) + okx;
         const float ay = (float)((double)(ct.y - cs.y) * side) + oky;
         const float az = (float)((double)(ct.z - cs.z) * side) + okz;
-        const Vec4<A> *sf = s_qf + gi * P, *st = s_qt + gi * P;
-        for (int m0 = 0; m0 < P; m0 += kFmmRun) {
-            const int m1 = min(m0 + kFmmRun, P);
+        const Vec4<A> *qfg = s_qf + gi * P, *qtg = s_qt + gi * P;
+        const float4 *so = s_off + gi * P;
+        for (int m0 = 0; m0 < cnt; m0 += kFmmRun) {
+            const int m1 = min(m0 + kFmmRun, cnt);
             A f6[6] = {0, 0, 0, 0, 0, 0};
             for (int m = m0; m < m1; ++m) {
-                const float4 o = s_off[m];
+                const float4 o = so[m];
                 const float dx = ax - o.x, dy = ay - o.y, dz = az - o.z;
-                rot_acc<A>(dx, dy, dz, fmaf(dz, dz, fmaf(dx, dx, dy * dy)), sf[m], st[m], f6);
+                rot_acc<A>(dx, dy, dz, fmaf(dz, dz, fmaf(dx, dx, dy * dy)), qfg[m], qtg[m], f6);
             }
 #pragma unroll
             for (int j = 0; j < 6; ++j) acc[j] += f6[j];
@@ -790,7 +830,7 @@ int m2l_groups(int P) {
 struct FmmPlan {
     int n = 0, P = 0, L = 0, ncell = 0, nleaf = 0;
     double o[3] = {0.0, 0.0, 0.0}, S = 0.0;  // root cube, units of length
-    int64_t n_near_pairs = 0;
+    int64_t n_near_pairs = 0, n_m2l_pairs = 0;
     std::vector<int> perm, lvl, parent, il_ptr, il, near_ptr, nearl;
     std::vector<int4> cc;
     std::vector<int2> rng, kids, work;
@@ -964,6 +1004,11 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
         q.L = L;
         q.ncell = ncell;
         q.nleaf = nleaf;
+        // M2L pair evaluations: n^3 per proxy of each listed cell, or per blob
+        // when the listed cell holds fewer blobs than proxies
+        q.n_m2l_pairs = 0;
+        for (int e = 0; e < (int)il.size(); ++e)
+            q.n_m2l_pairs += (int64_t)P * std::min(P, rng[il[e]].y - rng[il[e]].x);
         q.n_near_pairs = 0;
         for (int c = leaf0; c < leaf0 + nleaf; ++c)
             for (int e = near_ptr[c - leaf0]; e < near_ptr[c - leaf0 + 1]; ++e)
@@ -1025,7 +1070,7 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
         CellHash ph, ch;
         cells_of(1, pc, pr, pk2);
         ph.build(pk2.data(), (int)pk2.size(), 0);
-        int64_t il_total = 0, best = -1;
+        int64_t m2l_total = 0, best = -1;
         int L = 2;
         for (int l = 2; l <= Lhi; ++l) {
             cells_of(l, cc2, rr, kk2);
@@ -1046,9 +1091,10 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                             const int g = ph.get(l - 1, q.x + dx, q.y + dy, q.z + dz);
                             if (g < 0) continue;
                             for (int ch = kid[g].x; ch < kid[g].y; ++ch)
-                                il_total += std::abs(cc2[ch].x - cc2[c].x) > 1 ||
-                                            std::abs(cc2[ch].y - cc2[c].y) > 1 ||
-                                            std::abs(cc2[ch].z - cc2[c].z) > 1;
+                                if (std::abs(cc2[ch].x - cc2[c].x) > 1 ||
+                                    std::abs(cc2[ch].y - cc2[c].y) > 1 ||
+                                    std::abs(cc2[ch].z - cc2[c].z) > 1)
+                                    m2l_total += (int64_t)P * std::min(P, rr[ch].y - rr[ch].x);
                         }
             }
             int64_t near_pairs = 0;
@@ -1062,7 +1108,7 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                         }
                 near_pairs += adj * (rr[c].y - rr[c].x);
             }
-            const int64_t cl = near_pairs + il_total * P * P;
+            const int64_t cl = near_pairs + m2l_total;
             if (best >= 0 && cl >= best) break;
             best = cl;
             L = l;
@@ -1179,6 +1225,7 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
     F.nleaf = pl.nleaf;
     F.nwork = (int)pl.work.size();
     F.n_il = (int64_t)pl.il.size();
+    F.n_m2l_pairs = pl.n_m2l_pairs;
     F.n_near_pairs = pl.n_near_pairs;
     F.channels = channels;
     F.N = N;
@@ -1205,13 +1252,14 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
                                                                    F.kids.as<int2>(), F.lvl[l],
                                                                    qhat);
         const int groups = m2l_groups(P);
-        const size_t lds = (size_t)groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
+        const size_t lds = (size_t)groups * P * (sizeof(Vec4<A>) + sizeof(float4)) +
                            (size_t)3 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
         const int nc = F.lvl[L + 1] - F.lvl[2];
         fmm_m2l_kernel<WALL, A><<<round_up(nc, 8 * kXcdChunk), round_up(groups * P, kWave), lds, s>>>(
             g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc, groups,
-            qhat, F.v.as<double>());
+            F.rng.as<int2>(), F.shi.as<float4>(), F.slo.as<float4>(), slam, qhat,
+            F.v.as<double>());
         for (int l = 3; l <= L; ++l)
             fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
                 g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], F.v.as<double>());
@@ -1262,13 +1310,13 @@ void fmm_run6(const FmmState &F, hipStream_t s, const double *x6, double inv_a, 
                 fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
                     g, tab, F.cc.as<int4>(), F.kids.as<int2>(), F.lvl[l], ch ? qt : qf);
         const int groups = m2l_groups(P);
-        const size_t lds = (size_t)2 * groups * P * sizeof(Vec4<A>) + (size_t)P * sizeof(float4) +
+        const size_t lds = (size_t)groups * P * (2 * sizeof(Vec4<A>) + sizeof(float4)) +
                            (size_t)6 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
         const int nc = F.lvl[L + 1] - F.lvl[2];
         fmm_m2l6_kernel<A><<<round_up(nc, 8 * kXcdChunk), round_up(groups * P, kWave), lds, s>>>(
             g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc, groups,
-            qf, qt, vu, vw);
+            F.rng.as<int2>(), F.shi.as<float4>(), F.slo.as<float4>(), sf, st, qf, qt, vu, vw);
         for (int l = 3; l <= L; ++l)
             for (int ch = 0; ch < 2; ++ch)
                 fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
@@ -1312,7 +1360,7 @@ int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int 
     out->leaves = pl.nleaf;
     out->near_pairs = pl.n_near_pairs;
     out->interactions = (long long)pl.il.size();
-    out->m2l_pairs = (long long)pl.il.size() * pl.P * pl.P;
+    out->m2l_pairs = pl.n_m2l_pairs;
     out->build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return ARB_OK;

@@ -10,23 +10,30 @@ from oracle import fastsum
 from paper_2107_10800_amd import arb
 
 
-def counts(pos, a, n, L):
-    """(cells of levels 0..L, leaves, direct pairs, interaction-list entries)."""
+def counts(pos, a, n, L, with_pairs=False):
+    """(cells of levels 0..L, leaves, direct pairs, interaction-list entries[,
+    M2L pair evaluations: n^3 per proxy or blob of each listed cell, the blobs
+    when the cell holds fewer than n^3])."""
     o, S = fastsum.root_cube(pos, a)
+    P = n ** 3
     cells = 0
     inter = 0
+    m2l = 0
     for lev in range(L + 1):
-        u = np.unique(fastsum.cell_coords(pos, o, S, lev), axis=0)
+        u, occ = np.unique(fastsum.cell_coords(pos, o, S, lev), axis=0, return_counts=True)
         cells += len(u)
         if lev >= 2:
             for c in u:
-                inter += int(np.sum((np.abs(u // 2 - c // 2).max(1) <= 1)
-                                    & (np.abs(u - c).max(1) > 1)))
+                sel = (np.abs(u // 2 - c // 2).max(1) <= 1) & (np.abs(u - c).max(1) > 1)
+                inter += int(np.sum(sel))
+                m2l += int(P * np.minimum(occ[sel], P).sum())
     leaf = fastsum.cell_coords(pos, o, S, L)
     keys, cnt = np.unique(leaf, axis=0, return_counts=True)
     near = 0
     for k, m in zip(keys, cnt):
         near += int(m) * int(cnt[np.abs(keys - k).max(1) <= 1].sum())
+    if with_pairs:
+        return cells, len(keys), near, inter, m2l
     return cells, len(keys), near, inter
 
 
@@ -62,20 +69,21 @@ def test_plan_matches_the_definitions(N, box, L):
     Lexp = 0 if L < 2 else min(L, fastsum.max_level(pos, a))
     st = arb.arb_fmm_plan(pos, a, order=n, levels=L)
     assert st["levels"] == Lexp
-    cells, leaves, near, inter = counts(pos, a, n, Lexp)
+    cells, leaves, near, inter, m2l = counts(pos, a, n, Lexp, with_pairs=True)
     assert (st["cells"], st["leaves"], st["near_pairs"], st["interactions"]) == \
         (cells, leaves, near, inter)
-    assert st["m2l_pairs"] == inter * n ** 6
+    assert st["m2l_pairs"] == m2l <= inter * n ** 6
 
 
 def fewest_pairs_level(pos, a, n):
     """The documented default: from level 2, one level deeper while the pair
-    evaluations per product (direct pairs + n^6 per interaction-list entry)
-    fall."""
+    evaluations per product (direct pairs + M2L pairs) fall."""
     Lhi = min(fastsum.max_level(pos, a), 16)
     if Lhi < 2:
         return 0
-    cost = lambda lev: counts(pos, a, n, lev)[2] + counts(pos, a, n, lev)[3] * n ** 6  # noqa
+    def cost(lev):
+        c = counts(pos, a, n, lev, with_pairs=True)
+        return c[2] + c[4]
     L, best = 2, cost(2)
     for lev in range(3, Lhi + 1):
         c = cost(lev)
