@@ -107,7 +107,8 @@ typedef struct {
      * differ by at most 1.  Pairs in adjacent leaves are summed directly; the
      * tensor between well-separated cells is replaced by its tensor-product
      * Chebyshev interpolant (fmm_order points per direction) in both
-     * arguments.  The error falls geometrically with fmm_order (max error
+     * arguments (a listed cell with fewer blobs than proxies enters with its
+     * blobs).  The error falls geometrically with fmm_order (max error
      * relative to the largest entry about 1e-4 at 5, 1e-5 at 6 for dense
      * suspensions).  The tree is rebuilt on the host whenever the state
      * changes (one device-to-host copy of the positions and a sort).        */
@@ -115,9 +116,9 @@ typedef struct {
     int    fmm_levels; /* leaf level L; 0 = chosen: with fmm_leaf > 0 the       */
                        /* shallowest level whose mean occupancy is <= fmm_leaf, */
                        /* else the level with the fewest pair evaluations per   */
-                       /* product (direct pairs + fmm_order^6 per interaction-  */
-                       /* list entry), going deeper from level 2 while they     */
-                       /* fall; never deeper than the deepest level with a cell */
+                       /* product (direct pairs + M2L pairs, arb_fmm_stats),    */
+                       /* going deeper from level 2 while they fall; never      */
+                       /* deeper than the deepest level with a cell             */
                        /* side >= 2a; L <= 1 gives the direct sum               */
     int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = see fmm_levels)     */
 } arb_options;

@@ -18,9 +18,9 @@
 //   adjacent when their coordinates differ by at most 1 per direction.  Leaf
 //   level L: fixed by the options, or the shallowest level whose mean
 //   occupancy is at most the requested blobs per leaf, or by default the level
-//   with the fewest pair evaluations per product (direct pairs plus n^6 per
-//   interaction-list entry, counted level by level from level 2 while they
-//   fall); never deeper than the deepest level with a cell side >= 2a (so every
+//   with the fewest pair evaluations per product (direct pairs plus M2L pairs,
+//   counted level by level from level 2 while they fall); never deeper than
+//   the deepest level with a cell side >= 2a (so every
 //   interpolated pair has r > 2a and stays off the overlap branch of the
 //   tensor).  Interaction list of a cell at level l >= 2: the non-empty cells
 //   whose parent is adjacent to its parent and which are not adjacent to it.
@@ -32,7 +32,9 @@
 //   M2L  v^c_k = sum_{c' in IL(c)} sum_m M(t^c_k, s^c'_m) qhat^c'_m, matrix-free
 //        with the FP32 pair function (one workgroup per cell, lane groups of
 //        one lane per target proxy taking listed cells in turn, the source
-//        proxies of each listed cell staged in LDS);
+//        proxies of each listed cell staged in LDS; a listed cell with fewer
+//        blobs than proxies enters with its blobs, n^3 |c'| pairs instead of
+//        n^6);
 //   L2L  the children's v gain the parent's interpolant at their proxies;
 //   near + L2P  direct sums over the adjacent leaves (hi/lo split positions,
 //        float runs promoted to double, as in the dense FP32 kernel) plus
