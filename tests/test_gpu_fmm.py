@@ -33,12 +33,14 @@ def fmm(pos, lam, wall, n, L, a=1.0, eta=1.0, leaf=0, precision=arb.ARB_FP64):
         arb.arb_destroy(ctx)
 
 
-CASES = [  # (N, box, wall, n, L)
-    (400, (48, 48, 10), False, 4, 3),
-    (401, (48, 48, 10), False, 3, 3),
-    (700, (40, 40, 40), False, 5, 2),
-    (300, (48, 48, 10), True, 4, 2),
-    (257, (30, 60, 8), True, 3, 3),
+# (N, box, wall, n, L): cells hold more blobs than proxies (n^3) on average, so
+# that both interpolations are exercised next to the sparse-cell paths
+CASES = [
+    (2400, (48, 48, 10), False, 4, 2),
+    (1501, (48, 48, 10), False, 3, 2),
+    (2401, (48, 48, 10), False, 5, 2),
+    (1100, (48, 48, 10), True, 4, 2),
+    (700, (30, 60, 8), True, 3, 2),
 ]
 
 
@@ -196,8 +198,8 @@ def rot_kernel(a, eta):
     return K
 
 
-@pytest.mark.parametrize("M,box,n,L", [(300, (40, 40, 10), 4, 3), (301, (30, 30, 30), 3, 2),
-                                       (260, (48, 24, 12), 5, 2)])
+@pytest.mark.parametrize("M,box,n,L", [(2000, (48, 48, 10), 4, 2), (1801, (30, 30, 30), 2, 2),
+                                       (2200, (48, 24, 12), 3, 2)])
 def test_single_blob_matches_the_oracle_of_the_approximation(M, box, n, L):
     """The generalised tensor (Sec. 2.4) in the fast product, force and torque
     channels, both variants, against the oracle's plain sum of the same

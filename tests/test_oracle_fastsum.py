@@ -99,15 +99,16 @@ def test_no_interaction_list_is_the_direct_sum(wall):
 
 @pytest.mark.parametrize("wall", [False, True])
 def test_rpy_error_falls_geometrically_with_order(wall):
-    """A slab two leaves thick (leaf side 6a; 12a above the wall): the max error
-    over blobs, relative to the largest entry, falls by a roughly constant
-    factor per order."""
-    pos, lam = blobs(400 if not wall else 200, (48, 48, 10), 9)
+    """A slab of 16 cells at leaf level 2 (side 12a) holding more blobs than
+    proxies, so that both arguments are interpolated: the max error over blobs,
+    relative to the largest entry, falls by a roughly constant factor per
+    order.  (The wall tensor of the oracle is slow: fewer blobs and orders.)"""
+    N, orders = (2400, (2, 3, 4, 5)) if not wall else (1100, (2, 3, 4))
+    pos, lam = blobs(N, (48, 48, 10), 9)
     ref = rpy.mobility_apply(pos, lam, 1.0, 1.0, wall)
     errs = []
-    # (the wall tensor of the oracle is slow: fewer, larger cells there)
-    for n in ((2, 3, 4, 5) if not wall else (2, 3, 4)):
-        u = fastsum.fmm_apply(pos, lam, 1.0, 1.0, wall, n, 3 if not wall else 2)
+    for n in orders:
+        u = fastsum.fmm_apply(pos, lam, 1.0, 1.0, wall, n, 2)
         errs.append(np.abs(u - ref).max() / np.abs(ref).max())
     print("max error by order:", ["%.1e" % e for e in errs])
     assert errs[0] > 1e-4                   # the interpolation is really used
@@ -147,8 +148,8 @@ def test_generalised_rpy_error_falls_with_order():
     """The single-blob tensor (Sec. 2.4) in the interpolation: the error against
     the dense generalised sum falls with the order."""
     from oracle import rpy_rot
-    pos, _ = blobs(200, (48, 48, 10), 13)
-    ft = np.random.default_rng(5).standard_normal((200, 6))
+    pos, _ = blobs(2000, (48, 48, 10), 13)       # more bodies per cell than proxies
+    ft = np.random.default_rng(5).standard_normal((2000, 6))
     ref = rpy_rot.body_mobility_apply(pos, ft, 1.0, 1.0)
 
     def K(x, y):
