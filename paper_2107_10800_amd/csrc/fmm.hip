@@ -52,6 +52,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <thread>
 #include <type_traits>
 
 #include "rot_device.h"
@@ -774,6 +775,29 @@ inline uint64_t morton(int x, int y, int z) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// host threads for the O(N) steps of the tree build: at most 16 (one GPU's
+// share of the host), one per 65,536 blobs
+int host_threads(int N) {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    return std::max(1, std::min({16, hw, N / 65536}));
+}
+
+// f(t, i0, i1) on T contiguous slices of [0, N), thread t taking slice t
+template <class F>
+void parallel_slices(int T, int N, F &&f) {
+    if (T <= 1) {
+        f(0, 0, N);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t) {
+        const int i0 = (int)((int64_t)N * t / T), i1 = (int)((int64_t)N * (t + 1) / T);
+        th.emplace_back([&f, t, i0, i1] { f(t, i0, i1); });
+    }
+    for (auto &x : th) x.join();
+}
+
 // open-addressing map from the Morton keys of one level's cells (< 2^48) to
 // their indices
 struct CellHash {
@@ -858,38 +882,56 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
     const double S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : a;
     int Lhi = 0;  // deepest level with a cell side >= 2a
     while (Lhi < kFmmMaxLevel && S / std::ldexp(1.0, Lhi + 1) >= 2.0 * a) ++Lhi;
-    // cell coordinates at level Lhi and Morton keys
+    // cell coordinates at level Lhi and Morton keys (host threads over slices)
     std::vector<int> crd(3 * (size_t)N);
     std::vector<uint64_t> key((size_t)N), key2((size_t)N);
     std::vector<int> idx((size_t)N), idx2((size_t)N);
     const double scale = std::ldexp(1.0, Lhi);
-    for (int i = 0; i < N; ++i) {
-        int cq[3];
-        for (int d = 0; d < 3; ++d) {
-            const double u = (h[3 * (size_t)i + d] - o[d]) / S;
-            cq[d] = (int)std::floor(u * scale);
-            crd[3 * (size_t)i + d] = cq[d];
+    const int T = host_threads(N);
+    parallel_slices(T, N, [&](int, int i0, int i1) {
+        for (int i = i0; i < i1; ++i) {
+            int cq[3];
+            for (int d = 0; d < 3; ++d) {
+                const double u = (h[3 * (size_t)i + d] - o[d]) / S;
+                cq[d] = (int)std::floor(u * scale);
+                crd[3 * (size_t)i + d] = cq[d];
+            }
+            key[i] = morton(cq[0], cq[1], cq[2]);
+            idx[i] = i;
         }
-        key[i] = morton(cq[0], cq[1], cq[2]);
-        idx[i] = i;
-    }
+    });
     // stable LSD radix sort of the 3 Lhi-bit keys in the fewest passes of at
-    // most 14 bits: blobs in Morton order, equal keys in ascending blob index
+    // most 14 bits: blobs in Morton order, equal keys in ascending blob index.
+    // Each thread counts and then scatters its own contiguous slice, at offsets
+    // ordered by bucket and then by thread, which keeps the sort stable.
     {
         const int bits = 3 * Lhi, passes = (bits + 13) / 14;
         const int dbits = passes ? (bits + passes - 1) / passes : 0;
-        const uint64_t mask = (1ull << dbits) - 1;
-        std::vector<int> cnt((size_t)mask + 2);
+        const size_t B = (size_t)1 << dbits;
+        const uint64_t mask = B - 1;
+        std::vector<int> cnt((size_t)T * B);
         for (int ps = 0; ps < passes; ++ps) {
             const int shift = ps * dbits;
-            std::fill(cnt.begin(), cnt.end(), 0);
-            for (int i = 0; i < N; ++i) ++cnt[((key[i] >> shift) & mask) + 1];
-            for (size_t b = 0; b <= mask; ++b) cnt[b + 1] += cnt[b];
-            for (int i = 0; i < N; ++i) {
-                const int at = cnt[(key[i] >> shift) & mask]++;
-                key2[at] = key[i];
-                idx2[at] = idx[i];
-            }
+            parallel_slices(T, N, [&](int t, int i0, int i1) {
+                int *c = cnt.data() + (size_t)t * B;
+                std::fill(c, c + B, 0);
+                for (int i = i0; i < i1; ++i) ++c[(key[i] >> shift) & mask];
+            });
+            int run = 0;
+            for (size_t b = 0; b < B; ++b)
+                for (int t = 0; t < T; ++t) {
+                    const int m = cnt[(size_t)t * B + b];
+                    cnt[(size_t)t * B + b] = run;
+                    run += m;
+                }
+            parallel_slices(T, N, [&](int t, int i0, int i1) {
+                int *c = cnt.data() + (size_t)t * B;
+                for (int i = i0; i < i1; ++i) {
+                    const int at = c[(key[i] >> shift) & mask]++;
+                    key2[at] = key[i];
+                    idx2[at] = idx[i];
+                }
+            });
             key.swap(key2);
             idx.swap(idx2);
         }

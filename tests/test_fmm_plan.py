@@ -131,3 +131,14 @@ def test_degenerate_inputs():
     pos[3, 1] = np.nan
     with pytest.raises(arb.ArbError):
         arb.arb_fmm_plan(pos, 1.0)
+
+
+def test_plan_of_many_blobs():
+    """200,000 blobs in a slab: the plan's keys and sort run on several host
+    threads there; its counts against the definitions."""
+    pos = blobs(200_000, (400, 400, 12), 77)
+    st = arb.arb_fmm_plan(pos, 1.0, order=3, levels=5)
+    cells, leaves, near, inter, m2l = counts(pos, 1.0, 3, 5, with_pairs=True)
+    assert st["levels"] == 5
+    assert (st["cells"], st["leaves"], st["near_pairs"], st["interactions"], st["m2l_pairs"]) == \
+        (cells, leaves, near, inter, m2l)
