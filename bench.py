@@ -664,6 +664,8 @@ def main():
     ap.add_argument("--fmm-only", action="store_true",
                     help="run only the fast-product block (for profiling)")
     ap.add_argument("--no-fmm", action="store_true", help="skip the fast-product block")
+    ap.add_argument("--single-blob-only", action="store_true",
+                    help="run only the single-blob block (for profiling)")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -682,6 +684,9 @@ def main():
     arb.load()
     if args.fmm_only:
         print(json.dumps({"fmm": fmm_bench(torch, arb, W, reps=args.steps)}), flush=True)
+        return
+    if args.single_blob_only:
+        print(json.dumps({"single_blob": single_blob_bench(torch, arb, W)}), flush=True)
         return
     sl = W.slab()
     N = len(sl["pos"])

@@ -78,7 +78,9 @@ constexpr int kFmmDefaultOrder = 6;
 struct FmmState {
     DevBuf perm, cc, rng, parent, kids, il_ptr, il, near_ptr, nearl, work, tab, shi, slo, slam,
         qhat, v, slam2, qhat2, v2;  // second channel: the torques of single-blob bodies
+    DevBuf vsplit;  // M2L sums of the parts of split interaction lists (splits > 1)
     int N = 0, L = 0, n = 0, P = 0, ncell = 0, nleaf = 0, nwork = 0, channels = 1;
+    int splits = 1;  // M2L work items per cell
     int64_t n_il = 0, n_near_pairs = 0;  // interaction-list entries, direct pairs
     int64_t n_m2l_pairs = 0;             // M2L pair evaluations per product
     std::vector<int> lvl;

@@ -167,6 +167,19 @@ __device__ __forceinline__ double centre(double o, double side, int i) {
     return o + ((double)i + 0.5) * side;
 }
 
+// v of the cells of split interaction lists: the parts' sums, added in the
+// order of the parts (m values of 3 P doubles per cell)
+__global__ void fmm_split_sum_kernel(int64_t m, int splits, int P3,
+                                     const double *__restrict__ vpart, double *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int64_t c = i / P3, r = i - c * P3;
+    const double *p = vpart + c * splits * P3 + r;
+    double t = 0.0;
+    for (int j = 0; j < splits; ++j) t += p[(int64_t)j * P3];
+    v[i] = t;
+}
+
 __global__ void fmm_sort_pos_kernel(int N, const int *__restrict__ perm,
                                     const float4 *__restrict__ hi, const float4 *__restrict__ lo,
                                     float4 *__restrict__ shi, float4 *__restrict__ slo) {
@@ -291,8 +304,10 @@ template <bool WALL, class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
     const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int items, int groups,
+    int splits,
     const int2 *__restrict__ rng, const float4 *__restrict__ shi, const float4 *__restrict__ slo,
-    const Vec4<A> *__restrict__ slam, const Vec4<A> *__restrict__ qhat, double *__restrict__ v) {
+    const Vec4<A> *__restrict__ slam, const Vec4<A> *__restrict__ qhat, double *__restrict__ v,
+    double *__restrict__ vpart) {
     const int item = xcd_item(items);
     if (item < 0) return;
     // LDS sized by the host: the sources of `groups` listed cells (offsets from
@@ -305,7 +320,9 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     double *s_acc = reinterpret_cast<double *>(s_off + GP);
     float *tab = reinterpret_cast<float *>(s_acc + 3 * (GP - P));
     load_tab(tabg, tab);
-    const int c = cell0 + item;
+    // a cell's interaction list may be split over `splits` consecutive items,
+    // each of which stores its part's sum at its own place in vpart
+    const int c = cell0 + item / splits, part = item % splits;
     const int tid = threadIdx.x;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
@@ -319,8 +336,9 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     const float zi = (float)(czt + w * tab[kTabNode + kz]);  // target proxy height
     const TargetZ<float> zsc = target_z(zi);
     double ux = 0.0, uy = 0.0, uz = 0.0;
-    const int e1 = il_ptr[c + 1];
-    for (int e0 = il_ptr[c]; e0 < e1; e0 += groups) {
+    const int b0 = il_ptr[c], len = il_ptr[c + 1] - b0;
+    const int e1 = b0 + (int)((int64_t)len * (part + 1) / splits);
+    for (int e0 = b0 + (int)((int64_t)len * part / splits); e0 < e1; e0 += groups) {
         __syncthreads();
         // a listed cell with fewer blobs than proxies enters with its blobs,
         // the others with their proxies (offsets w xi) and multipole weights
@@ -395,7 +413,7 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
             uy += a[1];
             uz += a[2];
         }
-        double *o = v + ((size_t)c * P + k) * 3;
+        double *o = splits == 1 ? v + ((size_t)c * P + k) * 3 : vpart + ((size_t)item * P + k) * 3;
         o[0] = ux;
         o[1] = uy;
         o[2] = uz;
@@ -568,10 +586,11 @@ template <class A>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     Geo g, const float *__restrict__ tabg, const int4 *__restrict__ cc,
     const int *__restrict__ il_ptr, const int *__restrict__ il, int cell0, int items, int groups,
+    int splits,
     const int2 *__restrict__ rng, const float4 *__restrict__ shi, const float4 *__restrict__ slo,
     const Vec4<A> *__restrict__ sf, const Vec4<A> *__restrict__ st,
     const Vec4<A> *__restrict__ qf, const Vec4<A> *__restrict__ qt, double *__restrict__ vu,
-    double *__restrict__ vw) {
+    double *__restrict__ vw, double *__restrict__ vpart) {
     const int item = xcd_item(items);
     if (item < 0) return;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -583,7 +602,9 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     double *s_acc = reinterpret_cast<double *>(s_off + GP);
     float *tab = reinterpret_cast<float *>(s_acc + 6 * (GP - P));
     load_tab(tabg, tab);
-    const int c = cell0 + item;
+    // a cell's interaction list may be split over `splits` consecutive items,
+    // each of which stores its part's sum at its own place in vpart
+    const int c = cell0 + item / splits, part = item % splits;
     const int tid = threadIdx.x;
     const int4 ct = cc[c];
     const double side = ldexp(g.S, -ct.w), w = 0.5 * side;
@@ -594,8 +615,9 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
     const float okx = (float)(w * tab[kTabNode + kx]), oky = (float)(w * tab[kTabNode + ky]),
                 okz = (float)(w * tab[kTabNode + kz]);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int e1 = il_ptr[c + 1];
-    for (int e0 = il_ptr[c]; e0 < e1; e0 += groups) {
+    const int b0 = il_ptr[c], len = il_ptr[c + 1] - b0;
+    const int e1 = b0 + (int)((int64_t)len * (part + 1) / splits);
+    for (int e0 = b0 + (int)((int64_t)len * part / splits); e0 < e1; e0 += groups) {
         __syncthreads();
         // sparse listed cells enter with their bodies, the others with proxies
         for (int t = tid; t < GP; t += blockDim.x) {
@@ -658,7 +680,14 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l6_kernel(
         for (int gg = 1; gg < groups; ++gg)
 #pragma unroll
             for (int j = 0; j < 6; ++j) acc[j] += s_acc[6 * ((gg - 1) * P + k) + j];
-        double *ou = vu + ((size_t)c * P + k) * 3, *ow = vw + ((size_t)c * P + k) * 3;
+        double *ou, *ow;
+        if (splits == 1) {
+            ou = vu + ((size_t)c * P + k) * 3;
+            ow = vw + ((size_t)c * P + k) * 3;
+        } else {
+            ou = vpart + ((size_t)item * P + k) * 3;
+            ow = ou + (size_t)items * P * 3;
+        }
         ou[0] = acc[0];
         ou[1] = acc[1];
         ou[2] = acc[2];
@@ -834,6 +863,12 @@ struct CellHash {
         return -1;
     }
 };
+
+// work items per cell in M2L: one, or up to 8 when there are too few cells to
+// fill the chip (about 2,048 items wanted)
+int m2l_splits(int cells) {
+    return std::max(1, std::min(8, (2048 + cells - 1) / std::max(cells, 1)));
+}
 
 // M2L lane groups per workgroup: the count (up to 8 within 512 lanes) that
 // leaves the fewest idle lanes in its waves
@@ -1249,6 +1284,11 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
                (F.slam2.ensure((size_t)N * sizeof(double4)) == hipSuccess &&
                 F.qhat2.ensure((size_t)ncell * P * sizeof(double4)) == hipSuccess &&
                 F.v2.ensure((size_t)ncell * P * 3 * sizeof(double)) == hipSuccess));
+    const int nc_m2l = pl.L >= 2 ? pl.lvl[pl.L + 1] - pl.lvl[2] : 0;
+    const int splits = nc_m2l > 0 ? m2l_splits(nc_m2l) : 1;
+    ok = ok && (splits == 1 ||
+                F.vsplit.ensure((size_t)nc_m2l * splits * P * 3 * channels * sizeof(double)) ==
+                    hipSuccess);
     if (!ok) {
         *msg = "fast product: device allocation or copy failed";
         return ARB_E_DEVICE;
@@ -1261,6 +1301,7 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
     }
     F.L = pl.L;
     F.lvl = pl.lvl;
+    F.splits = splits;
     F.o[0] = pl.o[0] / a;
     F.o[1] = pl.o[1] / a;
     F.o[2] = pl.o[2] / a;
@@ -1299,11 +1340,18 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
         const size_t lds = (size_t)groups * P * (sizeof(Vec4<A>) + sizeof(float4)) +
                            (size_t)3 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
-        const int nc = F.lvl[L + 1] - F.lvl[2];
-        fmm_m2l_kernel<WALL, A><<<round_up(nc, 8 * kXcdChunk), round_up(groups * P, kWave), lds, s>>>(
-            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc, groups,
+        const int nc = F.lvl[L + 1] - F.lvl[2], splits = F.splits;
+        fmm_m2l_kernel<WALL, A><<<round_up(nc * splits, 8 * kXcdChunk), round_up(groups * P, kWave),
+                                  lds, s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc * splits,
+            groups, splits,
             F.rng.as<int2>(), F.shi.as<float4>(), F.slo.as<float4>(), slam, qhat,
-            F.v.as<double>());
+            F.v.as<double>(), F.vsplit.as<double>());
+        if (splits > 1) {
+            const int64_t m = (int64_t)nc * P * 3;
+            fmm_split_sum_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
+                m, splits, P * 3, F.vsplit.as<double>(), F.v.as<double>() + (size_t)F.lvl[2] * P * 3);
+        }
         for (int l = 3; l <= L; ++l)
             fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
                 g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], F.v.as<double>());
@@ -1357,10 +1405,20 @@ void fmm_run6(const FmmState &F, hipStream_t s, const double *x6, double inv_a, 
         const size_t lds = (size_t)groups * P * (2 * sizeof(Vec4<A>) + sizeof(float4)) +
                            (size_t)6 * (groups - 1) * P * sizeof(double) +
                            kTabSize * sizeof(float);
-        const int nc = F.lvl[L + 1] - F.lvl[2];
-        fmm_m2l6_kernel<A><<<round_up(nc, 8 * kXcdChunk), round_up(groups * P, kWave), lds, s>>>(
-            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc, groups,
-            F.rng.as<int2>(), F.shi.as<float4>(), F.slo.as<float4>(), sf, st, qf, qt, vu, vw);
+        const int nc = F.lvl[L + 1] - F.lvl[2], splits = F.splits;
+        fmm_m2l6_kernel<A><<<round_up(nc * splits, 8 * kXcdChunk), round_up(groups * P, kWave), lds,
+                             s>>>(
+            g, tab, F.cc.as<int4>(), F.il_ptr.as<int>(), F.il.as<int>(), F.lvl[2], nc * splits,
+            groups, splits,
+            F.rng.as<int2>(), F.shi.as<float4>(), F.slo.as<float4>(), sf, st, qf, qt, vu, vw,
+            F.vsplit.as<double>());
+        if (splits > 1) {
+            const int64_t m = (int64_t)nc * P * 3;
+            for (int ch = 0; ch < 2; ++ch)
+                fmm_split_sum_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
+                    m, splits, P * 3, F.vsplit.as<double>() + ch * (size_t)nc * splits * P * 3,
+                    (ch ? vw : vu) + (size_t)F.lvl[2] * P * 3);
+        }
         for (int l = 3; l <= L; ++l)
             for (int ch = 0; ch < 2; ++ch)
                 fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
