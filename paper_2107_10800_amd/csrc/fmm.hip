@@ -261,22 +261,27 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *_
                                                            const int2 *__restrict__ kids,
                                                            int cell0, Vec4<A> *__restrict__ qhat) {
     __shared__ float tab[kTabSize];
+    __shared__ Vec4<A> sq[kFmmMaxP];  // one child's weights, read by every lane
     load_tab(tabg, tab);
     const int c = cell0 + blockIdx.x;
     const int k = threadIdx.x;
-    if (k >= g.P) return;
     const int n = g.n, P = g.P;
+    const bool act = k < P;
     const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
     const int2 kr = kids[c];
     double qx = 0.0, qy = 0.0, qz = 0.0;
     for (int ch = kr.x; ch < kr.y; ++ch) {
+        __syncthreads();
+        if (act) sq[k] = qhat[(size_t)ch * P + k];
+        __syncthreads();
+        if (!act) continue;
         const int4 cci = cc[ch];
         // t1[sigma][k][m] = l_k(sigma/2 + xi_m/2): the parent's polynomial at the
         // child's proxies (sigma = -1 for the lower child, the even coordinate)
         const float *tx = tab + kTabT1 + (cci.x & 1) * kFmmMaxOrder * kFmmMaxOrder + kx * kFmmMaxOrder;
         const float *ty = tab + kTabT1 + (cci.y & 1) * kFmmMaxOrder * kFmmMaxOrder + ky * kFmmMaxOrder;
         const float *tz = tab + kTabT1 + (cci.z & 1) * kFmmMaxOrder * kFmmMaxOrder + kz * kFmmMaxOrder;
-        const Vec4<A> *q = qhat + (size_t)ch * P;
+        const Vec4<A> *q = sq;
         A fx = 0, fy = 0, fz = 0;
         for (int mx = 0; mx < n; ++mx)
             for (int my = 0; my < n; ++my) {
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *_
         qy += fy;
         qz += fz;
     }
-    qhat[(size_t)c * P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
+    if (act) qhat[(size_t)c * P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
 }
 
 // v of every cell of levels 2..L over its interaction list: `groups` lane
@@ -426,17 +431,23 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_l2l_kernel(Geo g, const float *_
                                                            const int *__restrict__ parent,
                                                            int cell0, double *__restrict__ v) {
     __shared__ float tab[kTabSize];
+    __shared__ double sv[3 * kFmmMaxP];  // the parent's values, read by every lane
     load_tab(tabg, tab);
     const int c = cell0 + blockIdx.x;
     const int m = threadIdx.x;
-    if (m >= g.P) return;
     const int n = g.n, P = g.P;
+    {
+        const double *vp = v + (size_t)parent[c] * P * 3;
+        for (int i = m; i < 3 * P; i += blockDim.x) sv[i] = vp[i];
+    }
+    __syncthreads();
+    if (m >= P) return;
     const int mx = m / (n * n), my = (m / n) % n, mz = m % n;
     const int4 cci = cc[c];
     const float *tx = tab + kTabT1 + (cci.x & 1) * kFmmMaxOrder * kFmmMaxOrder + mx;
     const float *ty = tab + kTabT1 + (cci.y & 1) * kFmmMaxOrder * kFmmMaxOrder + my;
     const float *tz = tab + kTabT1 + (cci.z & 1) * kFmmMaxOrder * kFmmMaxOrder + mz;
-    const double *vp = v + (size_t)parent[c] * P * 3;
+    const double *vp = sv;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int kx = 0; kx < n; ++kx)
         for (int ky = 0; ky < n; ++ky) {
