@@ -254,8 +254,8 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_p2m_kernel(
     if (act) qhat[(size_t)c * g.P + k] = vec4<A>((A)qx, (A)qy, (A)qz);
 }
 
-// qhat of the cells of one level from their children
-template <class A>
+// qhat of the cells of one level from their children (NO points per direction)
+template <class A, int NO>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *__restrict__ tabg,
                                                            const int4 *__restrict__ cc,
                                                            const int2 *__restrict__ kids,
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *_
     load_tab(tabg, tab);
     const int c = cell0 + blockIdx.x;
     const int k = threadIdx.x;
-    const int n = g.n, P = g.P;
+    constexpr int n = NO, P = NO * NO * NO;
     const bool act = k < P;
     const int kx = k / (n * n), ky = (k / n) % n, kz = k % n;
     const int2 kr = kids[c];
@@ -284,8 +284,10 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2m_kernel(Geo g, const float *_
         const Vec4<A> *q = sq;
         A fx = 0, fy = 0, fz = 0;
         for (int mx = 0; mx < n; ++mx)
+#pragma unroll
             for (int my = 0; my < n; ++my) {
                 const float a = tx[mx] * ty[my];
+#pragma unroll
                 for (int mz = 0; mz < n; ++mz) {
                     const A w = (A)(a * tz[mz]);
                     const Vec4<A> Q = q[(mx * n + my) * n + mz];
@@ -425,7 +427,9 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_m2l_kernel(
     }
 }
 
-// the children at one level gain the parent's interpolant at their proxies
+// the children at one level gain the parent's interpolant at their proxies (NO
+// points per direction)
+template <int NO>
 __global__ __launch_bounds__(kFmmMaxP) void fmm_l2l_kernel(Geo g, const float *__restrict__ tabg,
                                                            const int4 *__restrict__ cc,
                                                            const int *__restrict__ parent,
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_l2l_kernel(Geo g, const float *_
     load_tab(tabg, tab);
     const int c = cell0 + blockIdx.x;
     const int m = threadIdx.x;
-    const int n = g.n, P = g.P;
+    constexpr int n = NO, P = NO * NO * NO;
     {
         const double *vp = v + (size_t)parent[c] * P * 3;
         for (int i = m; i < 3 * P; i += blockDim.x) sv[i] = vp[i];
@@ -450,8 +454,10 @@ __global__ __launch_bounds__(kFmmMaxP) void fmm_l2l_kernel(Geo g, const float *_
     const double *vp = sv;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int kx = 0; kx < n; ++kx)
+#pragma unroll
         for (int ky = 0; ky < n; ++ky) {
             const double a = (double)(tx[kx * kFmmMaxOrder] * ty[ky * kFmmMaxOrder]);
+#pragma unroll
             for (int kz = 0; kz < n; ++kz) {
                 const double wk = a * (double)tz[kz * kFmmMaxOrder];
                 const double *pv = vp + 3 * ((kx * n + ky) * n + kz);
@@ -879,6 +885,21 @@ struct CellHash {
 // fill the chip (about 2,048 items wanted)
 int m2l_splits(int cells) {
     return std::max(1, std::min(8, (2048 + cells - 1) / std::max(cells, 1)));
+}
+
+// calls f with the order n (2..kFmmMaxOrder, checked when the options are
+// read) as a compile-time constant, for the kernels whose loops unroll over it
+template <class F> void with_order(int n, F &&f) {
+    static_assert(kFmmMaxOrder == 8, "cases 2..8");
+    switch (n) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+    }
 }
 
 // M2L lane groups per workgroup: the count (up to 8 within 512 lanes) that
@@ -1343,10 +1364,11 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
         fmm_p2m_kernel<A><<<F.lvl[L + 1] - F.lvl[L], B, 0, s>>>(
             g, tab, F.cc.as<int4>(), F.rng.as<int2>(), F.lvl[L], F.shi.as<float4>(),
             F.slo.as<float4>(), slam, qhat);
-        for (int l = L - 1; l >= 2; --l)
-            fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(g, tab, F.cc.as<int4>(),
-                                                                   F.kids.as<int2>(), F.lvl[l],
-                                                                   qhat);
+        with_order(F.n, [&](auto o) {
+            for (int l = L - 1; l >= 2; --l)
+                fmm_m2m_kernel<A, decltype(o)::value><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                    g, tab, F.cc.as<int4>(), F.kids.as<int2>(), F.lvl[l], qhat);
+        });
         const int groups = m2l_groups(P);
         const size_t lds = (size_t)groups * P * (sizeof(Vec4<A>) + sizeof(float4)) +
                            (size_t)3 * (groups - 1) * P * sizeof(double) +
@@ -1363,9 +1385,11 @@ void fmm_run(const FmmState &F, hipStream_t s, const double *lam, double *partia
             fmm_split_sum_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
                 m, splits, P * 3, F.vsplit.as<double>(), F.v.as<double>() + (size_t)F.lvl[2] * P * 3);
         }
-        for (int l = 3; l <= L; ++l)
-            fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
-                g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], F.v.as<double>());
+        with_order(F.n, [&](auto o) {
+            for (int l = 3; l <= L; ++l)
+                fmm_l2l_kernel<decltype(o)::value><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                    g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], F.v.as<double>());
+        });
     }
     fmm_near_kernel<WALL, A><<<round_up(F.nwork, 8 * kXcdChunk), kNearBlock, 0, s>>>(
         g, tab, N, L >= 2 ? 1 : 0, F.cc.as<int4>(), F.rng.as<int2>(), F.near_ptr.as<int>(),
@@ -1408,10 +1432,12 @@ void fmm_run6(const FmmState &F, hipStream_t s, const double *x6, double inv_a, 
             fmm_p2m_kernel<A><<<nl, B, 0, s>>>(g, tab, F.cc.as<int4>(), F.rng.as<int2>(),
                                                F.lvl[L], F.shi.as<float4>(), F.slo.as<float4>(),
                                                ch ? st : sf, ch ? qt : qf);
-        for (int l = L - 1; l >= 2; --l)
-            for (int ch = 0; ch < 2; ++ch)
-                fmm_m2m_kernel<A><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
-                    g, tab, F.cc.as<int4>(), F.kids.as<int2>(), F.lvl[l], ch ? qt : qf);
+        with_order(F.n, [&](auto o) {
+            for (int l = L - 1; l >= 2; --l)
+                for (int ch = 0; ch < 2; ++ch)
+                    fmm_m2m_kernel<A, decltype(o)::value><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                        g, tab, F.cc.as<int4>(), F.kids.as<int2>(), F.lvl[l], ch ? qt : qf);
+        });
         const int groups = m2l_groups(P);
         const size_t lds = (size_t)groups * P * (2 * sizeof(Vec4<A>) + sizeof(float4)) +
                            (size_t)6 * (groups - 1) * P * sizeof(double) +
@@ -1430,10 +1456,12 @@ void fmm_run6(const FmmState &F, hipStream_t s, const double *x6, double inv_a, 
                     m, splits, P * 3, F.vsplit.as<double>() + ch * (size_t)nc * splits * P * 3,
                     (ch ? vw : vu) + (size_t)F.lvl[2] * P * 3);
         }
-        for (int l = 3; l <= L; ++l)
-            for (int ch = 0; ch < 2; ++ch)
-                fmm_l2l_kernel<<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
-                    g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], ch ? vw : vu);
+        with_order(F.n, [&](auto o) {
+            for (int l = 3; l <= L; ++l)
+                for (int ch = 0; ch < 2; ++ch)
+                    fmm_l2l_kernel<decltype(o)::value><<<F.lvl[l + 1] - F.lvl[l], B, 0, s>>>(
+                        g, tab, F.cc.as<int4>(), F.parent.as<int>(), F.lvl[l], ch ? vw : vu);
+        });
     }
     fmm_near6_kernel<A><<<round_up(F.nwork, 8 * kXcdChunk), kNearBlock, 0, s>>>(
         g, tab, M, L >= 2 ? 1 : 0, F.cc.as<int4>(), F.rng.as<int2>(), F.near_ptr.as<int>(),

@@ -100,6 +100,57 @@ def test_error_against_dense_falls_with_order(wall):
     assert errs[-1] <= 2e-4
 
 
+def test_every_order_at_four_levels():
+    """Orders 2..8 on the slab above the wall with the leaf level fixed at 4,
+    so that M2M (levels 3, 2) and L2L (levels 3, 4), which are specialised to
+    the order, run at every order: sampled dense rows, the error falling with
+    the order (3e-2 at order 2 to about 1e-6 at order 8)."""
+    sl = W.slab()
+    pos, lam = sl["pos"], sl["lam"]
+    rows = np.random.default_rng(5).choice(len(pos), 48, replace=False)
+    ref = rpy.mobility_apply(pos, lam, 1.0, 1.0, True, targets=rows)
+    errs = []
+    for n in range(2, 9):
+        ctx = arb.arb_create(wall=1, pair_kernel=arb.ARB_PAIR_FMM, fmm_order=n, fmm_levels=4,
+                             precision=arb.ARB_FP64)
+        try:
+            u = arb.arb_rpy_apply(ctx, pos, lam).reshape(-1, 3)
+            assert arb.arb_fmm_get_stats(ctx)["levels"] == 4
+        finally:
+            arb.arb_destroy(ctx)
+        errs.append(np.abs(u[rows] - ref).max() / np.abs(ref).max())
+    print("slab at L=4: sampled max error by order 2..8:", ["%.1e" % e for e in errs], flush=True)
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] <= 1e-5
+
+
+def test_repeated_products_are_bit_identical():
+    """A tree of few cells splits its interaction lists over several M2L
+    items; their sums are added in a fixed order, so products repeat bit for
+    bit (three and six components, both variants)."""
+    pos, lam = blobs(2400, (48, 48, 10), 11)
+    for prec in (arb.ARB_FP64, arb.ARB_FP32C):
+        outs = []
+        for _ in range(2):
+            ctx = arb.arb_create(wall=1, pair_kernel=arb.ARB_PAIR_FMM, fmm_order=4, fmm_levels=2,
+                                 precision=prec)
+            try:
+                outs += [arb.arb_rpy_apply(ctx, pos, lam) for _ in range(2)]
+            finally:
+                arb.arb_destroy(ctx)
+        assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    sb = loose_bodies(2000, (48, 48, 10), 12, 1.0)
+    outs = []
+    for _ in range(2):
+        ctx = arb.context_for(sb, precision=arb.ARB_FP32C, pair_kernel=arb.ARB_PAIR_FMM,
+                              fmm_order=4, fmm_levels=2)
+        try:
+            outs += [arb.arb_body_mobility_apply(ctx, sb.F) for _ in range(2)]
+        finally:
+            arb.arb_destroy(ctx)
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
 def test_options_are_checked():
     for bad in (dict(fmm_order=1), dict(fmm_order=9), dict(fmm_levels=-1), dict(fmm_leaf=-2),
                 dict(pair_kernel=4)):
