@@ -51,6 +51,7 @@
 // refinement.
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <cmath>
 #include <thread>
 #include <type_traits>
@@ -933,28 +934,47 @@ struct FmmPlan {
 int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, int leaf,
              std::string *msg) {
     const int P = n * n * n;
-    for (size_t i = 0; i < 3 * (size_t)N; ++i)
-        if (!std::isfinite(h[i])) {
+    const int T = host_threads(N);
+    // finite positions and the root cube (host threads over slices; min and max
+    // are exact, so the result does not depend on the slicing)
+    std::vector<double> bound(6 * (size_t)T);
+    std::vector<char> bad((size_t)T, 0);
+    parallel_slices(T, N, [&](int t, int i0, int i1) {
+        double *lo = bound.data() + 6 * (size_t)t, *up = lo + 3;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = h[d];
+            up[d] = h[d];
+        }
+        for (int i = i0; i < i1; ++i)
+            for (int d = 0; d < 3; ++d) {
+                const double x = h[3 * (size_t)i + d];
+                if (!std::isfinite(x)) bad[t] = 1;
+                lo[d] = std::min(lo[d], x);
+                up[d] = std::max(up[d], x);
+            }
+    });
+    for (int t = 0; t < T; ++t)
+        if (bad[t]) {
             *msg = "fast product: a position is not finite";
             return ARB_E_NAN;
         }
-    // root cube
     double o[3] = {h[0], h[1], h[2]}, hi_d[3] = {h[0], h[1], h[2]}, ext = 0.0;
-    for (size_t i = 1; i < (size_t)N; ++i)
+    for (int t = 0; t < T; ++t)
         for (int d = 0; d < 3; ++d) {
-            o[d] = std::min(o[d], h[3 * i + d]);
-            hi_d[d] = std::max(hi_d[d], h[3 * i + d]);
+            o[d] = std::min(o[d], bound[6 * (size_t)t + d]);
+            hi_d[d] = std::max(hi_d[d], bound[6 * (size_t)t + 3 + d]);
         }
     for (int d = 0; d < 3; ++d) ext = std::max(ext, hi_d[d] - o[d]);
     const double S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : a;
     int Lhi = 0;  // deepest level with a cell side >= 2a
     while (Lhi < kFmmMaxLevel && S / std::ldexp(1.0, Lhi + 1) >= 2.0 * a) ++Lhi;
-    // cell coordinates at level Lhi and Morton keys (host threads over slices)
-    std::vector<int> crd(3 * (size_t)N);
-    std::vector<uint64_t> key((size_t)N), key2((size_t)N);
-    std::vector<int> idx((size_t)N), idx2((size_t)N);
+    // cell coordinates at level Lhi and Morton keys (host threads over slices;
+    // the arrays are left uninitialised, so that their pages are first touched
+    // by the threads that fill them)
+    std::unique_ptr<int[]> crd(new int[3 * (size_t)N]);
+    std::unique_ptr<uint64_t[]> key(new uint64_t[N]), key2(new uint64_t[N]);
+    std::unique_ptr<int[]> idx(new int[N]), idx2(new int[N]);
     const double scale = std::ldexp(1.0, Lhi);
-    const int T = host_threads(N);
     parallel_slices(T, N, [&](int, int i0, int i1) {
         for (int i = i0; i < i1; ++i) {
             int cq[3];
@@ -1005,18 +1025,24 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
     }
     // the shallowest level at which sorted blob j starts a new cell (a cell
     // starts at every deeper level too): the highest differing key bit / 3
-    std::vector<unsigned char> first((size_t)N, 0);
-    std::vector<int64_t> new_at(Lhi + 2, 0);
-    for (int j = 1; j < N; ++j) {
-        const uint64_t d = key[j] ^ key[j - 1];
-        if (!d) {
-            first[j] = (unsigned char)(Lhi + 1);  // same cell at every level
-            continue;
+    std::unique_ptr<unsigned char[]> first(new unsigned char[N > 0 ? N : 1]);
+    first[0] = 0;
+    std::vector<int64_t> new_at_t((size_t)T * (Lhi + 2), 0), new_at(Lhi + 2, 0);
+    parallel_slices(T, N, [&](int t, int i0, int i1) {
+        int64_t *na = new_at_t.data() + (size_t)t * (Lhi + 2);
+        for (int j = std::max(i0, 1); j < i1; ++j) {
+            const uint64_t d = key[j] ^ key[j - 1];
+            if (!d) {
+                first[j] = (unsigned char)(Lhi + 1);  // same cell at every level
+                continue;
+            }
+            const int hb = 63 - __builtin_clzll(d);
+            first[j] = (unsigned char)(Lhi - hb / 3);
+            ++na[first[j]];
         }
-        const int hb = 63 - __builtin_clzll(d);
-        first[j] = (unsigned char)(Lhi - hb / 3);
-        ++new_at[first[j]];
-    }
+    });
+    for (int t = 0; t < T; ++t)
+        for (int l = 0; l < Lhi + 2; ++l) new_at[l] += new_at_t[(size_t)t * (Lhi + 2) + l];
     // the cells of levels 0..L with their blob ranges, parents and children, the
     // interaction lists, the adjacent leaves and the work items of leaf level L
     auto build = [&](int L, FmmPlan &q) -> int {
@@ -1159,21 +1185,34 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
         // the level with the fewest pair evaluations: deeper from level 2 while
         // the count falls.  Counted level by level (the interaction lists of the
         // shallower levels are the same for every leaf level), then built once.
+        // the cells of level l: each host thread finds the cell starts in its
+        // slice of the sorted blobs, the slices' lists then joined in order
+        std::vector<std::vector<int>> st_t((size_t)T);
         auto cells_of = [&](int l, std::vector<int4> &c4, std::vector<int2> &r2,
                             std::vector<uint64_t> &k) {
-            c4.clear();
-            r2.clear();
-            k.clear();
+            parallel_slices(T, N, [&](int t, int i0, int i1) {
+                std::vector<int> &v = st_t[t];
+                v.clear();
+                for (int j = i0; j < i1; ++j)
+                    if (j == 0 || first[j] <= l) v.push_back(j);
+            });
+            size_t nc = 0;
+            for (int t = 0; t < T; ++t) nc += st_t[t].size();
+            c4.resize(nc);
+            r2.resize(nc);
+            k.resize(nc);
             const int sh = 3 * (Lhi - l), dl = Lhi - l;
-            for (int j0 = 0, j = 1; j <= N; ++j) {
-                if (j < N && first[j] > l) continue;
-                const int i0 = idx[j0];
-                c4.push_back(make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
-                                       crd[3 * (size_t)i0 + 2] >> dl, l));
-                r2.push_back(make_int2(j0, j));
-                k.push_back(key[j0] >> sh);
-                j0 = j;
-            }
+            size_t c = 0;
+            for (int t = 0; t < T; ++t)
+                for (const int j0 : st_t[t]) {
+                    const int i0 = idx[j0];
+                    c4[c] = make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
+                                      crd[3 * (size_t)i0 + 2] >> dl, l);
+                    r2[c] = make_int2(j0, N);
+                    if (c > 0) r2[c - 1].y = j0;
+                    k[c] = key[j0] >> sh;
+                    ++c;
+                }
         };
         std::vector<int4> pc, cc2;
         std::vector<int2> pr, rr;
@@ -1194,30 +1233,38 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                 while (c < cc2.size() && rr[c].x < pr[p].y) par[c++] = (int)p;
                 kid[p] = make_int2((int)c0, (int)c);
             }
-            for (size_t c = 0; c < cc2.size(); ++c) {
-                const int4 q = pc[par[c]];
-                for (int dx = -1; dx <= 1; ++dx)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dz = -1; dz <= 1; ++dz) {
-                            const int g = ph.get(l - 1, q.x + dx, q.y + dy, q.z + dz);
-                            if (g < 0) continue;
-                            for (int ch = kid[g].x; ch < kid[g].y; ++ch)
-                                if (std::abs(cc2[ch].x - cc2[c].x) > 1 ||
-                                    std::abs(cc2[ch].y - cc2[c].y) > 1 ||
-                                    std::abs(cc2[ch].z - cc2[c].z) > 1)
-                                    m2l_total += (int64_t)P * std::min(P, rr[ch].y - rr[ch].x);
-                        }
-            }
+            // integer counts over slices of the cells on host threads
+            const int ncl = (int)cc2.size();
+            const int Tc = std::max(1, std::min(T, ncl / 2048));
+            std::vector<int64_t> part(2 * (size_t)Tc, 0);
+            parallel_slices(Tc, ncl, [&](int t, int c0, int c1) {
+                int64_t m2l = 0, near = 0;
+                for (int c = c0; c < c1; ++c) {
+                    const int4 q = pc[par[c]];
+                    int64_t adj = 0;
+                    for (int dx = -1; dx <= 1; ++dx)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dz = -1; dz <= 1; ++dz) {
+                                const int g = ph.get(l - 1, q.x + dx, q.y + dy, q.z + dz);
+                                if (g >= 0)
+                                    for (int k = kid[g].x; k < kid[g].y; ++k)
+                                        if (std::abs(cc2[k].x - cc2[c].x) > 1 ||
+                                            std::abs(cc2[k].y - cc2[c].y) > 1 ||
+                                            std::abs(cc2[k].z - cc2[c].z) > 1)
+                                            m2l += (int64_t)P * std::min(P, rr[k].y - rr[k].x);
+                                const int e =
+                                    ch.get(l, cc2[c].x + dx, cc2[c].y + dy, cc2[c].z + dz);
+                                if (e >= 0) adj += rr[e].y - rr[e].x;
+                            }
+                    near += adj * (rr[c].y - rr[c].x);
+                }
+                part[2 * (size_t)t] = m2l;
+                part[2 * (size_t)t + 1] = near;
+            });
             int64_t near_pairs = 0;
-            for (size_t c = 0; c < cc2.size(); ++c) {
-                int64_t adj = 0;
-                for (int dx = -1; dx <= 1; ++dx)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dz = -1; dz <= 1; ++dz) {
-                            const int g = ch.get(l, cc2[c].x + dx, cc2[c].y + dy, cc2[c].z + dz);
-                            if (g >= 0) adj += rr[g].y - rr[g].x;
-                        }
-                near_pairs += adj * (rr[c].y - rr[c].x);
+            for (int t = 0; t < Tc; ++t) {
+                m2l_total += part[2 * (size_t)t];
+                near_pairs += part[2 * (size_t)t + 1];
             }
             const int64_t cl = near_pairs + m2l_total;
             if (best >= 0 && cl >= best) break;
@@ -1257,7 +1304,7 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
     pl.o[1] = o[1];
     pl.o[2] = o[2];
     pl.S = S;
-    pl.perm = std::move(idx);  // sorted position -> blob
+    pl.perm.assign(idx.get(), idx.get() + N);  // sorted position -> blob
     pl.tab = std::move(tab);
     return 0;
 }
