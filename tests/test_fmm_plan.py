@@ -142,3 +142,28 @@ def test_plan_of_many_blobs():
     assert st["levels"] == 5
     assert (st["cells"], st["leaves"], st["near_pairs"], st["interactions"], st["m2l_pairs"]) == \
         (cells, leaves, near, inter, m2l)
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_default_level_of_many_blobs(n):
+    """400,000 blobs in a thin slab: the level search counts its pairs on
+    several host threads. Its choice against the rule, with the pair counts of
+    plans at explicit levels (counted by the serial build of the lists): the
+    cost falls down to the chosen level and does not fall one level deeper."""
+    pos = blobs(400_000, (700, 700, 6), 90 + n)
+    st = arb.arb_fmm_plan(pos, 1.0, order=n)
+    L = st["levels"]
+    Lhi = min(fastsum.max_level(pos, 1.0), 16)
+    assert 3 <= L <= Lhi
+
+    def cost(lev):
+        s = arb.arb_fmm_plan(pos, 1.0, order=n, levels=lev)
+        assert s["levels"] == lev
+        return s["near_pairs"] + s["m2l_pairs"]
+
+    costs = [cost(lev) for lev in range(2, L + 1)]
+    assert all(b < a for a, b in zip(costs, costs[1:]))
+    if L < Lhi:
+        assert cost(L + 1) >= costs[-1]
+    ref = arb.arb_fmm_plan(pos, 1.0, order=n, levels=L)
+    assert {k: st[k] for k in st if k != "build_ms"} == {k: ref[k] for k in ref if k != "build_ms"}
