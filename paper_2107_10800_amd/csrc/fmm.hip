@@ -845,6 +845,28 @@ void parallel_slices(int T, int N, F &&f) {
     for (auto &x : th) x.join();
 }
 
+// per-cell lists on host threads: f(c, out) appends the entries of item c to
+// out for c in [0, n); ptr gets the prefix sums of their counts and out the
+// entries joined in item order, as a loop over the items would give them
+template <class V, class F>
+void lists_by_item(int threads, int n, std::vector<int> &ptr, std::vector<V> &out, F &&f) {
+    const int T = std::max(1, std::min(threads, n / 2048));
+    std::vector<std::vector<V>> part((size_t)T);
+    ptr.assign((size_t)n + 1, 0);
+    parallel_slices(T, n, [&](int t, int c0, int c1) {
+        std::vector<V> &v = part[t];
+        for (int c = c0; c < c1; ++c) {
+            const size_t before = v.size();
+            f(c, v);
+            ptr[c + 1] = (int)(v.size() - before);
+        }
+    });
+    for (int c = 0; c < n; ++c) ptr[c + 1] += ptr[c];
+    out.clear();
+    out.reserve((size_t)ptr[n]);
+    for (const std::vector<V> &v : part) out.insert(out.end(), v.begin(), v.end());
+}
+
 // open-addressing map from the Morton keys of one level's cells (< 2^48) to
 // their indices
 struct CellHash {
@@ -1089,35 +1111,34 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                    std::abs(cc[c1].z - cc[c2].z) <= 1;
         };
         // interaction lists (levels 2..L) and the adjacent leaves
-        std::vector<int> il_ptr(ncell + 1, 0), il;
-        for (int c = 0; c < ncell; ++c) {
+        std::vector<int> il_ptr, il;
+        lists_by_item(T, ncell, il_ptr, il, [&](int c, std::vector<int> &out) {
             const int l = cc[c].w;
-            if (l >= 2) {
-                const int4 pc = cc[parent[c]];
-                for (int dx = -1; dx <= 1; ++dx)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dz = -1; dz <= 1; ++dz) {
-                            const int q = find(l - 1, pc.x + dx, pc.y + dy, pc.z + dz);
-                            if (q < 0) continue;
-                            for (int ch = kids[q].x; ch < kids[q].y; ++ch)
-                                if (!adjacent(ch, c)) il.push_back(ch);
-                        }
-            }
-            il_ptr[c + 1] = (int)il.size();
-        }
-        const int leaf0 = lvl[L], nleaf = lvl[L + 1] - lvl[L];
-        std::vector<int> near_ptr(nleaf + 1, 0), nearl;
-        std::vector<int2> work;
-        for (int c = leaf0; c < leaf0 + nleaf; ++c) {
+            if (l < 2) return;
+            const int4 pc = cc[parent[c]];
             for (int dx = -1; dx <= 1; ++dx)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dz = -1; dz <= 1; ++dz) {
-                        const int q = find(L, cc[c].x + dx, cc[c].y + dy, cc[c].z + dz);
-                        if (q >= 0) nearl.push_back(q);
+                        const int q = find(l - 1, pc.x + dx, pc.y + dy, pc.z + dz);
+                        if (q < 0) continue;
+                        for (int ch = kids[q].x; ch < kids[q].y; ++ch)
+                            if (!adjacent(ch, c)) out.push_back(ch);
                     }
-            near_ptr[c - leaf0 + 1] = (int)nearl.size();
+        });
+        const int leaf0 = lvl[L], nleaf = lvl[L + 1] - lvl[L];
+        std::vector<int> near_ptr, nearl;
+        lists_by_item(T, nleaf, near_ptr, nearl, [&](int i, std::vector<int> &out) {
+            const int4 c4 = cc[leaf0 + i];
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int q = find(L, c4.x + dx, c4.y + dy, c4.z + dz);
+                        if (q >= 0) out.push_back(q);
+                    }
+        });
+        std::vector<int2> work;
+        for (int c = leaf0; c < leaf0 + nleaf; ++c)
             for (int k0 = rng[c].x; k0 < rng[c].y; k0 += kNearBlock) work.push_back(make_int2(c, k0));
-        }
         // every target sees every source exactly once: the adjacent leaves and the
         // interaction lists of its ancestors hold N blobs between them, and every
         // index handed to a kernel is in range
