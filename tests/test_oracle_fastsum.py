@@ -13,7 +13,10 @@ it against facts that do not come from that code:
   * with L <= 1 there is no interpolation: the direct RPY sum of the pinned
     dense oracle;
   * with the RPY tensor the error against the dense sum falls geometrically
-    with n (free space and above the wall).
+    with n (free space and above the wall);
+  * the RPY mobility is symmetric, so the approximation is too when both
+    arguments of every far pair are interpolated (every cell holding at least
+    n^3 blobs): a.(M b) = b.(M a), free and above the wall.
 """
 import numpy as np
 import pytest
@@ -161,3 +164,36 @@ def test_generalised_rpy_error_falls_with_order():
     print("generalised RPY, max error by order 2..4:", ["%.1e" % e for e in errs])
     assert errs[0] > 1e-4
     assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))
+
+
+def lattice(shape, spacing, seed, z0=1.5):
+    """Jittered lattice: every cell of the levels used holds several blobs."""
+    rng = np.random.default_rng(seed)
+    g = np.stack(np.meshgrid(*[np.arange(m) for m in shape], indexing="ij"), -1).reshape(-1, 3)
+    pos = (g + 0.5) * spacing + rng.uniform(-0.15, 0.15, g.shape) * spacing
+    pos[:, 2] += z0
+    return pos
+
+
+@pytest.mark.parametrize("wall,shape,n,L", [(False, (24, 24, 6), 2, 3), (False, (12, 12, 6), 3, 2),
+                                            (True, (8, 8, 2), 2, 2)])
+def test_symmetric_when_every_listed_cell_is_interpolated(wall, shape, n, L):
+    """The RPY mobility is symmetric, with or without the wall. When every cell
+    of levels 2..L holds at least n^3 blobs, both arguments of every far pair
+    are interpolated, so the approximation is symmetric too: a.(M b) = b.(M a)
+    to rounding. A weight applied on one side only, a list that is not mutual
+    or a wrong proxy on one side breaks it."""
+    pos = lattice(shape, 2.0, 3)
+    o, S = fastsum.root_cube(pos, 1.0)
+    for lev in range(2, L + 1):
+        _, occ = np.unique(fastsum.cell_coords(pos, o, S, lev), axis=0, return_counts=True)
+        assert occ.min() >= n ** 3
+    rng = np.random.default_rng(4)
+    a, b = rng.standard_normal((2,) + pos.shape)
+    Mb = fastsum.fmm_apply(pos, b, 1.0, 1.0, wall, n, L)
+    Ma = fastsum.fmm_apply(pos, a, 1.0, 1.0, wall, n, L)
+    if not wall:    # really approximated (the oracle's wall tensor is slow)
+        dense = rpy.mobility_apply(pos, b, 1.0, 1.0, wall)
+        assert np.abs(Mb - dense).max() > 1e-4 * np.abs(dense).max()
+    s1, s2 = np.sum(a * Mb), np.sum(b * Ma)
+    assert abs(s1 - s2) <= 1e-12 * np.linalg.norm(a) * np.linalg.norm(Mb)
