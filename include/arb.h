@@ -102,7 +102,7 @@ typedef struct {
                        /* 1 = plain launches                                   */
     int    model;      /* ARB_MODEL_MULTIBLOB (default) or ARB_MODEL_SINGLE_BLOB */
     /* ARB_PAIR_FMM only.  For single-blob bodies the generalised tensor of Sec. 2.4
- * is interpolated with force and torque channels.  The octree's root cube spans
+     * is interpolated with force and torque channels.  The octree's root cube spans
      * the blobs; cells of a level are adjacent when their integer coordinates
      * differ by at most 1.  Pairs in adjacent leaves are summed directly; the
      * tensor between well-separated cells is replaced by its tensor-product
@@ -111,7 +111,10 @@ typedef struct {
      * blobs).  The error falls geometrically with fmm_order (max error
      * relative to the largest entry about 1e-4 at 5, 1e-5 at 6 for dense
      * suspensions).  The tree is rebuilt on the host whenever the state
-     * changes (one device-to-host copy of the positions and a sort).        */
+     * changes (one device-to-host copy of the positions and a sort, on up to
+     * 16 host threads; the tree does not depend on their number).  Products
+     * are deterministic: the same positions and forces give the same result
+     * bit for bit.                                                          */
     int    fmm_order;  /* Chebyshev points per direction, 2..8 (0 = 6)          */
     int    fmm_levels; /* leaf level L; 0 = chosen: with fmm_leaf > 0 the       */
                        /* shallowest level whose mean occupancy is <= fmm_leaf, */
