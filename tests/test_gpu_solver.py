@@ -4,10 +4,14 @@ Steps: blob geometry (Sec. 2.3), K / K^T (Eq. no-slip, Eq. balance), constraint
 rows C, B (Eq. dg, App. A), the saddle operator A (Eq. linear_system), the block
 preconditioner (Sec. 3.1), GMRES, Euler update and position correction
 (Sec. 4.2-4.3, App. B).  FP64 path: operators at 1e-12 relative (1e-14 for
-the linear rigid-body maps); solve outputs at max(1e-12, 10 kappa(A) r) for a
-relative residual r, the forward-error bound of any solver on A; FP32C path
-(FP32 pair sums inside FP64 iterative refinement): FP64 residual <= tol and
-outputs within max(1e-5, 10 kappa(A) r_fp64).
+the linear rigid-body maps); the GPU solve against the oracle's GMRES (the same
+algorithm, the same steps) at 1e-12 relative L2 on each output (U, phi,
+lambda).  Comparisons with the direct (dense LU) solution are bounded by what
+any solver can reach at relative residual r, 10 kappa(A) r: that bar is used
+there and only there.  FP32C path (FP32 pair sums inside FP64 iterative
+refinement): the refinement is driven to r = 1e-5 / (10 kappa(A)) so that each
+output is within 1e-5 of the direct solution; the errors at the practical
+tolerance 1e-6 are reported beside.
 """
 import numpy as np
 import pytest
@@ -41,10 +45,20 @@ def kappa(A):
 
 
 def solve_tol(S, r):
-    """Forward-error bar for a solution with relative residual r: any solver
-    meets ||dy||/||y|| <= kappa(A) r, so the FP64 bar of 1e-12 is applied
-    where the conditioning allows it and 10 kappa r beyond that."""
+    """Forward-error bar against the direct solution for an iterate with
+    relative residual r: any solver meets ||dy||/||y|| <= kappa(A) r, so the
+    FP64 bar of 1e-12 is applied where the conditioning allows it and
+    10 kappa r beyond that.  Used only against the direct solve."""
     return max(1e-12, 10.0 * S["kappa"] * max(r, 2.0 ** -52))
+
+
+def outputs(wl, y):
+    """Split y = [lambda; U; phi] into its three outputs."""
+    N, M = wl.N, wl.M
+    out = dict(lam=y[:3 * N], U=y[3 * N:3 * N + 6 * M])
+    if wl.n_rows:
+        out["phi"] = y[3 * N + 6 * M:]
+    return out
 
 
 @pytest.fixture(scope="module", params=list(cases()))
@@ -112,11 +126,13 @@ def test_gmres_solve(case):
     P = precond.BlockPreconditioner(wl, S["r"], S["C"])
     y, oinfo = gmres.gmres(lambda v: S["A"] @ v, P.apply, S["b"], tol=1e-10)
     yg = np.concatenate([lam.ravel(), U.ravel(), phi])
-    # same algorithm on both sides: same iteration count and close iterates
+    # same algorithm on both sides: same iteration count and iterates that
+    # agree to 1e-12 on every output
     assert abs(info["iterations"] - oinfo["iterations"]) <= 1
-    tol = solve_tol(S, max(info["rel_residual"], oinfo["true_rel"]))
-    print(f"  gpu-vs-oracle gmres {rel(yg, y):.2e} (bar {tol:.1e}), kappa {S['kappa']:.1e}")
-    assert rel(yg, y) <= tol
+    errs = {k: rel(v, outputs(wl, y)[k]) for k, v in outputs(wl, yg).items()}
+    print(f"  gpu-vs-oracle gmres {errs}, iterations {info['iterations']} / "
+          f"{oinfo['iterations']}, kappa {S['kappa']:.1e}")
+    assert all(e <= 1e-12 for e in errs.values())
     yd = system.solve_dense(S["A"], S["b"])
     N, M = wl.N, wl.M
     assert rel(U, yd[3 * N:3 * N + 6 * M]) <= solve_tol(S, info["rel_residual"])
@@ -142,25 +158,31 @@ def test_gmres_tight_matches_direct(case):
 
 
 def test_fp32c_solve(case):
-    # FP32 pair sums inside GMRES iterative refinement with FP64 residuals: the
-    # returned iterate meets the tolerance in FP64, and each output is within
-    # the forward-error bar of that residual, never looser than 1e-5
+    # FP32 pair sums inside GMRES iterative refinement with FP64 residuals.  The
+    # returned iterate meets the tolerance in FP64.  Driven to
+    # r = 1e-5 / (10 kappa), every output is within 1e-5 of the direct solution
+    # (the forward-error bound); at the practical tolerance 1e-6 the errors are
+    # reported only, since there they are bounded by kappa * 1e-6
     name, wl, S, ctx = case
-    c2 = arb.context_for(wl, precision=arb.ARB_FP32C, tol=1e-6)
-    try:
-        rc, U, phi, lam, info = arb.arb_solve(c2, wl.F, u_slip=wl.u_slip)
-    finally:
-        arb.arb_destroy(c2)
-    assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
-    assert info["rel_residual_fp64"] <= 1e-6
     yd = system.solve_dense(S["A"], S["b"])
-    N, M = wl.N, wl.M
-    tol = max(1e-5, 10.0 * S["kappa"] * info["rel_residual_fp64"])
-    errs = dict(U=rel(U, yd[3 * N:3 * N + 6 * M]), lam=rel(lam, yd[:3 * N]))
-    if wl.n_rows:
-        errs["phi"] = rel(phi, yd[3 * N + 6 * M:])
-    print(f"  fp32c solve errors {errs} residual {info['rel_residual_fp64']:.1e} bar {tol:.1e}")
-    assert all(e <= tol for e in errs.values())
+    ref = outputs(wl, yd)
+    tight = 1e-5 / (10.0 * S["kappa"])
+    for tol in (1e-6, tight):
+        c2 = arb.context_for(wl, precision=arb.ARB_FP32C, tol=tol)
+        try:
+            rc, U, phi, lam, info = arb.arb_solve(c2, wl.F, u_slip=wl.u_slip)
+        finally:
+            arb.arb_destroy(c2)
+        assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
+        assert info["rel_residual_fp64"] <= tol
+        got = dict(lam=lam.ravel(), U=U.ravel())
+        if wl.n_rows:
+            got["phi"] = phi
+        errs = {k: rel(got[k], ref[k]) for k in ref}
+        print(f"  fp32c solve to {tol:.1e}: errors {errs} residual "
+              f"{info['rel_residual_fp64']:.1e}, {info['iterations']} iterations, "
+              f"{info['products_fp64']} FP64 products")
+    assert all(e <= 1e-5 for e in errs.values())
 
 
 def test_rank_deficient_hinge_uses_pinv():
