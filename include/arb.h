@@ -236,6 +236,23 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev,
 int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda,
                   double *u);
 
+/* Allocation-free version of arb_rpy_apply_dev, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops, hosts
+ * that forbid hipMalloc).  Same arguments and result; it always runs the
+ * target-parallel kernel (ctx's slices, else a heuristic count, at most what
+ * the scratch holds: 4 slices at the maximum size), so with
+ * pair_kernel = ARB_PAIR_TARGET and the same slices it matches
+ * arb_rpy_apply_dev bit for bit.  Every intermediate lives in one static
+ * device array of 10 MiB per device, held until the process ends: N may not
+ * exceed ARB_NOALLOC_MAX_BLOBS (ARB_E_ARG with a message otherwise), and the
+ * fast product is refused (ARB_E_ARG).  Calls on one device share that array:
+ * calls that overlap in time on one device (other host threads, other
+ * streams) race and give undefined results.  No device memory is allocated
+ * or freed. */
+#define ARB_NOALLOC_MAX_BLOBS 65536
+int arb_rpy_apply_noalloc_dev(arb_ctx *ctx, int N, const double *pos_dev,
+                              const double *lambda_dev, double *u_dev, void *stream);
+
 /* Body mobility of single-blob bodies (Sec. 2.4; ARB_MODEL_SINGLE_BLOB only):
  * UW = N FT with N the unbounded generalised RPY tensor (all ordered body
  * pairs, self blocks included) at the context's state.  FT: 6M (f, tau per

@@ -38,6 +38,7 @@ ARB_PAIR_AUTO = 0
 ARB_PAIR_TARGET = 1
 ARB_PAIR_SYMMETRIC = 2
 ARB_PAIR_FMM = 3
+ARB_NOALLOC_MAX_BLOBS = 65536
 
 SYMBOLS = [
     "arb_create", "arb_destroy", "arb_last_error", "arb_get_slices", "arb_set_bodies",
@@ -50,7 +51,7 @@ SYMBOLS = [
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
     "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
     "arb_body_mobility_apply", "arb_body_mobility_apply_dev", "arb_step_midpoint",
-    "arb_fmm_get_stats", "arb_fmm_plan",
+    "arb_fmm_get_stats", "arb_fmm_plan", "arb_rpy_apply_noalloc_dev",
 ]
 
 
@@ -135,6 +136,7 @@ def load():
         "arb_mobility_apply_dev": (C.c_int, [_P, _P, _P, _P]),
         "arb_rpy_apply_dev": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
         "arb_rpy_apply": (C.c_int, [_P, C.c_int, _DP, _DP, _DP]),
+        "arb_rpy_apply_noalloc_dev": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
         "arb_system_apply": (C.c_int, [_P, _DP, _DP]),
         "arb_K_apply": (C.c_int, [_P, _DP, _DP]),
         "arb_KT_apply": (C.c_int, [_P, _DP, _DP]),
@@ -330,6 +332,12 @@ def arb_rpy_apply(ctx, pos, lam):
 def arb_rpy_apply_dev(ctx, N, pos_dev, lam_dev, u_dev, stream=None):
     return _check(ctx, load().arb_rpy_apply_dev(ctx, int(N), _ptr(pos_dev), _ptr(lam_dev),
                                                 _ptr(u_dev), _ptr(stream)))
+
+
+def arb_rpy_apply_noalloc_dev(ctx, N, pos_dev, lam_dev, u_dev, stream=None):
+    return _check(ctx, load().arb_rpy_apply_noalloc_dev(ctx, int(N), _ptr(pos_dev),
+                                                        _ptr(lam_dev), _ptr(u_dev),
+                                                        _ptr(stream)))
 
 
 def arb_system_apply(ctx, y):

@@ -274,12 +274,7 @@ int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- pair launch
-int heuristic_slices(int N) {
-    const int ntiles = (N + arb::kTile - 1) / arb::kTile;
-    int s = 1;
-    while ((int64_t)ntiles * s * 2 <= 2048 && s * 2 <= ntiles) s *= 2;
-    return s;
-}
+using arb::heuristic_slices;
 
 int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R, int precision) {
     const int pi = precision == ARB_FP32C ? 1 : 0;
@@ -1110,6 +1105,9 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || opt->device < 0 || opt->device >= ndev)
         return ARB_E_DEVICE;
     if (hipSetDevice(opt->device) != hipSuccess) return ARB_E_DEVICE;
+    // the allocation-free entry point's scratch address on this device (its
+    // own calls report a failed lookup)
+    (void)arb::noalloc_setup(opt->device);
     ctx = new arb_ctx();
     ctx->opt = *opt;
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||

@@ -115,6 +115,12 @@ void fmm_apply6(const FmmState &F, hipStream_t s, bool fp64, const double *x6, d
 // then an ordered reduction.  Positions are prepared by prep_positions().
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
                     float4 *hi, float4 *lo);
+// device address of the allocation-free entry point's scratch array for the
+// current device (noalloc.hip), looked up once per device; 0 when known
+int noalloc_setup(int device);
+// source slices of the target-parallel kernel when none are given: doubled while
+// the grid stays within about 2,048 workgroups and every slice keeps a tile
+int heuristic_slices(int N);
 // returns the number of slices written (clamped to the tile count)
 int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
                   const float4 *hi, const float4 *lo, const double *lam, double a,

@@ -206,6 +206,13 @@ void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, doubl
     prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo);
 }
 
+int heuristic_slices(int N) {
+    const int ntiles = (N + kTile - 1) / kTile;
+    int s = 1;
+    while ((int64_t)ntiles * s * 2 <= 2048 && s * 2 <= ntiles) s *= 2;
+    return s;
+}
+
 int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
                   const float4 *hi, const float4 *lo, const double *lam, double a, int slices,
                   double *partial) {
