@@ -13,6 +13,10 @@ are documented where they are taken.
 Modules
   quat      unit quaternions and rotation matrices (Sec. 2.1, App. B)
   rpy       RPY blob mobility, unbounded and above a no-slip wall (Sec. 2.3)
+  rpy_c     the same mobility as plain C loops (rpy_sum.c, OpenMP over targets;
+            the wall image generated from rpy's symbolic definition by
+            gen_wall_image_c.py): full products, dense matrices and solves at
+            tens of thousands of blobs, and the timed CPU baseline
   bodies    blob positions, K, constraint Jacobian C and B (Sec. 2.2-2.3, App. A)
   system    the saddle system A y = b and its direct solutions (Sec. 2.2-2.3)
   precond   block-diagonal preconditioner (Sec. 3.1)

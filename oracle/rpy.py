@@ -50,8 +50,9 @@ def rpy_free_blocks(rvec: np.ndarray, a: float, eta: float) -> np.ndarray:
 
 
 @functools.lru_cache(maxsize=1)
-def _wall_image_fn():
-    """Lambdified F_x F_y (G^Blake - G^Oseen) as a function of (x, y, a)."""
+def wall_image_exprs():
+    """((x1, x2, x3), (y1, y2, y3), a, exprs): the nine components (row-major) of
+    F_x F_y (G^Blake - G^Oseen)(x, y) as sympy expressions."""
     import sympy as sp
 
     x = sp.symbols("x1:4", real=True)
@@ -82,6 +83,15 @@ def _wall_image_fn():
             w = image(i, j)
             lx = lap(w, x)
             exprs.append(w + a ** 2 / 6 * (lx + lap(w, y)) + a ** 4 / 36 * lap(lx, y))
+    return x, y, a, exprs
+
+
+@functools.lru_cache(maxsize=1)
+def _wall_image_fn():
+    """Lambdified F_x F_y (G^Blake - G^Oseen) as a function of (x, y, a)."""
+    import sympy as sp
+
+    x, y, a, exprs = wall_image_exprs()
     return sp.lambdify((*x, *y, a), exprs, "numpy", cse=True)
 
 
