@@ -124,6 +124,13 @@ typedef struct {
                        /* deeper than the deepest level with a cell             */
                        /* side >= 2a; L <= 1 gives the direct sum               */
     int    fmm_leaf;   /* mean blobs per leaf aimed at (0 = see fmm_levels)     */
+    int    left_precond; /* 0 = right preconditioning A P^-1 (default): the     */
+                       /* Krylov residual is the true residual; 1 = left       */
+                       /* preconditioning P^-1 A, the form Sec. 3.1 names: the */
+                       /* Givens recursion tracks ||P^-1 (b - A y)||, a cycle  */
+                       /* stops when that has fallen by the factor the true    */
+                       /* residual still has to fall, and the stopping test is */
+                       /* always on the true residual ||b - A y|| <= tol ||b|| */
 } arb_options;
 
 typedef struct {
@@ -287,8 +294,9 @@ int arb_precond_apply(arb_ctx *ctx, const double *r, double *z);
 int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde);
 
 /* -------------------------------------------------------------- solve
- * Solve A y = b with b = [u_s; -F; B] (Eq. linear_system) by restarted,
- * right-preconditioned GMRES to ||b - A y|| <= tol ||b|| in FP64.  With
+ * Solve A y = b with b = [u_s; -F; B] (Eq. linear_system) by restarted
+ * GMRES (right-preconditioned, or left with opt.left_precond) to
+ * ||b - A y|| <= tol ||b|| in FP64.  With
  * ARB_FP32C the solve is GMRES iterative refinement: inner GMRES with the FP32
  * pair sum on the correction equation, residuals formed in FP64.  F: 6M;
  * u_slip: 3N or NULL (zero); y0: n or NULL (zero initial guess, Sec. 3.2.1

@@ -12,17 +12,30 @@ The paper uses preconditioned GMRES with tolerance epsilon and warm starts
   * stop when the Givens residual estimate is <= tol ||b||; the iterate is then
     formed and the true residual recomputed; if it is still above tol ||b||
     the method restarts from that iterate.
+
+Left preconditioning (the paper's own word, Sec. 3.1) is the option
+``left=True``: the Krylov space is that of P^-1 A started from
+z0 = P^-1 r0, and the Givens recursion then estimates the preconditioned
+residual ||P^-1 (b - A y)||.  A cycle stops when that estimate has fallen by
+the factor the true residual still has to fall, tol ||b|| / ||r0||; the
+iterate y + V s is formed (no preconditioner at the end) and the stopping
+test is always taken on the true residual ||b - A y|| <= tol ||b||,
+restarting from y otherwise.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def gmres(A_apply, P_apply, b, tol=1e-10, restart=100, max_iter=1000, y0=None, record=None):
+def gmres(A_apply, P_apply, b, tol=1e-10, restart=100, max_iter=1000, y0=None, record=None,
+          left=False):
     """Return (y, info) with info = dict(iterations, restarts, history, true_rel, converged).
 
     ``record`` (a dict) receives the Arnoldi basis V and the unrotated
-    Hessenberg matrix of the first cycle, for checking the Arnoldi relation."""
+    Hessenberg matrix of the first cycle, for checking the Arnoldi relation.
+    ``left``: left preconditioning (module docstring); history then holds the
+    true relative residual at each cycle start and the preconditioned
+    estimates scaled to it inside a cycle."""
     b = np.asarray(b, float)
     n = len(b)
     bnorm = np.linalg.norm(b)
@@ -45,11 +58,23 @@ def gmres(A_apply, P_apply, b, tol=1e-10, restart=100, max_iter=1000, y0=None, r
         cs = np.zeros(m)
         sn = np.zeros(m)
         g = np.zeros(m + 1)
+        if left:
+            # Krylov space of P^-1 A from P^-1 r; the cycle's target is the
+            # preconditioned residual cut by the factor the true one needs
+            z = P_apply(r)
+            rnorm = beta
+            beta = np.linalg.norm(z)
+            target = tol * bnorm / rnorm * beta
+            scale = rnorm / beta
+            V[0] = z / beta
+        else:
+            target = tol * bnorm
+            scale = 1.0
+            V[0] = r / beta
         g[0] = beta
-        V[0] = r / beta
         k = 0
         for j in range(m):
-            w = A_apply(P_apply(V[j]))
+            w = P_apply(A_apply(V[j])) if left else A_apply(P_apply(V[j]))
             h = V[:j + 1] @ w
             w = w - V[:j + 1].T @ h
             h2 = V[:j + 1] @ w
@@ -79,14 +104,14 @@ def gmres(A_apply, P_apply, b, tol=1e-10, restart=100, max_iter=1000, y0=None, r
             total += 1
             k = j + 1
             est = abs(g[j + 1])
-            hist.append(est / bnorm)
-            if est <= tol * bnorm or total >= max_iter or hn == 0.0:
+            hist.append(est * scale / bnorm)
+            if est <= target or total >= max_iter or hn == 0.0:
                 break
             V[j + 1] = w / hn
         s = np.zeros(k)
         for i in range(k - 1, -1, -1):
             s[i] = (g[i] - H[i, i + 1:k] @ s[i + 1:k]) / H[i, i]
-        y = y + P_apply(V[:k].T @ s)
+        y = y + (V[:k].T @ s if left else P_apply(V[:k].T @ s))
         r = b - A_apply(y)
         restarts += 1
         hist.pop()          # the estimate is replaced by the true residual below

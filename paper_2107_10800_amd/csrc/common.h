@@ -209,6 +209,14 @@ void gemv_set(hipStream_t s, int64_t n, int k, const double *V, int64_t ldv, con
               double *out);
 void scale_copy(hipStream_t s, int64_t n, const double *x, const double *alpha_dev, double *y);
 void axpby(hipStream_t s, int64_t n, double a, const double *x, double b, double *y);
+// largest system (unknowns) whose Arnoldi orthogonalisation runs in one
+// workgroup (arnoldi_small), and the largest restart length
+constexpr int kSmallArnoldi = 4096;
+constexpr int kMaxRestart = 256;
+// CGS2 + norm + Givens update of Arnoldi step j for n <= kSmallArnoldi in one
+// launch: w is orthogonalised in place; out[0] = ||w||, out[1] = |g[j+1]|
+void arnoldi_small(hipStream_t s, int64_t n, int j, int m, const double *V, int64_t ldv,
+                   double *w, double *Hbar, double *cs, double *sn, double *g, double *out);
 void arnoldi_post(hipStream_t s, int j, int m, const double *h1, const double *h2,
                   const double *hn2, double *Hbar, double *cs, double *sn, double *g,
                   double *out);
@@ -297,6 +305,9 @@ void reconstruct(hipStream_t s, const ReconDev &D, int rebuild);
 // ---------------------------------------------------------------- context
 // HIP graphs of the GMRES iteration, one per Arnoldi index j >= 1, valid for
 // the key they were captured under
+constexpr int kPinnedScalars = 64;
+constexpr int kPinnedTotal = kPinnedScalars + 2 * 260;
+
 struct GmresGraphs {
     std::vector<hipGraphExec_t> exec;
     std::vector<long long> key;
@@ -353,7 +364,12 @@ struct arb_ctx {
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
-    double *pinned = nullptr;  // host pinned scratch (small)
+    // host pinned scratch: kPinnedScalars doubles for entry points, then two per
+    // Arnoldi step (h_{j+1,j}, residual estimate) at pinned + kPinnedScalars
+    double *pinned = nullptr;
+    // one event per Arnoldi step of a cycle: the host waits on step j's scalars
+    // while later steps may already run
+    std::vector<hipEvent_t> step_ev;
     GmresGraphs ggraph;
     // articulated bodies (bodies joined by links) for the correction and the
     // reconstruction, rebuilt when bodies or links change

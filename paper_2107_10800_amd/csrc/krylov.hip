@@ -89,19 +89,15 @@ __global__ void axpby_kernel(int64_t n, double a, const double *__restrict__ x, 
     if (t < n) y[t] = a * x[t] + b * y[t];
 }
 
-// hcol[0..j] = first CGS pass h, hcol2[0..j] = second pass, hn2 = ||w||^2.
+// h1[0..j] = first CGS pass h, h2[0..j] = second pass, hn2 = ||w||^2.
 // Applies the previous rotations, builds rotation j, updates g, stores the
 // rotated column in Hbar (column-major, ld = m+1), writes hn = ||w|| and the
-// residual estimate |g[j+1]| to out[0], out[1].
-__global__ void arnoldi_post_kernel(int j, int m, const double *__restrict__ h1,
-                                    const double *__restrict__ h2, const double *__restrict__ hn2,
-                                    double *__restrict__ Hbar, double *__restrict__ cs,
-                                    double *__restrict__ sn, double *__restrict__ g,
-                                    double *__restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// residual estimate |g[j+1]| to out[0], out[1].  One thread.
+__device__ void arnoldi_post_dev(int j, int m, const double *h1, const double *h2, double hn2,
+                                 double *Hbar, double *cs, double *sn, double *g, double *out) {
     double *col = Hbar + (int64_t)j * (m + 1);
     for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-    const double hn = sqrt(hn2[0]);
+    const double hn = sqrt(hn2);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
         const double t = cs[i] * col[i] + sn[i] * col[i + 1];
@@ -117,6 +113,63 @@ __global__ void arnoldi_post_kernel(int j, int m, const double *__restrict__ h1,
     g[j] = cs[j] * g[j];
     out[0] = hn;
     out[1] = fabs(g[j + 1]);
+}
+
+__global__ void arnoldi_post_kernel(int j, int m, const double *__restrict__ h1,
+                                    const double *__restrict__ h2, const double *__restrict__ hn2,
+                                    double *__restrict__ Hbar, double *__restrict__ cs,
+                                    double *__restrict__ sn, double *__restrict__ g,
+                                    double *__restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    arnoldi_post_dev(j, m, h1, h2, hn2[0], Hbar, cs, sn, g, out);
+}
+
+// The whole orthogonalisation of one Arnoldi step for a system of at most
+// kSmallArnoldi unknowns in one workgroup: w against V_0..V_j by classical
+// Gram-Schmidt twice (w held in LDS), ||w||, then the Givens update of
+// arnoldi_post.  One launch instead of nine; the same steps with a different
+// summation order (one wave per dot product, lanes strided over the rows).
+__global__ __launch_bounds__(1024) void arnoldi_small_kernel(
+    int n, int j, int m, const double *__restrict__ V, int64_t ldv, double *__restrict__ w,
+    double *__restrict__ Hbar, double *__restrict__ cs, double *__restrict__ sn,
+    double *__restrict__ g, double *__restrict__ out) {
+    __shared__ double ws[kSmallArnoldi];
+    __shared__ double hs[2][kMaxRestart + 1];
+    __shared__ double red[1024 / kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    constexpr int nwave = 1024 / kWave;
+    for (int t = tid; t < n; t += 1024) ws[t] = w[t];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        double *h = hs[pass];
+        for (int i = wave; i <= j; i += nwave) {
+            const double *v = V + (int64_t)i * ldv;
+            double sacc = 0.0;
+            for (int t = lane; t < n; t += kWave) sacc += v[t] * ws[t];
+            for (int off = kWave / 2; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+            if (lane == 0) h[i] = sacc;
+        }
+        __syncthreads();
+        for (int t = tid; t < n; t += 1024) {
+            double acc = 0.0;
+            for (int i = 0; i <= j; ++i) acc += V[(int64_t)i * ldv + t] * h[i];
+            ws[t] -= acc;
+        }
+        __syncthreads();
+    }
+    double sq = 0.0;
+    for (int t = tid; t < n; t += 1024) {
+        sq += ws[t] * ws[t];
+        w[t] = ws[t];
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if (lane == 0) red[wave] = sq;
+    __syncthreads();
+    if (tid == 0) {
+        double hn2 = 0.0;
+        for (int k = 0; k < nwave; ++k) hn2 += red[k];
+        arnoldi_post_dev(j, m, hs[0], hs[1], hn2, Hbar, cs, sn, g, out);
+    }
 }
 
 // back substitution of the rotated (upper-triangular) Hessenberg: s = H^-1 g
@@ -177,6 +230,10 @@ void arnoldi_post(hipStream_t s, int j, int m, const double *h1, const double *h
                   const double *hn2, double *Hbar, double *cs, double *sn, double *g,
                   double *out) {
     arnoldi_post_kernel<<<1, 64, 0, s>>>(j, m, h1, h2, hn2, Hbar, cs, sn, g, out);
+}
+void arnoldi_small(hipStream_t s, int64_t n, int j, int m, const double *V, int64_t ldv,
+                   double *w, double *Hbar, double *cs, double *sn, double *g, double *out) {
+    arnoldi_small_kernel<<<1, 1024, 0, s>>>((int)n, j, m, V, ldv, w, Hbar, cs, sn, g, out);
 }
 void upper_solve(hipStream_t s, int k, int m, const double *Hbar, const double *g, double *sv) {
     upper_solve_kernel<<<1, 64, 0, s>>>(k, m, Hbar, g, sv);

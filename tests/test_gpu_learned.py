@@ -136,13 +136,15 @@ def test_standardised_forward_matches_oracle(ctx):
 
 @pytest.fixture(scope="module")
 def trained():
-    X, T = learned.make_dataset(4096, seed=21)
+    # the benchmark's recipe: 2e5 body poses (1e5 bacteria) labelled by the exact
+    # block build, 400 epochs of batch 1,024 (about 15 s on the GPU)
+    X, T = learned.make_dataset(100000, seed=101)
     sc = learned.scaling(X, T)
     c = arb.arb_create(precision=arb.ARB_FP64, wall=True)
     learned.load_model(c, W.mlp_init_weights(seed=6), sc)
-    l0 = arb.arb_mlp_grad(c, X, T)[0]
-    learned.train(c, X, T, epochs=60, batch=512, lr=3e-3, seed=7)
-    l1 = arb.arb_mlp_grad(c, X, T)[0]
+    l0 = arb.arb_mlp_grad(c, X[:20000], T[:20000])[0]
+    learned.train(c, X, T, epochs=400, batch=1024, lr=2e-3, seed=7)
+    l1 = arb.arb_mlp_grad(c, X[:20000], T[:20000])[0]
     P = arb.arb_mlp_get_params(c)
     Y = arb.arb_mlp_forward(c, X[:2000])
     arb.arb_destroy(c)
@@ -159,42 +161,62 @@ def test_training_reduces_loss(trained):
     assert l1 < 0.05 * l0
 
 
-def bar_of(S, info):
+def kappa_of(S):
     s = np.linalg.svd(S["A"], compute_uv=False)
-    return max(1e-5, 10 * s[0] / s[-1] * info["rel_residual_fp64"])
+    return s[0] / s[-1]
 
 
 @pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
 def test_learned_preconditioner_solution(trained, prec):
+    # a preconditioner changes iterations, not the solution.  FP64: every block
+    # variant solves to 1e-8 and lands within the forward-error bound 10 kappa r
+    # of the direct solution.  FP32C: the learned solve driven to
+    # r = 1e-5 / (10 kappa) is within 1e-5 of the direct solution on U, phi and
+    # lambda.  What the network buys over the method without it (the unbounded
+    # body-frame blocks, which need no per-solve work either): fewer iterations
     model = trained[0]
     wl = W.bacteria(n_bact=4, side=60.0, seed=21)
     S = system.assemble(wl)
+    kap = kappa_of(S)
     yd = system.solve_dense(S["A"], S["b"])
     N, M = wl.N, wl.M
-    out = {}
-    for pc in (arb.ARB_PC_BLOCK, arb.ARB_PC_LEARNED, arb.ARB_PC_BODYFRAME):
-        c = arb.context_for(wl, precision=prec, tol=1e-8 if prec == arb.ARB_FP64 else 1e-6,
-                            precond=pc)
+    ref = dict(lam=yd[:3 * N], U=yd[3 * N:3 * N + 6 * M], phi=yd[3 * N + 6 * M:])
+    tol = 1e-8 if prec == arb.ARB_FP64 else 1e-6
+
+    def solve(pc, t):
+        c = arb.context_for(wl, precision=prec, tol=t, precond=pc)
         try:
             learned.load_model(c, *model)
             rc, U, phi, lam, info = arb.arb_solve(c, wl.F)
         finally:
             arb.arb_destroy(c)
         assert rc == arb.ARB_OK
-        out[pc] = (U, info)
-    U, info = out[arb.ARB_PC_LEARNED]
-    Ue, infoe = out[arb.ARB_PC_BLOCK]
-    infob = out[arb.ARB_PC_BODYFRAME][1]
+        assert info["rel_residual_fp64"] <= t
+        return dict(lam=lam.ravel(), U=U.ravel(), phi=phi), info
+
+    out = {pc: solve(pc, tol) for pc in (arb.ARB_PC_BLOCK, arb.ARB_PC_LEARNED,
+                                         arb.ARB_PC_BODYFRAME)}
+    infoe, info, infob = (out[pc][1] for pc in (arb.ARB_PC_BLOCK, arb.ARB_PC_LEARNED,
+                                                 arb.ARB_PC_BODYFRAME))
     print(f"prec {prec}: iterations exact {infoe['iterations']} learned {info['iterations']} "
           f"body-frame {infob['iterations']}, build ms exact {infoe['t_build_ms']:.2f} "
           f"learned {info['t_build_ms']:.2f} body-frame {infob['t_build_ms']:.2f}")
-    assert rel(out[arb.ARB_PC_BODYFRAME][0], Ue) <= 2 * max(1e-5, bar_of(S, infob))
-    assert info["rel_residual_fp64"] <= (1e-8 if prec == arb.ARB_FP64 else 1e-6)
-    bar = bar_of(S, info)
-    assert rel(U, yd[3 * N:3 * N + 6 * M]) <= bar
-    assert rel(U, Ue) <= 2 * bar
-    # the corrected learned blocks are about as strong as the exact ones
-    assert info["iterations"] <= infoe["iterations"] + 2
+    for pc, (y, inf) in out.items():
+        bar = max(1e-12, 10 * kap * inf["rel_residual_fp64"])
+        errs = {k: rel(y[k], ref[k]) for k in ref}
+        print(f"  pc {pc} to {tol:.0e}: errors {errs} (forward-error bar {bar:.1e})")
+        assert all(e <= bar for e in errs.values())
+    # the corrected learned blocks are as strong as the exact ones (measured:
+    # the same count on 4 to 256 bacteria) and stronger than the body-frame
+    # blocks without the network (one iteration more on each of those cases)
+    assert info["iterations"] <= infoe["iterations"] + 1
+    assert info["iterations"] < infob["iterations"]
+    if prec == arb.ARB_FP32C:
+        tight = 1e-5 / (10 * kap)
+        y, inf = solve(arb.ARB_PC_LEARNED, tight)
+        errs = {k: rel(y[k], ref[k]) for k in ref}
+        print(f"  learned fp32c to {tight:.1e}: errors {errs}, {inf['iterations']} iterations")
+        assert all(e <= 1e-5 for e in errs.values())
 
 
 def test_learned_apply_matches_oracle(trained):
@@ -251,13 +273,17 @@ def test_learned_fallback_on_invalid_factor():
 
 def test_full_size_learned_solve(trained):
     # 4,096 bacteria above the wall: the learned-block FP32 solve and the plain
-    # FP64 exact-block solve both reach 1e-6, and their velocities agree to 1e-5
+    # FP64 exact-block solve both reach 1e-6, and their velocities agree to 1e-5.
+    # What the network buys: the iteration count of the exact blocks (fewer
+    # than the body-frame blocks, the method without it) at a small fraction
+    # of the exact build
     model = trained[0]
     wl = W.bacteria(n_bact=4096, seed=5)
     print(f"full size learned: N={wl.N} M={wl.M} Nc={wl.n_rows}", flush=True)
-    out = {}
+    out, infos = {}, {}
     for name, prec, pc in (("exact_fp64", arb.ARB_FP64, arb.ARB_PC_BLOCK),
-                           ("learned_fp32", arb.ARB_FP32C, arb.ARB_PC_LEARNED)):
+                           ("learned_fp32", arb.ARB_FP32C, arb.ARB_PC_LEARNED),
+                           ("bodyframe_fp32", arb.ARB_FP32C, arb.ARB_PC_BODYFRAME)):
         c = arb.context_for(wl, precision=prec, tol=1e-6, restart=100, max_iter=1000,
                             precond=pc)
         try:
@@ -267,6 +293,11 @@ def test_full_size_learned_solve(trained):
             arb.arb_destroy(c)
         assert rc == arb.ARB_OK
         assert info["rel_residual_fp64"] <= 1e-6
-        print(f"  {name}: {info['iterations']} iterations", flush=True)
+        print(f"  {name}: {info['iterations']} iterations, build {info['t_build_ms']:.2f} ms, "
+              f"solve {info['t_solve_ms']:.1f} ms", flush=True)
         out[name] = U
+        infos[name] = info
     assert rel(out["learned_fp32"], out["exact_fp64"]) <= 1e-5
+    assert infos["learned_fp32"]["iterations"] <= infos["exact_fp64"]["iterations"] + 1
+    assert infos["learned_fp32"]["iterations"] < infos["bodyframe_fp32"]["iterations"]
+    assert infos["learned_fp32"]["t_build_ms"] <= 0.15 * infos["exact_fp64"]["t_build_ms"]

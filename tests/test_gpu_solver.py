@@ -138,6 +138,33 @@ def test_gmres_solve(case):
     assert rel(U, yd[3 * N:3 * N + 6 * M]) <= solve_tol(S, info["rel_residual"])
 
 
+def test_left_preconditioned_solve(case):
+    # left preconditioning (P^-1 A, the form Sec. 3.1 names) on the GPU and in
+    # the oracle: the same algorithm, so the same iteration count (to one) and
+    # outputs within 1e-12; the stopping test is on the true residual
+    name, wl, S, ctx = case
+    c2 = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10, left_precond=1)
+    try:
+        rc, U, phi, lam, info = arb.arb_solve(c2, wl.F, u_slip=wl.u_slip)
+    finally:
+        arb.arb_destroy(c2)
+    assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
+    assert info["rel_residual"] <= 1e-10
+    P = precond.BlockPreconditioner(wl, S["r"], S["C"])
+    y, oinfo = gmres.gmres(lambda v: S["A"] @ v, P.apply, S["b"], tol=1e-10, left=True)
+    assert oinfo["converged"]
+    yg = np.concatenate([lam.ravel(), U.ravel(), phi])
+    errs = {k: rel(v, outputs(wl, y)[k]) for k, v in outputs(wl, yg).items()}
+    print(f"  left: gpu-vs-oracle {errs}, iterations {info['iterations']} / "
+          f"{oinfo['iterations']}")
+    assert abs(info["iterations"] - oinfo["iterations"]) <= 1
+    assert all(e <= 1e-12 for e in errs.values())
+    # against the direct solution, within the forward-error bound
+    yd = system.solve_dense(S["A"], S["b"])
+    N, M = wl.N, wl.M
+    assert rel(U, yd[3 * N:3 * N + 6 * M]) <= solve_tol(S, info["rel_residual"])
+
+
 def test_gmres_tight_matches_direct(case):
     name, wl, S, ctx = case
     c2 = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-14, max_iter=2000)

@@ -107,6 +107,39 @@ def test_gmres_matches_direct(fil, rigid):
         assert np.abs(V @ V.T - np.eye(k + 1)).max() < 1e-13
 
 
+def test_left_preconditioned_gmres(fil, rigid):
+    # the left variant (P^-1 A, the form Sec. 3.1 names): exact in one iteration
+    # when the preconditioner is the inverse (one body), equal to the direct
+    # solve at a tight tolerance, the Arnoldi relation of P^-1 A, and a true
+    # residual below the tolerance at every exit
+    wl1 = W.random_rigid(1, 12, seed=3, wall=True)
+    S1 = system.assemble(wl1)
+    P1 = precond.BlockPreconditioner(wl1, S1["r"], S1["C"])
+    _, info = gmres.gmres(lambda v: S1["A"] @ v, P1.apply, S1["b"], tol=1e-10, left=True)
+    assert info["iterations"] == 1 and info["true_rel"] <= 1e-10
+    for wl, S in (fil, rigid):
+        A, b = S["A"], S["b"]
+        P = precond.BlockPreconditioner(wl, S["r"], S["C"])
+        y = system.solve_dense(A, b)
+        rec = {}
+        yg, info = gmres.gmres(lambda v: A @ v, P.apply, b, tol=1e-14, record=rec, left=True)
+        assert info["true_rel"] <= 1e-13
+        assert np.linalg.norm(yg - y) <= 1e-11 * np.linalg.norm(y)
+        k = min(rec["k"], 20)
+        V = np.vstack([rec["V"][:k + 1]])
+        V[k] = rec["V"][k] if k < rec["k"] else rec["w_last"]
+        H = rec["Hraw"][:k + 1, :k]
+        PAV = np.column_stack([P.apply(A @ V[j]) for j in range(k)])
+        assert np.abs(PAV - V.T @ H).max() < 1e-12 * np.abs(PAV).max()
+        assert np.abs(V @ V.T - np.eye(k + 1)).max() < 1e-13
+        # the first basis vector is P^-1 b normalised (zero initial guess)
+        z0 = P.apply(b)
+        assert np.allclose(rec["V"][0], z0 / np.linalg.norm(z0), rtol=0, atol=1e-14)
+        for tol in (1e-6, 1e-10):
+            _, inf = gmres.gmres(lambda v: A @ v, P.apply, b, tol=tol, left=True)
+            assert inf["converged"] and inf["true_rel"] <= tol
+
+
 def test_unpreconditioned_gmres_is_slow(fil):
     # Sec. 3.2.1: without preconditioner iterations scale with the system size
     wl, S = fil
