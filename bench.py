@@ -104,40 +104,53 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sl, budget_s=60.0, u_gpu=None):
-    """The oracle as it stands on a bounded sample: all 16,384 sources for a
-    block of targets, grown by 4x until one sample takes more than budget_s / 4
-    seconds (about 15 s by default).  With the
-    GPU product u_gpu (N x 3) the sampled rows also give its relative error."""
+def cpu_baseline(sl, budget_s=20.0, u_gpu=None):
+    """The oracle as it stands, timed on the host's cores: its compiled FP64 route
+    (oracle/rpy_sum.c, plain loops, OpenMP over targets, every host thread) on
+    the benchmark's product, target rows in blocks of 1,024 against all 16,384
+    sources until the whole product is done or budget_s has passed (a bounded
+    sample on small hosts).  With the GPU product u_gpu (N x 3) the sampled rows
+    also give its relative error."""
     import numpy as np
-    import psutil
 
-    from oracle import rpy
+    from oracle import rpy_c
 
     pos, lam = sl["pos"], sl["lam"]
     N = len(pos)
-    rpy.mobility_apply(pos, lam, 1.0, 1.0, True, targets=[0])   # symbolic set-up, untimed
-    proc = psutil.Process()
-    ntg, elapsed, cpu = 8, 0.0, 0.0
-    while True:
-        tg = np.arange(ntg) * (N // ntg)
-        c0 = sum(proc.cpu_times()[:2])
+    rpy_c.load()
+    done, elapsed, threads = 0, 0.0, 0
+    rows = []
+    block = 1024
+    while done < N and elapsed < budget_s:
+        tg = np.arange(done, min(N, done + block))
         t0 = time.perf_counter()
-        uo = rpy.mobility_apply(pos, lam, 1.0, 1.0, True, targets=tg)
-        elapsed = time.perf_counter() - t0
-        cpu = sum(proc.cpu_times()[:2]) - c0
-        if elapsed > budget_s / 4 or ntg >= 1024:
-            break
-        ntg *= 4
-    pairs = ntg * N
-    res = {"value": pairs / elapsed, "unit": "pairs/s",
-           "cores": max(1, round(cpu / elapsed)), "kind": "oracle",
-           "sample": f"{ntg} target blobs x all {N} sources of the wall slab "
-                     f"(float64 numpy, symbolic wall image), {elapsed:.1f} s"}
+        u, threads = rpy_c.mobility_apply(pos, lam, 1.0, 1.0, True, targets=tg,
+                                          return_threads=True)
+        elapsed += time.perf_counter() - t0
+        rows.append(u)
+        done += len(tg)
+    uo = np.vstack(rows)
+    pairs = done * N
+    what = "the whole product" if done == N else f"{done} target blobs x all {N} sources"
+    res = {"value": pairs / elapsed, "unit": "pairs/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{what} of the 16,384-blob wall slab (float64, plain C loops over "
+                     f"sources, OpenMP over targets, {threads} threads), {elapsed:.1f} s",
+           "cpu_model": _cpu_model()}
     if u_gpu is not None:
-        u = np.asarray(u_gpu).reshape(N, 3)[tg]
+        u = np.asarray(u_gpu).reshape(N, 3)[:done]
         res["gpu_rel_err_on_sample"] = float(np.linalg.norm(u - uo) / np.linalg.norm(uo))
     return res
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def matvec_bench(torch, arb, sl, precision, steps, warmup):
@@ -596,7 +609,6 @@ def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, batch=
     t0 = time.perf_counter()
     X, T = learned.make_dataset(n_train, seed=101)
     t_data = time.perf_counter() - t0
-    Xh, Th = learned.make_dataset(1000, seed=202)          # held-out poses
     sc = learned.scaling(X, T)
     ctx = arb.arb_create(precision=arb.ARB_FP64, wall=True)
     try:
@@ -607,10 +619,19 @@ def learned_bench(torch, arb, W, n_bact=4096, n_train=100000, epochs=400, batch=
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         params = arb.arb_mlp_get_params(ctx)
-        Yh = arb.arb_mlp_forward(ctx, Xh)
     finally:
         arb.arb_destroy(ctx)
-    Np, Ne = learned.mobility_from_output(Yh), learned.mobility_from_output(Th)
+    # held-out poses: the library's learned body mobilities (the blocks its learned
+    # build uses) against its exact ones (the block build of Sec. 3.1)
+    hold = W.bacterium_poses(1000, seed=202)
+    c = arb.context_for(hold, precision=arb.ARB_FP64, precond=arb.ARB_PC_LEARNED)
+    try:
+        learned.load_model(c, params, sc)
+        Ne = arb.arb_body_mobility(c)[0].reshape(-1, 6, 6)
+        arb.arb_precond_build(c)
+        Np = np.array([arb.arb_precond_block(c, p, 0)[1] for p in range(hold.M)])
+    finally:
+        arb.arb_destroy(c)
     err = np.linalg.norm(Np - Ne, axis=(1, 2)) / np.linalg.norm(Ne, axis=(1, 2))
     wl = W.bacteria(n_bact=n_bact, seed=5)
     dev = torch.device("cuda")
@@ -658,9 +679,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true",
                     help="skip comparing the timed product with the CPU baseline's oracle rows")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train the body-mobility network and compare preconditioners "
-                         "on 4,096 bacteria (several minutes)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the body-mobility network and the comparison of "
+                         "preconditioners on 4,096 bacteria (about a minute)")
     ap.add_argument("--fmm-only", action="store_true",
                     help="run only the fast-product block (for profiling)")
     ap.add_argument("--no-fmm", action="store_true", help="skip the fast-product block")
@@ -668,6 +689,9 @@ def main():
                     help="run only the single-blob block (for profiling)")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="run only the 1,024-bacteria FP32 solve (one warm-up, --steps timed; "
+                         "for per-kernel profiles) and the filament solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -687,6 +711,22 @@ def main():
         return
     if args.single_blob_only:
         print(json.dumps({"single_blob": single_blob_bench(torch, arb, W)}), flush=True)
+        return
+    if args.solve_only:
+        if args.pmc_copy:
+            a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            log("copy probe: 268435456 bytes read, 268435456 bytes written")
+        out = {"gmres": solve_bench(torch, arb, W.bacteria(n_bact=1024, seed=3),
+                                    "bacteria above a wall: 1024 x (42-blob head + 80-blob "
+                                    "flagellum)", arb.ARB_FP32C, reps=max(1, min(args.steps, 3))),
+               "filament": filament_bench(arb, W)}
+        log(f"bench: solve {out['gmres']['ms_per_solve']:.1f} ms, "
+            f"{out['gmres']['iterations']} iterations; filament "
+            f"{out['filament']['ms_per_solve']:.2f} ms")
+        print(json.dumps(out), flush=True)
         return
     sl = W.slab()
     N = len(sl["pos"])
@@ -785,9 +825,13 @@ def main():
         except Exception as e:          # reported, not fatal to the headline line
             res["fmm"] = {"error": str(e)}
             log(f"bench: fast product failed: {e}")
-    if args.learned:
-        log("bench: learned preconditioner")
-        res["learned"] = learned_bench(torch, arb, W)
+    if not args.no_solve and not args.no_learned:
+        log("bench: learned preconditioner, 4096 bacteria")
+        try:
+            res["learned"] = learned_bench(torch, arb, W)
+        except Exception as e:          # reported, not fatal to the headline line
+            res["learned"] = {"error": str(e)}
+            log(f"bench: learned preconditioner failed: {e}")
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(sl, u_gpu=None if args.no_check else r32["u"])

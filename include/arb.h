@@ -48,6 +48,9 @@ extern "C" {
 #define ARB_E_BELOW_WALL      -3   /* a blob at z <= a with the wall on          */
 #define ARB_E_DEVICE          -4   /* HIP runtime error                          */
 #define ARB_E_NAN             -5   /* non-finite value met                       */
+#define ARB_E_HOST            -6   /* host-side failure (memory allocation, a   */
+                                   /* worker thread); no C++ exception leaves   */
+                                   /* an entry point                            */
 
 /* precision of the blob-blob mobility product (the Krylov solver is always FP64) */
 #define ARB_FP64   0   /* pair sum in double                                   */
@@ -162,6 +165,9 @@ typedef struct {
                             /* each listed cell, or per blob when it holds fewer */
                             /* blobs than proxies                                */
     double    build_ms;     /* host time of the last tree build (incl. copies)   */
+    unsigned long long plan_hash; /* arb_fmm_plan only: FNV-1a hash of the plan's */
+                            /* index arrays (blob order, cells, lists, work      */
+                            /* items, tables); equal plans give equal hashes     */
 } arb_fmm_stats;
 
 /* -------------------------------------------------------------- lifetime */
@@ -222,8 +228,12 @@ int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out);
  * memory, units of length), planned on the host with no device and no
  * context: the leaf level and work counts a product over these positions
  * would use (a = blob radius; order, levels, leaf as the fmm_* options, 0 for
- * their defaults); build_ms is the host time of the planning.  Returns
- * ARB_E_ARG for bad sizes or options, ARB_E_NAN for a non-finite position. */
+ * their defaults); build_ms is the host time of the planning, plan_hash a
+ * digest of the whole plan.  The planning runs on up to 16 host threads (one
+ * per 65,536 blobs); the environment variable ARB_HOST_THREADS (1..16) caps
+ * them, here and in the products' tree builds; the plan does not depend on the
+ * count.  Returns ARB_E_ARG for bad sizes or options, ARB_E_NAN for a
+ * non-finite position, ARB_E_HOST when host memory or a thread fails. */
 int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int leaf,
                  arb_fmm_stats *out);
 

@@ -26,6 +26,7 @@ ARB_E_NOT_SPD = -2
 ARB_E_BELOW_WALL = -3
 ARB_E_DEVICE = -4
 ARB_E_NAN = -5
+ARB_E_HOST = -6
 ARB_FP64 = 0
 ARB_FP32C = 1
 ARB_PC_NONE = 0
@@ -74,7 +75,7 @@ class arb_fmm_stats(C.Structure):
     _fields_ = [("levels", C.c_int), ("order", C.c_int), ("cells", C.c_int),
                 ("leaves", C.c_int), ("near_pairs", C.c_longlong),
                 ("interactions", C.c_longlong), ("m2l_pairs", C.c_longlong),
-                ("build_ms", C.c_double)]
+                ("build_ms", C.c_double), ("plan_hash", C.c_ulonglong)]
 
 
 class arb_step_info(C.Structure):

@@ -214,6 +214,13 @@ int build_topology(arb_ctx *ctx) {
     TRY(upload(ctx, ctx->asm_mat_off, amo.data(), A + 1, s));
     HIPCHK(ctx->G.ensure(std::max<int64_t>(amo[A], 1) * sizeof(double)));
     HIPCHK(ctx->S.ensure(std::max<int64_t>(2 * amo[A], 1) * sizeof(double)));
+    // the blocked factorisation of the assemblies' S_a: diagonal-block inverses
+    // (1,024 doubles per 32-row block) and a failure flag per assembly
+    ctx->asm_max_rows = 0;
+    for (int a = 0; a < A; ++a) ctx->asm_max_rows = std::max(ctx->asm_max_rows, arp[a + 1] - arp[a]);
+    HIPCHK(ctx->asm_dinv.ensure(std::max<int64_t>(32 * (int64_t)Nc + 1024 * (int64_t)A, 1) *
+                                sizeof(double)));
+    HIPCHK(ctx->asm_fail.ensure(std::max(A, 1) * sizeof(int)));
     HIPCHK(ctx->crow.ensure(std::max(Nc, 1) * 12 * sizeof(double)));
     HIPCHK(ctx->Bc.ensure(std::max(Nc, 1) * sizeof(double)));
     // link data (zero-size arrays still get a valid pointer)
@@ -262,11 +269,12 @@ int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
     HIPCHK(ctx->p64.ensure((size_t)N * sizeof(double4)));
     HIPCHK(ctx->hi.ensure((size_t)N * sizeof(float4)));
     HIPCHK(ctx->lo.ensure((size_t)N * sizeof(float4)));
+    HIPCHK(ctx->tbox.ensure(2 * (size_t)std::max((N + 63) / 64, 1) * sizeof(float4)));
     arb::rotations(s, M, ctx->theta.as<double>(), ctx->R9.as<double>());
     arb::blob_geometry(s, N, ctx->body_of_blob.as<int>(), ctx->q.as<double>(), ctx->R9.as<double>(),
                        ctx->r_ref.as<double>(), ctx->pos.as<double>(), ctx->dvec.as<double>());
     arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->opt.a, ctx->p64.as<double4>(),
-                        ctx->hi.as<float4>(), ctx->lo.as<float4>());
+                        ctx->hi.as<float4>(), ctx->lo.as<float4>(), ctx->tbox.as<float4>());
     if (!ctx->topo_dirty) TRY(refresh_rows(ctx, s));
     ctx->pc_built = false;
     ctx->fmm.dirty = true;
@@ -294,7 +302,8 @@ int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R, int precision) {
 // one pair product; shape > 0: target-parallel kernel with that many source
 // slices; shape < 0: symmetric kernel with -shape source tiles per work item
 int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
-             const float4 *lo, const double *lam, double *out, const double *U, const int *bob,
+             const float4 *lo, const float4 *box, const double *lam, double *out, const double *U,
+             const int *bob,
              const double *dvec, int precision, bool wall, int shape) {
     const bool sym = shape < 0;
     int used = 1;
@@ -312,7 +321,7 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
         HIPCHK(hipEventRecord(e0, s));
     }
     if (sym)
-        arb::pair_sym(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a,
+        arb::pair_sym(s, precision, wall, N, p64, hi, lo, box, lam, ctx->opt.a,
                       ctx->sym_work[precision == ARB_FP32C].as<int4>(),
                       ctx->sym_n_work[precision == ARB_FP32C], ctx->partial.as<double>());
     else
@@ -332,7 +341,8 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
 // launch shape for (N, precision, wall): from the options, the cache, or by
 // timing every candidate shape on the first product of that size
 int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
-                  const float4 *lo, const double *lam, int precision, bool wall, int *shape) {
+                  const float4 *lo, const float4 *box, const double *lam, int precision, bool wall,
+                  int *shape) {
     const int kind = ctx->opt.pair_kernel;
     const bool sym_ok = kind != 1;
     if (ctx->opt.slices > 0 && kind != 2) {
@@ -373,7 +383,7 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
             float tmin = 1e30f;
             for (int rep = 0, reps = 5; rep < reps; ++rep) {
                 HIPCHK(hipEventRecord(e0, s));
-                TRY(run_pair(ctx, s, N, p64, hi, lo, lam, ctx->tune_out.as<double>(), nullptr,
+                TRY(run_pair(ctx, s, N, p64, hi, lo, box, lam, ctx->tune_out.as<double>(), nullptr,
                              nullptr, nullptr, precision, wall, c));
                 HIPCHK(hipEventRecord(e1, s));
                 HIPCHK(hipEventSynchronize(e1));
@@ -442,9 +452,10 @@ int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const 
     const bool wall = ctx->opt.wall != 0;
     int sl = 0;
     TRY(choose_slices(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
-                      ctx->lo.as<float4>(), lam, precision, wall, &sl));
+                      ctx->lo.as<float4>(), ctx->tbox.as<float4>(), lam, precision, wall, &sl));
     return run_pair(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
-                    ctx->lo.as<float4>(), lam, out, U, ctx->body_of_blob.as<int>(),
+                    ctx->lo.as<float4>(), ctx->tbox.as<float4>(), lam, out, U,
+                    ctx->body_of_blob.as<int>(),
                     ctx->dvec.as<double>(), precision, wall, sl);
 }
 
@@ -566,6 +577,9 @@ arb::PrecondDev pc_view(arb_ctx *ctx) {
     P.Nt = ctx->Nt.as<double>();
     P.G = ctx->G.as<double>();
     P.S = ctx->S.as<double>();
+    P.asm_max_rows = ctx->asm_max_rows;
+    P.asm_dinv = ctx->asm_dinv.as<double>();
+    P.asm_fail = ctx->asm_fail.as<int>();
     P.status = ctx->status.as<int>();
     P.tmp = ctx->pctmp.as<double>();
     P.learned = ctx->pc_learned ? 1 : 0;
@@ -680,7 +694,7 @@ int precond_build(arb_ctx *ctx, hipStream_t s) {
                                   ctx->R9.as<double>(), ctx->Nt.as<double>());
         ctx->pc_learned = true;  // same per-type apply path
         arb::PrecondDev P = pc_view(ctx);
-        arb::precond_assembly(s, P);
+        HIPCHK(arb::precond_assembly(s, P));
         int st[8];
         HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -711,7 +725,7 @@ int precond_build(arb_ctx *ctx, hipStream_t s) {
                             ctx->status.as<int>() + 4);
     ctx->pc_lcorr = true;
     arb::PrecondDev P = pc_view(ctx);
-    arb::precond_assembly(s, P);
+    HIPCHK(arb::precond_assembly(s, P));
     int st[8];
     HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -736,7 +750,7 @@ int precond_build_single(arb_ctx *ctx, hipStream_t s) {
     TRY(ensure_zero_offsets(ctx, s));
     arb::single_blob_body_mobility(s, M, ctx->opt.a, ctx->opt.eta, ctx->Nt.as<double>());
     arb::PrecondDev P = pc_view(ctx);
-    arb::precond_assembly(s, P);
+    HIPCHK(arb::precond_assembly(s, P));
     int st[8];
     HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -770,7 +784,7 @@ int precond_build_exact(arb_ctx *ctx, hipStream_t s) {
     arb::PrecondDev P = pc_view(ctx);
     arb::precond_assemble(s, P, ctx->pos.as<double>(), ctx->opt.a, ctx->opt.eta, ctx->opt.wall != 0);
     HIPCHK(arb::precond_factor(s, P, ctx->dvec.as<double>(), max_m));
-    arb::precond_assembly(s, P);
+    HIPCHK(arb::precond_assembly(s, P));
     int st[8];
     HIPCHK(hipMemcpyAsync(st, ctx->status.p, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1158,12 +1172,35 @@ int check_finite(arb_ctx *ctx, const double *v, size_t n, const char *what) {
     return 0;
 }
 
+// Entry points return ARB_E_HOST instead of letting a C++ exception (a failed
+// host allocation, a thread that cannot start) cross the C ABI.
+int guard_fail(const arb_ctx *c, const char *what) noexcept {
+    try {
+        if (c) const_cast<arb_ctx *>(c)->err = std::string("host failure: ") + what;
+    } catch (...) {
+    }
+    return ARB_E_HOST;
+}
+#define ARB_GUARD_BEGIN try {
+#define ARB_GUARD_END(c)                                           \
+    }                                                              \
+    catch (const std::bad_alloc &) {                               \
+        return guard_fail(c, "host memory allocation failed");     \
+    }                                                              \
+    catch (const std::exception &e_) {                             \
+        return guard_fail(c, e_.what());                           \
+    }                                                              \
+    catch (...) {                                                  \
+        return guard_fail(c, "unknown exception");                 \
+    }
+
 }  // namespace
 
 // ====================================================================== C ABI
 extern "C" {
 
 int arb_create(arb_ctx **out, const arb_options *opt) {
+    ARB_GUARD_BEGIN
     arb_ctx *ctx = nullptr;
     if (!out || !opt) return ARB_E_ARG;
     *out = nullptr;
@@ -1199,9 +1236,11 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
     }
     *out = ctx;
     return ARB_OK;
+    ARB_GUARD_END(nullptr)
 }
 
 void arb_destroy(arb_ctx *ctx) {
+    try {
     if (!ctx) return;
     (void)hipSetDevice(ctx->opt.device);
     (void)hipDeviceSynchronize();
@@ -1214,11 +1253,14 @@ void arb_destroy(arb_ctx *ctx) {
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+    } catch (...) {
+    }
 }
 
 const char *arb_last_error(const arb_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int arb_get_slices(const arb_ctx *ctx, int n_blobs) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     if (ctx->opt.slices > 0) return ctx->opt.slices;
     for (int prec = 0; prec < 2; ++prec) {
@@ -1229,10 +1271,12 @@ int arb_get_slices(const arb_ctx *ctx, int n_blobs) {
         }
     }
     return heuristic_slices(n_blobs);
+    ARB_GUARD_END(ctx)
 }
 
 int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset, const double *r_ref,
                    const int32_t *body_type) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     if (M <= 0 || !blob_offset || !r_ref) return fail(ctx, ARB_E_ARG, "bad body arguments");
     if (blob_offset[0] != 0) return fail(ctx, ARB_E_ARG, "blob_offset[0] must be 0");
@@ -1274,9 +1318,11 @@ int arb_set_bodies(arb_ctx *ctx, int M, const int32_t *blob_offset, const double
     ctx->pc_built = false;
     ctx->slice_cache.clear();
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_set_state(arb_ctx *ctx, const double *q, const double *theta) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     if (ctx->M <= 0) return fail(ctx, ARB_E_ARG, "bodies not set");
     if (!q || !theta) return fail(ctx, ARB_E_ARG, "null state");
@@ -1303,9 +1349,11 @@ int arb_set_state(arb_ctx *ctx, const double *q, const double *theta) {
         if (flag) return fail(ctx, ARB_E_BELOW_WALL, "a blob is at or below z = a with the wall on");
     }
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_blob_positions(arb_ctx *ctx, double *r_out) {
+    ARB_GUARD_BEGIN
     if (!ctx || !r_out) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1313,11 +1361,13 @@ int arb_blob_positions(arb_ctx *ctx, double *r_out) {
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p, const double *dl_q,
                   const double *dldot_p, const double *dldot_q, const int32_t *nproj,
                   const double *proj) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     if (P < 0 || (P > 0 && (!pq || !dl_p || !dl_q))) return fail(ctx, ARB_E_ARG, "bad link arguments");
     ctx->P = P;
@@ -1352,9 +1402,11 @@ int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p, co
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef, const double *rhs) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     if (R < 0 || (R > 0 && (!pq || !coef || !rhs))) return fail(ctx, ARB_E_ARG, "bad row arguments");
     ctx->Rg = R;
@@ -1374,9 +1426,11 @@ int arb_set_rows(arb_ctx *ctx, int R, const int32_t *pq, const double *coef, con
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     int nc = ctx->Nc;
     if (ctx->topo_dirty) {
@@ -1390,9 +1444,11 @@ int arb_sizes(const arb_ctx *ctx, int *N, int *M, int *Nc, int64_t *n) {
         *n = (ctx->opt.model == ARB_MODEL_SINGLE_BLOB ? 0 : 3 * (int64_t)ctx->N) +
              6 * (int64_t)ctx->M + nc;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out) {
+    ARB_GUARD_BEGIN
     if (!ctx || !out) return ARB_E_ARG;
     const arb::FmmState &F = ctx->fmm;
     if (ctx->opt.pair_kernel != ARB_PAIR_FMM || !F.ready) return ARB_E_ARG;
@@ -1405,18 +1461,22 @@ int arb_fmm_get_stats(const arb_ctx *ctx, arb_fmm_stats *out) {
     out->m2l_pairs = F.n_m2l_pairs;
     out->build_ms = F.build_ms;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mobility_apply_dev(arb_ctx *ctx, const double *lambda_dev, double *u_dev, void *stream) {
+    ARB_GUARD_BEGIN
     if (!ctx || !lambda_dev || !u_dev) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
     TRY(ctx_pair(ctx, pick(ctx, stream), lambda_dev, u_dev, nullptr, ctx->opt.precision));
     HIPCHK(hipGetLastError());
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mobility_apply(arb_ctx *ctx, const double *lambda, double *u) {
+    ARB_GUARD_BEGIN
     if (!ctx || !lambda || !u) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1430,19 +1490,24 @@ int arb_mobility_apply(arb_ctx *ctx, const double *lambda, double *u) {
     HIPCHK(hipMemcpyAsync(u, ctx->s_out.p, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *lambda_dev,
                       double *u_dev, void *stream) {
+    ARB_GUARD_BEGIN
     if (!ctx || N < 0 || (N > 0 && (!pos_dev || !lambda_dev || !u_dev))) return ARB_E_ARG;
     if (N == 0) return ARB_OK;
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = pick(ctx, stream);
-    HIPCHK(ctx->s_pos.ensure((size_t)N * (sizeof(double4) + 2 * sizeof(float4))));
+    const size_t ntb = 2 * (size_t)((N + 63) / 64);
+    HIPCHK(ctx->s_pos.ensure((size_t)N * (sizeof(double4) + 2 * sizeof(float4)) +
+                             ntb * sizeof(float4)));
     double4 *p64 = ctx->s_pos.as<double4>();
     float4 *hi = reinterpret_cast<float4 *>(p64 + N);
     float4 *lo = hi + N;
-    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo);
+    float4 *box = lo + N;
+    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo, box);
     if (ctx->opt.pair_kernel == ARB_PAIR_FMM) {
         // a tree of these positions; the context's own is rebuilt at its next product
         TRY(fmm_pair(ctx, s, N, pos_dev, hi, lo, lambda_dev, u_dev, nullptr, nullptr, nullptr,
@@ -1453,14 +1518,16 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *
     }
     const bool wall = ctx->opt.wall != 0;
     int sl = 0;
-    TRY(choose_slices(ctx, s, N, p64, hi, lo, lambda_dev, ctx->opt.precision, wall, &sl));
-    TRY(run_pair(ctx, s, N, p64, hi, lo, lambda_dev, u_dev, nullptr, nullptr, nullptr,
+    TRY(choose_slices(ctx, s, N, p64, hi, lo, box, lambda_dev, ctx->opt.precision, wall, &sl));
+    TRY(run_pair(ctx, s, N, p64, hi, lo, box, lambda_dev, u_dev, nullptr, nullptr, nullptr,
                  ctx->opt.precision, wall, sl));
     HIPCHK(hipGetLastError());
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda, double *u) {
+    ARB_GUARD_BEGIN
     if (!ctx || N < 0 || (N > 0 && (!pos || !lambda || !u))) return ARB_E_ARG;
     if (N == 0) return ARB_OK;
     if (check_finite(ctx, pos, 3 * (size_t)N, "pos") ||
@@ -1481,10 +1548,12 @@ int arb_rpy_apply(arb_ctx *ctx, int N, const double *pos, const double *lambda, 
     HIPCHK(hipMemcpyAsync(u, ctx->s_out.p, n3 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_body_mobility_apply_dev(arb_ctx *ctx, const double *FT_dev, double *UW_dev,
                                 void *stream) {
+    ARB_GUARD_BEGIN
     if (!ctx || !FT_dev || !UW_dev) return ARB_E_ARG;
     if (ctx->opt.model != ARB_MODEL_SINGLE_BLOB)
         return fail(ctx, ARB_E_ARG, "body mobility product needs the single-blob model");
@@ -1494,9 +1563,11 @@ int arb_body_mobility_apply_dev(arb_ctx *ctx, const double *FT_dev, double *UW_d
     TRY(body_mobility_dev(ctx, s, FT_dev, 1.0, nullptr, UW_dev, ctx->opt.precision));
     HIPCHK(hipGetLastError());
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_body_mobility_apply(arb_ctx *ctx, const double *FT, double *UW) {
+    ARB_GUARD_BEGIN
     if (!ctx || !FT || !UW) return ARB_E_ARG;
     if (ctx->opt.model != ARB_MODEL_SINGLE_BLOB)
         return fail(ctx, ARB_E_ARG, "body mobility product needs the single-blob model");
@@ -1512,9 +1583,11 @@ int arb_body_mobility_apply(arb_ctx *ctx, const double *FT, double *UW) {
     HIPCHK(hipMemcpyAsync(UW, ctx->s_out.p, m6 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_system_apply(arb_ctx *ctx, const double *y, double *out) {
+    ARB_GUARD_BEGIN
     if (!ctx || !y || !out) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1526,9 +1599,11 @@ int arb_system_apply(arb_ctx *ctx, const double *y, double *out) {
     HIPCHK(hipMemcpyAsync(out, ctx->s_out.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_K_apply(arb_ctx *ctx, const double *U, double *out) {
+    ARB_GUARD_BEGIN
     if (!ctx || !U || !out) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1541,9 +1616,11 @@ int arb_K_apply(arb_ctx *ctx, const double *U, double *out) {
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_KT_apply(arb_ctx *ctx, const double *lambda, double *out) {
+    ARB_GUARD_BEGIN
     if (!ctx || !lambda || !out) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1557,9 +1634,11 @@ int arb_KT_apply(arb_ctx *ctx, const double *lambda, double *out) {
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_constraint_rows(arb_ctx *ctx, double *coef, int32_t *pq, double *B) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1580,15 +1659,19 @@ int arb_constraint_rows(arb_ctx *ctx, double *coef, int32_t *pq, double *B) {
             pq[2 * k + 1] = rq[k];
         }
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_precond_build(arb_ctx *ctx) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     HIPCHK(hipSetDevice(ctx->opt.device));
     return precond_build(ctx, ctx->stream);
+    ARB_GUARD_END(ctx)
 }
 
 int arb_precond_apply(arb_ctx *ctx, const double *r, double *z) {
+    ARB_GUARD_BEGIN
     if (!ctx || !r || !z) return ARB_E_ARG;
     TRY(ready(ctx));
     if (ctx->opt.precond != ARB_PC_NONE && !ctx->pc_built)
@@ -1602,9 +1685,11 @@ int arb_precond_apply(arb_ctx *ctx, const double *r, double *z) {
     HIPCHK(hipMemcpyAsync(z, ctx->s_out.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     if (!ctx->pc_built) return fail(ctx, ARB_E_ARG, "preconditioner not built");
     if (p < 0 || p >= ctx->M) return fail(ctx, ARB_E_ARG, "body index out of range");
@@ -1630,17 +1715,21 @@ int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde) {
         for (int64_t i = 0; i < m; ++i)
             for (int64_t j = i + 1; j < m; ++j) L[i * m + j] = 0.0;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_solve_dev(arb_ctx *ctx, const double *F_dev, const double *u_slip_dev, double *y_dev,
                   int warm, arb_solve_info *info, void *stream) {
+    ARB_GUARD_BEGIN
     if (!ctx || !F_dev || !y_dev) return ARB_E_ARG;
     HIPCHK(hipSetDevice(ctx->opt.device));
     return solve_dev(ctx, F_dev, u_slip_dev, y_dev, warm, info, pick(ctx, stream));
+    ARB_GUARD_END(ctx)
 }
 
 int arb_solve(arb_ctx *ctx, const double *F, const double *u_slip, const double *y0, double *U,
               double *phi, double *lambda, arb_solve_info *info) {
+    ARB_GUARD_BEGIN
     if (!ctx || !F) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1671,9 +1760,11 @@ int arb_solve(arb_ctx *ctx, const double *F, const double *u_slip, const double 
                               hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return rc;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double *theta) {
+    ARB_GUARD_BEGIN
     if (!ctx || !U) return ARB_E_ARG;
     TRY(ready(ctx));
     if (check_finite(ctx, U, 6 * (size_t)ctx->M, "U")) return ARB_E_NAN;
@@ -1691,6 +1782,7 @@ int arb_euler_update(arb_ctx *ctx, const double *U, double dt, double *q, double
                               hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 // Articulated bodies of the link graph (bodies joined by links; bodies without
@@ -1924,6 +2016,7 @@ static int copy_state_out(arb_ctx *ctx, hipStream_t s, double *q, double *theta)
 
 int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, double *theta,
                           int *iters, double *resid) {
+    ARB_GUARD_BEGIN
     if (!ctx || !(tol > 0) || max_iter < 0) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1933,9 +2026,11 @@ int arb_correct_positions(arb_ctx *ctx, double tol, int max_iter, double *q, dou
     TRY(copy_state_out(ctx, s, q, theta));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_reconstruct(arb_ctx *ctx, double *q, double *g_inf, double *g2) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1948,9 +2043,11 @@ int arb_reconstruct(arb_ctx *ctx, double *q, double *g_inf, double *g2) {
     if (g_inf) *g_inf = gi;
     if (g2) *g2 = gs;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_link_residual(arb_ctx *ctx, double *g_inf, double *g2) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1959,6 +2056,7 @@ int arb_link_residual(arb_ctx *ctx, double *g_inf, double *g2) {
     if (g_inf) *g_inf = gi;
     if (g2) *g2 = gs;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 // figures of one advance (steps 2-5 of Sec. 4.3)
@@ -2036,6 +2134,7 @@ static void fill_step_info(arb_step_info *info, int rc, const arb_solve_info &si
 int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
                    double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
                    double *U, arb_step_info *info) {
+    ARB_GUARD_BEGIN
     TRY(step_prologue(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter));
     hipStream_t s = ctx->stream;
     arb_solve_info si{};
@@ -2051,11 +2150,13 @@ int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double d
     HIPCHK(hipStreamSynchronize(s));
     fill_step_info(info, rc, si, ai);
     return rc;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
                       double delta, double corr_tol, int corr_max_iter, int warm, double *q,
                       double *theta, double *U, arb_step_info *info) {
+    ARB_GUARD_BEGIN
     TRY(step_prologue(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter));
     hipStream_t s = ctx->stream;
     const int M = ctx->M;
@@ -2100,6 +2201,7 @@ int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, doubl
                        : (rc0 > 0 ? rc0 : rc1);
     fill_step_info(info, rc, st, af);
     return rc;
+    ARB_GUARD_END(ctx)
 }
 
 // parameter block: allocated once with identity standardisation
@@ -2115,6 +2217,7 @@ static int mlp_alloc(arb_ctx *ctx) {
 
 int arb_mlp_set_scaling(arb_ctx *ctx, const float *in_mu, const float *in_sd, const float *out_mu,
                         const float *out_sd) {
+    ARB_GUARD_BEGIN
     if (!ctx || !in_mu || !in_sd || !out_mu || !out_sd) return ARB_E_ARG;
     for (int k = 0; k < 7; ++k)
         if (!(in_sd[k] > 0) || !std::isfinite(in_mu[k])) return fail(ctx, ARB_E_ARG, "bad input scaling");
@@ -2124,9 +2227,11 @@ int arb_mlp_set_scaling(arb_ctx *ctx, const float *in_mu, const float *in_sd, co
     TRY(mlp_alloc(ctx));
     arb::mlp_set_scaling(ctx->stream, ctx->mlp_params.p, in_mu, in_sd, out_mu, out_sd);
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mlp_set_params(arb_ctx *ctx, int n, const float *params) {
+    ARB_GUARD_BEGIN
     if (!ctx || !params) return ARB_E_ARG;
     if (n != arb::mlp_n_params()) return fail(ctx, ARB_E_ARG, "wrong parameter count");
     for (int k = 0; k < n; ++k)
@@ -2142,9 +2247,11 @@ int arb_mlp_set_params(arb_ctx *ctx, int n, const float *params) {
     ctx->mlp_ready = true;
     ctx->mlp_step = 0;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mlp_get_params(arb_ctx *ctx, int n, float *params) {
+    ARB_GUARD_BEGIN
     if (!ctx || !params) return ARB_E_ARG;
     if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
     if (n != arb::mlp_n_params()) return fail(ctx, ARB_E_ARG, "wrong parameter count");
@@ -2153,9 +2260,11 @@ int arb_mlp_get_params(arb_ctx *ctx, int n, float *params) {
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mlp_forward(arb_ctx *ctx, int B, const float *X, float *Y) {
+    ARB_GUARD_BEGIN
     if (!ctx || B <= 0 || !X || !Y) return ARB_E_ARG;
     if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -2171,6 +2280,7 @@ int arb_mlp_forward(arb_ctx *ctx, int B, const float *X, float *Y) {
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < 21; ++k) Y[(size_t)b * 21 + k] = tmp[(size_t)b * 32 + k];
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 static int mlp_grad_dev(arb_ctx *ctx, hipStream_t s, int B, const float *Xd, const float *Td,
@@ -2191,6 +2301,7 @@ static int mlp_grad_dev(arb_ctx *ctx, hipStream_t s, int B, const float *Xd, con
 }
 
 int arb_mlp_grad(arb_ctx *ctx, int B, const float *X, const float *T, float *grad, double *loss) {
+    ARB_GUARD_BEGIN
     if (!ctx || B <= 0 || !X || !T || !grad) return ARB_E_ARG;
     if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -2203,10 +2314,12 @@ int arb_mlp_grad(arb_ctx *ctx, int B, const float *X, const float *T, float *gra
     HIPCHK(hipMemcpyAsync(grad, G, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mlp_train_step_dev(arb_ctx *ctx, int B, const float *X_dev, const float *T_dev, float lr,
                            double *loss, void *stream) {
+    ARB_GUARD_BEGIN
     if (!ctx || B <= 0 || !X_dev || !T_dev || !(lr > 0)) return ARB_E_ARG;
     if (!ctx->mlp_ready) return fail(ctx, ARB_E_ARG, "parameters not set");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -2215,9 +2328,11 @@ int arb_mlp_train_step_dev(arb_ctx *ctx, int B, const float *X_dev, const float 
     arb::mlp_adam(s, ctx->mlp_params.p, lr, ++ctx->mlp_step);
     HIPCHK(hipGetLastError());
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_mlp_features(arb_ctx *ctx, float *X) {
+    ARB_GUARD_BEGIN
     if (!ctx || !X) return ARB_E_ARG;
     TRY(ready(ctx));
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -2229,9 +2344,11 @@ int arb_mlp_features(arb_ctx *ctx, float *X) {
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_body_mobility(arb_ctx *ctx, double *Nt, float *target) {
+    ARB_GUARD_BEGIN
     if (!ctx || (!Nt && !target)) return ARB_E_ARG;
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = ctx->stream;
@@ -2255,15 +2372,19 @@ int arb_body_mobility(arb_ctx *ctx, double *Nt, float *target) {
     }
     HIPCHK(hipStreamSynchronize(s));
     return rc;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_profile(arb_ctx *ctx, int enable) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     ctx->prof = enable != 0;
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 int arb_profile_read(arb_ctx *ctx, double *pair_ms, int *pair_launches) {
+    ARB_GUARD_BEGIN
     if (!ctx) return ARB_E_ARG;
     HIPCHK(hipSetDevice(ctx->opt.device));
     double tot = 0.0;
@@ -2279,6 +2400,7 @@ int arb_profile_read(arb_ctx *ctx, double *pair_ms, int *pair_launches) {
     if (pair_launches) *pair_launches = (int)ctx->prof_ev.size();
     ctx->prof_ev.clear();
     return ARB_OK;
+    ARB_GUARD_END(ctx)
 }
 
 }  // extern "C"

@@ -113,8 +113,10 @@ void fmm_apply6(const FmmState &F, hipStream_t s, bool fp64, const double *x6, d
 // ---------------------------------------------------------------- kernel entry points
 // Pair sum u_i = sum_j M_ij lambda_j (Sec. 2.3): partial sums per source slice,
 // then an ordered reduction.  Positions are prepared by prep_positions().
+// box (may be null): 2 float4 per 64-blob tile, its bounding box and largest
+// |coordinate| (pair_sym's far test)
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
-                    float4 *hi, float4 *lo);
+                    float4 *hi, float4 *lo, float4 *box);
 // device address of the allocation-free entry point's scratch array for the
 // current device (noalloc.hip), looked up once per device; 0 when known
 int noalloc_setup(int device);
@@ -134,8 +136,8 @@ int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int 
 // unscaled, accumulated into u (cleared first by pair_sym_clear)
 void pair_sym_clear(hipStream_t s, int N, double *u);
 void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-              const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
-              int n_work, double *u);
+              const float4 *hi, const float4 *lo, const float4 *box, const double *lam, double a,
+              const int4 *work, int n_work, double *u);
 std::vector<int4> pair_sym_worklist(int N, int R);
 
 // Rigid-body kinematics (Sec. 2.1, 2.3, App. B)
@@ -177,6 +179,9 @@ struct PrecondDev {
     double *Nt = nullptr;     // per-body N~_p (36)
     double *G = nullptr;      // per-assembly G~_a
     double *S = nullptr;      // per-assembly scratch (S_a and its factor)
+    int asm_max_rows = 0;     // largest assembly (constraint rows)
+    double *asm_dinv = nullptr;  // diagonal-block inverses of the assemblies' factors
+    int *asm_fail = nullptr;     // per assembly: 1 if S_a failed the pivot test
     int *status = nullptr;    // [0] not-SPD body+1, [1] G~ pinv count, [2] below wall,
                               // [3] N~ with dropped eigenvalues
     double *tmp = nullptr;    // apply scratch: U-hat (6M)
@@ -193,7 +198,7 @@ void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos,
 // max_m = largest 3 n_p of the batch
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
 int64_t precond_dinv_size(int64_t n_blobs, int M);
-void precond_assembly(hipStream_t s, const PrecondDev &P);
+hipError_t precond_assembly(hipStream_t s, const PrecondDev &P);
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z);
 void rotate_body_mobility(hipStream_t s, int M, const int *type, const double *tNt,
                           const double *R9, double *Nt);
@@ -360,9 +365,12 @@ struct arb_ctx {
     arb::DevBuf blob_off, body_of_blob, r_ref, q, theta, R9, pos, dvec, p64, hi, lo,
         partial, row_p, row_q, row_kind, row_src, row_m, dl_p, dl_q, dldot_p, dldot_q, proj,
         gcoef, grhs, crow, Bc, brow_ptr, brow_ent, asm_body_ptr, asm_bodies, asm_row_ptr,
-        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp, lcorr, stmp;
+        asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp, lcorr, stmp,
+        asm_dinv, asm_fail;
+    int asm_max_rows = 0;  // largest assembly (constraint rows)
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
+    arb::DevBuf tbox;  // per 64-blob tile of the state's positions: bounding box (prep_positions)
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
     // host pinned scratch: kPinnedScalars doubles for entry points, then two per
     // Arnoldi step (h_{j+1,j}, residual estimate) at pinned + kPinnedScalars

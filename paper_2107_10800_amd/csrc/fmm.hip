@@ -53,6 +53,9 @@
 #include <chrono>
 #include <memory>
 #include <cmath>
+#include <cstdlib>
+#include <exception>
+#include <system_error>
 #include <thread>
 #include <type_traits>
 
@@ -823,13 +826,32 @@ inline uint64_t morton(int x, int y, int z) {
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // host threads for the O(N) steps of the tree build: at most 16 (one GPU's
-// share of the host), one per 65,536 blobs
+// share of the host), one per 65,536 blobs; the environment variable
+// ARB_HOST_THREADS (1..16) caps them (the plan does not depend on the count)
 int host_threads(int N) {
-    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    if (const char *e = std::getenv("ARB_HOST_THREADS")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 16) hw = std::min(hw, v);
+    }
     return std::max(1, std::min({16, hw, N / 65536}));
 }
 
-// f(t, i0, i1) on T contiguous slices of [0, N), thread t taking slice t
+// FNV-1a over the bytes of a vector
+template <class V>
+void fnv1a(uint64_t &h, const std::vector<V> &v) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(v.data());
+    const size_t n = v.size() * sizeof(V);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+}
+
+// f(t, i0, i1) on T contiguous slices of [0, N), thread t taking slice t.  An
+// exception in a slice is caught on its thread and rethrown on the caller's
+// after every thread has joined; a slice whose thread cannot be started runs
+// on the caller's thread (the result does not depend on where a slice runs).
 template <class F>
 void parallel_slices(int T, int N, F &&f) {
     if (T <= 1) {
@@ -837,12 +859,26 @@ void parallel_slices(int T, int N, F &&f) {
         return;
     }
     std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err((size_t)T);
     th.reserve(T);
-    for (int t = 0; t < T; ++t) {
+    auto slice = [&f, &err, T, N](int t) {
         const int i0 = (int)((int64_t)N * t / T), i1 = (int)((int64_t)N * (t + 1) / T);
-        th.emplace_back([&f, t, i0, i1] { f(t, i0, i1); });
+        try {
+            f(t, i0, i1);
+        } catch (...) {
+            err[t] = std::current_exception();
+        }
+    };
+    for (int t = 0; t < T; ++t) {
+        try {
+            th.emplace_back(slice, t);
+        } catch (const std::system_error &) {
+            slice(t);
+        }
     }
     for (auto &x : th) x.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 // per-cell lists on host threads: f(c, out) appends the entries of item c to
@@ -1561,8 +1597,13 @@ int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int 
     if (N == 0) return ARB_OK;
     const auto t0 = std::chrono::steady_clock::now();
     FmmPlan pl;
-    std::string msg;
-    const int rc = fmm_plan(pl, N, pos, a, n, levels, leaf, &msg);
+    int rc = 0;
+    try {
+        std::string msg;
+        rc = fmm_plan(pl, N, pos, a, n, levels, leaf, &msg);
+    } catch (...) {  // host allocation or worker-thread failure: no exception crosses the ABI
+        return ARB_E_HOST;
+    }
     if (rc) return rc;
     out->levels = pl.L;
     out->cells = pl.ncell;
@@ -1572,5 +1613,19 @@ int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int 
     out->m2l_pairs = pl.n_m2l_pairs;
     out->build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    uint64_t h = 0xcbf29ce484222325ull;
+    fnv1a(h, pl.perm);
+    fnv1a(h, pl.lvl);
+    fnv1a(h, pl.parent);
+    fnv1a(h, pl.il_ptr);
+    fnv1a(h, pl.il);
+    fnv1a(h, pl.near_ptr);
+    fnv1a(h, pl.nearl);
+    fnv1a(h, pl.cc);
+    fnv1a(h, pl.rng);
+    fnv1a(h, pl.kids);
+    fnv1a(h, pl.work);
+    fnv1a(h, pl.tab);
+    out->plan_hash = (unsigned long long)h;
     return ARB_OK;
 }

@@ -61,9 +61,8 @@ int noalloc_setup(int device) {
 
 }  // namespace arb
 
-extern "C" int arb_rpy_apply_noalloc_dev(arb_ctx *ctx, int N, const double *pos_dev,
-                                         const double *lambda_dev, double *u_dev,
-                                         void *stream) {
+static int rpy_apply_noalloc(arb_ctx *ctx, int N, const double *pos_dev,
+                             const double *lambda_dev, double *u_dev, void *stream) {
     if (!ctx) return ARB_E_ARG;
     if (N < 0 || (N > 0 && (!pos_dev || !lambda_dev || !u_dev)))
         return fail(ctx, ARB_E_ARG, "arb_rpy_apply_noalloc_dev: bad size or null pointer");
@@ -94,7 +93,7 @@ extern "C" int arb_rpy_apply_noalloc_dev(arb_ctx *ctx, int N, const double *pos_
     const int cap = (int)(kPartialDoubles / (3 * (size_t)N));
     slices = std::max(1, std::min(slices, cap));
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo);
+    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo, nullptr);
     const int used = arb::pair_partial(s, ctx->opt.precision, ctx->opt.wall != 0, N, p64, hi,
                                        lo, lambda_dev, ctx->opt.a, slices, partial);
     // FP32 sums are in units of the blob radius: M(a) = M_{a=1}(r / a) / a
@@ -105,4 +104,14 @@ extern "C" int arb_rpy_apply_noalloc_dev(arb_ctx *ctx, int N, const double *pos_
     if (e != hipSuccess)
         return fail(ctx, ARB_E_DEVICE, std::string("pair launch: ") + hipGetErrorString(e));
     return ARB_OK;
+}
+
+extern "C" int arb_rpy_apply_noalloc_dev(arb_ctx *ctx, int N, const double *pos_dev,
+                                         const double *lambda_dev, double *u_dev,
+                                         void *stream) {
+    try {
+        return rpy_apply_noalloc(ctx, N, pos_dev, lambda_dev, u_dev, stream);
+    } catch (...) {  // an error message that could not be formed
+        return ARB_E_HOST;
+    }
 }

@@ -30,19 +30,47 @@
 namespace arb {
 
 // p64: positions (w = 2 z); hi + lo: positions / a split into two floats, with
-// hi.w = 2 hi.z and lo.w = -(2 hi.z)^2, the source-height terms of the wall image
+// hi.w = 2 hi.z and lo.w = -(2 hi.z)^2, the source-height terms of the wall image.
+// box (may be null): per tile of 64 consecutive blobs (one wavefront here),
+// box[2t] = (min x, min y, min z, max |coordinate|) and box[2t+1] = (max x,
+// max y, max z, 0) of the hi positions, for the symmetric kernel's far test.
 __global__ void prep_positions_kernel(int N, const double *__restrict__ pos, double inv_a,
                                       double4 *__restrict__ p64, float4 *__restrict__ hi,
-                                      float4 *__restrict__ lo) {
+                                      float4 *__restrict__ lo, float4 *__restrict__ box) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 2.0 * pos[3 * i + 2]);
-    const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
-    const float xh = (float)x, yh = (float)y, zh = (float)z;
-    const float h2 = 2.f * zh;
-    hi[i] = make_float4(xh, yh, zh, h2);
-    lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
-                        (float)(z - (double)zh), -(h2 * h2));
+    const bool ok = i < N;
+    float xh = 0.f, yh = 0.f, zh = 0.f;
+    if (ok) {
+        p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 2.0 * pos[3 * i + 2]);
+        const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a,
+                     z = pos[3 * i + 2] * inv_a;
+        xh = (float)x;
+        yh = (float)y;
+        zh = (float)z;
+        const float h2 = 2.f * zh;
+        hi[i] = make_float4(xh, yh, zh, h2);
+        lo[i] = make_float4((float)(x - (double)xh), (float)(y - (double)yh),
+                            (float)(z - (double)zh), -(h2 * h2));
+    }
+    if (!box) return;
+    const float inf = __int_as_float(0x7f800000);
+    float l0 = ok ? xh : inf, l1 = ok ? yh : inf, l2 = ok ? zh : inf;
+    float h0 = ok ? xh : -inf, h1 = ok ? yh : -inf, hz = ok ? zh : -inf;
+    float mx = ok ? fmaxf(fabsf(xh), fmaxf(fabsf(yh), fabsf(zh))) : 0.f;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        l0 = fminf(l0, __shfl_xor(l0, off));
+        l1 = fminf(l1, __shfl_xor(l1, off));
+        l2 = fminf(l2, __shfl_xor(l2, off));
+        h0 = fmaxf(h0, __shfl_xor(h0, off));
+        h1 = fmaxf(h1, __shfl_xor(h1, off));
+        hz = fmaxf(hz, __shfl_xor(hz, off));
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+    }
+    const int t = i / kWave;
+    if ((i % kWave) == 0 && t * kWave < N) {
+        box[2 * t] = make_float4(l0, l1, l2, mx);
+        box[2 * t + 1] = make_float4(h0, h1, hz, 0.f);
+    }
 }
 
 constexpr int kRun = 32;  // sources per float partial sum in the FP32C kernel
@@ -201,9 +229,9 @@ __global__ void wall_check_kernel(int N, const double4 *__restrict__ p64, double
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
-                    float4 *hi, float4 *lo) {
+                    float4 *hi, float4 *lo, float4 *box) {
     if (N <= 0) return;
-    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo);
+    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo, box);
 }
 
 int heuristic_slices(int N) {

@@ -31,21 +31,24 @@
 
 namespace arb {
 
-// accumulate the free-space tensor both ways: f += M lj, a += M li
-template <class T, class C>
+// accumulate the free-space tensor both ways: f += M lj, a += M li (NEAR as in
+// wall_pair_coef)
+template <class T, class C, bool NEAR = true>
 __device__ __forceinline__ void sym_free(T dx, T dy, T dz, T r2, T rinv, T lix, T liy, T liz,
                                          T ljx, T ljy, T ljz, const C &c, T &fx, T &fy, T &fz,
                                          T &ax, T &ay, T &az) {
     const T rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
     T c1 = fma(c.k1, rinv3, rinv);
     T c2 = fma(-c.k2, rinv3 * rinv2, rinv3);
-    ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
-    if (r2 <= c.four_a2) {
-        const T rv = r2 > T(0) ? rinv : T(0);
-        c1 = fma(-c.n2, r2 * rv, c.n1);
-        c2 = rv * c.n3;
+    if (NEAR) {
+        ARB_IF_ANY_OVERLAP(r2 <= c.four_a2)
+        if (r2 <= c.four_a2) {
+            const T rv = r2 > T(0) ? rinv : T(0);
+            c1 = fma(-c.n2, r2 * rv, c.n1);
+            c2 = rv * c.n3;
+        }
+        ARB_END_IF_ANY
     }
-    ARB_END_IF_ANY
     const T tj = c2 * fma(dx, ljx, fma(dy, ljy, dz * ljz));
     const T ti = c2 * fma(dx, lix, fma(dy, liy, dz * liz));
     fx = fma(c1, ljx, fma(tj, dx, fx));
@@ -97,9 +100,77 @@ __global__ void zero_kernel(size_t n, double *__restrict__ u) {
     if (i < n) u[i] = 0.0;
 }
 
+// far test of a target tile against a source tile (units of a): the gap between
+// their boxes is at least kFarMin and at least kFarRel times the sum of their
+// largest |coordinates|, so that the hi parts alone give every difference to a
+// relative 2^-20 (hi rounding <= |x| 2^-24 per coordinate, sqrt(3) 2^-23 (|x_i| +
+// |x_j|) / r <= 2^-20 for r >= 0.11 (|x_i| + |x_j|)), and every pair is far from
+// overlapping (r > 2a)
+constexpr float kFarMin = 8.f;
+constexpr float kFarRel = 0.11f;
+
+// one source tile (staged twice over in LDS) against this lane's target, both ways;
+// NEAR: hi + lo differences and the overlap branch; else hi differences only
+template <bool WALL, bool NEAR>
+__device__ __forceinline__ void sym_tile_loop(const Blob32 &t, float zi, const TargetZ<float> &zsc,
+                                              int lane, int src, const float4 *s_hi,
+                                              const float4 *s_lo, const float4 *s_lam, float &fx,
+                                              float &fy, float &fz, float &ax, float &ay,
+                                              float &az) {
+    constexpr CoefF c = kUnitCoefF;
+#pragma unroll 2
+    for (int st = 0; st < 64; ++st) {
+        const int k = lane + st;
+        const float4 sh = s_hi[k], L = s_lam[k];
+        float dx, dy, dz, mh22;
+        if (NEAR) {
+            const float4 sl = s_lo[k];
+            dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
+            dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
+            dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
+            mh22 = sl.w;
+        } else {
+            dx = t.hi.x - sh.x;
+            dy = t.hi.y - sh.y;
+            dz = t.hi.z - sh.z;
+            mh22 = s_lo[k].w;
+        }
+        const float dxy2 = fmaf(dx, dx, dy * dy);
+        const float r2 = fmaf(dz, dz, dxy2);
+        const float rinv = rsq_f32(r2);
+        if (WALL) {
+            const float Rz = zi + sh.z;
+            const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+            const PairCoef<float> q = wall_pair_coef<float, CoefF, NEAR>(r2, rinv, dxy2, zsc, sh.z,
+                                                                         sh.w, mh22, Rz, Ri, c);
+            wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
+            wall_pair_apply<float>(q, q.d, q.c, dx, dy, dz, Rz, t.lam.x, t.lam.y, t.lam.z, ax, ay,
+                                   az);
+        } else {
+            sym_free<float, CoefF, NEAR>(dx, dy, dz, r2, rinv, t.lam.x, t.lam.y, t.lam.z, L.x, L.y,
+                                         L.z, c, fx, fy, fz, ax, ay, az);
+        }
+        // the source-side sums follow their sources: lane l takes lane l+1's.
+        // The free-space loop has VALU to spare and waits on the LDS, so it
+        // rotates with a whole-wave DPP move; the wall loop is VALU-bound and
+        // uses the LDS crossbar.
+        if (WALL) {
+            ax = __shfl(ax, src);
+            ay = __shfl(ay, src);
+            az = __shfl(az, src);
+        } else {
+            ax = from_next_lane(ax);
+            ay = from_next_lane(ay);
+            az = from_next_lane(az);
+        }
+    }
+}
+
 template <bool WALL>
-__global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 *__restrict__ hi,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+void pair_sym_f32c_kernel(int N, const float4 *__restrict__ hi,
                                                             const float4 *__restrict__ lo,
+                                                            const float4 *__restrict__ box,
                                                             const double *__restrict__ lam,
                                                             const int4 *__restrict__ work,
                                                             double *__restrict__ u) {
@@ -148,42 +219,26 @@ __global__ __launch_bounds__(256) void pair_sym_f32c_kernel(int N, const float4 
             }
         } else {
             float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll 2
-            for (int st = 0; st < 64; ++st) {
-                const int k = lane + st;
-                const float4 sh = s_hi[k], sl = s_lo[k], L = s_lam[k];
-                const float dx = (t.hi.x - sh.x) + (t.lo.x - sl.x);
-                const float dy = (t.hi.y - sh.y) + (t.lo.y - sl.y);
-                const float dz = (t.hi.z - sh.z) + (t.lo.z - sl.z);
-                const float dxy2 = fmaf(dx, dx, dy * dy);
-                const float r2 = fmaf(dz, dz, dxy2);
-                const float rinv = rsq_f32(r2);
-                if (WALL) {
-                    const float Rz = zi + sh.z;
-                    const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
-                    const PairCoef<float> q =
-                        wall_pair_coef<float>(r2, rinv, dxy2, zsc, sh.z, sh.w, sl.w, Rz, Ri, c);
-                    wall_pair_apply<float>(q, q.c, q.d, dx, dy, dz, Rz, L.x, L.y, L.z, fx, fy, fz);
-                    wall_pair_apply<float>(q, q.d, q.c, dx, dy, dz, Rz, t.lam.x, t.lam.y, t.lam.z,
-                                           ax, ay, az);
-                } else {
-                    sym_free<float>(dx, dy, dz, r2, rinv, t.lam.x, t.lam.y, t.lam.z, L.x, L.y, L.z,
-                                    c, fx, fy, fz, ax, ay, az);
-                }
-                // the source-side sums follow their sources: lane l takes lane l+1's.
-                // The free-space loop has VALU to spare and waits on the LDS, so it
-                // rotates with a whole-wave DPP move; the wall loop is VALU-bound and
-                // uses the LDS crossbar.
-                if (WALL) {
-                    ax = __shfl(ax, src);
-                    ay = __shfl(ay, src);
-                    az = __shfl(az, src);
-                } else {
-                    ax = from_next_lane(ax);
-                    ay = from_next_lane(ay);
-                    az = from_next_lane(az);
-                }
+            // far: every pair of the two tiles is farther apart than the FP32 hi parts
+            // alone resolve to 2^-20 (the lo parts dropped, no overlap possible)
+            bool far = false;
+            if (box) {
+                // this wavefront's target tile and the source tile (read again per
+                // source tile: L2-resident, and no registers held across the loop)
+                const float4 tl_ = box[2 * (4 * it.x + w)], th = box[2 * (4 * it.x + w) + 1];
+                const float4 jl = box[2 * J], jh = box[2 * J + 1];
+                const float gx = fmaxf(0.f, fmaxf(jl.x - th.x, tl_.x - jh.x));
+                const float gy = fmaxf(0.f, fmaxf(jl.y - th.y, tl_.y - jh.y));
+                const float gz = fmaxf(0.f, fmaxf(jl.z - th.z, tl_.z - jh.z));
+                const float thr = fmaxf(kFarMin, kFarRel * (tl_.w + jl.w));
+                far = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) >= thr * thr;
             }
+            if (far)
+                sym_tile_loop<WALL, false>(t, zi, zsc, lane, src, s_hi, s_lo, s_lam, fx, fy, fz, ax,
+                                           ay, az);
+            else
+                sym_tile_loop<WALL, true>(t, zi, zsc, lane, src, s_hi, s_lo, s_lam, fx, fy, fz, ax,
+                                          ay, az);
             comb[w][0][lane] = ax;
             comb[w][1][lane] = ay;
             comb[w][2][lane] = az;
@@ -324,14 +379,14 @@ void pair_sym_clear(hipStream_t s, int N, double *u) {
 
 // u (layout [3][N], FP64) += sum over all pairs, unscaled (units 1/(8 pi eta))
 void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-              const float4 *hi, const float4 *lo, const double *lam, double a, const int4 *work,
-              int n_work, double *u) {
+              const float4 *hi, const float4 *lo, const float4 *box, const double *lam, double a,
+              const int4 *work, int n_work, double *u) {
     if (N <= 0 || n_work <= 0) return;
     if (precision == ARB_FP32C) {
         if (wall)
-            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, u);
+            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, box, lam, work, u);
         else
-            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, lam, work, u);
+            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, box, lam, work, u);
     } else {
         const CoefD c = make_coef<CoefD, double>(a);
         if (wall)

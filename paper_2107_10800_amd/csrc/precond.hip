@@ -41,7 +41,8 @@ constexpr int kMaxAsmRows = 2048;
 // eigenvectors accumulated in V; writes the pseudo-inverse (cutoff relative to
 // the largest |eigenvalue|) to out.  Returns the number of dropped eigenvalues.
 // Single thread.
-__device__ int sym_pinv_serial(double *S, double *V, int n, double *out, double cutoff) {
+__device__ __forceinline__ int sym_pinv_serial(double *S, double *V, int n, double *out,
+                                                double cutoff) {
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 60; ++sweep) {
@@ -224,6 +225,9 @@ __global__ __launch_bounds__(256) void pc_inverse_kernel(const int *__restrict__
 constexpr int kNB = 32;          // block size of the blocked factorisation
 constexpr int kLd = kNB + 1;     // padded LDS row stride (doubles)
 constexpr int kFastMaxM = 480;   // largest body handled by the blocked kernels
+// assemblies whose largest S_a has more rows than this take the blocked kernels;
+// smaller ones (a few rows per articulated body) the one-workgroup kernel
+constexpr int kAsmBlockedMin = 64;
 
 // FP64 matrix core, one wavefront: D (16 x 16) += A (16 x 4) B (4 x 16).  Lane l
 // supplies a = A[l % 16][l / 16] and b = B[l / 16][l % 16] and holds
@@ -233,26 +237,56 @@ __device__ __forceinline__ mfma_acc mfma_f64_16x16x4(double a, double b, mfma_ac
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// offset (doubles) of body p's diagonal-block inverses: 1024 per 32-row block
-__device__ __forceinline__ int64_t dinv_offset(const int *blob_off, int p) {
-    return 32 * 3 * (int64_t)blob_off[p] + 1024 * (int64_t)p;
+// A batch of symmetric positive definite matrices for the blocked kernels:
+// matrix p has m_p = scale * (off[p+1] - off[p]) rows (scale 3 for the blob
+// mobilities, off = blob offsets; scale 1 for the assemblies' S_a, off = row
+// offsets), row-major at mats + mat_off[p]; its diagonal-block inverses at
+// dinv_offset.  A matrix whose pivot falls to rel_tol * (its largest diagonal
+// entry) or below fails: with fail != nullptr it is flagged there (and skipped
+// by the later kernels), else status[0] receives p + 1 (an error).
+struct MatBatch {
+    const int *off;
+    int scale;
+    const int64_t *mat_off;
+    double *mats;
+    double *ldiag;  // diag(L) per row (may be null)
+    double *dinv;
+    double *out;    // the inverses (same offsets as mats)
+    int *status;
+    int *fail;
+    double rel_tol;
+};
+__device__ __forceinline__ int mat_rows(const MatBatch &B, int p) {
+    return B.scale * (B.off[p + 1] - B.off[p]);
 }
+__device__ __forceinline__ bool mat_skip(const MatBatch &B, int p) {
+    return B.status[0] != 0 || (B.fail && B.fail[p]);
+}
+// offset (doubles) of matrix p's diagonal-block inverses: 1024 per 32-row block
+__device__ __forceinline__ int64_t dinv_offset(const MatBatch &B, int p) {
+    return 32 * B.scale * (int64_t)B.off[p] + 1024 * (int64_t)p;
+}
+
 
 // Blocked in-place Cholesky of each M_pp (lower triangle; the upper triangle is
 // not touched).  Dynamic LDS: the panel, max_m x kLd doubles.
-__global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ blob_off,
-                                                       const int64_t *__restrict__ mat_off,
-                                                       double *__restrict__ mats,
-                                                       double *__restrict__ ldiag,
-                                                       double *__restrict__ dinv,
-                                                       int *__restrict__ status) {
+__global__ __launch_bounds__(256) void pc_potrf_kernel(MatBatch B) {
     extern __shared__ double Pn[];
     __shared__ int fail;
+    __shared__ double piv_tol;
     const int p = blockIdx.x, tid = threadIdx.x;
-    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
-    double *A = mats + mat_off[p];
-    double *Dg = dinv + dinv_offset(blob_off, p);
-    if (tid == 0) fail = 0;
+    if (mat_skip(B, p)) return;
+    const int m = mat_rows(B, p);
+    double *A = B.mats + B.mat_off[p];
+    double *Dg = B.dinv + dinv_offset(B, p);
+    if (tid == 0) {
+        fail = 0;
+        double dmax = 0.0;
+        if (B.rel_tol > 0.0)
+            for (int k = 0; k < m; ++k) dmax = fmax(dmax, A[(size_t)k * m + k]);
+        piv_tol = B.rel_tol * dmax;
+    }
+    __syncthreads();
     for (int k0 = 0; k0 < m; k0 += kNB) {
         const int nb = min(kNB, m - k0), rows = m - k0;
         __syncthreads();
@@ -265,15 +299,17 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
         // columns to its right uses the unscaled column divided by the pivot
         for (int j = 0; j < nb; ++j) {
             const double d = Pn[j * kLd + j];
-            if (!(d > 0.0)) {  // the same value for every thread: a uniform exit
+            if (!(d > piv_tol)) {  // the same value for every thread: a uniform exit
                 if (tid == 0) fail = 1;
                 break;
             }
             const double inv = 1.0 / d;
-            const int w = nb - j - 1;
-            for (int idx = tid; idx < rows * w; idx += 256) {
-                const int i = idx / w, c = j + 1 + idx % w;
-                if (i >= c) Pn[i * kLd + c] -= Pn[i * kLd + j] * Pn[c * kLd + j] * inv;
+            // thread t updates rows t, t + 256, ... (entries c of the lower triangle
+            // right of column j); the column-j entries are broadcast reads
+            for (int i = j + 1 + tid; i < rows; i += 256) {
+                const double lij = Pn[i * kLd + j] * inv;
+                const int cmax = min(i, nb - 1);
+                for (int c = j + 1; c <= cmax; ++c) Pn[i * kLd + c] -= lij * Pn[c * kLd + j];
             }
             __syncthreads();
             const double sq = sqrt(d), isq = 1.0 / sq;
@@ -286,7 +322,9 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
             const int i = idx / kNB, t = idx % kNB;
             if (t < nb && i >= t) A[(size_t)(k0 + i) * m + k0 + t] = Pn[i * kLd + t];
         }
-        for (int t = tid; t < nb; t += 256) ldiag[3 * blob_off[p] + k0 + t] = Pn[t * kLd + t];
+        if (B.ldiag)
+            for (int t = tid; t < nb; t += 256)
+                B.ldiag[B.scale * (int64_t)B.off[p] + k0 + t] = Pn[t * kLd + t];
         // inverse of the diagonal block: thread c solves L z = e_c (zero padded)
         if (tid < kNB) {
             const int c = tid;
@@ -315,18 +353,15 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
             const int ntile = (nt + 63) / 64;
             const int w = tid >> 6, l = tid & 63, wr = w >> 1, wc = w & 1;
             const int kt = (nb + 3) & ~3;
-            for (int tile = 0; tile < ntile * (ntile + 1) / 2; ++tile) {
-                int bi = 0;
+            const int ntiles = ntile * (ntile + 1) / 2;
+            // tile -> (bi, bj), bj <= bi, row by row of the lower triangle of tiles
+            auto tile_ij = [](int tile, int &bi, int &bj) {
+                bi = 0;
                 while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
-                const int bj = tile - bi * (bi + 1) / 2;
-                const int i0 = 64 * bi + 32 * wr, j0 = 64 * bj + 32 * wc;
-                int ra[2], rb[2];  // panel rows of this lane's A and B operands
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    ra[q] = nb + min(i0 + 16 * q + (l & 15), nt - 1);
-                    rb[q] = nb + min(j0 + 16 * q + (l & 15), nt - 1);
-                }
-                double cur[2][2][4];  // issued before the products: the loads overlap them
+                bj = tile - bi * (bi + 1) / 2;
+            };
+            // this lane's 16 entries of a tile's 32 x 32 quarter (clamped into the matrix)
+            auto load_quarter = [&](int i0, int j0, double (&v)[2][2][4]) {
 #pragma unroll
                 for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -335,8 +370,28 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
                         for (int e = 0; e < 4; ++e) {
                             const int i = min(i0 + 16 * ti + 4 * e + (l >> 4), nt - 1);
                             const int j = min(j0 + 16 * tj + (l & 15), nt - 1);
-                            cur[ti][tj][e] = A[(size_t)(t0 + i) * m + t0 + j];
+                            v[ti][tj][e] = A[(size_t)(t0 + i) * m + t0 + j];
                         }
+            };
+            // the next tile's entries are read while the current tile's products run
+            double cur[2][2][4], nxt[2][2][4];
+            int bi, bj;
+            tile_ij(0, bi, bj);
+            load_quarter(64 * bi + 32 * wr, 64 * bj + 32 * wc, cur);
+            for (int tile = 0; tile < ntiles; ++tile) {
+                tile_ij(tile, bi, bj);
+                const int i0 = 64 * bi + 32 * wr, j0 = 64 * bj + 32 * wc;
+                if (tile + 1 < ntiles) {
+                    int bi1, bj1;
+                    tile_ij(tile + 1, bi1, bj1);
+                    load_quarter(64 * bi1 + 32 * wr, 64 * bj1 + 32 * wc, nxt);
+                }
+                int ra[2], rb[2];  // panel rows of this lane's A and B operands
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    ra[q] = nb + min(i0 + 16 * q + (l & 15), nt - 1);
+                    rb[q] = nb + min(j0 + 16 * q + (l & 15), nt - 1);
+                }
                 mfma_acc acc[2][2] = {};
                 for (int t = 0; t < kt; t += 4) {
                     const int tc = t + (l >> 4);
@@ -358,11 +413,22 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(const int *__restrict__ b
                             if (i < nt && j <= i)
                                 A[(size_t)(t0 + i) * m + t0 + j] = cur[ti][tj][e] - acc[ti][tj][e];
                         }
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) cur[ti][tj][e] = nxt[ti][tj][e];
             }
         }
     }
     __syncthreads();
-    if (fail && tid == 0) atomicMax(&status[0], p + 1);
+    if (fail && tid == 0) {
+        if (B.fail)
+            B.fail[p] = 1;
+        else
+            atomicMax(&B.status[0], p + 1);
+    }
 }
 
 // load (4 per thread) the 32 x 32 block of L at (R0, C0), zero padded beyond m
@@ -387,20 +453,16 @@ __device__ __forceinline__ void store_block(double (*Ls)[kLd], const double v[4]
 // part of X is stored transposed in the strictly upper triangle of M_pp's
 // storage (the diagonal of X is 1 / diag(L)).  Dynamic LDS: the block column,
 // ceil(max_m / 32) * 32 x kLd doubles.
-__global__ __launch_bounds__(256) void pc_trtri_kernel(const int *__restrict__ blob_off,
-                                                       const int64_t *__restrict__ mat_off,
-                                                       double *__restrict__ mats,
-                                                       const double *__restrict__ dinv,
-                                                       const int *__restrict__ status) {
+__global__ __launch_bounds__(256) void pc_trtri_kernel(MatBatch B) {
     extern __shared__ double X[];
     __shared__ double Ls[kNB][kLd];
     const int p = blockIdx.y, cb = blockIdx.x;
-    if (status[0] != 0) return;
-    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    if (mat_skip(B, p)) return;
+    const int m = mat_rows(B, p);
     const int nbk = (m + kNB - 1) / kNB;
     if (cb >= nbk) return;
-    double *A = mats + mat_off[p];
-    const double *Dg = dinv + dinv_offset(blob_off, p);
+    double *A = B.mats + B.mat_off[p];
+    const double *Dg = B.dinv + dinv_offset(B, p);
     // wavefront w holds the 16 x 16 tile (w / 2, w % 2) of each 32 x 32 block step
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int wr = 16 * (w >> 1), wc = 16 * (w & 1);
@@ -457,16 +519,11 @@ __global__ __launch_bounds__(256) void pc_trtri_kernel(const int *__restrict__ b
 // inverses).  One workgroup per (body, 64 x 64 tile (I, J), I <= J); the sum
 // over k >= J runs in chunks of 32 staged in LDS, the next chunk read into
 // registers meanwhile.  Writes both (I, J) and (J, I).
-__global__ __launch_bounds__(256) void pc_lauum_kernel(const int *__restrict__ blob_off,
-                                                       const int64_t *__restrict__ mat_off,
-                                                       const double *__restrict__ mats,
-                                                       const double *__restrict__ dinv,
-                                                       double *__restrict__ minv,
-                                                       const int *__restrict__ status) {
+__global__ __launch_bounds__(256) void pc_lauum_kernel(MatBatch B) {
     __shared__ double Ua[64][kLd], Ub[64][kLd];
     const int p = blockIdx.y;
-    if (status[0] != 0) return;
-    const int m = 3 * (blob_off[p + 1] - blob_off[p]);
+    if (mat_skip(B, p)) return;
+    const int m = mat_rows(B, p);
     const int nt = (m + 63) / 64;
     const int tile = blockIdx.x;
     if (tile >= nt * (nt + 1) / 2) return;
@@ -474,9 +531,9 @@ __global__ __launch_bounds__(256) void pc_lauum_kernel(const int *__restrict__ b
     while ((bj + 1) * (bj + 2) / 2 <= tile) ++bj;
     const int bi = tile - bj * (bj + 1) / 2;  // bi <= bj
     const int I0 = 64 * bi, J0 = 64 * bj;
-    const double *A = mats + mat_off[p];
-    const double *Dg = dinv + dinv_offset(blob_off, p);
-    double *Mi = minv + mat_off[p];
+    const double *A = B.mats + B.mat_off[p];
+    const double *Dg = B.dinv + dinv_offset(B, p);
+    double *Mi = B.out + B.mat_off[p];
     const int tid = threadIdx.x;
     const int kl = tid & 31, r0 = tid >> 5;  // a thread stages column kl of rows r0 + 8e
     // wavefront w computes the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 matrix-core tiles
@@ -606,6 +663,73 @@ __global__ __launch_bounds__(256) void pc_body_kernel(const int *__restrict__ bl
     }
 }
 
+// S = C_a N~_a C_a^T (na x na, row-major) for the assembly's rows r0 .. r0+na-1,
+// all threads of the block
+__device__ void asm_form_S(int r0, int na, const int *__restrict__ asm_rows,
+                           const int *__restrict__ row_p, const int *__restrict__ row_q,
+                           const double *__restrict__ crow, const double *__restrict__ Nt,
+                           double *__restrict__ S) {
+    for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+        const int k = idx / na, l = idx - (idx / na) * na;
+        const int rk = asm_rows[r0 + k], rl = asm_rows[r0 + l];
+        double sum = 0.0;
+#pragma unroll 1
+        for (int sk = 0; sk < 2; ++sk) {
+            const int bk = sk ? row_q[rk] : row_p[rk];
+            if (bk < 0) continue;
+            const double *ck = crow + 12 * (size_t)rk + 6 * sk;
+#pragma unroll 1
+            for (int sl = 0; sl < 2; ++sl) {
+                const int bl = sl ? row_q[rl] : row_p[rl];
+                if (bl != bk) continue;
+                const double *cl = crow + 12 * (size_t)rl + 6 * sl;
+                const double *Nb = Nt + 36 * (size_t)bk;
+                for (int u = 0; u < 6; ++u) {
+                    double t = 0.0;
+                    for (int v = 0; v < 6; ++v) t += Nb[u * 6 + v] * cl[v];
+                    sum += ck[u] * t;
+                }
+            }
+        }
+        S[(size_t)k * na + l] = sum;
+    }
+}
+
+// the assemblies' S_a for the blocked kernels (assemblies of at most kFastMaxM rows)
+__global__ __launch_bounds__(256) void pc_asm_form_kernel(
+    const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
+    const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
+    const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
+    double *__restrict__ Sbuf, int *__restrict__ fail, const int *__restrict__ status) {
+    const int a = blockIdx.x;
+    const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
+    if (threadIdx.x == 0) fail[a] = 0;
+    if (na == 0 || status[0] != 0) return;
+    asm_form_S(r0, na, asm_rows, row_p, row_q, crow, Nt, Sbuf + asm_mat_off[a]);
+}
+
+// assemblies whose S_a failed the Cholesky pivot test: S_a formed again and its
+// symmetric pseudo-inverse (eigenvalues below 1e-12 * max dropped), Sec. 3.1;
+// X is scratch of na^2 doubles after S in the same assembly slot of Xbuf
+__global__ __launch_bounds__(256) void pc_asm_pinv_kernel(
+    const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
+    const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
+    const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
+    double *__restrict__ Xbuf, double *__restrict__ Gbuf, const int *__restrict__ fail,
+    int *__restrict__ status) {
+    const int a = blockIdx.x;
+    if (!fail[a] || status[0] != 0) return;
+    const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
+    double *S = Xbuf + 2 * asm_mat_off[a];
+    asm_form_S(r0, na, asm_rows, row_p, row_q, crow, Nt, S);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sym_pinv_serial(S, S + (size_t)na * na, na, Gbuf + asm_mat_off[a], 1e-12);
+        atomicAdd(&status[1], 1);
+    }
+}
+
+// assemblies beyond kFastMaxM rows: unblocked Cholesky and inverse in global memory
 __global__ __launch_bounds__(256) void pc_asm_kernel(
     const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
     const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
@@ -623,28 +747,7 @@ __global__ __launch_bounds__(256) void pc_asm_kernel(
     double *G = Gbuf + asm_mat_off[a];
     for (int pass = 0; pass < 2; ++pass) {
         // S = C_a N~ C_a^T
-        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
-            const int k = idx / na, l = idx - (idx / na) * na;
-            const int rk = asm_rows[r0 + k], rl = asm_rows[r0 + l];
-            double s = 0.0;
-            for (int sk = 0; sk < 2; ++sk) {
-                const int bk = sk ? row_q[rk] : row_p[rk];
-                if (bk < 0) continue;
-                const double *ck = crow + 12 * (size_t)rk + 6 * sk;
-                for (int sl = 0; sl < 2; ++sl) {
-                    const int bl = sl ? row_q[rl] : row_p[rl];
-                    if (bl != bk) continue;
-                    const double *cl = crow + 12 * (size_t)rl + 6 * sl;
-                    const double *Nb = Nt + 36 * (size_t)bk;
-                    for (int u = 0; u < 6; ++u) {
-                        double t = 0.0;
-                        for (int v = 0; v < 6; ++v) t += Nb[u * 6 + v] * cl[v];
-                        s += ck[u] * t;
-                    }
-                }
-            }
-            S[(size_t)k * na + l] = s;
-        }
+        asm_form_S(r0, na, asm_rows, row_p, row_q, crow, Nt, S);
         __syncthreads();
         if (pass == 1) {
             // rank-deficient: symmetric pseudo-inverse (Sec. 3.1)
@@ -1117,12 +1220,11 @@ hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
         if (e != hipSuccess) return e;
         const int nt = (max_m + 63) / 64;
-        pc_potrf_kernel<<<P.M, 256, lds_f, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.dinv,
-                                                P.status);
-        pc_trtri_kernel<<<dim3(nbk, P.M), 256, lds_i, s>>>(P.blob_off, P.mat_off, P.mats, P.dinv,
-                                                           P.status);
-        pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.M), 256, 0, s>>>(P.blob_off, P.mat_off, P.mats,
-                                                                    P.dinv, P.minv, P.status);
+        const MatBatch B{P.blob_off, 3, P.mat_off, P.mats, P.ldiag, P.dinv, P.minv, P.status,
+                         nullptr, 0.0};
+        pc_potrf_kernel<<<P.M, 256, lds_f, s>>>(B);
+        pc_trtri_kernel<<<dim3(nbk, P.M), 256, lds_i, s>>>(B);
+        pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.M), 256, 0, s>>>(B);
     } else {
         pc_chol_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.status);
         pc_inverse_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag, P.minv,
@@ -1172,10 +1274,41 @@ void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_of
                                          P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);
 }
 
-void precond_assembly(hipStream_t s, const PrecondDev &P) {
-    if (P.A <= 0) return;
-    pc_asm_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p, P.row_q,
-                                      P.crow, P.Nt, P.S, P.G, P.status);
+// G~_a = S_a^-1 for every assembly (Sec. 3.1).  When the largest assembly has
+// between kAsmBlockedMin and kFastMaxM rows: the blocked kernels of the blob
+// mobilities (S_a formed in P.S, factored in place, the inverse written to P.G),
+// with a pivot test relative to the largest diagonal entry; assemblies that
+// fail it (constraints without full row rank) take the symmetric
+// pseudo-inverse.  Otherwise the one-workgroup kernel.
+hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
+    if (P.A <= 0) return hipSuccess;
+    if (P.asm_max_rows <= kAsmBlockedMin || P.asm_max_rows > kFastMaxM || !P.asm_dinv ||
+        !P.asm_fail) {
+        pc_asm_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
+                                          P.row_q, P.crow, P.Nt, P.S, P.G, P.status);
+        return hipGetLastError();
+    }
+    const int max_m = std::max(P.asm_max_rows, 1);
+    const size_t lds_f = (size_t)max_m * kLd * sizeof(double);
+    const int nbk = (max_m + kNB - 1) / kNB;
+    const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)pc_potrf_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
+    if (e != hipSuccess) return e;
+    const int nt = (max_m + 63) / 64;
+    pc_asm_form_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
+                                           P.row_q, P.crow, P.Nt, P.S, P.asm_fail, P.status);
+    const MatBatch B{P.asm_row_ptr, 1, P.asm_mat_off, P.S, nullptr, P.asm_dinv, P.G, P.status,
+                     P.asm_fail, 1e-12};
+    pc_potrf_kernel<<<P.A, 256, lds_f, s>>>(B);
+    pc_trtri_kernel<<<dim3(nbk, P.A), 256, lds_i, s>>>(B);
+    pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.A), 256, 0, s>>>(B);
+    pc_asm_pinv_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
+                                           P.row_q, P.crow, P.Nt, P.S, P.G, P.asm_fail, P.status);
+    return hipGetLastError();
 }
 
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z) {

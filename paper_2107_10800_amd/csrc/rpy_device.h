@@ -93,7 +93,9 @@ __device__ __forceinline__ TargetZ<T> target_z(T zi) {
 
 // rinv = 1/sqrt(r2) (infinite for coincident blobs), dxy2 = dx^2 + dy^2,
 // zs = target_z(zi), h2 = 2 zj, mh22 = -h2^2, Rz = zi + zj, Ri = 1/|R|
-template <class T, class C>
+// NEAR = false: the caller guarantees r > 2a for every lane (well-separated tiles),
+// so the overlap branch and its wave vote are left out
+template <class T, class C, bool NEAR = true>
 __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T dxy2, const TargetZ<T> &zs,
                                                       T zj, T h2, T mh22, T Rz, T Ri,
                                                       const C &k) {
@@ -101,13 +103,15 @@ __device__ __forceinline__ PairCoef<T> wall_pair_coef(T r2, T rinv, T dxy2, cons
     const T rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
     T c1 = fma(k.k1, rinv3, rinv);
     T c2 = fma(-k.k2, rinv3 * rinv2, rinv3);
-    ARB_IF_ANY_OVERLAP(r2 <= k.four_a2)
-    if (r2 <= k.four_a2) {
-        const T rv = r2 > T(0) ? rinv : T(0);
-        c1 = fma(-k.n2, r2 * rv, k.n1);
-        c2 = rv * k.n3;
+    if (NEAR) {
+        ARB_IF_ANY_OVERLAP(r2 <= k.four_a2)
+        if (r2 <= k.four_a2) {
+            const T rv = r2 > T(0) ? rinv : T(0);
+            c1 = fma(-k.n2, r2 * rv, k.n1);
+            c2 = rv * k.n3;
+        }
+        ARB_END_IF_ANY
     }
-    ARB_END_IF_ANY
     const T s = Ri * Ri;
     const T Ri3 = Ri * s;
     const T Ri5 = Ri3 * s;

@@ -79,17 +79,3 @@ def train(ctx, X, T, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed
         if log:
             log(f"epoch {ep}: loss {loss:.3e} lr {lr:.2e}")
     return hist
-
-
-def mobility_from_output(Y, a: float = 1.0, eta: float = 1.0):
-    """Body mobilities (B, 6, 6) from network outputs (B, 21): lower triangle of L
-    row by row with log L_ii on the diagonal, N~ = D^-1 L L^T D^-1,
-    D = diag(sqrt(6 pi eta a) I3, sqrt(8 pi eta a^3) I3) (for reporting)."""
-    Y = np.asarray(Y, np.float64).reshape(-1, 21)
-    rows, cols = np.tril_indices(6)
-    L = np.zeros((len(Y), 6, 6))
-    L[:, rows, cols] = Y
-    d = np.arange(6)
-    L[:, d, d] = np.exp(L[:, d, d])
-    D = np.array([np.sqrt(6 * np.pi * eta * a)] * 3 + [np.sqrt(8 * np.pi * eta * a ** 3)] * 3)
-    return (L @ L.transpose(0, 2, 1)) / D[None, :, None] / D[None, None, :]

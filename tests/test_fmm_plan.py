@@ -148,7 +148,7 @@ def test_plan_of_many_blobs():
 def test_default_level_of_many_blobs(n):
     """400,000 blobs in a thin slab: the level search counts its pairs on
     several host threads. Its choice against the rule, with the pair counts of
-    plans at explicit levels (counted by the serial build of the lists): the
+    plans at explicit levels (counted from the lists those plans build): the
     cost falls down to the chosen level and does not fall one level deeper."""
     pos = blobs(400_000, (700, 700, 6), 90 + n)
     st = arb.arb_fmm_plan(pos, 1.0, order=n)
@@ -167,3 +167,28 @@ def test_default_level_of_many_blobs(n):
         assert cost(L + 1) >= costs[-1]
     ref = arb.arb_fmm_plan(pos, 1.0, order=n, levels=L)
     assert {k: st[k] for k in st if k != "build_ms"} == {k: ref[k] for k in ref if k != "build_ms"}
+
+
+@pytest.mark.parametrize("N,box,seed,kw", [
+    (200_000, (400, 400, 12), 77, dict(order=3, levels=5)),
+    (400_000, (700, 700, 6), 94, dict(order=6)),
+    (400_000, (700, 700, 6), 94, dict(order=4, leaf=40)),
+])
+def test_threaded_plan_equals_serial_plan(monkeypatch, N, box, seed, kw):
+    """The octree planned on several host threads is the one a single thread
+    plans, array for array: blob order, cells, interaction and near lists,
+    work items and tables (their hash), and every count."""
+    pos = blobs(N, box, seed)
+    monkeypatch.setenv("ARB_HOST_THREADS", "1")
+    serial = arb.arb_fmm_plan(pos, 1.0, **kw)
+    monkeypatch.setenv("ARB_HOST_THREADS", "16")
+    threaded = arb.arb_fmm_plan(pos, 1.0, **kw)
+    drop = ("build_ms",)
+    assert {k: v for k, v in serial.items() if k not in drop} == \
+        {k: v for k, v in threaded.items() if k not in drop}
+    assert serial["plan_hash"] != 0
+    # a different input gives a different plan hash
+    pos2 = pos.copy()
+    pos2[[0, 1]] = pos2[[1, 0]]
+    assert arb.arb_fmm_plan(pos2, 1.0, **kw)["plan_hash"] != serial["plan_hash"]
+

@@ -77,6 +77,39 @@ def test_slab_full_size_sampled(ctxs, prec):
     assert rel(u[tg], uo) <= TOL[prec]
 
 
+@pytest.mark.parametrize("wall", [True, False])
+def test_far_tiles_on_ordered_blobs(wall):
+    # blobs stored in spatial order (the slab sorted along x; bacteria, whose
+    # blobs are contiguous per body): most 64-blob tiles are compact and far
+    # apart, so the symmetric FP32 kernel evaluates those tile pairs from the hi
+    # parts of the positions alone; sampled rows against the oracle's compiled
+    # route over every source, at the FP32 product's bar
+    from oracle import rpy_c
+
+    sl = W.slab()
+    order = np.argsort(sl["pos"][:, 0], kind="stable")
+    pos, lam = sl["pos"][order], sl["lam"][order]
+    if not wall:
+        pos = pos + np.array([0.0, 0.0, 30.0])
+    N = len(pos)
+    bact = W.bacteria(n_bact=256, seed=3)
+    import oracle.bodies as ob
+    bpos = ob.blob_positions(bact.q, bact.theta, bact.r_ref, bact.blob_offset)
+    blam = np.random.default_rng(5).standard_normal(bpos.shape)
+    for name, P, L in (("sorted slab", pos, lam), ("256 bacteria", bpos, blam)):
+        c = arb.arb_create(precision=arb.ARB_FP32C, wall=wall, pair_kernel=arb.ARB_PAIR_SYMMETRIC)
+        try:
+            u = arb.arb_rpy_apply(c, P, L).reshape(-1, 3)
+        finally:
+            arb.arb_destroy(c)
+        rng = np.random.default_rng(1)
+        tg = np.unique(np.concatenate([[0, 63, 64, len(P) - 1], rng.integers(0, len(P), 124)]))
+        uo = rpy_c.mobility_apply(P, L, 1.0, 1.0, wall, targets=tg)
+        e = rel(u[tg], uo)
+        print(f"  far tiles, {name}, wall={wall}: sampled-row error {e:.2e}", flush=True)
+        assert e <= TOL[arb.ARB_FP32C]
+
+
 def test_device_pointer_entry_point_matches_host(ctxs):
     import torch
 
