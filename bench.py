@@ -4,8 +4,11 @@ Headline (`value`): wall-RPY blob-pair interactions per second for one mobility
 product u = M lambda over the 16,384-blob slab above a no-slip wall
 (400a x 400a x [1.5a, 20a], minimum separation 2a, lambda ~ N(0,1)), FP32
 pair sums with hi/lo positions and double accumulation across tiles.  One step
-= one full product (all N^2 ordered pairs, self included); inputs resident on
-the GPU before timing.
+= one full product (all N^2 ordered pairs, self included) at a fixed
+configuration, as in the solver: the positions are a context's state, set once
+(the library prepares its own copy of them then), and every step multiplies
+lambda; inputs resident on the GPU before timing.  The stateless entry point
+(positions prepared inside every call) is reported beside it.
 
 Also reported: the same product in FP64, the dominant kernel's roofline
 (algorithmic flops / its HIP-event-timed duration), the CPU oracle on a bounded
@@ -71,15 +74,21 @@ def kernel_name(shape, prec="f32c"):
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 HBM_TBS = 8.0
-# HBM traffic of one timed pair product from the FETCH_SIZE / WRITE_SIZE runs recorded
-# under profiles/, scaled by the counts of a 256 MiB copy; each record is valid only
-# for the kernel sources and launch shape it was measured on
+# HBM traffic of one pair product from the FETCH_SIZE / WRITE_SIZE runs recorded
+# under profiles/ (KiB per dispatch, per launch shape the autotuner can pick),
+# scaled by the counts of a 256 MiB copy; valid only for the kernel sources they
+# were measured on (sha256 prefix of the listed files)
 COPY_CAL = {"copy_fetch_kib": 131091.4, "copy_write_kib": 262144.0, "copy_kib": 262144.0}
 TRAFFIC = {
-    "target": {"src": ("pair.hip", "rpy_device.h"), "sha256_16": None, "shape": 64,
-               "fetch_kib": None, "write_kib": None},
-    "symmetric": {"src": ("pair_sym.hip", "rpy_device.h"), "sha256_16": "20eb993d4912d64c",
-                  "shape": -1, "fetch_kib": 4062.8, "write_kib": 60864.0},
+    # target-parallel kernel: shape = source slices
+    "target": {"src": ("pair.hip", "rpy_device.h"), "sha256_16": "e09d2227e560edfa",
+               "by_shape": {16: (3858.0, 6144.0), 32: (3858.0, 12288.0),
+                            64: (3858.0, 24576.0)}},
+    # symmetric kernel: shape = -(source tiles per work item)
+    "symmetric": {"src": ("pair_sym.hip", "rpy_device.h"), "sha256_16": "38aaae37f5705084",
+                  "by_shape": {-1: (4415.2, 60864.0), -2: (4156.2, 36672.0),
+                               -4: (4072.9, 24576.0), -8: (3917.4, 18624.0),
+                               -16: (3967.9, 15648.0)}},
 }
 
 
@@ -87,16 +96,18 @@ def measured_traffic(kind, shape):
     import hashlib
 
     t = TRAFFIC[kind]
-    if t.get("shape", shape) != shape or t["sha256_16"] is None:
+    rec = t["by_shape"].get(shape)
+    if rec is None or t["sha256_16"] is None:
         return None
     d = hashlib.sha256()
     for f in t["src"]:
         d.update(open(os.path.join(ROOT, "paper_2107_10800_amd", "csrc", f), "rb").read())
     if d.hexdigest()[:16] != t["sha256_16"]:
         return None
+    fetch_kib, write_kib = rec
     c = COPY_CAL
-    kib = (t["fetch_kib"] * c["copy_kib"] / c["copy_fetch_kib"]
-           + t["write_kib"] * c["copy_kib"] / c["copy_write_kib"])
+    kib = (fetch_kib * c["copy_kib"] / c["copy_fetch_kib"]
+           + write_kib * c["copy_kib"] / c["copy_write_kib"])
     return kib * 1024.0
 
 
@@ -151,6 +162,45 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def matvec_bench_state(torch, arb, W, sl, precision, steps, warmup):
+    """The product over a context's blobs at a fixed configuration (the solver's
+    use: the positions are the state, set once; each step multiplies a new lambda):
+    the headline."""
+    N = len(sl["pos"])
+    wl = W.loose_blobs(sl["pos"], sl["a"], sl["eta"], wall=True, name="wall slab")
+    ctx = arb.context_for(wl, precision=precision)
+    try:
+        dev = torch.device("cuda")
+        lam = torch.tensor(sl["lam"].ravel(), dtype=torch.float64, device=dev)
+        u = torch.zeros_like(lam)
+        stream = torch.cuda.Stream()
+        sh = stream.cuda_stream
+        torch.cuda.synchronize()
+        for _ in range(max(warmup, 1)):          # includes the launch-shape autotune
+            arb.arb_mobility_apply_dev(ctx, lam, u, stream=sh)
+        torch.cuda.synchronize()
+        arb.arb_profile_read(ctx)
+        arb.arb_profile(ctx, True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            arb.arb_mobility_apply_dev(ctx, lam, u, stream=sh)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        kms, launches = arb.arb_profile_read(ctx)
+        arb.arb_profile(ctx, False)
+        slices = arb.arb_get_slices(ctx, N)
+        out = u.cpu().numpy()
+        return dict(ms_per_step=ms / steps, wall_s=wall, kernel_ms=kms / max(launches, 1),
+                    launches=launches, slices=slices, u=out)
+    finally:
+        arb.arb_destroy(ctx)
 
 
 def matvec_bench(torch, arb, sl, precision, steps, warmup):
@@ -689,6 +739,9 @@ def main():
                     help="run only the single-blob block (for profiling)")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="run only the headline FP32 product (autotune in the warm-up, then "
+                         "--steps timed; for the counter runs) and print its timing")
     ap.add_argument("--solve-only", action="store_true",
                     help="run only the 1,024-bacteria FP32 solve (one warm-up, --steps timed; "
                          "for per-kernel profiles) and the filament solve")
@@ -737,11 +790,18 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 268435456 bytes read, 268435456 bytes written")
     log(f"bench: wall slab N={N} f32c, {args.steps} steps")
-    r32 = matvec_bench(torch, arb, sl, arb.ARB_FP32C, args.steps, args.warmup)
+    r32 = matvec_bench_state(torch, arb, W, sl, arb.ARB_FP32C, args.steps, args.warmup)
     log(f"bench: f32c {r32['ms_per_step']:.4f} ms/step, kernel {r32['kernel_ms']:.4f} ms, "
         f"slices {r32['slices']}")
-    r64 = matvec_bench(torch, arb, sl, arb.ARB_FP64, max(args.steps // 4, 5), 2)
+    if args.matvec_only:
+        print(json.dumps({k: v for k, v in r32.items() if k != "u"}), flush=True)
+        return
+    r64 = matvec_bench_state(torch, arb, W, sl, arb.ARB_FP64, max(args.steps // 4, 5), 2)
     log(f"bench: f64 {r64['ms_per_step']:.4f} ms/step")
+    # the stateless entry point (positions prepared inside every call, blobs in the
+    # order given, here the generator's random order)
+    s32 = matvec_bench(torch, arb, sl, arb.ARB_FP32C, args.steps, args.warmup)
+    log(f"bench: stateless f32c {s32['ms_per_step']:.4f} ms/step, kernel {s32['kernel_ms']:.4f} ms")
     pairs = float(N) * N
     value = pairs / (r32["ms_per_step"] * 1e-3)
     flops = algorithmic_flops(N, r32["slices"], "f32c")
@@ -762,7 +822,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "wall-RPY mobility product, 16384 blobs in 400a x 400a x "
                                "[1.5a,20a] above a no-slip wall, min separation 2a, "
-                               "lambda ~ N(0,1); one product per step",
+                               "lambda ~ N(0,1); one product per step at a fixed "
+                               "configuration (positions set once as the context's state)",
                    "N": N, "pairs_per_step": int(pairs), "slices": r32["slices"],
                    "parity_rel_err_sampled": None},
         "roofline": {"bound": "alu",
@@ -772,9 +833,16 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "flops_per_pair": (FLOPS_SYM[("f32c", True)] if r32["slices"] < 0
                                         else FLOPS_ONE_WAY[("f32c", True)]),
-                     "kernel_ms": r32["kernel_ms"], "traffic": measured_traffic("symmetric" if r32["slices"] < 0 else "target",
+                     "kernel_ms": r32["kernel_ms"],
+                     "traffic": measured_traffic("symmetric" if r32["slices"] < 0 else "target",
                                                  r32["slices"]),
-                     "traffic_unit": "bytes per launch"},
+                     "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE of the "
+                                     "launch shape timed, scaled by a 256 MiB copy)"},
+        "stateless": {"value": pairs / (s32["ms_per_step"] * 1e-3), "unit": "pairs/s",
+                      "ms_per_step": s32["ms_per_step"], "kernel_ms": s32["kernel_ms"],
+                      "slices": s32["slices"],
+                      "note": "arb_rpy_apply_dev: positions prepared inside every call, blobs "
+                              "in the generator's random order"},
         "fp64": {"value": pairs / (r64["ms_per_step"] * 1e-3), "unit": "pairs/s",
                  "ms_per_step": r64["ms_per_step"], "kernel_ms": r64["kernel_ms"],
                  "kernel": kernel_name(r64["slices"], "f64"), "slices": r64["slices"],

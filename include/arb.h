@@ -95,6 +95,9 @@ typedef struct {
     int    max_iter;   /* GMRES iteration cap (all cycles)                     */
     int    precond;    /* ARB_PC_*                                             */
     int    slices;     /* source slices of the pair kernel; 0 = autotune       */
+                       /* (systems of at most 1,024 blobs sum over runs of 16  */
+                       /* sources per workgroup instead, unless pair_kernel =  */
+                       /* ARB_PAIR_SYMMETRIC)                                  */
     int    pair_kernel; /* 0 = autotuned choice, 1 = target-parallel kernel   */
                         /* (ordered reduction: bitwise reproducible),          */
                         /* 2 = symmetric kernel (each unordered pair once,     */

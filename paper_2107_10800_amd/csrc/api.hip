@@ -260,6 +260,85 @@ int ready(arb_ctx *ctx) {
     return 0;
 }
 
+// 21 bits of x spread to every third bit (Morton interleaving)
+uint64_t spread21(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// The dense pair kernels' blob order for the current state.  The symmetric FP32
+// kernel tests tiles of 64 consecutive blobs for distance; when the blobs' own
+// order leaves tiles spread over the suspension (loose blobs in random order:
+// mean tile diagonal above a quarter of the suspension's), the products run on
+// a copy sorted along a Morton curve, made here once per state (positions and
+// tile boxes in that order, and the permutation, through which the kernels read
+// lambda and write u).  Bodies' blobs, contiguous per body, already give compact
+// tiles and keep their order.
+int pair_order(arb_ctx *ctx, hipStream_t s) {
+    const int N = ctx->N;
+    const int nt = (N + 63) / 64;
+    ctx->psorted = false;
+    if (nt < 8) return 0;
+    std::vector<float4> box(2 * (size_t)nt);
+    HIPCHK(hipMemcpyAsync(box.data(), ctx->tbox.p, box.size() * sizeof(float4),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float lo[3] = {box[0].x, box[0].y, box[0].z}, hi[3] = {box[1].x, box[1].y, box[1].z};
+    double mean = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const float4 a = box[2 * t], b = box[2 * t + 1];
+        lo[0] = std::min(lo[0], a.x), lo[1] = std::min(lo[1], a.y), lo[2] = std::min(lo[2], a.z);
+        hi[0] = std::max(hi[0], b.x), hi[1] = std::max(hi[1], b.y), hi[2] = std::max(hi[2], b.z);
+        mean += std::sqrt(double(b.x - a.x) * (b.x - a.x) + double(b.y - a.y) * (b.y - a.y) +
+                          double(b.z - a.z) * (b.z - a.z));
+    }
+    mean /= nt;
+    const double dom = std::sqrt(double(hi[0] - lo[0]) * (hi[0] - lo[0]) +
+                                 double(hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                 double(hi[2] - lo[2]) * (hi[2] - lo[2]));
+    if (!(mean > 0.25 * dom)) return 0;
+    std::vector<double> pos(3 * (size_t)N);
+    HIPCHK(hipMemcpyAsync(pos.data(), ctx->pos.p, pos.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double pl[3], ph[3];
+    for (int c = 0; c < 3; ++c) pl[c] = ph[c] = pos[c];
+    for (int i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            pl[c] = std::min(pl[c], pos[3 * (size_t)i + c]);
+            ph[c] = std::max(ph[c], pos[3 * (size_t)i + c]);
+        }
+    const double side = std::max({ph[0] - pl[0], ph[1] - pl[1], ph[2] - pl[2], 1e-300});
+    std::vector<std::pair<uint64_t, int>> key((size_t)N);
+    for (int i = 0; i < N; ++i) {
+        uint64_t k = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double f = (pos[3 * (size_t)i + c] - pl[c]) / side;
+            const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, f * 2097151.0));
+            k |= spread21(q) << (2 - c);
+        }
+        key[i] = {k, i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> perm((size_t)N);
+    for (int k = 0; k < N; ++k) perm[k] = key[k].second;
+    TRY(upload(ctx, ctx->pperm, perm.data(), N, s));
+    HIPCHK(ctx->p64s.ensure((size_t)N * sizeof(double4)));
+    HIPCHK(ctx->his.ensure((size_t)N * sizeof(float4)));
+    HIPCHK(ctx->los.ensure((size_t)N * sizeof(float4)));
+    HIPCHK(ctx->tboxs.ensure(2 * (size_t)nt * sizeof(float4)));
+    arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->opt.a, ctx->p64s.as<double4>(),
+                        ctx->his.as<float4>(), ctx->los.as<float4>(), ctx->tboxs.as<float4>(),
+                        ctx->pperm.as<int>());
+    ctx->psorted = true;
+    return 0;
+}
+
 // geometry of the current state: rotations, blob positions, constraint rows
 int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
     const int N = ctx->N, M = ctx->M;
@@ -274,7 +353,9 @@ int refresh_geometry(arb_ctx *ctx, hipStream_t s) {
     arb::blob_geometry(s, N, ctx->body_of_blob.as<int>(), ctx->q.as<double>(), ctx->R9.as<double>(),
                        ctx->r_ref.as<double>(), ctx->pos.as<double>(), ctx->dvec.as<double>());
     arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->opt.a, ctx->p64.as<double4>(),
-                        ctx->hi.as<float4>(), ctx->lo.as<float4>(), ctx->tbox.as<float4>());
+                        ctx->hi.as<float4>(), ctx->lo.as<float4>(), ctx->tbox.as<float4>(),
+                        nullptr);
+    TRY(pair_order(ctx, s));
     if (!ctx->topo_dirty) TRY(refresh_rows(ctx, s));
     ctx->pc_built = false;
     ctx->fmm.dirty = true;
@@ -302,30 +383,38 @@ int sym_worklist(arb_ctx *ctx, hipStream_t s, int N, int R, int precision) {
 // one pair product; shape > 0: target-parallel kernel with that many source
 // slices; shape < 0: symmetric kernel with -shape source tiles per work item
 int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
-             const float4 *lo, const float4 *box, const double *lam, double *out, const double *U,
-             const int *bob,
+             const float4 *lo, const float4 *box, const int *perm, const double *lam, double *out,
+             const double *U, const int *bob,
              const double *dvec, int precision, bool wall, int shape) {
     const bool sym = shape < 0;
+    // small systems take the run-sliced target-parallel kernel whatever the shape
+    const bool small = N <= arb::kSmallPairN && ctx->opt.pair_kernel != ARB_PAIR_SYMMETRIC;
     int used = 1;
-    if (sym) {
+    if (small) {
+        const int runs = (N + arb::kSmallRun - 1) / arb::kSmallRun;
+        HIPCHK(ctx->partial.ensure((size_t)runs * 3 * N * sizeof(double)));
+    } else if (sym) {
         TRY(sym_worklist(ctx, s, N, -shape, precision));
         HIPCHK(ctx->partial.ensure((size_t)3 * N * sizeof(double)));
     } else {
         HIPCHK(ctx->partial.ensure((size_t)shape * 3 * N * sizeof(double)));
     }
-    if (sym) arb::pair_sym_clear(s, N, ctx->partial.as<double>());
+    if (sym && !small) arb::pair_sym_clear(s, N, ctx->partial.as<double>());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->prof) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, s));
     }
-    if (sym)
-        arb::pair_sym(s, precision, wall, N, p64, hi, lo, box, lam, ctx->opt.a,
+    if (small)
+        used = arb::pair_partial_small(s, precision, wall, N, p64, hi, lo, lam, perm, ctx->opt.a,
+                                       ctx->partial.as<double>());
+    else if (sym)
+        arb::pair_sym(s, precision, wall, N, p64, hi, lo, box, lam, perm, ctx->opt.a,
                       ctx->sym_work[precision == ARB_FP32C].as<int4>(),
                       ctx->sym_n_work[precision == ARB_FP32C], ctx->partial.as<double>());
     else
-        used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, ctx->opt.a, shape,
+        used = arb::pair_partial(s, precision, wall, N, p64, hi, lo, lam, perm, ctx->opt.a, shape,
                                  ctx->partial.as<double>());
     if (ctx->prof) {
         HIPCHK(hipEventRecord(e1, s));
@@ -334,15 +423,15 @@ int run_pair(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float
     // FP32 sums are in units of the blob radius: M(a) = M_{a=1}(r / a) / a
     const double scale = 1.0 / (8.0 * arb::kPi * ctx->opt.eta) /
                          (precision == ARB_FP32C ? ctx->opt.a : 1.0);
-    arb::pair_reduce(s, N, used, ctx->partial.as<double>(), scale, out, U, bob, dvec);
+    arb::pair_reduce(s, N, used, ctx->partial.as<double>(), scale, out, U, bob, dvec, perm);
     return 0;
 }
 
 // launch shape for (N, precision, wall): from the options, the cache, or by
 // timing every candidate shape on the first product of that size
 int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const float4 *hi,
-                  const float4 *lo, const float4 *box, const double *lam, int precision, bool wall,
-                  int *shape) {
+                  const float4 *lo, const float4 *box, const int *perm, const double *lam,
+                  int precision, bool wall, int *shape) {
     const int kind = ctx->opt.pair_kernel;
     const bool sym_ok = kind != 1;
     if (ctx->opt.slices > 0 && kind != 2) {
@@ -383,8 +472,8 @@ int choose_slices(arb_ctx *ctx, hipStream_t s, int N, const double4 *p64, const 
             float tmin = 1e30f;
             for (int rep = 0, reps = 5; rep < reps; ++rep) {
                 HIPCHK(hipEventRecord(e0, s));
-                TRY(run_pair(ctx, s, N, p64, hi, lo, box, lam, ctx->tune_out.as<double>(), nullptr,
-                             nullptr, nullptr, precision, wall, c));
+                TRY(run_pair(ctx, s, N, p64, hi, lo, box, perm, lam, ctx->tune_out.as<double>(),
+                             nullptr, nullptr, nullptr, precision, wall, c));
                 HIPCHK(hipEventRecord(e1, s));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -439,7 +528,8 @@ int fmm_pair(arb_ctx *ctx, hipStream_t s, int N, const double *pos, const float4
     }
     // sums in units of the blob radius: M(a) = M_{a=1}(r / a) / a
     const double scale = 1.0 / (8.0 * arb::kPi * ctx->opt.eta) / ctx->opt.a;
-    if (N > 0) arb::pair_reduce(s, N, 1, ctx->partial.as<double>(), scale, out, U, bob, dvec);
+    if (N > 0)
+        arb::pair_reduce(s, N, 1, ctx->partial.as<double>(), scale, out, U, bob, dvec, nullptr);
     return 0;
 }
 
@@ -450,13 +540,17 @@ int ctx_pair(arb_ctx *ctx, hipStream_t s, const double *lam, double *out, const 
                         ctx->lo.as<float4>(), lam, out, U, ctx->body_of_blob.as<int>(),
                         ctx->dvec.as<double>(), false, precision);
     const bool wall = ctx->opt.wall != 0;
+    // the state's positions in the pair kernels' order (pair_order)
+    const bool so = ctx->psorted;
+    const double4 *p64 = (so ? ctx->p64s : ctx->p64).as<double4>();
+    const float4 *hi = (so ? ctx->his : ctx->hi).as<float4>();
+    const float4 *lo = (so ? ctx->los : ctx->lo).as<float4>();
+    const float4 *box = (so ? ctx->tboxs : ctx->tbox).as<float4>();
+    const int *perm = so ? ctx->pperm.as<int>() : nullptr;
     int sl = 0;
-    TRY(choose_slices(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
-                      ctx->lo.as<float4>(), ctx->tbox.as<float4>(), lam, precision, wall, &sl));
-    return run_pair(ctx, s, ctx->N, ctx->p64.as<double4>(), ctx->hi.as<float4>(),
-                    ctx->lo.as<float4>(), ctx->tbox.as<float4>(), lam, out, U,
-                    ctx->body_of_blob.as<int>(),
-                    ctx->dvec.as<double>(), precision, wall, sl);
+    TRY(choose_slices(ctx, s, ctx->N, p64, hi, lo, box, perm, lam, precision, wall, &sl));
+    return run_pair(ctx, s, ctx->N, p64, hi, lo, box, perm, lam, out, U,
+                    ctx->body_of_blob.as<int>(), ctx->dvec.as<double>(), precision, wall, sl);
 }
 
 // out = A y (Eq. linear_system)
@@ -878,7 +972,7 @@ std::vector<long long> graph_key(arb_ctx *ctx, const Krylov &K, int prec) {
     const int64_t skey = (int64_t)ctx->N * 4 + prec * 2 + (ctx->opt.wall ? 1 : 0);
     auto it = ctx->slice_cache.find(skey);
     return {(long long)arb::alloc_generation().load(), (long long)K.n, K.m, prec,
-            ctx->opt.precond, ctx->opt.left_precond, ctx->pc_learned ? 1 : 0,
+            ctx->opt.precond, ctx->opt.left_precond, ctx->psorted ? 1 : 0, ctx->pc_learned ? 1 : 0,
             ctx->pc_lcorr ? 1 : 0, ctx->N, ctx->M,
             ctx->Nc, ctx->n_asm, it == ctx->slice_cache.end() ? 0 : it->second,
             (long long)(intptr_t)K.V, (long long)(intptr_t)ctx->pinned, ctx->fmm.version};
@@ -933,8 +1027,9 @@ int run_step_graph(arb_ctx *ctx, hipStream_t s, int j, const std::vector<long lo
 // after the iteration budget.  Returns the final residual norm in *res.
 //
 // The host reads two scalars per Arnoldi step (h_{j+1,j} and the estimate) to
-// decide when to stop.  When a step is cheap (under half a millisecond, e.g.
-// small systems whose steps are launch-bound) the next step is enqueued before
+// decide when to stop.  When a step is cheap (at most 65,536 unknowns, or a first
+// step under half a millisecond: steps that are launch-bound) the next step is
+// enqueued before
 // the host waits for the current one's scalars, so the device never idles on
 // the host; a step launched past the stopping point only writes Krylov columns
 // beyond those the update uses, so the result is the same.
@@ -1034,7 +1129,7 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
             const double t_launch = now_ms();
             while (launched < budget && launched <= j + lag) TRY(launch(launched++));
             HIPCHK(hipEventSynchronize(ctx->step_ev[j]));
-            if (j == 0) lag = (now_ms() - t_launch) < 0.5 ? 1 : 0;
+            if (j == 0) lag = (n <= 65536 || now_ms() - t_launch < 0.5) ? 1 : 0;
             const double hn = pin_step[2 * j], est = pin_step[2 * j + 1];
             if (!std::isfinite(est)) return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
             ++*total;
@@ -1507,7 +1602,7 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *
     float4 *hi = reinterpret_cast<float4 *>(p64 + N);
     float4 *lo = hi + N;
     float4 *box = lo + N;
-    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo, box);
+    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo, box, nullptr);
     if (ctx->opt.pair_kernel == ARB_PAIR_FMM) {
         // a tree of these positions; the context's own is rebuilt at its next product
         TRY(fmm_pair(ctx, s, N, pos_dev, hi, lo, lambda_dev, u_dev, nullptr, nullptr, nullptr,
@@ -1518,8 +1613,9 @@ int arb_rpy_apply_dev(arb_ctx *ctx, int N, const double *pos_dev, const double *
     }
     const bool wall = ctx->opt.wall != 0;
     int sl = 0;
-    TRY(choose_slices(ctx, s, N, p64, hi, lo, box, lambda_dev, ctx->opt.precision, wall, &sl));
-    TRY(run_pair(ctx, s, N, p64, hi, lo, box, lambda_dev, u_dev, nullptr, nullptr, nullptr,
+    TRY(choose_slices(ctx, s, N, p64, hi, lo, box, nullptr, lambda_dev, ctx->opt.precision, wall,
+                      &sl));
+    TRY(run_pair(ctx, s, N, p64, hi, lo, box, nullptr, lambda_dev, u_dev, nullptr, nullptr, nullptr,
                  ctx->opt.precision, wall, sl));
     HIPCHK(hipGetLastError());
     return ARB_OK;

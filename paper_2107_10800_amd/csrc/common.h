@@ -115,8 +115,9 @@ void fmm_apply6(const FmmState &F, hipStream_t s, bool fp64, const double *x6, d
 // then an ordered reduction.  Positions are prepared by prep_positions().
 // box (may be null): 2 float4 per 64-blob tile, its bounding box and largest
 // |coordinate| (pair_sym's far test)
+// perm (may be null): entry i of the outputs holds blob perm[i]
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
-                    float4 *hi, float4 *lo, float4 *box);
+                    float4 *hi, float4 *lo, float4 *box, const int *perm);
 // device address of the allocation-free entry point's scratch array for the
 // current device (noalloc.hip), looked up once per device; 0 when known
 int noalloc_setup(int device);
@@ -124,20 +125,31 @@ int noalloc_setup(int device);
 // the grid stays within about 2,048 workgroups and every slice keeps a tile
 int heuristic_slices(int N);
 // returns the number of slices written (clamped to the tile count)
+// small systems: target-parallel sums over runs of kSmallRun sources, one 64-lane
+// workgroup per (64 targets, run); partial holds ceil(N / kSmallRun) slices;
+// returns that count
+constexpr int kSmallPairN = 1024;
+constexpr int kSmallRun = 16;
+int pair_partial_small(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+                       const float4 *hi, const float4 *lo, const double *lam, const int *perm,
+                       double a, double *partial);
+// positions in the order of perm (may be null), lambda in blob order, partial in
+// the positions' order
 int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-                  const float4 *hi, const float4 *lo, const double *lam, double a,
-                  int slices, double *partial);
+                  const float4 *hi, const float4 *lo, const double *lam, const int *perm,
+                  double a, int slices, double *partial);
 // out_i = scale * sum_s partial[s][c][i]  -  (K U)_i   (the K term only if U != nullptr)
 void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double scale,
-                 double *out, const double *U, const int *body_of_blob, const double *dvec);
+                 double *out, const double *U, const int *body_of_blob, const double *dvec,
+                 const int *perm);
 int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,
                         int *flag_host);
 // symmetric pair sums, FP32 (hi/lo) or FP64 (p64) (pair_sym.hip): u [3][N]
 // unscaled, accumulated into u (cleared first by pair_sym_clear)
 void pair_sym_clear(hipStream_t s, int N, double *u);
 void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-              const float4 *hi, const float4 *lo, const float4 *box, const double *lam, double a,
-              const int4 *work, int n_work, double *u);
+              const float4 *hi, const float4 *lo, const float4 *box, const double *lam,
+              const int *perm, double a, const int4 *work, int n_work, double *u);
 std::vector<int4> pair_sym_worklist(int N, int R);
 
 // Rigid-body kinematics (Sec. 2.1, 2.3, App. B)
@@ -371,6 +383,11 @@ struct arb_ctx {
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
     arb::DevBuf tbox;  // per 64-blob tile of the state's positions: bounding box (prep_positions)
+    // the dense pair kernels' copy of the state's positions in Morton order when the
+    // blobs' own order leaves tiles spread out (pair_order in api.hip): the
+    // permutation (entry k = blob pperm[k]), positions and tile boxes in that order
+    bool psorted = false;
+    arb::DevBuf pperm, p64s, his, los, tboxs;
     arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
     // host pinned scratch: kPinnedScalars doubles for entry points, then two per
     // Arnoldi step (h_{j+1,j}, residual estimate) at pinned + kPinnedScalars

@@ -93,13 +93,13 @@ static int rpy_apply_noalloc(arb_ctx *ctx, int N, const double *pos_dev,
     const int cap = (int)(kPartialDoubles / (3 * (size_t)N));
     slices = std::max(1, std::min(slices, cap));
     hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo, nullptr);
+    arb::prep_positions(s, N, pos_dev, ctx->opt.a, p64, hi, lo, nullptr, nullptr);
     const int used = arb::pair_partial(s, ctx->opt.precision, ctx->opt.wall != 0, N, p64, hi,
-                                       lo, lambda_dev, ctx->opt.a, slices, partial);
+                                       lo, lambda_dev, nullptr, ctx->opt.a, slices, partial);
     // FP32 sums are in units of the blob radius: M(a) = M_{a=1}(r / a) / a
     const double scale = 1.0 / (8.0 * arb::kPi * ctx->opt.eta) /
                          (ctx->opt.precision == ARB_FP32C ? ctx->opt.a : 1.0);
-    arb::pair_reduce(s, N, used, partial, scale, u_dev, nullptr, nullptr, nullptr);
+    arb::pair_reduce(s, N, used, partial, scale, u_dev, nullptr, nullptr, nullptr, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess)
         return fail(ctx, ARB_E_DEVICE, std::string("pair launch: ") + hipGetErrorString(e));

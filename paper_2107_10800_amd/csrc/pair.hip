@@ -34,16 +34,19 @@ namespace arb {
 // box (may be null): per tile of 64 consecutive blobs (one wavefront here),
 // box[2t] = (min x, min y, min z, max |coordinate|) and box[2t+1] = (max x,
 // max y, max z, 0) of the hi positions, for the symmetric kernel's far test.
+// perm (may be null): entry i holds blob perm[i] (the pair kernels' blob order)
 __global__ void prep_positions_kernel(int N, const double *__restrict__ pos, double inv_a,
                                       double4 *__restrict__ p64, float4 *__restrict__ hi,
-                                      float4 *__restrict__ lo, float4 *__restrict__ box) {
+                                      float4 *__restrict__ lo, float4 *__restrict__ box,
+                                      const int *__restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = i < N;
     float xh = 0.f, yh = 0.f, zh = 0.f;
     if (ok) {
-        p64[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 2.0 * pos[3 * i + 2]);
-        const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a,
-                     z = pos[3 * i + 2] * inv_a;
+        const int b = perm ? perm[i] : i;
+        p64[i] = make_double4(pos[3 * b], pos[3 * b + 1], pos[3 * b + 2], 2.0 * pos[3 * b + 2]);
+        const double x = pos[3 * b] * inv_a, y = pos[3 * b + 1] * inv_a,
+                     z = pos[3 * b + 2] * inv_a;
         xh = (float)x;
         yh = (float)y;
         zh = (float)z;
@@ -78,7 +81,8 @@ constexpr int kRun = 32;  // sources per float partial sum in the FP32C kernel
 template <bool WALL>
 __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
     int N, const float4 *__restrict__ hi, const float4 *__restrict__ lo,
-    const double *__restrict__ lam, int tiles_per_slice, double *__restrict__ partial) {
+    const double *__restrict__ lam, const int *__restrict__ perm, int tiles_per_slice,
+    double *__restrict__ partial) {
     constexpr CoefF c = kUnitCoefF;
     __shared__ float4 s_hi[kTile], s_lo[kTile], s_lam[kTile];
     const int tid = threadIdx.x;
@@ -95,10 +99,10 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
         const int j = t * kTile + tid;
         __syncthreads();
         if (j < N) {
+            const size_t b = 3 * (size_t)(perm ? perm[j] : j);
             s_hi[tid] = hi[j];
             s_lo[tid] = lo[j];
-            s_lam[tid] = make_float4((float)lam[3 * j], (float)lam[3 * j + 1],
-                                     (float)lam[3 * j + 2], 0.f);
+            s_lam[tid] = make_float4((float)lam[b], (float)lam[b + 1], (float)lam[b + 2], 0.f);
         }
         __syncthreads();
         const int cnt = min(kTile, N - t * kTile);
@@ -141,6 +145,7 @@ __global__ __launch_bounds__(kTile) void pair_f32c_kernel(
 template <bool WALL>
 __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *__restrict__ p64,
                                                          const double *__restrict__ lam,
+                                                         const int *__restrict__ perm,
                                                          int tiles_per_slice, CoefD c,
                                                          double *__restrict__ partial) {
     __shared__ double4 s_p[kTile];
@@ -158,10 +163,11 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
         const int j = t * kTile + tid;
         __syncthreads();
         if (j < N) {
+            const size_t b = 3 * (size_t)(perm ? perm[j] : j);
             s_p[tid] = p64[j];
-            s_l[3 * tid] = lam[3 * j];
-            s_l[3 * tid + 1] = lam[3 * j + 1];
-            s_l[3 * tid + 2] = lam[3 * j + 2];
+            s_l[3 * tid] = lam[b];
+            s_l[3 * tid + 1] = lam[b + 1];
+            s_l[3 * tid + 2] = lam[b + 2];
         }
         __syncthreads();
         const int cnt = min(kTile, N - t * kTile);
@@ -191,15 +197,17 @@ __global__ __launch_bounds__(kTile) void pair_f64_kernel(int N, const double4 *_
     }
 }
 
+// partial in the pair kernels' order (entry k = blob perm[k]); out in blob order
 __global__ void pair_reduce_kernel(int N, int slices, const double *__restrict__ partial,
                                    double scale, double *__restrict__ out,
                                    const double *__restrict__ U, const int *__restrict__ bob,
-                                   const double *__restrict__ dvec) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+                                   const double *__restrict__ dvec, const int *__restrict__ perm) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int i = perm ? perm[k] : k;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int s = 0; s < slices; ++s) {
-        const size_t base = (size_t)s * 3 * N + i;
+        const size_t base = (size_t)s * 3 * N + k;
         s0 += partial[base];
         s1 += partial[base + N];
         s2 += partial[base + 2 * (size_t)N];
@@ -229,9 +237,10 @@ __global__ void wall_check_kernel(int N, const double4 *__restrict__ p64, double
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
-                    float4 *hi, float4 *lo, float4 *box) {
+                    float4 *hi, float4 *lo, float4 *box, const int *perm) {
     if (N <= 0) return;
-    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo, box);
+    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo, box,
+                                                       perm);
 }
 
 int heuristic_slices(int N) {
@@ -241,9 +250,114 @@ int heuristic_slices(int N) {
     return s;
 }
 
+// Small systems (N <= kSmallPairN, e.g. a 20-rod filament of 80 blobs): one
+// 64-lane workgroup per (64 targets, run of kSmallRun sources), sources read
+// straight from memory, so that a product of a few thousand pairs spreads over
+// N/64 x N/16 wavefronts instead of one workgroup; partial[run][c][i], reduced in
+// run order by pair_reduce (deterministic).
+template <bool WALL>
+__global__ __launch_bounds__(64) void pair_small_f64_kernel(int N, const double4 *__restrict__ p64,
+                                                            const double *__restrict__ lam,
+                                                            const int *__restrict__ perm, CoefD c,
+                                                            double *__restrict__ partial) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int ic = i < N ? i : N - 1;
+    const double4 ti = p64[ic];
+    const TargetZ<double> zsc = target_z(ti.z);
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    const int j0 = blockIdx.y * kSmallRun, j1 = min(j0 + kSmallRun, N);
+    for (int j = j0; j < j1; ++j) {
+        const double4 sj = p64[j];
+        const size_t b = 3 * (size_t)(perm ? perm[j] : j);
+        const double lx = lam[b], ly = lam[b + 1], lz = lam[b + 2];
+        const double dx = ti.x - sj.x, dy = ti.y - sj.y, dz = ti.z - sj.z;
+        const double dxy2 = fma(dx, dx, dy * dy);
+        const double r2 = fma(dz, dz, dxy2);
+        const double rinv = rsq_f64(r2);
+        if (WALL) {
+            const double Rz = ti.z + sj.z;
+            const double Ri = rsq_f64(fma(Rz, Rz, dxy2));
+            const PairCoef<double> w =
+                wall_pair_coef<double>(r2, rinv, dxy2, zsc, sj.z, sj.w, -(sj.w * sj.w), Rz, Ri, c);
+            wall_pair_apply<double>(w, w.c, w.d, dx, dy, dz, Rz, lx, ly, lz, ux, uy, uz);
+        } else {
+            rpy_free<double>(dx, dy, dz, r2, rinv, lx, ly, lz, c, ux, uy, uz);
+        }
+    }
+    if (i < N) {
+        const size_t base = (size_t)blockIdx.y * 3 * N + i;
+        partial[base] = ux;
+        partial[base + N] = uy;
+        partial[base + 2 * (size_t)N] = uz;
+    }
+}
+
+template <bool WALL>
+__global__ __launch_bounds__(64) void pair_small_f32c_kernel(int N, const float4 *__restrict__ hi,
+                                                             const float4 *__restrict__ lo,
+                                                             const double *__restrict__ lam,
+                                                             const int *__restrict__ perm,
+                                                             double *__restrict__ partial) {
+    constexpr CoefF c = kUnitCoefF;
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int ic = i < N ? i : N - 1;
+    const float4 th = hi[ic], tl = lo[ic];
+    const float zi = th.z + tl.z;
+    const TargetZ<float> zsc = target_z(zi);
+    float ax = 0.f, ay = 0.f, az = 0.f;  // one float run of at most kSmallRun sources
+    const int j0 = blockIdx.y * kSmallRun, j1 = min(j0 + kSmallRun, N);
+    for (int j = j0; j < j1; ++j) {
+        const float4 sh = hi[j], sl = lo[j];
+        const size_t b = 3 * (size_t)(perm ? perm[j] : j);
+        const float Lx = (float)lam[b], Ly = (float)lam[b + 1], Lz = (float)lam[b + 2];
+        const float dx = (th.x - sh.x) + (tl.x - sl.x);
+        const float dy = (th.y - sh.y) + (tl.y - sl.y);
+        const float dz = (th.z - sh.z) + (tl.z - sl.z);
+        const float dxy2 = fmaf(dx, dx, dy * dy);
+        const float r2 = fmaf(dz, dz, dxy2);
+        const float rinv = rsq_f32(r2);
+        if (WALL) {
+            const float Rz = zi + sh.z;
+            const float Ri = rsq_f32(fmaf(Rz, Rz, dxy2));
+            const PairCoef<float> w =
+                wall_pair_coef<float>(r2, rinv, dxy2, zsc, sh.z, sh.w, sl.w, Rz, Ri, c);
+            wall_pair_apply<float>(w, w.c, w.d, dx, dy, dz, Rz, Lx, Ly, Lz, ax, ay, az);
+        } else {
+            rpy_free<float>(dx, dy, dz, r2, rinv, Lx, Ly, Lz, c, ax, ay, az);
+        }
+    }
+    if (i < N) {
+        const size_t base = (size_t)blockIdx.y * 3 * N + i;
+        partial[base] = (double)ax;
+        partial[base + N] = (double)ay;
+        partial[base + 2 * (size_t)N] = (double)az;
+    }
+}
+
+int pair_partial_small(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
+                       const float4 *hi, const float4 *lo, const double *lam, const int *perm,
+                       double a, double *partial) {
+    if (N <= 0) return 0;
+    const int runs = (N + kSmallRun - 1) / kSmallRun;
+    dim3 grid((N + 63) / 64, runs);
+    if (precision == ARB_FP32C) {
+        if (wall)
+            pair_small_f32c_kernel<true><<<grid, 64, 0, s>>>(N, hi, lo, lam, perm, partial);
+        else
+            pair_small_f32c_kernel<false><<<grid, 64, 0, s>>>(N, hi, lo, lam, perm, partial);
+    } else {
+        const CoefD c = make_coef<CoefD, double>(a);
+        if (wall)
+            pair_small_f64_kernel<true><<<grid, 64, 0, s>>>(N, p64, lam, perm, c, partial);
+        else
+            pair_small_f64_kernel<false><<<grid, 64, 0, s>>>(N, p64, lam, perm, c, partial);
+    }
+    return runs;
+}
+
 int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-                  const float4 *hi, const float4 *lo, const double *lam, double a, int slices,
-                  double *partial) {
+                  const float4 *hi, const float4 *lo, const double *lam, const int *perm, double a,
+                  int slices, double *partial) {
     if (N <= 0) return 0;
     const int ntiles = (N + kTile - 1) / kTile;
     if (slices > ntiles) slices = ntiles;
@@ -251,24 +365,25 @@ int pair_partial(hipStream_t s, int precision, bool wall, int N, const double4 *
     dim3 grid(ntiles, slices);
     if (precision == ARB_FP32C) {
         if (wall)
-            pair_f32c_kernel<true><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, partial);
+            pair_f32c_kernel<true><<<grid, kTile, 0, s>>>(N, hi, lo, lam, perm, tps, partial);
         else
-            pair_f32c_kernel<false><<<grid, kTile, 0, s>>>(N, hi, lo, lam, tps, partial);
+            pair_f32c_kernel<false><<<grid, kTile, 0, s>>>(N, hi, lo, lam, perm, tps, partial);
     } else {
         const CoefD c = make_coef<CoefD, double>(a);
         if (wall)
-            pair_f64_kernel<true><<<grid, kTile, 0, s>>>(N, p64, lam, tps, c, partial);
+            pair_f64_kernel<true><<<grid, kTile, 0, s>>>(N, p64, lam, perm, tps, c, partial);
         else
-            pair_f64_kernel<false><<<grid, kTile, 0, s>>>(N, p64, lam, tps, c, partial);
+            pair_f64_kernel<false><<<grid, kTile, 0, s>>>(N, p64, lam, perm, tps, c, partial);
     }
     return slices;
 }
 
 void pair_reduce(hipStream_t s, int N, int slices, const double *partial, double scale,
-                 double *out, const double *U, const int *body_of_blob, const double *dvec) {
+                 double *out, const double *U, const int *body_of_blob, const double *dvec,
+                 const int *perm) {
     if (N <= 0) return;
     pair_reduce_kernel<<<nblk(N, 256), 256, 0, s>>>(N, slices, partial, scale, out, U,
-                                                      body_of_blob, dvec);
+                                                      body_of_blob, dvec, perm);
 }
 
 int pair_wall_violation(hipStream_t s, int N, const double4 *p64, double a, int *flag_dev,

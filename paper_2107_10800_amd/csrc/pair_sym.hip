@@ -77,16 +77,18 @@ struct Blob32 {
     float4 hi, lo, lam;
 };
 
-// blob i, or a far-away zero-force blob beyond N
+// entry i (blob perm[i], or blob i without perm), or a far-away zero-force blob
+// beyond N
 __device__ __forceinline__ Blob32 load_blob(int i, int N, const float4 *__restrict__ hi,
                                             const float4 *__restrict__ lo,
-                                            const double *__restrict__ lam) {
+                                            const double *__restrict__ lam,
+                                            const int *__restrict__ perm) {
     Blob32 b;
     if (i < N) {
+        const size_t l = 3 * (size_t)(perm ? perm[i] : i);
         b.hi = hi[i];
         b.lo = lo[i];
-        b.lam = make_float4((float)lam[3 * (size_t)i], (float)lam[3 * (size_t)i + 1],
-                            (float)lam[3 * (size_t)i + 2], 0.f);
+        b.lam = make_float4((float)lam[l], (float)lam[l + 1], (float)lam[l + 2], 0.f);
     } else {
         b.hi = make_float4(1e6f, 1e6f, 10.f, 20.f);
         b.lo = make_float4(0.f, 0.f, 0.f, -400.f);
@@ -172,6 +174,7 @@ void pair_sym_f32c_kernel(int N, const float4 *__restrict__ hi,
                                                             const float4 *__restrict__ lo,
                                                             const float4 *__restrict__ box,
                                                             const double *__restrict__ lam,
+                                                            const int *__restrict__ perm,
                                                             const int4 *__restrict__ work,
                                                             double *__restrict__ u) {
     constexpr CoefF c = kUnitCoefF;
@@ -182,7 +185,7 @@ void pair_sym_f32c_kernel(int N, const float4 *__restrict__ hi,
     const int4 it = work[blockIdx.x];
     const bool diag = it.w != 0;
     const int i = (4 * it.x + w) * 64 + lane;
-    const Blob32 t = load_blob(i, N, hi, lo, lam);
+    const Blob32 t = load_blob(i, N, hi, lo, lam, perm);
     const float zi = t.hi.z + t.lo.z;
     const TargetZ<float> zsc = target_z(zi);
     const int src = (lane + 1) & 63;
@@ -190,7 +193,7 @@ void pair_sym_f32c_kernel(int N, const float4 *__restrict__ hi,
     for (int J = it.y; J < it.y + it.z; ++J) {
         __syncthreads();
         if (tid < 64) {
-            const Blob32 s = load_blob(J * 64 + tid, N, hi, lo, lam);
+            const Blob32 s = load_blob(J * 64 + tid, N, hi, lo, lam, perm);
             s_hi[tid] = s_hi[tid + 64] = s.hi;
             s_lo[tid] = s_lo[tid + 64] = s.lo;
             s_lam[tid] = s_lam[tid + 64] = s.lam;
@@ -262,13 +265,15 @@ void pair_sym_f32c_kernel(int N, const float4 *__restrict__ hi,
     }
 }
 
-// blob i in FP64, or a far-away zero-force blob beyond N
+// entry i in FP64 (blob perm[i], or blob i), or a far-away zero-force blob beyond N
 __device__ __forceinline__ void load_blob64(int i, int N, const double4 *__restrict__ p64,
-                                            const double *__restrict__ lam, double4 &p,
+                                            const double *__restrict__ lam,
+                                            const int *__restrict__ perm, double4 &p,
                                             double4 &l) {
     if (i < N) {
+        const size_t b = 3 * (size_t)(perm ? perm[i] : i);
         p = p64[i];
-        l = make_double4(lam[3 * (size_t)i], lam[3 * (size_t)i + 1], lam[3 * (size_t)i + 2], 0.0);
+        l = make_double4(lam[b], lam[b + 1], lam[b + 2], 0.0);
     } else {
         p = make_double4(1e6, 1e6, 10.0, 20.0);
         l = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -279,6 +284,7 @@ __device__ __forceinline__ void load_blob64(int i, int N, const double4 *__restr
 template <bool WALL>
 __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 *__restrict__ p64,
                                                            const double *__restrict__ lam,
+                                                           const int *__restrict__ perm,
                                                            const int4 *__restrict__ work,
                                                            CoefD c, double *__restrict__ u) {
     __shared__ double4 s_p[128], s_l[128];  // the source tile twice over
@@ -288,14 +294,14 @@ __global__ __launch_bounds__(256) void pair_sym_f64_kernel(int N, const double4 
     const bool diag = it.w != 0;
     const int i = (4 * it.x + w) * 64 + lane;
     double4 tp, tl;
-    load_blob64(i, N, p64, lam, tp, tl);
+    load_blob64(i, N, p64, lam, perm, tp, tl);
     const TargetZ<double> zsc = target_z(tp.z);
     const int src = (lane + 1) & 63;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int J = it.y; J < it.y + it.z; ++J) {
         __syncthreads();
         if (tid < 64) {
-            load_blob64(J * 64 + tid, N, p64, lam, s_p[tid], s_l[tid]);
+            load_blob64(J * 64 + tid, N, p64, lam, perm, s_p[tid], s_l[tid]);
             s_p[tid + 64] = s_p[tid];
             s_l[tid + 64] = s_l[tid];
         }
@@ -379,20 +385,20 @@ void pair_sym_clear(hipStream_t s, int N, double *u) {
 
 // u (layout [3][N], FP64) += sum over all pairs, unscaled (units 1/(8 pi eta))
 void pair_sym(hipStream_t s, int precision, bool wall, int N, const double4 *p64,
-              const float4 *hi, const float4 *lo, const float4 *box, const double *lam, double a,
-              const int4 *work, int n_work, double *u) {
+              const float4 *hi, const float4 *lo, const float4 *box, const double *lam,
+              const int *perm, double a, const int4 *work, int n_work, double *u) {
     if (N <= 0 || n_work <= 0) return;
     if (precision == ARB_FP32C) {
         if (wall)
-            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, box, lam, work, u);
+            pair_sym_f32c_kernel<true><<<n_work, 256, 0, s>>>(N, hi, lo, box, lam, perm, work, u);
         else
-            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, box, lam, work, u);
+            pair_sym_f32c_kernel<false><<<n_work, 256, 0, s>>>(N, hi, lo, box, lam, perm, work, u);
     } else {
         const CoefD c = make_coef<CoefD, double>(a);
         if (wall)
-            pair_sym_f64_kernel<true><<<n_work, 256, 0, s>>>(N, p64, lam, work, c, u);
+            pair_sym_f64_kernel<true><<<n_work, 256, 0, s>>>(N, p64, lam, perm, work, c, u);
         else
-            pair_sym_f64_kernel<false><<<n_work, 256, 0, s>>>(N, p64, lam, work, c, u);
+            pair_sym_f64_kernel<false><<<n_work, 256, 0, s>>>(N, p64, lam, perm, work, c, u);
     }
 }
 

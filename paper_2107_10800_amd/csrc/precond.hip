@@ -225,9 +225,6 @@ __global__ __launch_bounds__(256) void pc_inverse_kernel(const int *__restrict__
 constexpr int kNB = 32;          // block size of the blocked factorisation
 constexpr int kLd = kNB + 1;     // padded LDS row stride (doubles)
 constexpr int kFastMaxM = 480;   // largest body handled by the blocked kernels
-// assemblies whose largest S_a has more rows than this take the blocked kernels;
-// smaller ones (a few rows per articulated body) the one-workgroup kernel
-constexpr int kAsmBlockedMin = 64;
 
 // FP64 matrix core, one wavefront: D (16 x 16) += A (16 x 4) B (4 x 16).  Lane l
 // supplies a = A[l % 16][l / 16] and b = B[l / 16][l % 16] and holds
@@ -726,6 +723,102 @@ __global__ __launch_bounds__(256) void pc_asm_pinv_kernel(
     if (threadIdx.x == 0) {
         sym_pinv_serial(S, S + (size_t)na * na, na, Gbuf + asm_mat_off[a], 1e-12);
         atomicAdd(&status[1], 1);
+    }
+}
+
+// assemblies of at most kAsmSmall rows, held in LDS: Cholesky in outer-product
+// form (one barrier per pivot; the pivot column is scaled at the end), pivot test
+// relative to the largest diagonal entry, then G~ = S^-1 column by column (thread c
+// solves L L^T g = e_c).  A failed pivot flags the assembly for the
+// pseudo-inverse kernel.
+constexpr int kAsmSmall = 64;
+__global__ __launch_bounds__(256) void pc_asm_small_kernel(
+    const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
+    const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
+    const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
+    double *__restrict__ Gbuf, int *__restrict__ fail, const int *__restrict__ status) {
+    __shared__ double S[kAsmSmall * (kAsmSmall + 1)];
+    __shared__ double Y[kAsmSmall * (kAsmSmall + 1)];
+    __shared__ double tol;
+    constexpr int ld = kAsmSmall + 1;
+    const int a = blockIdx.x, tid = threadIdx.x;
+    const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
+    if (tid == 0) fail[a] = 0;
+    if (na == 0 || status[0] != 0) return;
+    // S = C_a N~ C_a^T into LDS (row stride ld)
+    for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
+        const int k = idx >> 6, l = idx & 63;
+        if (k >= na || l >= na) continue;
+        const int rk = asm_rows[r0 + k], rl = asm_rows[r0 + l];
+        double sum = 0.0;
+#pragma unroll 1
+        for (int sk = 0; sk < 2; ++sk) {
+            const int bk = sk ? row_q[rk] : row_p[rk];
+            if (bk < 0) continue;
+            const double *ck = crow + 12 * (size_t)rk + 6 * sk;
+#pragma unroll 1
+            for (int sl = 0; sl < 2; ++sl) {
+                const int bl = sl ? row_q[rl] : row_p[rl];
+                if (bl != bk) continue;
+                const double *cl = crow + 12 * (size_t)rl + 6 * sl;
+                const double *Nb = Nt + 36 * (size_t)bk;
+                for (int u = 0; u < 6; ++u) {
+                    double t = 0.0;
+                    for (int v = 0; v < 6; ++v) t += Nb[u * 6 + v] * cl[v];
+                    sum += ck[u] * t;
+                }
+            }
+        }
+        S[k * ld + l] = sum;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double dmax = 0.0;
+        for (int k = 0; k < na; ++k) dmax = fmax(dmax, S[k * ld + k]);
+        tol = 1e-12 * dmax;
+    }
+    __syncthreads();
+    for (int k = 0; k < na; ++k) {
+        const double d = S[k * ld + k];
+        if (!(d > tol)) {  // the same value for every thread: a uniform exit
+            if (tid == 0) fail[a] = 1;
+            return;
+        }
+        const double inv = 1.0 / d;
+        for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
+            const int i = idx >> 6, j = idx & 63;
+            if (j > k && j <= i && i < na) S[i * ld + j] -= S[i * ld + k] * S[j * ld + k] * inv;
+        }
+        __syncthreads();
+    }
+    // L_ik = S_ik / sqrt(S_kk) (the pivots are the final S_kk)
+    for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
+        const int i = idx >> 6, k = idx & 63;
+        if (k < i && i < na) Y[i * ld + k] = S[i * ld + k] / sqrt(S[k * ld + k]);
+        if (k == i && i < na) Y[i * ld + i] = sqrt(S[i * ld + i]);
+    }
+    __syncthreads();
+    // thread c: L y = e_c forward, L^T g = y backward, g = column c of S^-1 (y in S's
+    // column c, which the factorisation no longer needs)
+    if (tid < na) {
+        const int c = tid;
+        double *G = Gbuf + asm_mat_off[a];
+        for (int i = 0; i < na; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            if (i < c) {
+                S[i * ld + c] = 0.0;
+                continue;
+            }
+            for (int k = c; k < i; ++k) v -= Y[i * ld + k] * S[k * ld + c];
+            S[i * ld + c] = v / Y[i * ld + i];
+        }
+        for (int i = na - 1; i >= 0; --i) {
+            double v = S[i * ld + c];
+            for (int k = i + 1; k < na; ++k) v -= Y[k * ld + i] * S[k * ld + c];
+            v /= Y[i * ld + i];
+            S[i * ld + c] = v;
+            G[(size_t)i * na + c] = v;
+        }
     }
 }
 
@@ -1274,16 +1367,24 @@ void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_of
                                          P.brow_ent, P.crow, P.tmp, z, P.A > 0 ? 1 : 0);
 }
 
-// G~_a = S_a^-1 for every assembly (Sec. 3.1).  When the largest assembly has
-// between kAsmBlockedMin and kFastMaxM rows: the blocked kernels of the blob
-// mobilities (S_a formed in P.S, factored in place, the inverse written to P.G),
-// with a pivot test relative to the largest diagonal entry; assemblies that
-// fail it (constraints without full row rank) take the symmetric
-// pseudo-inverse.  Otherwise the one-workgroup kernel.
+// G~_a = S_a^-1 for every assembly (Sec. 3.1), with a pivot test relative to the
+// largest diagonal entry; assemblies that fail it (constraints without full row
+// rank) take the symmetric pseudo-inverse.  Largest assembly of at most kAsmSmall
+// rows: one workgroup per assembly in LDS; up to kFastMaxM rows: the blocked
+// kernels of the blob mobilities (S_a formed in P.S, factored in place, the
+// inverse written to P.G); beyond: the unblocked kernel.
 hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
     if (P.A <= 0) return hipSuccess;
-    if (P.asm_max_rows <= kAsmBlockedMin || P.asm_max_rows > kFastMaxM || !P.asm_dinv ||
-        !P.asm_fail) {
+    if (P.asm_max_rows <= kAsmSmall && P.asm_fail) {
+        pc_asm_small_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
+                                                P.row_p, P.row_q, P.crow, P.Nt, P.G, P.asm_fail,
+                                                P.status);
+        pc_asm_pinv_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
+                                               P.row_q, P.crow, P.Nt, P.S, P.G, P.asm_fail,
+                                               P.status);
+        return hipGetLastError();
+    }
+    if (P.asm_max_rows > kFastMaxM || !P.asm_dinv || !P.asm_fail) {
         pc_asm_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
                                           P.row_q, P.crow, P.Nt, P.S, P.G, P.status);
         return hipGetLastError();

@@ -248,6 +248,19 @@ def slab(n: int = 16384, side: float = 400.0, zlo: float = 1.5, zhi: float = 20.
     return dict(pos=pos, lam=lam, a=1.0, eta=1.0)
 
 
+def loose_blobs(pos, a: float = 1.0, eta: float = 1.0, wall: bool = True,
+                name: str = "loose blobs") -> Workload:
+    """Loose blobs as a workload: every blob a body of one blob at its tracking
+    point (identity orientation, no links, zero forces), so that a context holds
+    their positions as its state."""
+    pos = np.asarray(pos, float).reshape(-1, 3)
+    n = len(pos)
+    theta = np.zeros((n, 4))
+    theta[:, 0] = 1.0
+    return Workload(name, a, eta, wall, np.zeros((n, 3)), np.arange(n + 1, dtype=np.int32),
+                    pos.copy(), theta, np.zeros((n, 6)), **_links(0))
+
+
 def random_blobs(n: int, seed: int, box: float = 8.0, zlo: float = 1.2,
                  zhi: float = 6.0, overlap: bool = True) -> dict:
     """Small random blob clouds for parity tests (overlaps allowed)."""

@@ -110,6 +110,36 @@ def test_far_tiles_on_ordered_blobs(wall):
         assert e <= TOL[arb.ARB_FP32C]
 
 
+@pytest.mark.parametrize("prec", [arb.ARB_FP64, arb.ARB_FP32C])
+def test_context_product_in_library_order(prec):
+    # the 16,384-blob slab as a context's state (one-blob bodies in the
+    # generator's random order): the library runs its products on a copy sorted
+    # along a Morton curve and reads lambda / writes u through the permutation.
+    # u = M lambda and the saddle operator's first rows M lambda - K U on sampled
+    # rows against the oracle's compiled route
+    from oracle import rpy_c
+
+    sl = W.slab()
+    N = len(sl["pos"])
+    wl = W.loose_blobs(sl["pos"])
+    rng = np.random.default_rng(2)
+    lam = sl["lam"]
+    U = rng.standard_normal((N, 6))
+    c = arb.context_for(wl, precision=prec)
+    try:
+        u = arb.arb_mobility_apply(c, lam).reshape(N, 3)
+        Ay = arb.arb_system_apply(c, np.concatenate([lam.ravel(), U.ravel()]))
+    finally:
+        arb.arb_destroy(c)
+    tg = np.unique(np.concatenate([[0, 63, 64, N - 1], rng.integers(0, N, 124)]))
+    uo = rpy_c.mobility_apply(sl["pos"], lam, 1.0, 1.0, True, targets=tg)
+    e1 = rel(u[tg], uo)
+    # one-blob bodies at their tracking points: (K U)_i = u_i
+    e2 = rel(Ay[:3 * N].reshape(N, 3)[tg], uo - U[tg, :3])
+    print(f"  context product prec={prec}: {e1:.2e}, system rows {e2:.2e}", flush=True)
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+
+
 def test_device_pointer_entry_point_matches_host(ctxs):
     import torch
 
