@@ -137,6 +137,13 @@ typedef struct {
                        /* stops when that has fallen by the factor the true    */
                        /* residual still has to fall, and the stopping test is */
                        /* always on the true residual ||b - A y|| <= tol ||b|| */
+    int    small_cycle; /* 0 = a small system (multiblob, FP64, block         */
+                       /* preconditioner, right preconditioning, at most 128   */
+                       /* blobs and 4,096 unknowns, assemblies of at most 64   */
+                       /* rows) runs each GMRES restart cycle in one launch of */
+                       /* one workgroup, with the stopping test on the device  */
+                       /* (default); 1 = one kernel per operation, a host      */
+                       /* stopping test per step                               */
 } arb_options;
 
 typedef struct {
@@ -153,6 +160,8 @@ typedef struct {
     int    products_fp64;   /* blob mobility products with the FP64 pair sum   */
     int    products_fp32;   /* ... with the FP32 pair sum                      */
     int    precond_applies; /* preconditioner applications                     */
+    int    one_launch_cycles; /* restart cycles run in one launch (small systems, */
+                            /* arb_options.small_cycle)                         */
 } arb_solve_info;
 
 /* Work of the fast product's current tree (ARB_PAIR_FMM), filled by

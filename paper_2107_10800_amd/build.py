@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["pair.hip", "pair_sym.hip", "bodies.hip", "precond.hip", "krylov.hip", "correct.hip", "reconstruct.hip", "rot_pair.hip", "fmm.hip", "mlp.hip",
-           "noalloc.hip", "api.hip"]
+           "small.hip", "noalloc.hip", "api.hip"]
 LIB = os.path.join(HERE, "libarb.so")
 
 HIPCC_FLAGS = [

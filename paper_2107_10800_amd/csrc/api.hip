@@ -674,6 +674,7 @@ arb::PrecondDev pc_view(arb_ctx *ctx) {
     P.asm_max_rows = ctx->asm_max_rows;
     P.asm_dinv = ctx->asm_dinv.as<double>();
     P.asm_fail = ctx->asm_fail.as<int>();
+    P.body_pinv = ctx->body_pinv.as<int>();
     P.status = ctx->status.as<int>();
     P.tmp = ctx->pctmp.as<double>();
     P.learned = ctx->pc_learned ? 1 : 0;
@@ -733,6 +734,7 @@ int ensure_types(arb_ctx *ctx, hipStream_t s) {
     HIPCHK(ctx->t_ldiag.ensure(std::max<size_t>(pos.size(), 1) * sizeof(double)));
     HIPCHK(ctx->t_dinv.ensure(arb::precond_dinv_size(tb[T], T) * sizeof(double)));
     HIPCHK(ctx->t_Nt.ensure(36 * (size_t)T * sizeof(double)));
+    HIPCHK(ctx->t_body_pinv.ensure(std::max(T, 1) * sizeof(int)));
     HIPCHK(ctx->t_status.ensure(8 * sizeof(int)));
     HIPCHK(hipMemsetAsync(ctx->t_status.p, 0, 8 * sizeof(int), s));
     arb::PrecondDev P;
@@ -746,6 +748,7 @@ int ensure_types(arb_ctx *ctx, hipStream_t s) {
     P.dinv = ctx->t_dinv.as<double>();
     P.Z = ctx->t_Z.as<double>();
     P.Nt = ctx->t_Nt.as<double>();
+    P.body_pinv = ctx->t_body_pinv.as<int>();
     P.status = ctx->t_status.as<int>();
     arb::precond_assemble(s, P, ctx->t_ref.as<double>(), ctx->opt.a, ctx->opt.eta, false);
     int t_max_m = 0;
@@ -872,6 +875,7 @@ int precond_build_exact(arb_ctx *ctx, hipStream_t s) {
     HIPCHK(ctx->dinv.ensure(arb::precond_dinv_size(ctx->N, M) * sizeof(double)));
     HIPCHK(ctx->Z.ensure(std::max<int64_t>(zo[M], 1) * sizeof(double)));
     HIPCHK(ctx->Nt.ensure(36 * (size_t)M * sizeof(double)));
+    HIPCHK(ctx->body_pinv.ensure(std::max(M, 1) * sizeof(int)));
     HIPCHK(ctx->pctmp.ensure(6 * (size_t)M * sizeof(double)));
     HIPCHK(ctx->status.ensure(8 * sizeof(int)));
     HIPCHK(hipMemsetAsync(ctx->status.p, 0, 8 * sizeof(int), s));
@@ -917,6 +921,7 @@ struct Krylov {
     int64_t n;
     int m, nch;
     double *b, *r, *z, *w, *V, *H, *cs, *sn, *g, *sv, *part, *h1, *h2, *sc;
+    double *steps;  // gmres_small_cycle's per-step figures (2 m + 1)
 };
 
 int krylov_buffers(arb_ctx *ctx, Krylov &K) {
@@ -938,6 +943,7 @@ int krylov_buffers(arb_ctx *ctx, Krylov &K) {
     HIPCHK(ctx->khcol.ensure((size_t)(2 * (m + 2) + 16) * sizeof(double)));
     HIPCHK(ctx->ksv.ensure((size_t)(m + 1) * sizeof(double)));
     HIPCHK(ctx->kpart.ensure((size_t)(m + 1) * K.nch * sizeof(double)));
+    HIPCHK(ctx->ksteps.ensure((size_t)(2 * m + 2) * sizeof(double)));
     K.b = ctx->kb.as<double>();
     K.r = ctx->kr.as<double>();
     K.z = ctx->kz.as<double>();
@@ -952,7 +958,55 @@ int krylov_buffers(arb_ctx *ctx, Krylov &K) {
     K.h1 = ctx->khcol.as<double>();
     K.h2 = K.h1 + (m + 2);
     K.sc = K.h2 + (m + 2);  // 16 device scalars
+    K.steps = ctx->ksteps.as<double>();
     return 0;
+}
+
+// Whether a GMRES cycle of this context runs in one workgroup (small.hip): a
+// small multiblob FP64 system with the exact block preconditioner
+bool small_cycle_ok(const arb_ctx *ctx, int prec, int64_t n) {
+    return ctx->opt.small_cycle == 0 && ctx->opt.model == ARB_MODEL_MULTIBLOB &&
+           prec == ARB_FP64 && ctx->opt.precond == ARB_PC_BLOCK && !ctx->pc_learned &&
+           ctx->opt.pair_kernel != ARB_PAIR_FMM && !ctx->prof && ctx->M > 0 &&
+           ctx->N <= arb::kSmallCycleN && n <= arb::kSmallArnoldi &&
+           (ctx->n_asm == 0 || ctx->asm_max_rows <= arb::kSmallCycleRows);
+}
+
+arb::SmallSystem small_system(arb_ctx *ctx) {
+    const arb::PrecondDev P = pc_view(ctx);
+    arb::SmallSystem S;
+    S.N = ctx->N;
+    S.M = ctx->M;
+    S.Nc = ctx->Nc;
+    S.A = ctx->n_asm;
+    S.n = n_unknowns(ctx);
+    S.wall = ctx->opt.wall != 0;
+    S.a = ctx->opt.a;
+    S.scale = 1.0 / (8.0 * arb::kPi * ctx->opt.eta);
+    const bool so = ctx->psorted;
+    S.p64 = (so ? ctx->p64s : ctx->p64).as<double4>();
+    S.perm = so ? ctx->pperm.as<int>() : nullptr;
+    S.bob = ctx->body_of_blob.as<int>();
+    S.blob_off = ctx->blob_off.as<int>();
+    S.dvec = ctx->dvec.as<double>();
+    S.brow_ptr = ctx->brow_ptr.as<int>();
+    S.brow_ent = ctx->brow_ent.as<int>();
+    S.row_p = ctx->row_p.as<int>();
+    S.row_q = ctx->row_q.as<int>();
+    S.crow = ctx->crow.as<double>();
+    S.mat_off = P.mat_off;
+    S.z_off = P.z_off;
+    S.minv = P.minv;
+    S.Z = P.Z;
+    S.Nt = P.Nt;
+    S.asm_row_ptr = P.asm_row_ptr;
+    S.asm_rows = P.asm_rows;
+    S.asm_mat_off = P.asm_mat_off;
+    S.G = P.G;
+    int tpt = 1;  // threads per target: the 512 threads in about one pass
+    while (tpt < 64 && 2 * tpt * S.N <= 512) tpt *= 2;
+    S.tpt = tpt;
+    return S;
 }
 
 int dev_norm(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *x, int slot, double *out) {
@@ -1061,6 +1115,10 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
     auto count_product = [&]() { ++(prec == ARB_FP64 ? inf->products_fp64 : inf->products_fp32); };
     const bool graphs = ctx->opt.graphs == 0 && !ctx->prof;
     const bool small = n <= arb::kSmallArnoldi;
+    // a whole cycle in one launch of one workgroup (stopping test on the device)
+    const bool one_launch = !left && small_cycle_ok(ctx, prec, n);
+    arb::SmallSystem SS;
+    if (one_launch) SS = small_system(ctx);
     for (;;) {
         double beta = 0.0;
         TRY(read_norm(K.r, 2, &beta));
@@ -1125,7 +1183,26 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         int k = 0, launched = 0, lag = 0;
         const int budget = std::min(m, max_iter - *total);
         double last_est = beta;
-        for (int j = 0; j < budget; ++j) {
+        if (one_launch) {
+            arb::gmres_small_cycle(s, SS, m, budget, target, K.V, K.H, K.cs, K.sn, K.g, K.steps);
+            HIPCHK(hipMemcpyAsync(pin_step, K.steps, (2 * (size_t)m + 1) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            k = (int)pin_step[2 * m];
+            if (k < 1 || k > budget) return fail(ctx, ARB_E_DEVICE, "GMRES cycle: bad step count");
+            ++inf->one_launch_cycles;
+            for (int j = 0; j < k; ++j) {
+                const double est = pin_step[2 * j + 1];
+                if (!std::isfinite(est))
+                    return fail(ctx, ARB_E_NAN, "GMRES produced a non-finite value");
+                ++*total;
+                count_product();
+                ++inf->precond_applies;
+                push(est * scale * hist_scale);
+                last_est = est;
+            }
+        }
+        for (int j = 0; j < budget && !one_launch; ++j) {
             const double t_launch = now_ms();
             while (launched < budget && launched <= j + lag) TRY(launch(launched++));
             HIPCHK(hipEventSynchronize(ctx->step_ev[j]));
@@ -1307,7 +1384,8 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         (opt->model != ARB_MODEL_MULTIBLOB && opt->model != ARB_MODEL_SINGLE_BLOB) ||
         (opt->fmm_order != 0 && (opt->fmm_order < 2 || opt->fmm_order > arb::kFmmMaxOrder)) ||
         opt->fmm_levels < 0 || opt->fmm_levels > arb::kFmmMaxLevel || opt->fmm_leaf < 0 ||
-        opt->left_precond < 0 || opt->left_precond > 1)
+        opt->left_precond < 0 || opt->left_precond > 1 || opt->small_cycle < 0 ||
+        opt->small_cycle > 1)
         return ARB_E_ARG;
     // single-blob bodies: unbounded generalised RPY, exact or no preconditioner,
     // direct sums

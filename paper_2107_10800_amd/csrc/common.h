@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <memory>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -75,7 +76,9 @@ constexpr int kFmmDefaultOrder = 6;
 
 // octree and proxy buffers of the fast product; cells of all levels 0..L in
 // Morton order, level l at [lvl[l], lvl[l+1])
+struct FmmHostCache;  // host buffers of the tree build, kept between builds (fmm.hip)
 struct FmmState {
+    std::shared_ptr<FmmHostCache> host;
     DevBuf perm, cc, rng, parent, kids, il_ptr, il, near_ptr, nearl, work, tab, shi, slo, slam,
         qhat, v, slam2, qhat2, v2;  // second channel: the torques of single-blob bodies
     DevBuf vsplit;  // M2L sums of the parts of split interaction lists (splits > 1)
@@ -194,6 +197,7 @@ struct PrecondDev {
     int asm_max_rows = 0;     // largest assembly (constraint rows)
     double *asm_dinv = nullptr;  // diagonal-block inverses of the assemblies' factors
     int *asm_fail = nullptr;     // per assembly: 1 if S_a failed the pivot test
+    int *body_pinv = nullptr;    // per body: 1 if R_p = K^T M^-1 K awaits the pseudo-inverse
     int *status = nullptr;    // [0] not-SPD body+1, [1] G~ pinv count, [2] below wall,
                               // [3] N~ with dropped eigenvalues
     double *tmp = nullptr;    // apply scratch: U-hat (6M)
@@ -207,6 +211,35 @@ struct PrecondDev {
 };
 void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos, double a,
                       double eta, bool wall);
+
+// A small multiblob system for gmres_small_cycle (small.hip): the state's arrays
+// (positions in the pair kernels' order, perm may be null), the exact block
+// preconditioner, FP64 pair sums.  tpt threads share a target (a power of 2 <= 64);
+// assemblies have at most 64 rows.
+struct SmallSystem {
+    int N = 0, M = 0, Nc = 0, A = 0, tpt = 1;
+    int64_t n = 0;
+    bool wall = false;
+    double a = 1.0, scale = 0.0;  // blob radius, 1 / (8 pi eta)
+    const double4 *p64 = nullptr;
+    const int *perm = nullptr, *bob = nullptr, *blob_off = nullptr;
+    const double *dvec = nullptr;
+    const int *brow_ptr = nullptr, *brow_ent = nullptr, *row_p = nullptr, *row_q = nullptr;
+    const double *crow = nullptr;
+    const int64_t *mat_off = nullptr, *z_off = nullptr;
+    const double *minv = nullptr, *Z = nullptr, *Nt = nullptr;
+    const int *asm_row_ptr = nullptr, *asm_rows = nullptr;
+    const int64_t *asm_mat_off = nullptr;
+    const double *G = nullptr;
+};
+constexpr int kSmallCycleN = 128;      // blobs
+constexpr int kSmallCycleRows = 64;    // rows of the largest assembly
+// Arnoldi steps 0 .. budget-1 of one cycle from v_0 = V[0..n) (Hbar, cs, sn, g as
+// the per-step path leaves them); steps[2 j] = h_{j+1,j}, steps[2 j + 1] = the
+// residual estimate, steps[2 m] = the steps taken (the cycle ends early when the
+// estimate reaches target or h_{j+1,j} = 0)
+void gmres_small_cycle(hipStream_t s, const SmallSystem &S, int m, int budget, double target,
+                       double *V, double *Hbar, double *cs, double *sn, double *g, double *steps);
 // max_m = largest 3 n_p of the batch
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
 int64_t precond_dinv_size(int64_t n_blobs, int M);
@@ -378,7 +411,7 @@ struct arb_ctx {
         partial, row_p, row_q, row_kind, row_src, row_m, dl_p, dl_q, dldot_p, dldot_q, proj,
         gcoef, grhs, crow, Bc, brow_ptr, brow_ent, asm_body_ptr, asm_bodies, asm_row_ptr,
         asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp, lcorr, stmp,
-        asm_dinv, asm_fail;
+        asm_dinv, asm_fail, body_pinv;
     int asm_max_rows = 0;  // largest assembly (constraint rows)
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
@@ -388,7 +421,7 @@ struct arb_ctx {
     // permutation (entry k = blob pperm[k]), positions and tile boxes in that order
     bool psorted = false;
     arb::DevBuf pperm, p64s, his, los, tboxs;
-    arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt;
+    arb::DevBuf kv, kH, kcs, ksn, kg, khcol, khn, ksv, kpart, kb, kr, kz, kw, ky, kt, ksteps;
     // host pinned scratch: kPinnedScalars doubles for entry points, then two per
     // Arnoldi step (h_{j+1,j}, residual estimate) at pinned + kPinnedScalars
     double *pinned = nullptr;
@@ -415,7 +448,7 @@ struct arb_ctx {
     arb::DevBuf tune_out;
     // learned body mobility: network parameters, workspace, per-type blocks
     arb::DevBuf mlp_params, mlp_ws, mlp_x, mlp_t, body_type_d, t_ref, t_mat_off, t_z_off, t_minv,
-        t_Z, t_mats, t_ldiag, t_dinv, t_Nt, t_blob_off, t_status;
+        t_Z, t_mats, t_ldiag, t_dinv, t_Nt, t_blob_off, t_status, t_body_pinv;
     bool mlp_ready = false;
     int mlp_step = 0;
     bool types_ready = false;

@@ -51,6 +51,9 @@
 // refinement.
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <memory>
 #include <cmath>
 #include <cstdlib>
@@ -822,6 +825,15 @@ inline uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
 inline uint64_t morton(int x, int y, int z) {
     return (spread3((uint64_t)x) << 2) | (spread3((uint64_t)y) << 1) | spread3((uint64_t)z);
 }
+inline int compact3(uint64_t x) {  // every third bit -> 21 bits (inverse of spread3)
+    x &= 0x1249249249249249ull;
+    x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x | (x >> 16)) & 0x1f00000000ffffull;
+    x = (x | (x >> 32)) & 0x1fffffull;
+    return (int)x;
+}
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -848,20 +860,84 @@ void fnv1a(uint64_t &h, const std::vector<V> &v) {
     }
 }
 
-// f(t, i0, i1) on T contiguous slices of [0, N), thread t taking slice t.  An
+// Host worker threads kept for the life of the process (started on first use,
+// at most 15), so that the tree build's many short parallel steps do not each
+// start and join threads.  One job at a time: a caller that finds the pool busy
+// (another context building its tree on another thread) gets false and runs
+// the step on threads of its own.  The pool is never destroyed; its idle
+// workers wait on a condition variable until the process ends.
+class HostPool {
+  public:
+    // slice(t) for t in [0, T): t = 0 on the caller's thread, the others on
+    // workers; slice must not throw.  False (nothing run) when the pool is busy
+    // or cannot start enough workers.
+    bool run(int T, const std::function<void(int)> &slice) {
+        std::unique_lock<std::mutex> busy(busy_, std::try_to_lock);
+        if (!busy.owns_lock()) return false;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            try {
+                while ((int)workers_.size() < T - 1) {
+                    const int id = (int)workers_.size() + 1;
+                    workers_.emplace_back([this, id] { worker(id); });
+                }
+            } catch (const std::system_error &) {
+                return false;
+            }
+            job_ = &slice;
+            job_T_ = T;
+            pending_ = T - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        slice(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [this] { return pending_ == 0; });
+        job_ = nullptr;
+        return true;
+    }
+
+  private:
+    void worker(int id) {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (id >= job_T_) continue;
+            const std::function<void(int)> *f = job_;
+            lk.unlock();
+            (*f)(id);
+            lk.lock();
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    std::mutex busy_, mu_;
+    std::condition_variable cv_, done_;
+    std::vector<std::thread> workers_;
+    const std::function<void(int)> *job_ = nullptr;
+    int job_T_ = 0, pending_ = 0;
+    uint64_t gen_ = 0;
+};
+
+HostPool &host_pool() {
+    static HostPool *pool = new HostPool;  // never freed (see above)
+    return *pool;
+}
+
+// f(t, i0, i1) on T contiguous slices of [0, N), slice t on thread t (of the
+// host pool, or of threads started for this step when the pool is busy).  An
 // exception in a slice is caught on its thread and rethrown on the caller's
-// after every thread has joined; a slice whose thread cannot be started runs
-// on the caller's thread (the result does not depend on where a slice runs).
+// after every slice has ended; a slice whose thread cannot be started runs on
+// the caller's thread (the result does not depend on where a slice runs).
 template <class F>
 void parallel_slices(int T, int N, F &&f) {
     if (T <= 1) {
         f(0, 0, N);
         return;
     }
-    std::vector<std::thread> th;
     std::vector<std::exception_ptr> err((size_t)T);
-    th.reserve(T);
-    auto slice = [&f, &err, T, N](int t) {
+    const std::function<void(int)> slice = [&f, &err, T, N](int t) {
         const int i0 = (int)((int64_t)N * t / T), i1 = (int)((int64_t)N * (t + 1) / T);
         try {
             f(t, i0, i1);
@@ -869,14 +945,18 @@ void parallel_slices(int T, int N, F &&f) {
             err[t] = std::current_exception();
         }
     };
-    for (int t = 0; t < T; ++t) {
-        try {
-            th.emplace_back(slice, t);
-        } catch (const std::system_error &) {
-            slice(t);
+    if (!host_pool().run(T, slice)) {
+        std::vector<std::thread> th;
+        th.reserve(T);
+        for (int t = 0; t < T; ++t) {
+            try {
+                th.emplace_back(slice, t);
+            } catch (const std::system_error &) {
+                slice(t);
+            }
         }
+        for (auto &x : th) x.join();
     }
-    for (auto &x : th) x.join();
     for (auto &e : err)
         if (e) std::rethrow_exception(e);
 }
@@ -886,7 +966,7 @@ void parallel_slices(int T, int N, F &&f) {
 // entries joined in item order, as a loop over the items would give them
 template <class V, class F>
 void lists_by_item(int threads, int n, std::vector<int> &ptr, std::vector<V> &out, F &&f) {
-    const int T = std::max(1, std::min(threads, n / 2048));
+    const int T = std::max(1, std::min(threads, n / 256));
     std::vector<std::vector<V>> part((size_t)T);
     ptr.assign((size_t)n + 1, 0);
     parallel_slices(T, n, [&](int t, int c0, int c1) {
@@ -916,19 +996,10 @@ struct CellHash {
         x *= 0x94d049bb133111ebull;
         return x ^ (x >> 31);
     }
-    void build(const uint64_t *k, int n, int base) {
-        size_t cap = 16;
-        while (cap < 2 * (size_t)n) cap *= 2;
-        mask = cap - 1;
-        keys.assign(cap, ~0ull);
-        vals.assign(cap, -1);
-        for (int i = 0; i < n; ++i) {
-            uint64_t h = mix(k[i]) & mask;
-            while (keys[h] != ~0ull) h = (h + 1) & mask;
-            keys[h] = k[i];
-            vals[h] = base + i;
-        }
-    }
+    // the keys k[0..n) (distinct) with values base + i; up to `threads` host
+    // threads claim slots with compare-and-swap, so the table's layout may depend
+    // on their timing, but every lookup finds the same value
+    void build(const uint64_t *k, int n, int base, int threads);
     // index of the cell with coordinates (x, y, z) at a level of side 2^l, or -1
     int get(int l, int x, int y, int z) const {
         const int lim = 1 << l;
@@ -939,6 +1010,29 @@ struct CellHash {
         return -1;
     }
 };
+
+void CellHash::build(const uint64_t *k, int n, int base, int threads) {
+    size_t cap = 16;
+    while (cap < 2 * (size_t)n) cap *= 2;
+    mask = cap - 1;
+    keys.assign(cap, ~0ull);
+    vals.assign(cap, -1);
+    const int T = std::max(1, std::min(threads, n / 16384));
+    parallel_slices(T, n, [&](int, int i0, int i1) {
+        for (int i = i0; i < i1; ++i) {
+            uint64_t h = mix(k[i]) & mask;
+            for (;;) {
+                uint64_t empty = ~0ull;
+                if (__atomic_compare_exchange_n(&keys[h], &empty, k[i], false, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED)) {
+                    vals[h] = base + i;
+                    break;
+                }
+                h = (h + 1) & mask;
+            }
+        }
+    });
+}
 
 // work items per cell in M2L: one, or up to 8 when there are too few cells to
 // fill the chip (about 2,048 items wanted)
@@ -989,8 +1083,62 @@ struct FmmPlan {
     std::vector<float> tab;
 };
 
-int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, int leaf,
-             std::string *msg) {
+// Host scratch of the tree build: grow-only arrays whose contents are not
+// initialised (every entry used is written first), kept between builds so that
+// their pages are allocated and touched once
+template <class T>
+struct HostArr {
+    std::unique_ptr<T[]> p;
+    size_t n = 0;
+    T *get(size_t m) {
+        if (m > n || !p) {
+            p.reset(new T[std::max<size_t>(m, 1)]);
+            n = std::max<size_t>(m, 1);
+        }
+        return p.get();
+    }
+};
+struct PlanScratch {
+    HostArr<int> crd, idx, idx2;
+    HostArr<uint64_t> key, key2;
+    HostArr<unsigned char> first;
+};
+
+}  // namespace arb
+
+// what a context keeps of its tree builds: the scratch, the last plan (its
+// vectors' capacity is reused) and pinned host memory for the positions
+struct arb::FmmHostCache {
+    PlanScratch scratch;
+    FmmPlan plan;
+    double *hpos = nullptr;
+    size_t hpos_n = 0;
+    FmmHostCache() = default;
+    FmmHostCache(const FmmHostCache &) = delete;
+    FmmHostCache &operator=(const FmmHostCache &) = delete;
+    ~FmmHostCache() {
+        if (hpos) (void)hipHostFree(hpos);
+    }
+    // pinned room for n doubles (null when it cannot be allocated)
+    double *positions(size_t n) {
+        if (n <= hpos_n && hpos) return hpos;
+        if (hpos) (void)hipHostFree(hpos);
+        hpos = nullptr;
+        hpos_n = 0;
+        if (hipHostMalloc((void **)&hpos, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            hpos = nullptr;
+            return nullptr;
+        }
+        hpos_n = n;
+        return hpos;
+    }
+};
+
+namespace arb {
+
+int fmm_plan(FmmPlan &pl, PlanScratch &sc, int N, const double *h, double a, int n, int levels,
+             int leaf, std::string *msg) {
     const int P = n * n * n;
     const int T = host_threads(N);
     // finite positions and the root cube (host threads over slices; min and max
@@ -998,18 +1146,22 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
     std::vector<double> bound(6 * (size_t)T);
     std::vector<char> bad((size_t)T, 0);
     parallel_slices(T, N, [&](int t, int i0, int i1) {
-        double *lo = bound.data() + 6 * (size_t)t, *up = lo + 3;
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = h[d];
-            up[d] = h[d];
-        }
+        // running bounds in registers, stored once (the threads' slots share
+        // cache lines)
+        double lo[3] = {h[0], h[1], h[2]}, up[3] = {h[0], h[1], h[2]};
+        bool finite = true;
         for (int i = i0; i < i1; ++i)
             for (int d = 0; d < 3; ++d) {
                 const double x = h[3 * (size_t)i + d];
-                if (!std::isfinite(x)) bad[t] = 1;
+                finite = finite && std::isfinite(x);
                 lo[d] = std::min(lo[d], x);
                 up[d] = std::max(up[d], x);
             }
+        for (int d = 0; d < 3; ++d) {
+            bound[6 * (size_t)t + d] = lo[d];
+            bound[6 * (size_t)t + 3 + d] = up[d];
+        }
+        if (!finite) bad[t] = 1;
     });
     for (int t = 0; t < T; ++t)
         if (bad[t]) {
@@ -1029,9 +1181,9 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
     // cell coordinates at level Lhi and Morton keys (host threads over slices;
     // the arrays are left uninitialised, so that their pages are first touched
     // by the threads that fill them)
-    std::unique_ptr<int[]> crd(new int[3 * (size_t)N]);
-    std::unique_ptr<uint64_t[]> key(new uint64_t[N]), key2(new uint64_t[N]);
-    std::unique_ptr<int[]> idx(new int[N]), idx2(new int[N]);
+    int *crd = sc.crd.get(3 * (size_t)N);
+    uint64_t *key = sc.key.get(N), *key2 = sc.key2.get(N);
+    int *idx = sc.idx.get(N), *idx2 = sc.idx2.get(N);
     const double scale = std::ldexp(1.0, Lhi);
     parallel_slices(T, N, [&](int, int i0, int i1) {
         for (int i = i0; i < i1; ++i) {
@@ -1077,13 +1229,13 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                     idx2[at] = idx[i];
                 }
             });
-            key.swap(key2);
-            idx.swap(idx2);
+            std::swap(key, key2);
+            std::swap(idx, idx2);
         }
     }
     // the shallowest level at which sorted blob j starts a new cell (a cell
     // starts at every deeper level too): the highest differing key bit / 3
-    std::unique_ptr<unsigned char[]> first(new unsigned char[N > 0 ? N : 1]);
+    unsigned char *first = sc.first.get(N);
     first[0] = 0;
     std::vector<int64_t> new_at_t((size_t)T * (Lhi + 2), 0), new_at(Lhi + 2, 0);
     parallel_slices(T, N, [&](int t, int i0, int i1) {
@@ -1140,7 +1292,7 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
         }
         std::vector<CellHash> hash(L + 1);
         for (int l = 0; l <= L; ++l)
-            hash[l].build(pk.data() + lvl[l], lvl[l + 1] - lvl[l], lvl[l]);
+            hash[l].build(pk.data() + lvl[l], lvl[l + 1] - lvl[l], lvl[l], T);
         auto find = [&](int l, int x, int y, int z) -> int { return hash[l].get(l, x, y, z); };
         auto adjacent = [&](int c1, int c2) {
             return std::abs(cc[c1].x - cc[c2].x) <= 1 && std::abs(cc[c1].y - cc[c2].y) <= 1 &&
@@ -1244,7 +1396,11 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
         // shallower levels are the same for every leaf level), then built once.
         // the cells of level l: each host thread finds the cell starts in its
         // slice of the sorted blobs, the slices' lists then joined in order
+        // (each thread fills its own cells, at the offset of its slice; a cell's
+        // coordinates are decoded from its Morton key)
         std::vector<std::vector<int>> st_t((size_t)T);
+        std::vector<size_t> st_off((size_t)T + 1);
+        std::vector<int> st_next((size_t)T);
         auto cells_of = [&](int l, std::vector<int4> &c4, std::vector<int2> &r2,
                             std::vector<uint64_t> &k) {
             parallel_slices(T, N, [&](int t, int i0, int i1) {
@@ -1253,35 +1409,39 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
                 for (int j = i0; j < i1; ++j)
                     if (j == 0 || first[j] <= l) v.push_back(j);
             });
-            size_t nc = 0;
-            for (int t = 0; t < T; ++t) nc += st_t[t].size();
+            st_off[0] = 0;
+            for (int t = 0; t < T; ++t) st_off[t + 1] = st_off[t] + st_t[t].size();
+            for (int t = T - 1, nx = N; t >= 0; --t) {  // first cell start after slice t
+                st_next[t] = nx;
+                if (!st_t[t].empty()) nx = st_t[t][0];
+            }
+            const size_t nc = st_off[T];
             c4.resize(nc);
             r2.resize(nc);
             k.resize(nc);
-            const int sh = 3 * (Lhi - l), dl = Lhi - l;
-            size_t c = 0;
-            for (int t = 0; t < T; ++t)
-                for (const int j0 : st_t[t]) {
-                    const int i0 = idx[j0];
-                    c4[c] = make_int4(crd[3 * (size_t)i0] >> dl, crd[3 * (size_t)i0 + 1] >> dl,
-                                      crd[3 * (size_t)i0 + 2] >> dl, l);
-                    r2[c] = make_int2(j0, N);
-                    if (c > 0) r2[c - 1].y = j0;
-                    k[c] = key[j0] >> sh;
-                    ++c;
+            const int sh = 3 * (Lhi - l);
+            parallel_slices(T, T, [&](int t, int, int) {
+                const std::vector<int> &v = st_t[t];
+                const size_t c0 = st_off[t];
+                for (size_t e = 0; e < v.size(); ++e) {
+                    const uint64_t kc = key[v[e]] >> sh;
+                    c4[c0 + e] = make_int4(compact3(kc >> 2), compact3(kc >> 1), compact3(kc), l);
+                    r2[c0 + e] = make_int2(v[e], e + 1 < v.size() ? v[e + 1] : st_next[t]);
+                    k[c0 + e] = kc;
                 }
+            });
         };
         std::vector<int4> pc, cc2;
         std::vector<int2> pr, rr;
         std::vector<uint64_t> pk2, kk2;
         CellHash ph, ch;
         cells_of(1, pc, pr, pk2);
-        ph.build(pk2.data(), (int)pk2.size(), 0);
+        ph.build(pk2.data(), (int)pk2.size(), 0, T);
         int64_t m2l_total = 0, best = -1;
         int L = 2;
         for (int l = 2; l <= Lhi; ++l) {
             cells_of(l, cc2, rr, kk2);
-            ch.build(kk2.data(), (int)kk2.size(), 0);
+            ch.build(kk2.data(), (int)kk2.size(), 0, T);
             // children of each parent (contiguous) and the parent of each cell
             std::vector<int2> kid(pc.size());
             std::vector<int> par(cc2.size());
@@ -1292,7 +1452,7 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
             }
             // integer counts over slices of the cells on host threads
             const int ncl = (int)cc2.size();
-            const int Tc = std::max(1, std::min(T, ncl / 2048));
+            const int Tc = std::max(1, std::min(T, ncl / 256));
             std::vector<int64_t> part(2 * (size_t)Tc, 0);
             parallel_slices(Tc, ncl, [&](int t, int c0, int c1) {
                 int64_t m2l = 0, near = 0;
@@ -1361,7 +1521,7 @@ int fmm_plan(FmmPlan &pl, int N, const double *h, double a, int n, int levels, i
     pl.o[1] = o[1];
     pl.o[2] = o[2];
     pl.S = S;
-    pl.perm.assign(idx.get(), idx.get() + N);  // sorted position -> blob
+    pl.perm.assign(idx, idx + N);  // sorted position -> blob
     pl.tab = std::move(tab);
     return 0;
 }
@@ -1383,15 +1543,22 @@ int fmm_build(FmmState &F, hipStream_t s, int N, const double *pos_dev, const fl
         F.ready = true;
         return 0;
     }
-    std::vector<double> h(3 * (size_t)N);
-    if (hipMemcpyAsync(h.data(), pos_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+    if (!F.host) F.host = std::make_shared<FmmHostCache>();
+    FmmHostCache &hc = *F.host;
+    std::vector<double> hpage;  // pageable fallback when pinned memory is refused
+    double *h = hc.positions(3 * (size_t)N);
+    if (!h) {
+        hpage.resize(3 * (size_t)N);
+        h = hpage.data();
+    }
+    if (hipMemcpyAsync(h, pos_dev, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         *msg = "fast product: copying positions failed";
         return ARB_E_DEVICE;
     }
-    FmmPlan pl;
-    const int prc = fmm_plan(pl, N, h.data(), a, n, levels, leaf, msg);
+    FmmPlan &pl = hc.plan;
+    const int prc = fmm_plan(pl, hc.scratch, N, h, a, n, levels, leaf, msg);
     if (prc) return prc;
     // upload
     const int P = F.P, ncell = pl.ncell;
@@ -1596,11 +1763,21 @@ int arb_fmm_plan(int N, const double *pos, double a, int order, int levels, int 
     out->order = n;
     if (N == 0) return ARB_OK;
     const auto t0 = std::chrono::steady_clock::now();
+    // one scratch kept for the process (plans on several threads at once: the
+    // others take scratch of their own for the call)
+    static std::mutex mu;
+    static PlanScratch kept;
     FmmPlan pl;
     int rc = 0;
     try {
         std::string msg;
-        rc = fmm_plan(pl, N, pos, a, n, levels, leaf, &msg);
+        std::unique_lock<std::mutex> lk(mu, std::try_to_lock);
+        if (lk.owns_lock()) {
+            rc = fmm_plan(pl, kept, N, pos, a, n, levels, leaf, &msg);
+        } else {
+            PlanScratch own;
+            rc = fmm_plan(pl, own, N, pos, a, n, levels, leaf, &msg);
+        }
     } catch (...) {  // host allocation or worker-thread failure: no exception crosses the ABI
         return ARB_E_HOST;
     }

@@ -265,17 +265,36 @@ __device__ __forceinline__ int64_t dinv_offset(const MatBatch &B, int p) {
 }
 
 
-// Blocked in-place Cholesky of each M_pp (lower triangle; the upper triangle is
-// not touched).  Dynamic LDS: the panel, max_m x kLd doubles.
-__global__ __launch_bounds__(256) void pc_potrf_kernel(MatBatch B) {
-    extern __shared__ double Pn[];
+// Blocked right-looking Cholesky of each matrix of the batch, in place (lower
+// triangle; the upper triangle is not touched), one workgroup per matrix,
+// 32-column panels.  Per panel:
+//   1. the 32 x 32 diagonal block is factored in LDS (outer-product form: one
+//      barrier per pivot, the columns scaled once at the end), and its inverse
+//      L_kk^-1 formed by the same row operations on the identity (kept in LDS and
+//      stored for the triangular-inverse kernel);
+//   2. the rows below become L_bel = A_bel L_kk^-T on the matrix cores (wavefront
+//      w takes the 16-row tiles w, w + 4, ...; both column tiles of a row tile in
+//      one wavefront, so a row is read completely before it is overwritten), stored
+//      in the matrix and, column-major, in a panel scratch: the first 32 m doubles
+//      of the matrix's slot in B.out, which only the later kernels write;
+//   3. the trailing lower triangle takes A -= L_bel L_bel^T on the matrix cores in
+//      64 x 64 tiles (wavefront w: the 32 x 32 quarter (w / 2, w % 2)), operands
+//      read from the scratch (16 consecutive rows per load); a tile's entries are
+//      read before its products run.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pc_potrf_kernel(
+    MatBatch B) {
+    __shared__ double Dk[kNB * kLd];  // diagonal block, then L_kk
+    __shared__ double Wi[kNB * kLd];  // L_kk^-1, zero padded
+    __shared__ double isq[kNB];
     __shared__ int fail;
     __shared__ double piv_tol;
     const int p = blockIdx.x, tid = threadIdx.x;
     if (mat_skip(B, p)) return;
     const int m = mat_rows(B, p);
     double *A = B.mats + B.mat_off[p];
+    double *Lp = B.out + B.mat_off[p];  // panel scratch, Lp[t * m + i]
     double *Dg = B.dinv + dinv_offset(B, p);
+    const int w = tid >> 6, l = tid & 63;
     if (tid == 0) {
         fail = 0;
         double dmax = 0.0;
@@ -283,140 +302,152 @@ __global__ __launch_bounds__(256) void pc_potrf_kernel(MatBatch B) {
             for (int k = 0; k < m; ++k) dmax = fmax(dmax, A[(size_t)k * m + k]);
         piv_tol = B.rel_tol * dmax;
     }
-    __syncthreads();
     for (int k0 = 0; k0 < m; k0 += kNB) {
-        const int nb = min(kNB, m - k0), rows = m - k0;
+        const int nb = min(kNB, m - k0), nt = m - k0 - nb;  // nt rows below the block
         __syncthreads();
-        for (int idx = tid; idx < rows * kNB; idx += 256) {
-            const int i = idx / kNB, t = idx % kNB;
-            Pn[i * kLd + t] = t < nb ? A[(size_t)(k0 + i) * m + k0 + t] : 0.0;
+        // 1. the diagonal block: thread tid holds entries (i, c) = (tid / 32 + 8 q, tid % 32).
+        // The row operations of the elimination (row i -= l_ij row j, l_ij = D_ij / D_jj)
+        // are applied to the identity in Wi as well, which turns it into the unit lower
+        // triangular inverse factor; scaled by the pivots' 1/sqrt it is L_kk^-1
+        const int c = tid & 31;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = (tid >> 5) + 8 * q;
+            Dk[i * kLd + c] = (i < nb && c <= i) ? A[(size_t)(k0 + i) * m + k0 + c] : 0.0;
+            Wi[i * kLd + c] = (i < nb && c == i) ? 1.0 : 0.0;
         }
         __syncthreads();
-        // panel: column j is final once its pivot is known; the update of the
-        // columns to its right uses the unscaled column divided by the pivot
+        bool bad = false;
         for (int j = 0; j < nb; ++j) {
-            const double d = Pn[j * kLd + j];
+            const double d = Dk[j * kLd + j];
             if (!(d > piv_tol)) {  // the same value for every thread: a uniform exit
-                if (tid == 0) fail = 1;
+                bad = true;
                 break;
             }
             const double inv = 1.0 / d;
-            // thread t updates rows t, t + 256, ... (entries c of the lower triangle
-            // right of column j); the column-j entries are broadcast reads
-            for (int i = j + 1 + tid; i < rows; i += 256) {
-                const double lij = Pn[i * kLd + j] * inv;
-                const int cmax = min(i, nb - 1);
-                for (int c = j + 1; c <= cmax; ++c) Pn[i * kLd + c] -= lij * Pn[c * kLd + j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = (tid >> 5) + 8 * q;
+                if (i > j && i < nb) {
+                    const double lij = Dk[i * kLd + j] * inv;
+                    if (c > j && c <= i)
+                        Dk[i * kLd + c] -= lij * Dk[c * kLd + j];
+                    else if (c <= j)
+                        Wi[i * kLd + c] -= lij * Wi[j * kLd + c];
+                }
             }
             __syncthreads();
-            const double sq = sqrt(d), isq = 1.0 / sq;
-            for (int i = j + tid; i < rows; i += 256)
-                Pn[i * kLd + j] = i == j ? sq : Pn[i * kLd + j] * isq;
+        }
+        if (bad) {
+            if (tid == 0) fail = 1;
+            break;
+        }
+        // L_ic = D_ic / sqrt(D_cc), (L^-1)_ic = E_ic / sqrt(D_ii) with the final pivots D
+        if (tid < nb) isq[tid] = 1.0 / sqrt(Dk[tid * kLd + tid]);
+        __syncthreads();
+        double lv[4], xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = (tid >> 5) + 8 * q;
+            const bool in = i < nb && c <= i;
+            lv[q] = in ? Dk[i * kLd + c] * isq[c] : 0.0;
+            xv[q] = in ? Wi[i * kLd + c] * isq[i] : 0.0;
         }
         __syncthreads();
-        if (fail) break;
-        for (int idx = tid; idx < rows * kNB; idx += 256) {
-            const int i = idx / kNB, t = idx % kNB;
-            if (t < nb && i >= t) A[(size_t)(k0 + i) * m + k0 + t] = Pn[i * kLd + t];
+        double *Db = Dg + (k0 / kNB) * (kNB * kNB);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = (tid >> 5) + 8 * q;
+            Dk[i * kLd + c] = lv[q];
+            Wi[i * kLd + c] = xv[q];
+            Db[i * kNB + c] = xv[q];
+            if (i < nb && c <= i) A[(size_t)(k0 + i) * m + k0 + c] = lv[q];
+            if (B.ldiag && i < nb && c == i) B.ldiag[B.scale * (int64_t)B.off[p] + k0 + i] = lv[q];
         }
-        if (B.ldiag)
-            for (int t = tid; t < nb; t += 256)
-                B.ldiag[B.scale * (int64_t)B.off[p] + k0 + t] = Pn[t * kLd + t];
-        // inverse of the diagonal block: thread c solves L z = e_c (zero padded)
-        if (tid < kNB) {
-            const int c = tid;
-            double z[kNB];
+        if (nt <= 0) break;  // the last panel (nb = 32 whenever rows remain below)
+        __syncthreads();
+        // 2. L_bel = A_bel L_kk^-T: tile (row tile rt, column tile ct), lane l supplies
+        // a = A_bel[16 rt + l % 16][4 s + l / 16] and b = Wi[16 ct + l % 16][4 s + l / 16]
+        const int nrt = (nt + 15) >> 4;
+        double *Abel = A + (size_t)(k0 + kNB) * m + k0;
+        for (int rt = w; rt < nrt; rt += 4) {
+            const int ra = min(16 * rt + (l & 15), nt - 1);
+            double av[8];
 #pragma unroll
-            for (int i = 0; i < kNB; ++i) {
-                double v = 0.0;
-                if (i < nb && c < nb && i >= c) {
-                    double acc = i == c ? 1.0 : 0.0;
+            for (int s = 0; s < 8; ++s) av[s] = Abel[(size_t)ra * m + 4 * s + (l >> 4)];
+            mfma_acc acc0 = {}, acc1 = {};
 #pragma unroll
-                    for (int k = 0; k < i; ++k)
-                        if (k >= c) acc -= Pn[i * kLd + k] * z[k];
-                    v = acc / Pn[i * kLd + i];
-                }
-                z[i] = v;
+            for (int s = 0; s < 8; ++s) {
+                const int kk = 4 * s + (l >> 4);
+                acc0 = mfma_f64_16x16x4(av[s], Wi[(l & 15) * kLd + kk], acc0);
+                acc1 = mfma_f64_16x16x4(av[s], Wi[(16 + (l & 15)) * kLd + kk], acc1);
             }
-            double *Db = Dg + (k0 / kNB) * (kNB * kNB);
 #pragma unroll
-            for (int i = 0; i < kNB; ++i) Db[i * kNB + c] = z[i];
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * rt + 4 * e + (l >> 4);
+                if (i < nt) {
+                    const int cc = l & 15;
+                    Abel[(size_t)i * m + cc] = acc0[e];
+                    Abel[(size_t)i * m + 16 + cc] = acc1[e];
+                    Lp[(size_t)cc * m + i] = acc0[e];
+                    Lp[(size_t)(16 + cc) * m + i] = acc1[e];
+                }
+            }
         }
-        // trailing update of the lower triangle, A_ij -= sum_t L_it L_jt, in 64 x 64
-        // tiles: wavefront w takes the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 matrix-core
-        // tiles; columns t >= nb of the panel are zero
-        const int t0 = k0 + nb, nt = m - t0;
-        if (nt > 0) {
-            const int ntile = (nt + 63) / 64;
-            const int w = tid >> 6, l = tid & 63, wr = w >> 1, wc = w & 1;
-            const int kt = (nb + 3) & ~3;
-            const int ntiles = ntile * (ntile + 1) / 2;
-            // tile -> (bi, bj), bj <= bi, row by row of the lower triangle of tiles
-            auto tile_ij = [](int tile, int &bi, int &bj) {
-                bi = 0;
-                while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
-                bj = tile - bi * (bi + 1) / 2;
-            };
-            // this lane's 16 entries of a tile's 32 x 32 quarter (clamped into the matrix)
-            auto load_quarter = [&](int i0, int j0, double (&v)[2][2][4]) {
+        __syncthreads();
+        // 3. trailing update of the lower triangle, A_ij -= sum_t L_it L_jt
+        const int t0 = k0 + kNB;
+        const int ntile = (nt + 63) / 64;
+        const int wr = w >> 1, wc = w & 1;
+        const int ntiles = ntile * (ntile + 1) / 2;
+        // tile -> (bi, bj), bj <= bi, row by row of the lower triangle of tiles
+        auto tile_ij = [](int tile, int &bi, int &bj) {
+            bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+            bj = tile - bi * (bi + 1) / 2;
+        };
+        // this lane's 16 entries of a tile's 32 x 32 quarter (clamped into the matrix)
+        auto load_quarter = [&](int i0, int j0, double (&v)[2][2][4]) {
 #pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
+            for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
+                for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int i = min(i0 + 16 * ti + 4 * e + (l >> 4), nt - 1);
-                            const int j = min(j0 + 16 * tj + (l & 15), nt - 1);
-                            v[ti][tj][e] = A[(size_t)(t0 + i) * m + t0 + j];
-                        }
-            };
-            // the next tile's entries are read while the current tile's products run
-            double cur[2][2][4], nxt[2][2][4];
+                    for (int e = 0; e < 4; ++e) {
+                        const int i = min(i0 + 16 * ti + 4 * e + (l >> 4), nt - 1);
+                        const int j = min(j0 + 16 * tj + (l & 15), nt - 1);
+                        v[ti][tj][e] = A[(size_t)(t0 + i) * m + t0 + j];
+                    }
+        };
+        for (int tile = 0; tile < ntiles; ++tile) {
             int bi, bj;
-            tile_ij(0, bi, bj);
-            load_quarter(64 * bi + 32 * wr, 64 * bj + 32 * wc, cur);
-            for (int tile = 0; tile < ntiles; ++tile) {
-                tile_ij(tile, bi, bj);
-                const int i0 = 64 * bi + 32 * wr, j0 = 64 * bj + 32 * wc;
-                if (tile + 1 < ntiles) {
-                    int bi1, bj1;
-                    tile_ij(tile + 1, bi1, bj1);
-                    load_quarter(64 * bi1 + 32 * wr, 64 * bj1 + 32 * wc, nxt);
-                }
-                int ra[2], rb[2];  // panel rows of this lane's A and B operands
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    ra[q] = nb + min(i0 + 16 * q + (l & 15), nt - 1);
-                    rb[q] = nb + min(j0 + 16 * q + (l & 15), nt - 1);
-                }
-                mfma_acc acc[2][2] = {};
-                for (int t = 0; t < kt; t += 4) {
-                    const int tc = t + (l >> 4);
-                    const double a0 = Pn[ra[0] * kLd + tc], a1 = Pn[ra[1] * kLd + tc];
-                    const double b0 = Pn[rb[0] * kLd + tc], b1 = Pn[rb[1] * kLd + tc];
-                    acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
-                    acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
-                    acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
-                    acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
-                }
-#pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int i = i0 + 16 * ti + 4 * e + (l >> 4);
-                            const int j = j0 + 16 * tj + (l & 15);
-                            if (i < nt && j <= i)
-                                A[(size_t)(t0 + i) * m + t0 + j] = cur[ti][tj][e] - acc[ti][tj][e];
-                        }
-#pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) cur[ti][tj][e] = nxt[ti][tj][e];
+            tile_ij(tile, bi, bj);
+            const int i0 = 64 * bi + 32 * wr, j0 = 64 * bj + 32 * wc;
+            double cur[2][2][4];
+            load_quarter(i0, j0, cur);
+            const int ra0 = min(i0 + (l & 15), nt - 1), ra1 = min(i0 + 16 + (l & 15), nt - 1);
+            const int rb0 = min(j0 + (l & 15), nt - 1), rb1 = min(j0 + 16 + (l & 15), nt - 1);
+            mfma_acc acc[2][2] = {};
+#pragma unroll 2
+            for (int s = 0; s < 8; ++s) {
+                const double *col = Lp + (size_t)(4 * s + (l >> 4)) * m;
+                const double a0 = col[ra0], a1 = col[ra1], b0 = col[rb0], b1 = col[rb1];
+                acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
+                acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
+                acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
+                acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
             }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int i = i0 + 16 * ti + 4 * e + (l >> 4);
+                        const int j = j0 + 16 * tj + (l & 15);
+                        if (i < nt && j <= i)
+                            A[(size_t)(t0 + i) * m + t0 + j] = cur[ti][tj][e] - acc[ti][tj][e];
+                    }
         }
     }
     __syncthreads();
@@ -612,6 +643,51 @@ __device__ __forceinline__ double K_entry(const double *d, int a, int c) {
     return b == 0 ? d[1] : -d[0];
 }
 
+// out = R^-1 for a symmetric positive definite 6 x 6 R by Cholesky (R = L L^T,
+// X = L^-1, R^-1 = X^T X; L and X are 36-double scratch, row-major); false,
+// with out untouched, when a pivot falls to 1e-8 of the largest diagonal entry
+// or below (then the caller takes the pseudo-inverse, which is the inverse
+// whenever this succeeds)
+__device__ inline bool chol_inv6(const double *R, double *L, double *X, double *out) {
+    double dmax = 0.0;
+    for (int i = 0; i < 6; ++i) dmax = fmax(dmax, R[i * 6 + i]);
+    const double tol = 1e-8 * dmax;
+    for (int j = 0; j < 6; ++j) {
+        double d = R[j * 6 + j];
+        for (int k = 0; k < j; ++k) d -= L[j * 6 + k] * L[j * 6 + k];
+        if (!(d > tol)) return false;
+        L[j * 6 + j] = sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double v = R[i * 6 + j];
+            for (int k = 0; k < j; ++k) v -= L[i * 6 + k] * L[j * 6 + k];
+            L[i * 6 + j] = v / L[j * 6 + j];
+        }
+    }
+    for (int c = 0; c < 6; ++c)
+        for (int i = 0; i < 6; ++i) {
+            if (i < c) {
+                X[i * 6 + c] = 0.0;
+                continue;
+            }
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) v -= L[i * 6 + k] * X[k * 6 + c];
+            X[i * 6 + c] = v / L[i * 6 + i];
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double v = 0.0;
+            for (int k = max(i, j); k < 6; ++k) v += X[k * 6 + i] * X[k * 6 + j];
+            out[i * 6 + j] = v;
+        }
+    return true;
+}
+
+// Per body: Z = M^-1 K (m x 6) and N~ = (K^T M^-1 K)^-1 (Sec. 3.1).  Thread r
+// takes row r of Z (M^-1 is symmetric, so the row is read as column r:
+// consecutive threads read consecutive addresses) and adds K_r^T Z_r to its
+// partial R = K^T Z (the 21 entries of the upper triangle); the partials are
+// summed over the wavefronts, then N~ = R^-1 by Cholesky; when R is singular (a
+// rod of collinear blobs) R is stored and flagged for pc_body_pinv_kernel.
 __global__ __launch_bounds__(256) void pc_body_kernel(const int *__restrict__ blob_off,
                                                       const int64_t *__restrict__ mat_off,
                                                       const int64_t *__restrict__ z_off,
@@ -619,20 +695,25 @@ __global__ __launch_bounds__(256) void pc_body_kernel(const int *__restrict__ bl
                                                       const double *__restrict__ dvec,
                                                       double *__restrict__ Zbuf,
                                                       double *__restrict__ Nt,
+                                                      int *__restrict__ body_pinv,
                                                       int *__restrict__ status) {
-    __shared__ double R[36], S6[36], V6[36];
+    __shared__ double red[4][21];
+    __shared__ double S6[36], V6[36], L6[36];  // R, then Cholesky scratch
     const int p = blockIdx.x;
     if (status[0] != 0) return;
     const int b0 = blob_off[p], n = blob_off[p + 1] - b0, m = 3 * n;
     const double *Mi = minv + mat_off[p];
     double *Z = Zbuf + z_off[p];
     const double *d = dvec + 3 * (size_t)b0;
-    // Z = M^-1 K (m x 6), row r
+    double racc[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) racc[e] = 0.0;
     for (int r = threadIdx.x; r < m; r += blockDim.x) {
         double z[6] = {0, 0, 0, 0, 0, 0};
-        const double *row = Mi + (size_t)r * m;
+        const double *col = Mi + r;
         for (int i = 0; i < n; ++i) {
-            const double m0 = row[3 * i], m1 = row[3 * i + 1], m2 = row[3 * i + 2];
+            const double m0 = col[(size_t)(3 * i) * m], m1 = col[(size_t)(3 * i + 1) * m],
+                         m2 = col[(size_t)(3 * i + 2) * m];
             const double *di = d + 3 * i;
             z[0] += m0;
             z[1] += m1;
@@ -643,21 +724,54 @@ __global__ __launch_bounds__(256) void pc_body_kernel(const int *__restrict__ bl
             z[5] += -m0 * di[1] + m1 * di[0];
         }
         for (int c = 0; c < 6; ++c) Z[(size_t)r * 6 + c] = z[c];
+        // row r = 3 i + a of K: e_a, then -(d_i^x) row a
+        const double *dr = d + 3 * (r / 3);
+        const int a = r % 3;
+        double kr[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) kr[c] = K_entry(dr, a, c);
+        int e = 0;
+#pragma unroll
+        for (int c1 = 0; c1 < 6; ++c1)
+#pragma unroll
+            for (int c2 = c1; c2 < 6; ++c2) racc[e++] += kr[c1] * z[c2];
     }
-    __syncthreads();
-    // R = K^T Z
-    if (threadIdx.x < 36) {
-        const int c1 = threadIdx.x / 6, c2 = threadIdx.x % 6;
-        double s = 0.0;
-        for (int r = 0; r < m; ++r) s += K_entry(d + 3 * (r / 3), r % 3, c1) * Z[(size_t)r * 6 + c2];
-        R[threadIdx.x] = s;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int e = 0; e < 21; ++e) {
+        double v = racc[e];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[w][e] = v;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 36; ++k) S6[k] = 0.5 * (R[k] + R[(k % 6) * 6 + k / 6]);
-        const int dropped = sym_pinv_serial(S6, V6, 6, Nt + 36 * (size_t)p, 1e-12);
-        if (dropped) atomicAdd(&status[3], 1);
+        int e = 0;
+        for (int c1 = 0; c1 < 6; ++c1)
+            for (int c2 = c1; c2 < 6; ++c2, ++e) {
+                double v = 0.0;
+                for (int k = 0; k < (int)(blockDim.x >> 6); ++k) v += red[k][e];
+                S6[c1 * 6 + c2] = v;
+                S6[c2 * 6 + c1] = v;
+            }
+        double *out = Nt + 36 * (size_t)p;
+        const bool ok = chol_inv6(S6, L6, V6, out);
+        if (!ok)  // R for pc_body_pinv_kernel
+            for (int k = 0; k < 36; ++k) out[k] = S6[k];
+        body_pinv[p] = ok ? 0 : 1;
     }
+}
+
+// N~_p = R_p^+ (symmetric pseudo-inverse, eigenvalues below 1e-12 of the largest
+// dropped) for the bodies whose R_p failed the Cholesky test, one thread each
+__global__ __launch_bounds__(64) void pc_body_pinv_kernel(int M, const int *__restrict__ body_pinv,
+                                                          double *__restrict__ Nt,
+                                                          int *__restrict__ status) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M || !body_pinv[p] || status[0] != 0) return;
+    double S[36], V[36];
+    double *out = Nt + 36 * (size_t)p;
+    for (int k = 0; k < 36; ++k) S[k] = out[k];
+    if (sym_pinv_serial(S, V, 6, out, 1e-12)) atomicAdd(&status[3], 1);
 }
 
 // S = C_a N~_a C_a^T (na x na, row-major) for the assembly's rows r0 .. r0+na-1,
@@ -692,17 +806,87 @@ __device__ void asm_form_S(int r0, int na, const int *__restrict__ asm_rows,
     }
 }
 
-// the assemblies' S_a for the blocked kernels (assemblies of at most kFastMaxM rows)
+// The rows of one assembly staged in LDS: cl[12 k + 6 side + u] the row's
+// coefficients on the body of that side, bl[2 k + side] the body (-1: none).
+__device__ void asm_stage_rows(int r0, int na, const int *__restrict__ asm_rows,
+                               const int *__restrict__ row_p, const int *__restrict__ row_q,
+                               const double *__restrict__ crow, double *cl, int *bl) {
+    for (int idx = threadIdx.x; idx < 12 * na; idx += blockDim.x) {
+        const int k = idx / 12, u = idx - 12 * k;
+        cl[idx] = crow[12 * (size_t)asm_rows[r0 + k] + u];
+    }
+    for (int k = threadIdx.x; k < na; k += blockDim.x) {
+        const int rk = asm_rows[r0 + k];
+        bl[2 * k] = row_p[rk];
+        bl[2 * k + 1] = row_q[rk];
+    }
+}
+
+// Column l of the lower triangle of S_a = C_a N~ C_a^T from the staged rows, by
+// the calling thread: t_side = N~_b c_l,side for the bodies b of row l, then
+// S_kl = sum of c_k,side' . t_side over the side pairs on the same body, k >= l.
+// store(k, value) receives every entry.  The rows are visited from k = 0 (the
+// threads of a wavefront store row k together, at consecutive addresses); rows
+// above the diagonal are skipped.
+template <class F>
+__device__ __forceinline__ void asm_column(int l, int na, const double *cl, const int *bl,
+                                           const double *__restrict__ Nt, F &&store) {
+    double t[2][6];
+    int bs[2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        bs[sd] = bl[2 * l + sd];
+        const double *c = cl + 12 * l + 6 * sd;
+        const double *Nb = Nt + 36 * (size_t)max(bs[sd], 0);
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            double v = 0.0;
+            if (bs[sd] >= 0)
+#pragma unroll
+                for (int w = 0; w < 6; ++w) v += Nb[u * 6 + w] * c[w];
+            t[sd][u] = v;
+        }
+    }
+    for (int k = 0; k < na; ++k) {
+        if (k < l) continue;
+        const int b0 = bl[2 * k], b1 = bl[2 * k + 1];
+        double sum = 0.0;
+#pragma unroll
+        for (int sk = 0; sk < 2; ++sk) {
+            const int bk = sk ? b1 : b0;
+            if (bk < 0) continue;
+            const double *c = cl + 12 * k + 6 * sk;
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd)
+                if (bk == bs[sd])
+#pragma unroll
+                    for (int u = 0; u < 6; ++u) sum += c[u] * t[sd][u];
+        }
+        store(k, sum);
+    }
+}
+
+// the lower triangle of the assemblies' S_a for the blocked kernels (assemblies of
+// at most kFastMaxM rows; the factorisation reads no other entries).  Dynamic LDS:
+// the staged rows, 12 doubles and 2 ints per row of the largest assembly.
 __global__ __launch_bounds__(256) void pc_asm_form_kernel(
     const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
     const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
     const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
-    double *__restrict__ Sbuf, int *__restrict__ fail, const int *__restrict__ status) {
+    double *__restrict__ Sbuf, int *__restrict__ fail, const int *__restrict__ status,
+    int max_rows) {
+    extern __shared__ double sm[];
+    double *cl = sm;
+    int *bl = reinterpret_cast<int *>(sm + 12 * (size_t)max_rows);
     const int a = blockIdx.x;
     const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
     if (threadIdx.x == 0) fail[a] = 0;
     if (na == 0 || status[0] != 0) return;
-    asm_form_S(r0, na, asm_rows, row_p, row_q, crow, Nt, Sbuf + asm_mat_off[a]);
+    asm_stage_rows(r0, na, asm_rows, row_p, row_q, crow, cl, bl);
+    __syncthreads();
+    double *S = Sbuf + asm_mat_off[a];
+    for (int l = threadIdx.x; l < na; l += blockDim.x)
+        asm_column(l, na, cl, bl, Nt, [&](int k, double v) { S[(size_t)k * na + l] = v; });
 }
 
 // assemblies whose S_a failed the Cholesky pivot test: S_a formed again and its
@@ -726,51 +910,41 @@ __global__ __launch_bounds__(256) void pc_asm_pinv_kernel(
     }
 }
 
-// assemblies of at most kAsmSmall rows, held in LDS: Cholesky in outer-product
-// form (one barrier per pivot; the pivot column is scaled at the end), pivot test
-// relative to the largest diagonal entry, then G~ = S^-1 column by column (thread c
-// solves L L^T g = e_c).  A failed pivot flags the assembly for the
-// pseudo-inverse kernel.
+// Assemblies of at most kAsmSmall rows, one workgroup each, everything in LDS
+// (dynamic: S and E, n (n + 1) doubles each, and the staged rows, for n rows of
+// the largest assembly):
+//   S = C_a N~ C_a^T (lower triangle, a column per thread);
+//   elimination in outer-product form (row i -= l_ij row j, l_ij = S_ij / S_jj,
+//   one barrier per pivot; pivot test relative to the largest diagonal entry),
+//   the same row operations applied to the identity in E, which becomes the unit
+//   lower triangular factor E with E S E^T = D (the final pivots);
+//   G~ = S^-1 = E^T D^-1 E, each entry by one thread.
+// A failed pivot flags the assembly for the pseudo-inverse kernel.
 constexpr int kAsmSmall = 64;
 __global__ __launch_bounds__(256) void pc_asm_small_kernel(
     const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
     const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
     const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
-    double *__restrict__ Gbuf, int *__restrict__ fail, const int *__restrict__ status) {
-    __shared__ double S[kAsmSmall * (kAsmSmall + 1)];
-    __shared__ double Y[kAsmSmall * (kAsmSmall + 1)];
+    double *__restrict__ Gbuf, int *__restrict__ fail, const int *__restrict__ status,
+    int max_rows) {
+    extern __shared__ double sm[];
+    const int ld = max_rows + 1;
+    double *S = sm, *E = S + (size_t)max_rows * ld, *cl = E + (size_t)max_rows * ld;
+    int *bl = reinterpret_cast<int *>(cl + 12 * (size_t)max_rows);
     __shared__ double tol;
-    constexpr int ld = kAsmSmall + 1;
+    __shared__ double invd[kAsmSmall];
     const int a = blockIdx.x, tid = threadIdx.x;
     const int r0 = asm_row_ptr[a], na = asm_row_ptr[a + 1] - r0;
     if (tid == 0) fail[a] = 0;
     if (na == 0 || status[0] != 0) return;
-    // S = C_a N~ C_a^T into LDS (row stride ld)
+    asm_stage_rows(r0, na, asm_rows, row_p, row_q, crow, cl, bl);
     for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
-        const int k = idx >> 6, l = idx & 63;
-        if (k >= na || l >= na) continue;
-        const int rk = asm_rows[r0 + k], rl = asm_rows[r0 + l];
-        double sum = 0.0;
-#pragma unroll 1
-        for (int sk = 0; sk < 2; ++sk) {
-            const int bk = sk ? row_q[rk] : row_p[rk];
-            if (bk < 0) continue;
-            const double *ck = crow + 12 * (size_t)rk + 6 * sk;
-#pragma unroll 1
-            for (int sl = 0; sl < 2; ++sl) {
-                const int bl = sl ? row_q[rl] : row_p[rl];
-                if (bl != bk) continue;
-                const double *cl = crow + 12 * (size_t)rl + 6 * sl;
-                const double *Nb = Nt + 36 * (size_t)bk;
-                for (int u = 0; u < 6; ++u) {
-                    double t = 0.0;
-                    for (int v = 0; v < 6; ++v) t += Nb[u * 6 + v] * cl[v];
-                    sum += ck[u] * t;
-                }
-            }
-        }
-        S[k * ld + l] = sum;
+        const int i = idx >> 6, c = idx & 63;
+        if (i < na && c <= i) E[i * ld + c] = i == c ? 1.0 : 0.0;
     }
+    __syncthreads();
+    for (int l = tid; l < na; l += 256)
+        asm_column(l, na, cl, bl, Nt, [&](int k, double v) { S[k * ld + l] = v; });
     __syncthreads();
     if (tid == 0) {
         double dmax = 0.0;
@@ -778,47 +952,49 @@ __global__ __launch_bounds__(256) void pc_asm_small_kernel(
         tol = 1e-12 * dmax;
     }
     __syncthreads();
-    for (int k = 0; k < na; ++k) {
-        const double d = S[k * ld + k];
+    // thread tid owns column c = tid % 64 of rows i = tid / 64 + 4 q (q < 16): the
+    // column-c entries of row j are read once per pivot, the rows' entries all
+    // issued before they are updated
+    const int c = tid & 63, i0 = tid >> 6;
+    for (int j = 0; j < na; ++j) {
+        const double d = S[j * ld + j];
         if (!(d > tol)) {  // the same value for every thread: a uniform exit
             if (tid == 0) fail[a] = 1;
             return;
         }
         const double inv = 1.0 / d;
-        for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
-            const int i = idx >> 6, j = idx & 63;
-            if (j > k && j <= i && i < na) S[i * ld + j] -= S[i * ld + k] * S[j * ld + k] * inv;
+        const bool right = c > j;  // S entry (right of the pivot column), else E entry
+        const double pj = c < na ? (right ? S[c * ld + j] : E[j * ld + c]) : 0.0;
+        double *X = right ? S : E;
+#pragma unroll
+        for (int q = 0; q < kAsmSmall / 4; ++q) {
+            const int i = i0 + 4 * q;
+            if (i > j && i < na && c <= i) X[i * ld + c] -= S[i * ld + j] * inv * pj;
         }
         __syncthreads();
     }
-    // L_ik = S_ik / sqrt(S_kk) (the pivots are the final S_kk)
-    for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
-        const int i = idx >> 6, k = idx & 63;
-        if (k < i && i < na) Y[i * ld + k] = S[i * ld + k] / sqrt(S[k * ld + k]);
-        if (k == i && i < na) Y[i * ld + i] = sqrt(S[i * ld + i]);
-    }
+    if (tid < na) invd[tid] = 1.0 / S[tid * ld + tid];
     __syncthreads();
-    // thread c: L y = e_c forward, L^T g = y backward, g = column c of S^-1 (y in S's
-    // column c, which the factorisation no longer needs)
-    if (tid < na) {
-        const int c = tid;
-        double *G = Gbuf + asm_mat_off[a];
-        for (int i = 0; i < na; ++i) {
-            double v = i == c ? 1.0 : 0.0;
-            if (i < c) {
-                S[i * ld + c] = 0.0;
-                continue;
+    // G~_ij = sum_k E_ki E_kj / D_k over k >= max(i, j): thread tid takes column
+    // j = tid % 64 of rows i = tid / 64 + 4 q, one pass over k
+    double *G = Gbuf + asm_mat_off[a];
+    const int j = c;
+    double acc[kAsmSmall / 4];
+#pragma unroll
+    for (int q = 0; q < kAsmSmall / 4; ++q) acc[q] = 0.0;
+    if (j < na)
+        for (int k = j; k < na; ++k) {
+            const double ekj = E[k * ld + j] * invd[k];
+#pragma unroll
+            for (int q = 0; q < kAsmSmall / 4; ++q) {
+                const int i = i0 + 4 * q;
+                if (i <= k) acc[q] += E[k * ld + i] * ekj;
             }
-            for (int k = c; k < i; ++k) v -= Y[i * ld + k] * S[k * ld + c];
-            S[i * ld + c] = v / Y[i * ld + i];
         }
-        for (int i = na - 1; i >= 0; --i) {
-            double v = S[i * ld + c];
-            for (int k = i + 1; k < na; ++k) v -= Y[k * ld + i] * S[k * ld + c];
-            v /= Y[i * ld + i];
-            S[i * ld + c] = v;
-            G[(size_t)i * na + c] = v;
-        }
+#pragma unroll
+    for (int q = 0; q < kAsmSmall / 4; ++q) {
+        const int i = i0 + 4 * q;
+        if (i < na && j < na) G[(size_t)i * na + j] = acc[q];
     }
 }
 
@@ -1303,19 +1479,15 @@ void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos, dou
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m) {
     if (P.M <= 0) return hipSuccess;
     if (max_m <= kFastMaxM) {
-        const size_t lds_f = (size_t)max_m * kLd * sizeof(double);
         const int nbk = (max_m + kNB - 1) / kNB;
         const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
-        hipError_t e = hipFuncSetAttribute((const void *)pc_potrf_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
+        const hipError_t e = hipFuncSetAttribute(
+            (const void *)pc_trtri_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
         if (e != hipSuccess) return e;
         const int nt = (max_m + 63) / 64;
         const MatBatch B{P.blob_off, 3, P.mat_off, P.mats, P.ldiag, P.dinv, P.minv, P.status,
                          nullptr, 0.0};
-        pc_potrf_kernel<<<P.M, 256, lds_f, s>>>(B);
+        pc_potrf_kernel<<<P.M, 256, 0, s>>>(B);
         pc_trtri_kernel<<<dim3(nbk, P.M), 256, lds_i, s>>>(B);
         pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.M), 256, 0, s>>>(B);
     } else {
@@ -1325,7 +1497,8 @@ hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec
         pc_restore_diag_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.mats, P.ldiag);
     }
     pc_body_kernel<<<P.M, 256, 0, s>>>(P.blob_off, P.mat_off, P.z_off, P.minv, dvec, P.Z, P.Nt,
-                                       P.status);
+                                       P.body_pinv, P.status);
+    pc_body_pinv_kernel<<<(P.M + 63) / 64, 64, 0, s>>>(P.M, P.body_pinv, P.Nt, P.status);
     return hipGetLastError();
 }
 
@@ -1375,10 +1548,16 @@ void precond_apply_single(hipStream_t s, const PrecondDev &P, const int *zero_of
 // inverse written to P.G); beyond: the unblocked kernel.
 hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
     if (P.A <= 0) return hipSuccess;
-    if (P.asm_max_rows <= kAsmSmall && P.asm_fail) {
-        pc_asm_small_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
-                                                P.row_p, P.row_q, P.crow, P.Nt, P.G, P.asm_fail,
-                                                P.status);
+    const int nmax = std::max(P.asm_max_rows, 1);
+    if (nmax <= kAsmSmall && P.asm_fail) {
+        const size_t lds = (2 * (size_t)nmax * (nmax + 1) + 12 * (size_t)nmax) * sizeof(double) +
+                           2 * (size_t)nmax * sizeof(int);
+        const hipError_t e = hipFuncSetAttribute(
+            (const void *)pc_asm_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        pc_asm_small_kernel<<<P.A, 256, lds, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
+                                                  P.row_p, P.row_q, P.crow, P.Nt, P.G,
+                                                  P.asm_fail, P.status, nmax);
         pc_asm_pinv_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
                                                P.row_q, P.crow, P.Nt, P.S, P.G, P.asm_fail,
                                                P.status);
@@ -1389,22 +1568,23 @@ hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
                                           P.row_q, P.crow, P.Nt, P.S, P.G, P.status);
         return hipGetLastError();
     }
-    const int max_m = std::max(P.asm_max_rows, 1);
-    const size_t lds_f = (size_t)max_m * kLd * sizeof(double);
+    const int max_m = nmax;
     const int nbk = (max_m + kNB - 1) / kNB;
     const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)pc_potrf_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f);
+    const size_t lds_r = 12 * (size_t)max_m * sizeof(double) + 2 * (size_t)max_m * sizeof(int);
+    hipError_t e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
+    e = hipFuncSetAttribute((const void *)pc_asm_form_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
     if (e != hipSuccess) return e;
     const int nt = (max_m + 63) / 64;
-    pc_asm_form_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
-                                           P.row_q, P.crow, P.Nt, P.S, P.asm_fail, P.status);
+    pc_asm_form_kernel<<<P.A, 256, lds_r, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
+                                               P.row_p, P.row_q, P.crow, P.Nt, P.S, P.asm_fail,
+                                               P.status, max_m);
     const MatBatch B{P.asm_row_ptr, 1, P.asm_mat_off, P.S, nullptr, P.asm_dinv, P.G, P.status,
                      P.asm_fail, 1e-12};
-    pc_potrf_kernel<<<P.A, 256, lds_f, s>>>(B);
+    pc_potrf_kernel<<<P.A, 256, 0, s>>>(B);
     pc_trtri_kernel<<<dim3(nbk, P.A), 256, lds_i, s>>>(B);
     pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.A), 256, 0, s>>>(B);
     pc_asm_pinv_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,

@@ -271,15 +271,45 @@ def test_learned_fallback_on_invalid_factor():
     assert info["rel_residual"] <= 1e-10
 
 
+def oracle_residual_rows(wl, U, phi, lam, sample):
+    """Rows of b - A y for the solution y = (lam, U, phi) from the oracle
+    (Sec. 2.3, Eq. linear_system): the blob rows of the sampled blobs (the C
+    oracle's M rows over every source), every body row and every constraint row;
+    and ||b||.  Also returns the oracle's (M lam) on the sampled blobs."""
+    from oracle import bodies, rpy_c
+
+    r = bodies.blob_positions(wl.q, wl.theta, wl.r_ref, wl.blob_offset)
+    lam3 = np.asarray(lam).reshape(-1, 3)
+    Ml = rpy_c.mobility_apply(r, lam3, wl.a, wl.eta, wl.wall, targets=sample)
+    KU = bodies.K_apply(r, wl.q, wl.blob_offset, U)[sample]
+    us = (np.zeros((wl.N, 3)) if wl.u_slip is None
+          else np.asarray(wl.u_slip).reshape(-1, 3))[sample]
+    r_blob = us - (Ml - KU)
+    C, B = bodies.constraint_rows(wl, sparse=True)
+    body = -np.asarray(wl.F).reshape(-1) - (-bodies.KT_apply(r, wl.q, wl.blob_offset, lam3)
+                                            .reshape(-1) + C.T @ phi)
+    cons = B - C @ np.asarray(U).reshape(-1)
+    us_all = np.zeros(3 * wl.N) if wl.u_slip is None else np.asarray(wl.u_slip).ravel()
+    bnorm = np.linalg.norm(np.concatenate([us_all, np.asarray(wl.F).ravel(), B]))
+    return r_blob, body, cons, bnorm, Ml
+
+
 def test_full_size_learned_solve(trained):
     # 4,096 bacteria above the wall: the learned-block FP32 solve and the plain
     # FP64 exact-block solve both reach 1e-6, and their velocities agree to 1e-5.
     # What the network buys: the iteration count of the exact blocks (fewer
     # than the body-frame blocks, the method without it) at a small fraction
-    # of the exact build
+    # of the exact build.  The oracle checks both solutions at this size: the
+    # residual on 256 sampled blob rows (its C pair sums over all 499,712
+    # sources), on every body row and on every constraint row is bounded by the
+    # residual the solver reports (each set of rows is part of the whole), and
+    # the FP64 product of the solver's context matches the oracle's rows to 1e-12
+    import torch
+
     model = trained[0]
     wl = W.bacteria(n_bact=4096, seed=5)
     print(f"full size learned: N={wl.N} M={wl.M} Nc={wl.n_rows}", flush=True)
+    sample = np.random.default_rng(44).choice(wl.N, 256, replace=False).astype(np.int32)
     out, infos = {}, {}
     for name, prec, pc in (("exact_fp64", arb.ARB_FP64, arb.ARB_PC_BLOCK),
                            ("learned_fp32", arb.ARB_FP32C, arb.ARB_PC_LEARNED),
@@ -289,6 +319,13 @@ def test_full_size_learned_solve(trained):
         try:
             learned.load_model(c, *model)
             rc, U, phi, lam, info = arb.arb_solve(c, wl.F)
+            if name == "exact_fp64":
+                lam_d = torch.tensor(np.asarray(lam).ravel(), dtype=torch.float64,
+                                     device="cuda")
+                u_d = torch.zeros_like(lam_d)
+                arb.arb_mobility_apply_dev(c, lam_d, u_d)
+                torch.cuda.synchronize()
+                Ml_gpu = u_d.cpu().numpy().reshape(-1, 3)[sample]
         finally:
             arb.arb_destroy(c)
         assert rc == arb.ARB_OK
@@ -297,6 +334,19 @@ def test_full_size_learned_solve(trained):
               f"solve {info['t_solve_ms']:.1f} ms", flush=True)
         out[name] = U
         infos[name] = info
+        if name == "bodyframe_fp32":
+            continue
+        r_blob, r_body, r_cons, bnorm, Ml = oracle_residual_rows(wl, U, phi, lam, sample)
+        res = info["rel_residual_fp64"]
+        e = [np.linalg.norm(x) / bnorm for x in (r_blob, r_body, r_cons)]
+        print(f"  {name}: oracle residual rows (sampled blobs, bodies, constraints) "
+              f"{e[0]:.2e} {e[1]:.2e} {e[2]:.2e}; solver {res:.2e}", flush=True)
+        for x in e:
+            assert x <= res * (1 + 1e-6) + 1e-12
+        if name == "exact_fp64":
+            perr = np.linalg.norm(Ml_gpu - Ml) / np.linalg.norm(Ml)
+            print(f"  FP64 product rows against the oracle: {perr:.2e}", flush=True)
+            assert perr <= 1e-12
     assert rel(out["learned_fp32"], out["exact_fp64"]) <= 1e-5
     assert infos["learned_fp32"]["iterations"] <= infos["exact_fp64"]["iterations"] + 1
     assert infos["learned_fp32"]["iterations"] < infos["bodyframe_fp32"]["iterations"]

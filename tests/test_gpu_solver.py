@@ -309,12 +309,13 @@ def test_preconditioner_large_bodies(n_helix):
 def test_graph_replays_match_plain_launches(name, prec):
     # the GMRES iteration captured in HIP graphs: every solve (the first
     # captures, the later ones replay, with plain launches and host syncs in
-    # between) gives bit for bit the iterates of plain launches
+    # between) gives bit for bit the iterates of plain launches (the kernel per
+    # operation path, which small systems would otherwise not take)
     wl = cases()[name]()
     tol = 1e-10 if prec == arb.ARB_FP64 else 1e-6
     outs = {}
     for graphs in (1, 0):
-        c = arb.context_for(wl, precision=prec, tol=tol, graphs=graphs)
+        c = arb.context_for(wl, precision=prec, tol=tol, graphs=graphs, small_cycle=1)
         try:
             outs[graphs] = [arb.arb_solve(c, wl.F, u_slip=wl.u_slip) for _ in range(3)]
         finally:
@@ -325,6 +326,34 @@ def test_graph_replays_match_plain_launches(name, prec):
         assert rc == ref[0] and info["iterations"] == ref[4]["iterations"]
         assert np.array_equal(U, ref[1]) and np.array_equal(phi, ref[2])
         assert np.array_equal(lam, ref[3])
+
+
+@pytest.mark.parametrize("name", list(cases()))
+def test_one_launch_cycle_matches_per_step_kernels(name):
+    # small FP64 systems (at most 128 blobs: the filament and the rigid chain
+    # here) run each GMRES cycle in one workgroup with the stopping test on the
+    # device; the kernel-per-operation path takes the same steps (summation
+    # orders differ), so the iteration counts agree within one and every output
+    # to 1e-12.  Larger systems keep the per-step path.
+    wl = cases()[name]()
+    res = {}
+    for sc in (0, 1):
+        c = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10, small_cycle=sc)
+        try:
+            rc, U, phi, lam, info = arb.arb_solve(c, wl.F, u_slip=wl.u_slip)
+        finally:
+            arb.arb_destroy(c)
+        assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
+        assert info["rel_residual"] <= 1e-10
+        res[sc] = (np.concatenate([np.ravel(lam), np.ravel(U), np.ravel(phi)]), info)
+    (y0, i0), (y1, i1) = res[0], res[1]
+    print(f"{name}: one launch {i0['iterations']} iterations in {i0['one_launch_cycles']} "
+          f"cycles, {i0['t_solve_ms']:.2f} ms; per step {i1['iterations']}, "
+          f"{i1['t_solve_ms']:.2f} ms; difference {rel(y0, y1):.1e}", flush=True)
+    assert (i0["one_launch_cycles"] >= 1) == (wl.N <= 128) and i1["one_launch_cycles"] == 0
+    assert abs(i0["iterations"] - i1["iterations"]) <= 1
+    for key in outputs(wl, y1):
+        assert rel(outputs(wl, y0)[key], outputs(wl, y1)[key]) <= 1e-12, key
 
 
 @pytest.mark.parametrize("cfg", ["bacteria1024", "diatoms256"])
