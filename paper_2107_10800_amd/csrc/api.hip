@@ -207,6 +207,7 @@ int build_topology(arb_ctx *ctx) {
     TRY(upload(ctx, ctx->row_m, rm.data(), Nc, s));
     TRY(upload(ctx, ctx->brow_ptr, bptr.data(), M + 1, s));
     TRY(upload(ctx, ctx->brow_ent, bent.data(), bent.size(), s));
+    ctx->n_brow_ent = (int)bent.size();
     TRY(upload(ctx, ctx->asm_body_ptr, abp.data(), A + 1, s));
     TRY(upload(ctx, ctx->asm_bodies, ab.data(), M, s));
     TRY(upload(ctx, ctx->asm_row_ptr, arp.data(), A + 1, s));
@@ -283,7 +284,9 @@ int pair_order(arb_ctx *ctx, hipStream_t s) {
     const int N = ctx->N;
     const int nt = (N + 63) / 64;
     ctx->psorted = false;
-    if (nt < 8) return 0;
+    // only the dense multiblob products read the sorted copy
+    if (nt < 8 || ctx->opt.model == ARB_MODEL_SINGLE_BLOB || ctx->opt.pair_kernel == ARB_PAIR_FMM)
+        return 0;
     std::vector<float4> box(2 * (size_t)nt);
     HIPCHK(hipMemcpyAsync(box.data(), ctx->tbox.p, box.size() * sizeof(float4),
                           hipMemcpyDeviceToHost, s));
@@ -298,10 +301,13 @@ int pair_order(arb_ctx *ctx, hipStream_t s) {
                           double(b.z - a.z) * (b.z - a.z));
     }
     mean /= nt;
-    const double dom = std::sqrt(double(hi[0] - lo[0]) * (hi[0] - lo[0]) +
-                                 double(hi[1] - lo[1]) * (hi[1] - lo[1]) +
-                                 double(hi[2] - lo[2]) * (hi[2] - lo[2]));
-    if (!(mean > 0.25 * dom)) return 0;
+    // the diagonal of a compact tile: a cube holding 64 blobs at the domain's mean
+    // density (positions in units of a); sort when the tiles as given are much
+    // larger (random order, or bodies whose tiles straddle distant bodies)
+    double vol = 1.0;
+    for (int c = 0; c < 3; ++c) vol *= std::max(double(hi[c] - lo[c]), 2.0);
+    const double compact = std::sqrt(3.0) * std::cbrt(64.0 * vol / N);
+    if (!(mean > 2.0 * compact)) return 0;
     std::vector<double> pos(3 * (size_t)N);
     HIPCHK(hipMemcpyAsync(pos.data(), ctx->pos.p, pos.size() * sizeof(double),
                           hipMemcpyDeviceToHost, s));
@@ -332,9 +338,11 @@ int pair_order(arb_ctx *ctx, hipStream_t s) {
     HIPCHK(ctx->his.ensure((size_t)N * sizeof(float4)));
     HIPCHK(ctx->los.ensure((size_t)N * sizeof(float4)));
     HIPCHK(ctx->tboxs.ensure(2 * (size_t)nt * sizeof(float4)));
+    // the sorted copy is centred in x and y: smaller |x| lets more tile pairs take
+    // the far path (its criterion scales with the largest |coordinate|)
     arb::prep_positions(s, N, ctx->pos.as<double>(), ctx->opt.a, ctx->p64s.as<double4>(),
                         ctx->his.as<float4>(), ctx->los.as<float4>(), ctx->tboxs.as<float4>(),
-                        ctx->pperm.as<int>());
+                        ctx->pperm.as<int>(), 0.5 * (pl[0] + ph[0]), 0.5 * (pl[1] + ph[1]));
     ctx->psorted = true;
     return 0;
 }
@@ -964,12 +972,15 @@ int krylov_buffers(arb_ctx *ctx, Krylov &K) {
 
 // Whether a GMRES cycle of this context runs in one workgroup (small.hip): a
 // small multiblob FP64 system with the exact block preconditioner
-bool small_cycle_ok(const arb_ctx *ctx, int prec, int64_t n) {
+arb::SmallSystem small_system(arb_ctx *ctx);
+
+bool small_cycle_ok(arb_ctx *ctx, int prec, int64_t n) {
     return ctx->opt.small_cycle == 0 && ctx->opt.model == ARB_MODEL_MULTIBLOB &&
            prec == ARB_FP64 && ctx->opt.precond == ARB_PC_BLOCK && !ctx->pc_learned &&
            ctx->opt.pair_kernel != ARB_PAIR_FMM && !ctx->prof && ctx->M > 0 &&
            ctx->N <= arb::kSmallCycleN && n <= arb::kSmallArnoldi &&
-           (ctx->n_asm == 0 || ctx->asm_max_rows <= arb::kSmallCycleRows);
+           (ctx->n_asm == 0 || ctx->asm_max_rows <= arb::kSmallCycleRows) &&
+           arb::small_layout(small_system(ctx)).bytes <= arb::kSmallCycleLds;
 }
 
 arb::SmallSystem small_system(arb_ctx *ctx) {
@@ -1003,6 +1014,16 @@ arb::SmallSystem small_system(arb_ctx *ctx) {
     S.asm_rows = P.asm_rows;
     S.asm_mat_off = P.asm_mat_off;
     S.G = P.G;
+    for (int p = 0; p < S.M; ++p) {
+        const int64_t mm = 3 * (int64_t)(ctx->h_blob_off[p + 1] - ctx->h_blob_off[p]);
+        S.n_minv += mm * mm;
+        S.n_z += 6 * mm;
+    }
+    for (int a = 0; a < S.A; ++a) {
+        const int64_t na = ctx->h_asm_row_ptr[a + 1] - ctx->h_asm_row_ptr[a];
+        S.n_g += na * na;
+    }
+    S.n_brow_ent = ctx->n_brow_ent;
     int tpt = 1;  // threads per target: the 512 threads in about one pass
     while (tpt < 64 && 2 * tpt * S.N <= 512) tpt *= 2;
     S.tpt = tpt;
@@ -1184,7 +1205,8 @@ int gmres_core(arb_ctx *ctx, hipStream_t s, Krylov &K, const double *rhs, double
         const int budget = std::min(m, max_iter - *total);
         double last_est = beta;
         if (one_launch) {
-            arb::gmres_small_cycle(s, SS, m, budget, target, K.V, K.H, K.cs, K.sn, K.g, K.steps);
+            HIPCHK(arb::gmres_small_cycle(s, SS, m, budget, target, K.V, K.H, K.cs, K.sn, K.g,
+                                          K.steps));
             HIPCHK(hipMemcpyAsync(pin_step, K.steps, (2 * (size_t)m + 1) * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));

@@ -119,8 +119,12 @@ void fmm_apply6(const FmmState &F, hipStream_t s, bool fp64, const double *x6, d
 // box (may be null): 2 float4 per 64-blob tile, its bounding box and largest
 // |coordinate| (pair_sym's far test)
 // perm (may be null): entry i of the outputs holds blob perm[i]
+// (sx, sy) is subtracted from every position (the products do not depend on a
+// shift parallel to the wall; a centred domain keeps |x| and the FP32 rounding
+// of the split positions small)
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
-                    float4 *hi, float4 *lo, float4 *box, const int *perm);
+                    float4 *hi, float4 *lo, float4 *box, const int *perm, double sx = 0.0,
+                    double sy = 0.0);
 // device address of the allocation-free entry point's scratch array for the
 // current device (noalloc.hip), looked up once per device; 0 when known
 int noalloc_setup(int device);
@@ -219,6 +223,10 @@ void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos_aos,
 struct SmallSystem {
     int N = 0, M = 0, Nc = 0, A = 0, tpt = 1;
     int64_t n = 0;
+    // sizes of the arrays staged in LDS: M_pp^-1 and Z_p of all bodies, G~ of all
+    // assemblies (doubles), the bodies' row entries
+    int64_t n_minv = 0, n_z = 0, n_g = 0;
+    int n_brow_ent = 0;
     bool wall = false;
     double a = 1.0, scale = 0.0;  // blob radius, 1 / (8 pi eta)
     const double4 *p64 = nullptr;
@@ -232,14 +240,75 @@ struct SmallSystem {
     const int64_t *asm_mat_off = nullptr;
     const double *G = nullptr;
 };
+// where gmres_small_cycle keeps everything in LDS, in units of 8 bytes for the
+// doubles (and 64-bit offsets) and of 4 bytes for the ints after them
+struct SmallLayout {
+    size_t vs, zs, ws, us, w6, yv, p64, dvec, minv, Z, Nt, G, crow, mat_off, z_off, asm_mat_off,
+        ints;
+    size_t bob, blob_off, brow_ptr, brow_ent, row_p, row_q, asm_row_ptr, asm_rows, slot_a, perm,
+        n_ints;
+    size_t bytes;
+};
+__host__ __device__ inline SmallLayout small_layout(const SmallSystem &S) {
+    SmallLayout L;
+    size_t o = 0;
+    auto d = [&](size_t cnt) {
+        const size_t at = (o + 1) & ~(size_t)1;  // 16-byte aligned
+        o = at + cnt;
+        return at;
+    };
+    L.vs = d(S.n);
+    L.zs = d(S.n);
+    L.ws = d(S.n);
+    L.us = d(6 * (size_t)S.M);
+    L.w6 = d(6 * (size_t)S.M);
+    L.yv = d(S.Nc);
+    L.p64 = d(4 * (size_t)S.N);
+    L.dvec = d(3 * (size_t)S.N);
+    L.minv = d(S.n_minv);
+    L.Z = d(S.n_z);
+    L.Nt = d(36 * (size_t)S.M);
+    L.G = d(S.n_g);
+    L.crow = d(12 * (size_t)S.Nc);
+    L.mat_off = d(S.M + 1);
+    L.z_off = d(S.M + 1);
+    L.asm_mat_off = d(S.A + 1);
+    L.ints = o;
+    size_t q = 0;
+    L.bob = q;
+    q += S.N;
+    L.blob_off = q;
+    q += S.M + 1;
+    L.brow_ptr = q;
+    q += S.M + 1;
+    L.brow_ent = q;
+    q += S.n_brow_ent;
+    L.row_p = q;
+    q += S.Nc;
+    L.row_q = q;
+    q += S.Nc;
+    L.asm_row_ptr = q;
+    q += S.A + 1;
+    L.asm_rows = q;
+    q += S.Nc;
+    L.slot_a = q;
+    q += S.Nc;
+    L.perm = q;
+    q += S.perm ? S.N : 0;
+    L.n_ints = q;
+    L.bytes = 8 * L.ints + 4 * L.n_ints;
+    return L;
+}
+constexpr size_t kSmallCycleLds = 144 * 1024;  // arena limit (bytes)
 constexpr int kSmallCycleN = 128;      // blobs
 constexpr int kSmallCycleRows = 64;    // rows of the largest assembly
 // Arnoldi steps 0 .. budget-1 of one cycle from v_0 = V[0..n) (Hbar, cs, sn, g as
 // the per-step path leaves them); steps[2 j] = h_{j+1,j}, steps[2 j + 1] = the
 // residual estimate, steps[2 m] = the steps taken (the cycle ends early when the
 // estimate reaches target or h_{j+1,j} = 0)
-void gmres_small_cycle(hipStream_t s, const SmallSystem &S, int m, int budget, double target,
-                       double *V, double *Hbar, double *cs, double *sn, double *g, double *steps);
+hipError_t gmres_small_cycle(hipStream_t s, const SmallSystem &S, int m, int budget,
+                             double target, double *V, double *Hbar, double *cs, double *sn,
+                             double *g, double *steps);
 // max_m = largest 3 n_p of the batch
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
 int64_t precond_dinv_size(int64_t n_blobs, int M);
@@ -413,6 +482,7 @@ struct arb_ctx {
         asm_rows, asm_mat_off, mat_off, z_off, mats, minv, ldiag, dinv, Z, Nt, G, S, status, pctmp, lcorr, stmp,
         asm_dinv, asm_fail, body_pinv;
     int asm_max_rows = 0;  // largest assembly (constraint rows)
+    int n_brow_ent = 0;    // entries of the bodies' constraint-row lists
     // generic scratch for host entry points and the solver
     arb::DevBuf s_in, s_out, s_aux, s_pos;
     arb::DevBuf tbox;  // per 64-blob tile of the state's positions: bounding box (prep_positions)

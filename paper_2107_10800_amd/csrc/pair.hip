@@ -36,17 +36,17 @@ namespace arb {
 // max y, max z, 0) of the hi positions, for the symmetric kernel's far test.
 // perm (may be null): entry i holds blob perm[i] (the pair kernels' blob order)
 __global__ void prep_positions_kernel(int N, const double *__restrict__ pos, double inv_a,
-                                      double4 *__restrict__ p64, float4 *__restrict__ hi,
-                                      float4 *__restrict__ lo, float4 *__restrict__ box,
-                                      const int *__restrict__ perm) {
+                                      double sx, double sy, double4 *__restrict__ p64,
+                                      float4 *__restrict__ hi, float4 *__restrict__ lo,
+                                      float4 *__restrict__ box, const int *__restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = i < N;
     float xh = 0.f, yh = 0.f, zh = 0.f;
     if (ok) {
         const int b = perm ? perm[i] : i;
-        p64[i] = make_double4(pos[3 * b], pos[3 * b + 1], pos[3 * b + 2], 2.0 * pos[3 * b + 2]);
-        const double x = pos[3 * b] * inv_a, y = pos[3 * b + 1] * inv_a,
-                     z = pos[3 * b + 2] * inv_a;
+        const double px = pos[3 * b] - sx, py = pos[3 * b + 1] - sy, pz = pos[3 * b + 2];
+        p64[i] = make_double4(px, py, pz, 2.0 * pz);
+        const double x = px * inv_a, y = py * inv_a, z = pz * inv_a;
         xh = (float)x;
         yh = (float)y;
         zh = (float)z;
@@ -237,10 +237,10 @@ __global__ void wall_check_kernel(int N, const double4 *__restrict__ p64, double
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void prep_positions(hipStream_t s, int N, const double *pos_aos, double a, double4 *p64,
-                    float4 *hi, float4 *lo, float4 *box, const int *perm) {
+                    float4 *hi, float4 *lo, float4 *box, const int *perm, double sx, double sy) {
     if (N <= 0) return;
-    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, p64, hi, lo, box,
-                                                       perm);
+    prep_positions_kernel<<<nblk(N, 256), 256, 0, s>>>(N, pos_aos, 1.0 / a, sx, sy, p64, hi, lo,
+                                                       box, perm);
 }
 
 int heuristic_slices(int N) {

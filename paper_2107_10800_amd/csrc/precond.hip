@@ -325,16 +325,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
                 break;
             }
             const double inv = 1.0 / d;
+            // the pivot-row factor of this thread's column, then its four entries
+            // (loads in bounds and unconditional; stores only below the pivot)
+            const bool right = c > j;
+            double *X = right ? Dk : Wi;
+            const double pj = (right ? Dk[c * kLd + j] : Wi[j * kLd + c]) * inv;
+            double lij[4], xv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = (tid >> 5) + 8 * q;
-                if (i > j && i < nb) {
-                    const double lij = Dk[i * kLd + j] * inv;
-                    if (c > j && c <= i)
-                        Dk[i * kLd + c] -= lij * Dk[c * kLd + j];
-                    else if (c <= j)
-                        Wi[i * kLd + c] -= lij * Wi[j * kLd + c];
-                }
+                lij[q] = Dk[i * kLd + j];
+                xv[q] = X[i * kLd + c];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = (tid >> 5) + 8 * q;
+                if (i > j && i < nb && (!right || c <= i)) X[i * kLd + c] = xv[q] - lij[q] * pj;
             }
             __syncthreads();
         }
@@ -910,10 +916,10 @@ __global__ __launch_bounds__(256) void pc_asm_pinv_kernel(
     }
 }
 
-// Assemblies of at most kAsmSmall rows, one workgroup each, everything in LDS
-// (dynamic: S and E, n (n + 1) doubles each, and the staged rows, for n rows of
-// the largest assembly):
-//   S = C_a N~ C_a^T (lower triangle, a column per thread);
+// Assemblies of at most kAsmSmall rows, one workgroup of 1,024 threads each,
+// everything in LDS (dynamic: S and E, n (n + 1) doubles each, the staged rows and
+// N~_b c per row, for n rows of the largest assembly):
+//   S = C_a N~ C_a^T (lower triangle, an entry per thread);
 //   elimination in outer-product form (row i -= l_ij row j, l_ij = S_ij / S_jj,
 //   one barrier per pivot; pivot test relative to the largest diagonal entry),
 //   the same row operations applied to the identity in E, which becomes the unit
@@ -921,7 +927,9 @@ __global__ __launch_bounds__(256) void pc_asm_pinv_kernel(
 //   G~ = S^-1 = E^T D^-1 E, each entry by one thread.
 // A failed pivot flags the assembly for the pseudo-inverse kernel.
 constexpr int kAsmSmall = 64;
-__global__ __launch_bounds__(256) void pc_asm_small_kernel(
+constexpr int kAsmThreads = 1024;
+constexpr int kAsmSlots = kAsmSmall * kAsmSmall / kAsmThreads;  // rows per thread
+__global__ __launch_bounds__(kAsmThreads) void pc_asm_small_kernel(
     const int *__restrict__ asm_row_ptr, const int *__restrict__ asm_rows,
     const int64_t *__restrict__ asm_mat_off, const int *__restrict__ row_p,
     const int *__restrict__ row_q, const double *__restrict__ crow, const double *__restrict__ Nt,
@@ -930,7 +938,8 @@ __global__ __launch_bounds__(256) void pc_asm_small_kernel(
     extern __shared__ double sm[];
     const int ld = max_rows + 1;
     double *S = sm, *E = S + (size_t)max_rows * ld, *cl = E + (size_t)max_rows * ld;
-    int *bl = reinterpret_cast<int *>(cl + 12 * (size_t)max_rows);
+    double *tl = cl + 12 * (size_t)max_rows;  // N~_b c for both sides of each row
+    int *bl = reinterpret_cast<int *>(tl + 12 * (size_t)max_rows);
     __shared__ double tol;
     __shared__ double invd[kAsmSmall];
     const int a = blockIdx.x, tid = threadIdx.x;
@@ -938,13 +947,36 @@ __global__ __launch_bounds__(256) void pc_asm_small_kernel(
     if (tid == 0) fail[a] = 0;
     if (na == 0 || status[0] != 0) return;
     asm_stage_rows(r0, na, asm_rows, row_p, row_q, crow, cl, bl);
-    for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += 256) {
+    for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += kAsmThreads) {
         const int i = idx >> 6, c = idx & 63;
         if (i < na && c <= i) E[i * ld + c] = i == c ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int l = tid; l < na; l += 256)
-        asm_column(l, na, cl, bl, Nt, [&](int k, double v) { S[k * ld + l] = v; });
+    // t = N~_b c per row and side (a thread per entry), then every entry of the
+    // lower triangle of S = C N~ C^T at once
+    for (int idx = tid; idx < 12 * na; idx += kAsmThreads) {
+        const int l = idx / 12, sd = (idx / 6) & 1, u = idx % 6;
+        const int b = bl[2 * l + sd];
+        double v = 0.0;
+        if (b >= 0)
+            for (int w = 0; w < 6; ++w) v += Nt[36 * (size_t)b + u * 6 + w] * cl[12 * l + 6 * sd + w];
+        tl[idx] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kAsmSmall * kAsmSmall; idx += kAsmThreads) {
+        const int k = idx >> 6, l = idx & 63;
+        if (k >= na || l > k) continue;
+        double sum = 0.0;
+        for (int sk = 0; sk < 2; ++sk) {
+            const int bk = bl[2 * k + sk];
+            if (bk < 0) continue;
+            for (int sl = 0; sl < 2; ++sl)
+                if (bl[2 * l + sl] == bk)
+                    for (int u = 0; u < 6; ++u)
+                        sum += cl[12 * k + 6 * sk + u] * tl[12 * l + 6 * sl + u];
+        }
+        S[k * ld + l] = sum;
+    }
     __syncthreads();
     if (tid == 0) {
         double dmax = 0.0;
@@ -952,8 +984,8 @@ __global__ __launch_bounds__(256) void pc_asm_small_kernel(
         tol = 1e-12 * dmax;
     }
     __syncthreads();
-    // thread tid owns column c = tid % 64 of rows i = tid / 64 + 4 q (q < 16): the
-    // column-c entries of row j are read once per pivot, the rows' entries all
+    // thread tid owns column c = tid % 64 of rows i = tid / 64 + 16 q (q < kAsmSlots):
+    // the column-c entries of row j are read once per pivot, the rows' entries all
     // issued before they are updated
     const int c = tid & 63, i0 = tid >> 6;
     for (int j = 0; j < na; ++j) {
@@ -963,37 +995,49 @@ __global__ __launch_bounds__(256) void pc_asm_small_kernel(
             return;
         }
         const double inv = 1.0 / d;
-        const bool right = c > j;  // S entry (right of the pivot column), else E entry
-        const double pj = c < na ? (right ? S[c * ld + j] : E[j * ld + c]) : 0.0;
-        double *X = right ? S : E;
+        if (c < na) {
+            const bool right = c > j;  // S entry (right of the pivot column), else E entry
+            const double pj = (right ? S[c * ld + j] : E[j * ld + c]) * inv;
+            double *X = right ? S : E;
+            // every load in bounds (rows clamped to the matrix) and issued before
+            // the updates, which only the slots below the pivot row store
+            double sij[kAsmSlots], xv[kAsmSlots];
 #pragma unroll
-        for (int q = 0; q < kAsmSmall / 4; ++q) {
-            const int i = i0 + 4 * q;
-            if (i > j && i < na && c <= i) X[i * ld + c] -= S[i * ld + j] * inv * pj;
+            for (int q = 0; q < kAsmSlots; ++q) {
+                const int i = min(i0 + 16 * q, na - 1);
+                sij[q] = S[i * ld + j];
+                xv[q] = X[i * ld + c];
+            }
+#pragma unroll
+            for (int q = 0; q < kAsmSlots; ++q) {
+                const int i = i0 + 16 * q;
+                if (i > j && i < na && c <= i) X[i * ld + c] = xv[q] - sij[q] * pj;
+            }
         }
         __syncthreads();
     }
     if (tid < na) invd[tid] = 1.0 / S[tid * ld + tid];
     __syncthreads();
     // G~_ij = sum_k E_ki E_kj / D_k over k >= max(i, j): thread tid takes column
-    // j = tid % 64 of rows i = tid / 64 + 4 q, one pass over k
+    // j = tid % 64 of rows i = tid / 64 + 16 q, one pass over k
     double *G = Gbuf + asm_mat_off[a];
     const int j = c;
-    double acc[kAsmSmall / 4];
+    double acc[kAsmSlots];
 #pragma unroll
-    for (int q = 0; q < kAsmSmall / 4; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kAsmSlots; ++q) acc[q] = 0.0;
     if (j < na)
         for (int k = j; k < na; ++k) {
             const double ekj = E[k * ld + j] * invd[k];
 #pragma unroll
-            for (int q = 0; q < kAsmSmall / 4; ++q) {
-                const int i = i0 + 4 * q;
-                if (i <= k) acc[q] += E[k * ld + i] * ekj;
+            for (int q = 0; q < kAsmSlots; ++q) {
+                const int i = i0 + 16 * q;
+                const double eki = E[k * ld + min(i, k)];  // in bounds; used for i <= k
+                acc[q] += i <= k ? eki * ekj : 0.0;
             }
         }
 #pragma unroll
-    for (int q = 0; q < kAsmSmall / 4; ++q) {
-        const int i = i0 + 4 * q;
+    for (int q = 0; q < kAsmSlots; ++q) {
+        const int i = i0 + 16 * q;
         if (i < na && j < na) G[(size_t)i * na + j] = acc[q];
     }
 }
@@ -1550,14 +1594,14 @@ hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
     if (P.A <= 0) return hipSuccess;
     const int nmax = std::max(P.asm_max_rows, 1);
     if (nmax <= kAsmSmall && P.asm_fail) {
-        const size_t lds = (2 * (size_t)nmax * (nmax + 1) + 12 * (size_t)nmax) * sizeof(double) +
+        const size_t lds = (2 * (size_t)nmax * (nmax + 1) + 24 * (size_t)nmax) * sizeof(double) +
                            2 * (size_t)nmax * sizeof(int);
         const hipError_t e = hipFuncSetAttribute(
             (const void *)pc_asm_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        pc_asm_small_kernel<<<P.A, 256, lds, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off,
-                                                  P.row_p, P.row_q, P.crow, P.Nt, P.G,
-                                                  P.asm_fail, P.status, nmax);
+        pc_asm_small_kernel<<<P.A, kAsmThreads, lds, s>>>(P.asm_row_ptr, P.asm_rows,
+                                                          P.asm_mat_off, P.row_p, P.row_q, P.crow,
+                                                          P.Nt, P.G, P.asm_fail, P.status, nmax);
         pc_asm_pinv_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
                                                P.row_q, P.crow, P.Nt, P.S, P.G, P.asm_fail,
                                                P.status);

@@ -6,7 +6,8 @@
 // separated by workgroup barriers, and the stopping test on the residual
 // estimate is taken on the device.  A system of a few hundred unknowns then
 // costs a few microseconds per step instead of ten launches and a host
-// round trip.  The arithmetic is that of the per-step kernels with other
+// round trip; the data a step reads sit in LDS (a step is a chain of short
+// phases, each of which would otherwise wait on memory).  The arithmetic is that of the per-step kernels with other
 // summation orders.
 #include "common.h"
 #include "rpy_device.h"
@@ -23,10 +24,10 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
-// the Givens update of the new Hessenberg column (as arnoldi_post_dev in krylov.hip)
-__device__ void givens_column(int j, int m, const double *h1, const double *h2, double hn2,
-                              double *Hbar, double *cs, double *sn, double *g, double *out) {
-    double *col = Hbar + (int64_t)j * (m + 1);
+// the Givens update of the new Hessenberg column (as arnoldi_post_dev in krylov.hip),
+// on LDS copies of the column, the rotations and g
+__device__ void givens_column(int j, const double *h1, const double *h2, double hn2, double *col,
+                              double *cs, double *sn, double *g, double *out) {
     for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
     const double hn = sqrt(hn2);
     col[j + 1] = hn;
@@ -46,107 +47,147 @@ __device__ void givens_column(int j, int m, const double *h1, const double *h2, 
     out[1] = fabs(g[j + 1]);
 }
 
+template <class T>
+__device__ __forceinline__ T *stage(const T *src, size_t cnt, T *dst) {
+    for (size_t t = threadIdx.x; t < cnt; t += kThreads) dst[t] = src[t];
+    return dst;
+}
+
+// Everything a step reads is staged once in the dynamic LDS arena (small_layout):
+// the state (positions, d_i), the preconditioner (M_pp^-1, Z_p, N~_p, G~_a),
+// the constraint rows and the index arrays; v_j, z = P^-1 v_j, w = A z and U^
+// live there too.  Only the Krylov basis V (written once per step, read by the
+// Gram-Schmidt passes) and the Hessenberg data stay in memory.
 template <bool WALL>
 __global__ __launch_bounds__(kThreads) void gmres_small_cycle_kernel(
-    SmallSystem S, int m, int budget, double target, double *__restrict__ V,
+    SmallSystem Sg, int m, int budget, double target, double *__restrict__ V,
     double *__restrict__ Hbar, double *__restrict__ cs,
     double *__restrict__ sn, double *__restrict__ g, double *__restrict__ steps) {
-    // v_j, z = P^-1 v_j and w = A z in LDS (the basis V stays in memory); U^ too
-    __shared__ double vs[kSmallArnoldi], zs[kSmallArnoldi], ws[kSmallArnoldi];
-    __shared__ double us[6 * kSmallCycleN];
+    extern __shared__ double arena[];
     __shared__ double hs[2][kMaxRestart + 1];
+    __shared__ double col[kMaxRestart + 2], cs_s[kMaxRestart + 1], sn_s[kMaxRestart + 1],
+        g_s[kMaxRestart + 2];
     __shared__ double red[kWaves];
     __shared__ double hn_est[2];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const SmallLayout L = small_layout(Sg);
+    int *ia = reinterpret_cast<int *>(arena + L.ints);
+    SmallSystem S = Sg;
+    S.p64 = stage(Sg.p64, Sg.N, reinterpret_cast<double4 *>(arena + L.p64));
+    S.dvec = stage(Sg.dvec, 3 * (size_t)Sg.N, arena + L.dvec);
+    S.minv = stage(Sg.minv, Sg.n_minv, arena + L.minv);
+    S.Z = stage(Sg.Z, Sg.n_z, arena + L.Z);
+    S.Nt = stage(Sg.Nt, 36 * (size_t)Sg.M, arena + L.Nt);
+    S.G = stage(Sg.G, Sg.n_g, arena + L.G);
+    S.crow = stage(Sg.crow, 12 * (size_t)Sg.Nc, arena + L.crow);
+    S.mat_off = stage(Sg.mat_off, Sg.M + 1, reinterpret_cast<int64_t *>(arena + L.mat_off));
+    S.z_off = stage(Sg.z_off, Sg.M + 1, reinterpret_cast<int64_t *>(arena + L.z_off));
+    S.asm_mat_off =
+        Sg.A > 0 ? stage(Sg.asm_mat_off, Sg.A + 1, reinterpret_cast<int64_t *>(arena + L.asm_mat_off))
+                 : nullptr;
+    S.bob = stage(Sg.bob, Sg.N, ia + L.bob);
+    S.blob_off = stage(Sg.blob_off, Sg.M + 1, ia + L.blob_off);
+    S.brow_ptr = Sg.Nc > 0 ? stage(Sg.brow_ptr, Sg.M + 1, ia + L.brow_ptr) : nullptr;
+    S.brow_ent = Sg.Nc > 0 ? stage(Sg.brow_ent, Sg.n_brow_ent, ia + L.brow_ent) : nullptr;
+    S.row_p = stage(Sg.row_p, Sg.Nc, ia + L.row_p);
+    S.row_q = stage(Sg.row_q, Sg.Nc, ia + L.row_q);
+    S.asm_row_ptr = Sg.A > 0 ? stage(Sg.asm_row_ptr, Sg.A + 1, ia + L.asm_row_ptr) : nullptr;
+    S.asm_rows = Sg.A > 0 ? stage(Sg.asm_rows, Sg.Nc, ia + L.asm_rows) : nullptr;
+    S.perm = Sg.perm ? stage(Sg.perm, Sg.N, ia + L.perm) : nullptr;
+    double *vs = arena + L.vs, *zs = arena + L.zs, *ws = arena + L.ws, *us = arena + L.us;
+    double *w6 = arena + L.w6, *yv = arena + L.yv;
+    int *slot_a = ia + L.slot_a;  // assembly of each slot of asm_rows
+    for (int a = tid; a < Sg.A; a += kThreads)
+        for (int sl = Sg.asm_row_ptr[a]; sl < Sg.asm_row_ptr[a + 1]; ++sl) slot_a[sl] = a;
     const int64_t n = S.n;
     const CoefD coef = make_coef<CoefD, double>(S.a);
     const size_t o_u = 3 * (size_t)S.N, o_phi = o_u + 6 * (size_t)S.M;
     int k = 0;
     for (int t = tid; t < n; t += kThreads) vs[t] = V[t];
+    for (int t = tid; t <= m; t += kThreads) g_s[t] = g[t];
     __syncthreads();
     for (int j = 0; j < budget; ++j) {
         const double *r = vs;
         double *z = zs;
-        // ---- z = P^-1 v_j: body blocks (one wavefront per body) -------------------
-        for (int p = wave; p < S.M; p += kWaves) {
-            const int b0 = S.blob_off[p], mm = 3 * (S.blob_off[p + 1] - b0);
+        // ---- z = P^-1 v_j, every phase a flat loop (a thread per row, per body and
+        // component, or per constraint row), no wavefront reductions -----------------
+        // blob rows: M_pp^-1 r_lambda (symmetric: column i, consecutive threads)
+        for (int R = tid; R < 3 * S.N; R += kThreads) {
+            const int p = S.bob[R / 3], b0 = S.blob_off[p], mm = 3 * (S.blob_off[p + 1] - b0);
+            const int i = R - 3 * b0;
             const double *Mi = S.minv + S.mat_off[p];
-            const double *Zp = S.Z + S.z_off[p];
             const double *rl = r + 3 * (size_t)b0;
-            double acc[6] = {0, 0, 0, 0, 0, 0};
-            for (int i = lane; i < mm; i += kWave) {
-                double s = 0.0;  // M_pp^-1 is symmetric: column i, consecutive lanes
-                for (int kk = 0; kk < mm; ++kk) s += Mi[(size_t)kk * mm + i] * rl[kk];
-                z[3 * (size_t)b0 + i] = s;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) acc[c] += Zp[(size_t)i * 6 + c] * rl[i];
-            }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] = wsum(acc[c]) + r[o_u + 6 * (size_t)p + c];
-            if (lane < 6) {
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) s += S.Nt[36 * (size_t)p + lane * 6 + c] * acc[c];
-                us[6 * p + lane] = -s;
-            }
+            double s = 0.0;
+            for (int kk = 0; kk < mm; ++kk) s += Mi[(size_t)kk * mm + i] * rl[kk];
+            z[R] = s;
         }
-        __syncthreads();
-        // assemblies (one wavefront each, at most one row per lane): phi = G~ (r_phi - C U^)
-        for (int a = wave; a < S.A; a += kWaves) {
-            const int r0 = S.asm_row_ptr[a], na = S.asm_row_ptr[a + 1] - r0;
-            double y = 0.0;
-            int rk = 0;
-            if (lane < na) {
-                rk = S.asm_rows[r0 + lane];
-                const double *c = S.crow + 12 * (size_t)rk;
-                const double *Up = us + 6 * S.row_p[rk];
-                double s = 0.0;
-                for (int u = 0; u < 6; ++u) s += c[u] * Up[u];
-                const int q = S.row_q[rk];
-                if (q >= 0)
-                    for (int u = 0; u < 6; ++u) s += c[6 + u] * us[6 * q + u];
-                y = r[o_phi + rk] - s;
-            }
-            const double *Ga = S.G + S.asm_mat_off[a];
-            double phi = 0.0;
-            for (int l = 0; l < na; ++l) {
-                const double yl = __shfl(y, l);
-                if (lane < na) phi += Ga[(size_t)lane * na + l] * yl;
-            }
-            if (lane < na) z[o_phi + rk] = phi;
-        }
-        __syncthreads();
-        // bodies again: U = U^ + N~ C^T phi, lambda += Z U
-        for (int p = wave; p < S.M; p += kWaves) {
-            double f[6] = {0, 0, 0, 0, 0, 0};
-            if (S.Nc > 0)
-                for (int e = S.brow_ptr[p] + lane; e < S.brow_ptr[p + 1]; e += kWave) {
-                    const int ent = S.brow_ent[e], row = ent >> 1, side = ent & 1;
-                    const double ph = z[o_phi + row];
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) f[c] += ph * S.crow[12 * (size_t)row + 6 * side + c];
-                }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) f[c] = wsum(f[c]);
-            double U[6];
-#pragma unroll
-            for (int c1 = 0; c1 < 6; ++c1) {
-                double s = us[6 * p + c1];
-#pragma unroll
-                for (int c2 = 0; c2 < 6; ++c2) s += S.Nt[36 * (size_t)p + 6 * c1 + c2] * f[c2];
-                U[c1] = s;
-            }
-#pragma unroll
-            for (int c = 0; c < 6; ++c)
-                if (lane == c) z[o_u + 6 * (size_t)p + c] = U[c];
+        // w6 = Z_p^T r_lambda + r_U per body and component
+        for (int e = tid; e < 6 * S.M; e += kThreads) {
+            const int p = e / 6, c = e - 6 * p;
             const int b0 = S.blob_off[p], mm = 3 * (S.blob_off[p + 1] - b0);
             const double *Zp = S.Z + S.z_off[p];
-            for (int i = lane; i < mm; i += kWave) {
-                double s = 0.0;
+            double acc = r[o_u + e];
+            for (int i = 0; i < mm; ++i) acc += Zp[(size_t)i * 6 + c] * r[3 * (size_t)b0 + i];
+            w6[e] = acc;
+        }
+        __syncthreads();
+        // U^ = -N~ w6
+        for (int e = tid; e < 6 * S.M; e += kThreads) {
+            const int p = e / 6, c = e - 6 * p;
+            double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) s += Zp[(size_t)i * 6 + c] * U[c];
-                z[3 * (size_t)b0 + i] += s;
-            }
+            for (int c2 = 0; c2 < 6; ++c2) s += S.Nt[36 * (size_t)p + 6 * c + c2] * w6[6 * p + c2];
+            us[e] = -s;
+        }
+        __syncthreads();
+        // assemblies: y = r_phi - C U^ per row, then phi = G~ y over each assembly's rows
+        for (int kr = tid; kr < S.Nc; kr += kThreads) {
+            const double *c = S.crow + 12 * (size_t)kr;
+            const double *Up = us + 6 * S.row_p[kr];
+            double s = 0.0;
+            for (int u = 0; u < 6; ++u) s += c[u] * Up[u];
+            const int q = S.row_q[kr];
+            if (q >= 0)
+                for (int u = 0; u < 6; ++u) s += c[6 + u] * us[6 * q + u];
+            yv[kr] = r[o_phi + kr] - s;
+        }
+        __syncthreads();
+        for (int sl = tid; sl < S.Nc; sl += kThreads) {
+            const int a = slot_a[sl], r0 = S.asm_row_ptr[a], na = S.asm_row_ptr[a + 1] - r0;
+            const double *Ga = S.G + S.asm_mat_off[a] + (size_t)(sl - r0) * na;
+            double s = 0.0;
+            for (int l = 0; l < na; ++l) s += Ga[l] * yv[S.asm_rows[r0 + l]];
+            z[o_phi + S.asm_rows[sl]] = s;
+        }
+        __syncthreads();
+        // U = U^ + N~ C^T phi: f = C^T phi per body and component, then U
+        for (int e = tid; e < 6 * S.M; e += kThreads) {
+            const int p = e / 6, c = e - 6 * p;
+            double f = 0.0;
+            if (S.Nc > 0)
+                for (int en = S.brow_ptr[p]; en < S.brow_ptr[p + 1]; ++en) {
+                    const int ent = S.brow_ent[en], row = ent >> 1, side = ent & 1;
+                    f += z[o_phi + row] * S.crow[12 * (size_t)row + 6 * side + c];
+                }
+            w6[e] = f;
+        }
+        __syncthreads();
+        for (int e = tid; e < 6 * S.M; e += kThreads) {
+            const int p = e / 6, c = e - 6 * p;
+            double s = us[e];
+#pragma unroll
+            for (int c2 = 0; c2 < 6; ++c2) s += S.Nt[36 * (size_t)p + 6 * c + c2] * w6[6 * p + c2];
+            z[o_u + e] = s;
+        }
+        __syncthreads();
+        // lambda += Z U per blob row
+        for (int R = tid; R < 3 * S.N; R += kThreads) {
+            const int p = S.bob[R / 3], b0 = S.blob_off[p];
+            const double *Zr = S.Z + S.z_off[p] + (size_t)(R - 3 * b0) * 6;
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) s += Zr[c] * z[o_u + 6 * (size_t)p + c];
+            z[R] += s;
         }
         __syncthreads();
         // ---- w = A z into LDS ------------------------------------------------------
@@ -194,33 +235,26 @@ __global__ __launch_bounds__(kThreads) void gmres_small_cycle_kernel(
                 ws[3 * ib + 2] = uz * S.scale - (Up[2] + (Up[3] * d1 - Up[4] * d0));
             }
         }
-        // body rows: -K^T lambda + C^T phi (one wavefront per body)
-        for (int p = wave; p < S.M; p += kWaves) {
-            double f[6] = {0, 0, 0, 0, 0, 0};
-            for (int ib = S.blob_off[p] + lane; ib < S.blob_off[p + 1]; ib += kWave) {
-                const double l0 = z[3 * (size_t)ib], l1 = z[3 * (size_t)ib + 1],
-                             l2 = z[3 * (size_t)ib + 2];
-                const double d0 = S.dvec[3 * (size_t)ib], d1 = S.dvec[3 * (size_t)ib + 1],
-                             d2 = S.dvec[3 * (size_t)ib + 2];
-                f[0] += l0;
-                f[1] += l1;
-                f[2] += l2;
-                f[3] += d1 * l2 - d2 * l1;
-                f[4] += d2 * l0 - d0 * l2;
-                f[5] += d0 * l1 - d1 * l0;
+        // body rows: -K^T lambda + C^T phi per body and component
+        for (int e = tid; e < 6 * S.M; e += kThreads) {
+            const int p = e / 6, c = e - 6 * p;
+            double f = 0.0;
+            for (int ib = S.blob_off[p]; ib < S.blob_off[p + 1]; ++ib) {
+                const double *l = z + 3 * (size_t)ib;
+                const double *dv = S.dvec + 3 * (size_t)ib;
+                // (K^T lambda)_c: the force, or d x lambda
+                f += c < 3 ? l[c]
+                           : (c == 3 ? dv[1] * l[2] - dv[2] * l[1]
+                                     : (c == 4 ? dv[2] * l[0] - dv[0] * l[2]
+                                               : dv[0] * l[1] - dv[1] * l[0]));
             }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) f[c] = -wsum(f[c]);
-            if (lane == 0) {
-                if (S.Nc > 0)
-                    for (int e = S.brow_ptr[p]; e < S.brow_ptr[p + 1]; ++e) {
-                        const int ent = S.brow_ent[e], row = ent >> 1, side = ent & 1;
-                        const double *c = S.crow + 12 * (size_t)row + 6 * side;
-                        const double ph = z[o_phi + row];
-                        for (int c6 = 0; c6 < 6; ++c6) f[c6] += ph * c[c6];
-                    }
-                for (int c = 0; c < 6; ++c) ws[o_u + 6 * (size_t)p + c] = f[c];
-            }
+            f = -f;
+            if (S.Nc > 0)
+                for (int en = S.brow_ptr[p]; en < S.brow_ptr[p + 1]; ++en) {
+                    const int ent = S.brow_ent[en], row = ent >> 1, side = ent & 1;
+                    f += z[o_phi + row] * S.crow[12 * (size_t)row + 6 * side + c];
+                }
+            ws[o_u + e] = f;
         }
         // constraint rows: C U
         for (int kr = tid; kr < S.Nc; kr += kThreads) {
@@ -260,11 +294,12 @@ __global__ __launch_bounds__(kThreads) void gmres_small_cycle_kernel(
         if (tid == 0) {
             double hn2 = 0.0;
             for (int q = 0; q < kWaves; ++q) hn2 += red[q];
-            givens_column(j, m, hs[0], hs[1], hn2, Hbar, cs, sn, g, steps + 2 * j);
-            hn_est[0] = steps[2 * j];
-            hn_est[1] = steps[2 * j + 1];
+            givens_column(j, hs[0], hs[1], hn2, col, cs_s, sn_s, g_s, hn_est);
+            steps[2 * j] = hn_est[0];
+            steps[2 * j + 1] = hn_est[1];
         }
         __syncthreads();
+        for (int i = tid; i <= j + 1; i += kThreads) Hbar[(int64_t)j * (m + 1) + i] = col[i];
         const double hn = hn_est[0], est = hn_est[1];
         k = j + 1;
         // the same value in every thread: a uniform exit (non-finite values end the
@@ -281,19 +316,34 @@ __global__ __launch_bounds__(kThreads) void gmres_small_cycle_kernel(
         }
         __syncthreads();
     }
+    // g, and the rotations, for the update after the cycle
+    __syncthreads();
+    for (int t = tid; t <= k; t += kThreads) g[t] = g_s[t];
+    for (int t = tid; t < k; t += kThreads) {
+        cs[t] = cs_s[t];
+        sn[t] = sn_s[t];
+    }
     if (tid == 0) steps[2 * m] = (double)k;
 }
 
 }  // namespace
 
-void gmres_small_cycle(hipStream_t s, const SmallSystem &S, int m, int budget, double target,
-                       double *V, double *Hbar, double *cs, double *sn, double *g, double *steps) {
+hipError_t gmres_small_cycle(hipStream_t s, const SmallSystem &S, int m, int budget,
+                             double target, double *V, double *Hbar, double *cs, double *sn,
+                             double *g, double *steps) {
+    const size_t lds = small_layout(S).bytes;
+    const void *fn = S.wall ? (const void *)gmres_small_cycle_kernel<true>
+                            : (const void *)gmres_small_cycle_kernel<false>;
+    const hipError_t e =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     if (S.wall)
         gmres_small_cycle_kernel<true>
-            <<<1, kThreads, 0, s>>>(S, m, budget, target, V, Hbar, cs, sn, g, steps);
+            <<<1, kThreads, lds, s>>>(S, m, budget, target, V, Hbar, cs, sn, g, steps);
     else
         gmres_small_cycle_kernel<false>
-            <<<1, kThreads, 0, s>>>(S, m, budget, target, V, Hbar, cs, sn, g, steps);
+            <<<1, kThreads, lds, s>>>(S, m, budget, target, V, Hbar, cs, sn, g, steps);
+    return hipGetLastError();
 }
 
 }  // namespace arb
