@@ -81,7 +81,7 @@ HBM_TBS = 8.0
 COPY_CAL = {"copy_fetch_kib": 131091.4, "copy_write_kib": 262144.0, "copy_kib": 262144.0}
 TRAFFIC = {
     # target-parallel kernel: shape = source slices
-    "target": {"src": ("pair.hip", "rpy_device.h"), "sha256_16": "e09d2227e560edfa",
+    "target": {"src": ("pair.hip", "rpy_device.h"), "sha256_16": "022cc0a9700c3711",
                "by_shape": {16: (3858.0, 6144.0), 32: (3858.0, 12288.0),
                             64: (3858.0, 24576.0)}},
     # symmetric kernel: shape = -(source tiles per work item)
