@@ -144,13 +144,22 @@ typedef struct {
                        /* one workgroup, with the stopping test on the device  */
                        /* (default); 1 = one kernel per operation, a host      */
                        /* stopping test per step                               */
+    int    refine_final; /* ARB_FP32C refinement: 0 = once one correction has  */
+                       /* been checked with the FP64 pair sum, a later one is  */
+                       /* accepted without that product when its inner GMRES   */
+                       /* residual plus 10x the FP32 error the checked one     */
+                       /* showed (scaled to the current residual) is within    */
+                       /* tol (default; arb_solve_info.residual_bounded = 1);  */
+                       /* 1 = every solve ends with the FP64 residual of the   */
+                       /* returned iterate                                     */
 } arb_options;
 
 typedef struct {
     int    iterations;      /* Arnoldi steps over all cycles                   */
     int    restarts;        /* completed cycles                                */
     double rel_residual;    /* ||b - A y|| / ||b|| of the returned iterate with
-                               the FP64 pair sum (the stopping test)          */
+                               the FP64 pair sum (the stopping test), or the
+                               bound on it when residual_bounded = 1          */
     double rel_residual_fp64; /* the same number (kept for callers that read it) */
     double t_build_ms;      /* preconditioner build                            */
     double t_solve_ms;      /* Krylov iterations incl. final residual          */
@@ -162,6 +171,9 @@ typedef struct {
     int    precond_applies; /* preconditioner applications                     */
     int    one_launch_cycles; /* restart cycles run in one launch (small systems, */
                             /* arb_options.small_cycle)                         */
+    int    residual_bounded; /* 1: ARB_FP32C, the last correction was accepted  */
+                            /* on the bound of arb_options.refine_final = 0     */
+                            /* (rel_residual is that bound, not an FP64 sum)    */
 } arb_solve_info;
 
 /* Work of the fast product's current tree (ARB_PAIR_FMM), filled by

@@ -69,7 +69,7 @@ class arb_options(C.Structure):
                 ("slices", C.c_int), ("pair_kernel", C.c_int), ("graphs", C.c_int),
                 ("model", C.c_int), ("fmm_order", C.c_int), ("fmm_levels", C.c_int),
                 ("fmm_leaf", C.c_int), ("left_precond", C.c_int),
-                ("small_cycle", C.c_int)]
+                ("small_cycle", C.c_int), ("refine_final", C.c_int)]
 
 
 class arb_fmm_stats(C.Structure):
@@ -95,7 +95,7 @@ class arb_solve_info(C.Structure):
                 ("t_solve_ms", C.c_double), ("pinv_used", C.c_int), ("history_len", C.c_int),
                 ("history", C.c_double * 1024), ("products_fp64", C.c_int),
                 ("products_fp32", C.c_int), ("precond_applies", C.c_int),
-                ("one_launch_cycles", C.c_int)]
+                ("one_launch_cycles", C.c_int), ("residual_bounded", C.c_int)]
 
     def to_dict(self):
         return dict(iterations=self.iterations, restarts=self.restarts,
@@ -105,7 +105,8 @@ class arb_solve_info(C.Structure):
                     history=list(self.history[:self.history_len]),
                     products_fp64=self.products_fp64, products_fp32=self.products_fp32,
                     precond_applies=self.precond_applies,
-                    one_launch_cycles=self.one_launch_cycles)
+                    one_launch_cycles=self.one_launch_cycles,
+                    residual_bounded=self.residual_bounded)
 
 
 _lib = None
@@ -227,10 +228,10 @@ def _check(ctx, rc):
 def arb_create(device=0, precision=ARB_FP64, wall=False, eta=1.0, a=1.0, tol=1e-10,
                restart=100, max_iter=1000, precond=ARB_PC_BLOCK, slices=0, pair_kernel=0,
                graphs=0, model=ARB_MODEL_MULTIBLOB, fmm_order=0, fmm_levels=0, fmm_leaf=0,
-               left_precond=0, small_cycle=0):
+               left_precond=0, small_cycle=0, refine_final=0):
     opt = arb_options(device, precision, int(bool(wall)), eta, a, tol, restart, max_iter,
                       precond, slices, pair_kernel, graphs, model, fmm_order, fmm_levels,
-                      fmm_leaf, int(left_precond), int(small_cycle))
+                      fmm_leaf, int(left_precond), int(small_cycle), int(refine_final))
     h = _P()
     rc = load().arb_create(C.byref(h), C.byref(opt))
     if rc < 0:
@@ -589,7 +590,8 @@ def arb_body_mobility(ctx):
 # ------------------------------------------------------------------ convenience
 def context_for(wl, precision=ARB_FP64, tol=1e-10, restart=100, max_iter=1000,
                 precond=ARB_PC_BLOCK, device=0, slices=0, pair_kernel=0, graphs=0, model=None,
-                fmm_order=0, fmm_levels=0, fmm_leaf=0, left_precond=0, small_cycle=0):
+                fmm_order=0, fmm_levels=0, fmm_leaf=0, left_precond=0, small_cycle=0,
+                refine_final=0):
     """Create a context and load a workload (bodies, links, rows, state).  The body
     model defaults to single-blob for workloads that mark themselves so."""
     if model is None:
@@ -598,7 +600,7 @@ def context_for(wl, precision=ARB_FP64, tol=1e-10, restart=100, max_iter=1000,
                      tol=tol, restart=restart, max_iter=max_iter, precond=precond, slices=slices,
                      pair_kernel=pair_kernel, graphs=graphs, model=model, fmm_order=fmm_order,
                      fmm_levels=fmm_levels, fmm_leaf=fmm_leaf, left_precond=left_precond,
-                     small_cycle=small_cycle)
+                     small_cycle=small_cycle, refine_final=refine_final)
     arb_set_bodies(ctx, wl.blob_offset, wl.r_ref, wl.body_type)
     if len(wl.pq):
         arb_set_links(ctx, wl.pq, wl.dl_p, wl.dl_q, wl.dldot_p, wl.dldot_q, wl.nproj, wl.proj)

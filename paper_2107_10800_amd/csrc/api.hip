@@ -23,6 +23,10 @@ constexpr int kMaxAsmRows = 2048;
 constexpr int kMaxCorrRows = 2048;
 // largest articulated body (in bodies) the reconstruction takes: G is M_a^2 doubles
 constexpr int kMaxReconBodies = 2048;
+// FP32 refinement: factor by which the FP32 product's error on the previous
+// correction (relative to its right-hand side) is inflated when it stands in
+// for the error on the last correction
+constexpr double kRefineSafety = 10.0;
 
 // in-place inverse of a symmetric positive definite n x n row-major matrix by
 // Cholesky (A = C C^T, A^-1 = C^-T C^-1); returns nonzero if not SPD
@@ -1327,10 +1331,18 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
     } else {
         // GMRES iterative refinement: the correction equation A d = r is solved by
         // GMRES with the FP32 pair sum to a modest relative tolerance; r = b - A y
-        // is always formed with the FP64 pair sum, so the stopping test is FP64.
+        // is formed with the FP64 pair sum, so the stopping test is FP64.  The
+        // one exception is the last correction (unless refine_final = 1): once a
+        // correction has been checked, the FP32 product's error on it is bounded
+        // by rho = (||r_new|| + e) / ||r_old|| (e the inner GMRES residual, by the
+        // triangle inequality), and a later correction whose inner residual plus
+        // kRefineSafety rho ||r|| is within tol ||b|| is accepted on that bound
+        // without a further FP64 product (right preconditioning only, where the
+        // inner residual is the unpreconditioned one).
         double *rhs = ctx->kt.as<double>();     // current FP64 residual (inner rhs)
         double *d = rhs + n;                     // inner solution
         TRY(dev_norm(ctx, s, K, K.r, 1, &res));
+        double rho = -1.0;  // no correction checked yet
         for (int outer = 0; outer < 30; ++outer) {
             inf->history[inf->history_len < 1024 ? inf->history_len++ : 1023] = res / bnorm;
             if (res <= tol * bnorm || total >= max_iter) break;
@@ -1341,11 +1353,24 @@ int solve_dev(arb_ctx *ctx, const double *F, const double *us, double *y, int wa
             TRY(gmres_core(ctx, s, K, rhs, d, eta * res, ARB_FP32C, max_iter, &total, &restarts,
                            1.0 / bnorm, inf, &rin, true));
             arb::axpby(s, n, 1.0, d, 1.0, y);
+            if (ctx->opt.refine_final == 0 && !ctx->opt.left_precond && rho >= 0.0 &&
+                rin <= eta * res) {
+                const double bound = rin + kRefineSafety * rho * res;
+                if (bound <= tol * bnorm) {
+                    res = bound;
+                    inf->residual_bounded = 1;
+                    inf->history[inf->history_len < 1024 ? inf->history_len++ : 1023] =
+                        res / bnorm;
+                    break;
+                }
+            }
             TRY(system_apply(ctx, s, y, K.r, ARB_FP64));
             ++inf->products_fp64;
             arb::axpby(s, n, 1.0, K.b, -1.0, K.r);
+            const double res_old = res;
             TRY(dev_norm(ctx, s, K, K.r, 1, &res));
             if (!std::isfinite(res)) return fail(ctx, ARB_E_NAN, "refinement residual not finite");
+            rho = (res + rin) / res_old;
         }
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1407,7 +1432,7 @@ int arb_create(arb_ctx **out, const arb_options *opt) {
         (opt->fmm_order != 0 && (opt->fmm_order < 2 || opt->fmm_order > arb::kFmmMaxOrder)) ||
         opt->fmm_levels < 0 || opt->fmm_levels > arb::kFmmMaxLevel || opt->fmm_leaf < 0 ||
         opt->left_precond < 0 || opt->left_precond > 1 || opt->small_cycle < 0 ||
-        opt->small_cycle > 1)
+        opt->small_cycle > 1 || opt->refine_final < 0 || opt->refine_final > 1)
         return ARB_E_ARG;
     // single-blob bodies: unbounded generalised RPY, exact or no preconditioner,
     // direct sums

@@ -39,9 +39,10 @@ def test_bad_options_rejected_before_device():
                # fast product: 2..8 points per direction, levels 0..16, leaf >= 0
                dict(pair_kernel=3, fmm_order=1), dict(pair_kernel=3, fmm_order=9),
                dict(fmm_levels=-1), dict(fmm_levels=17), dict(fmm_leaf=-1),
-               # left or right preconditioning only; one-launch small cycles on or off
+               # left or right preconditioning only; one-launch small cycles on or
+               # off; bounded last refinement correction on or off
                dict(left_precond=2), dict(left_precond=-1), dict(small_cycle=2),
-               dict(small_cycle=-1)):
+               dict(small_cycle=-1), dict(refine_final=2), dict(refine_final=-1)):
         base = dict(device=0, precision=0, wall=0, eta=1.0, a=1.0, tol=1e-8, restart=50,
                     max_iter=100, precond=1, slices=0, pair_kernel=0)
         base.update(kw)

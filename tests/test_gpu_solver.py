@@ -190,25 +190,40 @@ def test_fp32c_solve(case):
     # r = 1e-5 / (10 kappa), every output is within 1e-5 of the direct solution
     # (the forward-error bound); at the practical tolerance 1e-6 the errors are
     # reported only, since there they are bounded by kappa * 1e-6
+    # The residual of the returned iterate is also recomputed with the oracle's
+    # dense system: where the last correction was accepted on its bound
+    # (refine_final = 0) that bound must hold; refine_final = 1 always ends with
+    # an FP64 product.
     name, wl, S, ctx = case
     yd = system.solve_dense(S["A"], S["b"])
     ref = outputs(wl, yd)
     tight = 1e-5 / (10.0 * S["kappa"])
-    for tol in (1e-6, tight):
-        c2 = arb.context_for(wl, precision=arb.ARB_FP32C, tol=tol)
+    bnorm = np.linalg.norm(S["b"])
+    for tol, final in ((1e-6, 0), (1e-6, 1), (tight, 0)):
+        c2 = arb.context_for(wl, precision=arb.ARB_FP32C, tol=tol, refine_final=final)
         try:
             rc, U, phi, lam, info = arb.arb_solve(c2, wl.F, u_slip=wl.u_slip)
         finally:
             arb.arb_destroy(c2)
         assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED)
         assert info["rel_residual_fp64"] <= tol
+        yg = np.concatenate([lam.ravel(), U.ravel(), phi])
+        true_res = np.linalg.norm(S["b"] - S["A"] @ yg) / bnorm
+        # rounding of the two FP64 products (library and dense oracle)
+        slack = 1e-13 * np.linalg.norm(np.abs(S["A"]) @ np.abs(yg)) / bnorm
         got = dict(lam=lam.ravel(), U=U.ravel())
         if wl.n_rows:
             got["phi"] = phi
         errs = {k: rel(got[k], ref[k]) for k in ref}
-        print(f"  fp32c solve to {tol:.1e}: errors {errs} residual "
-              f"{info['rel_residual_fp64']:.1e}, {info['iterations']} iterations, "
+        print(f"  fp32c solve to {tol:.1e} (refine_final {final}): errors {errs} residual "
+              f"{info['rel_residual_fp64']:.1e} (oracle {true_res:.1e}, bounded "
+              f"{info['residual_bounded']}), {info['iterations']} iterations, "
               f"{info['products_fp64']} FP64 products")
+        if info["residual_bounded"]:
+            assert final == 0 and info["products_fp64"] >= 1
+            assert true_res <= info["rel_residual"] + slack
+        else:
+            assert true_res <= tol + slack
     assert all(e <= 1e-5 for e in errs.values())
 
 
@@ -383,8 +398,12 @@ def test_full_size_solve_sampled(cfg):
     us = np.zeros(3 * N) if wl.u_slip is None else wl.u_slip.ravel()
     b = np.concatenate([us, -wl.F.ravel(), B])
     res = np.linalg.norm(Ay - b) / np.linalg.norm(b)
-    print(f"  {info['iterations']} iterations, residual {res:.2e}", flush=True)
+    print(f"  {info['iterations']} iterations, residual {res:.2e} (reported "
+          f"{info['rel_residual']:.2e}, bounded {info['residual_bounded']}, "
+          f"{info['products_fp64']} FP64 products)", flush=True)
     assert res <= 1.01e-6
+    if info["residual_bounded"]:
+        assert res <= info["rel_residual"] * 1.01
     r = bodies.blob_positions(wl.q, wl.theta, wl.r_ref, wl.blob_offset)
     KU = bodies.K_apply(r, wl.q, wl.blob_offset, U)
     tg = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(5).integers(0, N, 24)]))
