@@ -322,7 +322,9 @@ int arb_precond_build(arb_ctx *ctx);
 /* z = P^-1 r (Eq. precond solved exactly), n doubles each. */
 int arb_precond_apply(arb_ctx *ctx, const double *r, double *z);
 /* Lower Cholesky factor of body p's blob mobility (3n_p x 3n_p row-major,
- * upper part zero), and N~_p (36, row-major); either may be NULL.  The
+ * upper part zero), and N~_p (36, row-major); either may be NULL.  (When no
+ * body has more than 256 rows the build forms M_pp^-1 without a factor and
+ * this call factors the kept M_pp on the host.)  The
  * per-type preconditioners (ARB_PC_LEARNED, ARB_PC_BODYFRAME) have no per-body
  * factor: L must be NULL there (ARB_E_ARG otherwise). */
 int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde);

@@ -28,6 +28,25 @@ constexpr int kMaxReconBodies = 2048;
 // for the error on the last correction
 constexpr double kRefineSafety = 10.0;
 
+// lower Cholesky factor of a symmetric positive definite n x n row-major matrix,
+// in place in the lower triangle (the upper one is left as it was); nonzero if
+// a pivot is not positive
+static int host_cholesky(double *A, int n) {
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(d > 0.0)) return 1;
+        const double ljj = std::sqrt(d);
+        A[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = v / ljj;
+        }
+    }
+    return 0;
+}
+
 // in-place inverse of a symmetric positive definite n x n row-major matrix by
 // Cholesky (A = C C^T, A^-1 = C^-T C^-1); returns nonzero if not SPD
 static int spd_inverse(double *A, int n) {
@@ -1924,6 +1943,9 @@ int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde) {
         off += m * m;
     }
     const int64_t m = 3 * (int64_t)(ctx->h_blob_off[p + 1] - ctx->h_blob_off[p]);
+    int max_m = 0;
+    for (int k = 0; k < ctx->M; ++k)
+        max_m = std::max(max_m, 3 * (ctx->h_blob_off[k + 1] - ctx->h_blob_off[k]));
     if (L) {
         HIPCHK(hipMemcpyAsync(L, ctx->mats.as<double>() + off, m * m * sizeof(double),
                               hipMemcpyDeviceToHost, s));
@@ -1932,9 +1954,13 @@ int arb_precond_block(arb_ctx *ctx, int p, double *L, double *Ntilde) {
         HIPCHK(hipMemcpyAsync(Ntilde, ctx->Nt.as<double>() + 36 * (size_t)p, 36 * sizeof(double),
                               hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (L)
+    if (L) {
+        // the inverse was formed out of place: factor the kept block here
+        if (!arb::precond_factor_in_place(max_m) && host_cholesky(L, (int)m) != 0)
+            return fail(ctx, ARB_E_NOT_SPD, "blob mobility block is not positive definite");
         for (int64_t i = 0; i < m; ++i)
             for (int64_t j = i + 1; j < m; ++j) L[i * m + j] = 0.0;
+    }
     return ARB_OK;
     ARB_GUARD_END(ctx)
 }

@@ -311,6 +311,9 @@ hipError_t gmres_small_cycle(hipStream_t s, const SmallSystem &S, int m, int bud
                              double *g, double *steps);
 // max_m = largest 3 n_p of the batch
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m);
+// whether precond_factor leaves the Cholesky factors in P.mats (else the blocks
+// themselves: the inverse is formed out of place)
+bool precond_factor_in_place(int max_m);
 int64_t precond_dinv_size(int64_t n_blobs, int M);
 hipError_t precond_assembly(hipStream_t s, const PrecondDev &P);
 void precond_apply(hipStream_t s, const PrecondDev &P, int N, const double *r, double *z);

@@ -2,6 +2,9 @@
 //
 // Build (once per state), per body p with m = 3 n_p:
 //   pc_assemble  M_pp (m x m, row-major) from the same pair code as the mat-vec
+//   pc_sweep     (no body above 256 rows) M_pp^-1 by the symmetric block sweep,
+//                the matrix held in registers as 16 x 16 matrix-core tiles, one
+//                workgroup per body; M_pp is kept.  Larger bodies:
 //   pc_potrf     M_pp = L L^T in place, blocked by 32 columns: the panel is
 //                factored in LDS, the trailing lower triangle updated in 64 x 64
 //                tiles on the FP64 matrix cores; the inverses of the 32 x 32
@@ -20,8 +23,9 @@
 //                1e-12 * max dropped: the minimum-norm velocity of bodies with
 //                a resistance-free motion)
 // per assembly a (bodies joined by constraints):
-//   pc_asm       S_a = C_a N~_a C_a^T, G~_a = S_a^-1 by Cholesky, or S_a^+ when a
-//                pivot falls below 1e-12 * max diagonal (C_a without full row rank)
+//   pc_asm       S_a = C_a N~_a C_a^T, G~_a = S_a^-1 (by the sweep up to 256 rows,
+//                else by Cholesky), or S_a^+ when a pivot falls below 1e-12 * max
+//                diagonal (C_a without full row rank)
 // Apply (every GMRES iteration), for residual r = (r_lam, r_U, r_phi):
 //   pc_apply1    t_p = M_pp^-1 r_lam,p;  U^_p = -N~_p (r_U,p + Z_p^T r_lam,p)
 //   pc_apply2    phi_a = G~_a (r_phi,a - C_a U^_a)
@@ -1520,9 +1524,214 @@ void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos, dou
                                            wall ? 1 : 0, a, P.mats, P.status);
 }
 
+// SPD inverse of each matrix of the batch by the symmetric block sweep (block
+// Gauss-Jordan elimination without pivoting, which positive definite matrices
+// allow; the pivot blocks are the Schur complements of the Cholesky
+// factorisation), out of place, for matrices of at most kSwRows rows.  One
+// workgroup of 512 threads per matrix holds its lower triangle in registers as
+// 16 x 16 tiles in the matrix-core accumulator layout: tile t = (ti, tj), tj <= ti,
+// counted row by row, belongs to wavefront t % 8 (slot t / 8).  Rows beyond m
+// are padded with the identity.  Sweeping block k with P = A_kk^-1 takes, with
+// the values before the step,
+//   A_ij -= A_ik P A_kj (i, j != k),   A_ik <- A_ik P,   A_kk <- -P,
+// which keeps the matrix symmetric; after the last block it holds -A^-1.  Per
+// step: the block column k is copied to LDS (C_r = A_rk, the tiles of row k
+// transposed); one wavefront inverts D = A_kk by Gauss-Jordan steps in its
+// registers (lane shuffles), testing each pivot (the Cholesky pivots, L_ii^2)
+// against rel_tol * (largest diagonal entry) as pc_potrf does and storing
+// sqrt(pivot) as diag(L) when asked; W_r = C_r P is formed on the matrix cores
+// (wavefront r % 8 takes block row r); every wavefront then updates its tiles on the
+// matrix cores, A_ij -= W_i C_j^T.  The flop count equals that of factor,
+// triangular inverse and product (m^3 in all), with the matrix read once and
+// its inverse (both triangles) written once.  Dynamic LDS: C and W, 16 nb rows
+// of kSwLd doubles each, and P.
+constexpr int kSwRows = 256;
+constexpr int kSwThreads = 512;
+constexpr int kSwWaves = kSwThreads / 64;
+constexpr int kSwSlots = ((kSwRows / 16) * (kSwRows / 16 + 1) / 2 + kSwWaves - 1) / kSwWaves;
+constexpr int kSwLd = 17;
+
+size_t sweep_lds_bytes(int max_m) {
+    const int nb = (max_m + 15) / 16;
+    return (2 * (size_t)16 * nb * kSwLd + 16 * kSwLd) * sizeof(double);
+}
+
+__global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
+    extern __shared__ double sw_lds[];
+    __shared__ int fail;
+    __shared__ double piv_tol;
+    __shared__ double red[kSwWaves];
+    const int p = blockIdx.x;
+    if (mat_skip(B, p)) return;
+    const int m = mat_rows(B, p);
+    const int nb = (m + 15) >> 4, T = nb * (nb + 1) / 2;
+    double *Cb = sw_lds;                            // C_r = A_rk, 16 nb x kSwLd
+    double *Wb = sw_lds + (size_t)16 * nb * kSwLd;  // W_r = C_r P
+    double *Pk = Wb + (size_t)16 * nb * kSwLd;      // P = A_kk^-1, 16 x kSwLd
+    const double *A = B.mats + B.mat_off[p];
+    double *Out = B.out + B.mat_off[p];
+    const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // this wavefront's tiles: row i of tile t is the largest with i (i + 1) / 2 <= t
+    int ti[kSwSlots], tj[kSwSlots];
+#pragma unroll
+    for (int s = 0; s < kSwSlots; ++s) {
+        const int t = w + kSwWaves * s;
+        int i = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+        i += (i + 1) * (i + 2) / 2 <= t;
+        i -= i * (i + 1) / 2 > t;
+        ti[s] = i;
+        tj[s] = t - i * (i + 1) / 2;
+    }
+    // load the lower triangle (the upper part of diagonal tiles by symmetry)
+    mfma_acc acc[kSwSlots];
+    double dloc = 0.0;
+#pragma unroll
+    for (int s = 0; s < kSwSlots; ++s) {
+        if (w + kSwWaves * s >= T) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 16 * ti[s] + 4 * e + lr, c = 16 * tj[s] + lc;
+            double v = r == c ? 1.0 : 0.0;
+            if (r < m && c < m) v = c <= r ? A[(size_t)r * m + c] : A[(size_t)c * m + r];
+            acc[s][e] = v;
+            if (r == c && r < m) dloc = fmax(dloc, v);
+        }
+    }
+    if (B.rel_tol > 0.0) {
+        for (int o = 32; o > 0; o >>= 1) dloc = fmax(dloc, __shfl_xor(dloc, o));
+        if (l == 0) red[w] = dloc;
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    if (tid == 0) {
+        double dmax = 0.0;
+        if (B.rel_tol > 0.0)
+            for (int q = 0; q < kSwWaves; ++q) dmax = fmax(dmax, red[q]);
+        piv_tol = B.rel_tol * dmax;
+    }
+    for (int k = 0; k < nb; ++k) {
+        __syncthreads();  // the previous step's reads of C, W and P are done
+        // 1. block column k: C_r = A_rk (tiles (r, k), r >= k, and (k, r)^T, r < k)
+#pragma unroll
+        for (int s = 0; s < kSwSlots; ++s) {
+            if (w + kSwWaves * s >= T) continue;
+            if (tj[s] == k) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Cb[(16 * ti[s] + 4 * e + lr) * kSwLd + lc] = acc[s][e];
+            } else if (ti[s] == k) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Cb[(16 * tj[s] + lc) * kSwLd + 4 * e + lr] = acc[s][e];
+            }
+        }
+        __syncthreads();
+        // 2. P = D^-1 by Gauss-Jordan in wavefront 0: lane l holds D[4e + l/16][l%16]
+        if (w == 0) {
+            const double tol = piv_tol;
+            double d[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = Cb[(16 * k + 4 * e + lr) * kSwLd + lc];
+            bool bad = false;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double piv = __shfl(d[q >> 2], 16 * (q & 3) + q);
+                if (!(piv > tol)) {  // the same value in every lane
+                    bad = true;
+                    break;
+                }
+                const double ip = 1.0 / piv;
+                const double rq = __shfl(d[q >> 2], 16 * (q & 3) + lc) * ip;  // D_q,c / D_qq
+                double cq[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cq[e] = __shfl(d[e], 16 * lr + q);  // D_r,q
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 4 * e + lr;
+                    if (r == q)
+                        d[e] = lc == q ? ip : d[e] * ip;
+                    else
+                        d[e] = lc == q ? -d[e] * ip : fma(-cq[e], rq, d[e]);
+                }
+                if (B.ldiag && l == 0 && 16 * k + q < m)
+                    B.ldiag[B.scale * (int64_t)B.off[p] + 16 * k + q] = sqrt(piv);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Pk[(4 * e + lr) * kSwLd + lc] = d[e];
+            if (bad && l == 0) fail = 1;
+        }
+        __syncthreads();
+        if (fail) break;
+        // 3. W_r = C_r P, block row r by wavefront r % kSwWaves
+        for (int r = w; r < nb; r += kSwWaves) {
+            if (r == k) continue;
+            mfma_acc x = {};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                x = mfma_f64_16x16x4(Cb[(16 * r + lc) * kSwLd + 4 * kk + lr],
+                                     Pk[(4 * kk + lr) * kSwLd + lc], x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Wb[(16 * r + 4 * e + lr) * kSwLd + lc] = x[e];
+        }
+        __syncthreads();
+        // 4. the tiles: A_ij -= W_i C_j^T; A_ik <- W_i; A_kj <- W_j^T; A_kk <- -P
+#pragma unroll
+        for (int s = 0; s < kSwSlots; ++s) {
+            if (w + kSwWaves * s >= T) continue;
+            const int i = ti[s], j = tj[s];
+            if (i != k && j != k) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    acc[s] = mfma_f64_16x16x4(-Wb[(16 * i + lc) * kSwLd + 4 * kk + lr],
+                                              Cb[(16 * j + lc) * kSwLd + 4 * kk + lr], acc[s]);
+            } else if (i != k) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[s][e] = Wb[(16 * i + 4 * e + lr) * kSwLd + lc];
+            } else if (j != k) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[s][e] = Wb[(16 * j + lc) * kSwLd + 4 * e + lr];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[s][e] = -Pk[(4 * e + lr) * kSwLd + lc];
+            }
+        }
+    }
+    if (fail) {
+        if (tid == 0) {
+            if (B.fail)
+                B.fail[p] = 1;
+            else
+                atomicMax(&B.status[0], p + 1);
+        }
+        return;
+    }
+    // A^-1 = -(the tiles), both triangles
+#pragma unroll
+    for (int s = 0; s < kSwSlots; ++s) {
+        if (w + kSwWaves * s >= T) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 16 * ti[s] + 4 * e + lr, c = 16 * tj[s] + lc;
+            if (r < m && c < m) {
+                Out[(size_t)r * m + c] = -acc[s][e];
+                if (ti[s] != tj[s]) Out[(size_t)c * m + r] = -acc[s][e];
+            }
+        }
+    }
+}
+
+bool precond_factor_in_place(int max_m) { return max_m > kSwRows; }
+
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m) {
     if (P.M <= 0) return hipSuccess;
-    if (max_m <= kFastMaxM) {
+    if (max_m <= kSwRows) {
+        const size_t lds = sweep_lds_bytes(max_m);
+        const hipError_t e = hipFuncSetAttribute(
+            (const void *)pc_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        const MatBatch B{P.blob_off, 3, P.mat_off, P.mats, P.ldiag, P.dinv, P.minv, P.status,
+                         nullptr, 0.0};
+        pc_sweep_kernel<<<P.M, kSwThreads, lds, s>>>(B);
+    } else if (max_m <= kFastMaxM) {
         const int nbk = (max_m + kNB - 1) / kNB;
         const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
         const hipError_t e = hipFuncSetAttribute(
@@ -1616,8 +1825,14 @@ hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
     const int nbk = (max_m + kNB - 1) / kNB;
     const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
     const size_t lds_r = 12 * (size_t)max_m * sizeof(double) + 2 * (size_t)max_m * sizeof(int);
-    hipError_t e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
+    const size_t lds_w = sweep_lds_bytes(max_m);
+    const bool sweep = max_m <= kSwRows;
+    hipError_t e = sweep ? hipFuncSetAttribute((const void *)pc_sweep_kernel,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds_w)
+                         : hipFuncSetAttribute((const void *)pc_trtri_kernel,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds_i);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)pc_asm_form_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
@@ -1628,9 +1843,13 @@ hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
                                                P.status, max_m);
     const MatBatch B{P.asm_row_ptr, 1, P.asm_mat_off, P.S, nullptr, P.asm_dinv, P.G, P.status,
                      P.asm_fail, 1e-12};
-    pc_potrf_kernel<<<P.A, 256, 0, s>>>(B);
-    pc_trtri_kernel<<<dim3(nbk, P.A), 256, lds_i, s>>>(B);
-    pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.A), 256, 0, s>>>(B);
+    if (sweep) {
+        pc_sweep_kernel<<<P.A, kSwThreads, lds_w, s>>>(B);
+    } else {
+        pc_potrf_kernel<<<P.A, 256, 0, s>>>(B);
+        pc_trtri_kernel<<<dim3(nbk, P.A), 256, lds_i, s>>>(B);
+        pc_lauum_kernel<<<dim3(nt * (nt + 1) / 2, P.A), 256, 0, s>>>(B);
+    }
     pc_asm_pinv_kernel<<<P.A, 256, 0, s>>>(P.asm_row_ptr, P.asm_rows, P.asm_mat_off, P.row_p,
                                            P.row_q, P.crow, P.Nt, P.S, P.G, P.asm_fail, P.status);
     return hipGetLastError();
