@@ -1536,27 +1536,33 @@ void precond_assemble(hipStream_t s, const PrecondDev &P, const double *pos, dou
 //   A_ij -= A_ik P A_kj (i, j != k),   A_ik <- A_ik P,   A_kk <- -P,
 // which keeps the matrix symmetric; after the last block it holds -A^-1.  Per
 // step: the block column k is copied to LDS (C_r = A_rk, the tiles of row k
-// transposed); one wavefront inverts D = A_kk by Gauss-Jordan steps in its
-// registers (lane shuffles), testing each pivot (the Cholesky pivots, L_ii^2)
+// transposed); one wavefront inverts D = A_kk in place there by Gauss-Jordan
+// steps, testing each pivot (the Cholesky pivots, L_ii^2)
 // against rel_tol * (largest diagonal entry) as pc_potrf does and storing
 // sqrt(pivot) as diag(L) when asked; W_r = C_r P is formed on the matrix cores
 // (wavefront r % 8 takes block row r); every wavefront then updates its tiles on the
 // matrix cores, A_ij -= W_i C_j^T.  The flop count equals that of factor,
 // triangular inverse and product (m^3 in all), with the matrix read once and
 // its inverse (both triangles) written once.  Dynamic LDS: C and W, 16 nb rows
-// of kSwLd doubles each, and P.
+// of kSwLd doubles each.
 constexpr int kSwRows = 256;
 constexpr int kSwThreads = 512;
 constexpr int kSwWaves = kSwThreads / 64;
-constexpr int kSwSlots = ((kSwRows / 16) * (kSwRows / 16 + 1) / 2 + kSwWaves - 1) / kSwWaves;
 constexpr int kSwLd = 17;
+// matrices of at most kSwSmall tile rows (144 rows) take an instance with fewer
+// registers, two or more workgroups per compute unit
+constexpr int kSwSmall = 9;
 
 size_t sweep_lds_bytes(int max_m) {
     const int nb = (max_m + 15) / 16;
-    return (2 * (size_t)16 * nb * kSwLd + 16 * kSwLd) * sizeof(double);
+    return 2 * (size_t)16 * nb * kSwLd * sizeof(double);
 }
 
-__global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
+// NBMAX: the most tile rows this instance holds; matrices of at most nb_lo tile
+// rows (or more than NBMAX) are skipped
+template <int NBMAX>
+__global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B, int nb_lo) {
+    constexpr int kSwSlots = (NBMAX * (NBMAX + 1) / 2 + kSwWaves - 1) / kSwWaves;
     extern __shared__ double sw_lds[];
     __shared__ int fail;
     __shared__ double piv_tol;
@@ -1565,9 +1571,9 @@ __global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
     if (mat_skip(B, p)) return;
     const int m = mat_rows(B, p);
     const int nb = (m + 15) >> 4, T = nb * (nb + 1) / 2;
+    if (nb <= nb_lo || nb > NBMAX) return;
     double *Cb = sw_lds;                            // C_r = A_rk, 16 nb x kSwLd
     double *Wb = sw_lds + (size_t)16 * nb * kSwLd;  // W_r = C_r P
-    double *Pk = Wb + (size_t)16 * nb * kSwLd;      // P = A_kk^-1, 16 x kSwLd
     const double *A = B.mats + B.mat_off[p];
     double *Out = B.out + B.mat_off[p];
     const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
@@ -1611,7 +1617,8 @@ __global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
         piv_tol = B.rel_tol * dmax;
     }
     for (int k = 0; k < nb; ++k) {
-        __syncthreads();  // the previous step's reads of C, W and P are done
+        double *Dk = Cb + (size_t)16 * k * kSwLd;  // rows of C holding D = A_kk, then P
+        __syncthreads();  // the previous step's reads of C and W are done
         // 1. block column k: C_r = A_rk (tiles (r, k), r >= k, and (k, r)^T, r < k)
 #pragma unroll
         for (int s = 0; s < kSwSlots; ++s) {
@@ -1625,38 +1632,48 @@ __global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
             }
         }
         __syncthreads();
-        // 2. P = D^-1 by Gauss-Jordan in wavefront 0: lane l holds D[4e + l/16][l%16]
+        // 2. P = D^-1 by Gauss-Jordan in wavefront 0, in place in the LDS rows of C
+        // that hold D (no later use of C_k): lane l keeps D[4e + l/16][l%16] in
+        // registers and publishes it after every pivot; one wavefront's LDS
+        // operations complete in order, so each pivot reads the previous one's
+        // values (the fences keep the compiler from reordering them)
         if (w == 0) {
             const double tol = piv_tol;
             double d[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) d[e] = Cb[(16 * k + 4 * e + lr) * kSwLd + lc];
+            for (int e = 0; e < 4; ++e) d[e] = Dk[(4 * e + lr) * kSwLd + lc];
             bool bad = false;
-#pragma unroll
+            double mypiv = 1.0;  // lane q < 16: pivot q
+#pragma unroll 1
             for (int q = 0; q < 16; ++q) {
-                const double piv = __shfl(d[q >> 2], 16 * (q & 3) + q);
-                if (!(piv > tol)) {  // the same value in every lane
-                    bad = true;
-                    break;
-                }
-                const double ip = 1.0 / piv;
-                const double rq = __shfl(d[q >> 2], 16 * (q & 3) + lc) * ip;  // D_q,c / D_qq
+                const double piv = Dk[q * kSwLd + q];
+                const double rqc = Dk[q * kSwLd + lc];  // D_q,c
                 double cq[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) cq[e] = __shfl(d[e], 16 * lr + q);  // D_r,q
+                for (int e = 0; e < 4; ++e) cq[e] = Dk[(4 * e + lr) * kSwLd + q];  // D_r,q
+                // a failed pivot is recorded, the (meaningless) steps still run
+                bad |= !(piv > tol);
+                mypiv = l == q ? piv : mypiv;
+                // 1 / piv: the hardware estimate and two Newton steps
+                double ip = __builtin_amdgcn_rcp(piv);
+                ip = fma(fma(-piv, ip, 1.0), ip, ip);
+                ip = fma(fma(-piv, ip, 1.0), ip, ip);
+                const double rq = rqc * ip;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int r = 4 * e + lr;
-                    if (r == q)
-                        d[e] = lc == q ? ip : d[e] * ip;
-                    else
-                        d[e] = lc == q ? -d[e] * ip : fma(-cq[e], rq, d[e]);
+                    // pivot row scaled, pivot column scaled and negated, the rest
+                    // eliminated; selects, no branches
+                    const bool rowq = 4 * e + lr == q, colq = lc == q;
+                    const double sc = d[e] * ip, el = fma(-cq[e], rq, d[e]);
+                    d[e] = rowq ? (colq ? ip : sc) : (colq ? -sc : el);
                 }
-                if (B.ldiag && l == 0 && 16 * k + q < m)
-                    B.ldiag[B.scale * (int64_t)B.off[p] + 16 * k + q] = sqrt(piv);
-            }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Pk[(4 * e + lr) * kSwLd + lc] = d[e];
+                for (int e = 0; e < 4; ++e) Dk[(4 * e + lr) * kSwLd + lc] = d[e];
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (B.ldiag && l < 16 && 16 * k + l < m)
+                B.ldiag[B.scale * (int64_t)B.off[p] + 16 * k + l] = sqrt(mypiv);
             if (bad && l == 0) fail = 1;
         }
         __syncthreads();
@@ -1668,7 +1685,7 @@ __global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
                 x = mfma_f64_16x16x4(Cb[(16 * r + lc) * kSwLd + 4 * kk + lr],
-                                     Pk[(4 * kk + lr) * kSwLd + lc], x);
+                                     Dk[(4 * kk + lr) * kSwLd + lc], x);
 #pragma unroll
             for (int e = 0; e < 4; ++e) Wb[(16 * r + 4 * e + lr) * kSwLd + lc] = x[e];
         }
@@ -1691,7 +1708,7 @@ __global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
                 for (int e = 0; e < 4; ++e) acc[s][e] = Wb[(16 * j + lc) * kSwLd + 4 * e + lr];
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[s][e] = -Pk[(4 * e + lr) * kSwLd + lc];
+                for (int e = 0; e < 4; ++e) acc[s][e] = -Dk[(4 * e + lr) * kSwLd + lc];
             }
         }
     }
@@ -1721,16 +1738,35 @@ __global__ __launch_bounds__(kSwThreads) void pc_sweep_kernel(MatBatch B) {
 
 bool precond_factor_in_place(int max_m) { return max_m > kSwRows; }
 
+// the sweep over a batch of count matrices of at most max_m <= kSwRows rows: the
+// small instance when every matrix fits it, else the large one for all of them
+// (one launch keeps small and large matrices interleaved over the compute units;
+// two launches measured slower on the bacteria)
+static hipError_t launch_sweep(hipStream_t s, const MatBatch &B, int count, int max_m) {
+    const size_t lds = sweep_lds_bytes(max_m);
+    if (max_m <= 16 * kSwSmall) {
+        const hipError_t e = hipFuncSetAttribute((const void *)pc_sweep_kernel<kSwSmall>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+        pc_sweep_kernel<kSwSmall><<<count, kSwThreads, lds, s>>>(B, 0);
+    } else {
+        const hipError_t e = hipFuncSetAttribute((const void *)pc_sweep_kernel<kSwRows / 16>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+        pc_sweep_kernel<kSwRows / 16><<<count, kSwThreads, lds, s>>>(B, 0);
+    }
+    return hipSuccess;
+}
+
 hipError_t precond_factor(hipStream_t s, const PrecondDev &P, const double *dvec, int max_m) {
     if (P.M <= 0) return hipSuccess;
     if (max_m <= kSwRows) {
-        const size_t lds = sweep_lds_bytes(max_m);
-        const hipError_t e = hipFuncSetAttribute(
-            (const void *)pc_sweep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
         const MatBatch B{P.blob_off, 3, P.mat_off, P.mats, P.ldiag, P.dinv, P.minv, P.status,
                          nullptr, 0.0};
-        pc_sweep_kernel<<<P.M, kSwThreads, lds, s>>>(B);
+        const hipError_t e = launch_sweep(s, B, P.M, max_m);
+        if (e != hipSuccess) return e;
     } else if (max_m <= kFastMaxM) {
         const int nbk = (max_m + kNB - 1) / kNB;
         const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
@@ -1825,14 +1861,9 @@ hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
     const int nbk = (max_m + kNB - 1) / kNB;
     const size_t lds_i = (size_t)nbk * kNB * kLd * sizeof(double);
     const size_t lds_r = 12 * (size_t)max_m * sizeof(double) + 2 * (size_t)max_m * sizeof(int);
-    const size_t lds_w = sweep_lds_bytes(max_m);
     const bool sweep = max_m <= kSwRows;
-    hipError_t e = sweep ? hipFuncSetAttribute((const void *)pc_sweep_kernel,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds_w)
-                         : hipFuncSetAttribute((const void *)pc_trtri_kernel,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds_i);
+    hipError_t e = hipFuncSetAttribute((const void *)pc_trtri_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_i);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)pc_asm_form_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
@@ -1844,7 +1875,8 @@ hipError_t precond_assembly(hipStream_t s, const PrecondDev &P) {
     const MatBatch B{P.asm_row_ptr, 1, P.asm_mat_off, P.S, nullptr, P.asm_dinv, P.G, P.status,
                      P.asm_fail, 1e-12};
     if (sweep) {
-        pc_sweep_kernel<<<P.A, kSwThreads, lds_w, s>>>(B);
+        e = launch_sweep(s, B, P.A, max_m);
+        if (e != hipSuccess) return e;
     } else {
         pc_potrf_kernel<<<P.A, 256, 0, s>>>(B);
         pc_trtri_kernel<<<dim3(nbk, P.A), 256, lds_i, s>>>(B);
