@@ -419,6 +419,35 @@ int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, doubl
                       double delta, double corr_tol, int corr_max_iter, int warm, double *q,
                       double *theta, double *U, arb_step_info *info);
 
+/* Link arms at one instant, for time steps whose arms change in time (Sec. 2.2:
+ * arms dl(t) and their rates enter the link velocity rows; Sec. 5.1: the sliding
+ * plates of the colonies): dl_p, dl_q (3P each, in the body frames of p and q),
+ * dldot_p, dldot_q (3P each, their time derivatives; NULL = zero) and proj (9P,
+ * the row projections as in arb_set_links, for rows that follow the arms; NULL
+ * = keep the context's).  Link pairs and row counts stay those of the last
+ * arb_set_links. */
+typedef struct {
+    const double *dl_p, *dl_q, *dldot_p, *dldot_q, *proj;
+} arb_arms;
+
+/* arb_step_euler for arms that change in time: the solve of step 1 uses the arms
+ * set on the context (time t); once the bodies have moved the arms become `end`
+ * (time t + dt), with which the rebuild, the check and the correction run and
+ * which the context keeps.  ARB_E_ARG if end (or its dl_p, dl_q with links) is
+ * NULL, ARB_E_NAN if it is not finite; the step is not started then. */
+int arb_step_euler_arms(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                        double delta, double corr_tol, int corr_max_iter, int warm,
+                        const arb_arms *end, double *q, double *theta, double *U,
+                        arb_step_info *info);
+/* arb_step_midpoint for arms that change in time (App. C with Sec. 2.2): U^k with
+ * the context's arms (t); the half step's rebuild, check and correction and
+ * U^(k+1/2) with `mid` (t + dt/2); the full step's with `end` (t + dt), which the
+ * context keeps.  Errors as for arb_step_euler_arms. */
+int arb_step_midpoint_arms(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                           double delta, double corr_tol, int corr_max_iter, int warm,
+                           const arb_arms *mid, const arb_arms *end, double *q, double *theta,
+                           double *U, arb_step_info *info);
+
 /* Position/orientation correction (Sec. 4.2, Eq. min_probl, App. B): per
  * assembly, Levenberg-Marquardt on the link residuals g_n plus
  * ||dtheta_p||^2 - 1, exact Jacobian, mu = ||F||^2, until ||F||_2 <= tol or

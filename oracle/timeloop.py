@@ -177,5 +177,29 @@ def midpoint_step(wl, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50, F=N
     return qn, thn, info
 
 
+def euler_step_arms(wl0, wl1, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50, F=None):
+    """Explicit Euler (Sec. 4.3) for links whose arms change in time (Sec. 2.2,
+    the arms and their rates in the link velocity rows): the velocities at t
+    with the links of wl0 (arms at t), the rebuild, check and correction with
+    those of wl1 (arms at t + dt).  The two workloads differ only in their
+    arms.  Returns as euler_step."""
+    U = _solve_multiblob(wl0, q, theta, F)
+    return advance(wl1, q, theta, U, dt, delta, corr_tol, corr_max_iter)
+
+
+def midpoint_step_arms(wl0, wlh, wl1, q, theta, dt, delta, corr_tol=1e-10, corr_max_iter=50,
+                       F=None):
+    """Explicit midpoint (App. C) for links whose arms change in time: U^k with
+    the arms at t (wl0); the half step's rebuild, check and correction and
+    U^(k+1/2) with the arms at t + dt/2 (wlh); the full step from (q, theta)
+    with the arms at t + dt (wl1).  Returns as midpoint_step."""
+    U0 = _solve_multiblob(wl0, q, theta, F)
+    qh, thh, ih = advance(wlh, q, theta, U0, 0.5 * dt, delta, corr_tol, corr_max_iter)
+    Uh = _solve_multiblob(wlh, qh, thh, F)
+    qn, thn, info = advance(wl1, q, theta, Uh, dt, delta, corr_tol, corr_max_iter)
+    info.update(half=ih, U0=np.asarray(U0).reshape(-1, 6), U_half=np.asarray(Uh).reshape(-1, 6))
+    return qn, thn, info
+
+
 def _solve_multiblob(wl, q, theta, F):
     return solve_velocities(wl, q, theta, F)[0]

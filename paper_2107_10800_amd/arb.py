@@ -52,7 +52,8 @@ SYMBOLS = [
     "arb_mlp_grad", "arb_mlp_train_step_dev", "arb_mlp_features", "arb_body_mobility",
     "arb_mlp_set_scaling", "arb_reconstruct", "arb_link_residual", "arb_step_euler",
     "arb_body_mobility_apply", "arb_body_mobility_apply_dev", "arb_step_midpoint",
-    "arb_fmm_get_stats", "arb_fmm_plan", "arb_rpy_apply_noalloc_dev",
+    "arb_fmm_get_stats", "arb_fmm_plan", "arb_rpy_apply_noalloc_dev", "arb_step_euler_arms",
+    "arb_step_midpoint_arms",
 ]
 
 
@@ -87,6 +88,12 @@ class arb_step_info(C.Structure):
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class arb_arms(C.Structure):
+    _fields_ = [("dl_p", C.POINTER(C.c_double)), ("dl_q", C.POINTER(C.c_double)),
+                ("dldot_p", C.POINTER(C.c_double)), ("dldot_q", C.POINTER(C.c_double)),
+                ("proj", C.POINTER(C.c_double))]
 
 
 class arb_solve_info(C.Structure):
@@ -176,6 +183,13 @@ def load():
                                    C.POINTER(arb_fmm_stats)]),
         "arb_step_euler": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double, C.c_int,
                                      C.c_int, _DP, _DP, _DP, C.POINTER(arb_step_info)]),
+        "arb_step_euler_arms": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double,
+                                          C.c_int, C.c_int, C.POINTER(arb_arms), _DP, _DP, _DP,
+                                          C.POINTER(arb_step_info)]),
+        "arb_step_midpoint_arms": (C.c_int, [_P, _DP, _DP, C.c_double, C.c_double, C.c_double,
+                                             C.c_int, C.c_int, C.POINTER(arb_arms),
+                                             C.POINTER(arb_arms), _DP, _DP, _DP,
+                                             C.POINTER(arb_step_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -486,6 +500,61 @@ def arb_step_midpoint(ctx, F, dt, delta=1e-10, corr_tol=1e-10, corr_max_iter=50,
     rc = _check(ctx, load().arb_step_midpoint(ctx, Fp, usp, float(dt), float(delta),
                                               float(corr_tol), int(corr_max_iter),
                                               int(bool(warm)), qp, tp, Up, C.byref(info)))
+    return rc, q.reshape(M, 3), t.reshape(M, 4), U.reshape(M, 6), info.to_dict()
+
+
+def _arms(P, dl_p, dl_q, dldot_p=None, dldot_q=None, proj=None):
+    """An arb_arms over float64 copies of the arrays (kept alive by the returned list)."""
+    keep = []
+    ptrs = []
+    for a, n in ((dl_p, 3), (dl_q, 3), (dldot_p, 3), (dldot_q, 3), (proj, 9)):
+        if a is None:
+            ptrs.append(None)
+            continue
+        x, xp = _d(a, n * P)
+        keep.append(x)
+        ptrs.append(xp)
+    return arb_arms(*ptrs), keep
+
+
+def arb_step_euler_arms(ctx, F, dt, end, delta=1e-10, corr_tol=1e-10, corr_max_iter=50,
+                        warm=True, u_slip=None):
+    """arb_step_euler with the arms at t + dt: end = (dl_p, dl_q[, dldot_p, dldot_q
+    [, proj]]), the optional ones may be None.  Returns as arb_step_euler."""
+    N, M, _, _ = arb_sizes(ctx)
+    P = len(np.asarray(end[0]).ravel()) // 3
+    ae, keep = _arms(P, *end)
+    F_, Fp = _d(F, 6 * M)
+    us_, usp = _d(u_slip, 3 * N) if u_slip is not None else (None, None)
+    q, qp = _out(3 * M)
+    t, tp = _out(4 * M)
+    U, Up = _out(6 * M)
+    info = arb_step_info()
+    rc = _check(ctx, load().arb_step_euler_arms(ctx, Fp, usp, float(dt), float(delta),
+                                                float(corr_tol), int(corr_max_iter),
+                                                int(bool(warm)), C.byref(ae), qp, tp, Up,
+                                                C.byref(info)))
+    return rc, q.reshape(M, 3), t.reshape(M, 4), U.reshape(M, 6), info.to_dict()
+
+
+def arb_step_midpoint_arms(ctx, F, dt, mid, end, delta=1e-10, corr_tol=1e-10, corr_max_iter=50,
+                           warm=True, u_slip=None):
+    """arb_step_midpoint with the arms at t + dt/2 (mid) and t + dt (end), each as
+    for arb_step_euler_arms.  Returns as arb_step_midpoint."""
+    N, M, _, _ = arb_sizes(ctx)
+    P = len(np.asarray(end[0]).ravel()) // 3
+    am, keep_m = _arms(P, *mid)
+    ae, keep_e = _arms(P, *end)
+    F_, Fp = _d(F, 6 * M)
+    us_, usp = _d(u_slip, 3 * N) if u_slip is not None else (None, None)
+    q, qp = _out(3 * M)
+    t, tp = _out(4 * M)
+    U, Up = _out(6 * M)
+    info = arb_step_info()
+    rc = _check(ctx, load().arb_step_midpoint_arms(ctx, Fp, usp, float(dt), float(delta),
+                                                   float(corr_tol), int(corr_max_iter),
+                                                   int(bool(warm)), C.byref(am), C.byref(ae),
+                                                   qp, tp, Up, C.byref(info)))
     return rc, q.reshape(M, 3), t.reshape(M, 4), U.reshape(M, 6), info.to_dict()
 
 

@@ -2312,14 +2312,58 @@ struct AdvanceInfo {
     int corrected = 0, corr_iterations = 0;
 };
 
+// arms that change in time: checked before a step starts, so that a bad array
+// leaves the context as it was
+static int check_arms(arb_ctx *ctx, const arb_arms *a) {
+    if (!a) return fail(ctx, ARB_E_ARG, "arms: null");
+    const size_t n3 = 3 * (size_t)ctx->P;
+    if (ctx->P > 0 && (!a->dl_p || !a->dl_q)) return fail(ctx, ARB_E_ARG, "arms: dl_p, dl_q required");
+    if (check_finite(ctx, a->dl_p, ctx->P > 0 ? n3 : 0, "arms dl_p") ||
+        check_finite(ctx, a->dl_q, ctx->P > 0 ? n3 : 0, "arms dl_q") ||
+        check_finite(ctx, a->dldot_p, ctx->P > 0 ? n3 : 0, "arms dldot_p") ||
+        check_finite(ctx, a->dldot_q, ctx->P > 0 ? n3 : 0, "arms dldot_q") ||
+        check_finite(ctx, a->proj, ctx->P > 0 ? 3 * n3 : 0, "arms proj"))
+        return ARB_E_NAN;
+    return 0;
+}
+
+// the context's arms (and projections, when given; host copies and device
+// arrays) become a; the constraint rows follow at the next refresh of the geometry
+static int apply_arms(arb_ctx *ctx, hipStream_t s, const arb_arms *a) {
+    const size_t n3 = 3 * (size_t)ctx->P;
+    if (n3 == 0) return 0;
+    ctx->h_dl_p.assign(a->dl_p, a->dl_p + n3);
+    ctx->h_dl_q.assign(a->dl_q, a->dl_q + n3);
+    if (a->dldot_p)
+        ctx->h_dldot_p.assign(a->dldot_p, a->dldot_p + n3);
+    else
+        ctx->h_dldot_p.assign(n3, 0.0);
+    if (a->dldot_q)
+        ctx->h_dldot_q.assign(a->dldot_q, a->dldot_q + n3);
+    else
+        ctx->h_dldot_q.assign(n3, 0.0);
+    TRY(upload(ctx, ctx->dl_p, ctx->h_dl_p.data(), n3, s));
+    TRY(upload(ctx, ctx->dl_q, ctx->h_dl_q.data(), n3, s));
+    TRY(upload(ctx, ctx->dldot_p, ctx->h_dldot_p.data(), n3, s));
+    TRY(upload(ctx, ctx->dldot_q, ctx->h_dldot_q.data(), n3, s));
+    if (a->proj) {
+        ctx->h_proj.assign(a->proj, a->proj + 3 * n3);
+        TRY(upload(ctx, ctx->proj, ctx->h_proj.data(), 3 * n3, s));
+    }
+    return 0;
+}
+
 // steps 2-5 of Sec. 4.3 from the context's state with body velocities Ud (device,
 // 6M) over dt: every body by explicit Euler (the mean of the new tracking points
 // of an articulated body is then q_COM + dt u_COM), orientations by
-// theta_{w dt} . theta, rebuild, check sum g.g < delta, else correction
+// theta_{w dt} . theta, rebuild, check sum g.g < delta, else correction; arms
+// (may be null) are those of the end of the interval, set once the bodies moved
 static int advance_dev(arb_ctx *ctx, hipStream_t s, const double *Ud, double dt, double delta,
-                       double corr_tol, int corr_max_iter, AdvanceInfo *ai) {
+                       double corr_tol, int corr_max_iter, AdvanceInfo *ai,
+                       const arb_arms *arms = nullptr) {
     arb::euler_update(s, ctx->M, Ud, dt, ctx->q.as<double>(), ctx->theta.as<double>());
     HIPCHK(hipGetLastError());
+    if (arms) TRY(apply_arms(ctx, s, arms));
     TRY(recon_run(ctx, s, 1, &ai->g_inf_star, &ai->g2_star));
     ai->g_inf = ai->g_inf_star;
     if (ctx->lasm_A > 0 && !(ai->g2_star < delta)) {
@@ -2378,10 +2422,10 @@ static void fill_step_info(arb_step_info *info, int rc, const arb_solve_info &si
     info->g_inf = ai.g_inf;
 }
 
-int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
-                   double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
-                   double *U, arb_step_info *info) {
-    ARB_GUARD_BEGIN
+static int step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                      double delta, double corr_tol, int corr_max_iter, int warm,
+                      const arb_arms *end, double *q, double *theta, double *U,
+                      arb_step_info *info) {
     TRY(step_prologue(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter));
     hipStream_t s = ctx->stream;
     arb_solve_info si{};
@@ -2389,7 +2433,7 @@ int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double d
     if (rc < 0) return rc;
     const double *Ud = ctx->ky.as<double>() + u_offset(ctx);
     AdvanceInfo ai;
-    TRY(advance_dev(ctx, s, Ud, dt, delta, corr_tol, corr_max_iter, &ai));
+    TRY(advance_dev(ctx, s, Ud, dt, delta, corr_tol, corr_max_iter, &ai, end));
     TRY(copy_state_out(ctx, s, q, theta));
     if (U)
         HIPCHK(hipMemcpyAsync(U, Ud, 6 * (size_t)ctx->M * sizeof(double), hipMemcpyDeviceToHost,
@@ -2397,13 +2441,12 @@ int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double d
     HIPCHK(hipStreamSynchronize(s));
     fill_step_info(info, rc, si, ai);
     return rc;
-    ARB_GUARD_END(ctx)
 }
 
-int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
-                      double delta, double corr_tol, int corr_max_iter, int warm, double *q,
-                      double *theta, double *U, arb_step_info *info) {
-    ARB_GUARD_BEGIN
+static int step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                         double delta, double corr_tol, int corr_max_iter, int warm,
+                         const arb_arms *mid, const arb_arms *end, double *q, double *theta,
+                         double *U, arb_step_info *info) {
     TRY(step_prologue(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter));
     hipStream_t s = ctx->stream;
     const int M = ctx->M;
@@ -2420,7 +2463,7 @@ int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, doubl
     const int rc0 = step_solve(ctx, s, u_slip != nullptr, warm, &s0);
     if (rc0 < 0) return rc0;
     AdvanceInfo ah;
-    TRY(advance_dev(ctx, s, Ud, 0.5 * dt, delta, corr_tol, corr_max_iter, &ah));
+    TRY(advance_dev(ctx, s, Ud, 0.5 * dt, delta, corr_tol, corr_max_iter, &ah, mid));
     // U^(k+1/2) at the midpoint state, warm-started from U^k's solution
     arb_solve_info s1{};
     const int rc1 = step_solve(ctx, s, u_slip != nullptr, 1, &s1);
@@ -2431,7 +2474,7 @@ int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, doubl
     HIPCHK(hipMemcpyAsync(ctx->theta.p, ctx->th0.p, 4 * (size_t)M * sizeof(double),
                           hipMemcpyDeviceToDevice, s));
     AdvanceInfo af;
-    TRY(advance_dev(ctx, s, Ud, dt, delta, corr_tol, corr_max_iter, &af));
+    TRY(advance_dev(ctx, s, Ud, dt, delta, corr_tol, corr_max_iter, &af, end));
     TRY(copy_state_out(ctx, s, q, theta));
     if (U) HIPCHK(hipMemcpyAsync(U, Ud, 6 * (size_t)M * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -2448,6 +2491,48 @@ int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, doubl
                        : (rc0 > 0 ? rc0 : rc1);
     fill_step_info(info, rc, st, af);
     return rc;
+}
+
+int arb_step_euler(arb_ctx *ctx, const double *F, const double *u_slip, double dt, double delta,
+                   double corr_tol, int corr_max_iter, int warm, double *q, double *theta,
+                   double *U, arb_step_info *info) {
+    ARB_GUARD_BEGIN
+    return step_euler(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter, warm, nullptr, q,
+                      theta, U, info);
+    ARB_GUARD_END(ctx)
+}
+
+int arb_step_euler_arms(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                        double delta, double corr_tol, int corr_max_iter, int warm,
+                        const arb_arms *end, double *q, double *theta, double *U,
+                        arb_step_info *info) {
+    ARB_GUARD_BEGIN
+    if (!ctx) return ARB_E_ARG;
+    TRY(check_arms(ctx, end));
+    return step_euler(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter, warm, end, q, theta,
+                      U, info);
+    ARB_GUARD_END(ctx)
+}
+
+int arb_step_midpoint(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                      double delta, double corr_tol, int corr_max_iter, int warm, double *q,
+                      double *theta, double *U, arb_step_info *info) {
+    ARB_GUARD_BEGIN
+    return step_midpoint(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter, warm, nullptr,
+                         nullptr, q, theta, U, info);
+    ARB_GUARD_END(ctx)
+}
+
+int arb_step_midpoint_arms(arb_ctx *ctx, const double *F, const double *u_slip, double dt,
+                           double delta, double corr_tol, int corr_max_iter, int warm,
+                           const arb_arms *mid, const arb_arms *end, double *q, double *theta,
+                           double *U, arb_step_info *info) {
+    ARB_GUARD_BEGIN
+    if (!ctx) return ARB_E_ARG;
+    TRY(check_arms(ctx, mid));
+    TRY(check_arms(ctx, end));
+    return step_midpoint(ctx, F, u_slip, dt, delta, corr_tol, corr_max_iter, warm, mid, end, q,
+                         theta, U, info);
     ARB_GUARD_END(ctx)
 }
 

@@ -57,4 +57,8 @@ def test_null_context_calls_are_errors():
     lib = arb.load()
     assert lib.arb_set_state(None, None, None) == arb.ARB_E_ARG
     assert lib.arb_solve(None, None, None, None, None, None, None, None) == arb.ARB_E_ARG
+    assert lib.arb_step_euler_arms(None, None, None, 0.1, 0.0, 1e-10, 10, 0, None, None, None,
+                                   None, None) == arb.ARB_E_ARG
+    assert lib.arb_step_midpoint_arms(None, None, None, 0.1, 0.0, 1e-10, 10, 0, None, None,
+                                      None, None, None, None) == arb.ARB_E_ARG
     assert lib.arb_last_error(None) == b"null context"

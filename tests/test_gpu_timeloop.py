@@ -321,3 +321,57 @@ def test_time_dependent_arms_by_composition():
     assert np.abs(q - q_ref).max() <= 1e-11 * scale
     assert abs(gi - ref["g_inf_star"]) <= 1e-12 * scale
     assert 0 < gi < 0.2 * dt ** 2
+
+
+@pytest.mark.parametrize("delta", [np.inf, 1e-20])
+def test_fused_steps_with_moving_arms_match_oracle(delta):
+    """Active links (Sec. 2.2, Sec. 5.1 colonies) in the fused steps: explicit
+    Euler with the arms of t + dt for the rebuild, and the midpoint scheme (App.
+    C) with the arms of t + dt/2 for its half step and midpoint solve and of
+    t + dt for the full step, against the oracle's steps with the same stage
+    arms (and the projections of the sliding links' rows, which follow the
+    arms).  As in the other step tests, the velocities agree with the oracle's
+    dense solves within max(1e-9, 10 kappa(A) r), and the oracle's integrator,
+    run on the GPU's velocities, gives the GPU's new state; the context keeps
+    the arms of t + dt (its link residual after the step is the oracle's)."""
+    dt = 0.05
+    kw = dict(n_col=2, kmin=5, kmax=7, seed=22, lattice=(2, 1, 1))
+    wl0, wlh, wl1 = (W.diatoms(t=t, **kw) for t in (0.0, 0.5 * dt, dt))
+    arms = lambda w: (w.dl_p, w.dl_q, w.dldot_p, w.dldot_q, w.proj)
+    scale = 1.0 + np.abs(wl0.q).max()
+    kap = _kappa(system.assemble(wl0)["A"])
+    tolU = max(1e-9, 10 * kap * 1e-12)
+    for name in ("euler", "midpoint"):
+        ctx = arb.context_for(wl0, tol=1e-12)
+        try:
+            if name == "euler":
+                rc, q, th, U, info = arb.arb_step_euler_arms(ctx, wl0.F, dt, arms(wl1), delta=delta,
+                                                             corr_tol=1e-12, warm=False)
+            else:
+                rc, q, th, U, info = arb.arb_step_midpoint_arms(ctx, wl0.F, dt, arms(wlh),
+                                                                arms(wl1), delta=delta,
+                                                                corr_tol=1e-12, warm=False)
+            gi_after, _ = arb.arb_link_residual(ctx)
+        finally:
+            arb.arb_destroy(ctx)
+        assert rc in (arb.ARB_OK, arb.ARB_W_PINV_USED) and info["rel_residual"] <= 1e-12
+        if name == "euler":
+            _, _, full = timeloop.euler_step_arms(wl0, wl1, wl0.q, wl0.theta, dt, delta=delta,
+                                                  corr_tol=1e-12)
+            U_ref, bar = full["U"], tolU
+        else:
+            _, _, full = timeloop.midpoint_step_arms(wl0, wlh, wl1, wl0.q, wl0.theta, dt,
+                                                     delta=delta, corr_tol=1e-12)
+            U_ref, bar = full["U_half"], tolU
+        # the oracle's integrator with the end arms on the GPU's velocities
+        q_ref, th_ref, ref = timeloop.advance(wl1, wl0.q, wl0.theta, U, dt, delta,
+                                              corr_tol=1e-12)
+        du = np.linalg.norm(U - U_ref) / np.linalg.norm(U_ref)
+        print(f"{name} with moving arms, delta={delta}: kappa {kap:.1e}, U {du:.1e} (bar "
+              f"{bar:.1e}), |q - oracle| {np.abs(q - q_ref).max():.2e}, g_inf "
+              f"{info['g_inf']:.2e} / {ref['g_inf']:.2e}", flush=True)
+        assert du <= bar
+        assert np.abs(q - q_ref).max() <= 1e-10 * scale
+        assert np.abs(th - th_ref).max() <= 1e-10
+        assert abs(info["g_inf"] - ref["g_inf"]) <= 1e-10 * scale
+        assert abs(gi_after - ref["g_inf"]) <= 1e-10 * scale

@@ -217,3 +217,52 @@ def test_midpoint_step_stages():
     assert np.allclose(info["U_half"], U_half, atol=1e-14)
     q2, th2, _ = timeloop.advance(wl, wl.q, wl.theta, U_half, 0.3, np.inf)
     assert np.abs(q - q2).max() < 1e-13 and np.abs(th - th2).max() < 1e-13
+
+
+def _colony(t):
+    # one colony of three plates whose link arms slide in time (Sec. 5.1)
+    return W.diatoms(n_col=1, kmin=3, kmax=3, seed=31, lattice=(1, 1, 1), t=t)
+
+
+def test_arms_steps_with_fixed_arms_are_the_plain_steps():
+    """With the same arms at every stage time the steps for time-dependent arms
+    are the plain steps, bit for bit."""
+    wl = _colony(0.3)
+    a = timeloop.euler_step_arms(wl, wl, wl.q, wl.theta, 0.05, delta=np.inf)
+    b = timeloop.euler_step(wl, wl.q, wl.theta, 0.05, delta=np.inf)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    a = timeloop.midpoint_step_arms(wl, wl, wl, wl.q, wl.theta, 0.05, delta=np.inf)
+    b = timeloop.midpoint_step(wl, wl.q, wl.theta, 0.05, delta=np.inf)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _integrate_arms(step, T, n, stage_arms=True, **kw):
+    wl = _colony(0.0)
+    q, th = wl.q.copy(), wl.theta.copy()
+    dt = T / n
+    for k in range(n):
+        t = k * dt
+        w0 = _colony(t)
+        wh, w1 = (_colony(t + 0.5 * dt), _colony(t + dt)) if stage_arms else (w0, w0)
+        if step == "euler":
+            q, th, _ = timeloop.euler_step_arms(w0, w1, q, th, dt, **kw)
+        else:
+            q, th, _ = timeloop.midpoint_step_arms(w0, wh, w1, q, th, dt, **kw)
+    return q
+
+
+def test_moving_arms_keep_the_orders_only_with_stage_arms():
+    """Sliding plates driven by their arms alone (no forces): with the arms of
+    each stage time (App. C with Sec. 2.2) explicit Euler converges at first
+    and the midpoint scheme at second order; the midpoint scheme that keeps the
+    arms of the start of each step for its later stages falls to first order
+    (errors at t = 0.4 against 128 midpoint steps)."""
+    T = 0.4
+    kw = dict(delta=1e-20, corr_tol=1e-13)
+    ref = _integrate_arms("midpoint", T, 128, **kw)
+    for step, stage, order in (("euler", True, 1), ("midpoint", True, 2),
+                               ("midpoint", False, 1)):
+        errs = [np.abs(_integrate_arms(step, T, n, stage, **kw) - ref).max() for n in (8, 16, 32)]
+        print(step, stage, errs)
+        for a, b in zip(errs, errs[1:]):
+            assert 0.75 * 2 ** order < a / b < 1.3 * 2 ** order, (step, stage, errs)
