@@ -103,13 +103,15 @@ def max_level(pos: np.ndarray, a: float) -> int:
     return L
 
 
-def fmm_apply(pos, lam, a, eta, wall, n, L, kernel=None):
+def fmm_apply(pos, lam, a, eta, wall, n, L, kernel=None, sparse_cells=True):
     """The approximation defined in the module docstring, (N, d).
 
     lam: (N, d) generalised forces; kernel(x, y) -> (..., d, d) blocks for
     broadcastable point arrays; by default the RPY tensor M(x, y) (d = 3,
     unbounded or above the wall).  For single-blob bodies (Sec. 2.4) the kernel
-    is the generalised RPY tensor N(x, y) (d = 6) and lam = (f, tau)."""
+    is the generalised RPY tensor N(x, y) (d = 6) and lam = (f, tau).
+    sparse_cells=False interpolates every listed cell, the plain
+    tensor-product interpolation (for the pins of the sparse-cell rule)."""
     pos = np.asarray(pos, float)
     lam = np.asarray(lam, float).reshape(len(pos), -1)
     if kernel is None:
@@ -144,10 +146,11 @@ def fmm_apply(pos, lam, a, eta, wall, n, L, kernel=None):
                 continue
             t = proxies(n, centre[c], w)
             # sparse listed cells enter with their blobs, the others with proxies
-            s = np.concatenate([pos[members[d]] if len(members[d]) < n ** 3
-                                else proxies(n, centre[d], w) for d in il])
-            q = np.concatenate([lam[members[d]] if len(members[d]) < n ** 3 else qhat[d]
-                                for d in il])
+            sparse = [sparse_cells and len(members[d]) < n ** 3 for d in il]
+            s = np.concatenate([pos[members[d]] if sp else proxies(n, centre[d], w)
+                                for d, sp in zip(il, sparse)])
+            q = np.concatenate([lam[members[d]] if sp else qhat[d]
+                                for d, sp in zip(il, sparse)])
             v = np.einsum("tsij,sj->ti", kernel(t[:, None, :], s[None, :, :]), q)
             out[members[c]] += weights(n, pos[members[c]], centre[c], w) @ v
     return out

@@ -197,3 +197,27 @@ def test_symmetric_when_every_listed_cell_is_interpolated(wall, shape, n, L):
         assert np.abs(Mb - dense).max() > 1e-4 * np.abs(dense).max()
     s1, s2 = np.sum(a * Mb), np.sum(b * Ma)
     assert abs(s1 - s2) <= 1e-12 * np.linalg.norm(a) * np.linalg.norm(Mb)
+
+
+def test_sparse_cell_rule_only_removes_source_interpolation():
+    """The rule that a listed cell with fewer blobs than proxies enters with its
+    blobs replaces that cell's source-side interpolation by the exact sum: for
+    a kernel of degree n - 1 (interpolated exactly) both forms agree to
+    rounding; with the RPY tensor on a loose suspension (most cells sparse) the
+    rule changes the result and brings it closer to the dense sum, at the
+    orders whose n^3 proxies outnumber the blobs of the cells (about 19 here)."""
+    pos, lam = blobs(300, (48, 48, 10), 12)
+    for n in (3, 4):
+        K = poly_kernel(n)
+        u1 = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, n, 2, kernel=K)
+        u0 = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, n, 2, kernel=K, sparse_cells=False)
+        assert np.abs(u1 - u0).max() <= 1e-12 * np.abs(u0).max()
+    ref = rpy.mobility_apply(pos, lam, 1.0, 1.0, False)
+    for n in (3, 4, 5):
+        u1 = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, n, 2)
+        u0 = fastsum.fmm_apply(pos, lam, 1.0, 1.0, False, n, 2, sparse_cells=False)
+        e1 = np.linalg.norm(u1 - ref) / np.linalg.norm(ref)
+        e0 = np.linalg.norm(u0 - ref) / np.linalg.norm(ref)
+        print(f"order {n}: error with the rule {e1:.2e}, all cells interpolated {e0:.2e}")
+        assert np.abs(u1 - u0).max() > 1e-6 * np.abs(ref).max()
+        assert e1 < e0
