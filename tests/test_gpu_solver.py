@@ -244,6 +244,29 @@ def test_rank_deficient_hinge_uses_pinv():
     assert rel(S["C"].T @ phi, S["C"].T @ yd[3 * N + 6 * M:]) <= 1e-8
 
 
+def test_rank_deficient_large_assembly_uses_pinv():
+    # a colony of 14 plates whose second link per plate pair keeps its third
+    # row (a repeat of the first link's): one assembly of 78 rows, rank 65, so
+    # the block sweep's pivot test fails for it and the pseudo-inverse takes
+    # over (Sec. 3.1 with Sec. 5.1); only U and C^T phi are unique
+    wl = W.diatoms(n_col=1, kmin=14, kmax=14, seed=9, lattice=(1, 1, 1), literal=True)
+    S = system.assemble(wl)
+    assert S["C"].shape[0] == 78
+    ctx = arb.context_for(wl, precision=arb.ARB_FP64, tol=1e-10)
+    try:
+        rc, U, phi, lam, info = arb.arb_solve(ctx, wl.F)
+    finally:
+        arb.arb_destroy(ctx)
+    assert rc == arb.ARB_W_PINV_USED and info["pinv_used"] >= 1
+    yd = system.solve_dense(S["A"], S["b"])
+    N, M = wl.N, wl.M
+    print(f"  78-row rank-deficient assembly: {info['iterations']} iterations, U "
+          f"{rel(U, yd[3 * N:3 * N + 6 * M]):.1e}, C^T phi "
+          f"{rel(S['C'].T @ phi, S['C'].T @ yd[3 * N + 6 * M:]):.1e}")
+    assert rel(U, yd[3 * N:3 * N + 6 * M]) <= 1e-8
+    assert rel(S["C"].T @ phi, S["C"].T @ yd[3 * N + 6 * M:]) <= 1e-8
+
+
 def test_euler_and_correction():
     wl = W.filament()
     S = system.assemble(wl)
