@@ -342,8 +342,10 @@ def blob_filaments(nx: int = 1, nz: int = 1, n_blobs: int = 15, lc: float = 2.5,
 
 
 def blob_shells(n_side: int = 1, lc: float = 2.5, forcing: str = "random",
-                seed: int = 32) -> Workload:
-    """Cubic lattice of n_side^3 deformable shells of single-blob bodies (Sec. 3.2.2).
+                seed: int = 32, centres=None) -> Workload:
+    """Cubic lattice of n_side^3 deformable shells of single-blob bodies (Sec. 3.2.2);
+    with ``centres`` ((k, 3), in units of the shell radius R) the shells sit there
+    instead (the two sedimenting shells of Sec. 4.4 at (+-1.5, 0, +-1.5) R).
 
     A shell is the 42-point icosphere (12 icosahedron vertices, 30 projected
     edge midpoints) scaled so that a vertex and a neighbouring midpoint are lc
@@ -361,12 +363,13 @@ def blob_shells(n_side: int = 1, lc: float = 2.5, forcing: str = "random",
     pairs1 = [(i, 12 + e) for e, (i, j) in enumerate(edges)] + \
              [(j, 12 + e) for e, (i, j) in enumerate(edges)]
     q, pairs = [], []
-    for ix in range(n_side):
-        for iy in range(n_side):
-            for iz in range(n_side):
-                b0 = len(q)
-                q.extend(shell + 4 * R * np.array([ix, iy, iz], float))
-                pairs += [(b0 + a, b0 + b) for a, b in pairs1]
+    if centres is None:
+        centres = [4.0 * np.array([ix, iy, iz], float) for ix in range(n_side)
+                   for iy in range(n_side) for iz in range(n_side)]
+    for c in np.asarray(centres, float).reshape(-1, 3):
+        b0 = len(q)
+        q.extend(shell + R * c)
+        pairs += [(b0 + a, b0 + b) for a, b in pairs1]
     q = np.array(q)
     M = len(q)
     theta = _quat_scalar_first(Rotation.random(M, random_state=rng))

@@ -266,3 +266,30 @@ def test_moving_arms_keep_the_orders_only_with_stage_arms():
         print(step, stage, errs)
         for a, b in zip(errs, errs[1:]):
             assert 0.75 * 2 ** order < a / b < 1.3 * 2 ** order, (step, stage, errs)
+
+
+def _shell_solve(wl, q, theta, F):
+    from oracle import single_blob
+    S = single_blob.assemble(wl, q, theta, F)
+    return single_blob.solve_dense(S)[:6 * wl.M].reshape(-1, 6)
+
+
+def two_shells():
+    # E6 (Sec. 4.4): two deformable shells of single blobs sedimenting side by side
+    return W.blob_shells(forcing="gravity", centres=[[-1.5, 0.0, -1.5], [1.5, 0.0, 1.5]])
+
+
+def test_two_sedimenting_shells_orders():
+    """Sec. 4.4's two sedimenting shells (42 single-blob bodies and 60 links each,
+    centres (+-1.5, 0, +-1.5) R, gravity): with reconstruction and correction
+    explicit Euler converges at first and the midpoint scheme at second order
+    (errors at t = 8 against 48 midpoint steps)."""
+    wl = two_shells()
+    T = 8.0
+    kw = dict(delta=1e-20, corr_tol=1e-13, solve=_shell_solve)
+    ref = _integrate(wl, timeloop.midpoint_step, T, 48, **kw)[0]
+    for step, order in ((timeloop.euler_step, 1), (timeloop.midpoint_step, 2)):
+        errs = [np.abs(_integrate(wl, step, T, n, **kw)[0] - ref).max() for n in (4, 8, 16)]
+        print(step.__name__, ["%.2e" % e for e in errs])
+        for a, b in zip(errs, errs[1:]):
+            assert 0.75 * 2 ** order < a / b < 1.3 * 2 ** order, (step.__name__, errs)
