@@ -413,3 +413,38 @@ def test_two_sedimenting_shells_on_gpu():
     for order, e in errs.items():
         for a, b in zip(e, e[1:]):
             assert 0.75 * 2 ** order < a / b < 1.3 * 2 ** order
+
+
+def test_swimming_bacterium_needs_a_tight_check():
+    """E5 (Sec. 4.4): a bacterium whose hinge keeps all six rows (rank 5 of 6,
+    the motor row on top) converges at first order in time with explicit Euler
+    only when the check of step 5 is tight: with delta <= 1e-9 the errors at
+    t = 8 against 256 midpoint steps halve with the step, with delta = 1e-6 the
+    occasional correction breaks the convergence, and without it the errors do
+    not fall steadily (and the drifted states make the redundant rows
+    inconsistent: some solves stop short of the tolerance there)."""
+    wl = W.bacteria(n_bact=1, seed=3, literal_hinge=True)
+    T = 8.0
+    ctx = arb.context_for(wl, tol=1e-12)
+
+    def run(step, n, delta):
+        arb.arb_set_state(ctx, wl.q, wl.theta)
+        ok = (arb.ARB_OK, arb.ARB_W_PINV_USED)
+        for _ in range(n):
+            rc, q, th, U, info = step(ctx, wl.F, T / n, delta=delta, corr_tol=1e-13)
+            assert rc in (ok if delta <= 1e-9 else ok + (arb.ARB_W_NOT_CONVERGED,))
+        return q
+
+    try:
+        ref = run(arb.arb_step_midpoint, 256, 1e-20)
+        ratios = {}
+        for delta in (1e-20, 1e-9, 1e-6, np.inf):
+            e = [np.abs(run(arb.arb_step_euler, n, delta) - ref).max() for n in (8, 16, 32, 64)]
+            ratios[delta] = [a / b for a, b in zip(e, e[1:])]
+            print(f"delta={delta}: errors {['%.2e' % x for x in e]}", flush=True)
+    finally:
+        arb.arb_destroy(ctx)
+    for delta in (1e-20, 1e-9):
+        assert all(1.7 < r < 2.4 for r in ratios[delta])
+    for delta in (1e-6, np.inf):
+        assert not all(1.7 < r < 2.4 for r in ratios[delta])
