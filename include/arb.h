@@ -227,7 +227,9 @@ int arb_blob_positions(arb_ctx *ctx, double *r_out);
  * rows of proj[9n..] are body-p-frame directions d onto which the link's
  * velocity constraint is projected (NULL = e_x, e_y, e_z).  Each kept row
  * reads d.(u_p + w_p x l_p - u_q - w_q x l_q) = d.B_n, l = R dl (App. A).
- * Replaces previously set links. */
+ * Replaces previously set links.  ARB_E_ARG if links and rows together give
+ * one articulated body more than 2048 constraint rows (the per-assembly
+ * blocks of the preconditioner and the correction are sized for that). */
 int arb_set_links(arb_ctx *ctx, int P, const int32_t *pq, const double *dl_p,
                   const double *dl_q, const double *dldot_p, const double *dldot_q,
                   const int32_t *nproj, const double *proj);

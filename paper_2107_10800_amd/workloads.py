@@ -341,11 +341,41 @@ def blob_filaments(nx: int = 1, nz: int = 1, n_blobs: int = 15, lc: float = 2.5,
                     extra=dict(single_blob=True), **_single_blob_links(q, theta, pairs))
 
 
+def _shell_mesh(level: int):
+    """Unit-sphere shell points and links after `level` subdivisions of the
+    icosahedron (12, 42, 162, 642 points for 0..3): each subdivision adds the
+    projected midpoint of every edge and splits every face in four; the links
+    join each point of the last subdivision to the two ends of its edge (60,
+    240, 960 for levels 1..3).  Level 1 is the 42-point shell with its points
+    and links in the icosahedron's edge order."""
+    v, edges = _icosahedron()
+    es = set(edges)
+    faces = [(i, j, k) for (i, j) in edges for k in range(j + 1, 12)
+             if (i, k) in es and (j, k) in es]
+    pts = [p for p in v]
+    links = []
+    for _ in range(level):
+        mid = {}
+        for (i, j) in edges:
+            mid[(i, j)] = len(pts)
+            m = pts[i] + pts[j]
+            pts.append(m / np.linalg.norm(m))
+        links = [(i, mid[(i, j)]) for (i, j) in edges] + [(j, mid[(i, j)]) for (i, j) in edges]
+        e = lambda a, b: mid[(min(a, b), max(a, b))]
+        faces = [f for (a, b, c) in faces for f in ((a, e(a, b), e(c, a)), (b, e(b, c), e(a, b)),
+                                                    (c, e(c, a), e(b, c)),
+                                                    (e(a, b), e(b, c), e(c, a)))]
+        edges = sorted({(min(x, y), max(x, y)) for f in faces for x, y in
+                        ((f[0], f[1]), (f[1], f[2]), (f[2], f[0]))})
+    return np.array(pts), links
+
+
 def blob_shells(n_side: int = 1, lc: float = 2.5, forcing: str = "random",
-                seed: int = 32, centres=None) -> Workload:
+                seed: int = 32, centres=None, level: int = 1) -> Workload:
     """Cubic lattice of n_side^3 deformable shells of single-blob bodies (Sec. 3.2.2);
     with ``centres`` ((k, 3), in units of the shell radius R) the shells sit there
-    instead (the two sedimenting shells of Sec. 4.4 at (+-1.5, 0, +-1.5) R).
+    instead (the two sedimenting shells of Sec. 4.4 at (+-1.5, 0, +-1.5) R); ``level``
+    2 or 3 gives the 162- and 642-point shells of Sec. 4.4 (240 and 960 links).
 
     A shell is the 42-point icosphere (12 icosahedron vertices, 30 projected
     edge midpoints) scaled so that a vertex and a neighbouring midpoint are lc
@@ -356,12 +386,9 @@ def blob_shells(n_side: int = 1, lc: float = 2.5, forcing: str = "random",
     Unbounded.
     """
     rng = np.random.default_rng(seed)
-    v, edges = _icosahedron()
-    mids = np.array([(v[i] + v[j]) / np.linalg.norm(v[i] + v[j]) for i, j in edges])
-    R = lc / np.linalg.norm(v[edges[0][0]] - mids[0])
-    shell = R * np.vstack([v, mids])
-    pairs1 = [(i, 12 + e) for e, (i, j) in enumerate(edges)] + \
-             [(j, 12 + e) for e, (i, j) in enumerate(edges)]
+    unit, pairs1 = _shell_mesh(level)
+    R = lc / np.linalg.norm(unit[pairs1[0][0]] - unit[pairs1[0][1]])
+    shell = R * unit
     q, pairs = [], []
     if centres is None:
         centres = [4.0 * np.array([ix, iy, iz], float) for ix in range(n_side)

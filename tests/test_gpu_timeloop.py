@@ -448,3 +448,34 @@ def test_swimming_bacterium_needs_a_tight_check():
         assert all(1.7 < r < 2.4 for r in ratios[delta])
     for delta in (1e-6, np.inf):
         assert not all(1.7 < r < 2.4 for r in ratios[delta])
+
+
+def test_correction_of_larger_shells_matches_oracle():
+    """E4 (Sec. 4.4) on the GPU: the 42- and 162-blob shells with links violated
+    by about 1e-2 take the oracle's number of Levenberg-Marquardt steps (fewer
+    than five) and reach its corrected state; the 642-blob shell (3,522
+    residual rows, 2,880 of them link rows) is beyond the 2,048 constraint rows
+    one articulated body may have and is refused when the context is made."""
+    from oracle import correct
+    for level in (1, 2, 3):
+        wl = W.blob_shells(level=level, seed=40 + level)
+        rng = np.random.default_rng(7)
+        q = wl.q + 2.5e-3 * rng.standard_normal(wl.q.shape)
+        th = quat_mul(quat_from_rotvec(1e-3 * rng.standard_normal((wl.M, 3))), wl.theta)
+        if level == 3:
+            with pytest.raises(arb.ArbError, match="2048 constraint rows"):
+                arb.context_for(wl, tol=1e-12)
+            continue
+        ctx = arb.context_for(wl, tol=1e-12)
+        try:
+            arb.arb_set_state(ctx, q, th)
+            q2, t2, it, res = arb.arb_correct_positions(ctx, tol=1e-10, max_iter=50)
+        finally:
+            arb.arb_destroy(ctx)
+        qc, tc, info = correct.correct(wl, q, th, tol=1e-10, max_iter=50)
+        scale = 1.0 + np.abs(wl.q).max()
+        print(f"shell of {wl.M}: {it} iterations (oracle {info['iterations']}), |q - oracle| "
+              f"{np.abs(q2 - qc).max():.1e}", flush=True)
+        assert it < 5 and abs(it - info["iterations"]) <= 1
+        assert res <= 1e-10
+        assert np.abs(q2 - qc).max() <= 1e-8 * scale

@@ -10,7 +10,7 @@ fixed points)."""
 import numpy as np
 import pytest
 
-from oracle import bodies, timeloop
+from oracle import bodies, correct, timeloop
 from oracle.correct import link_assemblies
 from oracle.quat import quat_from_rotvec, quat_mul, rotation_matrix
 from paper_2107_10800_amd import workloads as W
@@ -293,3 +293,19 @@ def test_two_sedimenting_shells_orders():
         print(step.__name__, ["%.2e" % e for e in errs])
         for a, b in zip(errs, errs[1:]):
             assert 0.75 * 2 ** order < a / b < 1.3 * 2 ** order, (step.__name__, errs)
+
+
+def test_correction_iterations_stay_flat_with_shell_size():
+    """E4 (Sec. 4.4): the correction of Sec. 4.2 needs fewer than five
+    Levenberg-Marquardt iterations per articulated body whatever the shell's
+    size: the 42-, 162- and 642-blob shells (60, 240, 960 links) with links
+    violated by about 1e-2 (a time step's worth) reach 1e-10."""
+    for level in (1, 2, 3):
+        wl = W.blob_shells(level=level, seed=40 + level)
+        rng = np.random.default_rng(7)
+        q = wl.q + 2.5e-3 * rng.standard_normal(wl.q.shape)
+        th = quat_mul(quat_from_rotvec(1e-3 * rng.standard_normal((wl.M, 3))), wl.theta)
+        qc, tc, info = correct.correct(wl, q, th, tol=1e-10, max_iter=50)
+        g = np.abs(bodies.link_residual(wl, qc, tc)).max()
+        print(f"shell of {wl.M}: {info['iterations']} iterations, |g| {g:.1e}")
+        assert info["iterations"] < 5 and g <= 1e-10
